@@ -1,0 +1,331 @@
+"""Pins of the CPU oracle against facts fixed outside it: Table I sizes, a
+closed-form two-bus power flow, 50-digit reference derivatives, an autograd
+Hessian, finite differences, Taylor remainders and physical invariants."""
+import dataclasses
+import os
+
+import mpmath as mp
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+import torch
+
+import gridgen
+import oracle
+from tests import smallgrids
+from tests.mpref import MPGrid
+
+
+def _setup(g, seed=7, sigma="random", rho=10.0, tol=1e-12):
+    M = oracle.Model(g)
+    u = M.u_from_setpoints(g["vg0"], g["pg0"])
+    pf = oracle.solve_pf(M, u, g["pd"], g["qd"], tol=tol)
+    P = oracle.Point.from_dict(smallgrids.point_for(g, seed=seed, rho=rho, sigma=sigma))
+    return M, u, pf.x, P
+
+
+# ---------------------------------------------------------------- Table I
+def _table1():
+    here = os.path.join(os.path.dirname(__file__), "golden", "table1_sizes.csv")
+    rows = []
+    for line in open(here):
+        if line.strip() and not line.startswith("#"):
+            name, *vals = line.strip().split(",")
+            rows.append((name, *map(int, vals)))
+    return rows
+
+
+@pytest.mark.parametrize("row", _table1(), ids=lambda r: r[0])
+def test_table1_dimensions(row):
+    """Table I: (n_x, n_u, m) of the PEGASE cases follow from (n_b, n_l) and
+    n_pv = (n_u - 1) / 2 through the state/control split and the count m."""
+    name, nb, nl, nx, nu, m = row
+    npv = (nu - 1) // 2
+    w = gridgen.Workload("t", nb, nl, npv + 1, 5, "geometric")
+    M = oracle.Model(gridgen.make_grid(w))
+    assert (M.nx, M.nu, M.m) == (nx, nu, m)
+
+
+def test_workload_dimensions():
+    M = oracle.Model(gridgen.grid("tiny10"))
+    assert (M.nx, M.nu, M.m) == (16, 5, 37)
+    M = oracle.Model(gridgen.grid("syn300"))
+    assert (M.nx, M.nu) == (530, 137)
+    M = oracle.Model(gridgen.grid("syn2000"))
+    assert (M.nu,) == (1079,)
+
+
+# ------------------------------------------------------ two-bus closed form
+def test_two_bus_closed_form():
+    """Slack V1 feeding P + jQ over r + jx: v2^4 + (2(rP + xQ) - v1^2) v2^2
+    + (r^2 + x^2)(P^2 + Q^2) = 0 (larger root), theta2 = -atan2(xP - rQ,
+    v2^2 + rP + xQ)."""
+    r, x, P, Q, v1 = 0.03, 0.12, 1.1, 0.45, 1.03
+    g = smallgrids.two_bus(r=r, x=x, P=P, Q=Q, v1=v1)
+    M = oracle.Model(g)
+    u = M.u_from_setpoints(g["vg0"], g["pg0"])
+    pf = oracle.solve_pf(M, u, g["pd"], g["qd"])
+    bq = 2 * (r * P + x * Q) - v1 ** 2
+    cq = (r * r + x * x) * (P * P + Q * Q)
+    v2sq = (-bq + np.sqrt(bq * bq - 4 * cq)) / 2
+    th2 = -np.arctan2(x * P - r * Q, v2sq + r * P + x * Q)
+    assert pf.converged and pf.resid < 1e-10
+    np.testing.assert_allclose(pf.x, [th2, np.sqrt(v2sq)], rtol=0, atol=1e-13)
+    # slack generation = load + series loss r (P^2 + Q^2) / v2^2
+    pg = M.gen_p(pf.x, u, g["pd"])
+    np.testing.assert_allclose(pg[0], P + r * (P * P + Q * Q) / v2sq, rtol=1e-13)
+
+
+# -------------------------------------------- 50-digit reduced derivatives
+@pytest.mark.parametrize("which", ["two_bus", "two_bus_charging", "three_bus"])
+def test_reduced_derivatives_vs_mpmath(which):
+    """Prop. 1 gradient and the Schur-form Hessian against 50-digit
+    numerical derivatives of the closed-loop phi(u)."""
+    if which == "two_bus":
+        g = smallgrids.two_bus()
+    elif which == "two_bus_charging":
+        g = smallgrids.two_bus(b=0.08)
+    else:
+        g = smallgrids.three_bus()
+    M, u, x, P = _setup(g, seed=11, tol=1e-14)
+    grad, lam = oracle.reduced_gradient(M, x, u, g["pd"], g["qd"], P)
+    H = oracle.reduced_hessian(M, x, u, g["pd"], g["qd"], P, lam)
+    pt = smallgrids.point_for(g, seed=11)
+    ref = MPGrid(g, pt, dps=40)
+    gm, Hm = ref.derivatives(list(u))
+    gm = np.array([float(v) for v in gm])
+    Hm = np.array([[float(v) for v in row] for row in Hm])
+    np.testing.assert_allclose(grad, gm, rtol=1e-11, atol=1e-11 * np.abs(gm).max())
+    np.testing.assert_allclose(H, Hm, rtol=1e-10, atol=1e-10 * np.abs(Hm).max())
+    phi, _ = oracle.al_objective(M, x, u, g["pd"], g["qd"], P)
+    assert abs(phi - float(ref.phi([mp.mpf(v) for v in u]))) <= 1e-12 * max(1.0, abs(phi))
+
+
+def test_cost_only_special_case():
+    """rho = 0, y = 0, sigma_f = 1: the reduced Hessian is that of the cost
+    f(x(u), u) alone."""
+    g = smallgrids.three_bus()
+    M = oracle.Model(g)
+    u = M.u_from_setpoints(g["vg0"], g["pg0"])
+    x = oracle.solve_pf(M, u, g["pd"], g["qd"], tol=1e-14).x
+    pt = smallgrids.point_for(g)
+    pt = dict(pt, rho=0.0, y=np.zeros_like(pt["y"]), sigma_f=1.0)
+    P = oracle.Point.from_dict(pt)
+    grad, lam = oracle.reduced_gradient(M, x, u, g["pd"], g["qd"], P)
+    H = oracle.reduced_hessian(M, x, u, g["pd"], g["qd"], P, lam)
+    ref = MPGrid(g, pt, dps=40)
+    gm, Hm = ref.derivatives(list(u))
+    np.testing.assert_allclose(grad, [float(v) for v in gm], rtol=1e-11)
+    Hm = np.array([[float(v) for v in r] for r in Hm])
+    np.testing.assert_allclose(H, Hm, rtol=1e-10, atol=1e-10 * np.abs(Hm).max())
+
+
+# ------------------------------------------------- autograd Hessian of l
+def _torch_lagrangian(M, g, pd, qd, P, lam):
+    """l(z) = phi(z) + lambda^T g(z), z = (theta, v, p_pv), in plain torch."""
+    nb = M.nb
+    Y = torch.tensor(M.Y.toarray())
+    Yf = torch.tensor(M.Yf.toarray())
+    Yt = torch.tensor(M.Yt.toarray())
+    f_idx = torch.tensor(M.f)
+    t_idx = torch.tensor(M.t)
+    pd_t = torch.tensor(pd)
+    qd_t = torch.tensor(qd)
+    lam_t = torch.tensor(lam)
+    y = torch.tensor(P.y)
+    s = torch.tensor(P.s)
+    sc = torch.tensor(P.sigma_c)
+    c2 = torch.tensor(g["c2"])
+    c1 = torch.tensor(g["c1"])
+    base = g["base_mva"]
+    pv = torch.tensor(M.pv)
+    pq = torch.tensor(M.pq)
+
+    def ell(z):
+        th, v, ppv = z[:nb], z[nb:2 * nb], z[2 * nb:]
+        V = torch.polar(v, th)
+        S = V * torch.conj(Y @ V)
+        Sf = V[f_idx] * torch.conj(Yf @ V)
+        St = V[t_idx] * torch.conj(Yt @ V)
+        gvec = torch.cat([S.real[pv] - ppv + pd_t[pv], S.real[pq] + pd_t[pq], S.imag[pq] + qd_t[pq]])
+        pref = S.real[M.ref] + pd_t[M.ref]
+        qnet = S.imag + qd_t
+        c = torch.cat([Sf.real ** 2 + Sf.imag ** 2, St.real ** 2 + St.imag ** 2, v[pq],
+                       pref.reshape(1), qnet[M.ref].reshape(1), qnet[pv]])
+        pg = torch.zeros(M.ng, dtype=torch.float64)
+        pg = pg.index_put((torch.tensor(M.gen_pv),), ppv)
+        pg = pg.index_put((torch.tensor([M.gen_ref]),), pref.reshape(1))
+        f = torch.sum(c2 * (base * pg) ** 2 + c1 * base * pg)
+        r = sc * (c - s)
+        return P.sigma_f * f + y @ r + 0.5 * P.rho * r @ r + lam_t @ gvec
+
+    return ell
+
+
+@pytest.mark.parametrize("name", ["tiny10", "three_bus"])
+def test_lagrangian_hessian_vs_autograd(name):
+    g = gridgen.grid(name) if name != "three_bus" else smallgrids.three_bus()
+    M, u, x, P = _setup(g)
+    grad, lam = oracle.reduced_gradient(M, x, u, g["pd"], g["qd"], P)
+    Hz = oracle.lagrangian_hessian_full(M, x, u, g["pd"], g["qd"], P, lam).toarray()
+    th, v, ppv = M.full(x, u)
+    z = torch.tensor(np.concatenate([th, v, ppv]))
+    ell = _torch_lagrangian(M, g, g["pd"], g["qd"], P, lam)
+    Ht = torch.autograd.functional.hessian(ell, z).numpy()
+    np.testing.assert_allclose(Hz, Ht, rtol=0, atol=1e-12 * np.abs(Ht).max())
+    # first derivatives: d phi/dz (without lambda^T g) against autograd
+    ell0 = _torch_lagrangian(M, g, g["pd"], g["qd"], P, np.zeros_like(lam))
+    gt = torch.autograd.functional.jacobian(ell0, z).numpy()
+    gz = oracle.full_gradient(M, x, u, g["pd"], g["qd"], P)
+    np.testing.assert_allclose(gz, gt, rtol=0, atol=1e-12 * np.abs(gt).max())
+
+
+# ----------------------------------------- Schur form == adjoint-adjoint
+@pytest.mark.parametrize("name", ["tiny10", "syn300"])
+def test_schur_equals_adjoint_adjoint(name):
+    """Proposition 2 applied to the identity equals Z^T (grad^2 l) Z."""
+    g = gridgen.grid(name)
+    M, u, x, P = _setup(g)
+    grad, lam = oracle.reduced_gradient(M, x, u, g["pd"], g["qd"], P)
+    H = oracle.reduced_hessian(M, x, u, g["pd"], g["qd"], P, lam)
+    Ha = oracle.hvp_adjoint_adjoint(M, x, u, g["pd"], g["qd"], P, lam, np.eye(M.nu))
+    assert np.linalg.norm(H - Ha) <= 1e-12 * np.linalg.norm(H)
+
+
+# ------------------------------------------------ finite differences, Taylor
+def _reduced_phi(M, u, g, P, x0):
+    x = oracle.solve_pf(M, u, g["pd"], g["qd"], x0=x0, tol=1e-13).x
+    return oracle.al_objective(M, x, u, g["pd"], g["qd"], P)[0], x
+
+
+@pytest.mark.parametrize("name", ["tiny10", "syn300"])
+def test_hessian_vs_fd_of_gradient(name):
+    g = gridgen.grid(name)
+    M, u, x, P = _setup(g)
+    grad, lam = oracle.reduced_gradient(M, x, u, g["pd"], g["qd"], P)
+    H = oracle.reduced_hessian(M, x, u, g["pd"], g["qd"], P, lam)
+    rng = np.random.default_rng(3)
+    cols = range(M.nu) if M.nu <= 8 else rng.choice(M.nu, 8, replace=False)
+    for k in cols:
+        h = 1e-6 * max(1.0, abs(u[k]))
+        gs = []
+        for sgn in (1, -1):
+            up = u.copy(); up[k] += sgn * h
+            xp = oracle.solve_pf(M, up, g["pd"], g["qd"], x0=x, tol=1e-13).x
+            gs.append(oracle.reduced_gradient(M, xp, up, g["pd"], g["qd"], P)[0])
+        fd = (gs[0] - gs[1]) / (2 * h)
+        assert np.linalg.norm(fd - H[:, k]) <= 1e-6 * max(1.0, np.linalg.norm(H[:, k]))
+
+
+def test_gradient_vs_fd_of_phi():
+    g = gridgen.grid("tiny10")
+    M, u, x, P = _setup(g)
+    grad, _ = oracle.reduced_gradient(M, x, u, g["pd"], g["qd"], P)
+    for k in range(M.nu):
+        h = 1e-6
+        up = u.copy(); up[k] += h
+        um = u.copy(); um[k] -= h
+        fd = (_reduced_phi(M, up, g, P, x)[0] - _reduced_phi(M, um, g, P, x)[0]) / (2 * h)
+        assert abs(fd - grad[k]) <= 1e-7 * max(1.0, abs(grad[k]))
+
+
+def test_taylor_remainder_is_cubic():
+    """|phi(u + t d) - phi - t g.d - t^2/2 d^T H d| = O(t^3): log-log slopes
+    near 3 (a wrong Hessian gives 2), well above the rounding floor."""
+    g = gridgen.grid("tiny10")
+    M, u, x, P = _setup(g)
+    phi0, _ = oracle.al_objective(M, x, u, g["pd"], g["qd"], P)
+    grad, lam = oracle.reduced_gradient(M, x, u, g["pd"], g["qd"], P)
+    H = oracle.reduced_hessian(M, x, u, g["pd"], g["qd"], P, lam)
+    d = np.random.default_rng(5).standard_normal(M.nu)
+    d /= np.linalg.norm(d)
+    ts = np.array([4e-3, 2e-3, 1e-3, 5e-4])
+    rem = []
+    for t in ts:
+        ph, _ = _reduced_phi(M, u + t * d, g, P, x)
+        rem.append(abs(ph - phi0 - t * grad @ d - 0.5 * t * t * d @ H @ d))
+    slopes = np.diff(np.log(rem)) / np.diff(np.log(ts))
+    assert np.all((slopes > 2.8) & (slopes < 3.5)), slopes
+    assert min(rem) > 1e3 * np.finfo(float).eps * abs(phi0)
+
+
+# -------------------------------------------------------------- invariants
+@pytest.mark.parametrize("name", ["tiny10", "syn300", "syn2000"])
+def test_invariants(name):
+    g = gridgen.grid(name)
+    M, u, x, P = _setup(g)
+    gres = M.residual(x, u, g["pd"], g["qd"])
+    assert np.linalg.norm(gres) < 1e-10
+    th, v, _ = M.full(x, u)
+    Sf, St = M.branch_flows(th, v)
+    pg = M.gen_p(x, u, g["pd"])
+    # generation = load + losses (active); reactive incl. line charging
+    assert abs(pg.sum() - g["pd"].sum() - np.sum(Sf.real + St.real)) < 1e-10
+    S = M.injections(th, v)
+    qnet = S.imag + g["qd"]
+    assert abs(qnet[g["gen_bus"]].sum() - g["qd"].sum() - np.sum(Sf.imag + St.imag)) < 1e-10
+    # adjoint identity <lambda, J_x z> = -<d_x phi, z>
+    grad, lam = oracle.reduced_gradient(M, x, u, g["pd"], g["qd"], P)
+    Jx, Ju = M.jacobians(x, u)
+    gz = oracle.full_gradient(M, x, u, g["pd"], g["qd"], P)
+    z = np.random.default_rng(1).standard_normal(M.nx)
+    assert abs(lam @ (Jx @ z) + gz[M.ix] @ z) <= 1e-10 * np.abs(gz[M.ix] @ z) + 1e-12
+    if M.nu <= 200:
+        H = oracle.reduced_hessian(M, x, u, g["pd"], g["qd"], P, lam)
+        assert np.linalg.norm(H - H.T) <= 1e-12 * np.linalg.norm(H)
+
+
+@pytest.mark.slow
+def test_largest_workload_power_flow_within_six_steps():
+    """The 9241-bus workload's base power flow converges in <= 6 Newton
+    steps from a flat start to ||g||_2 < 1e-10."""
+    g = gridgen.grid("syn9241")
+    M = oracle.Model(g)
+    assert (M.nx, M.nu, M.m) == (17036, 2889, 41340)
+    u = M.u_from_setpoints(g["vg0"], g["pg0"])
+    pf = oracle.solve_pf(M, u, g["pd"], g["qd"], max_iter=6)
+    assert pf.converged and pf.iters <= 6
+
+
+# ---------------------------------------------------------------- Cholesky
+def test_cholesky_matches_lapack_and_reconstructs():
+    rng = np.random.default_rng(0)
+    A = rng.standard_normal((40, 40))
+    K = A @ A.T + 40 * np.eye(40)
+    L, info = oracle.cholesky_lower(K)
+    assert info == 0
+    assert np.linalg.norm(L @ L.T - K) <= 1e-14 * np.linalg.norm(K)
+    np.testing.assert_allclose(L, np.linalg.cholesky(K), rtol=1e-12, atol=1e-13)
+
+
+def test_cholesky_reports_first_failing_column():
+    K = np.diag([4.0, 1.0, -2.0, 3.0])
+    L, info = oracle.cholesky_lower(K)
+    assert info == 3
+
+
+def test_factor_solve_symmetrises_and_solves():
+    rng = np.random.default_rng(2)
+    A = rng.standard_normal((12, 12))
+    H = A @ A.T + 0.3 * rng.standard_normal((12, 12))     # not symmetric
+    diag = rng.uniform(0.5, 1.0, 12)
+    rhs = rng.standard_normal(12)
+    L, info, d = oracle.factor_solve(H, diag, 2.0, rhs)
+    K = 0.5 * (H + H.T) + np.diag(diag) + 2.0 * np.eye(12)
+    assert info == 0
+    np.testing.assert_allclose(K @ d, -rhs, rtol=1e-12, atol=1e-12)
+
+
+# ------------------------------------------------------------ tracking bits
+def test_slack_minimiser_minimises_the_al_in_s():
+    g = gridgen.grid("tiny10")
+    M, u, x, P = _setup(g)
+    _, c = oracle.al_objective(M, x, u, g["pd"], g["qd"], P)
+    lo, hi = gridgen.constraint_bounds(g)
+    s = oracle.slack_minimiser(c, P, lo, hi)
+    # per-coordinate objective -sigma y s + rho/2 sigma^2 (c - s)^2 on a grid
+    for k in range(0, len(c), 5):
+        grid = np.linspace(lo[k], hi[k], 20001)
+        obj = P.sigma_c[k] * P.y[k] * (c[k] - grid) + 0.5 * P.rho * (P.sigma_c[k] * (c[k] - grid)) ** 2
+        best = grid[np.argmin(obj)]
+        assert abs(best - s[k]) <= (hi[k] - lo[k]) / 20000 + 1e-12
