@@ -1,0 +1,189 @@
+/*
+ * rpf.h -- C ABI of the reduced-space power-flow derivative library for
+ * AMD MI355X (gfx950), FP64 throughout.
+ *
+ * The library computes the quantities of the feasible reduced-space method
+ * for optimal power flow (Pacaud et al., "A Feasible Reduced Space Method
+ * for Real-Time Optimal Power Flow"):
+ *
+ *   rpf_pf_solve               Newton-Raphson power flow g(x, u) = 0
+ *                              (Section III-A, eq. projection:newtonraphson;
+ *                              stopping rule ||g||_2 < tol of Section V-A.1)
+ *   rpf_al_objective           scaled augmented-Lagrangian value and the
+ *                              operational constraints c (Section IV-A.1,
+ *                              IV-A.2; c = (h, r) of eq. acopf_controlstate)
+ *   rpf_reduced_gradient       reduced gradient by the adjoint method
+ *                              (Proposition 1, eq. reduced_gradient)
+ *   rpf_reduced_hessian_batch  reduced Hessian-vector products by the
+ *                              adjoint-adjoint method (Proposition 2,
+ *                              eq. hessvecprod, eq. socadjoint)
+ *   rpf_reduced_hessian        the dense reduced Hessian, n_u products in
+ *                              batches (Section III-C, reduced Hessian)
+ *   rpf_factor_solve           Cholesky of the symmetrised, shifted reduced
+ *                              Hessian and the resulting step (Section IV-B.2,
+ *                              Proposition 3 and the inertia-control remark)
+ *
+ * Variables and orderings (Section II-B, eq. statecontrol):
+ *   u = (v_ref, v_pv, p_pv)            n_u = 1 + 2 n_pv
+ *   x = (theta_pv, theta_pq, v_pq)     n_x = n_pv + 2 n_pq
+ *   g rows = (P balance at PV, P balance at PQ, Q balance at PQ)
+ * Buses within each group in ascending bus id; theta_ref = 0.
+ *   c = (|S_f|^2 per branch, |S_t|^2 per branch, v_pq, p^g_ref,
+ *        q^net_ref, q^net_pv)          m = 2 n_l + n_pq + n_pv + 2
+ * with S_f, S_t the complex flows at the from/to ends (pi model, no taps),
+ * p^g_ref = P_ref + p^d_ref, q^net_i = Q_i + q^d_i.  The cost is
+ * f = sum_g c2 (B p_g)^2 + c1 (B p_g) + c0, B = base_mva, over all
+ * generators (the slack's p_g is p^g_ref).  The AL value is
+ *   phi = sigma_f f + y^T D_c (c - s) + rho/2 ||D_c (c - s)||^2,
+ * D_c = diag(sigma_c).
+ *
+ * Conventions for every call:
+ *  - Pointers marked "device" are device memory on the current HIP device;
+ *    "host" pointers are read during the call only.  The caller owns all
+ *    buffers it passes; the handle owns its internal workspace.
+ *  - Compute calls enqueue work on `stream` and return without waiting,
+ *    except rpf_pf_solve, which reads the residual norm on the host after
+ *    each Newton step (it synchronises the stream once per step).
+ *  - Dense matrices are row-major.  A batch of vectors is an [n x nbatch]
+ *    row-major block with leading dimension ld >= nbatch (element (i, k) at
+ *    i * ld + k).
+ *  - Return value: 0 on success, a negative RPF_E* code otherwise, with a
+ *    message from rpf_last_error().  Numerical outcomes (power flow not
+ *    converged, zero pivot, Cholesky failure) are reported in device status
+ *    words, never as return codes.
+ *  - A handle is not thread-safe; use one handle per host thread / stream.
+ */
+#ifndef RPF_H
+#define RPF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ihipStream_t* rpf_stream_t; /* hipStream_t; NULL = default stream */
+
+enum {
+  RPF_OK = 0,
+  RPF_EINVAL = -1, /* bad argument (null pointer, size out of range, bad grid) */
+  RPF_ENOMEM = -2, /* device allocation failed */
+  RPF_EHIP = -3,   /* a HIP runtime call failed */
+  RPF_ESTATE = -4, /* call order: e.g. Hessian products before rpf_reduced_gradient */
+  RPF_ESIZE = -5   /* nbatch above the max_batch given at creation */
+};
+
+typedef struct rpf_grid rpf_grid;
+
+/* Grid description (host pointers, copied by rpf_grid_create).
+ * bus_type: 0 = PQ, 1 = PV, 2 = REF (exactly one REF).  Branches are pi
+ * models with series impedance br_r + j br_x and total line charging br_b
+ * (half at each end), all per unit; no parallel branches.  gen_bus: one
+ * generator at each PV and REF bus and none elsewhere.  Costs c2, c1, c0
+ * apply to the generator's active output in MW (per-unit times base_mva). */
+typedef struct {
+  int32_t nb, nl, ng;
+  double base_mva;
+  const int32_t* bus_type; /* [nb] */
+  const int32_t* br_from;  /* [nl] */
+  const int32_t* br_to;    /* [nl] */
+  const double* br_r;      /* [nl] */
+  const double* br_x;      /* [nl] */
+  const double* br_b;      /* [nl] */
+  const int32_t* gen_bus;  /* [ng] */
+  const double* c2;        /* [ng] */
+  const double* c1;        /* [ng] */
+  const double* c0;        /* [ng] */
+} rpf_grid_desc;
+
+/* Host presolve (index maps, fill-reducing ordering, symbolic LU of J_x,
+ * level schedules, gather lists) and device allocations for batches of up
+ * to max_batch Hessian-vector products.  Uses the current HIP device.
+ * Static pivoting: the diagonal pairs P_i/theta_i, Q_i/v_i are the pivots
+ * (Section V-A.1: symbolic factorization once, numeric refactorization on
+ * the device).  On failure *out is NULL. */
+int rpf_grid_create(const rpf_grid_desc* desc, int32_t max_batch, rpf_grid** out);
+void rpf_grid_destroy(rpf_grid* grid);
+
+/* Sizes n_x, n_u, m (eq. statecontrol, eq. acopf_controlstate). Host ints. */
+int rpf_dims(const rpf_grid* grid, int32_t* nx, int32_t* nu, int32_t* m);
+
+/* Structure figures of the presolve (host int64 [10]): nnz(J_x), nnz(L+U),
+ * forward levels, backward levels, longest LU row, refactorization
+ * updates, nnz(J_u), nnz(K), nnz(rank-one rows), max_batch. */
+int rpf_structure(const rpf_grid* grid, int64_t* out10);
+
+/* Newton-Raphson power flow at fixed control u and loads (Section III-A):
+ * x_{k+1} = x_k - (grad_x g_k)^{-1} g_k, stopped when ||g||_2 < tol or after
+ * max_iter steps.
+ *   u [n_u], pd [nb], qd [nb]: device, read only.
+ *   x [n_x]: device, in: starting point, out: last iterate.
+ *   status [2]: device int32, out: {Newton steps taken, converged (0/1)}.
+ *   resid [1]: device, out: ||g(x, u)||_2 at the returned x.
+ * Leaves J_x of the last step factorized in the handle.  Synchronises the
+ * stream once per Newton step to test convergence. */
+int rpf_pf_solve(rpf_grid* grid, const double* u, const double* pd, const double* qd, double* x,
+                 double tol, int32_t max_iter, int32_t* status, double* resid, rpf_stream_t stream);
+
+/* AL value and constraints at (x, u) (Section IV-A).
+ *   x [n_x], u [n_u], pd/qd [nb], s/y [m], sigma [1 + m] = (sigma_f,
+ *   sigma_c): device, read only.
+ *   phi [1], c [m]: device, out.  c may be NULL. */
+int rpf_al_objective(rpf_grid* grid, const double* x, const double* u, const double* pd,
+                     const double* qd, const double* s, const double* y, double rho,
+                     const double* sigma, double* phi, double* c, rpf_stream_t stream);
+
+/* Reduced gradient of phi (Proposition 1 applied to the AL function):
+ * solves (grad_x g)^T lambda = -(d_x phi)^T with the LU of J_x refactorized
+ * at x, then grad = d_u phi + lambda^T grad_u g.
+ *   inputs as rpf_al_objective (device).
+ *   grad [n_u], lambda [n_x] (x order): device, out.  lambda may be NULL.
+ * Caches the point (factorized J_x, J_u, the Lagrangian Hessian of
+ * l = phi + lambda^T g, rank-one constraint terms) for the Hessian calls. */
+int rpf_reduced_gradient(rpf_grid* grid, const double* x, const double* u, const double* pd,
+                         const double* qd, const double* s, const double* y, double rho,
+                         const double* sigma, double* grad, double* lambda, rpf_stream_t stream);
+
+/* Reduced Hessian-vector products at the cached point (Proposition 2):
+ * for each column w of V: J_x z = -J_u w; J_x^T psi = -(K_xu w + K_xx z);
+ * H w = K_uu w + K_ux z + J_u^T psi, with K the Hessian of
+ * l = phi + lambda^T g in (x, u).
+ *   V: device [n_u x nbatch], leading dimension ldv, read only.
+ *   HV: device [n_u x nbatch], leading dimension ldhv, out.
+ *   1 <= nbatch <= max_batch.  RPF_ESTATE before rpf_reduced_gradient. */
+int rpf_reduced_hessian_batch(rpf_grid* grid, const double* V, int32_t nbatch, int32_t ldv,
+                              double* HV, int32_t ldhv, rpf_stream_t stream);
+
+/* The dense reduced Hessian H [n_u x n_u] (device, row-major, out) at the
+ * cached point: products with the identity in batches of `batch` columns
+ * (0 = the library's choice, at most max_batch). */
+int rpf_reduced_hessian(rpf_grid* grid, double* H, int32_t batch, rpf_stream_t stream);
+
+/* Dense step (Section IV-B.2): K = (H + H^T)/2 + diag(d) + delta I is
+ * factorized as L L^T (Cholesky), then step = -K^{-1} rhs.
+ *   n: order; Kmat [n x n]: device, in: H, out: L in the lower triangle
+ *   (upper triangle left as K).  diag [n] or NULL, rhs [n]: device, read.
+ *   step [n]: device, out (left unchanged when info != 0).
+ *   info [1]: device int32, out: 0, or the 1-based column whose pivot was
+ *   not positive. */
+int rpf_factor_solve(rpf_grid* grid, int32_t n, double* Kmat, const double* diag, double delta,
+                     const double* rhs, double* step, int32_t* info, rpf_stream_t stream);
+
+/* Host-only presolve introspection (no device needed), for checking the
+ * index maps and the symbolic factorization:
+ *   rpf_presolve_info: out16 = {n_x, n_u, m, nnz(J_x), nnz(L+U), forward
+ *   levels, backward levels, longest LU row, refactorization updates,
+ *   nnz(J_u), nnz(K), nnz(rank-one rows), 0, 0, 0, 0}.
+ *   rpf_presolve_pattern: perm [n_x] (internal state index -> paper x
+ *   index), lu_ptr [n_x + 1], lu_col [nnz(L+U)] (internal order, sorted
+ *   columns, diagonal included); any pointer may be NULL. */
+int rpf_presolve_info(const rpf_grid_desc* desc, int64_t* out16);
+int rpf_presolve_pattern(const rpf_grid_desc* desc, int32_t* perm, int32_t* lu_ptr, int32_t* lu_col);
+
+/* Message for the last nonzero return on this thread. */
+const char* rpf_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RPF_H */

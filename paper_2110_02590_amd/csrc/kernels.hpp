@@ -1,0 +1,717 @@
+// Device kernels of the reduced-space hot path (gfx950, wave64, FP64).
+//
+// Data layout: state vectors in the internal (fill-reducing) order, controls
+// in the paper's order; batches of vectors are row-major [n x ld] blocks so
+// that the lanes of a wavefront run over directions (columns) and every row
+// access is contiguous.  All reductions are deterministic (fixed gather
+// orders, no floating-point atomics).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "presolve.hpp"
+
+namespace rpf {
+namespace dev {
+
+using rpf::RECW;
+using rpf::WREC;
+
+// ------------------------------------------------------------------ helpers
+__global__ void k_permute_gather(int n, const int32_t* __restrict__ idx, const double* __restrict__ src,
+                                 double* __restrict__ dst) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = src[idx[i]];
+}
+
+__global__ void k_permute_scatter(int n, const int32_t* __restrict__ idx, const double* __restrict__ src,
+                                  double* __restrict__ dst) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[idx[i]] = src[i];
+}
+
+// out[i] = base[i] + sum_{j in [ptr[i], ptr[i+1])} in[src[j]]
+__global__ void k_gather_sum(int n, const int32_t* __restrict__ ptr, const int32_t* __restrict__ src,
+                             const double* __restrict__ in, const double* __restrict__ base,
+                             double* __restrict__ out) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double acc = base ? base[i] : 0.0;
+  for (int j = ptr[i]; j < ptr[i + 1]; ++j) acc += in[src[j]];
+  out[i] = acc;
+}
+
+// out[p] = in[srcpos[p]]
+__global__ void k_gather_pos(int n, const int32_t* __restrict__ srcpos, const double* __restrict__ in,
+                             double* __restrict__ out) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = in[srcpos[i]];
+}
+
+// ------------------------------------------------------------- bus state
+__global__ void k_bus_state(int nb, int nx, const int32_t* __restrict__ th_var,
+                            const int32_t* __restrict__ v_var, const double* __restrict__ xi,
+                            const double* __restrict__ u, double* __restrict__ th, double* __restrict__ vm) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nb) return;
+  int a = th_var[i];
+  th[i] = a >= 0 ? xi[a] : 0.0;
+  int b = v_var[i];
+  vm[i] = b < nx ? xi[b] : u[b - nx];
+}
+
+// --------------------------------------------------------- branch records
+// One thread per branch: flows at both ends of the pi model and their
+// partial derivatives with respect to (theta_f, theta_t, v_f, v_t).
+// Each end flow is v_o^2 K_o + v_f v_t T(theta_f - theta_t) with T'' = -T.
+__global__ void k_branch_eval(int nl, const int32_t* __restrict__ bf, const int32_t* __restrict__ bt,
+                              const double* __restrict__ br, const double* __restrict__ bx,
+                              const double* __restrict__ bb, const double* __restrict__ th,
+                              const double* __restrict__ vm, double* __restrict__ rec) {
+  int l = blockIdx.x * blockDim.x + threadIdx.x;
+  if (l >= nl) return;
+  int f = bf[l], t = bt[l];
+  double r = br[l], x = bx[l], bsh = 0.5 * bb[l];
+  double z2 = r * r + x * x;
+  double gs = r / z2, bs = -x / z2;
+  // self (own) admittance Y_oo = gs + j(bs + b/2); mutual Y_ft = Y_tf = -gs - j bs
+  double Goo = gs, Boo = bs + bsh, Gm = -gs, Bm = -bs;
+  double vf = vm[f], vt = vm[t];
+  double d = th[f] - th[t];
+  double sn, cs;
+  sincos(d, &sn, &cs);
+  double vv = vf * vt;
+  // from end: A = Gm cos + Bm sin, C = Gm sin - Bm cos; A' = -C, C' = A
+  double Af = Gm * cs + Bm * sn, Cf = Gm * sn - Bm * cs;
+  // to end:   A = Gm cos - Bm sin, C = -Gm sin - Bm cos; A' = C, C' = -A
+  double At = Gm * cs - Bm * sn, Ct = -Gm * sn - Bm * cs;
+  double* o = rec + (size_t)l * RECW;
+  o[0] = vf * vf * Goo + vv * Af;
+  o[1] = -vf * vf * Boo + vv * Cf;
+  o[2] = vt * vt * Goo + vv * At;
+  o[3] = -vt * vt * Boo + vv * Ct;
+  // P_f: T = Af, T' = -Cf, own f, K = Goo
+  o[4] = -vv * Cf;
+  o[5] = vv * Cf;
+  o[6] = vt * Af + 2.0 * vf * Goo;
+  o[7] = vf * Af;
+  // Q_f: T = Cf, T' = Af, own f, K = -Boo
+  o[8] = vv * Af;
+  o[9] = -vv * Af;
+  o[10] = vt * Cf - 2.0 * vf * Boo;
+  o[11] = vf * Cf;
+  // P_t: T = At, T' = Ct, own t, K = Goo
+  o[12] = vv * Ct;
+  o[13] = -vv * Ct;
+  o[14] = vt * At;
+  o[15] = vf * At + 2.0 * vt * Goo;
+  // Q_t: T = Ct, T' = -At, own t, K = -Boo
+  o[16] = -vv * At;
+  o[17] = vv * At;
+  o[18] = vt * Ct;
+  o[19] = vf * Ct - 2.0 * vt * Boo;
+}
+
+// ------------------------------------------------------------- residual
+// g[row] = sum of branch-end flows at the row's bus + load - p_pv, and the
+// per-block partial sums of g^2.
+__global__ void k_residual(int nx, const int32_t* __restrict__ ptr, const int32_t* __restrict__ src,
+                           const double* __restrict__ rec, const int32_t* __restrict__ row_bus,
+                           const int32_t* __restrict__ row_isq, const int32_t* __restrict__ row_pvar,
+                           const double* __restrict__ pd, const double* __restrict__ qd,
+                           const double* __restrict__ u, double* __restrict__ g,
+                           double* __restrict__ partial) {
+  __shared__ double red[256];
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  double v = 0.0;
+  if (i < nx) {
+    double acc = 0.0;
+    for (int j = ptr[i]; j < ptr[i + 1]; ++j) acc += rec[src[j]];
+    int b = row_bus[i];
+    acc += row_isq[i] ? qd[b] : pd[b];
+    int pv = row_pvar[i];
+    if (pv >= 0) acc -= u[pv];
+    g[i] = acc;
+    v = acc * acc;
+  }
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+// Single-block deterministic sum of `n` values; optionally sqrt.  Also sets
+// done[0] = (result < tol) when done is given.
+__global__ void k_reduce_final(int n, const double* __restrict__ in, double* __restrict__ out,
+                               int take_sqrt, double tol, int32_t* __restrict__ done) {
+  __shared__ double red[1024];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) acc += in[i];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    double r = take_sqrt ? sqrt(red[0]) : red[0];
+    out[0] = r;
+    if (done) done[0] = (r < tol) ? 1 : 0;
+  }
+}
+
+// ----------------------------------------------------- LU refactorization
+// Row-by-row (up-looking) elimination on the static pattern, level by level,
+// one wavefront per row with the row staged in LDS.  For each L entry
+// (i, k) in ascending k: l_ik = a_ik / u_kk, then a_ij -= l_ik u_kj for the
+// U entries of row k (target positions precomputed).  Rows of one level are
+// independent; levels are separated by workgroup barriers.  A pivot with
+// |u_ii| <= pivtol * max_j |a_ij| records the row in status[0] (row + 1).
+__global__ void k_refactor(int lev0, int lev1, const int32_t* __restrict__ lev_ptr,
+                           const int32_t* __restrict__ lev_rows, const int32_t* __restrict__ ptr,
+                           const int32_t* __restrict__ col, const int32_t* __restrict__ diag,
+                           const int64_t* __restrict__ upd_ptr, const int32_t* __restrict__ upd_tgt,
+                           double* __restrict__ a, int maxrow, double pivtol,
+                           int32_t* __restrict__ status) {
+  extern __shared__ double lds[];
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int nwave = blockDim.x >> 6;
+  const int gw = blockIdx.x * nwave + wave;          // global wave id
+  const int gnw = gridDim.x * nwave;
+  double* w = lds + (size_t)wave * maxrow;
+  for (int lev = lev0; lev < lev1; ++lev) {
+    for (int r = lev_ptr[lev] + gw; r < lev_ptr[lev + 1]; r += gnw) {
+      const int i = lev_rows[r];
+      const int p0 = ptr[i], pdg = diag[i], p1 = ptr[i + 1];
+      double amax = 0.0;
+      for (int q = lane; q < p1 - p0; q += 64) {
+        double v = a[p0 + q];
+        w[q] = v;
+        amax = fmax(amax, fabs(v));
+      }
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      for (int p = p0; p < pdg; ++p) {
+        const int k = col[p];
+        const int dk = diag[k];
+        const double l = w[p - p0] / a[dk];
+        const int64_t u0 = upd_ptr[p], nu = upd_ptr[p + 1] - u0;
+        for (int64_t t = lane; t < nu; t += 64) {
+          int tg = upd_tgt[u0 + t] - p0;
+          w[tg] -= l * a[dk + 1 + (int)t];
+        }
+        if (lane == 0) w[p - p0] = l;
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+      }
+      for (int off = 32; off > 0; off >>= 1) amax = fmax(amax, __shfl_xor(amax, off, 64));
+      for (int q = lane; q < p1 - p0; q += 64) a[p0 + q] = w[q];
+      if (lane == 0) {
+        double piv = w[pdg - p0];
+        if (!(fabs(piv) > pivtol * amax)) atomicCAS(status, 0, i + 1);
+      }
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+    }
+    __syncthreads();
+  }
+}
+
+// -------------------------------------------- level-scheduled triangular
+// Solves T X = scale * B in place (X holds B on entry) for TW columns per
+// workgroup, all columns of a workgroup advancing level by level.  LOWER:
+// row i uses entries [ptr[i], diag[i]); otherwise (diag[i], ptr[i+1]).
+// UNIT: no division by the diagonal value val[diag[i]].
+template <int TW, bool LOWER, bool UNIT>
+__global__ void k_trsv_batch(int nlev, const int32_t* __restrict__ lev_ptr,
+                             const int32_t* __restrict__ lev_rows, const int32_t* __restrict__ ptr,
+                             const int32_t* __restrict__ col, const int32_t* __restrict__ diag,
+                             const double* __restrict__ val, double* __restrict__ X, int ld,
+                             int ncols, double scale) {
+  const int slot = threadIdx.x / TW;
+  const int nslot = blockDim.x / TW;
+  const int c = blockIdx.x * TW + (threadIdx.x % TW);
+  const bool active = c < ncols;
+  for (int lev = 0; lev < nlev; ++lev) {
+    const int r1 = lev_ptr[lev + 1];
+    for (int r = lev_ptr[lev] + slot; r < r1; r += nslot) {
+      const int i = lev_rows[r];
+      int pa, pb;
+      if (LOWER) { pa = ptr[i]; pb = diag[i]; } else { pa = diag[i] + 1; pb = ptr[i + 1]; }
+      if (active) {
+        double acc = scale * X[(size_t)i * ld + c];
+        for (int p = pa; p < pb; ++p) acc -= val[p] * X[(size_t)col[p] * ld + c];
+        if (!UNIT) acc /= val[diag[i]];
+        X[(size_t)i * ld + c] = acc;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------------ SpMM
+// Y[i, c] = (Yadd ? Yadd[i, c] : 0) + alpha * sum_p v(p) * s(col) * X[col, c]
+// with v(p) = val[valpos ? valpos[p] : p], s = xscale ? xscale[col] : 1.
+__global__ void k_spmm(int nrows, const int32_t* __restrict__ ptr, const int32_t* __restrict__ colidx,
+                       const double* __restrict__ val, const int32_t* __restrict__ valpos,
+                       const double* __restrict__ xscale, const double* __restrict__ X, int ldx,
+                       int ncols, double alpha, const double* __restrict__ Yadd, int ldya,
+                       double* __restrict__ Y, int ldy) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = blockIdx.y * blockDim.y + threadIdx.y;
+  if (i >= nrows || c >= ncols) return;
+  double acc = 0.0;
+  for (int p = ptr[i]; p < ptr[i + 1]; ++p) {
+    const int j = colidx[p];
+    double v = val[valpos ? valpos[p] : p];
+    if (xscale) v *= xscale[j];
+    acc += v * X[(size_t)j * ldx + c];
+  }
+  acc *= alpha;
+  if (Yadd) acc += Yadd[(size_t)i * ldya + c];
+  Y[(size_t)i * ldy + c] = acc;
+}
+
+// copy an [n x ncols] block between leading dimensions
+__global__ void k_copy_block(int n, int ncols, const double* __restrict__ src, int lds_,
+                             double* __restrict__ dst, int ldd) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = blockIdx.y * blockDim.y + threadIdx.y;
+  if (i < n && c < ncols) dst[(size_t)i * ldd + c] = src[(size_t)i * lds_ + c];
+}
+
+// identity columns j0 .. j0 + ncols - 1 of an n x n identity, as [n x ncols]
+__global__ void k_identity_block(int n, int ncols, int j0, double* __restrict__ dst, int ldd) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = blockIdx.y * blockDim.y + threadIdx.y;
+  if (i < n && c < ncols) dst[(size_t)i * ldd + c] = (i == j0 + c) ? 1.0 : 0.0;
+}
+
+// ----------------------------------------------- AL constraints, weights
+struct ALArgs {
+  int nb, nl, npq, npv, ng, m, nx, nu;
+  int ref, gen_ref;
+  double base, rho;
+  const double* sigf;       // [1] sigma_f (device)
+  const int32_t* pq;        // [npq]
+  const int32_t* pv;        // [npv]
+  const int32_t* gen_pidx;  // [ng] control index of p_g (PV), -1 for the slack
+  const int32_t* pv_gen;    // [npv] generator at each PV bus
+  const double* c2;
+  const double* c1;
+  const double* c0;
+  const double* rec;        // branch records
+  const double* Pbus;       // [nb] bus injections P_i
+  const double* Qbus;       // [nb]
+  const double* vm;         // [nb]
+  const double* pd;
+  const double* qd;
+  const double* u;
+  const double* s;          // [m]
+  const double* y;          // [m]
+  const double* sigma_c;    // [m]
+};
+
+// c_k, the AL weight w_k = d phi / d c_k and the phi term of constraint k
+// (terms[k]); generator cost terms sigma_f f_g in terms[m + g].
+__global__ void k_constraints(ALArgs A, double* __restrict__ c, double* __restrict__ w,
+                              double* __restrict__ terms) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < A.m) {
+    double ck;
+    if (k < A.nl) {
+      const double* o = A.rec + (size_t)k * RECW;
+      ck = o[0] * o[0] + o[1] * o[1];
+    } else if (k < 2 * A.nl) {
+      const double* o = A.rec + (size_t)(k - A.nl) * RECW;
+      ck = o[2] * o[2] + o[3] * o[3];
+    } else if (k < 2 * A.nl + A.npq) {
+      ck = A.vm[A.pq[k - 2 * A.nl]];
+    } else if (k == 2 * A.nl + A.npq) {
+      ck = A.Pbus[A.ref] + A.pd[A.ref];
+    } else if (k == 2 * A.nl + A.npq + 1) {
+      ck = A.Qbus[A.ref] + A.qd[A.ref];
+    } else {
+      const int b = A.pv[k - 2 * A.nl - A.npq - 2];
+      ck = A.Qbus[b] + A.qd[b];
+    }
+    const double sc = A.sigma_c[k];
+    const double r = sc * (ck - A.s[k]);
+    if (c) c[k] = ck;
+    if (w) w[k] = sc * (A.y[k] + A.rho * r);
+    if (terms) terms[k] = A.y[k] * r + 0.5 * A.rho * r * r;
+  } else if (k < A.m + A.ng) {
+    const int gi = k - A.m;
+    const double p = gi == A.gen_ref ? A.Pbus[A.ref] + A.pd[A.ref] : A.u[A.gen_pidx[gi]];
+    const double pm = A.base * p;
+    if (terms) terms[k] = A.sigf[0] * (A.c2[gi] * pm * pm + A.c1[gi] * pm + A.c0[gi]);
+  }
+}
+
+// Weights of the bus injections in l = phi + lambda^T g: a_i on P_i and
+// b_i on Q_i (lambda may be null); threads past nb fill the rank-one
+// coefficients kappa of (p_ref, q_ref, q_pv).
+__global__ void k_bus_weights(ALArgs A, const double* __restrict__ w, const double* __restrict__ lam,
+                              const int32_t* __restrict__ rowP, const int32_t* __restrict__ rowQ,
+                              const int32_t* __restrict__ bus_pvpos, double* __restrict__ a,
+                              double* __restrict__ b, double* __restrict__ kappa) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int kp = 2 * A.nl + A.npq;
+  const double sigma_f = A.sigf[0];
+  if (i < A.nb) {
+    double ai = 0.0, bi = 0.0;
+    if (lam) {
+      if (rowP[i] >= 0) ai += lam[rowP[i]];
+      if (rowQ[i] >= 0) bi += lam[rowQ[i]];
+    }
+    if (i == A.ref) {
+      const double pref = A.Pbus[A.ref] + A.pd[A.ref];
+      const int gr = A.gen_ref;
+      ai += sigma_f * A.base * (2.0 * A.c2[gr] * A.base * pref + A.c1[gr]) + w[kp];
+      bi += w[kp + 1];
+    }
+    const int pp = bus_pvpos[i];
+    if (pp >= 0) bi += w[kp + 2 + pp];
+    a[i] = ai;
+    b[i] = bi;
+  } else if (i < A.nb + 2 + A.npv) {
+    const int r = i - A.nb;
+    const double sc = A.sigma_c[kp + r];
+    double kap = A.rho * sc * sc;
+    if (r == 0) kap += sigma_f * 2.0 * A.c2[A.gen_ref] * A.base * A.base;
+    kappa[r] = kap;
+  }
+}
+
+// Second-order branch records: for l = sum_e (a P_e + b Q_e + w_h h_e) +
+// rho/2 (sigma_h h_e)^2-type curvature, the local gradient (4) and the
+// local 4x4 Hessian W in (theta_f, theta_t, v_f, v_t):
+//   alpha_e = a + 2 w_h P_e, beta_e = b + 2 w_h Q_e,
+//   W = sum_e d2(alpha_e P_e + beta_e Q_e) + 2 w_h (dP dP^T + dQ dQ^T)
+//       + kappa_h dh dh^T,  dh = 2 P dP + 2 Q dQ,  kappa_h = rho sigma_h^2.
+__global__ void k_branch_second(int nl, const int32_t* __restrict__ bf, const int32_t* __restrict__ bt,
+                                const double* __restrict__ br, const double* __restrict__ bx,
+                                const double* __restrict__ bb, const double* __restrict__ th,
+                                const double* __restrict__ vm, const double* __restrict__ rec,
+                                const double* __restrict__ a, const double* __restrict__ b,
+                                const double* __restrict__ w, const double* __restrict__ sigma_c,
+                                double rho, double* __restrict__ wrec) {
+  int l = blockIdx.x * blockDim.x + threadIdx.x;
+  if (l >= nl) return;
+  const int f = bf[l], t = bt[l];
+  const double r = br[l], x = bx[l], bsh = 0.5 * bb[l];
+  const double z2 = r * r + x * x;
+  const double gs = r / z2, bs = -x / z2;
+  const double Goo = gs, Boo = bs + bsh, Gm = -gs, Bm = -bs;
+  const double vf = vm[f], vt = vm[t];
+  double sn, cs;
+  sincos(th[f] - th[t], &sn, &cs);
+  const double vv = vf * vt;
+  const double Af = Gm * cs + Bm * sn, Cf = Gm * sn - Bm * cs;
+  const double At = Gm * cs - Bm * sn, Ct = -Gm * sn - Bm * cs;
+  const double* o = rec + (size_t)l * RECW;
+  double W[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) W[i][j] = 0.0;
+  double gl[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int e = 0; e < 2; ++e) {
+    const int bus = e == 0 ? f : t;
+    const int kc = e == 0 ? l : nl + l;
+    const double wh = w[kc];
+    const double sh = sigma_c[kc];
+    const double P = o[2 * e], Q = o[2 * e + 1];
+    const double* dP = o + 4 + 8 * e;
+    const double* dQ = o + 8 + 8 * e;
+    const double al = a[bus] + 2.0 * wh * P;
+    const double be = b[bus] + 2.0 * wh * Q;
+    // second derivatives of al * P_e + be * Q_e
+    double T, Tp, K;
+    if (e == 0) {
+      T = al * Af + be * Cf;
+      Tp = -al * Cf + be * Af;
+      K = al * Goo - be * Boo;
+    } else {
+      T = al * At + be * Ct;
+      Tp = al * Ct - be * At;
+      K = al * Goo - be * Boo;
+    }
+    W[0][0] += -vv * T;
+    W[1][1] += -vv * T;
+    W[0][1] += vv * T;
+    W[0][2] += vt * Tp;
+    W[0][3] += vf * Tp;
+    W[1][2] += -vt * Tp;
+    W[1][3] += -vf * Tp;
+    W[2][3] += T;
+    W[2 + e][2 + e] += 2.0 * K;
+    const double kap = rho * sh * sh;
+    double dh[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      dh[i] = 2.0 * (P * dP[i] + Q * dQ[i]);
+      gl[i] += al * dP[i] + be * dQ[i];
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = i; j < 4; ++j)
+        W[i][j] += 2.0 * wh * (dP[i] * dP[j] + dQ[i] * dQ[j]) + kap * dh[i] * dh[j];
+  }
+  double* q = wrec + (size_t)l * WREC;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) q[4 * i + j] = i <= j ? W[i][j] : W[j][i];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) q[16 + i] = gl[i];
+}
+
+// Gradient of the (Lagrangian) function over all variables: gathered
+// branch-local gradients plus the terms not carried by branches:
+// v_pq: w of the voltage constraint; p_pv: sigma_f f'(p) - lambda_P.
+struct VarArgs {
+  int nvar, nx, npq, npv, nl;
+  double base;
+  const double* sigf;    // [1] sigma_f (device)
+  const int32_t* kind;   // 0 theta, 1 v_pq, 2 v control, 3 p_pv
+  const int32_t* aux;    // v_pq: pq position; p_pv: pv position
+  const int32_t* pv_gen;
+  const int32_t* pv;
+  const int32_t* rowP;
+  const double* c2;
+  const double* c1;
+  const double* u;
+};
+
+__global__ void k_var_grad(VarArgs V, const int32_t* __restrict__ ptr, const int32_t* __restrict__ src,
+                           const double* __restrict__ wrec, const double* __restrict__ w,
+                           const double* __restrict__ lam, double* __restrict__ out) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= V.nvar) return;
+  double acc = 0.0;
+  for (int j = ptr[c]; j < ptr[c + 1]; ++j) acc += wrec[src[j]];
+  const int kd = V.kind[c];
+  if (kd == 1) {
+    acc += w[2 * V.nl + V.aux[c]];
+  } else if (kd == 3) {
+    const int k = V.aux[c];
+    const int gi = V.pv_gen[k];
+    const double p = V.u[1 + V.npv + k];
+    acc += V.sigf[0] * V.base * (2.0 * V.c2[gi] * V.base * p + V.c1[gi]);
+    if (lam) acc -= lam[V.rowP[V.pv[k]]];
+  }
+  out[c] = acc;
+}
+
+// Diagonal terms of K not carried by branches: rho sigma_v^2 on v_pq and
+// the PV cost curvature sigma_f 2 c2 B^2 on p_pv.
+__global__ void k_k_diag(VarArgs V, const int32_t* __restrict__ kdiag, const double* __restrict__ sigma_c,
+                         double rho, double* __restrict__ kval) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= V.nvar) return;
+  const int kd = V.kind[c];
+  if (kd == 1) {
+    const double sv = sigma_c[2 * V.nl + V.aux[c]];
+    kval[kdiag[c]] += rho * sv * sv;
+  } else if (kd == 3) {
+    const int gi = V.pv_gen[V.aux[c]];
+    kval[kdiag[c]] += V.sigf[0] * 2.0 * V.c2[gi] * V.base * V.base;
+  }
+}
+
+__global__ void k_axpy(int n, double a, const double* __restrict__ x, double* __restrict__ y) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] += a * x[i];
+}
+
+__global__ void k_set_status(int32_t* __restrict__ st, int32_t it, int32_t conv,
+                             const double* __restrict__ rsrc, double* __restrict__ rdst) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    st[0] = it;
+    st[1] = conv;
+    if (rdst) rdst[0] = rsrc[0];
+  }
+}
+
+__global__ void k_fill_int(int n, int32_t* __restrict__ p, int32_t v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+// ------------------------------------------------------------ dense step
+// K = (H + H^T)/2 + diag + delta I, written to both triangles.
+__global__ void k_symmetrize(int n, double* __restrict__ K, const double* __restrict__ d, double delta) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = blockIdx.y * blockDim.y + threadIdx.y;
+  if (i >= n || j > i) return;
+  if (i == j) {
+    K[(size_t)i * n + i] += (d ? d[i] : 0.0) + delta;
+  } else {
+    const double v = 0.5 * (K[(size_t)i * n + j] + K[(size_t)j * n + i]);
+    K[(size_t)i * n + j] = v;
+    K[(size_t)j * n + i] = v;
+  }
+}
+
+constexpr int CB = 64;  // Cholesky panel width
+
+// Unblocked Cholesky of the diagonal block A[k0:k0+nb, k0:k0+nb] in LDS.
+__global__ void k_chol_diag(int n, int k0, double* __restrict__ A, int32_t* __restrict__ info) {
+  __shared__ double T[CB][CB + 1];
+  __shared__ int bad;
+  if (info[0] != 0) return;
+  const int nb = min(CB, n - k0);
+  for (int e = threadIdx.x; e < nb * nb; e += blockDim.x) {
+    int i = e / nb, j = e % nb;
+    T[i][j] = j <= i ? A[(size_t)(k0 + i) * n + k0 + j] : 0.0;
+  }
+  if (threadIdx.x == 0) bad = 0;
+  __syncthreads();
+  for (int j = 0; j < nb; ++j) {
+    if (threadIdx.x == 0) {
+      double d = T[j][j];
+      if (!(d > 0.0)) {
+        bad = j + 1;
+      } else {
+        T[j][j] = sqrt(d);
+      }
+    }
+    __syncthreads();
+    if (bad) break;
+    const double djj = T[j][j];
+    for (int i = j + 1 + threadIdx.x; i < nb; i += blockDim.x) T[i][j] /= djj;
+    __syncthreads();
+    for (int e = threadIdx.x; e < (nb - j - 1) * (nb - j - 1); e += blockDim.x) {
+      int i = j + 1 + e / (nb - j - 1), c = j + 1 + e % (nb - j - 1);
+      if (c <= i) T[i][c] -= T[i][j] * T[c][j];
+    }
+    __syncthreads();
+  }
+  if (bad) {
+    if (threadIdx.x == 0) info[0] = k0 + bad;
+    return;
+  }
+  for (int e = threadIdx.x; e < nb * nb; e += blockDim.x) {
+    int i = e / nb, j = e % nb;
+    if (j <= i) A[(size_t)(k0 + i) * n + k0 + j] = T[i][j];
+  }
+}
+
+// Panel below the diagonal block: A21 <- A21 L11^{-T}; one row per thread.
+__global__ void k_chol_trsm(int n, int k0, double* __restrict__ A, const int32_t* __restrict__ info) {
+  __shared__ double L[CB][CB + 1];
+  if (info[0] != 0) return;
+  const int nb = min(CB, n - k0);
+  for (int e = threadIdx.x; e < nb * nb; e += blockDim.x) {
+    int i = e / nb, j = e % nb;
+    L[i][j] = j <= i ? A[(size_t)(k0 + i) * n + k0 + j] : 0.0;
+  }
+  __syncthreads();
+  const int row = k0 + nb + blockIdx.x * blockDim.x + threadIdx.x;
+  if (row >= n) return;
+  double x[CB];
+  double* a = A + (size_t)row * n + k0;
+  for (int j = 0; j < nb; ++j) {
+    double v = a[j];
+    for (int k = 0; k < j; ++k) v -= x[k] * L[j][k];
+    x[j] = v / L[j][j];
+  }
+  for (int j = 0; j < nb; ++j) a[j] = x[j];
+}
+
+// Trailing update A22 -= L21 L21^T on lower-triangle tiles of 64 x 64.
+__global__ void k_chol_update(int n, int k0, double* __restrict__ A, const int32_t* __restrict__ info) {
+  __shared__ double Ls[CB][CB + 1];
+  __shared__ double Rs[CB][CB + 1];
+  if (info[0] != 0) return;
+  const int nb = min(CB, n - k0);
+  const int base = k0 + nb;
+  const int ti = blockIdx.y, tj = blockIdx.x;
+  if (tj > ti) return;
+  const int i0 = base + ti * CB, j0 = base + tj * CB;
+  for (int e = threadIdx.x; e < CB * CB; e += blockDim.x) {
+    int r = e / CB, k = e % CB;
+    Ls[r][k] = (i0 + r < n && k < nb) ? A[(size_t)(i0 + r) * n + k0 + k] : 0.0;
+    Rs[r][k] = (j0 + r < n && k < nb) ? A[(size_t)(j0 + r) * n + k0 + k] : 0.0;
+  }
+  __syncthreads();
+  // 256 threads, each a 4 x 4 sub-tile
+  const int tr = (threadIdx.x / 16) * 4, tc = (threadIdx.x % 16) * 4;
+  double acc[4][4] = {};
+  for (int k = 0; k < nb; ++k)
+#pragma unroll
+    for (int p = 0; p < 4; ++p)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) acc[p][q] += Ls[tr + p][k] * Rs[tc + q][k];
+#pragma unroll
+  for (int p = 0; p < 4; ++p)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      int i = i0 + tr + p, j = j0 + tc + q;
+      if (i < n && j < n && j <= i) A[(size_t)i * n + j] -= acc[p][q];
+    }
+}
+
+// Forward/back substitution with the lower factor (single workgroup):
+// L y = -rhs, L^T step = y.
+__global__ void k_chol_solve(int n, const double* __restrict__ L, const double* __restrict__ rhs,
+                             double* __restrict__ step, double* __restrict__ work,
+                             const int32_t* __restrict__ info) {
+  if (info[0] != 0) return;
+  __shared__ double xs[CB];
+  double* yv = work;
+  // forward: blocks of CB rows
+  for (int b0 = 0; b0 < n; b0 += CB) {
+    const int nb = min(CB, n - b0);
+    // partial dot products with solved entries, one row per thread group
+    for (int r = threadIdx.x; r < nb; r += blockDim.x) {
+      double v = -rhs[b0 + r];
+      const double* Lr = L + (size_t)(b0 + r) * n;
+      for (int k = 0; k < b0; ++k) v -= Lr[k] * yv[k];
+      xs[r] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      for (int r = 0; r < nb; ++r) {
+        double v = xs[r];
+        const double* Lr = L + (size_t)(b0 + r) * n + b0;
+        for (int k = 0; k < r; ++k) v -= Lr[k] * xs[k];
+        xs[r] = v / Lr[r];
+      }
+    }
+    __syncthreads();
+    for (int r = threadIdx.x; r < nb; r += blockDim.x) yv[b0 + r] = xs[r];
+    __syncthreads();
+  }
+  // backward with L^T: step_i = (y_i - sum_{k>i} L_ki step_k) / L_ii
+  for (int b1 = n; b1 > 0; b1 -= CB) {
+    const int b0 = max(0, b1 - CB), nb = b1 - b0;
+    for (int r = threadIdx.x; r < nb; r += blockDim.x) {
+      double v = yv[b0 + r];
+      for (int k = b1; k < n; ++k) v -= L[(size_t)k * n + b0 + r] * step[k];
+      xs[r] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      for (int r = nb - 1; r >= 0; --r) {
+        double v = xs[r];
+        for (int k = r + 1; k < nb; ++k) v -= L[(size_t)(b0 + k) * n + b0 + r] * xs[k];
+        xs[r] = v / L[(size_t)(b0 + r) * n + b0 + r];
+      }
+    }
+    __syncthreads();
+    for (int r = threadIdx.x; r < nb; r += blockDim.x) step[b0 + r] = xs[r];
+    __syncthreads();
+  }
+}
+
+}  // namespace dev
+}  // namespace rpf

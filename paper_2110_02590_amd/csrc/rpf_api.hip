@@ -1,0 +1,690 @@
+// C ABI of the reduced-space hot path: device buffers owned by the handle,
+// launch sequences for the power flow, AL value, reduced gradient, batched
+// reduced Hessian-vector products and the dense Cholesky step.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/rpf.h"
+#include "kernels.hpp"
+#include "presolve.hpp"
+
+using namespace rpf;
+using namespace rpf::dev;
+
+namespace {
+
+thread_local std::string g_err;
+
+int set_err(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+struct HipError : std::runtime_error {
+  using std::runtime_error::runtime_error;
+};
+
+#define HIPCHK(call)                                                                  \
+  do {                                                                                \
+    hipError_t e_ = (call);                                                           \
+    if (e_ != hipSuccess)                                                             \
+      throw HipError(std::string(#call) + ": " + hipGetErrorString(e_));              \
+  } while (0)
+
+#define LAUNCHCHK() HIPCHK(hipGetLastError())
+
+inline int cdiv(long a, long b) { return (int)((a + b - 1) / b); }
+
+}  // namespace
+
+struct rpf_grid {
+  Presolve P;
+  GridData G;
+  int max_batch = 0;
+  int nr1 = 0;
+  std::vector<void*> allocs;
+  bool have_point = false;
+  double rho = 0.0;
+
+  // ------------------------------------------------------- device topology
+  int32_t *th_var, *v_var, *rowP, *rowQ, *x_i2p, *bus_pvpos;
+  int32_t *br_f, *br_t;
+  double *br_r, *br_x, *br_b;
+  int32_t *pb_ptr, *pb_src, *qb_src;
+  int32_t *lu_ptr, *lu_col, *lu_diag, *lut_src;
+  int32_t *lo_ptr, *lo_rows, *up_ptr, *up_rows;
+  int64_t* upd_ptr;
+  int32_t* upd_tgt;
+  int32_t *jx_sp, *jx_s;
+  int32_t *ju_ptr, *ju_col, *ju_sp, *ju_s, *jut_ptr, *jut_col, *jut_pos;
+  double* ju_const;
+  int32_t *g_sp, *g_s, *row_bus, *row_isq, *row_pvar;
+  int32_t *G_ptr, *G_col, *G_sp, *G_s, *Gt_ptr, *Gt_col, *Gt_pos;
+  int32_t *K_ptr, *K_col, *K_sp, *K_s, *K_diag, *vg_sp, *vg_s;
+  int32_t *pq, *pv, *gen_pidx, *pv_gen, *var_kind, *var_aux;
+  double *c2, *c1, *c0;
+
+  // ------------------------------------------------------------ workspace
+  double *xi, *th, *vm, *rec, *g, *partial, *resid_d, *d;
+  double *luv, *lutv, *juv, *Gv, *Kv, *wrec, *kappa, *a, *b, *Pbus, *Qbus;
+  double *cvec, *wvec, *terms, *varg, *lam;
+  double *D, *Y, *T, *chol_work;
+  int32_t *flag, *piv_status;
+  double* host_resid;  // pinned
+
+  // refactor launch plan: (lev0, lev1, nblocks)
+  struct RfStep {
+    int lev0, lev1, nblocks;
+  };
+  std::vector<RfStep> rf_plan;
+  int rf_waves = 16;
+
+  template <class T>
+  T* up(const std::vector<T>& v) {
+    size_t n = std::max<size_t>(v.size(), 1);
+    void* p = nullptr;
+    if (hipMalloc(&p, n * sizeof(T)) != hipSuccess) throw std::bad_alloc();
+    allocs.push_back(p);
+    if (!v.empty()) HIPCHK(hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+    return (T*)p;
+  }
+  template <class T>
+  T* alloc(size_t n) {
+    void* p = nullptr;
+    if (hipMalloc(&p, std::max<size_t>(n, 1) * sizeof(T)) != hipSuccess) throw std::bad_alloc();
+    allocs.push_back(p);
+    HIPCHK(hipMemset(p, 0, std::max<size_t>(n, 1) * sizeof(T)));
+    return (T*)p;
+  }
+  ~rpf_grid() {
+    for (void* p : allocs) (void)hipFree(p);
+    if (host_resid) (void)hipHostFree(host_resid);
+  }
+};
+
+namespace {
+
+void setup(rpf_grid* h) {
+  const Presolve& P = h->P;
+  const GridData& G = h->G;
+  h->nr1 = P.nr1;
+  std::vector<int32_t> bus_pvpos(P.nb, -1);
+  for (int k = 0; k < P.npv; ++k) bus_pvpos[P.pv[k]] = k;
+  h->th_var = h->up(P.th_var);
+  h->v_var = h->up(P.v_var);
+  h->rowP = h->up(P.rowP);
+  h->rowQ = h->up(P.rowQ);
+  h->x_i2p = h->up(P.x_int2paper);
+  h->bus_pvpos = h->up(bus_pvpos);
+  h->br_f = h->up(G.br_from);
+  h->br_t = h->up(G.br_to);
+  h->br_r = h->up(G.br_r);
+  h->br_x = h->up(G.br_x);
+  h->br_b = h->up(G.br_b);
+  // bus injection gather lists
+  std::vector<int32_t> pbs, qbs;
+  for (int i = 0; i < P.nb; ++i)
+    for (int q = P.inc_ptr[i]; q < P.inc_ptr[i + 1]; ++q) {
+      int l = P.inc_end[q] >> 1, e = P.inc_end[q] & 1;
+      pbs.push_back(l * RECW + 2 * e);
+      qbs.push_back(l * RECW + 2 * e + 1);
+    }
+  h->pb_ptr = h->up(P.inc_ptr);
+  h->pb_src = h->up(pbs);
+  h->qb_src = h->up(qbs);
+  h->lu_ptr = h->up(P.lu_ptr);
+  h->lu_col = h->up(P.lu_col);
+  h->lu_diag = h->up(P.lu_diag);
+  h->lut_src = h->up(P.lut_src);
+  h->lo_ptr = h->up(P.lev_lo.ptr);
+  h->lo_rows = h->up(P.lev_lo.rows);
+  h->up_ptr = h->up(P.lev_up.ptr);
+  h->up_rows = h->up(P.lev_up.rows);
+  h->upd_ptr = h->up(P.upd_ptr);
+  h->upd_tgt = h->up(P.upd_tgt);
+  h->jx_sp = h->up(P.jx_src_ptr);
+  h->jx_s = h->up(P.jx_src);
+  h->ju_ptr = h->up(P.ju_ptr);
+  h->ju_col = h->up(P.ju_col);
+  h->ju_sp = h->up(P.ju_src_ptr);
+  h->ju_s = h->up(P.ju_src);
+  h->ju_const = h->up(P.ju_const);
+  h->jut_ptr = h->up(P.jut_ptr);
+  h->jut_col = h->up(P.jut_col);
+  h->jut_pos = h->up(P.jut_srcpos);
+  h->g_sp = h->up(P.g_src_ptr);
+  h->g_s = h->up(P.g_src);
+  h->row_bus = h->up(P.row_bus);
+  h->row_isq = h->up(P.row_isq);
+  h->row_pvar = h->up(P.row_pvar);
+  h->G_ptr = h->up(P.G_ptr);
+  h->G_col = h->up(P.G_col);
+  h->G_sp = h->up(P.G_src_ptr);
+  h->G_s = h->up(P.G_src);
+  h->Gt_ptr = h->up(P.Gt_ptr);
+  h->Gt_col = h->up(P.Gt_col);
+  h->Gt_pos = h->up(P.Gt_srcpos);
+  h->K_ptr = h->up(P.K_ptr);
+  h->K_col = h->up(P.K_col);
+  h->K_sp = h->up(P.K_src_ptr);
+  h->K_s = h->up(P.K_src);
+  h->K_diag = h->up(P.K_diag);
+  h->vg_sp = h->up(P.vg_src_ptr);
+  h->vg_s = h->up(P.vg_src);
+  h->pq = h->up(P.pq);
+  h->pv = h->up(P.pv);
+  std::vector<int32_t> gen_pidx(P.ng, -1), pv_gen(P.npv, 0);
+  for (int k = 0; k < P.npv; ++k) {
+    int gi = P.gen_at[P.pv[k]];
+    gen_pidx[gi] = 1 + P.npv + k;
+    pv_gen[k] = gi;
+  }
+  h->gen_pidx = h->up(gen_pidx);
+  h->pv_gen = h->up(pv_gen);
+  std::vector<int32_t> kind(P.nvar, 0), aux(P.nvar, -1);
+  for (int c = 0; c < P.nx; ++c)
+    if (P.var_isv[c]) {
+      kind[c] = 1;
+      int bus = P.var_bus[c];
+      aux[c] = (int)(std::lower_bound(P.pq.begin(), P.pq.end(), bus) - P.pq.begin());
+    }
+  kind[P.nx] = 2;
+  for (int k = 0; k < P.npv; ++k) {
+    kind[P.nx + 1 + k] = 2;
+    kind[P.nx + 1 + P.npv + k] = 3;
+    aux[P.nx + 1 + P.npv + k] = k;
+  }
+  h->var_kind = h->up(kind);
+  h->var_aux = h->up(aux);
+  h->c2 = h->up(G.c2);
+  h->c1 = h->up(G.c1);
+  h->c0 = h->up(G.c0);
+
+  const size_t nnz = P.lu_col.size();
+  h->xi = h->alloc<double>(P.nx);
+  h->th = h->alloc<double>(P.nb);
+  h->vm = h->alloc<double>(P.nb);
+  h->rec = h->alloc<double>((size_t)P.nl * RECW);
+  h->g = h->alloc<double>(P.nx);
+  h->partial = h->alloc<double>(cdiv(std::max(P.nx, P.m + P.ng), 256) + 8);
+  h->resid_d = h->alloc<double>(4);
+  h->d = h->alloc<double>(P.nx);
+  h->luv = h->alloc<double>(nnz);
+  h->lutv = h->alloc<double>(nnz);
+  h->juv = h->alloc<double>(P.ju_col.size());
+  h->Gv = h->alloc<double>(P.G_col.size());
+  h->Kv = h->alloc<double>(P.K_col.size());
+  h->wrec = h->alloc<double>((size_t)P.nl * WREC);
+  h->kappa = h->alloc<double>(P.nr1);
+  h->a = h->alloc<double>(P.nb);
+  h->b = h->alloc<double>(P.nb);
+  h->Pbus = h->alloc<double>(P.nb);
+  h->Qbus = h->alloc<double>(P.nb);
+  h->cvec = h->alloc<double>(P.m);
+  h->wvec = h->alloc<double>(P.m);
+  h->terms = h->alloc<double>(P.m + P.ng);
+  h->varg = h->alloc<double>(P.nvar);
+  h->lam = h->alloc<double>(P.nx);
+  h->D = h->alloc<double>((size_t)P.nvar * h->max_batch);
+  h->Y = h->alloc<double>((size_t)P.nvar * h->max_batch);
+  h->T = h->alloc<double>((size_t)P.nr1 * h->max_batch);
+  h->chol_work = h->alloc<double>(P.nu);
+  h->flag = h->alloc<int32_t>(4);
+  h->piv_status = h->alloc<int32_t>(4);
+  HIPCHK(hipHostMalloc((void**)&h->host_resid, sizeof(double) * 4, hipHostMallocDefault));
+
+  // refactor plan: wide levels get a multi-workgroup launch each, runs of
+  // narrow levels share one single-workgroup launch
+  int maxrow = std::max(P.max_lu_row, 1);
+  int waves = 16;
+  while (waves > 1 && (size_t)waves * maxrow * 8 > 65536) waves /= 2;
+  if ((size_t)waves * maxrow * 8 > 65536) throw std::runtime_error("LU row too long for LDS staging");
+  h->rf_waves = waves;
+  const auto& lp = P.lev_lo.ptr;
+  int nlev = P.lev_lo.nlev();
+  int k = 0;
+  while (k < nlev) {
+    int rows = lp[k + 1] - lp[k];
+    if (rows > 2 * waves) {
+      h->rf_plan.push_back({k, k + 1, cdiv(rows, waves)});
+      ++k;
+    } else {
+      int k1 = k;
+      while (k1 < nlev && lp[k1 + 1] - lp[k1] <= 2 * waves) ++k1;
+      h->rf_plan.push_back({k, k1, 1});
+      k = k1;
+    }
+  }
+}
+
+// ---------------------------------------------------------- launch helpers
+void state_and_records(rpf_grid* h, const double* u, hipStream_t s) {
+  const Presolve& P = h->P;
+  k_bus_state<<<cdiv(P.nb, 256), 256, 0, s>>>(P.nb, P.nx, h->th_var, h->v_var, h->xi, u, h->th, h->vm);
+  LAUNCHCHK();
+  k_branch_eval<<<cdiv(P.nl, 256), 256, 0, s>>>(P.nl, h->br_f, h->br_t, h->br_r, h->br_x, h->br_b, h->th,
+                                                 h->vm, h->rec);
+  LAUNCHCHK();
+}
+
+void x_in(rpf_grid* h, const double* x, hipStream_t s) {
+  k_permute_gather<<<cdiv(h->P.nx, 256), 256, 0, s>>>(h->P.nx, h->x_i2p, x, h->xi);
+  LAUNCHCHK();
+}
+
+void refactor(rpf_grid* h, hipStream_t s) {
+  const Presolve& P = h->P;
+  const size_t nnz = P.lu_col.size();
+  k_gather_sum<<<cdiv(nnz, 256), 256, 0, s>>>((int)nnz, h->jx_sp, h->jx_s, h->rec, nullptr, h->luv);
+  LAUNCHCHK();
+  const int maxrow = std::max(P.max_lu_row, 1);
+  const size_t shm = (size_t)h->rf_waves * maxrow * sizeof(double);
+  for (auto& st : h->rf_plan) {
+    k_refactor<<<st.nblocks, 64 * h->rf_waves, shm, s>>>(st.lev0, st.lev1, h->lo_ptr, h->lo_rows, h->lu_ptr,
+                                                         h->lu_col, h->lu_diag, h->upd_ptr, h->upd_tgt,
+                                                         h->luv, maxrow, 1e-14, h->piv_status);
+    LAUNCHCHK();
+  }
+  k_gather_pos<<<cdiv(nnz, 256), 256, 0, s>>>((int)nnz, h->lut_src, h->luv, h->lutv);
+  LAUNCHCHK();
+}
+
+template <int TW>
+void trsv_t(rpf_grid* h, bool lower, bool unit, bool transposed, double* X, int ld, int ncols, double scale,
+            hipStream_t s) {
+  const Presolve& P = h->P;
+  const Levels& L = lower ? P.lev_lo : P.lev_up;
+  const int32_t* lp = lower ? h->lo_ptr : h->up_ptr;
+  const int32_t* lr = lower ? h->lo_rows : h->up_rows;
+  const double* val = transposed ? h->lutv : h->luv;
+  const int threads = TW == 1 ? 1024 : 512;
+  const int grid = cdiv(ncols, TW);
+  if (lower && unit)
+    k_trsv_batch<TW, true, true><<<grid, threads, 0, s>>>(L.nlev(), lp, lr, h->lu_ptr, h->lu_col, h->lu_diag,
+                                                          val, X, ld, ncols, scale);
+  else if (lower)
+    k_trsv_batch<TW, true, false><<<grid, threads, 0, s>>>(L.nlev(), lp, lr, h->lu_ptr, h->lu_col, h->lu_diag,
+                                                           val, X, ld, ncols, scale);
+  else if (unit)
+    k_trsv_batch<TW, false, true><<<grid, threads, 0, s>>>(L.nlev(), lp, lr, h->lu_ptr, h->lu_col, h->lu_diag,
+                                                           val, X, ld, ncols, scale);
+  else
+    k_trsv_batch<TW, false, false><<<grid, threads, 0, s>>>(L.nlev(), lp, lr, h->lu_ptr, h->lu_col,
+                                                            h->lu_diag, val, X, ld, ncols, scale);
+  LAUNCHCHK();
+}
+
+void trsv(rpf_grid* h, bool lower, bool unit, bool transposed, double* X, int ld, int ncols, double scale,
+          hipStream_t s) {
+  if (ncols == 1)
+    trsv_t<1>(h, lower, unit, transposed, X, ld, ncols, scale, s);
+  else
+    trsv_t<8>(h, lower, unit, transposed, X, ld, ncols, scale, s);
+}
+
+void spmm(int nrows, const int32_t* ptr, const int32_t* col, const double* val, const int32_t* valpos,
+          const double* xscale, const double* X, int ldx, int ncols, double alpha, const double* Yadd,
+          int ldya, double* Y, int ldy, hipStream_t s) {
+  dim3 blk(64, 4);
+  dim3 grd(cdiv(ncols, 64), cdiv(nrows, 4));
+  k_spmm<<<grd, blk, 0, s>>>(nrows, ptr, col, val, valpos, xscale, X, ldx, ncols, alpha, Yadd, ldya, Y, ldy);
+  LAUNCHCHK();
+}
+
+ALArgs al_args(rpf_grid* h, const double* u, const double* pd, const double* qd, const double* s,
+               const double* y, double rho, const double* sigma) {
+  const Presolve& P = h->P;
+  ALArgs A;
+  A.nb = P.nb; A.nl = P.nl; A.npq = P.npq; A.npv = P.npv; A.ng = P.ng; A.m = P.m; A.nx = P.nx; A.nu = P.nu;
+  A.ref = P.ref; A.gen_ref = P.gen_at[P.ref];
+  A.base = P.base_mva; A.rho = rho; A.sigf = sigma;
+  A.pq = h->pq; A.pv = h->pv; A.gen_pidx = h->gen_pidx; A.pv_gen = h->pv_gen;
+  A.c2 = h->c2; A.c1 = h->c1; A.c0 = h->c0;
+  A.rec = h->rec; A.Pbus = h->Pbus; A.Qbus = h->Qbus; A.vm = h->vm;
+  A.pd = pd; A.qd = qd; A.u = u; A.s = s; A.y = y; A.sigma_c = sigma + 1;
+  return A;
+}
+
+VarArgs var_args(rpf_grid* h, const double* u, const double* sigma) {
+  const Presolve& P = h->P;
+  VarArgs V;
+  V.nvar = P.nvar; V.nx = P.nx; V.npq = P.npq; V.npv = P.npv; V.nl = P.nl;
+  V.base = P.base_mva; V.sigf = sigma;
+  V.kind = h->var_kind; V.aux = h->var_aux; V.pv_gen = h->pv_gen; V.pv = h->pv; V.rowP = h->rowP;
+  V.c2 = h->c2; V.c1 = h->c1; V.u = u;
+  return V;
+}
+
+void bus_injections(rpf_grid* h, hipStream_t s) {
+  const Presolve& P = h->P;
+  k_gather_sum<<<cdiv(P.nb, 256), 256, 0, s>>>(P.nb, h->pb_ptr, h->pb_src, h->rec, nullptr, h->Pbus);
+  LAUNCHCHK();
+  k_gather_sum<<<cdiv(P.nb, 256), 256, 0, s>>>(P.nb, h->pb_ptr, h->qb_src, h->rec, nullptr, h->Qbus);
+  LAUNCHCHK();
+}
+
+// One batch of reduced Hessian-vector products at the cached point.
+// V (ldv) or, when V is null, identity columns j0.. of the n_u identity.
+void hvp_batch(rpf_grid* h, const double* V, int ldv, int j0, int B, double* HV, int ldhv, hipStream_t s) {
+  const Presolve& P = h->P;
+  const int ld = B;
+  double* Dx = h->D;
+  double* Du = h->D + (size_t)P.nx * ld;
+  dim3 blk(64, 4);
+  if (V) {
+    k_copy_block<<<dim3(cdiv(B, 64), cdiv(P.nu, 4)), blk, 0, s>>>(P.nu, B, V, ldv, Du, ld);
+  } else {
+    k_identity_block<<<dim3(cdiv(B, 64), cdiv(P.nu, 4)), blk, 0, s>>>(P.nu, B, j0, Du, ld);
+  }
+  LAUNCHCHK();
+  // R = -J_u V
+  spmm(P.nx, h->ju_ptr, h->ju_col, h->juv, nullptr, nullptr, Du, ld, B, -1.0, nullptr, 0, Dx, ld, s);
+  // Z = U^{-1} L^{-1} R
+  trsv(h, true, true, false, Dx, ld, B, 1.0, s);
+  trsv(h, false, false, false, Dx, ld, B, 1.0, s);
+  // Y = K [Z; V] + G^T diag(kappa) G [Z; V]
+  spmm(P.nvar, h->K_ptr, h->K_col, h->Kv, nullptr, nullptr, h->D, ld, B, 1.0, nullptr, 0, h->Y, ld, s);
+  spmm(P.nr1, h->G_ptr, h->G_col, h->Gv, nullptr, nullptr, h->D, ld, B, 1.0, nullptr, 0, h->T, ld, s);
+  spmm(P.nvar, h->Gt_ptr, h->Gt_col, h->Gv, h->Gt_pos, h->kappa, h->T, ld, B, 1.0, h->Y, ld, h->Y, ld, s);
+  // Psi = -J_x^{-T} Y_x  (U^T then L^T)
+  trsv(h, true, false, true, h->Y, ld, B, -1.0, s);
+  trsv(h, false, true, true, h->Y, ld, B, 1.0, s);
+  // HV = Y_u + J_u^T Psi
+  spmm(P.nu, h->jut_ptr, h->jut_col, h->juv, h->jut_pos, nullptr, h->Y, ld, B, 1.0, h->Y + (size_t)P.nx * ld,
+       ld, HV, ldhv, s);
+}
+
+template <class F>
+int guard(F&& f) {
+  try {
+    return f();
+  } catch (const HipError& e) {
+    return set_err(RPF_EHIP, e.what());
+  } catch (const std::bad_alloc&) {
+    return set_err(RPF_ENOMEM, "device allocation failed");
+  } catch (const std::exception& e) {
+    return set_err(RPF_EINVAL, e.what());
+  }
+}
+
+}  // namespace
+
+namespace {
+GridData grid_from_desc(const rpf_grid_desc* desc) {
+  if (!desc) throw std::runtime_error("desc is NULL");
+  if (!desc->bus_type || !desc->br_from || !desc->br_to || !desc->br_r || !desc->br_x || !desc->br_b ||
+      !desc->gen_bus || !desc->c2 || !desc->c1 || !desc->c0)
+    throw std::runtime_error("grid description has a NULL array");
+  if (desc->nb < 2 || desc->nl < 1 || desc->ng < 1) throw std::runtime_error("grid needs nb >= 2, nl >= 1, ng >= 1");
+  if (!(desc->base_mva > 0.0)) throw std::runtime_error("base_mva must be positive");
+  GridData G;
+  G.nb = desc->nb; G.nl = desc->nl; G.ng = desc->ng; G.base_mva = desc->base_mva;
+  G.bus_type.assign(desc->bus_type, desc->bus_type + G.nb);
+  G.br_from.assign(desc->br_from, desc->br_from + G.nl);
+  G.br_to.assign(desc->br_to, desc->br_to + G.nl);
+  G.br_r.assign(desc->br_r, desc->br_r + G.nl);
+  G.br_x.assign(desc->br_x, desc->br_x + G.nl);
+  G.br_b.assign(desc->br_b, desc->br_b + G.nl);
+  G.gen_bus.assign(desc->gen_bus, desc->gen_bus + G.ng);
+  G.c2.assign(desc->c2, desc->c2 + G.ng);
+  G.c1.assign(desc->c1, desc->c1 + G.ng);
+  G.c0.assign(desc->c0, desc->c0 + G.ng);
+  return G;
+}
+}  // namespace
+
+extern "C" {
+
+const char* rpf_last_error(void) { return g_err.c_str(); }
+
+int rpf_presolve_info(const rpf_grid_desc* desc, int64_t* o) {
+  if (!o) return set_err(RPF_EINVAL, "out is NULL");
+  return guard([&]() -> int {
+    Presolve P = build_presolve(grid_from_desc(desc));
+    PresolveStats st = stats(P);
+    int64_t v[16] = {P.nx, P.nu, P.m, st.nnz_jx, st.nnz_lu, st.nlev_lo, st.nlev_up, st.max_lu_row,
+                     st.refactor_updates, st.nnz_ju, st.nnz_k, st.nnz_g, 0, 0, 0, 0};
+    std::memcpy(o, v, sizeof(v));
+    return RPF_OK;
+  });
+}
+
+int rpf_presolve_pattern(const rpf_grid_desc* desc, int32_t* perm, int32_t* lu_ptr, int32_t* lu_col) {
+  return guard([&]() -> int {
+    Presolve P = build_presolve(grid_from_desc(desc));
+    if (perm) std::copy(P.x_int2paper.begin(), P.x_int2paper.end(), perm);
+    if (lu_ptr) std::copy(P.lu_ptr.begin(), P.lu_ptr.end(), lu_ptr);
+    if (lu_col) std::copy(P.lu_col.begin(), P.lu_col.end(), lu_col);
+    return RPF_OK;
+  });
+}
+
+int rpf_grid_create(const rpf_grid_desc* desc, int32_t max_batch, rpf_grid** out) {
+  if (!out) return set_err(RPF_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (max_batch < 1) return set_err(RPF_EINVAL, "max_batch must be >= 1");
+  return guard([&]() -> int {
+    GridData G0 = grid_from_desc(desc);
+    rpf_grid* h = new rpf_grid();
+    try {
+      h->G = std::move(G0);
+      const GridData& G = h->G;
+      h->P = build_presolve(G);
+      h->max_batch = max_batch;
+      if ((int64_t)h->P.nvar * max_batch >= (int64_t)1 << 31)
+        throw std::runtime_error("n_var * max_batch must stay below 2^31");
+      setup(h);
+    } catch (...) {
+      delete h;
+      throw;
+    }
+    *out = h;
+    return RPF_OK;
+  });
+}
+
+void rpf_grid_destroy(rpf_grid* grid) { delete grid; }
+
+int rpf_dims(const rpf_grid* h, int32_t* nx, int32_t* nu, int32_t* m) {
+  if (!h) return set_err(RPF_EINVAL, "grid is NULL");
+  if (nx) *nx = h->P.nx;
+  if (nu) *nu = h->P.nu;
+  if (m) *m = h->P.m;
+  return RPF_OK;
+}
+
+int rpf_structure(const rpf_grid* h, int64_t* o) {
+  if (!h || !o) return set_err(RPF_EINVAL, "NULL argument");
+  PresolveStats st = stats(h->P);
+  o[0] = st.nnz_jx; o[1] = st.nnz_lu; o[2] = st.nlev_lo; o[3] = st.nlev_up; o[4] = st.max_lu_row;
+  o[5] = st.refactor_updates; o[6] = st.nnz_ju; o[7] = st.nnz_k; o[8] = st.nnz_g; o[9] = h->max_batch;
+  return RPF_OK;
+}
+
+int rpf_pf_solve(rpf_grid* h, const double* u, const double* pd, const double* qd, double* x, double tol,
+                 int32_t max_iter, int32_t* status, double* resid, rpf_stream_t stream) {
+  if (!h || !u || !pd || !qd || !x || !status || !resid) return set_err(RPF_EINVAL, "NULL argument");
+  if (max_iter < 0) return set_err(RPF_EINVAL, "max_iter must be >= 0");
+  return guard([&]() -> int {
+    hipStream_t s = (hipStream_t)stream;
+    const Presolve& P = h->P;
+    h->have_point = false;
+    x_in(h, x, s);
+    int it = 0, conv = 0;
+    const int nblk = cdiv(P.nx, 256);
+    k_fill_int<<<1, 4, 0, s>>>(4, h->piv_status, 0);
+    for (;;) {
+      state_and_records(h, u, s);
+      k_residual<<<nblk, 256, 0, s>>>(P.nx, h->g_sp, h->g_s, h->rec, h->row_bus, h->row_isq, h->row_pvar, pd,
+                                      qd, u, h->g, h->partial);
+      LAUNCHCHK();
+      k_reduce_final<<<1, 1024, 0, s>>>(nblk, h->partial, h->resid_d, 1, tol, nullptr);
+      LAUNCHCHK();
+      HIPCHK(hipMemcpyAsync(h->host_resid, h->resid_d, sizeof(double), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      const double r = h->host_resid[0];
+      if (r < tol) {
+        conv = 1;
+        break;
+      }
+      if (!std::isfinite(r) || it >= max_iter) break;
+      refactor(h, s);
+      HIPCHK(hipMemcpyAsync(h->d, h->g, sizeof(double) * P.nx, hipMemcpyDeviceToDevice, s));
+      trsv(h, true, true, false, h->d, 1, 1, 1.0, s);
+      trsv(h, false, false, false, h->d, 1, 1, 1.0, s);
+      k_axpy<<<nblk, 256, 0, s>>>(P.nx, -1.0, h->d, h->xi);
+      LAUNCHCHK();
+      ++it;
+    }
+    k_set_status<<<1, 1, 0, s>>>(status, it, conv, h->resid_d, resid);
+    LAUNCHCHK();
+    k_permute_scatter<<<nblk, 256, 0, s>>>(P.nx, h->x_i2p, h->xi, x);
+    LAUNCHCHK();
+    return RPF_OK;
+  });
+}
+
+int rpf_al_objective(rpf_grid* h, const double* x, const double* u, const double* pd, const double* qd,
+                     const double* sv, const double* y, double rho, const double* sigma, double* phi,
+                     double* c, rpf_stream_t stream) {
+  if (!h || !x || !u || !pd || !qd || !sv || !y || !sigma || !phi) return set_err(RPF_EINVAL, "NULL argument");
+  return guard([&]() -> int {
+    hipStream_t s = (hipStream_t)stream;
+    const Presolve& P = h->P;
+    x_in(h, x, s);
+    state_and_records(h, u, s);
+    bus_injections(h, s);
+    ALArgs A = al_args(h, u, pd, qd, sv, y, rho, sigma);
+    k_constraints<<<cdiv(P.m + P.ng, 256), 256, 0, s>>>(A, c ? c : h->cvec, h->wvec, h->terms);
+    LAUNCHCHK();
+    k_reduce_final<<<1, 1024, 0, s>>>(P.m + P.ng, h->terms, phi, 0, 0.0, nullptr);
+    LAUNCHCHK();
+    return RPF_OK;
+  });
+}
+
+int rpf_reduced_gradient(rpf_grid* h, const double* x, const double* u, const double* pd, const double* qd,
+                         const double* sv, const double* y, double rho, const double* sigma, double* grad,
+                         double* lambda, rpf_stream_t stream) {
+  if (!h || !x || !u || !pd || !qd || !sv || !y || !sigma || !grad) return set_err(RPF_EINVAL, "NULL argument");
+  return guard([&]() -> int {
+    hipStream_t s = (hipStream_t)stream;
+    const Presolve& P = h->P;
+    h->have_point = false;
+    x_in(h, x, s);
+    state_and_records(h, u, s);
+    bus_injections(h, s);
+    ALArgs A = al_args(h, u, pd, qd, sv, y, rho, sigma);
+    VarArgs V = var_args(h, u, sigma);
+    k_constraints<<<cdiv(P.m + P.ng, 256), 256, 0, s>>>(A, h->cvec, h->wvec, nullptr);
+    LAUNCHCHK();
+    const int nbw = cdiv(P.nb + 2 + P.npv, 256);
+    // d phi / d(variables) through branch-local gradients
+    k_bus_weights<<<nbw, 256, 0, s>>>(A, h->wvec, nullptr, h->rowP, h->rowQ, h->bus_pvpos, h->a, h->b, h->kappa);
+    LAUNCHCHK();
+    k_branch_second<<<cdiv(P.nl, 256), 256, 0, s>>>(P.nl, h->br_f, h->br_t, h->br_r, h->br_x, h->br_b, h->th,
+                                                     h->vm, h->rec, h->a, h->b, h->wvec, sigma + 1, rho, h->wrec);
+    LAUNCHCHK();
+    k_var_grad<<<cdiv(P.nvar, 256), 256, 0, s>>>(V, h->vg_sp, h->vg_s, h->wrec, h->wvec, nullptr, h->varg);
+    LAUNCHCHK();
+    // J_x factorized at x; lambda: U^T w = -d_x phi, L^T lambda = w
+    k_fill_int<<<1, 4, 0, s>>>(4, h->piv_status, 0);
+    refactor(h, s);
+    HIPCHK(hipMemcpyAsync(h->lam, h->varg, sizeof(double) * P.nx, hipMemcpyDeviceToDevice, s));
+    trsv(h, true, false, true, h->lam, 1, 1, -1.0, s);
+    trsv(h, false, true, true, h->lam, 1, 1, 1.0, s);
+    // gradient of l = phi + lambda^T g: its control part is the reduced gradient
+    k_bus_weights<<<nbw, 256, 0, s>>>(A, h->wvec, h->lam, h->rowP, h->rowQ, h->bus_pvpos, h->a, h->b, h->kappa);
+    LAUNCHCHK();
+    k_branch_second<<<cdiv(P.nl, 256), 256, 0, s>>>(P.nl, h->br_f, h->br_t, h->br_r, h->br_x, h->br_b, h->th,
+                                                     h->vm, h->rec, h->a, h->b, h->wvec, sigma + 1, rho, h->wrec);
+    LAUNCHCHK();
+    k_var_grad<<<cdiv(P.nvar, 256), 256, 0, s>>>(V, h->vg_sp, h->vg_s, h->wrec, h->wvec, h->lam, h->varg);
+    LAUNCHCHK();
+    HIPCHK(hipMemcpyAsync(grad, h->varg + P.nx, sizeof(double) * P.nu, hipMemcpyDeviceToDevice, s));
+    if (lambda) {
+      k_permute_scatter<<<cdiv(P.nx, 256), 256, 0, s>>>(P.nx, h->x_i2p, h->lam, lambda);
+      LAUNCHCHK();
+    }
+    // cached point for the Hessian products
+    k_gather_sum<<<cdiv(P.K_col.size(), 256), 256, 0, s>>>((int)P.K_col.size(), h->K_sp, h->K_s, h->wrec,
+                                                            nullptr, h->Kv);
+    LAUNCHCHK();
+    k_k_diag<<<cdiv(P.nvar, 256), 256, 0, s>>>(V, h->K_diag, sigma + 1, rho, h->Kv);
+    LAUNCHCHK();
+    k_gather_sum<<<cdiv(P.ju_col.size(), 256), 256, 0, s>>>((int)P.ju_col.size(), h->ju_sp, h->ju_s, h->rec,
+                                                             h->ju_const, h->juv);
+    LAUNCHCHK();
+    k_gather_sum<<<cdiv(P.G_col.size(), 256), 256, 0, s>>>((int)P.G_col.size(), h->G_sp, h->G_s, h->rec,
+                                                            nullptr, h->Gv);
+    LAUNCHCHK();
+    h->rho = rho;
+    h->have_point = true;
+    return RPF_OK;
+  });
+}
+
+int rpf_reduced_hessian_batch(rpf_grid* h, const double* V, int32_t nbatch, int32_t ldv, double* HV,
+                              int32_t ldhv, rpf_stream_t stream) {
+  if (!h || !V || !HV) return set_err(RPF_EINVAL, "NULL argument");
+  if (!h->have_point) return set_err(RPF_ESTATE, "no cached point: call rpf_reduced_gradient first");
+  if (nbatch < 1 || nbatch > h->max_batch) return set_err(RPF_ESIZE, "nbatch outside [1, max_batch]");
+  if (ldv < nbatch || ldhv < nbatch) return set_err(RPF_EINVAL, "leading dimension below nbatch");
+  return guard([&]() -> int {
+    hvp_batch(h, V, ldv, 0, nbatch, HV, ldhv, (hipStream_t)stream);
+    return RPF_OK;
+  });
+}
+
+int rpf_reduced_hessian(rpf_grid* h, double* H, int32_t batch, rpf_stream_t stream) {
+  if (!h || !H) return set_err(RPF_EINVAL, "NULL argument");
+  if (!h->have_point) return set_err(RPF_ESTATE, "no cached point: call rpf_reduced_gradient first");
+  if (batch < 0) return set_err(RPF_EINVAL, "batch must be >= 0");
+  return guard([&]() -> int {
+    const int nu = h->P.nu;
+    int B = batch == 0 ? std::min(h->max_batch, nu) : std::min<int>(batch, std::min(h->max_batch, nu));
+    for (int j0 = 0; j0 < nu; j0 += B) {
+      int nbb = std::min(B, nu - j0);
+      hvp_batch(h, nullptr, 0, j0, nbb, H + j0, nu, (hipStream_t)stream);
+    }
+    return RPF_OK;
+  });
+}
+
+int rpf_factor_solve(rpf_grid* h, int32_t n, double* K, const double* diag, double delta, const double* rhs,
+                     double* step, int32_t* info, rpf_stream_t stream) {
+  if (!h || !K || !rhs || !step || !info) return set_err(RPF_EINVAL, "NULL argument");
+  if (n < 1 || n > h->P.nu) return set_err(RPF_EINVAL, "n must be in [1, n_u]");
+  return guard([&]() -> int {
+    hipStream_t s = (hipStream_t)stream;
+    k_fill_int<<<1, 1, 0, s>>>(1, info, 0);
+    LAUNCHCHK();
+    k_symmetrize<<<dim3(cdiv(n, 32), cdiv(n, 8)), dim3(32, 8), 0, s>>>(n, K, diag, delta);
+    LAUNCHCHK();
+    for (int k0 = 0; k0 < n; k0 += CB) {
+      k_chol_diag<<<1, 256, 0, s>>>(n, k0, K, info);
+      LAUNCHCHK();
+      const int nb = std::min(CB, n - k0);
+      const int rest = n - k0 - nb;
+      if (rest > 0) {
+        k_chol_trsm<<<cdiv(rest, 128), 128, 0, s>>>(n, k0, K, info);
+        LAUNCHCHK();
+        const int nt = cdiv(rest, CB);
+        k_chol_update<<<dim3(nt, nt), 256, 0, s>>>(n, k0, K, info);
+        LAUNCHCHK();
+      }
+    }
+    k_chol_solve<<<1, 256, 0, s>>>(n, K, rhs, step, h->chol_work, info);
+    LAUNCHCHK();
+    return RPF_OK;
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,227 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle on the
+same seeded inputs.  Tolerances: x 1e-12, phi and c 1e-12, gradient and
+lambda 1e-10, reduced Hessian 1e-9 (relative Frobenius), Cholesky factor
+and step 1e-9 relative."""
+import numpy as np
+import pytest
+
+import gridgen
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _rel(a, b):
+    a = np.asarray(a); b = np.asarray(b)
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+class Case:
+    def __init__(self, name, max_batch=256):
+        from paper_2110_02590_amd import Problem
+        print(f"[case] {name} max_batch={max_batch}", flush=True)
+        self.name = name
+        self.g = gridgen.grid(name)
+        self.ep = gridgen.eval_point(self.g)
+        self.pr = Problem(self.g, max_batch=max_batch)
+        self.M = oracle.Model(self.g)
+        self.u = self.M.u_from_setpoints(self.g["vg0"], self.g["pg0"])
+        self.P = oracle.Point.from_dict(self.ep)
+        self._o = {}
+
+    def oracle(self, what):
+        if what not in self._o:
+            g, M, u, P = self.g, self.M, self.u, self.P
+            if what == "pf":
+                self._o[what] = oracle.solve_pf(M, u, g["pd"], g["qd"])
+            elif what == "grad":
+                x = self.oracle("pf").x
+                self._o[what] = oracle.reduced_gradient(M, x, u, g["pd"], g["qd"], P)
+            elif what == "H":
+                x = self.oracle("pf").x
+                self._o[what] = oracle.reduced_hessian(M, x, u, g["pd"], g["qd"], P, self.oracle("grad")[1])
+        return self._o[what]
+
+    def gpu_point(self):
+        pr = self.pr
+        x = pr.flat_x()
+        st, res = pr.grid.pf_solve(pr.u0, pr.pd, pr.qd, x)
+        s, y, rho, sigma = pr.point(self.ep)
+        grad, lam = pr.grid.reduced_gradient(x, pr.u0, pr.pd, pr.qd, s, y, rho, sigma)
+        torch.cuda.synchronize()
+        return x, st, res, grad, lam
+
+
+_cases = {}
+
+
+def case(name, max_batch=256):
+    key = (name, max_batch)
+    if key not in _cases:
+        _cases[key] = Case(name, max_batch)
+    return _cases[key]
+
+
+SMALL = ["tiny10", "syn300", "syn2000"]
+
+
+@pytest.mark.parametrize("name", SMALL + ["syn9241"])
+def test_power_flow(name):
+    c = case(name)
+    pr = c.pr
+    x = pr.flat_x()
+    st, res = pr.grid.pf_solve(pr.u0, pr.pd, pr.qd, x)
+    torch.cuda.synchronize()
+    o = c.oracle("pf")
+    assert int(st[1]) == 1 and float(res) < 1e-10
+    assert abs(int(st[0]) - o.iters) <= 1
+    assert _rel(x.cpu().numpy(), o.x) < 1e-12
+
+
+@pytest.mark.parametrize("name", SMALL)
+def test_al_objective(name):
+    c = case(name)
+    pr = c.pr
+    x = torch.tensor(c.oracle("pf").x, device="cuda")
+    s, y, rho, sigma = pr.point(c.ep)
+    phi, cv = pr.grid.al_objective(x, pr.u0, pr.pd, pr.qd, s, y, rho, sigma)
+    torch.cuda.synchronize()
+    phio, co = oracle.al_objective(c.M, c.oracle("pf").x, c.u, c.g["pd"], c.g["qd"], c.P)
+    assert abs(float(phi) - phio) <= 1e-12 * abs(phio)
+    assert _rel(cv.cpu().numpy(), co) < 1e-12
+
+
+@pytest.mark.parametrize("name", SMALL + ["syn9241"])
+def test_reduced_gradient(name):
+    c = case(name)
+    x, st, res, grad, lam = c.gpu_point()
+    go, lo = c.oracle("grad")
+    assert _rel(grad.cpu().numpy(), go) < 1e-10
+    assert _rel(lam.cpu().numpy(), lo) < 1e-10
+
+
+@pytest.mark.parametrize("name,batch", [("tiny10", 0), ("syn300", 64), ("syn300", 16), ("syn2000", 256)])
+def test_reduced_hessian_full(name, batch):
+    c = case(name)
+    c.gpu_point()
+    H = c.pr.grid.reduced_hessian(batch=batch)
+    torch.cuda.synchronize()
+    Ho = c.oracle("H")
+    Hg = H.cpu().numpy()
+    assert _rel(Hg, Ho) < 1e-9
+    assert np.linalg.norm(Hg - Hg.T) <= 1e-11 * np.linalg.norm(Hg)
+
+
+def test_batch_width_one_equals_batched():
+    c = case("syn300")
+    c.gpu_point()
+    pr = c.pr
+    V = torch.tensor(gridgen.directions(pr.nu, 5, 2005), device="cuda")
+    HV = pr.grid.hessian_batch(V.contiguous())
+    cols = [pr.grid.hessian_batch(V[:, k:k + 1].contiguous()) for k in range(5)]
+    torch.cuda.synchronize()
+    one = torch.cat(cols, dim=1).cpu().numpy()
+    assert _rel(one, HV.cpu().numpy()) < 1e-13
+    Ho = c.oracle("H")
+    assert _rel(HV.cpu().numpy(), Ho @ V.cpu().numpy()) < 1e-9
+
+
+def test_random_directions_linear():
+    c = case("syn2000")
+    c.gpu_point()
+    pr = c.pr
+    V = torch.tensor(gridgen.directions(pr.nu, 33, 2002), device="cuda")   # ragged width
+    HV = pr.grid.hessian_batch(V)
+    W = (2.0 * V[:, :7] - 0.5 * V[:, 7:14]).contiguous()
+    HW = pr.grid.hessian_batch(W)
+    torch.cuda.synchronize()
+    lin = 2.0 * HV[:, :7] - 0.5 * HV[:, 7:14]
+    assert _rel(HW.cpu().numpy(), lin.cpu().numpy()) < 1e-12
+    assert _rel(HV.cpu().numpy(), c.oracle("H") @ V.cpu().numpy()) < 1e-9
+
+
+def test_largest_workload_sampled_columns():
+    """9241-bus grid: full reduced Hessian on the GPU, sampled columns
+    against the oracle's adjoint-adjoint products, symmetry at full size."""
+    c = case("syn9241", max_batch=1024)
+    c.gpu_point()
+    H = c.pr.grid.reduced_hessian(batch=1024)
+    torch.cuda.synchronize()
+    Hg = H.cpu().numpy()
+    cols = np.array([0, 1, 2, 777, 1444, 1445, 2000, 2888])
+    W = np.zeros((c.M.nu, cols.size))
+    W[cols, np.arange(cols.size)] = 1.0
+    x = c.oracle("pf").x
+    lam = c.oracle("grad")[1]
+    Ho = oracle.hvp_adjoint_adjoint(c.M, x, c.u, c.g["pd"], c.g["qd"], c.P, lam, W)
+    assert _rel(Hg[:, cols], Ho) < 1e-9
+    assert np.linalg.norm(Hg - Hg.T) <= 1e-11 * np.linalg.norm(Hg)
+
+
+def test_factor_solve_matches_lapack():
+    c = case("syn300")
+    x, st, res, grad, lam = c.gpu_point()
+    H = c.pr.grid.reduced_hessian(batch=64)
+    Hn = H.cpu().numpy()
+    delta = oracle.delta_ladder(Hn)
+    delta = max(delta, 1.0)
+    diag = torch.tensor(np.linspace(0.1, 0.5, c.pr.nu), device="cuda")
+    K = H.clone()
+    step, info = c.pr.grid.factor_solve(K, grad, diag=diag, delta=delta)
+    torch.cuda.synchronize()
+    Lo, io, so = oracle.factor_solve(Hn, diag.cpu().numpy(), delta, grad.cpu().numpy())
+    assert int(info) == 0 and io == 0
+    Lg = np.tril(K.cpu().numpy())
+    assert _rel(Lg, Lo) < 1e-11
+    assert _rel(step.cpu().numpy(), so) < 1e-9
+
+
+def test_factor_reports_first_bad_pivot():
+    c = case("tiny10")
+    n = 100
+    rng = np.random.default_rng(4)
+    A = rng.standard_normal((n, n)) * 1e-3
+    K = np.diag(np.full(n, 2.0)) + A + A.T
+    K[70, 70] = -1.0
+    Kt = torch.tensor(K, device="cuda")
+    rhs = torch.ones(n, dtype=torch.float64, device="cuda")
+    grid = c.pr.grid
+    from paper_2110_02590_amd import RpfError
+    with pytest.raises(RpfError):
+        grid.factor_solve(Kt, rhs)          # n above n_u of this grid
+    big = case("syn300")
+    step, info = big.pr.grid.factor_solve(Kt, rhs)
+    torch.cuda.synchronize()
+    _, io = oracle.cholesky_lower(K)
+    assert int(info) == io == 71
+
+
+def test_call_order_and_size_errors():
+    from paper_2110_02590_amd import Problem, RpfError
+    from paper_2110_02590_amd.binding import RPF_ESIZE, RPF_ESTATE
+    g = gridgen.grid("tiny10")
+    pr = Problem(g, max_batch=4)
+    V = torch.zeros((pr.nu, 2), dtype=torch.float64, device="cuda")
+    with pytest.raises(RpfError) as e:
+        pr.grid.hessian_batch(V)
+    assert e.value.code == RPF_ESTATE
+    x = pr.flat_x()
+    pr.grid.pf_solve(pr.u0, pr.pd, pr.qd, x)
+    s, y, rho, sigma = pr.point(gridgen.eval_point(g))
+    pr.grid.reduced_gradient(x, pr.u0, pr.pd, pr.qd, s, y, rho, sigma)
+    V5 = torch.zeros((pr.nu, 5), dtype=torch.float64, device="cuda")
+    with pytest.raises(RpfError) as e:
+        pr.grid.hessian_batch(V5)
+    assert e.value.code == RPF_ESIZE
+
+
+def test_power_flow_divergence_is_reported():
+    c = case("syn300")
+    pr = c.pr
+    x = pr.flat_x()
+    st, res = pr.grid.pf_solve(pr.u0, pr.pd * 8.0, pr.qd * 8.0, x, max_iter=8)
+    torch.cuda.synchronize()
+    o = oracle.solve_pf(c.M, c.u, c.g["pd"] * 8.0, c.g["qd"] * 8.0, max_iter=8, raise_on_fail=False)
+    assert int(st[1]) == 0 and not o.converged
