@@ -169,11 +169,23 @@ int rpf_reduced_hessian(rpf_grid* grid, double* H, int32_t batch, rpf_stream_t s
 int rpf_factor_solve(rpf_grid* grid, int32_t n, double* Kmat, const double* diag, double delta,
                      const double* rhs, double* step, int32_t* info, rpf_stream_t stream);
 
+/* Kernel timing with HIP events recorded on the launch stream, per kernel
+ * class: 0 batched triangular solves (more than one right-hand side),
+ * 1 single right-hand-side triangular solves, 2 LU refactorization,
+ * 3 sparse products of the Hessian batches, 4 dense Cholesky kernels.
+ * rpf_profile_read waits for the recorded events, returns the summed
+ * milliseconds and launch counts per class (host arrays [RPF_PROF_CLASSES])
+ * and clears them when reset != 0. */
+#define RPF_PROF_CLASSES 5
+int rpf_profile_enable(rpf_grid* grid, int32_t enable);
+int rpf_profile_read(rpf_grid* grid, double* ms, int64_t* launches, int32_t reset);
+
 /* Host-only presolve introspection (no device needed), for checking the
  * index maps and the symbolic factorization:
  *   rpf_presolve_info: out16 = {n_x, n_u, m, nnz(J_x), nnz(L+U), forward
  *   levels, backward levels, longest LU row, refactorization updates,
- *   nnz(J_u), nnz(K), nnz(rank-one rows), 0, 0, 0, 0}.
+ *   nnz(J_u), nnz(K), nnz(rank-one rows), packs of independent subtrees,
+ *   rows of the top part, most levels in one pack, levels of the top part}.
  *   rpf_presolve_pattern: perm [n_x] (internal state index -> paper x
  *   index), lu_ptr [n_x + 1], lu_col [nnz(L+U)] (internal order, sorted
  *   columns, diagonal included); any pointer may be NULL. */

@@ -60,6 +60,8 @@ def lib():
             "rpf_reduced_hessian": [vp, vp, i32, vp],
             "rpf_factor_solve": [vp, i32, vp, vp, dbl, vp, vp, vp, vp],
             "rpf_presolve_info": [vp, i64p],
+            "rpf_profile_enable": [vp, i32],
+            "rpf_profile_read": [vp, vp, vp, i32],
             "rpf_presolve_pattern": [vp, vp, vp, vp],
         }
         for name, args in sig.items():
@@ -108,8 +110,9 @@ def presolve_info(g: dict) -> dict:
     out = np.zeros(16, dtype=np.int64)
     _check(lib().rpf_presolve_info(d.ref(), out.ctypes.data))
     keys = ["nx", "nu", "m", "nnz_jx", "nnz_lu", "nlev_lo", "nlev_up", "max_lu_row",
-            "refactor_updates", "nnz_ju", "nnz_k", "nnz_g"]
-    return dict(zip(keys, out[:12].tolist()))
+            "refactor_updates", "nnz_ju", "nnz_k", "nnz_g", "npacks", "ntop", "max_pack_levels",
+            "top_levels"]
+    return dict(zip(keys, out.tolist()))
 
 
 def presolve_pattern(g: dict):
@@ -182,6 +185,17 @@ class Grid:
         keys = ["nnz_jx", "nnz_lu", "nlev_lo", "nlev_up", "max_lu_row", "refactor_updates",
                 "nnz_ju", "nnz_k", "nnz_g", "max_batch"]
         return dict(zip(keys, out.tolist()))
+
+    PROF_CLASSES = ["trsv_batch", "trsv_single", "refactor", "spmm", "dense"]
+
+    def profile(self, enable: bool = True):
+        _check(lib().rpf_profile_enable(self._h, 1 if enable else 0))
+
+    def profile_read(self, reset: bool = True) -> dict:
+        ms = np.zeros(5, dtype=np.float64)
+        n = np.zeros(5, dtype=np.int64)
+        _check(lib().rpf_profile_read(self._h, ms.ctypes.data, n.ctypes.data, 1 if reset else 0))
+        return {k: (float(ms[i]), int(n[i])) for i, k in enumerate(self.PROF_CLASSES)}
 
     def _empty(self, n, dtype=None):
         torch = _torch()

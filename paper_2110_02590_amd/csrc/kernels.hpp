@@ -17,6 +17,7 @@ namespace dev {
 
 using rpf::RECW;
 using rpf::WREC;
+constexpr int CB = 64;  // dense block width
 
 // ------------------------------------------------------------------ helpers
 __global__ void k_permute_gather(int n, const int32_t* __restrict__ idx, const double* __restrict__ src,
@@ -165,92 +166,302 @@ __global__ void k_reduce_final(int n, const double* __restrict__ in, double* __r
 }
 
 // ----------------------------------------------------- LU refactorization
-// Row-by-row (up-looking) elimination on the static pattern, level by level,
-// one wavefront per row with the row staged in LDS.  For each L entry
-// (i, k) in ascending k: l_ik = a_ik / u_kk, then a_ij -= l_ik u_kj for the
-// U entries of row k (target positions precomputed).  Rows of one level are
-// independent; levels are separated by workgroup barriers.  A pivot with
-// |u_ii| <= pivtol * max_j |a_ij| records the row in status[0] (row + 1).
-__global__ void k_refactor(int lev0, int lev1, const int32_t* __restrict__ lev_ptr,
-                           const int32_t* __restrict__ lev_rows, const int32_t* __restrict__ ptr,
-                           const int32_t* __restrict__ col, const int32_t* __restrict__ diag,
-                           const int64_t* __restrict__ upd_ptr, const int32_t* __restrict__ upd_tgt,
-                           double* __restrict__ a, int maxrow, double pivtol,
-                           int32_t* __restrict__ status) {
-  extern __shared__ double lds[];
+// Row-by-row (up-looking) elimination on the static pattern, one wavefront
+// per row with the row staged in LDS: for each L entry (i, k), k ascending,
+// l_ik = a_ik / u_kk and a_ij -= l_ik u_kj for the U entries of row k
+// (target positions precomputed).  Only L entries in [ptr[i], pend) are
+// eliminated.  With check, a pivot |u_ii| <= pivtol max_j |a_ij| records
+// row + 1 in status[0].
+__device__ inline void rf_row(int i, int pend, bool check, const int32_t* __restrict__ ptr,
+                              const int32_t* __restrict__ col, const int32_t* __restrict__ diag,
+                              const int64_t* __restrict__ upd_ptr, const int32_t* __restrict__ upd_tgt,
+                              double* __restrict__ a, double* __restrict__ w, double pivtol,
+                              int32_t* __restrict__ status) {
   const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
-  const int nwave = blockDim.x >> 6;
-  const int gw = blockIdx.x * nwave + wave;          // global wave id
-  const int gnw = gridDim.x * nwave;
+  const int p0 = ptr[i], pdg = diag[i], p1 = ptr[i + 1];
+  double amax = 0.0;
+  for (int q = lane; q < p1 - p0; q += 64) {
+    double v = a[p0 + q];
+    w[q] = v;
+    amax = fmax(amax, fabs(v));
+  }
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  for (int p = p0; p < pend; ++p) {
+    const int k = col[p];
+    const int dk = diag[k];
+    const double l = w[p - p0] / a[dk];
+    const int64_t u0 = upd_ptr[p], nu = upd_ptr[p + 1] - u0;
+    for (int64_t t = lane; t < nu; t += 64) {
+      const int tg = upd_tgt[u0 + t] - p0;
+      w[tg] -= l * a[dk + 1 + (int)t];
+    }
+    if (lane == 0) w[p - p0] = l;
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+  }
+  for (int off = 32; off > 0; off >>= 1) amax = fmax(amax, __shfl_xor(amax, off, 64));
+  for (int q = lane; q < p1 - p0; q += 64) a[p0 + q] = w[q];
+  if (check && lane == 0) {
+    const double piv = w[pdg - p0];
+    if (!(fabs(piv) > pivtol * amax)) atomicCAS(status, 0, i + 1);
+  }
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+// Packs of independent subtrees: one workgroup per pack, its forward levels
+// separated by workgroup barriers, one wavefront per row.
+__global__ void k_rf_pack(const int32_t* __restrict__ flev, const int32_t* __restrict__ flev_off,
+                          const int32_t* __restrict__ frows, const int32_t* __restrict__ ptr,
+                          const int32_t* __restrict__ col, const int32_t* __restrict__ diag,
+                          const int64_t* __restrict__ upd_ptr, const int32_t* __restrict__ upd_tgt,
+                          double* __restrict__ a, int maxrow, double pivtol, int32_t* __restrict__ status) {
+  extern __shared__ double lds[];
+  const int wave = threadIdx.x >> 6, nwave = blockDim.x >> 6;
   double* w = lds + (size_t)wave * maxrow;
-  for (int lev = lev0; lev < lev1; ++lev) {
-    for (int r = lev_ptr[lev] + gw; r < lev_ptr[lev + 1]; r += gnw) {
-      const int i = lev_rows[r];
-      const int p0 = ptr[i], pdg = diag[i], p1 = ptr[i + 1];
-      double amax = 0.0;
-      for (int q = lane; q < p1 - p0; q += 64) {
-        double v = a[p0 + q];
-        w[q] = v;
-        amax = fmax(amax, fabs(v));
-      }
-      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      for (int p = p0; p < pdg; ++p) {
-        const int k = col[p];
-        const int dk = diag[k];
-        const double l = w[p - p0] / a[dk];
-        const int64_t u0 = upd_ptr[p], nu = upd_ptr[p + 1] - u0;
-        for (int64_t t = lane; t < nu; t += 64) {
-          int tg = upd_tgt[u0 + t] - p0;
-          w[tg] -= l * a[dk + 1 + (int)t];
-        }
-        if (lane == 0) w[p - p0] = l;
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-      }
-      for (int off = 32; off > 0; off >>= 1) amax = fmax(amax, __shfl_xor(amax, off, 64));
-      for (int q = lane; q < p1 - p0; q += 64) a[p0 + q] = w[q];
-      if (lane == 0) {
-        double piv = w[pdg - p0];
-        if (!(fabs(piv) > pivtol * amax)) atomicCAS(status, 0, i + 1);
-      }
-      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-      __builtin_amdgcn_wave_barrier();
+  const int q = blockIdx.x;
+  for (int lv = flev_off[q]; lv < flev_off[q + 1]; ++lv) {
+    for (int r = flev[lv] + wave; r < flev[lv + 1]; r += nwave) {
+      const int i = frows[r];
+      rf_row(i, diag[i], true, ptr, col, diag, upd_ptr, upd_tgt, a, w, pivtol, status);
     }
     __syncthreads();
   }
 }
 
-// -------------------------------------------- level-scheduled triangular
-// Solves T X = scale * B in place (X holds B on entry) for TW columns per
-// workgroup, all columns of a workgroup advancing level by level.  LOWER:
-// row i uses entries [ptr[i], diag[i]); otherwise (diag[i], ptr[i+1]).
-// UNIT: no division by the diagonal value val[diag[i]].
-template <int TW, bool LOWER, bool UNIT>
-__global__ void k_trsv_batch(int nlev, const int32_t* __restrict__ lev_ptr,
-                             const int32_t* __restrict__ lev_rows, const int32_t* __restrict__ ptr,
+// Top rows, eliminations by pack columns (all final): independent rows.
+__global__ void k_rf_top_ext(int t0, int n, const int32_t* __restrict__ lo_split, const int32_t* __restrict__ ptr,
                              const int32_t* __restrict__ col, const int32_t* __restrict__ diag,
-                             const double* __restrict__ val, double* __restrict__ X, int ld,
-                             int ncols, double scale) {
-  const int slot = threadIdx.x / TW;
-  const int nslot = blockDim.x / TW;
-  const int c = blockIdx.x * TW + (threadIdx.x % TW);
-  const bool active = c < ncols;
-  for (int lev = 0; lev < nlev; ++lev) {
-    const int r1 = lev_ptr[lev + 1];
-    for (int r = lev_ptr[lev] + slot; r < r1; r += nslot) {
-      const int i = lev_rows[r];
-      int pa, pb;
-      if (LOWER) { pa = ptr[i]; pb = diag[i]; } else { pa = diag[i] + 1; pb = ptr[i + 1]; }
-      if (active) {
-        double acc = scale * X[(size_t)i * ld + c];
-        for (int p = pa; p < pb; ++p) acc -= val[p] * X[(size_t)col[p] * ld + c];
-        if (!UNIT) acc /= val[diag[i]];
-        X[(size_t)i * ld + c] = acc;
+                             const int64_t* __restrict__ upd_ptr, const int32_t* __restrict__ upd_tgt,
+                             double* __restrict__ a, int maxrow, int32_t* __restrict__ status) {
+  extern __shared__ double lds[];
+  const int wave = threadIdx.x >> 6, nwave = blockDim.x >> 6;
+  double* w = lds + (size_t)wave * maxrow;
+  const int i = t0 + blockIdx.x * nwave + wave;
+  if (i >= n) return;
+  rf_row(i, lo_split[i], false, ptr, col, diag, upd_ptr, upd_tgt, a, w, 0.0, status);
+}
+
+__global__ void k_fill_dbl(int64_t n, double* __restrict__ p, double v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+// dense[off[e]] = a[pos[e]] (to_dense) or a[pos[e]] = dense[off[e]]
+__global__ void k_dense_xfer(int n, const int32_t* __restrict__ pos, const int64_t* __restrict__ off,
+                             double* __restrict__ a, double* __restrict__ dense, int to_dense) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  if (to_dense) dense[off[e]] = a[pos[e]];
+  else a[pos[e]] = dense[off[e]];
+}
+
+// ---------------------------------------- partitioned triangular solves
+// X is an [n x ld] row-major block; each workgroup owns TW columns.  The
+// rows of one pack (or of the top part) live in LDS for the whole solve;
+// levels are separated by workgroup barriers.  LOWER entries of row i are
+// [ptr[i], diag[i]); upper entries (diag[i], ptr[i+1]).
+
+// xs[b0 + r][c] -= sum_{j in [j0, j1)} M[b0 + r][j] xs[j][c] for the nb rows
+// of one block: M staged through LDS in 64 x 32 tiles (coalesced rows),
+// each thread accumulating up to four (row, column) pairs.
+__device__ inline void top_block_update(const double* __restrict__ M, int s, int b0, int nb, int j0, int j1,
+                                        double* xs, int tw, double (*mt)[33]) {
+  const int t = threadIdx.x;
+  const int npair = nb * tw;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int jt = j0; jt < j1; jt += 32) {
+    const int w = min(32, j1 - jt);
+    for (int e = t; e < CB * 32; e += blockDim.x) {
+      const int r = e >> 5, j = e & 31;
+      mt[r][j] = (r < nb && j < w) ? M[(size_t)(b0 + r) * s + jt + j] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int e = t + k * 256;
+      if (e < npair) {
+        const int r = e / tw, c = e - r * tw;
+        double a = acc[k];
+        for (int j = 0; j < w; ++j) a += mt[r][j] * xs[(jt + j) * tw + c];
+        acc[k] = a;
       }
     }
     __syncthreads();
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int e = t + k * 256;
+    if (e < npair) {
+      const int r = e / tw, c = e - r * tw;
+      xs[(b0 + r) * tw + c] -= acc[k];
+    }
+  }
+  __syncthreads();
+}
+
+// Top part with its dense factor M (s x s, row-major): rows of the top
+// block after the pack contributions are subtracted; forward solve with the
+// lower part of M (unit or not), then with BWD the backward solve with its
+// upper part.  Blocks of CB rows: products with solved blocks by all
+// threads (one (row, column) pair each), the CB x CB triangle by one
+// wavefront per column (lane = row, its row of the triangle in registers).
+// 256 threads, tw columns per workgroup.
+template <bool FUNIT, bool BWD, bool BUNIT>
+__global__ void __launch_bounds__(256) k_top_dense(int t0, int n, const int32_t* __restrict__ lo_split,
+                                                   const int32_t* __restrict__ ptr, const int32_t* __restrict__ col,
+                                                   const double* __restrict__ fval, const double* __restrict__ M,
+                                                   double* __restrict__ X, int ld, int ncols, double scale, int tw) {
+  extern __shared__ double xs[];
+  __shared__ double mt[CB][33];
+  const int s = n - t0;
+  const int c0 = blockIdx.x * tw;
+  const int t = threadIdx.x;
+  // contributions of the final pack rows (sparse, independent)
+  for (int e = t; e < s * tw; e += blockDim.x) {
+    const int r = e / tw, c = e - r * tw;
+    const int i = t0 + r;
+    double acc = 0.0;
+    if (c0 + c < ncols) {
+      acc = scale * X[(size_t)i * ld + c0 + c];
+      for (int p = ptr[i]; p < lo_split[i]; ++p) acc -= fval[p] * X[(size_t)col[p] * ld + c0 + c];
+    }
+    xs[e] = acc;
+  }
+  __syncthreads();
+  const int wv = t >> 6, lane = t & 63;
+  const int nwv = blockDim.x >> 6;
+  // forward
+  for (int b0 = 0; b0 < s; b0 += CB) {
+    const int nb = min(CB, s - b0);
+    top_block_update(M, s, b0, nb, 0, b0, xs, tw, mt);
+    if (wv < tw) {
+      double mr[CB];
+      const double* Mr = M + (size_t)(b0 + min(lane, nb - 1)) * s + b0;
+#pragma unroll
+      for (int j = 0; j < CB; ++j) mr[j] = j < nb ? Mr[j] : 0.0;
+      for (int c = wv; c < tw; c += nwv) {
+        double v = lane < nb ? xs[(b0 + lane) * tw + c] : 0.0;
+#pragma unroll
+        for (int j = 0; j < CB; ++j) {
+          if (j < nb) {
+            double xj = __shfl(v, j, 64);
+            if (!FUNIT) xj /= __shfl(mr[j], j, 64);
+            if (lane == j) v = xj;
+            if (lane > j) v -= mr[j] * xj;
+          }
+        }
+        if (lane < nb) xs[(b0 + lane) * tw + c] = v;
+      }
+    }
+    __syncthreads();
+  }
+  if (BWD) {
+    for (int b1 = s; b1 > 0; b1 -= CB) {
+      const int b0 = max(0, b1 - CB), nb = b1 - b0;
+      top_block_update(M, s, b0, nb, b1, s, xs, tw, mt);
+      if (wv < tw) {
+        double mr[CB];
+        const double* Mr = M + (size_t)(b0 + min(lane, nb - 1)) * s + b0;
+#pragma unroll
+        for (int j = 0; j < CB; ++j) mr[j] = j < nb ? Mr[j] : 0.0;
+        for (int c = wv; c < tw; c += nwv) {
+          double v = lane < nb ? xs[(b0 + lane) * tw + c] : 0.0;
+#pragma unroll
+          for (int j = CB - 1; j >= 0; --j) {
+            if (j < nb) {
+              double xj = __shfl(v, j, 64);
+              if (!BUNIT) xj /= __shfl(mr[j], j, 64);
+              if (lane == j) v = xj;
+              if (lane < j) v -= mr[j] * xj;
+            }
+          }
+          if (lane < nb) xs[(b0 + lane) * tw + c] = v;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  for (int e = t; e < s * tw; e += blockDim.x) {
+    const int r = e / tw, c = e - r * tw;
+    if (c0 + c < ncols) X[(size_t)(t0 + r) * ld + c0 + c] = xs[e];
+  }
+}
+
+// Staged pack solves: the pack's level lists, local columns, factor values
+// and diagonal are copied to LDS first, so the level loop reads only LDS.
+// LDS layout: xs[nr*TW] | val[ne] | dg[nr] | rp[nr+1] (int) | lev[nlev+1]
+// (int) | rows[nr] (short) | col[ne] (short).
+__host__ __device__ inline size_t pack_lds_bytes(int nr, int ne, int nlev, int tw) {
+  size_t b = (size_t)nr * tw * 8 + (size_t)ne * 8 + (size_t)nr * 8 + (size_t)(nr + 1) * 4 +
+             (size_t)(nlev + 1) * 4 + (size_t)nr * 2 + (size_t)ne * 2;
+  return (b + 15) & ~(size_t)15;
+}
+
+template <int TW, bool FWD, bool UNIT>
+__global__ void k_pack_solve_s(const int32_t* __restrict__ pack_ptr, const int32_t* __restrict__ lev,
+                               const int32_t* __restrict__ lev_off, const int32_t* __restrict__ lrows,
+                               const int32_t* __restrict__ rp, const int32_t* __restrict__ epos,
+                               const int16_t* __restrict__ ecol, const int32_t* __restrict__ diag,
+                               const int32_t* __restrict__ up_split, const int32_t* __restrict__ ptr,
+                               const int32_t* __restrict__ col, const double* __restrict__ val,
+                               double* __restrict__ X, int ld, int ncols, double scale) {
+  extern __shared__ double smem[];
+  const int q = blockIdx.x;
+  const int c0 = blockIdx.y * TW;
+  const int r0 = pack_ptr[q], nr = pack_ptr[q + 1] - r0;
+  const int e0 = rp[r0], ne = rp[r0 + nr] - e0;
+  const int l0 = lev_off[q], nlev = lev_off[q + 1] - l0;
+  const int base_row = lev[l0];
+  double* xs = smem;
+  double* sv = xs + (size_t)nr * TW;
+  double* dg = sv + ne;
+  int* srp = (int*)(dg + nr);
+  int* slev = srp + nr + 1;
+  short* srow = (short*)(slev + nlev + 1);
+  short* scol = srow + nr;
+  const int t = threadIdx.x;
+  for (int e = t; e < ne; e += blockDim.x) {
+    sv[e] = val[epos[e0 + e]];
+    scol[e] = ecol[e0 + e];
+  }
+  for (int r = t; r <= nr; r += blockDim.x) srp[r] = rp[r0 + r] - e0;
+  for (int r = t; r < nr; r += blockDim.x) {
+    if (!UNIT) dg[r] = val[diag[r0 + r]];
+    srow[r] = (short)(lrows[base_row + r] - r0);
+  }
+  for (int k = t; k <= nlev; k += blockDim.x) slev[k] = lev[l0 + k] - base_row;
+  for (int e = t; e < nr * TW; e += blockDim.x) {
+    const int r = e / TW, c = e - r * TW;
+    const int i = r0 + r;
+    double acc = 0.0;
+    if (c0 + c < ncols) {
+      if (FWD) {
+        acc = scale * X[(size_t)i * ld + c0 + c];
+      } else {
+        acc = X[(size_t)i * ld + c0 + c];
+        for (int p = up_split[i]; p < ptr[i + 1]; ++p) acc -= val[p] * X[(size_t)col[p] * ld + c0 + c];
+      }
+    }
+    xs[e] = acc;
+  }
+  __syncthreads();
+  const int cc = t % TW, slot = t / TW, nslot = blockDim.x / TW;
+  for (int lv = 0; lv < nlev; ++lv) {
+    const int b1 = slev[lv + 1];
+    for (int k = slev[lv] + slot; k < b1; k += nslot) {
+      const int r = srow[k];
+      double acc = xs[r * TW + cc];
+      for (int e = srp[r]; e < srp[r + 1]; ++e) acc -= sv[e] * xs[scol[e] * TW + cc];
+      if (!UNIT) acc /= dg[r];
+      xs[r * TW + cc] = acc;
+    }
+    __syncthreads();
+  }
+  for (int e = t; e < nr * TW; e += blockDim.x) {
+    const int r = e / TW, c = e - r * TW;
+    if (c0 + c < ncols) X[(size_t)(r0 + r) * ld + c0 + c] = xs[e];
   }
 }
 
@@ -561,154 +772,253 @@ __global__ void k_symmetrize(int n, double* __restrict__ K, const double* __rest
   }
 }
 
-constexpr int CB = 64;  // Cholesky panel width
 
-// Unblocked Cholesky of the diagonal block A[k0:k0+nb, k0:k0+nb] in LDS.
-__global__ void k_chol_diag(int n, int k0, double* __restrict__ A, int32_t* __restrict__ info) {
-  __shared__ double T[CB][CB + 1];
-  __shared__ int bad;
+// ------------------------------------------- blocked dense factorizations
+// Right-looking blocked LU without pivoting (CHOL = false) or Cholesky
+// (CHOL = true, lower triangle) of a row-major n x n matrix, per block of
+// CB columns: diagonal block by one wavefront, panels one wavefront per row
+// (and per column for LU), trailing update in 64 x 64 tiles.  A failing
+// pivot records base + (column + 1) in info[0]; later kernels return early.
+
+template <bool CHOL>
+__global__ void __launch_bounds__(64) k_blk_diag(int n, int b0, double* __restrict__ A, int32_t* __restrict__ info, int base) {
+  __shared__ double bc[CB];
   if (info[0] != 0) return;
-  const int nb = min(CB, n - k0);
-  for (int e = threadIdx.x; e < nb * nb; e += blockDim.x) {
-    int i = e / nb, j = e % nb;
-    T[i][j] = j <= i ? A[(size_t)(k0 + i) * n + k0 + j] : 0.0;
-  }
-  if (threadIdx.x == 0) bad = 0;
-  __syncthreads();
-  for (int j = 0; j < nb; ++j) {
-    if (threadIdx.x == 0) {
-      double d = T[j][j];
-      if (!(d > 0.0)) {
-        bad = j + 1;
-      } else {
-        T[j][j] = sqrt(d);
+  const int nb = min(CB, n - b0);
+  const int i = threadIdx.x;  // one wavefront: lane i owns row i in registers
+  double r[CB];
+  const double* Ar = A + (size_t)(b0 + min(i, nb - 1)) * n + b0;
+#pragma unroll
+  for (int j = 0; j < CB; ++j) r[j] = (i < nb && j < nb && (!CHOL || j <= i)) ? Ar[j] : 0.0;
+#pragma unroll
+  for (int j = 0; j < CB; ++j) {
+    if (j < nb) {
+      const double d = __shfl(r[j], j, 64);
+      const bool ok = CHOL ? (d > 0.0) : (fabs(d) > 0.0 && isfinite(d));
+      if (!ok) {
+        if (i == 0) info[0] = base + b0 + j + 1;
+        return;
       }
+      const double piv = CHOL ? sqrt(d) : d;
+      double lij = 0.0;
+      if (i > j && i < nb) {
+        lij = r[j] / piv;
+        r[j] = lij;
+      }
+      if (CHOL && i == j) r[j] = piv;
+      // broadcast column j of L (Cholesky) or row j of U (LU) through LDS
+      if (CHOL) {
+        bc[i] = lij;
+      } else if (i == j) {
+#pragma unroll
+        for (int c = 0; c < CB; ++c) bc[c] = r[c];
+      }
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      if (i > j && i < nb) {
+#pragma unroll
+        for (int c = j + 1; c < CB; ++c)
+          if (c < nb && (!CHOL || c <= i)) r[c] -= lij * bc[c];
+      }
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      __builtin_amdgcn_wave_barrier();
     }
-    __syncthreads();
-    if (bad) break;
-    const double djj = T[j][j];
-    for (int i = j + 1 + threadIdx.x; i < nb; i += blockDim.x) T[i][j] /= djj;
-    __syncthreads();
-    for (int e = threadIdx.x; e < (nb - j - 1) * (nb - j - 1); e += blockDim.x) {
-      int i = j + 1 + e / (nb - j - 1), c = j + 1 + e % (nb - j - 1);
-      if (c <= i) T[i][c] -= T[i][j] * T[c][j];
-    }
-    __syncthreads();
   }
-  if (bad) {
-    if (threadIdx.x == 0) info[0] = k0 + bad;
-    return;
-  }
-  for (int e = threadIdx.x; e < nb * nb; e += blockDim.x) {
-    int i = e / nb, j = e % nb;
-    if (j <= i) A[(size_t)(k0 + i) * n + k0 + j] = T[i][j];
+  if (i < nb) {
+    double* Aw = A + (size_t)(b0 + i) * n + b0;
+#pragma unroll
+    for (int j = 0; j < CB; ++j)
+      if (j < nb && (!CHOL || j <= i)) Aw[j] = r[j];
   }
 }
 
-// Panel below the diagonal block: A21 <- A21 L11^{-T}; one row per thread.
-__global__ void k_chol_trsm(int n, int k0, double* __restrict__ A, const int32_t* __restrict__ info) {
-  __shared__ double L[CB][CB + 1];
+// Panels: wave task t < rows below: row r solves x U11 = a (LU) or
+// x L11^T = a (Cholesky); for LU, tasks past the rows solve L11 y = a for a
+// column to the right (unit lower).  Lanes hold the CB entries.
+template <bool CHOL>
+__global__ void k_blk_panel(int n, int b0, double* __restrict__ A, const int32_t* __restrict__ info) {
+  __shared__ double T[CB][CB + 1];
   if (info[0] != 0) return;
-  const int nb = min(CB, n - k0);
-  for (int e = threadIdx.x; e < nb * nb; e += blockDim.x) {
-    int i = e / nb, j = e % nb;
-    L[i][j] = j <= i ? A[(size_t)(k0 + i) * n + k0 + j] : 0.0;
+  const int nb = min(CB, n - b0);
+  const int rest = n - b0 - nb;
+  for (int e = threadIdx.x; e < CB * CB; e += blockDim.x) {
+    const int r = e / CB, c = e % CB;
+    T[r][c] = (r < nb && c < nb) ? A[(size_t)(b0 + r) * n + b0 + c] : (r == c ? 1.0 : 0.0);
   }
   __syncthreads();
-  const int row = k0 + nb + blockIdx.x * blockDim.x + threadIdx.x;
-  if (row >= n) return;
-  double x[CB];
-  double* a = A + (size_t)row * n + k0;
-  for (int j = 0; j < nb; ++j) {
-    double v = a[j];
-    for (int k = 0; k < j; ++k) v -= x[k] * L[j][k];
-    x[j] = v / L[j][j];
+  const int lane = threadIdx.x & 63;
+  const int task = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (task < rest) {
+    double* a = A + (size_t)(b0 + nb + task) * n + b0;
+    double v = lane < nb ? a[lane] : 0.0;
+    for (int j = 0; j < nb; ++j) {
+      const double xj = __shfl(v, j, 64) / T[j][j];
+      if (lane == j) v = xj;
+      if (lane > j) v -= xj * (CHOL ? T[lane][j] : T[j][lane]);
+    }
+    if (lane < nb) a[lane] = v;
+  } else if (!CHOL && task < 2 * rest) {
+    const int c = b0 + nb + (task - rest);
+    double v = lane < nb ? A[(size_t)(b0 + lane) * n + c] : 0.0;
+    for (int j = 0; j < nb; ++j) {
+      const double yj = __shfl(v, j, 64);
+      if (lane > j) v -= T[lane][j] * yj;
+    }
+    if (lane < nb) A[(size_t)(b0 + lane) * n + c] = v;
   }
-  for (int j = 0; j < nb; ++j) a[j] = x[j];
 }
 
-// Trailing update A22 -= L21 L21^T on lower-triangle tiles of 64 x 64.
-__global__ void k_chol_update(int n, int k0, double* __restrict__ A, const int32_t* __restrict__ info) {
+// Trailing update A22 -= L21 U12 (LU) or L21 L21^T (Cholesky, lower tiles).
+template <bool CHOL>
+__global__ void k_blk_update(int n, int b0, double* __restrict__ A, const int32_t* __restrict__ info) {
   __shared__ double Ls[CB][CB + 1];
-  __shared__ double Rs[CB][CB + 1];
+  __shared__ double Us[CB][CB + 1];
   if (info[0] != 0) return;
-  const int nb = min(CB, n - k0);
-  const int base = k0 + nb;
+  const int nb = min(CB, n - b0);
+  const int base = b0 + nb;
   const int ti = blockIdx.y, tj = blockIdx.x;
-  if (tj > ti) return;
+  if (CHOL && tj > ti) return;
   const int i0 = base + ti * CB, j0 = base + tj * CB;
   for (int e = threadIdx.x; e < CB * CB; e += blockDim.x) {
-    int r = e / CB, k = e % CB;
-    Ls[r][k] = (i0 + r < n && k < nb) ? A[(size_t)(i0 + r) * n + k0 + k] : 0.0;
-    Rs[r][k] = (j0 + r < n && k < nb) ? A[(size_t)(j0 + r) * n + k0 + k] : 0.0;
+    const int r = e / CB, k = e % CB;
+    Ls[r][k] = (i0 + r < n && k < nb) ? A[(size_t)(i0 + r) * n + b0 + k] : 0.0;
+    if (CHOL)
+      Us[k][r] = (j0 + r < n && k < nb) ? A[(size_t)(j0 + r) * n + b0 + k] : 0.0;
+    else
+      Us[r][k] = (r < nb && j0 + k < n) ? A[(size_t)(b0 + r) * n + j0 + k] : 0.0;
   }
   __syncthreads();
-  // 256 threads, each a 4 x 4 sub-tile
-  const int tr = (threadIdx.x / 16) * 4, tc = (threadIdx.x % 16) * 4;
+  const int tr = (threadIdx.x >> 4) * 4, tc = (threadIdx.x & 15) * 4;
   double acc[4][4] = {};
-  for (int k = 0; k < nb; ++k)
+  for (int k = 0; k < nb; ++k) {
+    double l[4], u[4];
+#pragma unroll
+    for (int p = 0; p < 4; ++p) l[p] = Ls[tr + p][k];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) u[q] = Us[k][tc + q];
 #pragma unroll
     for (int p = 0; p < 4; ++p)
 #pragma unroll
-      for (int q = 0; q < 4; ++q) acc[p][q] += Ls[tr + p][k] * Rs[tc + q][k];
+      for (int q = 0; q < 4; ++q) acc[p][q] += l[p] * u[q];
+  }
 #pragma unroll
   for (int p = 0; p < 4; ++p)
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      int i = i0 + tr + p, j = j0 + tc + q;
-      if (i < n && j < n && j <= i) A[(size_t)i * n + j] -= acc[p][q];
+      const int i = i0 + tr + p, j = j0 + tc + q;
+      if (i < n && j < n && (!CHOL || j <= i)) A[(size_t)i * n + j] -= acc[p][q];
     }
 }
 
-// Forward/back substitution with the lower factor (single workgroup):
-// L y = -rhs, L^T step = y.
-__global__ void k_chol_solve(int n, const double* __restrict__ L, const double* __restrict__ rhs,
-                             double* __restrict__ step, double* __restrict__ work,
-                             const int32_t* __restrict__ info) {
+__global__ void k_transpose(int n, const double* __restrict__ A, double* __restrict__ B) {
+  __shared__ double t[32][33];
+  const int bx = blockIdx.x * 32, by = blockIdx.y * 32;
+  for (int k = threadIdx.y; k < 32; k += blockDim.y) {
+    const int r = by + k, c = bx + threadIdx.x;
+    if (r < n && c < n) t[k][threadIdx.x] = A[(size_t)r * n + c];
+  }
+  __syncthreads();
+  for (int k = threadIdx.y; k < 32; k += blockDim.y) {
+    const int r = bx + k, c = by + threadIdx.x;
+    if (r < n && c < n) B[(size_t)r * n + c] = t[threadIdx.x][k];
+  }
+}
+
+// Forward/back substitution with the lower factor in one workgroup of 1024
+// threads: per block of 64 rows, the products with the solved entries use
+// all threads (16 per row), the 64 x 64 triangle one wavefront with its row
+// of the triangle in registers.   L y = -rhs,  L^T step = y.
+__global__ void __launch_bounds__(256) k_chol_solve(int n, const double* __restrict__ L,
+                                                    const double* __restrict__ rhs, double* __restrict__ step,
+                                                    double* __restrict__ work, const int32_t* __restrict__ info) {
   if (info[0] != 0) return;
-  __shared__ double xs[CB];
+  __shared__ double part[CB][17];
+  const int t = threadIdx.x;
+  const int rr = t >> 4, sl = t & 15;   // row (of 16 per pass), slice
   double* yv = work;
-  // forward: blocks of CB rows
   for (int b0 = 0; b0 < n; b0 += CB) {
     const int nb = min(CB, n - b0);
-    // partial dot products with solved entries, one row per thread group
-    for (int r = threadIdx.x; r < nb; r += blockDim.x) {
-      double v = -rhs[b0 + r];
-      const double* Lr = L + (size_t)(b0 + r) * n;
-      for (int k = 0; k < b0; ++k) v -= Lr[k] * yv[k];
-      xs[r] = v;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      for (int r = 0; r < nb; ++r) {
-        double v = xs[r];
-        const double* Lr = L + (size_t)(b0 + r) * n + b0;
-        for (int k = 0; k < r; ++k) v -= Lr[k] * xs[k];
-        xs[r] = v / Lr[r];
+    for (int r = rr; r < CB; r += 16) {
+      double a0 = 0.0, a1 = 0.0;
+      if (r < nb) {
+        const double* Lr = L + (size_t)(b0 + r) * n;
+        double a2 = 0.0, a3 = 0.0;
+        int k = sl;
+        for (; k + 48 < b0; k += 64) {
+          a0 += Lr[k] * yv[k];
+          a1 += Lr[k + 16] * yv[k + 16];
+          a2 += Lr[k + 32] * yv[k + 32];
+          a3 += Lr[k + 48] * yv[k + 48];
+        }
+        for (; k < b0; k += 16) a0 += Lr[k] * yv[k];
+        a0 += a2;
+        a1 += a3;
       }
+      part[r][sl] = a0 + a1;
     }
     __syncthreads();
-    for (int r = threadIdx.x; r < nb; r += blockDim.x) yv[b0 + r] = xs[r];
+    if (t < 64) {
+      double lr[CB];
+      const double* Lr = L + (size_t)(b0 + min(t, nb - 1)) * n + b0;
+#pragma unroll
+      for (int j = 0; j < CB; ++j) lr[j] = j < nb ? Lr[j] : 0.0;
+      double v = 0.0;
+      if (t < nb) {
+        v = -rhs[b0 + t];
+        for (int q = 0; q < 16; ++q) v -= part[t][q];
+      }
+#pragma unroll
+      for (int k = 0; k < CB; ++k) {
+        if (k < nb) {
+          const double yk = __shfl(v, k, 64) / __shfl(lr[k], k, 64);
+          if (t == k) v = yk;
+          if (t > k) v -= lr[k] * yk;
+        }
+      }
+      if (t < nb) yv[b0 + t] = v;
+    }
     __syncthreads();
   }
-  // backward with L^T: step_i = (y_i - sum_{k>i} L_ki step_k) / L_ii
   for (int b1 = n; b1 > 0; b1 -= CB) {
     const int b0 = max(0, b1 - CB), nb = b1 - b0;
-    for (int r = threadIdx.x; r < nb; r += blockDim.x) {
-      double v = yv[b0 + r];
-      for (int k = b1; k < n; ++k) v -= L[(size_t)k * n + b0 + r] * step[k];
-      xs[r] = v;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      for (int r = nb - 1; r >= 0; --r) {
-        double v = xs[r];
-        for (int k = r + 1; k < nb; ++k) v -= L[(size_t)(b0 + k) * n + b0 + r] * xs[k];
-        xs[r] = v / L[(size_t)(b0 + r) * n + b0 + r];
+    for (int r = rr; r < CB; r += 16) {
+      double a0 = 0.0, a1 = 0.0;
+      if (r < nb) {
+        double a2 = 0.0, a3 = 0.0;
+        int k = b1 + sl;
+        for (; k + 48 < n; k += 64) {
+          a0 += L[(size_t)k * n + b0 + r] * step[k];
+          a1 += L[(size_t)(k + 16) * n + b0 + r] * step[k + 16];
+          a2 += L[(size_t)(k + 32) * n + b0 + r] * step[k + 32];
+          a3 += L[(size_t)(k + 48) * n + b0 + r] * step[k + 48];
+        }
+        for (; k < n; k += 16) a0 += L[(size_t)k * n + b0 + r] * step[k];
+        a0 += a2;
+        a1 += a3;
       }
+      part[r][sl] = a0 + a1;
     }
     __syncthreads();
-    for (int r = threadIdx.x; r < nb; r += blockDim.x) step[b0 + r] = xs[r];
+    if (t < 64) {
+      // lane t holds column t of the triangle: L[b0 + k][b0 + t]
+      double lc[CB];
+#pragma unroll
+      for (int k = 0; k < CB; ++k) lc[k] = (k < nb && t < nb) ? L[(size_t)(b0 + k) * n + b0 + t] : 0.0;
+      double v = 0.0;
+      if (t < nb) {
+        v = yv[b0 + t];
+        for (int q = 0; q < 16; ++q) v -= part[t][q];
+      }
+#pragma unroll
+      for (int k = CB - 1; k >= 0; --k) {
+        if (k < nb) {
+          const double xk = __shfl(v, k, 64) / __shfl(lc[k], k, 64);
+          if (t == k) v = xk;
+          if (t < k) v -= lc[k] * xk;
+        }
+      }
+      if (t < nb) step[b0 + t] = v;
+    }
     __syncthreads();
   }
 }

@@ -108,8 +108,9 @@ void to_lists(int nslots, std::vector<std::pair<int, int>>& pairs, std::vector<i
 
 }  // namespace
 
-Presolve build_presolve(const GridData& g) {
+Presolve build_presolve(const GridData& g, int subtree_max) {
   Presolve P;
+  P.subtree_max = subtree_max;
   const int nb = g.nb, nl = g.nl, ng = g.ng;
   if (nb < 2 || nl < 1 || ng < 1) fail("grid needs nb >= 2, nl >= 1, ng >= 1");
   if ((int)g.bus_type.size() != nb || (int)g.br_from.size() != nl || (int)g.br_to.size() != nl ||
@@ -167,86 +168,148 @@ Presolve build_presolve(const GridData& g) {
   std::vector<int> weight(nb, 0);
   for (int i = 0; i < nb; ++i) weight[i] = g.bus_type[i] == BUS_PQ ? 2 : (g.bus_type[i] == BUS_PV ? 1 : 0);
   std::vector<int> order = bus_min_degree(nb, P.ref, adj, weight);
-
-  P.th_var.assign(nb, -1);
-  P.v_var.assign(nb, -1);
-  P.p_var.assign(nb, -1);
-  P.rowP.assign(nb, -1);
-  P.rowQ.assign(nb, -1);
-  P.x_int2paper.assign(nx, -1);
-  P.var_bus.assign(nx, -1);
-  P.var_isv.assign(nx, 0);
+  // state variables in elimination order: theta_i, then v_i for PQ buses
+  std::vector<std::pair<int, int>> vars;   // (bus, is_v)
+  for (int bus : order) {
+    vars.push_back({bus, 0});
+    if (g.bus_type[bus] == BUS_PQ) vars.push_back({bus, 1});
+  }
+  if ((int)vars.size() != nx) fail("internal: state count mismatch");
   std::vector<int> pv_pos(nb, -1), pq_pos(nb, -1);
   for (int k = 0; k < P.npv; ++k) pv_pos[P.pv[k]] = k;
   for (int k = 0; k < P.npq; ++k) pq_pos[P.pq[k]] = k;
-  int cnt = 0;
-  for (int bus : order) {
-    P.th_var[bus] = cnt;
-    P.rowP[bus] = cnt;
-    P.var_bus[cnt] = bus;
-    P.x_int2paper[cnt] = g.bus_type[bus] == BUS_PV ? pv_pos[bus] : P.npv + pq_pos[bus];
-    ++cnt;
-    if (g.bus_type[bus] == BUS_PQ) {
-      P.v_var[bus] = cnt;
-      P.rowQ[bus] = cnt;
-      P.var_bus[cnt] = bus;
-      P.var_isv[cnt] = 1;
-      P.x_int2paper[cnt] = P.npv + P.npq + pq_pos[bus];
-      ++cnt;
-    }
-  }
-  if (cnt != nx) fail("internal: state count mismatch");
-  P.v_var[P.ref] = nx;
-  for (int k = 0; k < P.npv; ++k) {
-    P.v_var[P.pv[k]] = nx + 1 + k;
-    P.p_var[P.pv[k]] = nx + 1 + P.npv + k;
-  }
 
-  // ------------------------------------------------- pattern of J_x, etree
-  std::vector<std::vector<int>> arow(nx);
-  for (int r = 0; r < nx; ++r) {
-    int i = P.var_bus[r];
-    auto add_bus = [&](int b) {
-      if (P.th_var[b] >= 0) arow[r].push_back(P.th_var[b]);
-      if (g.bus_type[b] == BUS_PQ) arow[r].push_back(P.v_var[b]);
-    };
-    add_bus(i);
-    for (int j : adj[i]) add_bus(j);
-    std::sort(arow[r].begin(), arow[r].end());
-  }
-  std::vector<int> parent(nx, -1), ancestor(nx, -1);
-  for (int i = 0; i < nx; ++i)
-    for (int k : arow[i]) {
-      if (k >= i) break;
-      int r = k;
-      while (ancestor[r] != -1 && ancestor[r] != i) {
-        int nxt = ancestor[r];
-        ancestor[r] = i;
-        r = nxt;
-      }
-      if (ancestor[r] == -1) {
-        ancestor[r] = i;
-        parent[r] = i;
-      }
-    }
-  std::vector<std::vector<int>> lrow(nx), urow(nx);
-  std::vector<int> mark(nx, -1);
-  for (int i = 0; i < nx; ++i) {
-    mark[i] = i;
-    for (int k : arow[i]) {
-      if (k >= i) break;
-      int j = k;
-      while (mark[j] != i) {
-        lrow[i].push_back(j);
-        mark[j] = i;
-        j = parent[j];
-        if (j < 0) fail("internal: broken elimination tree");
+  std::vector<int> parent;
+  std::vector<std::vector<int>> lrow, urow;
+  // number the variables in the order `vars` and compute the symbolic
+  // factorization (elimination tree, row patterns of L and U)
+  auto symbolic = [&]() {
+    P.th_var.assign(nb, -1);
+    P.v_var.assign(nb, -1);
+    P.p_var.assign(nb, -1);
+    P.rowP.assign(nb, -1);
+    P.rowQ.assign(nb, -1);
+    P.x_int2paper.assign(nx, -1);
+    P.var_bus.assign(nx, -1);
+    P.var_isv.assign(nx, 0);
+    for (int c = 0; c < nx; ++c) {
+      int bus = vars[c].first;
+      P.var_bus[c] = bus;
+      if (vars[c].second == 0) {
+        P.th_var[bus] = c;
+        P.rowP[bus] = c;
+        P.x_int2paper[c] = g.bus_type[bus] == BUS_PV ? pv_pos[bus] : P.npv + pq_pos[bus];
+      } else {
+        P.v_var[bus] = c;
+        P.rowQ[bus] = c;
+        P.var_isv[c] = 1;
+        P.x_int2paper[c] = P.npv + P.npq + pq_pos[bus];
       }
     }
-    std::sort(lrow[i].begin(), lrow[i].end());
+    P.v_var[P.ref] = nx;
+    for (int k = 0; k < P.npv; ++k) {
+      P.v_var[P.pv[k]] = nx + 1 + k;
+      P.p_var[P.pv[k]] = nx + 1 + P.npv + k;
+    }
+    std::vector<std::vector<int>> arow(nx);
+    for (int r = 0; r < nx; ++r) {
+      int i = P.var_bus[r];
+      auto add_bus = [&](int bb) {
+        if (P.th_var[bb] >= 0) arow[r].push_back(P.th_var[bb]);
+        if (g.bus_type[bb] == BUS_PQ) arow[r].push_back(P.v_var[bb]);
+      };
+      add_bus(i);
+      for (int j : adj[i]) add_bus(j);
+      std::sort(arow[r].begin(), arow[r].end());
+    }
+    parent.assign(nx, -1);
+    std::vector<int> ancestor(nx, -1);
+    for (int i = 0; i < nx; ++i)
+      for (int k : arow[i]) {
+        if (k >= i) break;
+        int r = k;
+        while (ancestor[r] != -1 && ancestor[r] != i) {
+          int nxt = ancestor[r];
+          ancestor[r] = i;
+          r = nxt;
+        }
+        if (ancestor[r] == -1) {
+          ancestor[r] = i;
+          parent[r] = i;
+        }
+      }
+    lrow.assign(nx, {});
+    urow.assign(nx, {});
+    std::vector<int> mark(nx, -1);
+    for (int i = 0; i < nx; ++i) {
+      mark[i] = i;
+      for (int k : arow[i]) {
+        if (k >= i) break;
+        int j = k;
+        while (mark[j] != i) {
+          lrow[i].push_back(j);
+          mark[j] = i;
+          j = parent[j];
+          if (j < 0) fail("internal: broken elimination tree");
+        }
+      }
+      std::sort(lrow[i].begin(), lrow[i].end());
+    }
+    for (int i = 0; i < nx; ++i)
+      for (int k : lrow[i]) urow[k].push_back(i);   // ascending i -> sorted
+  };
+  symbolic();
+
+  // ------------------------------------------------ subtree partition
+  // Subtrees of the elimination tree with at most subtree_max rows are
+  // independent in the forward solves and in the refactorization; they are
+  // packed into contiguous row ranges (packs), and the remaining "top" rows
+  // (ancestors of the packs) are numbered last.  Any topological order of
+  // the elimination tree has the same fill, so the factor pattern is only
+  // permuted.
+  {
+    const int smax = std::max(1, P.subtree_max);
+    std::vector<int> size(nx, 1);
+    for (int i = 0; i < nx; ++i)
+      if (parent[i] >= 0) size[parent[i]] += size[i];
+    std::vector<int> root_of(nx, -1);
+    std::vector<char> is_top(nx, 0);
+    for (int i = nx - 1; i >= 0; --i) {
+      if (size[i] > smax) {
+        is_top[i] = 1;
+      } else if (parent[i] < 0 || size[parent[i]] > smax) {
+        root_of[i] = i;
+      } else {
+        root_of[i] = root_of[parent[i]];
+      }
+    }
+    // packs: consecutive subtree roots (ascending) up to smax rows each
+    std::vector<int> pack_of_root(nx, -1);
+    int npk = 0, fillc = 0;
+    for (int i = 0; i < nx; ++i)
+      if (root_of[i] == i) {
+        if (npk == 0 || fillc + size[i] > smax) {
+          ++npk;
+          fillc = 0;
+        }
+        pack_of_root[i] = npk - 1;
+        fillc += size[i];
+      }
+    std::vector<int> key(nx);
+    for (int i = 0; i < nx; ++i) key[i] = is_top[i] ? npk : pack_of_root[root_of[i]];
+    std::vector<int> newo(nx);
+    std::iota(newo.begin(), newo.end(), 0);
+    std::stable_sort(newo.begin(), newo.end(), [&](int x0, int x1) { return key[x0] < key[x1]; });
+    std::vector<std::pair<int, int>> v2(nx);
+    for (int c = 0; c < nx; ++c) v2[c] = vars[newo[c]];
+    vars = v2;
+    P.pack_ptr.assign(npk + 1, 0);
+    for (int i = 0; i < nx; ++i)
+      if (!is_top[i]) P.pack_ptr[pack_of_root[root_of[i]] + 1]++;
+    for (int q = 0; q < npk; ++q) P.pack_ptr[q + 1] += P.pack_ptr[q];
+    P.t0 = P.pack_ptr[npk];
   }
-  for (int i = 0; i < nx; ++i)
-    for (int k : lrow[i]) urow[k].push_back(i);   // ascending i -> sorted
+  symbolic();
   std::vector<std::vector<int>> lurow(nx);
   P.lu_diag.assign(nx, 0);
   for (int i = 0; i < nx; ++i) {
@@ -284,6 +347,142 @@ Presolve build_presolve(const GridData& g) {
   }
   P.lev_lo = make_levels(lev);
   P.lev_up = make_levels(ulev);
+
+  // ------------------------------------------- partition level lists
+  {
+    const int t0 = P.t0;
+    const int npk = (int)P.pack_ptr.size() - 1;
+    P.lo_split.assign(nx, 0);
+    P.up_split.assign(nx, 0);
+    for (int i = 0; i < nx; ++i) {
+      int p = P.lu_ptr[i];
+      while (p < P.lu_diag[i] && P.lu_col[p] < t0) ++p;
+      P.lo_split[i] = p;
+      int q = P.lu_diag[i] + 1;
+      while (q < P.lu_ptr[i + 1] && P.lu_col[q] < t0) ++q;
+      P.up_split[i] = q;
+    }
+    // every LDS index of the partitioned solves stays inside its block:
+    // pack rows reference their own pack or the top part, top rows
+    // reference packs (below t0) only through their first lower entries
+    for (int q = 0; q + 1 < (int)P.pack_ptr.size(); ++q)
+      for (int i = P.pack_ptr[q]; i < P.pack_ptr[q + 1]; ++i)
+        for (int p = P.lu_ptr[i]; p < P.lu_ptr[i + 1]; ++p) {
+          int c = P.lu_col[p];
+          bool own = c >= P.pack_ptr[q] && c < P.pack_ptr[q + 1];
+          if (!own && c < t0) fail("internal: pack row references another pack");
+          if (c >= t0 && p < P.lu_diag[i]) fail("internal: pack row has a top column below its diagonal");
+        }
+    for (int i = t0; i < nx; ++i)
+      for (int p = P.lu_diag[i]; p < P.lu_ptr[i + 1]; ++p)
+        if (P.lu_col[p] < t0) fail("internal: top row references a pack above its diagonal");
+    // forward / backward levels inside each pack (pack-local dependencies)
+    P.pk_flev.assign(1, 0);
+    P.pk_blev.assign(1, 0);
+    P.pk_flev_off.assign(npk + 1, 0);
+    P.pk_blev_off.assign(npk + 1, 0);
+    P.pk_frows.clear();
+    P.pk_brows.clear();
+    std::vector<int> lv(nx, 0);
+    for (int q = 0; q < npk; ++q) {
+      const int r0 = P.pack_ptr[q], r1 = P.pack_ptr[q + 1];
+      int nlv = 0;
+      for (int i = r0; i < r1; ++i) {
+        int v = 0;
+        for (int k : lrow[i]) {
+          if (k < r0 || k >= r1) fail("internal: pack dependency leaves the pack");
+          v = std::max(v, lv[k] + 1);
+        }
+        lv[i] = v;
+        nlv = std::max(nlv, v + 1);
+      }
+      std::vector<std::vector<int>> byl(nlv);
+      for (int i = r0; i < r1; ++i) byl[lv[i]].push_back(i);
+      for (auto& b : byl) {
+        P.pk_frows.insert(P.pk_frows.end(), b.begin(), b.end());
+        P.pk_flev.push_back((int)P.pk_frows.size());
+      }
+      P.pk_flev_off[q + 1] = (int)P.pk_flev.size() - 1;
+      int nbl = 0;
+      for (int i = r1 - 1; i >= r0; --i) {
+        int v = 0;
+        for (int j : urow[i])
+          if (j < r1) v = std::max(v, lv[j] + 1);
+        lv[i] = v;
+        nbl = std::max(nbl, v + 1);
+      }
+      std::vector<std::vector<int>> byb(nbl);
+      for (int i = r0; i < r1; ++i) byb[lv[i]].push_back(i);
+      for (auto& b : byb) {
+        P.pk_brows.insert(P.pk_brows.end(), b.begin(), b.end());
+        P.pk_blev.push_back((int)P.pk_brows.size());
+      }
+      P.pk_blev_off[q + 1] = (int)P.pk_blev.size() - 1;
+    }
+    // staged programs (pack-local columns fit int16: packs hold at most
+    // subtree_max <= 32767 rows)
+    if (P.subtree_max > 32767) fail("subtree_max must stay below 32768");
+    P.pkf_rp.assign(t0 + 1, 0);
+    P.pkb_rp.assign(t0 + 1, 0);
+    P.pkf_pos.clear(); P.pkf_col.clear(); P.pkb_pos.clear(); P.pkb_col.clear();
+    for (int q = 0; q < npk; ++q) {
+      const int r0 = P.pack_ptr[q], r1 = P.pack_ptr[q + 1];
+      for (int i = r0; i < r1; ++i) {
+        for (int p = P.lu_ptr[i]; p < P.lu_diag[i]; ++p) {
+          P.pkf_pos.push_back(p);
+          P.pkf_col.push_back((int16_t)(P.lu_col[p] - r0));
+        }
+        P.pkf_rp[i + 1] = (int32_t)P.pkf_pos.size();
+        for (int p = P.lu_diag[i] + 1; p < P.up_split[i]; ++p) {
+          P.pkb_pos.push_back(p);
+          P.pkb_col.push_back((int16_t)(P.lu_col[p] - r0));
+        }
+        P.pkb_rp[i + 1] = (int32_t)P.pkb_pos.size();
+      }
+    }
+    // top part: forward levels over top-internal lower entries, backward over upper
+    std::vector<int> tl(nx, 0);
+    int ntf = 0, ntb = 0;
+    for (int i = t0; i < nx; ++i) {
+      int v = 0;
+      for (int k : lrow[i])
+        if (k >= t0) v = std::max(v, tl[k] + 1);
+      tl[i] = v;
+      ntf = std::max(ntf, v + 1);
+    }
+    std::vector<std::vector<int>> tf(ntf);
+    for (int i = t0; i < nx; ++i) tf[tl[i]].push_back(i);
+    for (int i = nx - 1; i >= t0; --i) {
+      int v = 0;
+      for (int j : urow[i]) v = std::max(v, tl[j] + 1);
+      tl[i] = v;
+      ntb = std::max(ntb, v + 1);
+    }
+    std::vector<std::vector<int>> tb(ntb);
+    for (int i = t0; i < nx; ++i) tb[tl[i]].push_back(i);
+    P.top_flev.assign(1, 0);
+    P.top_frows.clear();
+    for (auto& b : tf) {
+      P.top_frows.insert(P.top_frows.end(), b.begin(), b.end());
+      P.top_flev.push_back((int)P.top_frows.size());
+    }
+    P.top_blev.assign(1, 0);
+    P.top_brows.clear();
+    for (auto& b : tb) {
+      P.top_brows.insert(P.top_brows.end(), b.begin(), b.end());
+      P.top_blev.push_back((int)P.top_brows.size());
+    }
+    // dense top block positions: for each top row, LU positions with col >= t0
+    const int s = nx - t0;
+    P.ntop = s;
+    P.top_pos.clear();
+    P.top_dense.clear();
+    for (int i = t0; i < nx; ++i)
+      for (int p = P.lo_split[i]; p < P.lu_ptr[i + 1]; ++p) {
+        P.top_pos.push_back(p);
+        P.top_dense.push_back((int64_t)(i - t0) * s + (P.lu_col[p] - t0));
+      }
+  }
 
   // -------------------------------------------------- refactorization map
   const int64_t nnz = (int64_t)P.lu_col.size();
@@ -500,6 +699,13 @@ PresolveStats stats(const Presolve& p) {
   s.nnz_ju = (int64_t)p.ju_col.size();
   s.nnz_k = (int64_t)p.K_col.size();
   s.nnz_g = (int64_t)p.G_col.size();
+  s.npacks = (int64_t)p.pack_ptr.size() - 1;
+  s.ntop = p.ntop;
+  int64_t mx = 0;
+  for (int64_t q = 0; q < s.npacks; ++q)
+    mx = std::max<int64_t>(mx, p.pk_flev_off[q + 1] - p.pk_flev_off[q]);
+  s.max_pack_levels = mx;
+  s.top_levels = (int64_t)p.top_flev.size() - 1;
   return s;
 }
 

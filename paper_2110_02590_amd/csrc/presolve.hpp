@@ -67,6 +67,28 @@ struct Presolve {
   std::vector<int32_t> lu_ptr, lu_col, lu_diag;
   // transposed factor (CSR of (L+U)^T) and source positions in lu
   std::vector<int32_t> lut_ptr, lut_col, lut_diag, lut_src;
+  // subtree partition: packs [pack_ptr[q], pack_ptr[q+1]) of independent
+  // subtrees, then the top rows [t0, nx)
+  int subtree_max = 1024;
+  int t0 = 0, ntop = 0;
+  std::vector<int32_t> pack_ptr;
+  std::vector<int32_t> lo_split;   // first lower entry with col >= t0
+  std::vector<int32_t> up_split;   // first upper entry with col >= t0
+  // pack-local level lists: pack q's forward levels are
+  // pk_frows[pk_flev[pk_flev_off[q] + k] .. pk_flev[pk_flev_off[q] + k + 1])
+  std::vector<int32_t> pk_flev, pk_flev_off, pk_frows;
+  std::vector<int32_t> pk_blev, pk_blev_off, pk_brows;
+  // staged programs of the pack solves: for pack rows i < t0, the
+  // pack-internal lower (forward) / upper (backward) entries of row i are
+  // pkf_pos/pkf_col[pkf_rp[i] .. pkf_rp[i+1]) (LU positions, pack-local
+  // columns), likewise pkb_*
+  std::vector<int32_t> pkf_rp, pkf_pos, pkb_rp, pkb_pos;
+  std::vector<int16_t> pkf_col, pkb_col;
+  // top-part levels (global row ids)
+  std::vector<int32_t> top_flev, top_frows, top_blev, top_brows;
+  // dense top block: LU positions and their dense (row-major) offsets
+  std::vector<int32_t> top_pos;
+  std::vector<int64_t> top_dense;
   Levels lev_lo;   // forward schedule: L solve, U^T solve, refactor
   Levels lev_up;   // backward schedule: U solve, L^T solve
   // refactorization program: for each L entry p of row i (column k), the
@@ -106,10 +128,12 @@ struct Presolve {
 };
 
 // Throws std::runtime_error with a message on invalid input.
-Presolve build_presolve(const GridData& g);
+// subtree_max bounds the rows of one pack of independent subtrees.
+Presolve build_presolve(const GridData& g, int subtree_max = 1024);
 
 struct PresolveStats {
   int64_t nnz_jx, nnz_lu, nlev_lo, nlev_up, max_lu_row, refactor_updates, nnz_ju, nnz_k, nnz_g;
+  int64_t npacks, ntop, max_pack_levels, top_levels;
 };
 PresolveStats stats(const Presolve& p);
 

@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <stdexcept>
 #include <string>
@@ -69,6 +70,15 @@ struct rpf_grid {
   int32_t *G_ptr, *G_col, *G_sp, *G_s, *Gt_ptr, *Gt_col, *Gt_pos;
   int32_t *K_ptr, *K_col, *K_sp, *K_s, *K_diag, *vg_sp, *vg_s;
   int32_t *pq, *pv, *gen_pidx, *pv_gen, *var_kind, *var_aux;
+  int32_t *pack_ptr, *lo_split, *up_split, *pk_flev, *pk_flev_off, *pk_frows, *pk_blev, *pk_blev_off, *pk_brows;
+  int32_t *top_flev, *top_frows, *top_blev, *top_brows, *top_pos;
+  int64_t* top_dense;
+  double *dense_top, *dense_topT;
+  int npacks = 0, max_pack = 0, tw = 16;
+  int32_t *pkf_rp, *pkf_pos, *pkb_rp, *pkb_pos;
+  int16_t *pkf_col, *pkb_col;
+  int tw_pack = 8, tw_top = 8;
+  size_t lds_limit = 65536, lds_pack[5] = {0, 0, 0, 0, 0};
   double *c2, *c1, *c0;
 
   // ------------------------------------------------------------ workspace
@@ -79,12 +89,31 @@ struct rpf_grid {
   int32_t *flag, *piv_status;
   double* host_resid;  // pinned
 
-  // refactor launch plan: (lev0, lev1, nblocks)
-  struct RfStep {
-    int lev0, lev1, nblocks;
-  };
-  std::vector<RfStep> rf_plan;
   int rf_waves = 16;
+
+  // event timing per kernel class
+  bool prof_on = false;
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_used = 0;
+  std::vector<std::pair<int, size_t>> ev_marks;  // (class, index of start event)
+
+  size_t prof_begin(hipStream_t s) {
+    if (ev_used + 2 > ev_pool.size()) {
+      for (int k = 0; k < 64; ++k) {
+        hipEvent_t e;
+        HIPCHK(hipEventCreate(&e));
+        ev_pool.push_back(e);
+      }
+    }
+    size_t i = ev_used;
+    ev_used += 2;
+    HIPCHK(hipEventRecord(ev_pool[i], s));
+    return i;
+  }
+  void prof_end(int cls, size_t i, hipStream_t s) {
+    HIPCHK(hipEventRecord(ev_pool[i + 1], s));
+    ev_marks.push_back({cls, i});
+  }
 
   template <class T>
   T* up(const std::vector<T>& v) {
@@ -104,6 +133,7 @@ struct rpf_grid {
     return (T*)p;
   }
   ~rpf_grid() {
+    for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
     for (void* p : allocs) (void)hipFree(p);
     if (host_resid) (void)hipHostFree(host_resid);
   }
@@ -206,7 +236,59 @@ void setup(rpf_grid* h) {
   h->c2 = h->up(G.c2);
   h->c1 = h->up(G.c1);
   h->c0 = h->up(G.c0);
-
+  h->pack_ptr = h->up(P.pack_ptr);
+  h->lo_split = h->up(P.lo_split);
+  h->up_split = h->up(P.up_split);
+  h->pk_flev = h->up(P.pk_flev);
+  h->pk_flev_off = h->up(P.pk_flev_off);
+  h->pk_frows = h->up(P.pk_frows);
+  h->pk_blev = h->up(P.pk_blev);
+  h->pk_blev_off = h->up(P.pk_blev_off);
+  h->pk_brows = h->up(P.pk_brows);
+  h->top_flev = h->up(P.top_flev);
+  h->top_frows = h->up(P.top_frows);
+  h->top_blev = h->up(P.top_blev);
+  h->top_brows = h->up(P.top_brows);
+  h->top_pos = h->up(P.top_pos);
+  h->top_dense = h->up(P.top_dense);
+  h->pkf_rp = h->up(P.pkf_rp);
+  h->pkf_pos = h->up(P.pkf_pos);
+  h->pkf_col = h->up(P.pkf_col);
+  h->pkb_rp = h->up(P.pkb_rp);
+  h->pkb_pos = h->up(P.pkb_pos);
+  h->pkb_col = h->up(P.pkb_col);
+  h->dense_top = h->alloc<double>((size_t)P.ntop * P.ntop);
+  h->dense_topT = h->alloc<double>((size_t)P.ntop * P.ntop);
+  h->npacks = (int)P.pack_ptr.size() - 1;
+  for (int q = 0; q < h->npacks; ++q) h->max_pack = std::max(h->max_pack, P.pack_ptr[q + 1] - P.pack_ptr[q]);
+  {
+    int dev = 0, lim = 0;
+    HIPCHK(hipGetDevice(&dev));
+    HIPCHK(hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+    h->lds_limit = (size_t)std::max(lim, 32768);
+    // staged pack solves: LDS of the largest pack for each column tile width
+    const int tws[5] = {16, 8, 4, 2, 1};
+    for (int k = 0; k < 5; ++k) {
+      size_t mx = 0;
+      for (int q = 0; q < h->npacks; ++q) {
+        const int r0 = P.pack_ptr[q], nr = P.pack_ptr[q + 1] - r0;
+        const int nef = P.pkf_rp[r0 + nr] - P.pkf_rp[r0], neb = P.pkb_rp[r0 + nr] - P.pkb_rp[r0];
+        const int nlf = P.pk_flev_off[q + 1] - P.pk_flev_off[q], nlb = P.pk_blev_off[q + 1] - P.pk_blev_off[q];
+        mx = std::max(mx, pack_lds_bytes(nr, std::max(nef, neb), std::max(nlf, nlb), tws[k]));
+      }
+      h->lds_pack[k] = mx;
+    }
+    h->tw_pack = 0;
+    for (int k = 0; k < 5; ++k)
+      if (h->lds_pack[k] <= h->lds_limit) {
+        h->tw_pack = tws[k];
+        break;
+      }
+    if (h->tw_pack == 0) throw std::runtime_error("a pack of subtrees does not fit in LDS");
+    h->tw_top = 16;
+    while (h->tw_top > 1 && (size_t)P.ntop * h->tw_top * 8 > h->lds_limit) h->tw_top /= 2;
+    if ((size_t)P.ntop * 8 > h->lds_limit) throw std::runtime_error("top part of the elimination tree too large for LDS");
+  }
   const size_t nnz = P.lu_col.size();
   h->xi = h->alloc<double>(P.nx);
   h->th = h->alloc<double>(P.nb);
@@ -240,28 +322,11 @@ void setup(rpf_grid* h) {
   h->piv_status = h->alloc<int32_t>(4);
   HIPCHK(hipHostMalloc((void**)&h->host_resid, sizeof(double) * 4, hipHostMallocDefault));
 
-  // refactor plan: wide levels get a multi-workgroup launch each, runs of
-  // narrow levels share one single-workgroup launch
   int maxrow = std::max(P.max_lu_row, 1);
   int waves = 16;
   while (waves > 1 && (size_t)waves * maxrow * 8 > 65536) waves /= 2;
   if ((size_t)waves * maxrow * 8 > 65536) throw std::runtime_error("LU row too long for LDS staging");
   h->rf_waves = waves;
-  const auto& lp = P.lev_lo.ptr;
-  int nlev = P.lev_lo.nlev();
-  int k = 0;
-  while (k < nlev) {
-    int rows = lp[k + 1] - lp[k];
-    if (rows > 2 * waves) {
-      h->rf_plan.push_back({k, k + 1, cdiv(rows, waves)});
-      ++k;
-    } else {
-      int k1 = k;
-      while (k1 < nlev && lp[k1 + 1] - lp[k1] <= 2 * waves) ++k1;
-      h->rf_plan.push_back({k, k1, 1});
-      k = k1;
-    }
-  }
 }
 
 // ---------------------------------------------------------- launch helpers
@@ -279,63 +344,146 @@ void x_in(rpf_grid* h, const double* x, hipStream_t s) {
   LAUNCHCHK();
 }
 
+// Blocked dense LU (no pivoting) or Cholesky of a row-major n x n matrix.
+template <bool CHOL>
+void dense_factor(int n, double* A, int32_t* info, int base, hipStream_t s) {
+  for (int b0 = 0; b0 < n; b0 += CB) {
+    const int nb = std::min(CB, n - b0);
+    k_blk_diag<CHOL><<<1, 64, 0, s>>>(n, b0, A, info, base);
+    LAUNCHCHK();
+    const int rest = n - b0 - nb;
+    if (rest > 0) {
+      const int tasks = CHOL ? rest : 2 * rest;
+      k_blk_panel<CHOL><<<cdiv(tasks, 4), 256, 0, s>>>(n, b0, A, info);
+      LAUNCHCHK();
+      const int nt = cdiv(rest, CB);
+      k_blk_update<CHOL><<<dim3(nt, nt), 256, 0, s>>>(n, b0, A, info);
+      LAUNCHCHK();
+    }
+  }
+}
+
 void refactor(rpf_grid* h, hipStream_t s) {
   const Presolve& P = h->P;
   const size_t nnz = P.lu_col.size();
   k_gather_sum<<<cdiv(nnz, 256), 256, 0, s>>>((int)nnz, h->jx_sp, h->jx_s, h->rec, nullptr, h->luv);
   LAUNCHCHK();
   const int maxrow = std::max(P.max_lu_row, 1);
-  const size_t shm = (size_t)h->rf_waves * maxrow * sizeof(double);
-  for (auto& st : h->rf_plan) {
-    k_refactor<<<st.nblocks, 64 * h->rf_waves, shm, s>>>(st.lev0, st.lev1, h->lo_ptr, h->lo_rows, h->lu_ptr,
-                                                         h->lu_col, h->lu_diag, h->upd_ptr, h->upd_tgt,
-                                                         h->luv, maxrow, 1e-14, h->piv_status);
+  const int wv = h->rf_waves;
+  const size_t shm = (size_t)wv * maxrow * sizeof(double);
+  size_t pi = h->prof_on ? h->prof_begin(s) : 0;
+  if (h->npacks > 0) {
+    k_rf_pack<<<h->npacks, 64 * wv, shm, s>>>(h->pk_flev, h->pk_flev_off, h->pk_frows, h->lu_ptr, h->lu_col,
+                                              h->lu_diag, h->upd_ptr, h->upd_tgt, h->luv, maxrow, 1e-14,
+                                              h->piv_status);
     LAUNCHCHK();
   }
+  if (P.ntop > 0) {
+    k_rf_top_ext<<<cdiv(P.ntop, wv), 64 * wv, shm, s>>>(P.t0, P.nx, h->lo_split, h->lu_ptr, h->lu_col, h->lu_diag,
+                                                       h->upd_ptr, h->upd_tgt, h->luv, maxrow, h->piv_status);
+    LAUNCHCHK();
+    const int64_t nd = (int64_t)P.ntop * P.ntop;
+    k_fill_dbl<<<cdiv(nd, 256), 256, 0, s>>>(nd, h->dense_top, 0.0);
+    LAUNCHCHK();
+    const int ne = (int)P.top_pos.size();
+    k_dense_xfer<<<cdiv(ne, 256), 256, 0, s>>>(ne, h->top_pos, h->top_dense, h->luv, h->dense_top, 1);
+    LAUNCHCHK();
+    dense_factor<false>(P.ntop, h->dense_top, h->piv_status, P.t0, s);
+    k_transpose<<<dim3(cdiv(P.ntop, 32), cdiv(P.ntop, 32)), dim3(32, 8), 0, s>>>(P.ntop, h->dense_top,
+                                                                                 h->dense_topT);
+    LAUNCHCHK();
+    k_dense_xfer<<<cdiv(ne, 256), 256, 0, s>>>(ne, h->top_pos, h->top_dense, h->luv, h->dense_top, 0);
+    LAUNCHCHK();
+  }
+  if (h->prof_on) h->prof_end(2, pi, s);
   k_gather_pos<<<cdiv(nnz, 256), 256, 0, s>>>((int)nnz, h->lut_src, h->luv, h->lutv);
   LAUNCHCHK();
 }
 
 template <int TW>
-void trsv_t(rpf_grid* h, bool lower, bool unit, bool transposed, double* X, int ld, int ncols, double scale,
-            hipStream_t s) {
+void pack_solve(rpf_grid* h, bool fwd, bool unit, const double* val, double* X, int ld, int ncols, double scale,
+                int cls, hipStream_t s) {
   const Presolve& P = h->P;
-  const Levels& L = lower ? P.lev_lo : P.lev_up;
-  const int32_t* lp = lower ? h->lo_ptr : h->up_ptr;
-  const int32_t* lr = lower ? h->lo_rows : h->up_rows;
-  const double* val = transposed ? h->lutv : h->luv;
-  const int threads = TW == 1 ? 1024 : 512;
-  const int grid = cdiv(ncols, TW);
-  if (lower && unit)
-    k_trsv_batch<TW, true, true><<<grid, threads, 0, s>>>(L.nlev(), lp, lr, h->lu_ptr, h->lu_col, h->lu_diag,
-                                                          val, X, ld, ncols, scale);
-  else if (lower)
-    k_trsv_batch<TW, true, false><<<grid, threads, 0, s>>>(L.nlev(), lp, lr, h->lu_ptr, h->lu_col, h->lu_diag,
-                                                           val, X, ld, ncols, scale);
-  else if (unit)
-    k_trsv_batch<TW, false, true><<<grid, threads, 0, s>>>(L.nlev(), lp, lr, h->lu_ptr, h->lu_col, h->lu_diag,
-                                                           val, X, ld, ncols, scale);
-  else
-    k_trsv_batch<TW, false, false><<<grid, threads, 0, s>>>(L.nlev(), lp, lr, h->lu_ptr, h->lu_col,
-                                                            h->lu_diag, val, X, ld, ncols, scale);
+  if (h->npacks == 0) return;
+  const int k = TW == 16 ? 0 : TW == 8 ? 1 : TW == 4 ? 2 : TW == 2 ? 3 : 4;
+  const size_t shm = h->lds_pack[k];
+  dim3 grd(h->npacks, cdiv(ncols, TW));
+  size_t pi = h->prof_on ? h->prof_begin(s) : 0;
+  auto launch = [&](auto kern, const int32_t* lev, const int32_t* lev_off, const int32_t* rows, const int32_t* rp,
+                    const int32_t* pos, const int16_t* ecol) {
+    if (shm > 65536) HIPCHK(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
+    kern<<<grd, 256, shm, s>>>(h->pack_ptr, lev, lev_off, rows, rp, pos, ecol, h->lu_diag, h->up_split, h->lu_ptr,
+                               h->lu_col, val, X, ld, ncols, scale);
+  };
+  if (fwd) {
+    if (unit)
+      launch(k_pack_solve_s<TW, true, true>, h->pk_flev, h->pk_flev_off, h->pk_frows, h->pkf_rp, h->pkf_pos, h->pkf_col);
+    else
+      launch(k_pack_solve_s<TW, true, false>, h->pk_flev, h->pk_flev_off, h->pk_frows, h->pkf_rp, h->pkf_pos, h->pkf_col);
+  } else {
+    if (unit)
+      launch(k_pack_solve_s<TW, false, true>, h->pk_blev, h->pk_blev_off, h->pk_brows, h->pkb_rp, h->pkb_pos, h->pkb_col);
+    else
+      launch(k_pack_solve_s<TW, false, false>, h->pk_blev, h->pk_blev_off, h->pk_brows, h->pkb_rp, h->pkb_pos, h->pkb_col);
+  }
   LAUNCHCHK();
+  if (h->prof_on) h->prof_end(cls, pi, s);
+  (void)P;
 }
 
-void trsv(rpf_grid* h, bool lower, bool unit, bool transposed, double* X, int ld, int ncols, double scale,
-          hipStream_t s) {
-  if (ncols == 1)
-    trsv_t<1>(h, lower, unit, transposed, X, ld, ncols, scale, s);
-  else
-    trsv_t<8>(h, lower, unit, transposed, X, ld, ncols, scale, s);
+void pack_solve_any(rpf_grid* h, int tw, bool fwd, bool unit, const double* val, double* X, int ld, int ncols,
+                    double scale, int cls, hipStream_t s) {
+  switch (tw) {
+    case 16: return pack_solve<16>(h, fwd, unit, val, X, ld, ncols, scale, cls, s);
+    case 8: return pack_solve<8>(h, fwd, unit, val, X, ld, ncols, scale, cls, s);
+    case 4: return pack_solve<4>(h, fwd, unit, val, X, ld, ncols, scale, cls, s);
+    case 2: return pack_solve<2>(h, fwd, unit, val, X, ld, ncols, scale, cls, s);
+    default: return pack_solve<1>(h, fwd, unit, val, X, ld, ncols, scale, cls, s);
+  }
 }
 
-void spmm(int nrows, const int32_t* ptr, const int32_t* col, const double* val, const int32_t* valpos,
-          const double* xscale, const double* X, int ldx, int ncols, double alpha, const double* Yadd,
-          int ldya, double* Y, int ldy, hipStream_t s) {
+// Solves with both factors of J_x (transposed = false): X <- U^{-1} L^{-1}
+// (scale X), or of J_x^T (transposed = true): X <- L^{-T} U^{-T} (scale X).
+// Three launches: packs forward, top part forward + backward, packs
+// backward.
+void solve_pair(rpf_grid* h, bool transposed, double* X, int ld, int ncols, double scale, hipStream_t s) {
+  const Presolve& P = h->P;
+  const double* val = transposed ? h->lutv : h->luv;
+  // forward factor: L (unit) or U^T (non-unit); backward: U (non-unit) or L^T (unit)
+  const bool fwd_unit = !transposed;
+  const int cls = ncols > 1 ? 0 : 1;
+  const int twp = ncols == 1 ? 1 : h->tw_pack;
+  const int twt = ncols == 1 ? 1 : h->tw_top;
+  pack_solve_any(h, twp, true, fwd_unit, val, X, ld, ncols, scale, cls, s);
+  if (P.ntop > 0) {
+    size_t pi = h->prof_on ? h->prof_begin(s) : 0;
+    const size_t shm = (size_t)P.ntop * twt * sizeof(double);
+    const double* M = transposed ? h->dense_topT : h->dense_top;
+    const int ct = cdiv(ncols, twt);
+    if (fwd_unit) {
+      auto kern = k_top_dense<true, true, false>;
+      if (shm > 65536) HIPCHK(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
+      kern<<<ct, 256, shm, s>>>(P.t0, P.nx, h->lo_split, h->lu_ptr, h->lu_col, val, M, X, ld, ncols, scale, twt);
+    } else {
+      auto kern = k_top_dense<false, true, true>;
+      if (shm > 65536) HIPCHK(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
+      kern<<<ct, 256, shm, s>>>(P.t0, P.nx, h->lo_split, h->lu_ptr, h->lu_col, val, M, X, ld, ncols, scale, twt);
+    }
+    LAUNCHCHK();
+    if (h->prof_on) h->prof_end(cls, pi, s);
+  }
+  pack_solve_any(h, twp, false, !fwd_unit, val, X, ld, ncols, 1.0, cls, s);
+}
+
+void spmm(rpf_grid* h, int nrows, const int32_t* ptr, const int32_t* col, const double* val,
+          const int32_t* valpos, const double* xscale, const double* X, int ldx, int ncols, double alpha,
+          const double* Yadd, int ldya, double* Y, int ldy, hipStream_t s) {
   dim3 blk(64, 4);
   dim3 grd(cdiv(ncols, 64), cdiv(nrows, 4));
+  size_t pi = h->prof_on ? h->prof_begin(s) : 0;
   k_spmm<<<grd, blk, 0, s>>>(nrows, ptr, col, val, valpos, xscale, X, ldx, ncols, alpha, Yadd, ldya, Y, ldy);
   LAUNCHCHK();
+  if (h->prof_on) h->prof_end(3, pi, s);
 }
 
 ALArgs al_args(rpf_grid* h, const double* u, const double* pd, const double* qd, const double* s,
@@ -385,19 +533,17 @@ void hvp_batch(rpf_grid* h, const double* V, int ldv, int j0, int B, double* HV,
   }
   LAUNCHCHK();
   // R = -J_u V
-  spmm(P.nx, h->ju_ptr, h->ju_col, h->juv, nullptr, nullptr, Du, ld, B, -1.0, nullptr, 0, Dx, ld, s);
+  spmm(h, P.nx, h->ju_ptr, h->ju_col, h->juv, nullptr, nullptr, Du, ld, B, -1.0, nullptr, 0, Dx, ld, s);
   // Z = U^{-1} L^{-1} R
-  trsv(h, true, true, false, Dx, ld, B, 1.0, s);
-  trsv(h, false, false, false, Dx, ld, B, 1.0, s);
+  solve_pair(h, false, Dx, ld, B, 1.0, s);
   // Y = K [Z; V] + G^T diag(kappa) G [Z; V]
-  spmm(P.nvar, h->K_ptr, h->K_col, h->Kv, nullptr, nullptr, h->D, ld, B, 1.0, nullptr, 0, h->Y, ld, s);
-  spmm(P.nr1, h->G_ptr, h->G_col, h->Gv, nullptr, nullptr, h->D, ld, B, 1.0, nullptr, 0, h->T, ld, s);
-  spmm(P.nvar, h->Gt_ptr, h->Gt_col, h->Gv, h->Gt_pos, h->kappa, h->T, ld, B, 1.0, h->Y, ld, h->Y, ld, s);
+  spmm(h, P.nvar, h->K_ptr, h->K_col, h->Kv, nullptr, nullptr, h->D, ld, B, 1.0, nullptr, 0, h->Y, ld, s);
+  spmm(h, P.nr1, h->G_ptr, h->G_col, h->Gv, nullptr, nullptr, h->D, ld, B, 1.0, nullptr, 0, h->T, ld, s);
+  spmm(h, P.nvar, h->Gt_ptr, h->Gt_col, h->Gv, h->Gt_pos, h->kappa, h->T, ld, B, 1.0, h->Y, ld, h->Y, ld, s);
   // Psi = -J_x^{-T} Y_x  (U^T then L^T)
-  trsv(h, true, false, true, h->Y, ld, B, -1.0, s);
-  trsv(h, false, true, true, h->Y, ld, B, 1.0, s);
+  solve_pair(h, true, h->Y, ld, B, -1.0, s);
   // HV = Y_u + J_u^T Psi
-  spmm(P.nu, h->jut_ptr, h->jut_col, h->juv, h->jut_pos, nullptr, h->Y, ld, B, 1.0, h->Y + (size_t)P.nx * ld,
+  spmm(h, P.nu, h->jut_ptr, h->jut_col, h->juv, h->jut_pos, nullptr, h->Y, ld, B, 1.0, h->Y + (size_t)P.nx * ld,
        ld, HV, ldhv, s);
 }
 
@@ -444,13 +590,42 @@ extern "C" {
 
 const char* rpf_last_error(void) { return g_err.c_str(); }
 
+int rpf_profile_enable(rpf_grid* h, int32_t enable) {
+  if (!h) return set_err(RPF_EINVAL, "grid is NULL");
+  h->prof_on = enable != 0;
+  return RPF_OK;
+}
+
+int rpf_profile_read(rpf_grid* h, double* ms, int64_t* launches, int32_t reset) {
+  if (!h || !ms || !launches) return set_err(RPF_EINVAL, "NULL argument");
+  return guard([&]() -> int {
+    for (int c = 0; c < RPF_PROF_CLASSES; ++c) {
+      ms[c] = 0.0;
+      launches[c] = 0;
+    }
+    for (auto& mk : h->ev_marks) {
+      HIPCHK(hipEventSynchronize(h->ev_pool[mk.second + 1]));
+      float t = 0.f;
+      HIPCHK(hipEventElapsedTime(&t, h->ev_pool[mk.second], h->ev_pool[mk.second + 1]));
+      ms[mk.first] += t;
+      launches[mk.first] += 1;
+    }
+    if (reset) {
+      h->ev_marks.clear();
+      h->ev_used = 0;
+    }
+    return RPF_OK;
+  });
+}
+
 int rpf_presolve_info(const rpf_grid_desc* desc, int64_t* o) {
   if (!o) return set_err(RPF_EINVAL, "out is NULL");
   return guard([&]() -> int {
     Presolve P = build_presolve(grid_from_desc(desc));
     PresolveStats st = stats(P);
     int64_t v[16] = {P.nx, P.nu, P.m, st.nnz_jx, st.nnz_lu, st.nlev_lo, st.nlev_up, st.max_lu_row,
-                     st.refactor_updates, st.nnz_ju, st.nnz_k, st.nnz_g, 0, 0, 0, 0};
+                     st.refactor_updates, st.nnz_ju, st.nnz_k, st.nnz_g, st.npacks, st.ntop,
+                     st.max_pack_levels, st.top_levels};
     std::memcpy(o, v, sizeof(v));
     return RPF_OK;
   });
@@ -476,7 +651,11 @@ int rpf_grid_create(const rpf_grid_desc* desc, int32_t max_batch, rpf_grid** out
     try {
       h->G = std::move(G0);
       const GridData& G = h->G;
-      h->P = build_presolve(G);
+      // packs of independent subtrees: at most RPF_SUBTREE_MAX rows (default
+      // 1024, sized for 160 KB of LDS per workgroup)
+      int smax = 1024;
+      if (const char* e = std::getenv("RPF_SUBTREE_MAX")) smax = std::max(1, std::min(32767, std::atoi(e)));
+      h->P = build_presolve(G, smax);
       h->max_batch = max_batch;
       if ((int64_t)h->P.nvar * max_batch >= (int64_t)1 << 31)
         throw std::runtime_error("n_var * max_batch must stay below 2^31");
@@ -537,8 +716,7 @@ int rpf_pf_solve(rpf_grid* h, const double* u, const double* pd, const double* q
       if (!std::isfinite(r) || it >= max_iter) break;
       refactor(h, s);
       HIPCHK(hipMemcpyAsync(h->d, h->g, sizeof(double) * P.nx, hipMemcpyDeviceToDevice, s));
-      trsv(h, true, true, false, h->d, 1, 1, 1.0, s);
-      trsv(h, false, false, false, h->d, 1, 1, 1.0, s);
+      solve_pair(h, false, h->d, 1, 1, 1.0, s);
       k_axpy<<<nblk, 256, 0, s>>>(P.nx, -1.0, h->d, h->xi);
       LAUNCHCHK();
       ++it;
@@ -598,8 +776,7 @@ int rpf_reduced_gradient(rpf_grid* h, const double* x, const double* u, const do
     k_fill_int<<<1, 4, 0, s>>>(4, h->piv_status, 0);
     refactor(h, s);
     HIPCHK(hipMemcpyAsync(h->lam, h->varg, sizeof(double) * P.nx, hipMemcpyDeviceToDevice, s));
-    trsv(h, true, false, true, h->lam, 1, 1, -1.0, s);
-    trsv(h, false, true, true, h->lam, 1, 1, 1.0, s);
+    solve_pair(h, true, h->lam, 1, 1, -1.0, s);
     // gradient of l = phi + lambda^T g: its control part is the reduced gradient
     k_bus_weights<<<nbw, 256, 0, s>>>(A, h->wvec, h->lam, h->rowP, h->rowQ, h->bus_pvpos, h->a, h->b, h->kappa);
     LAUNCHCHK();
@@ -666,23 +843,13 @@ int rpf_factor_solve(rpf_grid* h, int32_t n, double* K, const double* diag, doub
     hipStream_t s = (hipStream_t)stream;
     k_fill_int<<<1, 1, 0, s>>>(1, info, 0);
     LAUNCHCHK();
+    size_t pi = h->prof_on ? h->prof_begin(s) : 0;
     k_symmetrize<<<dim3(cdiv(n, 32), cdiv(n, 8)), dim3(32, 8), 0, s>>>(n, K, diag, delta);
     LAUNCHCHK();
-    for (int k0 = 0; k0 < n; k0 += CB) {
-      k_chol_diag<<<1, 256, 0, s>>>(n, k0, K, info);
-      LAUNCHCHK();
-      const int nb = std::min(CB, n - k0);
-      const int rest = n - k0 - nb;
-      if (rest > 0) {
-        k_chol_trsm<<<cdiv(rest, 128), 128, 0, s>>>(n, k0, K, info);
-        LAUNCHCHK();
-        const int nt = cdiv(rest, CB);
-        k_chol_update<<<dim3(nt, nt), 256, 0, s>>>(n, k0, K, info);
-        LAUNCHCHK();
-      }
-    }
+    dense_factor<true>(n, K, info, 0, s);
     k_chol_solve<<<1, 256, 0, s>>>(n, K, rhs, step, h->chol_work, info);
     LAUNCHCHK();
+    if (h->prof_on) h->prof_end(4, pi, s);
     return RPF_OK;
   });
 }
