@@ -39,6 +39,10 @@ def parse():
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
     ap.add_argument("--quick", action="store_true", help="skip the comparison passes")
+    ap.add_argument("--tracking", action="store_true",
+                    help="batched real-time tracking: 64 grids, one tracking update per step")
+    ap.add_argument("--instances", type=int, default=64)
+    ap.add_argument("--track-steps", type=int, default=50)
     return ap.parse_args()
 
 
@@ -54,6 +58,9 @@ def main():
     import gridgen
     from paper_2110_02590_amd import Problem
     from paper_2110_02590_amd import tune
+
+    if a.tracking:
+        return tracking_bench(a)
 
     torch.cuda.set_device(0)
     g = gridgen.grid(a.workload)
@@ -192,6 +199,77 @@ def main():
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(g, ep, a.cpu_sample_cols)
 
+    print(json.dumps(out), flush=True)
+
+
+def tracking_bench(a):
+    """64 synthetic grids (n_b ~ U[300, 2000], seeds 100..163), each tracking
+    per-step load perturbations with one device-resident reduced-Hessian
+    Newton AL update; eager per-instance launches vs. one HIP graph per step
+    (instances forked over streams)."""
+    import numpy as np
+    import torch
+
+    import gridgen
+    from paper_2110_02590_amd.tracking import TrackingBatch, TrackingItem
+
+    torch.cuda.set_device(0)
+    steps = a.track_steps
+    items = []
+    for sd in gridgen.TRACKING_SEEDS[:a.instances]:
+        g = gridgen.make_grid(gridgen.tracking_workload(sd))
+        ep = gridgen.eval_point(g, seed=sd + 1000)
+        lo, hi = gridgen.constraint_bounds(g)
+        items.append(TrackingItem(g, ep, lo, hi, gridgen.tracking_factors(sd, steps, g["nb"])))
+    t0 = time.perf_counter()
+    tb = TrackingBatch(items, max_batch=256, nstreams=8)
+    setup_s = time.perf_counter() - t0
+    n = len(items)
+
+    def run(fn):
+        lat = []
+        torch.cuda.synchronize()
+        T0 = time.perf_counter()
+        for t in range(steps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn(t)
+            e1.record()
+            e1.synchronize()
+            lat.append(e0.elapsed_time(e1))
+        torch.cuda.synchronize()
+        return time.perf_counter() - T0, np.array(lat)
+
+    s0 = tb.state()
+    tb.step_eager(0)                      # warm-up
+    torch.cuda.synchronize()
+    tb.load_state(s0)
+    te, le = run(tb.step_eager)
+    st_e = [i.status.cpu().numpy().copy() for i in tb.inst]
+    tb.load_state(s0)
+    tb.capture()
+    tb.load_state(s0)
+    tg, lg = run(tb.step_graph)
+    st_g = [i.status.cpu().numpy().copy() for i in tb.inst]
+    acc = np.array([s[1] for s in st_g])
+    out = {
+        "metric": "batched real-time tracking: instances/s and step latency (64 grids, FP64)",
+        "value": round(n * steps / tg, 1), "unit": "instances/s", "n_gpus": 1, "steps": steps,
+        "higher_is_better": True, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"{n} grids, n_b in [{min(int(i.grid['nb']) for i in items)}, "
+                               f"{max(int(i.grid['nb']) for i in items)}], one tracking update per grid "
+                               f"and step (power flow, gradient, full reduced Hessian, Cholesky step, "
+                               f"halving on power-flow failure, multiplier update)",
+                   "streams": tb.nstreams},
+        "graph": {"instances_per_s": round(n * steps / tg, 1), "p50_ms": round(float(np.percentile(lg, 50)), 3),
+                  "p99_ms": round(float(np.percentile(lg, 99)), 3)},
+        "eager_per_instance": {"instances_per_s": round(n * steps / te, 1),
+                               "p50_ms": round(float(np.percentile(le, 50)), 3),
+                               "p99_ms": round(float(np.percentile(le, 99)), 3)},
+        "graph_over_eager": round(te / tg, 2),
+        "last_step_accepted_full_step": int((acc == 0).sum()), "last_step_no_step": int((acc < 0).sum()),
+        "setup_s": round(setup_s, 1),
+    }
     print(json.dumps(out), flush=True)
 
 

@@ -169,6 +169,27 @@ int rpf_reduced_hessian(rpf_grid* grid, double* H, int32_t batch, rpf_stream_t s
 int rpf_factor_solve(rpf_grid* grid, int32_t n, double* Kmat, const double* diag, double delta,
                      const double* rhs, double* step, int32_t* info, rpf_stream_t stream);
 
+/* One real-time tracking update at new loads (Section IV-C, steps 1-3),
+ * entirely on the device with no host synchronisation (capturable in a HIP
+ * graph).  The bounded QP of step 2 is replaced by one shifted Newton step:
+ *   loads pd = pd0 * load_factor, qd = qd0 * load_factor (per bus);
+ *   power flow at u from x (pf_iters predicated Newton steps, tol);
+ *   s = clip(c + y / (rho sigma_c), s_lo, s_hi) (minimiser of the scaled
+ *   AL in s); reduced gradient and Hessian at (u, s, y);
+ *   d = -((H + H^T)/2 + delta I)^{-1} grad (d = 0 if the Cholesky fails);
+ *   u <- clip(u + d / 2^k, u_lo, u_hi) for the first k <= max_halvings whose
+ *   power flow converges (u unchanged if none);
+ *   s = clip(c(u) + y / (rho sigma_c), s_lo, s_hi), y <- y + rho D_c (c - s).
+ * u [n_u], x [n_x], y [m]: device, in/out.  pd0, qd0, load_factor [nb],
+ * s_lo, s_hi [m], u_lo, u_hi [n_u], sigma [1 + m]: device, read.
+ * status [4]: device int32 out {first power flow converged, accepted
+ * halving k (-1: none), Cholesky info, Newton steps of the first power
+ * flow}.  Uses the handle's workspace (one step at a time per handle). */
+int rpf_track_step(rpf_grid* grid, double* u, double* x, double* y, const double* pd0, const double* qd0,
+                   const double* load_factor, const double* s_lo, const double* s_hi, const double* u_lo,
+                   const double* u_hi, double rho, const double* sigma, double delta, int32_t pf_iters,
+                   int32_t max_halvings, double tol, int32_t* status, rpf_stream_t stream);
+
 /* Kernel timing with HIP events recorded on the launch stream, per kernel
  * class: 0 batched triangular solves (more than one right-hand side),
  * 1 single right-hand-side triangular solves, 2 LU refactorization,

@@ -270,28 +270,38 @@ def slack_minimiser(c, P: Point, lo, hi):
     return np.clip(c + P.y / (P.rho * P.sigma_c), lo, hi)
 
 
-def tracking_step(M: Model, u, x, pd, qd, P: Point, s_lo, s_hi, max_halvings=4):
-    """One tracking update at new loads (Section IV-C, steps 1-3 with the
-    QP replaced by a regularised Newton step).  Returns (u, x, y, info)."""
-    x = solve_pf(M, u, pd, qd, x0=x).x
-    _, c = al_objective(M, x, u, pd, qd, P)
-    s = slack_minimiser(c, P, s_lo, s_hi)
-    Pt = dataclasses.replace(P, s=s)
+def tracking_step(M: Model, u, x, y, pd0, qd0, factor, P: Point, s_lo, s_hi, delta,
+                  pf_iters=6, max_halvings=4, tol=1e-10):
+    """One tracking update at new loads (Section IV-C, steps 1-3), with the
+    bounded QP replaced by a shifted Newton step:
+    loads pd0*factor, qd0*factor; power flow at u (at most pf_iters Newton
+    steps from x); s = clip(c + y/(rho sigma), lo, hi); reduced gradient and
+    Hessian at (u, s, y); d = -((H+H^T)/2 + delta I)^{-1} grad (0 when the
+    Cholesky fails); u <- clip(u + d/2^k) for the first k <= max_halvings whose
+    power flow converges; s = clip(c(u) + y/(rho sigma)); y <- y + rho D_c(c - s).
+    Returns (u, x, y, info dict)."""
+    pd = pd0 * factor
+    qd = qd0 * factor
+    pf = solve_pf(M, u, pd, qd, x0=x, tol=tol, max_iter=pf_iters, raise_on_fail=False)
+    x = pf.x
+    c = M.constraints(x, u, pd, qd)
+    s = slack_minimiser(c, dataclasses.replace(P, y=y), s_lo, s_hi)
+    Pt = dataclasses.replace(P, s=s, y=y)
     grad, lam = reduced_gradient(M, x, u, pd, qd, Pt)
     H = reduced_hessian(M, x, u, pd, qd, Pt, lam)
-    delta = delta_ladder(H)
     _, info, d = factor_solve(H, None, delta, grad)
+    if info != 0:
+        d = np.zeros(M.nu)
     ulo, uhi = M.u_bounds()
-    step = d.copy()
+    accepted = -1
     for k in range(max_halvings + 1):
-        un = np.clip(u + step, ulo, uhi)
-        pf = solve_pf(M, un, pd, qd, x0=x, raise_on_fail=False)
-        if pf.converged:
+        ut = np.clip(u + d / 2.0 ** k, ulo, uhi)
+        pf2 = solve_pf(M, ut, pd, qd, x0=x, tol=tol, max_iter=pf_iters, raise_on_fail=False)
+        if pf2.converged:
+            u, x, accepted = ut, pf2.x, k
             break
-        step *= 0.5
-    else:
-        un, pf = u, solve_pf(M, u, pd, qd, x0=x)
-    _, cn = al_objective(M, pf.x, un, pd, qd, Pt)
-    sn = slack_minimiser(cn, Pt, s_lo, s_hi)
-    yn = P.y + P.rho * P.sigma_c * (cn - sn)
-    return un, pf.x, yn, dict(delta=delta, halvings=k, s=sn, grad=grad)
+    c = M.constraints(x, u, pd, qd)
+    s = slack_minimiser(c, dataclasses.replace(P, y=y), s_lo, s_hi)
+    y = y + P.rho * P.sigma_c * (c - s)
+    return u, x, y, dict(pf_converged=pf.converged, pf_iters=pf.iters, accepted=accepted, info=info,
+                         grad=grad, step=d, s=s)

@@ -61,6 +61,7 @@ def lib():
             "rpf_factor_solve": [vp, i32, vp, vp, dbl, vp, vp, vp, vp],
             "rpf_presolve_info": [vp, i64p],
             "rpf_profile_enable": [vp, i32],
+            "rpf_track_step": [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, dbl, vp, dbl, i32, i32, dbl, vp, vp],
             "rpf_profile_read": [vp, vp, vp, i32],
             "rpf_presolve_pattern": [vp, vp, vp, vp],
         }
@@ -249,6 +250,22 @@ class Grid:
         H = self._empty(self.nu * self.nu).view(self.nu, self.nu) if H is None else H
         _check(lib().rpf_reduced_hessian(self._h, _dev(H, self.nu * self.nu, "H"), int(batch), _stream()))
         return H
+
+    def track_step(self, u, x, y, pd0, qd0, factor, s_lo, s_hi, u_lo, u_hi, rho, sigma, delta,
+                   pf_iters=6, max_halvings=4, tol=1e-10, status=None):
+        """One device-resident tracking update; u, x, y updated in place.
+        Returns the status tensor (first PF converged, accepted halving,
+        Cholesky info, Newton steps)."""
+        torch = _torch()
+        status = self._empty(4, torch.int32) if status is None else status
+        _check(lib().rpf_track_step(self._h, _dev(u, self.nu, "u"), _dev(x, self.nx, "x"), _dev(y, self.m, "y"),
+                                    _dev(pd0, self.nb, "pd0"), _dev(qd0, self.nb, "qd0"),
+                                    _dev(factor, self.nb, "factor"), _dev(s_lo, self.m, "s_lo"),
+                                    _dev(s_hi, self.m, "s_hi"), _dev(u_lo, self.nu, "u_lo"),
+                                    _dev(u_hi, self.nu, "u_hi"), float(rho), _dev(sigma, 1 + self.m, "sigma"),
+                                    float(delta), int(pf_iters), int(max_halvings), float(tol),
+                                    _dev(status, 4, "status", torch.int32), _stream()))
+        return status
 
     def factor_solve(self, K, rhs, diag=None, delta=0.0):
         """In place: K (holding H) becomes L in its lower triangle.  Returns

@@ -21,13 +21,17 @@ constexpr int CB = 64;  // dense block width
 
 // ------------------------------------------------------------------ helpers
 __global__ void k_permute_gather(int n, const int32_t* __restrict__ idx, const double* __restrict__ src,
-                                 double* __restrict__ dst) {
+                                 double* __restrict__ dst,
+    const int32_t* __restrict__ skip) {
+  if (skip && *skip) return;
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) dst[i] = src[idx[i]];
 }
 
 __global__ void k_permute_scatter(int n, const int32_t* __restrict__ idx, const double* __restrict__ src,
-                                  double* __restrict__ dst) {
+                                  double* __restrict__ dst,
+    const int32_t* __restrict__ skip) {
+  if (skip && *skip) return;
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) dst[idx[i]] = src[i];
 }
@@ -35,7 +39,9 @@ __global__ void k_permute_scatter(int n, const int32_t* __restrict__ idx, const 
 // out[i] = base[i] + sum_{j in [ptr[i], ptr[i+1])} in[src[j]]
 __global__ void k_gather_sum(int n, const int32_t* __restrict__ ptr, const int32_t* __restrict__ src,
                              const double* __restrict__ in, const double* __restrict__ base,
-                             double* __restrict__ out) {
+                             double* __restrict__ out,
+    const int32_t* __restrict__ skip) {
+  if (skip && *skip) return;
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   double acc = base ? base[i] : 0.0;
@@ -45,7 +51,9 @@ __global__ void k_gather_sum(int n, const int32_t* __restrict__ ptr, const int32
 
 // out[p] = in[srcpos[p]]
 __global__ void k_gather_pos(int n, const int32_t* __restrict__ srcpos, const double* __restrict__ in,
-                             double* __restrict__ out) {
+                             double* __restrict__ out,
+    const int32_t* __restrict__ skip) {
+  if (skip && *skip) return;
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) out[i] = in[srcpos[i]];
 }
@@ -53,7 +61,9 @@ __global__ void k_gather_pos(int n, const int32_t* __restrict__ srcpos, const do
 // ------------------------------------------------------------- bus state
 __global__ void k_bus_state(int nb, int nx, const int32_t* __restrict__ th_var,
                             const int32_t* __restrict__ v_var, const double* __restrict__ xi,
-                            const double* __restrict__ u, double* __restrict__ th, double* __restrict__ vm) {
+                            const double* __restrict__ u, double* __restrict__ th, double* __restrict__ vm,
+    const int32_t* __restrict__ skip) {
+  if (skip && *skip) return;
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= nb) return;
   int a = th_var[i];
@@ -69,7 +79,9 @@ __global__ void k_bus_state(int nb, int nx, const int32_t* __restrict__ th_var,
 __global__ void k_branch_eval(int nl, const int32_t* __restrict__ bf, const int32_t* __restrict__ bt,
                               const double* __restrict__ br, const double* __restrict__ bx,
                               const double* __restrict__ bb, const double* __restrict__ th,
-                              const double* __restrict__ vm, double* __restrict__ rec) {
+                              const double* __restrict__ vm, double* __restrict__ rec,
+    const int32_t* __restrict__ skip) {
+  if (skip && *skip) return;
   int l = blockIdx.x * blockDim.x + threadIdx.x;
   if (l >= nl) return;
   int f = bf[l], t = bt[l];
@@ -122,7 +134,9 @@ __global__ void k_residual(int nx, const int32_t* __restrict__ ptr, const int32_
                            const int32_t* __restrict__ row_isq, const int32_t* __restrict__ row_pvar,
                            const double* __restrict__ pd, const double* __restrict__ qd,
                            const double* __restrict__ u, double* __restrict__ g,
-                           double* __restrict__ partial) {
+                           double* __restrict__ partial,
+    const int32_t* __restrict__ skip) {
+  if (skip && *skip) return;
   __shared__ double red[256];
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   double v = 0.0;
@@ -148,7 +162,9 @@ __global__ void k_residual(int nx, const int32_t* __restrict__ ptr, const int32_
 // Single-block deterministic sum of `n` values; optionally sqrt.  Also sets
 // done[0] = (result < tol) when done is given.
 __global__ void k_reduce_final(int n, const double* __restrict__ in, double* __restrict__ out,
-                               int take_sqrt, double tol, int32_t* __restrict__ done) {
+                               int take_sqrt, double tol, int32_t* __restrict__ done,
+    const int32_t* __restrict__ skip) {
+  if (skip && *skip) return;
   __shared__ double red[1024];
   double acc = 0.0;
   for (int i = threadIdx.x; i < n; i += blockDim.x) acc += in[i];
@@ -216,7 +232,9 @@ __global__ void k_rf_pack(const int32_t* __restrict__ flev, const int32_t* __res
                           const int32_t* __restrict__ frows, const int32_t* __restrict__ ptr,
                           const int32_t* __restrict__ col, const int32_t* __restrict__ diag,
                           const int64_t* __restrict__ upd_ptr, const int32_t* __restrict__ upd_tgt,
-                          double* __restrict__ a, int maxrow, double pivtol, int32_t* __restrict__ status) {
+                          double* __restrict__ a, int maxrow, double pivtol, int32_t* __restrict__ status,
+    const int32_t* __restrict__ skip) {
+  if (skip && *skip) return;
   extern __shared__ double lds[];
   const int wave = threadIdx.x >> 6, nwave = blockDim.x >> 6;
   double* w = lds + (size_t)wave * maxrow;
@@ -234,7 +252,9 @@ __global__ void k_rf_pack(const int32_t* __restrict__ flev, const int32_t* __res
 __global__ void k_rf_top_ext(int t0, int n, const int32_t* __restrict__ lo_split, const int32_t* __restrict__ ptr,
                              const int32_t* __restrict__ col, const int32_t* __restrict__ diag,
                              const int64_t* __restrict__ upd_ptr, const int32_t* __restrict__ upd_tgt,
-                             double* __restrict__ a, int maxrow, int32_t* __restrict__ status) {
+                             double* __restrict__ a, int maxrow, int32_t* __restrict__ status,
+    const int32_t* __restrict__ skip) {
+  if (skip && *skip) return;
   extern __shared__ double lds[];
   const int wave = threadIdx.x >> 6, nwave = blockDim.x >> 6;
   double* w = lds + (size_t)wave * maxrow;
@@ -243,14 +263,18 @@ __global__ void k_rf_top_ext(int t0, int n, const int32_t* __restrict__ lo_split
   rf_row(i, lo_split[i], false, ptr, col, diag, upd_ptr, upd_tgt, a, w, 0.0, status);
 }
 
-__global__ void k_fill_dbl(int64_t n, double* __restrict__ p, double v) {
+__global__ void k_fill_dbl(int64_t n, double* __restrict__ p, double v,
+    const int32_t* __restrict__ skip) {
+  if (skip && *skip) return;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;
 }
 
 // dense[off[e]] = a[pos[e]] (to_dense) or a[pos[e]] = dense[off[e]]
 __global__ void k_dense_xfer(int n, const int32_t* __restrict__ pos, const int64_t* __restrict__ off,
-                             double* __restrict__ a, double* __restrict__ dense, int to_dense) {
+                             double* __restrict__ a, double* __restrict__ dense, int to_dense,
+    const int32_t* __restrict__ skip) {
+  if (skip && *skip) return;
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= n) return;
   if (to_dense) dense[off[e]] = a[pos[e]];
@@ -312,7 +336,9 @@ template <bool FUNIT, bool BWD, bool BUNIT>
 __global__ void __launch_bounds__(256) k_top_dense(int t0, int n, const int32_t* __restrict__ lo_split,
                                                    const int32_t* __restrict__ ptr, const int32_t* __restrict__ col,
                                                    const double* __restrict__ fval, const double* __restrict__ M,
-                                                   double* __restrict__ X, int ld, int ncols, double scale, int tw) {
+                                                   double* __restrict__ X, int ld, int ncols, double scale, int tw,
+    const int32_t* __restrict__ skip) {
+  if (skip && *skip) return;
   extern __shared__ double xs[];
   __shared__ double mt[CB][33];
   const int s = n - t0;
@@ -406,7 +432,9 @@ __global__ void k_pack_solve_s(const int32_t* __restrict__ pack_ptr, const int32
                                const int16_t* __restrict__ ecol, const int32_t* __restrict__ diag,
                                const int32_t* __restrict__ up_split, const int32_t* __restrict__ ptr,
                                const int32_t* __restrict__ col, const double* __restrict__ val,
-                               double* __restrict__ X, int ld, int ncols, double scale) {
+                               double* __restrict__ X, int ld, int ncols, double scale,
+    const int32_t* __restrict__ skip) {
+  if (skip && *skip) return;
   extern __shared__ double smem[];
   const int q = blockIdx.x;
   const int c0 = blockIdx.y * TW;
@@ -738,7 +766,9 @@ __global__ void k_k_diag(VarArgs V, const int32_t* __restrict__ kdiag, const dou
   }
 }
 
-__global__ void k_axpy(int n, double a, const double* __restrict__ x, double* __restrict__ y) {
+__global__ void k_axpy(int n, double a, const double* __restrict__ x, double* __restrict__ y,
+    const int32_t* __restrict__ skip) {
+  if (skip && *skip) return;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) y[i] += a * x[i];
 }
@@ -755,6 +785,97 @@ __global__ void k_set_status(int32_t* __restrict__ st, int32_t it, int32_t conv,
 __global__ void k_fill_int(int n, int32_t* __restrict__ p, int32_t v) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;
+}
+
+// --------------------------------------------------------- tracking step
+__global__ void k_copy_vec(int n, const double* __restrict__ src, double* __restrict__ dst,
+                           const int32_t* __restrict__ skip) {
+  if (skip && *skip) return;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = src[i];
+}
+
+__global__ void k_count(const int32_t* __restrict__ skip, int32_t* __restrict__ count) {
+  if (skip && *skip) return;
+  if (threadIdx.x == 0 && blockIdx.x == 0) count[0] += 1;
+}
+
+__global__ void k_copy_int(const int32_t* __restrict__ src, int32_t* __restrict__ dst) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) dst[0] = src[0];
+}
+
+// loads of one tracking step: base loads times per-bus factors
+__global__ void k_track_loads(int nb, const double* __restrict__ pd0, const double* __restrict__ qd0,
+                              const double* __restrict__ fac, double* __restrict__ pd, double* __restrict__ qd) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nb) {
+    pd[i] = pd0[i] * fac[i];
+    qd[i] = qd0[i] * fac[i];
+  }
+}
+
+// closed-form minimiser of the scaled AL in s: clip(c + y / (rho sigma_c))
+__global__ void k_slack(int m, const double* __restrict__ c, const double* __restrict__ y,
+                        const double* __restrict__ sigma_c, double rho, const double* __restrict__ lo,
+                        const double* __restrict__ hi, double* __restrict__ s) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < m) s[k] = fmin(fmax(c[k] + y[k] / (rho * sigma_c[k]), lo[k]), hi[k]);
+}
+
+// multiplier update with the slack minimiser at the new point:
+// s = clip(c + y / (rho sigma)), y += rho sigma (c - s)
+__global__ void k_y_update(int m, const double* __restrict__ c, const double* __restrict__ sigma_c, double rho,
+                           const double* __restrict__ lo, const double* __restrict__ hi, double* __restrict__ y,
+                           double* __restrict__ s) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < m) {
+    const double sk = fmin(fmax(c[k] + y[k] / (rho * sigma_c[k]), lo[k]), hi[k]);
+    s[k] = sk;
+    y[k] = y[k] + rho * sigma_c[k] * (c[k] - sk);
+  }
+}
+
+// trial control u + f d clipped to the control bounds
+__global__ void k_try_u(int n, const double* __restrict__ u, const double* __restrict__ d, double f,
+                        const double* __restrict__ lo, const double* __restrict__ hi, double* __restrict__ ut,
+                        const int32_t* __restrict__ skip) {
+  if (skip && *skip) return;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) ut[i] = fmin(fmax(u[i] + f * d[i], lo[i]), hi[i]);
+}
+
+// accept the trial control when its power flow converged: accepted = 1,
+// u = ut, status = attempt index
+__global__ void k_accept(int n, const double* __restrict__ resid, double tol, int32_t* __restrict__ accepted,
+                         const double* __restrict__ ut, double* __restrict__ u, int32_t attempt,
+                         int32_t* __restrict__ which) {
+  __shared__ int ok;
+  if (threadIdx.x == 0) ok = (accepted[0] == 0 && resid[0] < tol) ? 1 : 0;
+  __syncthreads();
+  if (!ok) return;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) u[i] = ut[i];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    accepted[0] = 1;
+    which[0] = attempt;
+  }
+}
+
+// status of a tracking step: first power flow converged, accepted trial
+// (-1: none), Cholesky info, Newton steps of the first power flow
+__global__ void k_track_status(const int32_t* __restrict__ f, int32_t* __restrict__ st) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    st[0] = f[5];
+    st[1] = f[3];
+    st[2] = f[4];
+    st[3] = f[6];
+  }
+}
+
+__global__ void k_zero_if(int n, const int32_t* __restrict__ info, double* __restrict__ v) {
+  if (info[0] == 0) return;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) v[i] = 0.0;
 }
 
 // ------------------------------------------------------------ dense step
@@ -781,7 +902,9 @@ __global__ void k_symmetrize(int n, double* __restrict__ K, const double* __rest
 // pivot records base + (column + 1) in info[0]; later kernels return early.
 
 template <bool CHOL>
-__global__ void __launch_bounds__(64) k_blk_diag(int n, int b0, double* __restrict__ A, int32_t* __restrict__ info, int base) {
+__global__ void __launch_bounds__(64) k_blk_diag(int n, int b0, double* __restrict__ A, int32_t* __restrict__ info, int base,
+    const int32_t* __restrict__ skip) {
+  if (skip && *skip) return;
   __shared__ double bc[CB];
   if (info[0] != 0) return;
   const int nb = min(CB, n - b0);
@@ -836,7 +959,9 @@ __global__ void __launch_bounds__(64) k_blk_diag(int n, int b0, double* __restri
 // x L11^T = a (Cholesky); for LU, tasks past the rows solve L11 y = a for a
 // column to the right (unit lower).  Lanes hold the CB entries.
 template <bool CHOL>
-__global__ void k_blk_panel(int n, int b0, double* __restrict__ A, const int32_t* __restrict__ info) {
+__global__ void k_blk_panel(int n, int b0, double* __restrict__ A, const int32_t* __restrict__ info,
+    const int32_t* __restrict__ skip) {
+  if (skip && *skip) return;
   __shared__ double T[CB][CB + 1];
   if (info[0] != 0) return;
   const int nb = min(CB, n - b0);
@@ -870,7 +995,9 @@ __global__ void k_blk_panel(int n, int b0, double* __restrict__ A, const int32_t
 
 // Trailing update A22 -= L21 U12 (LU) or L21 L21^T (Cholesky, lower tiles).
 template <bool CHOL>
-__global__ void k_blk_update(int n, int b0, double* __restrict__ A, const int32_t* __restrict__ info) {
+__global__ void k_blk_update(int n, int b0, double* __restrict__ A, const int32_t* __restrict__ info,
+    const int32_t* __restrict__ skip) {
+  if (skip && *skip) return;
   __shared__ double Ls[CB][CB + 1];
   __shared__ double Us[CB][CB + 1];
   if (info[0] != 0) return;
@@ -910,7 +1037,9 @@ __global__ void k_blk_update(int n, int b0, double* __restrict__ A, const int32_
     }
 }
 
-__global__ void k_transpose(int n, const double* __restrict__ A, double* __restrict__ B) {
+__global__ void k_transpose(int n, const double* __restrict__ A, double* __restrict__ B,
+    const int32_t* __restrict__ skip) {
+  if (skip && *skip) return;
   __shared__ double t[32][33];
   const int bx = blockIdx.x * 32, by = blockIdx.y * 32;
   for (int k = threadIdx.y; k < 32; k += blockDim.y) {

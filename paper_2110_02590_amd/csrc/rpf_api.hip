@@ -86,6 +86,9 @@ struct rpf_grid {
   double *luv, *lutv, *juv, *Gv, *Kv, *wrec, *kappa, *a, *b, *Pbus, *Qbus;
   double *cvec, *wvec, *terms, *varg, *lam;
   double *D, *Y, *T, *chol_work;
+  // tracking step workspace
+  double *Hbuf, *Kbuf, *gradbuf, *dstep, *u_try, *xi_save, *scur, *pdt, *qdt, *tres;
+  int32_t* tflags;
   int32_t *flag, *piv_status;
   double* host_resid;  // pinned
 
@@ -288,6 +291,24 @@ void setup(rpf_grid* h) {
     h->tw_top = 16;
     while (h->tw_top > 1 && (size_t)P.ntop * h->tw_top * 8 > h->lds_limit) h->tw_top /= 2;
     if ((size_t)P.ntop * 8 > h->lds_limit) throw std::runtime_error("top part of the elimination tree too large for LDS");
+    // allow the dynamic LDS sizes above the default for the solve kernels
+    const int ldsmax = (int)h->lds_limit;
+    auto allow = [&](const void* f) {
+      HIPCHK(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, ldsmax));
+    };
+    allow((const void*)k_top_dense<true, true, false>);
+    allow((const void*)k_top_dense<false, true, true>);
+#define RPF_ALLOW_PACK(TW)                                  \
+  allow((const void*)k_pack_solve_s<TW, true, true>);       \
+  allow((const void*)k_pack_solve_s<TW, true, false>);      \
+  allow((const void*)k_pack_solve_s<TW, false, true>);      \
+  allow((const void*)k_pack_solve_s<TW, false, false>);
+    RPF_ALLOW_PACK(16)
+    RPF_ALLOW_PACK(8)
+    RPF_ALLOW_PACK(4)
+    RPF_ALLOW_PACK(2)
+    RPF_ALLOW_PACK(1)
+#undef RPF_ALLOW_PACK
   }
   const size_t nnz = P.lu_col.size();
   h->xi = h->alloc<double>(P.nx);
@@ -318,6 +339,17 @@ void setup(rpf_grid* h) {
   h->Y = h->alloc<double>((size_t)P.nvar * h->max_batch);
   h->T = h->alloc<double>((size_t)P.nr1 * h->max_batch);
   h->chol_work = h->alloc<double>(P.nu);
+  h->Hbuf = h->alloc<double>((size_t)P.nu * P.nu);
+  h->Kbuf = h->alloc<double>((size_t)P.nu * P.nu);
+  h->gradbuf = h->alloc<double>(P.nu);
+  h->dstep = h->alloc<double>(P.nu);
+  h->u_try = h->alloc<double>(P.nu);
+  h->xi_save = h->alloc<double>(P.nx);
+  h->scur = h->alloc<double>(P.m);
+  h->pdt = h->alloc<double>(P.nb);
+  h->qdt = h->alloc<double>(P.nb);
+  h->tres = h->alloc<double>(4);
+  h->tflags = h->alloc<int32_t>(8);
   h->flag = h->alloc<int32_t>(4);
   h->piv_status = h->alloc<int32_t>(4);
   HIPCHK(hipHostMalloc((void**)&h->host_resid, sizeof(double) * 4, hipHostMallocDefault));
@@ -330,43 +362,43 @@ void setup(rpf_grid* h) {
 }
 
 // ---------------------------------------------------------- launch helpers
-void state_and_records(rpf_grid* h, const double* u, hipStream_t s) {
+void state_and_records(rpf_grid* h, const double* u, hipStream_t s, const int32_t* skip = nullptr) {
   const Presolve& P = h->P;
-  k_bus_state<<<cdiv(P.nb, 256), 256, 0, s>>>(P.nb, P.nx, h->th_var, h->v_var, h->xi, u, h->th, h->vm);
+  k_bus_state<<<cdiv(P.nb, 256), 256, 0, s>>>(P.nb, P.nx, h->th_var, h->v_var, h->xi, u, h->th, h->vm, skip);
   LAUNCHCHK();
   k_branch_eval<<<cdiv(P.nl, 256), 256, 0, s>>>(P.nl, h->br_f, h->br_t, h->br_r, h->br_x, h->br_b, h->th,
-                                                 h->vm, h->rec);
+                                                 h->vm, h->rec, skip);
   LAUNCHCHK();
 }
 
-void x_in(rpf_grid* h, const double* x, hipStream_t s) {
-  k_permute_gather<<<cdiv(h->P.nx, 256), 256, 0, s>>>(h->P.nx, h->x_i2p, x, h->xi);
+void x_in(rpf_grid* h, const double* x, hipStream_t s, const int32_t* skip = nullptr) {
+  k_permute_gather<<<cdiv(h->P.nx, 256), 256, 0, s>>>(h->P.nx, h->x_i2p, x, h->xi, skip);
   LAUNCHCHK();
 }
 
 // Blocked dense LU (no pivoting) or Cholesky of a row-major n x n matrix.
 template <bool CHOL>
-void dense_factor(int n, double* A, int32_t* info, int base, hipStream_t s) {
+void dense_factor(int n, double* A, int32_t* info, int base, hipStream_t s, const int32_t* skip = nullptr) {
   for (int b0 = 0; b0 < n; b0 += CB) {
     const int nb = std::min(CB, n - b0);
-    k_blk_diag<CHOL><<<1, 64, 0, s>>>(n, b0, A, info, base);
+    k_blk_diag<CHOL><<<1, 64, 0, s>>>(n, b0, A, info, base, skip);
     LAUNCHCHK();
     const int rest = n - b0 - nb;
     if (rest > 0) {
       const int tasks = CHOL ? rest : 2 * rest;
-      k_blk_panel<CHOL><<<cdiv(tasks, 4), 256, 0, s>>>(n, b0, A, info);
+      k_blk_panel<CHOL><<<cdiv(tasks, 4), 256, 0, s>>>(n, b0, A, info, skip);
       LAUNCHCHK();
       const int nt = cdiv(rest, CB);
-      k_blk_update<CHOL><<<dim3(nt, nt), 256, 0, s>>>(n, b0, A, info);
+      k_blk_update<CHOL><<<dim3(nt, nt), 256, 0, s>>>(n, b0, A, info, skip);
       LAUNCHCHK();
     }
   }
 }
 
-void refactor(rpf_grid* h, hipStream_t s) {
+void refactor(rpf_grid* h, hipStream_t s, const int32_t* skip = nullptr) {
   const Presolve& P = h->P;
   const size_t nnz = P.lu_col.size();
-  k_gather_sum<<<cdiv(nnz, 256), 256, 0, s>>>((int)nnz, h->jx_sp, h->jx_s, h->rec, nullptr, h->luv);
+  k_gather_sum<<<cdiv(nnz, 256), 256, 0, s>>>((int)nnz, h->jx_sp, h->jx_s, h->rec, nullptr, h->luv, skip);
   LAUNCHCHK();
   const int maxrow = std::max(P.max_lu_row, 1);
   const int wv = h->rf_waves;
@@ -375,34 +407,35 @@ void refactor(rpf_grid* h, hipStream_t s) {
   if (h->npacks > 0) {
     k_rf_pack<<<h->npacks, 64 * wv, shm, s>>>(h->pk_flev, h->pk_flev_off, h->pk_frows, h->lu_ptr, h->lu_col,
                                               h->lu_diag, h->upd_ptr, h->upd_tgt, h->luv, maxrow, 1e-14,
-                                              h->piv_status);
+                                              h->piv_status, skip);
     LAUNCHCHK();
   }
   if (P.ntop > 0) {
     k_rf_top_ext<<<cdiv(P.ntop, wv), 64 * wv, shm, s>>>(P.t0, P.nx, h->lo_split, h->lu_ptr, h->lu_col, h->lu_diag,
-                                                       h->upd_ptr, h->upd_tgt, h->luv, maxrow, h->piv_status);
+                                                       h->upd_ptr, h->upd_tgt, h->luv, maxrow, h->piv_status,
+                                                       skip);
     LAUNCHCHK();
     const int64_t nd = (int64_t)P.ntop * P.ntop;
-    k_fill_dbl<<<cdiv(nd, 256), 256, 0, s>>>(nd, h->dense_top, 0.0);
+    k_fill_dbl<<<cdiv(nd, 256), 256, 0, s>>>(nd, h->dense_top, 0.0, skip);
     LAUNCHCHK();
     const int ne = (int)P.top_pos.size();
-    k_dense_xfer<<<cdiv(ne, 256), 256, 0, s>>>(ne, h->top_pos, h->top_dense, h->luv, h->dense_top, 1);
+    k_dense_xfer<<<cdiv(ne, 256), 256, 0, s>>>(ne, h->top_pos, h->top_dense, h->luv, h->dense_top, 1, skip);
     LAUNCHCHK();
-    dense_factor<false>(P.ntop, h->dense_top, h->piv_status, P.t0, s);
+    dense_factor<false>(P.ntop, h->dense_top, h->piv_status, P.t0, s, skip);
     k_transpose<<<dim3(cdiv(P.ntop, 32), cdiv(P.ntop, 32)), dim3(32, 8), 0, s>>>(P.ntop, h->dense_top,
-                                                                                 h->dense_topT);
+                                                                                 h->dense_topT, skip);
     LAUNCHCHK();
-    k_dense_xfer<<<cdiv(ne, 256), 256, 0, s>>>(ne, h->top_pos, h->top_dense, h->luv, h->dense_top, 0);
+    k_dense_xfer<<<cdiv(ne, 256), 256, 0, s>>>(ne, h->top_pos, h->top_dense, h->luv, h->dense_top, 0, skip);
     LAUNCHCHK();
   }
   if (h->prof_on) h->prof_end(2, pi, s);
-  k_gather_pos<<<cdiv(nnz, 256), 256, 0, s>>>((int)nnz, h->lut_src, h->luv, h->lutv);
+  k_gather_pos<<<cdiv(nnz, 256), 256, 0, s>>>((int)nnz, h->lut_src, h->luv, h->lutv, skip);
   LAUNCHCHK();
 }
 
 template <int TW>
 void pack_solve(rpf_grid* h, bool fwd, bool unit, const double* val, double* X, int ld, int ncols, double scale,
-                int cls, hipStream_t s) {
+                int cls, hipStream_t s, const int32_t* skip) {
   const Presolve& P = h->P;
   if (h->npacks == 0) return;
   const int k = TW == 16 ? 0 : TW == 8 ? 1 : TW == 4 ? 2 : TW == 2 ? 3 : 4;
@@ -411,9 +444,8 @@ void pack_solve(rpf_grid* h, bool fwd, bool unit, const double* val, double* X, 
   size_t pi = h->prof_on ? h->prof_begin(s) : 0;
   auto launch = [&](auto kern, const int32_t* lev, const int32_t* lev_off, const int32_t* rows, const int32_t* rp,
                     const int32_t* pos, const int16_t* ecol) {
-    if (shm > 65536) HIPCHK(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
     kern<<<grd, 256, shm, s>>>(h->pack_ptr, lev, lev_off, rows, rp, pos, ecol, h->lu_diag, h->up_split, h->lu_ptr,
-                               h->lu_col, val, X, ld, ncols, scale);
+                               h->lu_col, val, X, ld, ncols, scale, skip);
   };
   if (fwd) {
     if (unit)
@@ -432,13 +464,13 @@ void pack_solve(rpf_grid* h, bool fwd, bool unit, const double* val, double* X, 
 }
 
 void pack_solve_any(rpf_grid* h, int tw, bool fwd, bool unit, const double* val, double* X, int ld, int ncols,
-                    double scale, int cls, hipStream_t s) {
+                    double scale, int cls, hipStream_t s, const int32_t* skip) {
   switch (tw) {
-    case 16: return pack_solve<16>(h, fwd, unit, val, X, ld, ncols, scale, cls, s);
-    case 8: return pack_solve<8>(h, fwd, unit, val, X, ld, ncols, scale, cls, s);
-    case 4: return pack_solve<4>(h, fwd, unit, val, X, ld, ncols, scale, cls, s);
-    case 2: return pack_solve<2>(h, fwd, unit, val, X, ld, ncols, scale, cls, s);
-    default: return pack_solve<1>(h, fwd, unit, val, X, ld, ncols, scale, cls, s);
+    case 16: return pack_solve<16>(h, fwd, unit, val, X, ld, ncols, scale, cls, s, skip);
+    case 8: return pack_solve<8>(h, fwd, unit, val, X, ld, ncols, scale, cls, s, skip);
+    case 4: return pack_solve<4>(h, fwd, unit, val, X, ld, ncols, scale, cls, s, skip);
+    case 2: return pack_solve<2>(h, fwd, unit, val, X, ld, ncols, scale, cls, s, skip);
+    default: return pack_solve<1>(h, fwd, unit, val, X, ld, ncols, scale, cls, s, skip);
   }
 }
 
@@ -446,7 +478,8 @@ void pack_solve_any(rpf_grid* h, int tw, bool fwd, bool unit, const double* val,
 // (scale X), or of J_x^T (transposed = true): X <- L^{-T} U^{-T} (scale X).
 // Three launches: packs forward, top part forward + backward, packs
 // backward.
-void solve_pair(rpf_grid* h, bool transposed, double* X, int ld, int ncols, double scale, hipStream_t s) {
+void solve_pair(rpf_grid* h, bool transposed, double* X, int ld, int ncols, double scale, hipStream_t s,
+                const int32_t* skip = nullptr) {
   const Presolve& P = h->P;
   const double* val = transposed ? h->lutv : h->luv;
   // forward factor: L (unit) or U^T (non-unit); backward: U (non-unit) or L^T (unit)
@@ -454,7 +487,7 @@ void solve_pair(rpf_grid* h, bool transposed, double* X, int ld, int ncols, doub
   const int cls = ncols > 1 ? 0 : 1;
   const int twp = ncols == 1 ? 1 : h->tw_pack;
   const int twt = ncols == 1 ? 1 : h->tw_top;
-  pack_solve_any(h, twp, true, fwd_unit, val, X, ld, ncols, scale, cls, s);
+  pack_solve_any(h, twp, true, fwd_unit, val, X, ld, ncols, scale, cls, s, skip);
   if (P.ntop > 0) {
     size_t pi = h->prof_on ? h->prof_begin(s) : 0;
     const size_t shm = (size_t)P.ntop * twt * sizeof(double);
@@ -462,17 +495,15 @@ void solve_pair(rpf_grid* h, bool transposed, double* X, int ld, int ncols, doub
     const int ct = cdiv(ncols, twt);
     if (fwd_unit) {
       auto kern = k_top_dense<true, true, false>;
-      if (shm > 65536) HIPCHK(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
-      kern<<<ct, 256, shm, s>>>(P.t0, P.nx, h->lo_split, h->lu_ptr, h->lu_col, val, M, X, ld, ncols, scale, twt);
+      kern<<<ct, 256, shm, s>>>(P.t0, P.nx, h->lo_split, h->lu_ptr, h->lu_col, val, M, X, ld, ncols, scale, twt, skip);
     } else {
       auto kern = k_top_dense<false, true, true>;
-      if (shm > 65536) HIPCHK(hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)shm));
-      kern<<<ct, 256, shm, s>>>(P.t0, P.nx, h->lo_split, h->lu_ptr, h->lu_col, val, M, X, ld, ncols, scale, twt);
+      kern<<<ct, 256, shm, s>>>(P.t0, P.nx, h->lo_split, h->lu_ptr, h->lu_col, val, M, X, ld, ncols, scale, twt, skip);
     }
     LAUNCHCHK();
     if (h->prof_on) h->prof_end(cls, pi, s);
   }
-  pack_solve_any(h, twp, false, !fwd_unit, val, X, ld, ncols, 1.0, cls, s);
+  pack_solve_any(h, twp, false, !fwd_unit, val, X, ld, ncols, 1.0, cls, s, skip);
 }
 
 void spmm(rpf_grid* h, int nrows, const int32_t* ptr, const int32_t* col, const double* val,
@@ -512,9 +543,9 @@ VarArgs var_args(rpf_grid* h, const double* u, const double* sigma) {
 
 void bus_injections(rpf_grid* h, hipStream_t s) {
   const Presolve& P = h->P;
-  k_gather_sum<<<cdiv(P.nb, 256), 256, 0, s>>>(P.nb, h->pb_ptr, h->pb_src, h->rec, nullptr, h->Pbus);
+  k_gather_sum<<<cdiv(P.nb, 256), 256, 0, s>>>(P.nb, h->pb_ptr, h->pb_src, h->rec, nullptr, h->Pbus, nullptr);
   LAUNCHCHK();
-  k_gather_sum<<<cdiv(P.nb, 256), 256, 0, s>>>(P.nb, h->pb_ptr, h->qb_src, h->rec, nullptr, h->Qbus);
+  k_gather_sum<<<cdiv(P.nb, 256), 256, 0, s>>>(P.nb, h->pb_ptr, h->qb_src, h->rec, nullptr, h->Qbus, nullptr);
   LAUNCHCHK();
 }
 
@@ -702,9 +733,9 @@ int rpf_pf_solve(rpf_grid* h, const double* u, const double* pd, const double* q
     for (;;) {
       state_and_records(h, u, s);
       k_residual<<<nblk, 256, 0, s>>>(P.nx, h->g_sp, h->g_s, h->rec, h->row_bus, h->row_isq, h->row_pvar, pd,
-                                      qd, u, h->g, h->partial);
+                                      qd, u, h->g, h->partial, nullptr);
       LAUNCHCHK();
-      k_reduce_final<<<1, 1024, 0, s>>>(nblk, h->partial, h->resid_d, 1, tol, nullptr);
+      k_reduce_final<<<1, 1024, 0, s>>>(nblk, h->partial, h->resid_d, 1, tol, nullptr, nullptr);
       LAUNCHCHK();
       HIPCHK(hipMemcpyAsync(h->host_resid, h->resid_d, sizeof(double), hipMemcpyDeviceToHost, s));
       HIPCHK(hipStreamSynchronize(s));
@@ -717,13 +748,13 @@ int rpf_pf_solve(rpf_grid* h, const double* u, const double* pd, const double* q
       refactor(h, s);
       HIPCHK(hipMemcpyAsync(h->d, h->g, sizeof(double) * P.nx, hipMemcpyDeviceToDevice, s));
       solve_pair(h, false, h->d, 1, 1, 1.0, s);
-      k_axpy<<<nblk, 256, 0, s>>>(P.nx, -1.0, h->d, h->xi);
+      k_axpy<<<nblk, 256, 0, s>>>(P.nx, -1.0, h->d, h->xi, nullptr);
       LAUNCHCHK();
       ++it;
     }
     k_set_status<<<1, 1, 0, s>>>(status, it, conv, h->resid_d, resid);
     LAUNCHCHK();
-    k_permute_scatter<<<nblk, 256, 0, s>>>(P.nx, h->x_i2p, h->xi, x);
+    k_permute_scatter<<<nblk, 256, 0, s>>>(P.nx, h->x_i2p, h->xi, x, nullptr);
     LAUNCHCHK();
     return RPF_OK;
   });
@@ -742,11 +773,108 @@ int rpf_al_objective(rpf_grid* h, const double* x, const double* u, const double
     ALArgs A = al_args(h, u, pd, qd, sv, y, rho, sigma);
     k_constraints<<<cdiv(P.m + P.ng, 256), 256, 0, s>>>(A, c ? c : h->cvec, h->wvec, h->terms);
     LAUNCHCHK();
-    k_reduce_final<<<1, 1024, 0, s>>>(P.m + P.ng, h->terms, phi, 0, 0.0, nullptr);
+    k_reduce_final<<<1, 1024, 0, s>>>(P.m + P.ng, h->terms, phi, 0, 0.0, nullptr, nullptr);
     LAUNCHCHK();
     return RPF_OK;
   });
 }
+
+}  // extern "C"
+
+namespace {
+
+// Reduced gradient at the state already in h->xi (internal order); caches
+// the point for the Hessian products.  grad and lambda (paper order) may be
+// null.
+void gradient_core(rpf_grid* h, const double* u, const double* pd, const double* qd, const double* sv,
+                   const double* y, double rho, const double* sigma, double* grad, double* lambda, hipStream_t s) {
+  const Presolve& P = h->P;
+  h->have_point = false;
+  state_and_records(h, u, s);
+  bus_injections(h, s);
+  ALArgs A = al_args(h, u, pd, qd, sv, y, rho, sigma);
+  VarArgs V = var_args(h, u, sigma);
+  k_constraints<<<cdiv(P.m + P.ng, 256), 256, 0, s>>>(A, h->cvec, h->wvec, nullptr);
+  LAUNCHCHK();
+  const int nbw = cdiv(P.nb + 2 + P.npv, 256);
+  // d phi / d(variables) through branch-local gradients
+  k_bus_weights<<<nbw, 256, 0, s>>>(A, h->wvec, nullptr, h->rowP, h->rowQ, h->bus_pvpos, h->a, h->b, h->kappa);
+  LAUNCHCHK();
+  k_branch_second<<<cdiv(P.nl, 256), 256, 0, s>>>(P.nl, h->br_f, h->br_t, h->br_r, h->br_x, h->br_b, h->th,
+                                                   h->vm, h->rec, h->a, h->b, h->wvec, sigma + 1, rho, h->wrec);
+  LAUNCHCHK();
+  k_var_grad<<<cdiv(P.nvar, 256), 256, 0, s>>>(V, h->vg_sp, h->vg_s, h->wrec, h->wvec, nullptr, h->varg);
+  LAUNCHCHK();
+  // J_x factorized at x; lambda: U^T w = -d_x phi, L^T lambda = w
+  k_fill_int<<<1, 4, 0, s>>>(4, h->piv_status, 0);
+  LAUNCHCHK();
+  refactor(h, s);
+  k_copy_vec<<<cdiv(P.nx, 256), 256, 0, s>>>(P.nx, h->varg, h->lam, nullptr);
+  LAUNCHCHK();
+  solve_pair(h, true, h->lam, 1, 1, -1.0, s);
+  // gradient of l = phi + lambda^T g: its control part is the reduced gradient
+  k_bus_weights<<<nbw, 256, 0, s>>>(A, h->wvec, h->lam, h->rowP, h->rowQ, h->bus_pvpos, h->a, h->b, h->kappa);
+  LAUNCHCHK();
+  k_branch_second<<<cdiv(P.nl, 256), 256, 0, s>>>(P.nl, h->br_f, h->br_t, h->br_r, h->br_x, h->br_b, h->th,
+                                                   h->vm, h->rec, h->a, h->b, h->wvec, sigma + 1, rho, h->wrec);
+  LAUNCHCHK();
+  k_var_grad<<<cdiv(P.nvar, 256), 256, 0, s>>>(V, h->vg_sp, h->vg_s, h->wrec, h->wvec, h->lam, h->varg);
+  LAUNCHCHK();
+  if (grad) {
+    k_copy_vec<<<cdiv(P.nu, 256), 256, 0, s>>>(P.nu, h->varg + P.nx, grad, nullptr);
+    LAUNCHCHK();
+  }
+  if (lambda) {
+    k_permute_scatter<<<cdiv(P.nx, 256), 256, 0, s>>>(P.nx, h->x_i2p, h->lam, lambda, nullptr);
+    LAUNCHCHK();
+  }
+  // cached point for the Hessian products
+  k_gather_sum<<<cdiv(P.K_col.size(), 256), 256, 0, s>>>((int)P.K_col.size(), h->K_sp, h->K_s, h->wrec, nullptr,
+                                                          h->Kv, nullptr);
+  LAUNCHCHK();
+  k_k_diag<<<cdiv(P.nvar, 256), 256, 0, s>>>(V, h->K_diag, sigma + 1, rho, h->Kv);
+  LAUNCHCHK();
+  k_gather_sum<<<cdiv(P.ju_col.size(), 256), 256, 0, s>>>((int)P.ju_col.size(), h->ju_sp, h->ju_s, h->rec,
+                                                           h->ju_const, h->juv, nullptr);
+  LAUNCHCHK();
+  k_gather_sum<<<cdiv(P.G_col.size(), 256), 256, 0, s>>>((int)P.G_col.size(), h->G_sp, h->G_s, h->rec, nullptr,
+                                                          h->Gv, nullptr);
+  LAUNCHCHK();
+  h->rho = rho;
+  h->have_point = true;
+}
+
+// Newton power flow on h->xi with `iters` predicated steps and no host
+// synchronisation: done[0] is raised when ||g||_2 < tol and every later
+// kernel of the loop returns at once; count[0] counts the steps taken and
+// resid[0] holds the last residual norm.  A nonzero done[0] on entry skips
+// the whole solve.
+void pf_device(rpf_grid* h, const double* u, const double* pd, const double* qd, int iters, double tol,
+               int32_t* done, int32_t* count, double* resid, hipStream_t s) {
+  const Presolve& P = h->P;
+  const int nblk = cdiv(P.nx, 256);
+  for (int k = 0; k <= iters; ++k) {
+    state_and_records(h, u, s, done);
+    k_residual<<<nblk, 256, 0, s>>>(P.nx, h->g_sp, h->g_s, h->rec, h->row_bus, h->row_isq, h->row_pvar, pd, qd, u,
+                                    h->g, h->partial, done);
+    LAUNCHCHK();
+    k_reduce_final<<<1, 1024, 0, s>>>(nblk, h->partial, resid, 1, tol, done, done);
+    LAUNCHCHK();
+    if (k == iters) break;
+    refactor(h, s, done);
+    k_copy_vec<<<nblk, 256, 0, s>>>(P.nx, h->g, h->d, done);
+    LAUNCHCHK();
+    solve_pair(h, false, h->d, 1, 1, 1.0, s, done);
+    k_axpy<<<nblk, 256, 0, s>>>(P.nx, -1.0, h->d, h->xi, done);
+    LAUNCHCHK();
+    k_count<<<1, 1, 0, s>>>(done, count);
+    LAUNCHCHK();
+  }
+}
+
+}  // namespace
+
+extern "C" {
 
 int rpf_reduced_gradient(rpf_grid* h, const double* x, const double* u, const double* pd, const double* qd,
                          const double* sv, const double* y, double rho, const double* sigma, double* grad,
@@ -754,56 +882,8 @@ int rpf_reduced_gradient(rpf_grid* h, const double* x, const double* u, const do
   if (!h || !x || !u || !pd || !qd || !sv || !y || !sigma || !grad) return set_err(RPF_EINVAL, "NULL argument");
   return guard([&]() -> int {
     hipStream_t s = (hipStream_t)stream;
-    const Presolve& P = h->P;
-    h->have_point = false;
     x_in(h, x, s);
-    state_and_records(h, u, s);
-    bus_injections(h, s);
-    ALArgs A = al_args(h, u, pd, qd, sv, y, rho, sigma);
-    VarArgs V = var_args(h, u, sigma);
-    k_constraints<<<cdiv(P.m + P.ng, 256), 256, 0, s>>>(A, h->cvec, h->wvec, nullptr);
-    LAUNCHCHK();
-    const int nbw = cdiv(P.nb + 2 + P.npv, 256);
-    // d phi / d(variables) through branch-local gradients
-    k_bus_weights<<<nbw, 256, 0, s>>>(A, h->wvec, nullptr, h->rowP, h->rowQ, h->bus_pvpos, h->a, h->b, h->kappa);
-    LAUNCHCHK();
-    k_branch_second<<<cdiv(P.nl, 256), 256, 0, s>>>(P.nl, h->br_f, h->br_t, h->br_r, h->br_x, h->br_b, h->th,
-                                                     h->vm, h->rec, h->a, h->b, h->wvec, sigma + 1, rho, h->wrec);
-    LAUNCHCHK();
-    k_var_grad<<<cdiv(P.nvar, 256), 256, 0, s>>>(V, h->vg_sp, h->vg_s, h->wrec, h->wvec, nullptr, h->varg);
-    LAUNCHCHK();
-    // J_x factorized at x; lambda: U^T w = -d_x phi, L^T lambda = w
-    k_fill_int<<<1, 4, 0, s>>>(4, h->piv_status, 0);
-    refactor(h, s);
-    HIPCHK(hipMemcpyAsync(h->lam, h->varg, sizeof(double) * P.nx, hipMemcpyDeviceToDevice, s));
-    solve_pair(h, true, h->lam, 1, 1, -1.0, s);
-    // gradient of l = phi + lambda^T g: its control part is the reduced gradient
-    k_bus_weights<<<nbw, 256, 0, s>>>(A, h->wvec, h->lam, h->rowP, h->rowQ, h->bus_pvpos, h->a, h->b, h->kappa);
-    LAUNCHCHK();
-    k_branch_second<<<cdiv(P.nl, 256), 256, 0, s>>>(P.nl, h->br_f, h->br_t, h->br_r, h->br_x, h->br_b, h->th,
-                                                     h->vm, h->rec, h->a, h->b, h->wvec, sigma + 1, rho, h->wrec);
-    LAUNCHCHK();
-    k_var_grad<<<cdiv(P.nvar, 256), 256, 0, s>>>(V, h->vg_sp, h->vg_s, h->wrec, h->wvec, h->lam, h->varg);
-    LAUNCHCHK();
-    HIPCHK(hipMemcpyAsync(grad, h->varg + P.nx, sizeof(double) * P.nu, hipMemcpyDeviceToDevice, s));
-    if (lambda) {
-      k_permute_scatter<<<cdiv(P.nx, 256), 256, 0, s>>>(P.nx, h->x_i2p, h->lam, lambda);
-      LAUNCHCHK();
-    }
-    // cached point for the Hessian products
-    k_gather_sum<<<cdiv(P.K_col.size(), 256), 256, 0, s>>>((int)P.K_col.size(), h->K_sp, h->K_s, h->wrec,
-                                                            nullptr, h->Kv);
-    LAUNCHCHK();
-    k_k_diag<<<cdiv(P.nvar, 256), 256, 0, s>>>(V, h->K_diag, sigma + 1, rho, h->Kv);
-    LAUNCHCHK();
-    k_gather_sum<<<cdiv(P.ju_col.size(), 256), 256, 0, s>>>((int)P.ju_col.size(), h->ju_sp, h->ju_s, h->rec,
-                                                             h->ju_const, h->juv);
-    LAUNCHCHK();
-    k_gather_sum<<<cdiv(P.G_col.size(), 256), 256, 0, s>>>((int)P.G_col.size(), h->G_sp, h->G_s, h->rec,
-                                                            nullptr, h->Gv);
-    LAUNCHCHK();
-    h->rho = rho;
-    h->have_point = true;
+    gradient_core(h, u, pd, qd, sv, y, rho, sigma, grad, lambda, s);
     return RPF_OK;
   });
 }
@@ -850,6 +930,92 @@ int rpf_factor_solve(rpf_grid* h, int32_t n, double* K, const double* diag, doub
     k_chol_solve<<<1, 256, 0, s>>>(n, K, rhs, step, h->chol_work, info);
     LAUNCHCHK();
     if (h->prof_on) h->prof_end(4, pi, s);
+    return RPF_OK;
+  });
+}
+
+int rpf_track_step(rpf_grid* h, double* u, double* x, double* y, const double* pd0, const double* qd0,
+                   const double* load_factor, const double* s_lo, const double* s_hi, const double* u_lo,
+                   const double* u_hi, double rho, const double* sigma, double delta, int32_t pf_iters,
+                   int32_t max_halvings, double tol, int32_t* status, rpf_stream_t stream) {
+  if (!h || !u || !x || !y || !pd0 || !qd0 || !load_factor || !s_lo || !s_hi || !u_lo || !u_hi || !sigma || !status)
+    return set_err(RPF_EINVAL, "NULL argument");
+  if (pf_iters < 1 || max_halvings < 0 || max_halvings > 30) return set_err(RPF_EINVAL, "bad iteration counts");
+  return guard([&]() -> int {
+    hipStream_t s = (hipStream_t)stream;
+    const Presolve& P = h->P;
+    const int nu = P.nu, nx = P.nx, m = P.m;
+    int32_t* done = h->tflags;        // predication flag of the current power flow
+    int32_t* count = h->tflags + 1;
+    int32_t* accepted = h->tflags + 2;
+    int32_t* which = h->tflags + 3;
+    int32_t* info = h->tflags + 4;
+    k_fill_int<<<1, 8, 0, s>>>(8, h->tflags, 0);
+    LAUNCHCHK();
+    k_fill_int<<<1, 1, 0, s>>>(1, which, -1);
+    LAUNCHCHK();
+    k_track_loads<<<cdiv(P.nb, 256), 256, 0, s>>>(P.nb, pd0, qd0, load_factor, h->pdt, h->qdt);
+    LAUNCHCHK();
+    // 1. power flow at the current control and the new loads (warm start)
+    x_in(h, x, s);
+    pf_device(h, u, h->pdt, h->qdt, pf_iters, tol, done, count, h->tres, s);
+    k_copy_int<<<1, 1, 0, s>>>(done, h->tflags + 5);
+    LAUNCHCHK();
+    k_copy_int<<<1, 1, 0, s>>>(count, h->tflags + 6);
+    LAUNCHCHK();
+    // 2. slack minimiser at the current multipliers
+    state_and_records(h, u, s);
+    bus_injections(h, s);
+    ALArgs A = al_args(h, u, h->pdt, h->qdt, h->scur, y, rho, sigma);
+    k_constraints<<<cdiv(m + P.ng, 256), 256, 0, s>>>(A, h->cvec, nullptr, nullptr);
+    LAUNCHCHK();
+    k_slack<<<cdiv(m, 256), 256, 0, s>>>(m, h->cvec, y, sigma + 1, rho, s_lo, s_hi, h->scur);
+    LAUNCHCHK();
+    // 3. reduced gradient and Hessian at (u, s, y)
+    gradient_core(h, u, h->pdt, h->qdt, h->scur, y, rho, sigma, h->gradbuf, nullptr, s);
+    const int B = std::min(h->max_batch, nu);
+    for (int j0 = 0; j0 < nu; j0 += B) hvp_batch(h, nullptr, 0, j0, std::min(B, nu - j0), h->Hbuf + j0, nu, s);
+    // 4. step = -(H + delta I)^{-1} grad (zero when the factorization fails)
+    k_copy_vec<<<cdiv((long)nu * nu, 256), 256, 0, s>>>(nu * nu, h->Hbuf, h->Kbuf, nullptr);
+    LAUNCHCHK();
+    k_symmetrize<<<dim3(cdiv(nu, 32), cdiv(nu, 8)), dim3(32, 8), 0, s>>>(nu, h->Kbuf, nullptr, delta);
+    LAUNCHCHK();
+    dense_factor<true>(nu, h->Kbuf, info, 0, s);
+    k_chol_solve<<<1, 256, 0, s>>>(nu, h->Kbuf, h->gradbuf, h->dstep, h->chol_work, info);
+    LAUNCHCHK();
+    k_zero_if<<<cdiv(nu, 256), 256, 0, s>>>(nu, info, h->dstep);
+    LAUNCHCHK();
+    // 5. u + step / 2^k clipped to the bounds, first k whose power flow converges
+    k_copy_vec<<<cdiv(nx, 256), 256, 0, s>>>(nx, h->xi, h->xi_save, nullptr);
+    LAUNCHCHK();
+    double f = 1.0;
+    for (int k = 0; k <= max_halvings; ++k, f *= 0.5) {
+      k_try_u<<<cdiv(nu, 256), 256, 0, s>>>(nu, u, h->dstep, f, u_lo, u_hi, h->u_try, accepted);
+      LAUNCHCHK();
+      k_copy_vec<<<cdiv(nx, 256), 256, 0, s>>>(nx, h->xi_save, h->xi, accepted);
+      LAUNCHCHK();
+      k_copy_int<<<1, 1, 0, s>>>(accepted, done);
+      LAUNCHCHK();
+      pf_device(h, h->u_try, h->pdt, h->qdt, pf_iters, tol, done, count, h->tres + 1, s);
+      k_accept<<<1, 256, 0, s>>>(nu, h->tres + 1, tol, accepted, h->u_try, u, k, which);
+      LAUNCHCHK();
+    }
+    // no trial accepted: keep u and the power flow at u
+    k_fill_int<<<1, 1, 0, s>>>(1, done, 0);
+    LAUNCHCHK();
+    k_copy_vec<<<cdiv(nx, 256), 256, 0, s>>>(nx, h->xi_save, h->xi, accepted);
+    LAUNCHCHK();
+    // 6. constraints at the new point, slack minimiser and multiplier update
+    state_and_records(h, u, s);
+    bus_injections(h, s);
+    k_constraints<<<cdiv(m + P.ng, 256), 256, 0, s>>>(A, h->cvec, nullptr, nullptr);
+    LAUNCHCHK();
+    k_y_update<<<cdiv(m, 256), 256, 0, s>>>(m, h->cvec, sigma + 1, rho, s_lo, s_hi, y, h->scur);
+    LAUNCHCHK();
+    k_permute_scatter<<<cdiv(nx, 256), 256, 0, s>>>(nx, h->x_i2p, h->xi, x, nullptr);
+    LAUNCHCHK();
+    k_track_status<<<1, 1, 0, s>>>(h->tflags, status);
+    LAUNCHCHK();
     return RPF_OK;
   });
 }

@@ -329,3 +329,53 @@ def test_slack_minimiser_minimises_the_al_in_s():
         obj = P.sigma_c[k] * P.y[k] * (c[k] - grid) + 0.5 * P.rho * (P.sigma_c[k] * (c[k] - grid)) ** 2
         best = grid[np.argmin(obj)]
         assert abs(best - s[k]) <= (hi[k] - lo[k]) / 20000 + 1e-12
+
+
+def _tracking_setup(seed=100):
+    w = gridgen.tracking_workload(seed)
+    g = gridgen.make_grid(dataclasses.replace(w, nb=300, nl=480, ng=81))
+    M = oracle.Model(g)
+    u = M.u_from_setpoints(g["vg0"], g["pg0"])
+    x = oracle.solve_pf(M, u, g["pd"], g["qd"]).x
+    ep = gridgen.eval_point(g, seed=seed + 1000)
+    lo, hi = gridgen.constraint_bounds(g)
+    return g, M, u, x, ep, lo, hi
+
+
+def test_tracking_multiplier_update_vanishes_inside_bounds():
+    """y_new = y + rho sigma (c - clip(c + y/(rho sigma))): for constraints
+    whose shifted value stays strictly inside the bounds, y_new = 0."""
+    g, M, u, x, ep, lo, hi = _tracking_setup()
+    P = oracle.Point.from_dict(ep)
+    fac = np.ones(g["nb"])
+    un, xn, yn, info = oracle.tracking_step(M, u, x, P.y, g["pd"], g["qd"], fac, P, lo, hi, delta=1e6)
+    c = M.constraints(xn, un, g["pd"], g["qd"])
+    z = c + P.y / (P.rho * P.sigma_c)
+    inside = (z > lo + 1e-9) & (z < hi - 1e-9)
+    assert inside.sum() > 0
+    assert np.max(np.abs(yn[inside])) < 1e-9
+    out = ~inside
+    assert np.allclose(yn[out], P.y[out] + P.rho * P.sigma_c[out] * (c[out] - np.clip(z[out], lo[out], hi[out])))
+
+
+def test_tracking_huge_shift_keeps_the_control():
+    """With delta -> infinity the Newton step vanishes: u stays put and the
+    first trial is accepted."""
+    g, M, u, x, ep, lo, hi = _tracking_setup()
+    P = oracle.Point.from_dict(ep)
+    fac = np.ones(g["nb"])
+    ulo, uhi = M.u_bounds()
+    un, xn, yn, info = oracle.tracking_step(M, u, x, P.y, g["pd"], g["qd"], fac, P, lo, hi, delta=1e15)
+    assert info["accepted"] == 0
+    assert np.allclose(un, np.clip(u, ulo, uhi), atol=1e-9)
+
+
+def test_tracking_step_is_a_descent_direction():
+    """The shifted Newton step d = -(H + delta I)^{-1} grad has grad.d < 0."""
+    g, M, u, x, ep, lo, hi = _tracking_setup()
+    P = oracle.Point.from_dict(ep)
+    fac = gridgen.tracking_factors(100, 1, g["nb"])[0]
+    H0 = None
+    un, xn, yn, info = oracle.tracking_step(M, u, x, P.y, g["pd"], g["qd"], fac, P, lo, hi, delta=1e3)
+    assert info["info"] == 0
+    assert float(info["grad"] @ info["step"]) < 0
