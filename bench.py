@@ -25,6 +25,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6
 
 
 def parse():
@@ -124,18 +125,7 @@ def main():
     ms_step = (t1 - t0) * 1e3 / steps
     value = nu * steps / (t1 - t0)
 
-    # dominant kernel: batched level-scheduled triangular solves
-    S = grid.structure()
-    nnz_strict = (S["nnz_lu"] - nx) // 2
-    bytes_per_launch = 12 * nnz_strict + 6 * nx + 8 * (nx + 1) + 16 * nx * B
-    ms_trsv, n_trsv = prof["trsv_batch"]
-    avg_us = ms_trsv * 1e3 / max(n_trsv, 1)
-    achieved = bytes_per_launch / (avg_us * 1e-6) / 1e9
-    # launches of one reduced Hessian: 4 per batch
-    cols_per_launch = [min(B, nu - j0) for j0 in range(0, nu, B)]
-    alg_bytes = sum(12 * nnz_strict + 6 * nx + 8 * (nx + 1) + 16 * nx * c for c in cols_per_launch) * 4
-    achieved_avg = alg_bytes / (ms_trsv * 1e-3 / steps) / 1e9
-
+    rl, rl_all = roofline(g, pr, prof, B, steps)
     out = {
         "metric": "reduced-Hessian HVPs/sec and full reduced-Hessian time, 9241-bus grid, FP64",
         "value": round(value, 1),
@@ -153,11 +143,8 @@ def main():
                                f"m={pr.m}; step = warm power flow at perturbed loads + AL value + "
                                f"reduced gradient + {nu} HVPs + Cholesky step",
                    "hvp_batch": B, "parallelism": "single GPU"},
-        "roofline": {"bound": "hbm", "achieved": round(achieved_avg, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(achieved_avg / HBM_PEAK_GBS, 4), "traffic": None,
-                     "kernel": "k_trsv_batch (level-scheduled triangular solves, all 4 per batch)",
-                     "avg_launch_us": round(avg_us, 2),
-                     "bytes_per_launch_full_batch": int(bytes_per_launch)},
+        "roofline": rl,
+        "roofline_other_kernels": rl_all,
         "breakdown_ms_per_step": {k: round(v[0] / steps, 4) for k, v in prof.items()},
         "cholesky_ok": ok,
         "cholesky_shift": delta,
@@ -200,6 +187,73 @@ def main():
         out["cpu_baseline"] = cpu_baseline(g, ep, a.cpu_sample_cols)
 
     print(json.dumps(out), flush=True)
+
+
+def roofline(g, pr, prof, B, steps):
+    """Roofline figures of the batched kernels from the library's HIP-event
+    timings (events on the launch stream around each launch).
+
+    Algorithmic bytes per launch (each factor entry read once, 8 B value +
+    4 B column index; row pointers 4 B; diagonal 8 B for the non-unit
+    factor; every right-hand-side row read and written once, 16 B):
+      pack solve (k_pack_solve_s), rows [0, t0) of one factor, ncols columns:
+        forward  12 nnz(L strict, pack rows) + 4 (t0 + 1) + 16 t0 ncols
+        backward 12 nnz(U strict, pack rows) + 4 (t0 + 1) + 8 t0 + 16 t0 ncols
+        (with J_x^T the unit and non-unit factors swap; the average of the
+        two launches is the same);
+      top solve (k_top_dense), rows [t0, n_x) of both factors:
+        12 nnz(L, top rows, pack columns) + 8 n_top^2 (dense top block
+        L\\U) + 8 ncols #(distinct pack columns read) + 16 n_top ncols.
+    The dense Cholesky group is priced in FLOPs: n_u^3/3 + 2 n_u^2."""
+    import numpy as np
+    from paper_2110_02590_amd import binding
+    info = binding.presolve_info(g)
+    _, ptr, col = binding.presolve_pattern(g)
+    nx, ntop = info["nx"], info["ntop"]
+    t0 = nx - ntop
+    rows = np.repeat(np.arange(nx), np.diff(ptr))
+    pack = rows < t0
+    nnz_lp = int(np.sum(pack & (col < rows)))
+    nnz_up = int(np.sum(pack & (col > rows)))
+    topl = (rows >= t0) & (col < t0)
+    nnz_tl = int(np.sum(topl))
+    ncol_tl = int(np.unique(col[topl]).size)
+    nu = pr.nu
+    cols = [min(B, nu - j0) for j0 in range(0, nu, B)]   # one reduced Hessian
+    # per batch: two solve pairs (J_x and J_x^T), each one forward and one
+    # backward pack launch and one top launch
+    pack_bytes = sum(2 * (12 * (nnz_lp + nnz_up) + 8 * (t0 + 1) + 8 * t0 + 32 * t0 * c) for c in cols)
+    top_bytes = sum(2 * (12 * nnz_tl + 8 * ntop * ntop + 8 * c * ncol_tl + 16 * ntop * c) for c in cols)
+    pack_launches, top_launches = 4 * len(cols), 2 * len(cols)
+    chol_flops = nu ** 3 / 3.0 + 2.0 * nu * nu
+    ent = {}
+
+    def add(name, kernel, cls, alg_total, launches_per_step, bound, peak, unit, per_unit):
+        ms, n = prof[cls]
+        if n == 0:
+            return
+        avg_us = ms * 1e3 / n
+        per_launch = alg_total / launches_per_step
+        achieved = per_launch / (avg_us * 1e-6) / (1e9 if unit == "GB/s" else 1e12)
+        ent[name] = {"bound": bound, "achieved": round(achieved, 2), "peak": peak, "unit": unit,
+                     "frac": round(achieved / peak, 5), "traffic": None, "kernel": kernel,
+                     "avg_launch_us": round(avg_us, 2), "launches_per_step": n // steps,
+                     "ms_per_step": round(ms / steps, 3),
+                     "algorithmic_per_launch": round(per_launch, 1), "per_unit": per_unit}
+
+    add("pack_solve", "k_pack_solve_s (batched triangular solves in the subtree packs)", "pack_batch",
+        pack_bytes, pack_launches, "hbm", HBM_PEAK_GBS, "GB/s",
+        f"bytes; nnz(L_pack)={nnz_lp}, nnz(U_pack)={nnz_up}, t0={t0}, B={B}")
+    add("top_solve", "k_top_dense (batched triangular solves of the top rows)", "top_batch",
+        top_bytes, top_launches, "hbm", HBM_PEAK_GBS, "GB/s",
+        f"bytes; nnz(L_top,pack cols)={nnz_tl}, n_top={ntop}, distinct pack cols={ncol_tl}, B={B}")
+    add("cholesky", "dense Cholesky group (k_symmetrize, k_blk_*<true>, k_chol_solve)", "dense",
+        chol_flops, 1, "mfma", FP64_PEAK_TFLOPS, "TFLOP/s", f"flops n_u^3/3 + 2 n_u^2, n_u={nu}")
+    if not ent:
+        return None, {}
+    dom = max(ent, key=lambda k: ent[k]["ms_per_step"])
+    return ent[dom], {k: v for k, v in ent.items() if k != dom}
+
 
 
 def tracking_bench(a):

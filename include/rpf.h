@@ -191,13 +191,15 @@ int rpf_track_step(rpf_grid* grid, double* u, double* x, double* y, const double
                    int32_t max_halvings, double tol, int32_t* status, rpf_stream_t stream);
 
 /* Kernel timing with HIP events recorded on the launch stream, per kernel
- * class: 0 batched triangular solves (more than one right-hand side),
- * 1 single right-hand-side triangular solves, 2 LU refactorization,
- * 3 sparse products of the Hessian batches, 4 dense Cholesky kernels.
+ * class: 0 batched triangular solves inside the independent subtree packs
+ * (k_pack_solve_s, more than one right-hand side), 1 single right-hand-side
+ * triangular solves (all parts), 2 LU refactorization, 3 sparse products of
+ * the Hessian batches, 4 dense Cholesky kernels, 5 batched triangular solves
+ * of the top (separator) rows (k_top_dense, more than one right-hand side).
  * rpf_profile_read waits for the recorded events, returns the summed
  * milliseconds and launch counts per class (host arrays [RPF_PROF_CLASSES])
  * and clears them when reset != 0. */
-#define RPF_PROF_CLASSES 5
+#define RPF_PROF_CLASSES 6
 int rpf_profile_enable(rpf_grid* grid, int32_t enable);
 int rpf_profile_read(rpf_grid* grid, double* ms, int64_t* launches, int32_t reset);
 

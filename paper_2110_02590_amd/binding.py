@@ -187,7 +187,7 @@ class Grid:
                 "nnz_ju", "nnz_k", "nnz_g", "max_batch"]
         return dict(zip(keys, out.tolist()))
 
-    PROF_CLASSES = ["trsv_batch", "trsv_single", "refactor", "spmm", "dense"]
+    PROF_CLASSES = ["pack_batch", "trsv_single", "refactor", "spmm", "dense", "top_batch"]
 
     def profile(self, enable: bool = True):
         _check(lib().rpf_profile_enable(self._h, 1 if enable else 0))

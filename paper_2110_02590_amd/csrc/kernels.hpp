@@ -341,6 +341,7 @@ __global__ void __launch_bounds__(256) k_top_dense(int t0, int n, const int32_t*
   if (skip && *skip) return;
   extern __shared__ double xs[];
   __shared__ double mt[CB][33];
+  __shared__ double dt[CB][CB + 1];
   const int s = n - t0;
   const int c0 = blockIdx.x * tw;
   const int t = threadIdx.x;
@@ -362,11 +363,15 @@ __global__ void __launch_bounds__(256) k_top_dense(int t0, int n, const int32_t*
   for (int b0 = 0; b0 < s; b0 += CB) {
     const int nb = min(CB, s - b0);
     top_block_update(M, s, b0, nb, 0, b0, xs, tw, mt);
+    for (int e = t; e < CB * CB; e += blockDim.x) {
+      const int r = e >> 6, j = e & 63;
+      dt[r][j] = (r < nb && j < nb) ? M[(size_t)(b0 + r) * s + b0 + j] : 0.0;
+    }
+    __syncthreads();
     if (wv < tw) {
       double mr[CB];
-      const double* Mr = M + (size_t)(b0 + min(lane, nb - 1)) * s + b0;
 #pragma unroll
-      for (int j = 0; j < CB; ++j) mr[j] = j < nb ? Mr[j] : 0.0;
+      for (int j = 0; j < CB; ++j) mr[j] = dt[lane][j];
       for (int c = wv; c < tw; c += nwv) {
         double v = lane < nb ? xs[(b0 + lane) * tw + c] : 0.0;
 #pragma unroll
@@ -387,11 +392,15 @@ __global__ void __launch_bounds__(256) k_top_dense(int t0, int n, const int32_t*
     for (int b1 = s; b1 > 0; b1 -= CB) {
       const int b0 = max(0, b1 - CB), nb = b1 - b0;
       top_block_update(M, s, b0, nb, b1, s, xs, tw, mt);
+      for (int e = t; e < CB * CB; e += blockDim.x) {
+        const int r = e >> 6, j = e & 63;
+        dt[r][j] = (r < nb && j < nb) ? M[(size_t)(b0 + r) * s + b0 + j] : 0.0;
+      }
+      __syncthreads();
       if (wv < tw) {
         double mr[CB];
-        const double* Mr = M + (size_t)(b0 + min(lane, nb - 1)) * s + b0;
 #pragma unroll
-        for (int j = 0; j < CB; ++j) mr[j] = j < nb ? Mr[j] : 0.0;
+        for (int j = 0; j < CB; ++j) mr[j] = dt[lane][j];
         for (int c = wv; c < tw; c += nwv) {
           double v = lane < nb ? xs[(b0 + lane) * tw + c] : 0.0;
 #pragma unroll
@@ -906,13 +915,17 @@ __global__ void __launch_bounds__(64) k_blk_diag(int n, int b0, double* __restri
     const int32_t* __restrict__ skip) {
   if (skip && *skip) return;
   __shared__ double bc[CB];
+  __shared__ double tile[CB][CB + 1];
   if (info[0] != 0) return;
   const int nb = min(CB, n - b0);
   const int i = threadIdx.x;  // one wavefront: lane i owns row i in registers
+  // coalesced load (lanes over columns) through LDS
+  for (int rr = 0; rr < nb; ++rr) tile[rr][i] = i < nb ? A[(size_t)(b0 + rr) * n + b0 + i] : 0.0;
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
   double r[CB];
-  const double* Ar = A + (size_t)(b0 + min(i, nb - 1)) * n + b0;
 #pragma unroll
-  for (int j = 0; j < CB; ++j) r[j] = (i < nb && j < nb && (!CHOL || j <= i)) ? Ar[j] : 0.0;
+  for (int j = 0; j < CB; ++j) r[j] = (i < nb && j < nb && (!CHOL || j <= i)) ? tile[i][j] : 0.0;
 #pragma unroll
   for (int j = 0; j < CB; ++j) {
     if (j < nb) {
@@ -947,12 +960,12 @@ __global__ void __launch_bounds__(64) k_blk_diag(int n, int b0, double* __restri
       __builtin_amdgcn_wave_barrier();
     }
   }
-  if (i < nb) {
-    double* Aw = A + (size_t)(b0 + i) * n + b0;
 #pragma unroll
-    for (int j = 0; j < CB; ++j)
-      if (j < nb && (!CHOL || j <= i)) Aw[j] = r[j];
-  }
+  for (int j = 0; j < CB; ++j) tile[i][j] = r[j];
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  for (int rr = 0; rr < nb; ++rr)
+    if (i < nb && (!CHOL || i <= rr)) A[(size_t)(b0 + rr) * n + b0 + i] = tile[rr][i];
 }
 
 // Panels: wave task t < rows below: row r solves x U11 = a (LU) or
@@ -1062,6 +1075,7 @@ __global__ void __launch_bounds__(256) k_chol_solve(int n, const double* __restr
                                                     double* __restrict__ work, const int32_t* __restrict__ info) {
   if (info[0] != 0) return;
   __shared__ double part[CB][17];
+  __shared__ double tri[CB][CB + 1];
   const int t = threadIdx.x;
   const int rr = t >> 4, sl = t & 15;   // row (of 16 per pass), slice
   double* yv = work;
@@ -1085,12 +1099,15 @@ __global__ void __launch_bounds__(256) k_chol_solve(int n, const double* __restr
       }
       part[r][sl] = a0 + a1;
     }
+    for (int e = t; e < CB * CB; e += blockDim.x) {
+      const int r = e >> 6, j = e & 63;
+      tri[r][j] = (r < nb && j < nb) ? L[(size_t)(b0 + r) * n + b0 + j] : 0.0;
+    }
     __syncthreads();
     if (t < 64) {
       double lr[CB];
-      const double* Lr = L + (size_t)(b0 + min(t, nb - 1)) * n + b0;
 #pragma unroll
-      for (int j = 0; j < CB; ++j) lr[j] = j < nb ? Lr[j] : 0.0;
+      for (int j = 0; j < CB; ++j) lr[j] = tri[t][j];
       double v = 0.0;
       if (t < nb) {
         v = -rhs[b0 + t];
@@ -1127,12 +1144,16 @@ __global__ void __launch_bounds__(256) k_chol_solve(int n, const double* __restr
       }
       part[r][sl] = a0 + a1;
     }
+    for (int e = t; e < CB * CB; e += blockDim.x) {
+      const int r = e >> 6, j = e & 63;
+      tri[r][j] = (r < nb && j < nb) ? L[(size_t)(b0 + r) * n + b0 + j] : 0.0;
+    }
     __syncthreads();
     if (t < 64) {
       // lane t holds column t of the triangle: L[b0 + k][b0 + t]
       double lc[CB];
 #pragma unroll
-      for (int k = 0; k < CB; ++k) lc[k] = (k < nb && t < nb) ? L[(size_t)(b0 + k) * n + b0 + t] : 0.0;
+      for (int k = 0; k < CB; ++k) lc[k] = tri[k][t];
       double v = 0.0;
       if (t < nb) {
         v = yv[b0 + t];

@@ -288,16 +288,22 @@ void setup(rpf_grid* h) {
         break;
       }
     if (h->tw_pack == 0) throw std::runtime_error("a pack of subtrees does not fit in LDS");
+    // the dense top solve also holds two static tiles (about 50 KB)
+    const size_t top_static = 52 * 1024;
     h->tw_top = 16;
-    while (h->tw_top > 1 && (size_t)P.ntop * h->tw_top * 8 > h->lds_limit) h->tw_top /= 2;
-    if ((size_t)P.ntop * 8 > h->lds_limit) throw std::runtime_error("top part of the elimination tree too large for LDS");
+    while (h->tw_top > 1 && (size_t)P.ntop * h->tw_top * 8 + top_static > h->lds_limit) h->tw_top /= 2;
+    if ((size_t)P.ntop * 8 + top_static > h->lds_limit)
+      throw std::runtime_error("top part of the elimination tree too large for LDS");
     // allow the dynamic LDS sizes above the default for the solve kernels
     const int ldsmax = (int)h->lds_limit;
     auto allow = [&](const void* f) {
       HIPCHK(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, ldsmax));
     };
-    allow((const void*)k_top_dense<true, true, false>);
-    allow((const void*)k_top_dense<false, true, true>);
+    auto allow_top = [&](const void* f) {
+      HIPCHK(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, ldsmax - (int)top_static));
+    };
+    allow_top((const void*)k_top_dense<true, true, false>);
+    allow_top((const void*)k_top_dense<false, true, true>);
 #define RPF_ALLOW_PACK(TW)                                  \
   allow((const void*)k_pack_solve_s<TW, true, true>);       \
   allow((const void*)k_pack_solve_s<TW, true, false>);      \
@@ -501,7 +507,7 @@ void solve_pair(rpf_grid* h, bool transposed, double* X, int ld, int ncols, doub
       kern<<<ct, 256, shm, s>>>(P.t0, P.nx, h->lo_split, h->lu_ptr, h->lu_col, val, M, X, ld, ncols, scale, twt, skip);
     }
     LAUNCHCHK();
-    if (h->prof_on) h->prof_end(cls, pi, s);
+    if (h->prof_on) h->prof_end(cls == 0 ? 5 : cls, pi, s);
   }
   pack_solve_any(h, twp, false, !fwd_unit, val, X, ld, ncols, 1.0, cls, s, skip);
 }
