@@ -165,7 +165,10 @@ int rpf_reduced_hessian(rpf_grid* grid, double* H, int32_t batch, rpf_stream_t s
  *   (upper triangle left as K).  diag [n] or NULL, rhs [n]: device, read.
  *   step [n]: device, out (left unchanged when info != 0).
  *   info [1]: device int32, out: 0, or the 1-based column whose pivot was
- *   not positive. */
+ *   not positive, or -1 when a workgroup of the triangular solves gave up
+ *   waiting for another block (the solves are spread over one workgroup per
+ *   block of 64 rows that wait for each other with a bounded spin; -1 is
+ *   not expected on an idle or shared device and marks step as invalid). */
 int rpf_factor_solve(rpf_grid* grid, int32_t n, double* Kmat, const double* diag, double delta,
                      const double* rhs, double* step, int32_t* info, rpf_stream_t stream);
 

@@ -193,8 +193,8 @@ class Grid:
         _check(lib().rpf_profile_enable(self._h, 1 if enable else 0))
 
     def profile_read(self, reset: bool = True) -> dict:
-        ms = np.zeros(5, dtype=np.float64)
-        n = np.zeros(5, dtype=np.int64)
+        ms = np.zeros(len(self.PROF_CLASSES), dtype=np.float64)
+        n = np.zeros(len(self.PROF_CLASSES), dtype=np.int64)
         _check(lib().rpf_profile_read(self._h, ms.ctypes.data, n.ctypes.data, 1 if reset else 0))
         return {k: (float(ms[i]), int(n[i])) for i, k in enumerate(self.PROF_CLASSES)}
 

@@ -186,13 +186,16 @@ __global__ void k_reduce_final(int n, const double* __restrict__ in, double* __r
 // per row with the row staged in LDS: for each L entry (i, k), k ascending,
 // l_ik = a_ik / u_kk and a_ij -= l_ik u_kj for the U entries of row k
 // (target positions precomputed).  Only L entries in [ptr[i], pend) are
-// eliminated.  With check, a pivot |u_ii| <= pivtol max_j |a_ij| records
-// row + 1 in status[0].
+// eliminated.  Rows k are final when row i starts, so their data (pivot
+// reciprocal rdg[k] = 1 / u_kk, U values, targets) are loaded one step
+// ahead; only the row's own entries in LDS form the dependency chain.  The
+// finished row stores 1 / u_ii in rdg[i].  With check, a pivot
+// |u_ii| <= pivtol max_j |a_ij| records row + 1 in status[0].
 __device__ inline void rf_row(int i, int pend, bool check, const int32_t* __restrict__ ptr,
                               const int32_t* __restrict__ col, const int32_t* __restrict__ diag,
                               const int64_t* __restrict__ upd_ptr, const int32_t* __restrict__ upd_tgt,
-                              double* __restrict__ a, double* __restrict__ w, double pivtol,
-                              int32_t* __restrict__ status) {
+                              double* __restrict__ a, double* __restrict__ rdg, double* __restrict__ w,
+                              double pivtol, int32_t* __restrict__ status) {
   const int lane = threadIdx.x & 63;
   const int p0 = ptr[i], pdg = diag[i], p1 = ptr[i + 1];
   double amax = 0.0;
@@ -203,24 +206,40 @@ __device__ inline void rf_row(int i, int pend, bool check, const int32_t* __rest
   }
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   __builtin_amdgcn_wave_barrier();
-  for (int p = p0; p < pend; ++p) {
-    const int k = col[p];
-    const int dk = diag[k];
-    const double l = w[p - p0] / a[dk];
-    const int64_t u0 = upd_ptr[p], nu = upd_ptr[p + 1] - u0;
-    for (int64_t t = lane; t < nu; t += 64) {
-      const int tg = upd_tgt[u0 + t] - p0;
-      w[tg] -= l * a[dk + 1 + (int)t];
+  // step data of entry p: U row of k = col[p] starts at diag[k] + 1
+  int n_dk = 0, n_nu = 0, n_tg = 0;
+  int64_t n_u0 = 0;
+  double n_rk = 0.0, n_av = 0.0;
+  auto fetch = [&](int pp) {
+    const int k = col[pp];
+    n_dk = diag[k];
+    n_rk = rdg[k];
+    n_u0 = upd_ptr[pp];
+    n_nu = (int)(upd_ptr[pp + 1] - n_u0);
+    if (lane < n_nu) {
+      n_tg = upd_tgt[n_u0 + lane];
+      n_av = a[n_dk + 1 + lane];
     }
+  };
+  if (p0 < pend) fetch(p0);
+  for (int p = p0; p < pend; ++p) {
+    const int dk = n_dk, nu = n_nu, tg = n_tg;
+    const int64_t u0 = n_u0;
+    const double rk = n_rk, av = n_av;
+    if (p + 1 < pend) fetch(p + 1);
+    const double l = w[p - p0] * rk;
+    if (lane < nu) w[tg - p0] -= l * av;
+    for (int t = lane + 64; t < nu; t += 64) w[upd_tgt[u0 + t] - p0] -= l * a[dk + 1 + t];
     if (lane == 0) w[p - p0] = l;
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
   }
   for (int off = 32; off > 0; off >>= 1) amax = fmax(amax, __shfl_xor(amax, off, 64));
   for (int q = lane; q < p1 - p0; q += 64) a[p0 + q] = w[q];
-  if (check && lane == 0) {
+  if (lane == 0) {
     const double piv = w[pdg - p0];
-    if (!(fabs(piv) > pivtol * amax)) atomicCAS(status, 0, i + 1);
+    rdg[i] = 1.0 / piv;
+    if (check && !(fabs(piv) > pivtol * amax)) atomicCAS(status, 0, i + 1);
   }
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   __builtin_amdgcn_wave_barrier();
@@ -232,8 +251,8 @@ __global__ void k_rf_pack(const int32_t* __restrict__ flev, const int32_t* __res
                           const int32_t* __restrict__ frows, const int32_t* __restrict__ ptr,
                           const int32_t* __restrict__ col, const int32_t* __restrict__ diag,
                           const int64_t* __restrict__ upd_ptr, const int32_t* __restrict__ upd_tgt,
-                          double* __restrict__ a, int maxrow, double pivtol, int32_t* __restrict__ status,
-    const int32_t* __restrict__ skip) {
+                          double* __restrict__ a, double* __restrict__ rdg, int maxrow, double pivtol,
+                          int32_t* __restrict__ status, const int32_t* __restrict__ skip) {
   if (skip && *skip) return;
   extern __shared__ double lds[];
   const int wave = threadIdx.x >> 6, nwave = blockDim.x >> 6;
@@ -242,7 +261,7 @@ __global__ void k_rf_pack(const int32_t* __restrict__ flev, const int32_t* __res
   for (int lv = flev_off[q]; lv < flev_off[q + 1]; ++lv) {
     for (int r = flev[lv] + wave; r < flev[lv + 1]; r += nwave) {
       const int i = frows[r];
-      rf_row(i, diag[i], true, ptr, col, diag, upd_ptr, upd_tgt, a, w, pivtol, status);
+      rf_row(i, diag[i], true, ptr, col, diag, upd_ptr, upd_tgt, a, rdg, w, pivtol, status);
     }
     __syncthreads();
   }
@@ -252,15 +271,15 @@ __global__ void k_rf_pack(const int32_t* __restrict__ flev, const int32_t* __res
 __global__ void k_rf_top_ext(int t0, int n, const int32_t* __restrict__ lo_split, const int32_t* __restrict__ ptr,
                              const int32_t* __restrict__ col, const int32_t* __restrict__ diag,
                              const int64_t* __restrict__ upd_ptr, const int32_t* __restrict__ upd_tgt,
-                             double* __restrict__ a, int maxrow, int32_t* __restrict__ status,
-    const int32_t* __restrict__ skip) {
+                             double* __restrict__ a, double* __restrict__ rdg, int maxrow,
+                             int32_t* __restrict__ status, const int32_t* __restrict__ skip) {
   if (skip && *skip) return;
   extern __shared__ double lds[];
   const int wave = threadIdx.x >> 6, nwave = blockDim.x >> 6;
   double* w = lds + (size_t)wave * maxrow;
   const int i = t0 + blockIdx.x * nwave + wave;
   if (i >= n) return;
-  rf_row(i, lo_split[i], false, ptr, col, diag, upd_ptr, upd_tgt, a, w, 0.0, status);
+  rf_row(i, lo_split[i], false, ptr, col, diag, upd_ptr, upd_tgt, a, rdg, w, 0.0, status);
 }
 
 __global__ void k_fill_dbl(int64_t n, double* __restrict__ p, double v,
@@ -325,19 +344,116 @@ __device__ inline void top_block_update(const double* __restrict__ M, int s, int
   __syncthreads();
 }
 
-// Top part with its dense factor M (s x s, row-major): rows of the top
-// block after the pack contributions are subtracted; forward solve with the
-// lower part of M (unit or not), then with BWD the backward solve with its
-// upper part.  Blocks of CB rows: products with solved blocks by all
-// threads (one (row, column) pair each), the CB x CB triangle by one
-// wavefront per column (lane = row, its row of the triangle in registers).
-// 256 threads, tw columns per workgroup.
-template <bool FUNIT, bool BWD, bool BUNIT>
-__global__ void __launch_bounds__(256) k_top_dense(int t0, int n, const int32_t* __restrict__ lo_split,
-                                                   const int32_t* __restrict__ ptr, const int32_t* __restrict__ col,
-                                                   const double* __restrict__ fval, const double* __restrict__ M,
-                                                   double* __restrict__ X, int ld, int ncols, double scale, int tw,
-    const int32_t* __restrict__ skip) {
+// Right-hand side of the top rows: X[i, c] <- scale X[i, c] - sum_p f(p)
+// X[col(p), c] over the lower entries of top row i in pack columns
+// ([ptr[i], lo_split[i])).  Reads only pack rows, so in place.  One thread
+// per (row, column), four partial sums.
+__global__ void k_top_rhs(int t0, int n, const int32_t* __restrict__ lo_split, const int32_t* __restrict__ ptr,
+                          const int32_t* __restrict__ col, const double* __restrict__ fval,
+                          double* __restrict__ X, int ld, int ncols, double scale,
+                          const int32_t* __restrict__ skip) {
+  if (skip && *skip) return;
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = t0 + blockIdx.y * blockDim.y + threadIdx.y;
+  if (i >= n || c >= ncols) return;
+  double q0 = 0.0, q1 = 0.0, q2 = 0.0, q3 = 0.0;
+  const int p1 = lo_split[i];
+  int p = ptr[i];
+  for (; p + 3 < p1; p += 4) {
+    const int j0 = col[p], j1 = col[p + 1], j2 = col[p + 2], j3 = col[p + 3];
+    q0 += fval[p] * X[(size_t)j0 * ld + c];
+    q1 += fval[p + 1] * X[(size_t)j1 * ld + c];
+    q2 += fval[p + 2] * X[(size_t)j2 * ld + c];
+    q3 += fval[p + 3] * X[(size_t)j3 * ld + c];
+  }
+  for (; p < p1; ++p) q0 += fval[p] * X[(size_t)col[p] * ld + c];
+  X[(size_t)i * ld + c] = scale * X[(size_t)i * ld + c] - ((q0 + q1) + (q2 + q3));
+}
+
+// Inverses of the CB x CB diagonal blocks of a dense factor M (s x s,
+// row-major, lower part L, upper part U): blockIdx.y = 0 inverts the lower
+// triangle of block blockIdx.x (unit diagonal if lower_unit), 1 the upper
+// triangle (unit if upper_unit).  Output dinv[(kb * 2 + part) * CB * CB],
+// row-major CB x CB, zero outside the block's nb x nb corner.  One
+// wavefront; lane c computes column c of the inverse by substitution.
+__global__ void __launch_bounds__(64) k_top_diag_inv(int s, const double* __restrict__ M, double* __restrict__ dinv,
+                                                     int lower_unit, int upper_unit,
+                                                     const int32_t* __restrict__ skip) {
+  if (skip && *skip) return;
+  __shared__ double T[CB][CB + 1];
+  __shared__ double Z[CB][CB + 1];
+  const int kb = blockIdx.x, part = blockIdx.y;
+  const int b0 = kb * CB, nb = min(CB, s - b0);
+  const int c = threadIdx.x;
+  for (int e = c; e < CB * CB; e += 64) {
+    const int r = e >> 6, j = e & 63;
+    T[r][j] = (r < nb && j < nb) ? M[(size_t)(b0 + r) * s + b0 + j] : 0.0;
+  }
+  __syncthreads();
+  if (part == 0) {
+    for (int i = 0; i < CB; ++i) {
+      double acc = (i == c) ? 1.0 : 0.0;
+      for (int j = 0; j < i; ++j) acc -= T[i][j] * Z[j][c];
+      if (!lower_unit && i < nb) acc /= T[i][i];
+      Z[i][c] = (i < nb && c < nb) ? acc : 0.0;
+    }
+  } else {
+    for (int i = CB - 1; i >= 0; --i) {
+      double acc = (i == c) ? 1.0 : 0.0;
+      for (int j = i + 1; j < CB; ++j) acc -= T[i][j] * Z[j][c];
+      if (!upper_unit && i < nb) acc /= T[i][i];
+      Z[i][c] = (i < nb && c < nb) ? acc : 0.0;
+    }
+  }
+  __syncthreads();
+  double* out = dinv + (size_t)(kb * 2 + part) * CB * CB;
+  for (int e = c; e < CB * CB; e += 64) out[e] = Z[e >> 6][e & 63];
+}
+
+// xs[b0 + r][c] <- sum_j D[r][j] xs[b0 + j][c] for the nb rows of one block
+// (D: a CB x CB inverse diagonal block staged through LDS).
+__device__ inline void top_diag_apply(const double* __restrict__ D, int b0, int nb, double* xs, int tw,
+                                      double (*dt)[CB + 1]) {
+  const int t = threadIdx.x;
+  for (int e = t; e < CB * CB; e += blockDim.x) dt[e >> 6][e & 63] = D[e];
+  __syncthreads();
+  const int npair = nb * tw;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int e = t + k * 256;
+    if (e < npair) {
+      const int r = e / tw, c = e - r * tw;
+      double a0 = 0.0, a1 = 0.0;
+      int j = 0;
+      for (; j + 1 < nb; j += 2) {
+        a0 += dt[r][j] * xs[(b0 + j) * tw + c];
+        a1 += dt[r][j + 1] * xs[(b0 + j + 1) * tw + c];
+      }
+      if (j < nb) a0 += dt[r][j] * xs[(b0 + j) * tw + c];
+      acc[k] = a0 + a1;
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int e = t + k * 256;
+    if (e < npair) {
+      const int r = e / tw, c = e - r * tw;
+      xs[(b0 + r) * tw + c] = acc[k];
+    }
+  }
+  __syncthreads();
+}
+
+// Dense forward and backward solves of the top rows (after k_top_rhs) with
+// the factor M (s x s, row-major) and its inverse diagonal blocks dinv:
+// per block of CB rows, subtract the products with the solved blocks
+// (top_block_update), then multiply by the block's inverse.  The tw columns
+// of one workgroup stay in LDS.  256 threads, tw <= 16.
+__global__ void __launch_bounds__(256) k_top_dense(int t0, int n, const double* __restrict__ M,
+                                                   const double* __restrict__ dinv, double* __restrict__ X,
+                                                   int ld, int ncols, int tw, const int32_t* __restrict__ skip) {
   if (skip && *skip) return;
   extern __shared__ double xs[];
   __shared__ double mt[CB][33];
@@ -345,78 +461,21 @@ __global__ void __launch_bounds__(256) k_top_dense(int t0, int n, const int32_t*
   const int s = n - t0;
   const int c0 = blockIdx.x * tw;
   const int t = threadIdx.x;
-  // contributions of the final pack rows (sparse, independent)
   for (int e = t; e < s * tw; e += blockDim.x) {
     const int r = e / tw, c = e - r * tw;
-    const int i = t0 + r;
-    double acc = 0.0;
-    if (c0 + c < ncols) {
-      acc = scale * X[(size_t)i * ld + c0 + c];
-      for (int p = ptr[i]; p < lo_split[i]; ++p) acc -= fval[p] * X[(size_t)col[p] * ld + c0 + c];
-    }
-    xs[e] = acc;
+    xs[e] = (c0 + c < ncols) ? X[(size_t)(t0 + r) * ld + c0 + c] : 0.0;
   }
   __syncthreads();
-  const int wv = t >> 6, lane = t & 63;
-  const int nwv = blockDim.x >> 6;
-  // forward
-  for (int b0 = 0; b0 < s; b0 += CB) {
+  for (int b0 = 0, kb = 0; b0 < s; b0 += CB, ++kb) {
     const int nb = min(CB, s - b0);
     top_block_update(M, s, b0, nb, 0, b0, xs, tw, mt);
-    for (int e = t; e < CB * CB; e += blockDim.x) {
-      const int r = e >> 6, j = e & 63;
-      dt[r][j] = (r < nb && j < nb) ? M[(size_t)(b0 + r) * s + b0 + j] : 0.0;
-    }
-    __syncthreads();
-    if (wv < tw) {
-      double mr[CB];
-#pragma unroll
-      for (int j = 0; j < CB; ++j) mr[j] = dt[lane][j];
-      for (int c = wv; c < tw; c += nwv) {
-        double v = lane < nb ? xs[(b0 + lane) * tw + c] : 0.0;
-#pragma unroll
-        for (int j = 0; j < CB; ++j) {
-          if (j < nb) {
-            double xj = __shfl(v, j, 64);
-            if (!FUNIT) xj /= __shfl(mr[j], j, 64);
-            if (lane == j) v = xj;
-            if (lane > j) v -= mr[j] * xj;
-          }
-        }
-        if (lane < nb) xs[(b0 + lane) * tw + c] = v;
-      }
-    }
-    __syncthreads();
+    top_diag_apply(dinv + (size_t)(kb * 2) * CB * CB, b0, nb, xs, tw, dt);
   }
-  if (BWD) {
-    for (int b1 = s; b1 > 0; b1 -= CB) {
-      const int b0 = max(0, b1 - CB), nb = b1 - b0;
-      top_block_update(M, s, b0, nb, b1, s, xs, tw, mt);
-      for (int e = t; e < CB * CB; e += blockDim.x) {
-        const int r = e >> 6, j = e & 63;
-        dt[r][j] = (r < nb && j < nb) ? M[(size_t)(b0 + r) * s + b0 + j] : 0.0;
-      }
-      __syncthreads();
-      if (wv < tw) {
-        double mr[CB];
-#pragma unroll
-        for (int j = 0; j < CB; ++j) mr[j] = dt[lane][j];
-        for (int c = wv; c < tw; c += nwv) {
-          double v = lane < nb ? xs[(b0 + lane) * tw + c] : 0.0;
-#pragma unroll
-          for (int j = CB - 1; j >= 0; --j) {
-            if (j < nb) {
-              double xj = __shfl(v, j, 64);
-              if (!BUNIT) xj /= __shfl(mr[j], j, 64);
-              if (lane == j) v = xj;
-              if (lane < j) v -= mr[j] * xj;
-            }
-          }
-          if (lane < nb) xs[(b0 + lane) * tw + c] = v;
-        }
-      }
-      __syncthreads();
-    }
+  const int nblk = (s + CB - 1) / CB;
+  for (int kb = nblk - 1; kb >= 0; --kb) {
+    const int b0 = kb * CB, nb = min(CB, s - b0);
+    top_block_update(M, s, b0, nb, b0 + nb, s, xs, tw, mt);
+    top_diag_apply(dinv + (size_t)(kb * 2 + 1) * CB * CB, b0, nb, xs, tw, dt);
   }
   for (int e = t; e < s * tw; e += blockDim.x) {
     const int r = e / tw, c = e - r * tw;
@@ -435,7 +494,7 @@ __host__ __device__ inline size_t pack_lds_bytes(int nr, int ne, int nlev, int t
 }
 
 template <int TW, bool FWD, bool UNIT>
-__global__ void k_pack_solve_s(const int32_t* __restrict__ pack_ptr, const int32_t* __restrict__ lev,
+__global__ void __launch_bounds__(256) k_pack_solve_s(const int32_t* __restrict__ pack_ptr, const int32_t* __restrict__ lev,
                                const int32_t* __restrict__ lev_off, const int32_t* __restrict__ lrows,
                                const int32_t* __restrict__ rp, const int32_t* __restrict__ epos,
                                const int16_t* __restrict__ ecol, const int32_t* __restrict__ diag,
@@ -477,22 +536,62 @@ __global__ void k_pack_solve_s(const int32_t* __restrict__ pack_ptr, const int32
       if (FWD) {
         acc = scale * X[(size_t)i * ld + c0 + c];
       } else {
-        acc = X[(size_t)i * ld + c0 + c];
-        for (int p = up_split[i]; p < ptr[i + 1]; ++p) acc -= val[p] * X[(size_t)col[p] * ld + c0 + c];
+        // solved top rows: independent products, two partial sums
+        double a0 = 0.0, a1 = 0.0;
+        const int p1 = ptr[i + 1];
+        int p = up_split[i];
+        for (; p + 1 < p1; p += 2) {
+          a0 += val[p] * X[(size_t)col[p] * ld + c0 + c];
+          a1 += val[p + 1] * X[(size_t)col[p + 1] * ld + c0 + c];
+        }
+        if (p < p1) a0 += val[p] * X[(size_t)col[p] * ld + c0 + c];
+        acc = X[(size_t)i * ld + c0 + c] - (a0 + a1);
       }
     }
     xs[e] = acc;
   }
   __syncthreads();
-  const int cc = t % TW, slot = t / TW, nslot = blockDim.x / TW;
+  // Level loop.  A level of nrow rows has nrow * TW (row, column) pairs; when
+  // that is below the block size, G = 2^lg lanes share one pair, each
+  // summing every G-th entry of the row (four partial sums, so the LDS loads
+  // of a row overlap), and the G partial sums are combined by butterfly
+  // shuffles inside the wavefront (groups of G lanes are aligned).
+  const int nthr = blockDim.x;
   for (int lv = 0; lv < nlev; ++lv) {
-    const int b1 = slev[lv + 1];
-    for (int k = slev[lv] + slot; k < b1; k += nslot) {
-      const int r = srow[k];
-      double acc = xs[r * TW + cc];
-      for (int e = srp[r]; e < srp[r + 1]; ++e) acc -= sv[e] * xs[scol[e] * TW + cc];
-      if (!UNIT) acc /= dg[r];
-      xs[r * TW + cc] = acc;
+    const int a = slev[lv], nrow = slev[lv + 1] - a;
+    const int pairs = nrow * TW;
+    int lg = 0;
+    while (lg < 6 && (pairs << (lg + 1)) <= nthr) ++lg;
+    const int G = 1 << lg;
+    const int work = pairs << lg;
+    for (int w0 = 0; w0 < work; w0 += nthr) {
+      const int w = w0 + t;
+      const bool act = w < work;
+      const int pair = w >> lg, seg = w & (G - 1);
+      const int rk = pair / TW;
+      const int cc = pair - rk * TW;
+      int r = 0;
+      double q0 = 0.0, q1 = 0.0, q2 = 0.0, q3 = 0.0;
+      if (act) {
+        r = srow[a + rk];
+        const int e1 = srp[r + 1];
+        int e = srp[r] + seg;
+        for (; e + 3 * G < e1; e += 4 * G) {
+          const int j0 = scol[e], j1 = scol[e + G], j2 = scol[e + 2 * G], j3 = scol[e + 3 * G];
+          q0 += sv[e] * xs[j0 * TW + cc];
+          q1 += sv[e + G] * xs[j1 * TW + cc];
+          q2 += sv[e + 2 * G] * xs[j2 * TW + cc];
+          q3 += sv[e + 3 * G] * xs[j3 * TW + cc];
+        }
+        for (; e < e1; e += G) q0 += sv[e] * xs[scol[e] * TW + cc];
+      }
+      double part = (q0 + q1) + (q2 + q3);
+      for (int o = G >> 1; o > 0; o >>= 1) part += __shfl_xor(part, o, 64);
+      if (act && seg == 0) {
+        double acc = xs[r * TW + cc] - part;
+        if (!UNIT) acc /= dg[r];
+        xs[r * TW + cc] = acc;
+      }
     }
     __syncthreads();
   }
@@ -911,61 +1010,88 @@ __global__ void k_symmetrize(int n, double* __restrict__ K, const double* __rest
 // pivot records base + (column + 1) in info[0]; later kernels return early.
 
 template <bool CHOL>
-__global__ void __launch_bounds__(64) k_blk_diag(int n, int b0, double* __restrict__ A, int32_t* __restrict__ info, int base,
-    const int32_t* __restrict__ skip) {
+__global__ void __launch_bounds__(256) k_blk_diag(int n, int b0, double* __restrict__ A, int32_t* __restrict__ info,
+                                                  int base, const int32_t* __restrict__ skip) {
   if (skip && *skip) return;
-  __shared__ double bc[CB];
   __shared__ double tile[CB][CB + 1];
+  __shared__ double colb[2][CB];
+  __shared__ double rowb[2][CB];
   if (info[0] != 0) return;
   const int nb = min(CB, n - b0);
-  const int i = threadIdx.x;  // one wavefront: lane i owns row i in registers
-  // coalesced load (lanes over columns) through LDS
-  for (int rr = 0; rr < nb; ++rr) tile[rr][i] = i < nb ? A[(size_t)(b0 + rr) * n + b0 + i] : 0.0;
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  double r[CB];
+  const int t = threadIdx.x;
+  // coalesced load through LDS; outside the nb x nb corner an identity
+  for (int e = t; e < CB * CB; e += 256) {
+    const int r = e >> 6, c = e & 63;
+    tile[r][c] = (r < nb && c < nb) ? A[(size_t)(b0 + r) * n + b0 + c] : (r == c ? 1.0 : 0.0);
+  }
+  __syncthreads();
+  // thread (tr, tc) holds rows 4 tr .. 4 tr + 3, columns 4 tc .. 4 tc + 3
+  const int tr = t >> 4, tc = t & 15;
+  double a[4][4];
 #pragma unroll
-  for (int j = 0; j < CB; ++j) r[j] = (i < nb && j < nb && (!CHOL || j <= i)) ? tile[i][j] : 0.0;
+  for (int p = 0; p < 4; ++p)
 #pragma unroll
-  for (int j = 0; j < CB; ++j) {
-    if (j < nb) {
-      const double d = __shfl(r[j], j, 64);
-      const bool ok = CHOL ? (d > 0.0) : (fabs(d) > 0.0 && isfinite(d));
-      if (!ok) {
-        if (i == 0) info[0] = base + b0 + j + 1;
-        return;
-      }
-      const double piv = CHOL ? sqrt(d) : d;
-      double lij = 0.0;
-      if (i > j && i < nb) {
-        lij = r[j] / piv;
-        r[j] = lij;
-      }
-      if (CHOL && i == j) r[j] = piv;
-      // broadcast column j of L (Cholesky) or row j of U (LU) through LDS
-      if (CHOL) {
-        bc[i] = lij;
-      } else if (i == j) {
+    for (int q = 0; q < 4; ++q) a[p][q] = tile[4 * tr + p][4 * tc + q];
+  // right-looking elimination, one barrier per pivot: the owners of column
+  // j (and, for LU, row j) publish it in a double-buffered LDS vector, every
+  // thread updates its 16 entries
+  for (int j = 0; j < nb; ++j) {
+    const int buf = j & 1, jt = j >> 2, jq = j & 3;
+    if (tc == jt) {
 #pragma unroll
-        for (int c = 0; c < CB; ++c) bc[c] = r[c];
-      }
-      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      if (i > j && i < nb) {
+      for (int p = 0; p < 4; ++p) colb[buf][4 * tr + p] = a[p][jq];
+    }
+    if (!CHOL && tr == jt) {
 #pragma unroll
-        for (int c = j + 1; c < CB; ++c)
-          if (c < nb && (!CHOL || c <= i)) r[c] -= lij * bc[c];
+      for (int q = 0; q < 4; ++q) rowb[buf][4 * tc + q] = a[jq][q];
+    }
+    __syncthreads();
+    const double d = colb[buf][j];
+    const bool ok = CHOL ? (d > 0.0 && isfinite(d)) : (fabs(d) > 0.0 && isfinite(d));
+    if (!ok) {  // same d in every thread: uniform exit
+      if (t == 0) info[0] = base + b0 + j + 1;
+      return;
+    }
+    const double piv = CHOL ? sqrt(d) : d;
+    const double rp = 1.0 / piv;
+    double l[4], u[4];
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+      const int r = 4 * tr + p;
+      l[p] = r > j ? colb[buf][r] * rp : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int c = 4 * tc + q;
+      u[q] = c > j ? (CHOL ? colb[buf][c] * rp : rowb[buf][c]) : 0.0;
+    }
+#pragma unroll
+    for (int p = 0; p < 4; ++p)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) a[p][q] -= l[p] * u[q];
+    if (tc == jt) {
+#pragma unroll
+      for (int p = 0; p < 4; ++p) {
+        const int r = 4 * tr + p;
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          if (q == jq) {
+            if (r > j) a[p][q] = l[p];
+            else if (CHOL && r == j) a[p][q] = piv;
+          }
       }
-      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-      __builtin_amdgcn_wave_barrier();
     }
   }
+  __syncthreads();
 #pragma unroll
-  for (int j = 0; j < CB; ++j) tile[i][j] = r[j];
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  for (int rr = 0; rr < nb; ++rr)
-    if (i < nb && (!CHOL || i <= rr)) A[(size_t)(b0 + rr) * n + b0 + i] = tile[rr][i];
+  for (int p = 0; p < 4; ++p)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) tile[4 * tr + p][4 * tc + q] = a[p][q];
+  __syncthreads();
+  for (int e = t; e < CB * CB; e += 256) {
+    const int r = e >> 6, c = e & 63;
+    if (r < nb && c < nb && (!CHOL || c <= r)) A[(size_t)(b0 + r) * n + b0 + c] = tile[r][c];
+  }
 }
 
 // Panels: wave task t < rows below: row r solves x U11 = a (LU) or
@@ -976,6 +1102,7 @@ __global__ void k_blk_panel(int n, int b0, double* __restrict__ A, const int32_t
     const int32_t* __restrict__ skip) {
   if (skip && *skip) return;
   __shared__ double T[CB][CB + 1];
+  __shared__ double rd[CB];
   if (info[0] != 0) return;
   const int nb = min(CB, n - b0);
   const int rest = n - b0 - nb;
@@ -984,13 +1111,15 @@ __global__ void k_blk_panel(int n, int b0, double* __restrict__ A, const int32_t
     T[r][c] = (r < nb && c < nb) ? A[(size_t)(b0 + r) * n + b0 + c] : (r == c ? 1.0 : 0.0);
   }
   __syncthreads();
+  for (int j = threadIdx.x; j < CB; j += blockDim.x) rd[j] = 1.0 / T[j][j];
+  __syncthreads();
   const int lane = threadIdx.x & 63;
   const int task = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   if (task < rest) {
     double* a = A + (size_t)(b0 + nb + task) * n + b0;
     double v = lane < nb ? a[lane] : 0.0;
     for (int j = 0; j < nb; ++j) {
-      const double xj = __shfl(v, j, 64) / T[j][j];
+      const double xj = __shfl(v, j, 64) * rd[j];
       if (lane == j) v = xj;
       if (lane > j) v -= xj * (CHOL ? T[lane][j] : T[j][lane]);
     }
@@ -1066,111 +1195,146 @@ __global__ void k_transpose(int n, const double* __restrict__ A, double* __restr
   }
 }
 
-// Forward/back substitution with the lower factor in one workgroup of 1024
-// threads: per block of 64 rows, the products with the solved entries use
-// all threads (16 per row), the 64 x 64 triangle one wavefront with its row
-// of the triangle in registers.   L y = -rhs,  L^T step = y.
-__global__ void __launch_bounds__(256) k_chol_solve(int n, const double* __restrict__ L,
-                                                    const double* __restrict__ rhs, double* __restrict__ step,
-                                                    double* __restrict__ work, const int32_t* __restrict__ info) {
-  if (info[0] != 0) return;
-  __shared__ double part[CB][17];
+// Triangular solves with the dense Cholesky factor, L y = -rhs and
+// L^T step = y, spread over one workgroup per block of CB rows.  A block
+// publishes its solved entries by a flag (release at agent scope after its
+// stores); the workgroups that need them wait for the flag (acquire).  A
+// workgroup only waits for blocks of workgroups dispatched before it
+// (forward: lower block indices; backward: block = nblk - 1 - blockIdx.x),
+// so every awaited workgroup is already running.  Each wait is bounded: on
+// expiry info[0] is set to -1 and the solve continues, so every wave exits.
+// flags: int32 [nblk] per direction (its own array for each launch), zero
+// before the launch.
+
+__device__ inline void blk_wait(const int32_t* flag, int32_t* info) {
+  unsigned it = 0;
+  while (__hip_atomic_load(flag, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == 0) {
+    // after one expiry anywhere, no further waiting
+    if (++it > (1u << 20) || __hip_atomic_load(info, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < 0) {
+      __hip_atomic_store(info, -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      break;
+    }
+    __builtin_amdgcn_s_sleep(2);
+  }
+}
+
+__device__ inline void blk_publish(int32_t* flag) {
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) __hip_atomic_store(flag, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__global__ void __launch_bounds__(256) k_chol_fwd(int n, const double* __restrict__ L, const double* __restrict__ rhs,
+                                                  double* __restrict__ y, int32_t* __restrict__ flags,
+                                                  int32_t* __restrict__ info) {
+  if (info[0] > 0) return;
+  __shared__ double part[CB][5];
   __shared__ double tri[CB][CB + 1];
+  __shared__ double rd[CB];
+  const int w = blockIdx.x;
+  const int b0 = w * CB, nb = min(CB, n - b0);
   const int t = threadIdx.x;
-  const int rr = t >> 4, sl = t & 15;   // row (of 16 per pass), slice
-  double* yv = work;
-  for (int b0 = 0; b0 < n; b0 += CB) {
-    const int nb = min(CB, n - b0);
-    for (int r = rr; r < CB; r += 16) {
-      double a0 = 0.0, a1 = 0.0;
-      if (r < nb) {
-        const double* Lr = L + (size_t)(b0 + r) * n;
-        double a2 = 0.0, a3 = 0.0;
-        int k = sl;
-        for (; k + 48 < b0; k += 64) {
-          a0 += Lr[k] * yv[k];
-          a1 += Lr[k + 16] * yv[k + 16];
-          a2 += Lr[k + 32] * yv[k + 32];
-          a3 += Lr[k + 48] * yv[k + 48];
-        }
-        for (; k < b0; k += 16) a0 += Lr[k] * yv[k];
-        a0 += a2;
-        a1 += a3;
-      }
-      part[r][sl] = a0 + a1;
-    }
-    for (int e = t; e < CB * CB; e += blockDim.x) {
-      const int r = e >> 6, j = e & 63;
-      tri[r][j] = (r < nb && j < nb) ? L[(size_t)(b0 + r) * n + b0 + j] : 0.0;
-    }
-    __syncthreads();
-    if (t < 64) {
-      double lr[CB];
-#pragma unroll
-      for (int j = 0; j < CB; ++j) lr[j] = tri[t][j];
-      double v = 0.0;
-      if (t < nb) {
-        v = -rhs[b0 + t];
-        for (int q = 0; q < 16; ++q) v -= part[t][q];
-      }
-#pragma unroll
-      for (int k = 0; k < CB; ++k) {
-        if (k < nb) {
-          const double yk = __shfl(v, k, 64) / __shfl(lr[k], k, 64);
-          if (t == k) v = yk;
-          if (t > k) v -= lr[k] * yk;
-        }
-      }
-      if (t < nb) yv[b0 + t] = v;
-    }
-    __syncthreads();
+  // diagonal block and reciprocal pivots first (no dependency)
+  for (int e = t; e < CB * CB; e += 256) {
+    const int r = e >> 6, c = e & 63;
+    tri[r][c] = (r < nb && c < nb) ? L[(size_t)(b0 + r) * n + b0 + c] : (r == c ? 1.0 : 0.0);
   }
-  for (int b1 = n; b1 > 0; b1 -= CB) {
-    const int b0 = max(0, b1 - CB), nb = b1 - b0;
-    for (int r = rr; r < CB; r += 16) {
-      double a0 = 0.0, a1 = 0.0;
-      if (r < nb) {
-        double a2 = 0.0, a3 = 0.0;
-        int k = b1 + sl;
-        for (; k + 48 < n; k += 64) {
-          a0 += L[(size_t)k * n + b0 + r] * step[k];
-          a1 += L[(size_t)(k + 16) * n + b0 + r] * step[k + 16];
-          a2 += L[(size_t)(k + 32) * n + b0 + r] * step[k + 32];
-          a3 += L[(size_t)(k + 48) * n + b0 + r] * step[k + 48];
-        }
-        for (; k < n; k += 16) a0 += L[(size_t)k * n + b0 + r] * step[k];
-        a0 += a2;
-        a1 += a3;
-      }
-      part[r][sl] = a0 + a1;
-    }
-    for (int e = t; e < CB * CB; e += blockDim.x) {
-      const int r = e >> 6, j = e & 63;
-      tri[r][j] = (r < nb && j < nb) ? L[(size_t)(b0 + r) * n + b0 + j] : 0.0;
-    }
+  __syncthreads();
+  if (t < CB) rd[t] = 1.0 / tri[t][t];
+  // products with the solved blocks: thread (row r, slice sl of 16 columns)
+  const int r = t >> 2, sl = t & 3;
+  double a0 = 0.0, a1 = 0.0;
+  for (int k = 0; k < w; ++k) {
+    if (t == 0) blk_wait(flags + k, info);
     __syncthreads();
-    if (t < 64) {
-      // lane t holds column t of the triangle: L[b0 + k][b0 + t]
-      double lc[CB];
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    if (r < nb) {
+      const double* Lr = L + (size_t)(b0 + r) * n + k * CB + sl * 16;
+      const double* yk = y + k * CB + sl * 16;
 #pragma unroll
-      for (int k = 0; k < CB; ++k) lc[k] = tri[k][t];
-      double v = 0.0;
-      if (t < nb) {
-        v = yv[b0 + t];
-        for (int q = 0; q < 16; ++q) v -= part[t][q];
+      for (int q = 0; q < 16; q += 2) {
+        a0 += Lr[q] * yk[q];
+        a1 += Lr[q + 1] * yk[q + 1];
       }
-#pragma unroll
-      for (int k = CB - 1; k >= 0; --k) {
-        if (k < nb) {
-          const double xk = __shfl(v, k, 64) / __shfl(lc[k], k, 64);
-          if (t == k) v = xk;
-          if (t < k) v -= lc[k] * xk;
-        }
-      }
-      if (t < nb) step[b0 + t] = v;
     }
-    __syncthreads();
   }
+  part[r][sl] = a0 + a1;
+  __syncthreads();
+  if (t < 64) {
+    double lr[CB];
+#pragma unroll
+    for (int j = 0; j < CB; ++j) lr[j] = tri[t][j];
+    double v = 0.0;
+    if (t < nb) v = -rhs[b0 + t] - ((part[t][0] + part[t][1]) + (part[t][2] + part[t][3]));
+#pragma unroll
+    for (int k = 0; k < CB; ++k) {
+      if (k < nb) {
+        const double yk = __shfl(v, k, 64) * rd[k];
+        if (t == k) v = yk;
+        if (t > k) v -= lr[k] * yk;
+      }
+    }
+    if (t < nb) y[b0 + t] = v;
+  }
+  blk_publish(flags + w);
+}
+
+__global__ void __launch_bounds__(256) k_chol_bwd(int n, const double* __restrict__ L, const double* __restrict__ y,
+                                                  double* __restrict__ x, int32_t* __restrict__ flags,
+                                                  int32_t* __restrict__ info) {
+  if (info[0] > 0) return;
+  __shared__ double part[4][CB];
+  __shared__ double tri[CB][CB + 1];
+  __shared__ double rd[CB];
+  const int nblk = (n + CB - 1) / CB;
+  const int w = nblk - 1 - blockIdx.x;
+  const int b0 = w * CB, nb = min(CB, n - b0);
+  const int t = threadIdx.x;
+  for (int e = t; e < CB * CB; e += 256) {
+    const int r = e >> 6, c = e & 63;
+    tri[r][c] = (r < nb && c < nb) ? L[(size_t)(b0 + r) * n + b0 + c] : (r == c ? 1.0 : 0.0);
+  }
+  __syncthreads();
+  if (t < CB) rd[t] = 1.0 / tri[t][t];
+  // products with the solved blocks: lane i = column b0 + i of L (row of
+  // L^T), wave sl takes rows k CB + 16 sl .. + 15 of each later block
+  const int i = t & 63, sl = t >> 6;
+  double a0 = 0.0, a1 = 0.0;
+  for (int k = nblk - 1; k > w; --k) {
+    if (t == 0) blk_wait(flags + k, info);
+    __syncthreads();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    const int kr0 = k * CB + sl * 16;
+    const int kr1 = min(kr0 + 16, n);
+    if (i < nb) {
+      int j = kr0;
+      for (; j + 1 < kr1; j += 2) {
+        a0 += L[(size_t)j * n + b0 + i] * x[j];
+        a1 += L[(size_t)(j + 1) * n + b0 + i] * x[j + 1];
+      }
+      if (j < kr1) a0 += L[(size_t)j * n + b0 + i] * x[j];
+    }
+  }
+  part[sl][i] = a0 + a1;
+  __syncthreads();
+  if (t < 64) {
+    // lane t holds column t of the triangle: L[b0 + k][b0 + t]
+    double lc[CB];
+#pragma unroll
+    for (int k = 0; k < CB; ++k) lc[k] = tri[k][t];
+    double v = 0.0;
+    if (t < nb) v = y[b0 + t] - ((part[0][t] + part[1][t]) + (part[2][t] + part[3][t]));
+#pragma unroll
+    for (int k = CB - 1; k >= 0; --k) {
+      if (k < nb) {
+        const double xk = __shfl(v, k, 64) * rd[k];
+        if (t == k) v = xk;
+        if (t < k) v -= lc[k] * xk;
+      }
+    }
+    if (t < nb) x[b0 + t] = v;
+  }
+  blk_publish(flags + w);
 }
 
 }  // namespace dev

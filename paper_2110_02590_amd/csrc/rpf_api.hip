@@ -74,6 +74,7 @@ struct rpf_grid {
   int32_t *top_flev, *top_frows, *top_blev, *top_brows, *top_pos;
   int64_t* top_dense;
   double *dense_top, *dense_topT;
+  double *top_dinv, *top_dinvT;   // inverse diagonal blocks of the dense top factor
   int npacks = 0, max_pack = 0, tw = 16;
   int32_t *pkf_rp, *pkf_pos, *pkb_rp, *pkb_pos;
   int16_t *pkf_col, *pkb_col;
@@ -86,10 +87,12 @@ struct rpf_grid {
   double *luv, *lutv, *juv, *Gv, *Kv, *wrec, *kappa, *a, *b, *Pbus, *Qbus;
   double *cvec, *wvec, *terms, *varg, *lam;
   double *D, *Y, *T, *chol_work;
+  int32_t* chol_flags;   // block flags of the dense triangular solves [2 cdiv(n_u, CB)]
   // tracking step workspace
   double *Hbuf, *Kbuf, *gradbuf, *dstep, *u_try, *xi_save, *scur, *pdt, *qdt, *tres;
   int32_t* tflags;
   int32_t *flag, *piv_status;
+  double* rdiag;   // 1 / u_ii of the refactorized rows [n_x]
   double* host_resid;  // pinned
 
   int rf_waves = 16;
@@ -262,6 +265,8 @@ void setup(rpf_grid* h) {
   h->pkb_col = h->up(P.pkb_col);
   h->dense_top = h->alloc<double>((size_t)P.ntop * P.ntop);
   h->dense_topT = h->alloc<double>((size_t)P.ntop * P.ntop);
+  h->top_dinv = h->alloc<double>((size_t)cdiv(P.ntop, CB) * 2 * CB * CB);
+  h->top_dinvT = h->alloc<double>((size_t)cdiv(P.ntop, CB) * 2 * CB * CB);
   h->npacks = (int)P.pack_ptr.size() - 1;
   for (int q = 0; q < h->npacks; ++q) h->max_pack = std::max(h->max_pack, P.pack_ptr[q + 1] - P.pack_ptr[q]);
   {
@@ -302,8 +307,7 @@ void setup(rpf_grid* h) {
     auto allow_top = [&](const void* f) {
       HIPCHK(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, ldsmax - (int)top_static));
     };
-    allow_top((const void*)k_top_dense<true, true, false>);
-    allow_top((const void*)k_top_dense<false, true, true>);
+    allow_top((const void*)k_top_dense);
 #define RPF_ALLOW_PACK(TW)                                  \
   allow((const void*)k_pack_solve_s<TW, true, true>);       \
   allow((const void*)k_pack_solve_s<TW, true, false>);      \
@@ -345,6 +349,7 @@ void setup(rpf_grid* h) {
   h->Y = h->alloc<double>((size_t)P.nvar * h->max_batch);
   h->T = h->alloc<double>((size_t)P.nr1 * h->max_batch);
   h->chol_work = h->alloc<double>(P.nu);
+  h->chol_flags = h->alloc<int32_t>(2 * (size_t)cdiv(P.nu, CB));
   h->Hbuf = h->alloc<double>((size_t)P.nu * P.nu);
   h->Kbuf = h->alloc<double>((size_t)P.nu * P.nu);
   h->gradbuf = h->alloc<double>(P.nu);
@@ -358,6 +363,7 @@ void setup(rpf_grid* h) {
   h->tflags = h->alloc<int32_t>(8);
   h->flag = h->alloc<int32_t>(4);
   h->piv_status = h->alloc<int32_t>(4);
+  h->rdiag = h->alloc<double>(P.nx);
   HIPCHK(hipHostMalloc((void**)&h->host_resid, sizeof(double) * 4, hipHostMallocDefault));
 
   int maxrow = std::max(P.max_lu_row, 1);
@@ -387,7 +393,7 @@ template <bool CHOL>
 void dense_factor(int n, double* A, int32_t* info, int base, hipStream_t s, const int32_t* skip = nullptr) {
   for (int b0 = 0; b0 < n; b0 += CB) {
     const int nb = std::min(CB, n - b0);
-    k_blk_diag<CHOL><<<1, 64, 0, s>>>(n, b0, A, info, base, skip);
+    k_blk_diag<CHOL><<<1, 256, 0, s>>>(n, b0, A, info, base, skip);
     LAUNCHCHK();
     const int rest = n - b0 - nb;
     if (rest > 0) {
@@ -412,14 +418,14 @@ void refactor(rpf_grid* h, hipStream_t s, const int32_t* skip = nullptr) {
   size_t pi = h->prof_on ? h->prof_begin(s) : 0;
   if (h->npacks > 0) {
     k_rf_pack<<<h->npacks, 64 * wv, shm, s>>>(h->pk_flev, h->pk_flev_off, h->pk_frows, h->lu_ptr, h->lu_col,
-                                              h->lu_diag, h->upd_ptr, h->upd_tgt, h->luv, maxrow, 1e-14,
-                                              h->piv_status, skip);
+                                              h->lu_diag, h->upd_ptr, h->upd_tgt, h->luv, h->rdiag, maxrow,
+                                              1e-14, h->piv_status, skip);
     LAUNCHCHK();
   }
   if (P.ntop > 0) {
     k_rf_top_ext<<<cdiv(P.ntop, wv), 64 * wv, shm, s>>>(P.t0, P.nx, h->lo_split, h->lu_ptr, h->lu_col, h->lu_diag,
-                                                       h->upd_ptr, h->upd_tgt, h->luv, maxrow, h->piv_status,
-                                                       skip);
+                                                       h->upd_ptr, h->upd_tgt, h->luv, h->rdiag, maxrow,
+                                                       h->piv_status, skip);
     LAUNCHCHK();
     const int64_t nd = (int64_t)P.ntop * P.ntop;
     k_fill_dbl<<<cdiv(nd, 256), 256, 0, s>>>(nd, h->dense_top, 0.0, skip);
@@ -432,6 +438,12 @@ void refactor(rpf_grid* h, hipStream_t s, const int32_t* skip = nullptr) {
                                                                                  h->dense_topT, skip);
     LAUNCHCHK();
     k_dense_xfer<<<cdiv(ne, 256), 256, 0, s>>>(ne, h->top_pos, h->top_dense, h->luv, h->dense_top, 0, skip);
+    LAUNCHCHK();
+    // inverse diagonal blocks: J_x uses L (unit) and U; J_x^T uses U^T and L^T (unit)
+    const dim3 gi(cdiv(P.ntop, CB), 2);
+    k_top_diag_inv<<<gi, 64, 0, s>>>(P.ntop, h->dense_top, h->top_dinv, 1, 0, skip);
+    LAUNCHCHK();
+    k_top_diag_inv<<<gi, 64, 0, s>>>(P.ntop, h->dense_topT, h->top_dinvT, 0, 1, skip);
     LAUNCHCHK();
   }
   if (h->prof_on) h->prof_end(2, pi, s);
@@ -482,8 +494,8 @@ void pack_solve_any(rpf_grid* h, int tw, bool fwd, bool unit, const double* val,
 
 // Solves with both factors of J_x (transposed = false): X <- U^{-1} L^{-1}
 // (scale X), or of J_x^T (transposed = true): X <- L^{-T} U^{-T} (scale X).
-// Three launches: packs forward, top part forward + backward, packs
-// backward.
+// Four launches: packs forward, right-hand side of the top rows (pack
+// contributions), dense top part forward + backward, packs backward.
 void solve_pair(rpf_grid* h, bool transposed, double* X, int ld, int ncols, double scale, hipStream_t s,
                 const int32_t* skip = nullptr) {
   const Presolve& P = h->P;
@@ -496,16 +508,17 @@ void solve_pair(rpf_grid* h, bool transposed, double* X, int ld, int ncols, doub
   pack_solve_any(h, twp, true, fwd_unit, val, X, ld, ncols, scale, cls, s, skip);
   if (P.ntop > 0) {
     size_t pi = h->prof_on ? h->prof_begin(s) : 0;
+    int bx = 64;
+    while (bx > 1 && bx / 2 >= ncols) bx /= 2;
+    const dim3 rb(bx, 256 / bx);
+    k_top_rhs<<<dim3(cdiv(ncols, bx), cdiv(P.ntop, (int)rb.y)), rb, 0, s>>>(P.t0, P.nx, h->lo_split, h->lu_ptr,
+                                                                            h->lu_col, val, X, ld, ncols, scale,
+                                                                            skip);
+    LAUNCHCHK();
     const size_t shm = (size_t)P.ntop * twt * sizeof(double);
     const double* M = transposed ? h->dense_topT : h->dense_top;
-    const int ct = cdiv(ncols, twt);
-    if (fwd_unit) {
-      auto kern = k_top_dense<true, true, false>;
-      kern<<<ct, 256, shm, s>>>(P.t0, P.nx, h->lo_split, h->lu_ptr, h->lu_col, val, M, X, ld, ncols, scale, twt, skip);
-    } else {
-      auto kern = k_top_dense<false, true, true>;
-      kern<<<ct, 256, shm, s>>>(P.t0, P.nx, h->lo_split, h->lu_ptr, h->lu_col, val, M, X, ld, ncols, scale, twt, skip);
-    }
+    const double* dinv = transposed ? h->top_dinvT : h->top_dinv;
+    k_top_dense<<<cdiv(ncols, twt), 256, shm, s>>>(P.t0, P.nx, M, dinv, X, ld, ncols, twt, skip);
     LAUNCHCHK();
     if (h->prof_on) h->prof_end(cls == 0 ? 5 : cls, pi, s);
   }
@@ -521,6 +534,19 @@ void spmm(rpf_grid* h, int nrows, const int32_t* ptr, const int32_t* col, const 
   k_spmm<<<grd, blk, 0, s>>>(nrows, ptr, col, val, valpos, xscale, X, ldx, ncols, alpha, Yadd, ldya, Y, ldy);
   LAUNCHCHK();
   if (h->prof_on) h->prof_end(3, pi, s);
+}
+
+// step = -(L L^T)^{-1} rhs with the dense Cholesky factor L (row-major n x n,
+// lower triangle): one workgroup per block of CB rows in each direction.
+void chol_solve(rpf_grid* h, int n, const double* L, const double* rhs, double* step, int32_t* info,
+                hipStream_t s) {
+  const int nblk = cdiv(n, CB);
+  k_fill_int<<<cdiv(2 * nblk, 256), 256, 0, s>>>(2 * nblk, h->chol_flags, 0);
+  LAUNCHCHK();
+  k_chol_fwd<<<nblk, 256, 0, s>>>(n, L, rhs, h->chol_work, h->chol_flags, info);
+  LAUNCHCHK();
+  k_chol_bwd<<<nblk, 256, 0, s>>>(n, L, h->chol_work, step, h->chol_flags + nblk, info);
+  LAUNCHCHK();
 }
 
 ALArgs al_args(rpf_grid* h, const double* u, const double* pd, const double* qd, const double* s,
@@ -933,8 +959,7 @@ int rpf_factor_solve(rpf_grid* h, int32_t n, double* K, const double* diag, doub
     k_symmetrize<<<dim3(cdiv(n, 32), cdiv(n, 8)), dim3(32, 8), 0, s>>>(n, K, diag, delta);
     LAUNCHCHK();
     dense_factor<true>(n, K, info, 0, s);
-    k_chol_solve<<<1, 256, 0, s>>>(n, K, rhs, step, h->chol_work, info);
-    LAUNCHCHK();
+    chol_solve(h, n, K, rhs, step, info, s);
     if (h->prof_on) h->prof_end(4, pi, s);
     return RPF_OK;
   });
@@ -987,8 +1012,7 @@ int rpf_track_step(rpf_grid* h, double* u, double* x, double* y, const double* p
     k_symmetrize<<<dim3(cdiv(nu, 32), cdiv(nu, 8)), dim3(32, 8), 0, s>>>(nu, h->Kbuf, nullptr, delta);
     LAUNCHCHK();
     dense_factor<true>(nu, h->Kbuf, info, 0, s);
-    k_chol_solve<<<1, 256, 0, s>>>(nu, h->Kbuf, h->gradbuf, h->dstep, h->chol_work, info);
-    LAUNCHCHK();
+    chol_solve(h, nu, h->Kbuf, h->gradbuf, h->dstep, info, s);
     k_zero_if<<<cdiv(nu, 256), 256, 0, s>>>(nu, info, h->dstep);
     LAUNCHCHK();
     // 5. u + step / 2^k clipped to the bounds, first k whose power flow converges

@@ -92,3 +92,12 @@ def test_presolve_rejects_bad_grids():
     bad = dict(g, br_to=np.array([1, 2, 2], np.int32))       # branch 2 -> 2
     with pytest.raises(RpfError):
         presolve_info(bad)
+
+
+def test_profile_class_count_matches_header():
+    """The binding's timing arrays are as long as the library writes."""
+    import re
+    from paper_2110_02590_amd.binding import Grid
+    txt = open(os.path.join(ROOT, "include", "rpf.h")).read()
+    n = int(re.search(r"#define\s+RPF_PROF_CLASSES\s+(\d+)", txt).group(1))
+    assert len(Grid.PROF_CLASSES) == n
