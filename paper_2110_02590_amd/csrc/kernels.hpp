@@ -601,6 +601,104 @@ __global__ void __launch_bounds__(256) k_pack_solve_s(const int32_t* __restrict_
   }
 }
 
+// Batched pack solves in place in global memory, for many right-hand
+// sides.  One workgroup (16 wavefronts) per (pack, 64-column tile); the
+// pack's column indices and row ranges are staged in LDS, factor values
+// and X are read from global memory (the rows a pack reads are written by
+// the same workgroup before a workgroup barrier, or are final top rows).
+// Per level, a wavefront takes one unit = (row, chunk of 64 / G columns)
+// with G lanes per column summing every G-th entry (G = 2^lg chosen so
+// the level's units fill the wavefronts), butterfly-reduced.
+// FWD: entries [ptr[i], diag[i]) (L, or U^T), x_i = scale b_i - sum;
+// backward: entries (diag[i], ptr[i+1]) (U, or L^T, top columns included),
+// x_i = b_i - sum; UNIT = false multiplies by 1 / val[diag[i]].
+// LDS: scol[seg] | sptr[nr + 1] | sdiag[nr] | srow[nr] | slev[nlev + 1] |
+// srd[nr] (double), seg = nnz of the pack's CSR rows.
+__host__ __device__ inline size_t packg_lds_bytes(int nr, int seg, int nlev) {
+  size_t b = (size_t)seg * 4 + (size_t)(nr + 1) * 4 + (size_t)nr * 8 + (size_t)(nlev + 1) * 4;
+  b = (b + 7) & ~(size_t)7;
+  return b + (size_t)nr * 8;
+}
+
+template <bool FWD, bool UNIT>
+__global__ void __launch_bounds__(1024) k_pack_solve_g(const int32_t* __restrict__ pack_ptr,
+                                                       const int32_t* __restrict__ lev,
+                                                       const int32_t* __restrict__ lev_off,
+                                                       const int32_t* __restrict__ lrows,
+                                                       const int32_t* __restrict__ ptr,
+                                                       const int32_t* __restrict__ diag,
+                                                       const int32_t* __restrict__ col,
+                                                       const double* __restrict__ val, double* __restrict__ X,
+                                                       int ld, int ncols, double scale,
+                                                       const int32_t* __restrict__ skip) {
+  if (skip && *skip) return;
+  extern __shared__ int32_t smi[];
+  const int q = blockIdx.x;
+  const int c0 = blockIdx.y * 64;
+  const int r0 = pack_ptr[q], nr = pack_ptr[q + 1] - r0;
+  const int l0 = lev_off[q], nlev = lev_off[q + 1] - l0;
+  const int gp0 = ptr[r0], seg = ptr[r0 + nr] - gp0;
+  const int base_row = lev[l0];
+  int32_t* scol = smi;
+  int32_t* sptr = scol + seg;
+  int32_t* sdiag = sptr + nr + 1;
+  int32_t* srow = sdiag + nr;
+  int32_t* slev = srow + nr;
+  size_t off = (size_t)seg + (nr + 1) + 2 * (size_t)nr + (nlev + 1);
+  off = (off + 1) & ~(size_t)1;
+  double* srd = (double*)(smi + off);
+  const int t = threadIdx.x;
+  for (int e = t; e < seg; e += blockDim.x) scol[e] = col[gp0 + e];
+  for (int r = t; r <= nr; r += blockDim.x) sptr[r] = ptr[r0 + r] - gp0;
+  for (int r = t; r < nr; r += blockDim.x) {
+    const int dg = diag[r0 + r];
+    sdiag[r] = dg - gp0;
+    srow[r] = lrows[base_row + r] - r0;
+    srd[r] = UNIT ? 1.0 : 1.0 / val[dg];
+  }
+  for (int k = t; k <= nlev; k += blockDim.x) slev[k] = lev[l0 + k] - base_row;
+  __syncthreads();
+  const int wave = t >> 6, lane = t & 63, nwave = blockDim.x >> 6;
+  for (int lv = 0; lv < nlev; ++lv) {
+    const int a = slev[lv], nrow = slev[lv + 1] - a;
+    int lg = 0;
+    while (lg < 4 && (nrow << (lg + 1)) <= nwave) ++lg;
+    const int G = 1 << lg;
+    const int units = nrow << lg;
+    const int segl = lane & (G - 1);
+    for (int u = wave; u < units; u += nwave) {
+      const int k = u >> lg, qch = u & (G - 1);
+      const int rl = srow[a + k];
+      const int i = r0 + rl;
+      const int c = c0 + (qch << (6 - lg)) + (lane >> lg);
+      const bool cok = c < ncols;
+      const int e0 = FWD ? sptr[rl] : sdiag[rl] + 1;
+      const int e1 = FWD ? sdiag[rl] : sptr[rl + 1];
+      double q0 = 0.0, q1 = 0.0, q2 = 0.0, q3 = 0.0;
+      if (cok) {
+        int e = e0 + segl;
+        for (; e + 3 * G < e1; e += 4 * G) {
+          const int j0 = scol[e], j1 = scol[e + G], j2 = scol[e + 2 * G], j3 = scol[e + 3 * G];
+          q0 += val[gp0 + e] * X[(size_t)j0 * ld + c];
+          q1 += val[gp0 + e + G] * X[(size_t)j1 * ld + c];
+          q2 += val[gp0 + e + 2 * G] * X[(size_t)j2 * ld + c];
+          q3 += val[gp0 + e + 3 * G] * X[(size_t)j3 * ld + c];
+        }
+        for (; e < e1; e += G) q0 += val[gp0 + e] * X[(size_t)scol[e] * ld + c];
+      }
+      double part = (q0 + q1) + (q2 + q3);
+      for (int o = G >> 1; o > 0; o >>= 1) part += __shfl_xor(part, o, 64);
+      if (cok && segl == 0) {
+        const size_t xi = (size_t)i * ld + c;
+        double v = (FWD ? scale * X[xi] : X[xi]) - part;
+        if (!UNIT) v *= srd[rl];
+        X[xi] = v;
+      }
+    }
+    __syncthreads();
+  }
+}
+
 // ------------------------------------------------------------------ SpMM
 // Y[i, c] = (Yadd ? Yadd[i, c] : 0) + alpha * sum_p v(p) * s(col) * X[col, c]
 // with v(p) = val[valpos ? valpos[p] : p], s = xscale ? xscale[col] : 1.
@@ -1019,7 +1117,8 @@ __global__ void __launch_bounds__(256) k_blk_diag(int n, int b0, double* __restr
   if (info[0] != 0) return;
   const int nb = min(CB, n - b0);
   const int t = threadIdx.x;
-  // coalesced load through LDS; outside the nb x nb corner an identity
+  // coalesced load through LDS; outside the nb x nb corner an identity, so
+  // the padded pivots are 1 and leave the corner's factor unchanged
   for (int e = t; e < CB * CB; e += 256) {
     const int r = e >> 6, c = e & 63;
     tile[r][c] = (r < nb && c < nb) ? A[(size_t)(b0 + r) * n + b0 + c] : (r == c ? 1.0 : 0.0);
@@ -1033,60 +1132,80 @@ __global__ void __launch_bounds__(256) k_blk_diag(int n, int b0, double* __restr
 #pragma unroll
     for (int q = 0; q < 4; ++q) a[p][q] = tile[4 * tr + p][4 * tc + q];
   // right-looking elimination, one barrier per pivot: the owners of column
-  // j (and, for LU, row j) publish it in a double-buffered LDS vector, every
-  // thread updates its 16 entries
-  for (int j = 0; j < nb; ++j) {
-    const int buf = j & 1, jt = j >> 2, jq = j & 3;
-    if (tc == jt) {
+  // j (and, for LU, row j) publish it in a double-buffered LDS vector and
+  // write the finished column (row) of the factor into the LDS tile; every
+  // thread updates its 16 entries.  Pivots are unrolled by four so that
+  // every register index is static.
+  for (int jt = 0; 4 * jt < nb; ++jt) {
 #pragma unroll
-      for (int p = 0; p < 4; ++p) colb[buf][4 * tr + p] = a[p][jq];
-    }
-    if (!CHOL && tr == jt) {
+    for (int jq = 0; jq < 4; ++jq) {
+      const int j = 4 * jt + jq;
+      const int buf = jq & 1;
+      if (tc == jt) {
 #pragma unroll
-      for (int q = 0; q < 4; ++q) rowb[buf][4 * tc + q] = a[jq][q];
-    }
-    __syncthreads();
-    const double d = colb[buf][j];
-    const bool ok = CHOL ? (d > 0.0 && isfinite(d)) : (fabs(d) > 0.0 && isfinite(d));
-    if (!ok) {  // same d in every thread: uniform exit
-      if (t == 0) info[0] = base + b0 + j + 1;
-      return;
-    }
-    const double piv = CHOL ? sqrt(d) : d;
-    const double rp = 1.0 / piv;
-    double l[4], u[4];
+        for (int p = 0; p < 4; ++p) colb[buf][4 * tr + p] = a[p][jq];
+      }
+      if (!CHOL && tr == jt) {
 #pragma unroll
-    for (int p = 0; p < 4; ++p) {
-      const int r = 4 * tr + p;
-      l[p] = r > j ? colb[buf][r] * rp : 0.0;
-    }
+        for (int q = 0; q < 4; ++q) rowb[buf][4 * tc + q] = a[jq][q];
+      }
+      __syncthreads();
+      const double d = colb[buf][j];
+      const bool ok = CHOL ? (d > 0.0 && isfinite(d)) : (fabs(d) > 0.0 && isfinite(d));
+      if (!ok) {  // same d in every thread: uniform exit
+        if (t == 0) info[0] = base + b0 + j + 1;
+        return;
+      }
+      // rp = 1 / sqrt(d) (Cholesky) or 1 / d (LU): hardware estimate and
+      // one Newton step (relative error ~1e-16; far shorter chain than the
+      // correctly rounded library sequences)
+      double rp;
+      if (CHOL) {
+        const double y0 = __builtin_amdgcn_rsq(d);
+        const double h = 0.5 * y0, g = d * y0;
+        rp = fma(y0, fma(-h, g, 0.5), y0);
+      } else {
+        const double y0 = __builtin_amdgcn_rcp(d);
+        rp = fma(y0, fma(-d, y0, 1.0), y0);
+      }
+      const double piv = CHOL ? d * rp : d;
+      double cr[4], cc[4];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int c = 4 * tc + q;
-      u[q] = c > j ? (CHOL ? colb[buf][c] * rp : rowb[buf][c]) : 0.0;
-    }
+      for (int p = 0; p < 4; ++p) cr[p] = colb[buf][4 * tr + p];
 #pragma unroll
-    for (int p = 0; p < 4; ++p)
-#pragma unroll
-      for (int q = 0; q < 4; ++q) a[p][q] -= l[p] * u[q];
-    if (tc == jt) {
+      for (int q = 0; q < 4; ++q) cc[q] = CHOL ? colb[buf][4 * tc + q] : rowb[buf][4 * tc + q];
+      double l[4], u[4];
 #pragma unroll
       for (int p = 0; p < 4; ++p) {
-        const int r = 4 * tr + p;
+        const bool below = tr > jt || (tr == jt && p > jq);
+        l[p] = below ? cr[p] * rp : 0.0;
+      }
 #pragma unroll
-        for (int q = 0; q < 4; ++q)
-          if (q == jq) {
-            if (r > j) a[p][q] = l[p];
-            else if (CHOL && r == j) a[p][q] = piv;
-          }
+      for (int q = 0; q < 4; ++q) {
+        const bool right = tc > jt || (tc == jt && q > jq);
+        u[q] = right ? (CHOL ? cc[q] * rp : cc[q]) : 0.0;
+      }
+#pragma unroll
+      for (int p = 0; p < 4; ++p)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) a[p][q] -= l[p] * u[q];
+      if (tc == jt) {
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+          const int r = 4 * tr + p;
+          if (r > j) tile[r][j] = l[p];
+          else if (r == j) tile[r][j] = piv;
+        }
+      }
+      if (!CHOL && tr == jt) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int c = 4 * tc + q;
+          if (c > j) tile[j][c] = u[q];
+        }
       }
     }
   }
-  __syncthreads();
-#pragma unroll
-  for (int p = 0; p < 4; ++p)
-#pragma unroll
-    for (int q = 0; q < 4; ++q) tile[4 * tr + p][4 * tc + q] = a[p][q];
   __syncthreads();
   for (int e = t; e < CB * CB; e += 256) {
     const int r = e >> 6, c = e & 63;

@@ -79,6 +79,7 @@ struct rpf_grid {
   int32_t *pkf_rp, *pkf_pos, *pkb_rp, *pkb_pos;
   int16_t *pkf_col, *pkb_col;
   int tw_pack = 8, tw_top = 8;
+  size_t lds_packg = 0;   // LDS of the global-memory batched pack solves
   size_t lds_limit = 65536, lds_pack[5] = {0, 0, 0, 0, 0};
   double *c2, *c1, *c0;
 
@@ -286,6 +287,13 @@ void setup(rpf_grid* h) {
       }
       h->lds_pack[k] = mx;
     }
+    // global-memory batched pack solves: largest pack, either direction
+    for (int q = 0; q < h->npacks; ++q) {
+      const int r0 = P.pack_ptr[q], nr = P.pack_ptr[q + 1] - r0;
+      const int seg = P.lu_ptr[r0 + nr] - P.lu_ptr[r0];
+      const int nl = std::max(P.pk_flev_off[q + 1] - P.pk_flev_off[q], P.pk_blev_off[q + 1] - P.pk_blev_off[q]);
+      h->lds_packg = std::max(h->lds_packg, packg_lds_bytes(nr, seg, nl));
+    }
     h->tw_pack = 0;
     for (int k = 0; k < 5; ++k)
       if (h->lds_pack[k] <= h->lds_limit) {
@@ -313,6 +321,11 @@ void setup(rpf_grid* h) {
   allow((const void*)k_pack_solve_s<TW, true, false>);      \
   allow((const void*)k_pack_solve_s<TW, false, true>);      \
   allow((const void*)k_pack_solve_s<TW, false, false>);
+    if (h->lds_packg > h->lds_limit) throw std::runtime_error("a pack of subtrees does not fit in LDS");
+    allow((const void*)k_pack_solve_g<true, true>);
+    allow((const void*)k_pack_solve_g<true, false>);
+    allow((const void*)k_pack_solve_g<false, true>);
+    allow((const void*)k_pack_solve_g<false, false>);
     RPF_ALLOW_PACK(16)
     RPF_ALLOW_PACK(8)
     RPF_ALLOW_PACK(4)
@@ -481,8 +494,31 @@ void pack_solve(rpf_grid* h, bool fwd, bool unit, const double* val, double* X, 
   (void)P;
 }
 
+// Many right-hand sides: one workgroup of 1024 threads per (pack, 64 columns),
+// solved in place in X.
+void pack_solve_g(rpf_grid* h, bool fwd, bool unit, const double* val, double* X, int ld, int ncols, double scale,
+                  int cls, hipStream_t s, const int32_t* skip) {
+  if (h->npacks == 0) return;
+  dim3 grd(h->npacks, cdiv(ncols, 64));
+  size_t pi = h->prof_on ? h->prof_begin(s) : 0;
+  auto launch = [&](auto kern, const int32_t* lev, const int32_t* lev_off, const int32_t* rows) {
+    kern<<<grd, 1024, h->lds_packg, s>>>(h->pack_ptr, lev, lev_off, rows, h->lu_ptr, h->lu_diag, h->lu_col, val, X,
+                                         ld, ncols, scale, skip);
+  };
+  if (fwd) {
+    if (unit) launch(k_pack_solve_g<true, true>, h->pk_flev, h->pk_flev_off, h->pk_frows);
+    else launch(k_pack_solve_g<true, false>, h->pk_flev, h->pk_flev_off, h->pk_frows);
+  } else {
+    if (unit) launch(k_pack_solve_g<false, true>, h->pk_blev, h->pk_blev_off, h->pk_brows);
+    else launch(k_pack_solve_g<false, false>, h->pk_blev, h->pk_blev_off, h->pk_brows);
+  }
+  LAUNCHCHK();
+  if (h->prof_on) h->prof_end(cls, pi, s);
+}
+
 void pack_solve_any(rpf_grid* h, int tw, bool fwd, bool unit, const double* val, double* X, int ld, int ncols,
                     double scale, int cls, hipStream_t s, const int32_t* skip) {
+  if (ncols > 1) return pack_solve_g(h, fwd, unit, val, X, ld, ncols, scale, cls, s, skip);
   switch (tw) {
     case 16: return pack_solve<16>(h, fwd, unit, val, X, ld, ncols, scale, cls, s, skip);
     case 8: return pack_solve<8>(h, fwd, unit, val, X, ld, ncols, scale, cls, s, skip);
