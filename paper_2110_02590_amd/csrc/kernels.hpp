@@ -267,6 +267,108 @@ __global__ void k_rf_pack(const int32_t* __restrict__ flev, const int32_t* __res
   }
 }
 
+// Packs with their LU values resident in LDS: one workgroup (16
+// wavefronts) per pack, forward levels separated by barriers, one
+// wavefront per row, eliminating in place in LDS.  The metadata of up to
+// 64 elimination steps of a row (pivot column, U-row start, update range)
+// is loaded at once, lane s holding step s, and broadcast by readlane; the
+// update targets of step s + 2 are loaded during step s.  Reciprocal
+// pivots of finished rows go to LDS and to rdg.  LDS: values of the pack's
+// CSR rows [seg] | 1 / u_ii [nr].
+__device__ inline int64_t readlane64(int64_t v, int s) {
+  const int lo = __builtin_amdgcn_readlane((int)(uint32_t)(v & 0xffffffff), s);
+  const int hi = __builtin_amdgcn_readlane((int)(v >> 32), s);
+  return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+
+__global__ void __launch_bounds__(1024) k_rf_pack_lds(const int32_t* __restrict__ pack_ptr,
+                                                      const int32_t* __restrict__ flev,
+                                                      const int32_t* __restrict__ flev_off,
+                                                      const int32_t* __restrict__ frows,
+                                                      const int32_t* __restrict__ ptr,
+                                                      const int32_t* __restrict__ col,
+                                                      const int32_t* __restrict__ diag,
+                                                      const int32_t* __restrict__ ustart,
+                                                      const int64_t* __restrict__ upd_ptr,
+                                                      const int32_t* __restrict__ upd_tgt,
+                                                      double* __restrict__ a, double* __restrict__ rdg,
+                                                      double pivtol, int32_t* __restrict__ status,
+                                                      const int32_t* __restrict__ skip) {
+  if (skip && *skip) return;
+  extern __shared__ double sv[];
+  const int q = blockIdx.x;
+  const int r0 = pack_ptr[q], nr = pack_ptr[q + 1] - r0;
+  const int gp0 = ptr[r0], seg = ptr[r0 + nr] - gp0;
+  double* srd = sv + seg;
+  const int t = threadIdx.x;
+  for (int e = t; e < seg; e += blockDim.x) sv[e] = a[gp0 + e];
+  __syncthreads();
+  const int wave = t >> 6, lane = t & 63, nwave = blockDim.x >> 6;
+  for (int lv = flev_off[q]; lv < flev_off[q + 1]; ++lv) {
+    for (int rr = flev[lv] + wave; rr < flev[lv + 1]; rr += nwave) {
+      const int i = frows[rr];
+      const int p0 = ptr[i], pdg = diag[i], p1 = ptr[i + 1];
+      double amax = 0.0;
+      for (int e = p0 + lane; e < p1; e += 64) amax = fmax(amax, fabs(sv[e - gp0]));
+      for (int w0 = p0; w0 < pdg; w0 += 64) {
+        const int nw = min(64, pdg - w0);
+        int m_k = 0, m_us = 0, m_nu = 0;
+        int64_t m_u0 = 0;
+        if (lane < nw) {
+          const int p = w0 + lane;
+          m_k = col[p];
+          m_us = ustart[p];
+          m_u0 = upd_ptr[p];
+          m_nu = (int)(upd_ptr[p + 1] - m_u0);
+        }
+        int tg_a = 0, tg_b = 0;
+        {
+          const int64_t u = readlane64(m_u0, 0);
+          if (lane < __builtin_amdgcn_readlane(m_nu, 0)) tg_a = upd_tgt[u + lane];
+        }
+        if (nw > 1) {
+          const int64_t u = readlane64(m_u0, 1);
+          if (lane < __builtin_amdgcn_readlane(m_nu, 1)) tg_b = upd_tgt[u + lane];
+        }
+        for (int s = 0; s < nw; ++s) {
+          const int k = __builtin_amdgcn_readlane(m_k, s);
+          const int us = __builtin_amdgcn_readlane(m_us, s) - gp0;
+          const int nu = __builtin_amdgcn_readlane(m_nu, s);
+          const int tg = tg_a - gp0;
+          tg_a = tg_b;
+          if (s + 2 < nw) {
+            const int64_t u2 = readlane64(m_u0, s + 2);
+            tg_b = lane < __builtin_amdgcn_readlane(m_nu, s + 2) ? upd_tgt[u2 + lane] : 0;
+          }
+          const int pl = w0 + s - gp0;
+          const double av = lane < nu ? sv[us + lane] : 0.0;
+          const double l = sv[pl] * srd[k - r0];
+          if (lane < nu) sv[tg] -= l * av;
+          if (nu > 64) {
+            const int64_t u0 = readlane64(m_u0, s);
+            for (int tt = lane + 64; tt < nu; tt += 64) sv[upd_tgt[u0 + tt] - gp0] -= l * sv[us + tt];
+          }
+          if (lane == 0) sv[pl] = l;
+          __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+          __builtin_amdgcn_wave_barrier();
+        }
+      }
+      for (int off = 32; off > 0; off >>= 1) amax = fmax(amax, __shfl_xor(amax, off, 64));
+      if (lane == 0) {
+        const double piv = sv[pdg - gp0];
+        const double rp = 1.0 / piv;
+        srd[i - r0] = rp;
+        rdg[i] = rp;
+        if (!(fabs(piv) > pivtol * amax)) atomicCAS(status, 0, i + 1);
+      }
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+    }
+    __syncthreads();
+  }
+  for (int e = t; e < seg; e += blockDim.x) a[gp0 + e] = sv[e];
+}
+
 // Top rows, eliminations by pack columns (all final): independent rows.
 __global__ void k_rf_top_ext(int t0, int n, const int32_t* __restrict__ lo_split, const int32_t* __restrict__ ptr,
                              const int32_t* __restrict__ col, const int32_t* __restrict__ diag,
@@ -307,39 +409,61 @@ __global__ void k_dense_xfer(int n, const int32_t* __restrict__ pos, const int64
 // [ptr[i], diag[i]); upper entries (diag[i], ptr[i+1]).
 
 // xs[b0 + r][c] -= sum_{j in [j0, j1)} M[b0 + r][j] xs[j][c] for the nb rows
-// of one block: M staged through LDS in 64 x 32 tiles (coalesced rows),
-// each thread accumulating up to four (row, column) pairs.
+// of one block: M staged through LDS in 64 x 32 tiles (coalesced rows,
+// zero outside [j0, j1)), the next tile loaded into registers while the
+// current one is used; each thread accumulates up to four (row, column)
+// pairs over a fully unrolled 32-wide tile.  xs rows are clamped to s - 1
+// where the tile is zero, so every LDS index stays inside xs.
 __device__ inline void top_block_update(const double* __restrict__ M, int s, int b0, int nb, int j0, int j1,
                                         double* xs, int tw, double (*mt)[33]) {
   const int t = threadIdx.x;
   const int npair = nb * tw;
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  int rk[4], ck[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int e = t + k * 256;
+    rk[k] = e < npair ? e / tw : 0;
+    ck[k] = e < npair ? e - rk[k] * tw : 0;
+  }
+  // tile element e = t + 256 m (m < 8): row e >> 5, column e & 31
+  double nxt[8];
+  auto load = [&](int jt) {
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+      const int e = t + 256 * m, r = e >> 5, j = e & 31;
+      nxt[m] = (r < nb && jt + j < j1) ? M[(size_t)(b0 + r) * s + jt + j] : 0.0;
+    }
+  };
+  if (j0 < j1) load(j0);
   for (int jt = j0; jt < j1; jt += 32) {
-    const int w = min(32, j1 - jt);
-    for (int e = t; e < CB * 32; e += blockDim.x) {
-      const int r = e >> 5, j = e & 31;
-      mt[r][j] = (r < nb && j < w) ? M[(size_t)(b0 + r) * s + jt + j] : 0.0;
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+      const int e = t + 256 * m;
+      mt[e >> 5][e & 31] = nxt[m];
     }
     __syncthreads();
+    if (jt + 32 < j1) load(jt + 32);
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      const int e = t + k * 256;
-      if (e < npair) {
-        const int r = e / tw, c = e - r * tw;
-        double a = acc[k];
-        for (int j = 0; j < w; ++j) a += mt[r][j] * xs[(jt + j) * tw + c];
-        acc[k] = a;
+      if (t + k * 256 < npair) {
+        const int r = rk[k], c = ck[k];
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+#pragma unroll
+        for (int j = 0; j < 32; j += 4) {
+          a0 += mt[r][j] * xs[min(jt + j, s - 1) * tw + c];
+          a1 += mt[r][j + 1] * xs[min(jt + j + 1, s - 1) * tw + c];
+          a2 += mt[r][j + 2] * xs[min(jt + j + 2, s - 1) * tw + c];
+          a3 += mt[r][j + 3] * xs[min(jt + j + 3, s - 1) * tw + c];
+        }
+        acc[k] += (a0 + a1) + (a2 + a3);
       }
     }
     __syncthreads();
   }
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
-    const int e = t + k * 256;
-    if (e < npair) {
-      const int r = e / tw, c = e - r * tw;
-      xs[(b0 + r) * tw + c] -= acc[k];
-    }
+    if (t + k * 256 < npair) xs[(b0 + rk[k]) * tw + ck[k]] -= acc[k];
   }
   __syncthreads();
 }
@@ -380,39 +504,46 @@ __global__ void __launch_bounds__(64) k_top_diag_inv(int s, const double* __rest
                                                      int lower_unit, int upper_unit,
                                                      const int32_t* __restrict__ skip) {
   if (skip && *skip) return;
-  __shared__ double T[CB][CB + 1];
-  __shared__ double Z[CB][CB + 1];
+  __shared__ double T[CB][CB + 1];   // strict triangle of the part, zero elsewhere
+  __shared__ double Z[CB][CB + 1];   // the inverse, built row by row (zero = not yet)
+  __shared__ double rd[CB];          // 1 / diagonal (1 for a unit diagonal)
   const int kb = blockIdx.x, part = blockIdx.y;
   const int b0 = kb * CB, nb = min(CB, s - b0);
   const int c = threadIdx.x;
+  const bool unit = part == 0 ? lower_unit != 0 : upper_unit != 0;
   for (int e = c; e < CB * CB; e += 64) {
     const int r = e >> 6, j = e & 63;
-    T[r][j] = (r < nb && j < nb) ? M[(size_t)(b0 + r) * s + b0 + j] : 0.0;
+    const bool in = r < nb && j < nb && (part == 0 ? j < r : j > r);
+    T[r][j] = in ? M[(size_t)(b0 + r) * s + b0 + j] : 0.0;
+    Z[r][j] = 0.0;
   }
+  rd[c] = (unit || c >= nb) ? 1.0 : 1.0 / M[(size_t)(b0 + c) * s + b0 + c];
   __syncthreads();
-  if (part == 0) {
-    for (int i = 0; i < CB; ++i) {
-      double acc = (i == c) ? 1.0 : 0.0;
-      for (int j = 0; j < i; ++j) acc -= T[i][j] * Z[j][c];
-      if (!lower_unit && i < nb) acc /= T[i][i];
-      Z[i][c] = (i < nb && c < nb) ? acc : 0.0;
+  // lane c: column c of the inverse; row i needs rows solved before it
+  for (int k = 0; k < CB; ++k) {
+    const int i = part == 0 ? k : CB - 1 - k;
+    double a0 = (i == c) ? 1.0 : 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+#pragma unroll
+    for (int j = 0; j < CB; j += 4) {
+      a0 -= T[i][j] * Z[j][c];
+      a1 -= T[i][j + 1] * Z[j + 1][c];
+      a2 -= T[i][j + 2] * Z[j + 2][c];
+      a3 -= T[i][j + 3] * Z[j + 3][c];
     }
-  } else {
-    for (int i = CB - 1; i >= 0; --i) {
-      double acc = (i == c) ? 1.0 : 0.0;
-      for (int j = i + 1; j < CB; ++j) acc -= T[i][j] * Z[j][c];
-      if (!upper_unit && i < nb) acc /= T[i][i];
-      Z[i][c] = (i < nb && c < nb) ? acc : 0.0;
-    }
+    const double v = ((a0 + a1) + (a2 + a3)) * rd[i];
+    Z[i][c] = (i < nb && c < nb) ? v : 0.0;
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
   }
-  __syncthreads();
   double* out = dinv + (size_t)(kb * 2 + part) * CB * CB;
   for (int e = c; e < CB * CB; e += 64) out[e] = Z[e >> 6][e & 63];
 }
 
 // xs[b0 + r][c] <- sum_j D[r][j] xs[b0 + j][c] for the nb rows of one block
-// (D: a CB x CB inverse diagonal block staged through LDS).
-__device__ inline void top_diag_apply(const double* __restrict__ D, int b0, int nb, double* xs, int tw,
+// (D: a CB x CB inverse diagonal block, zero outside its nb x nb corner,
+// staged through LDS; the unrolled sum clamps xs rows to s - 1 where D is
+// zero).
+__device__ inline void top_diag_apply(const double* __restrict__ D, int s, int b0, int nb, double* xs, int tw,
                                       double (*dt)[CB + 1]) {
   const int t = threadIdx.x;
   for (int e = t; e < CB * CB; e += blockDim.x) dt[e >> 6][e & 63] = D[e];
@@ -424,14 +555,15 @@ __device__ inline void top_diag_apply(const double* __restrict__ D, int b0, int 
     const int e = t + k * 256;
     if (e < npair) {
       const int r = e / tw, c = e - r * tw;
-      double a0 = 0.0, a1 = 0.0;
-      int j = 0;
-      for (; j + 1 < nb; j += 2) {
-        a0 += dt[r][j] * xs[(b0 + j) * tw + c];
-        a1 += dt[r][j + 1] * xs[(b0 + j + 1) * tw + c];
+      double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+#pragma unroll
+      for (int j = 0; j < CB; j += 4) {
+        a0 += dt[r][j] * xs[min(b0 + j, s - 1) * tw + c];
+        a1 += dt[r][j + 1] * xs[min(b0 + j + 1, s - 1) * tw + c];
+        a2 += dt[r][j + 2] * xs[min(b0 + j + 2, s - 1) * tw + c];
+        a3 += dt[r][j + 3] * xs[min(b0 + j + 3, s - 1) * tw + c];
       }
-      if (j < nb) a0 += dt[r][j] * xs[(b0 + j) * tw + c];
-      acc[k] = a0 + a1;
+      acc[k] = (a0 + a1) + (a2 + a3);
     }
   }
   __syncthreads();
@@ -469,13 +601,13 @@ __global__ void __launch_bounds__(256) k_top_dense(int t0, int n, const double* 
   for (int b0 = 0, kb = 0; b0 < s; b0 += CB, ++kb) {
     const int nb = min(CB, s - b0);
     top_block_update(M, s, b0, nb, 0, b0, xs, tw, mt);
-    top_diag_apply(dinv + (size_t)(kb * 2) * CB * CB, b0, nb, xs, tw, dt);
+    top_diag_apply(dinv + (size_t)(kb * 2) * CB * CB, s, b0, nb, xs, tw, dt);
   }
   const int nblk = (s + CB - 1) / CB;
   for (int kb = nblk - 1; kb >= 0; --kb) {
     const int b0 = kb * CB, nb = min(CB, s - b0);
     top_block_update(M, s, b0, nb, b0 + nb, s, xs, tw, mt);
-    top_diag_apply(dinv + (size_t)(kb * 2 + 1) * CB * CB, b0, nb, xs, tw, dt);
+    top_diag_apply(dinv + (size_t)(kb * 2 + 1) * CB * CB, s, b0, nb, xs, tw, dt);
   }
   for (int e = t; e < s * tw; e += blockDim.x) {
     const int r = e / tw, c = e - r * tw;

@@ -502,6 +502,10 @@ Presolve build_presolve(const GridData& g, int subtree_max) {
     }
   }
   P.upd_tgt = std::move(tg);
+  // U-row start of the pivot row of every L entry (lu_diag[col] + 1)
+  P.rf_ustart.assign(nnz, 0);
+  for (int i = 0; i < nx; ++i)
+    for (int p = P.lu_ptr[i]; p < P.lu_diag[i]; ++p) P.rf_ustart[p] = P.lu_diag[P.lu_col[p]] + 1;
 
   // ------------------------------------------------------- branch locals
   P.br_var.assign((size_t)nl * 4, -1);

@@ -95,6 +95,7 @@ struct Presolve {
   // target positions in row i of U-row k entries beyond the diagonal
   std::vector<int64_t> upd_ptr;  // [nnz_lu + 1], only L entries non-empty
   std::vector<int32_t> upd_tgt;
+  std::vector<int32_t> rf_ustart;  // [nnz_lu], L entries: first U position of the pivot row
   int max_lu_row = 0;
 
   // gather lists.  Every J_x pattern position (including fill) is a slot;

@@ -63,6 +63,7 @@ struct rpf_grid {
   int32_t *lo_ptr, *lo_rows, *up_ptr, *up_rows;
   int64_t* upd_ptr;
   int32_t* upd_tgt;
+  int32_t* rf_ustart;
   int32_t *jx_sp, *jx_s;
   int32_t *ju_ptr, *ju_col, *ju_sp, *ju_s, *jut_ptr, *jut_col, *jut_pos;
   double* ju_const;
@@ -80,6 +81,7 @@ struct rpf_grid {
   int16_t *pkf_col, *pkb_col;
   int tw_pack = 8, tw_top = 8;
   size_t lds_packg = 0;   // LDS of the global-memory batched pack solves
+  size_t lds_rf = 0;      // LDS of the LDS-resident pack refactorization (0: not used)
   size_t lds_limit = 65536, lds_pack[5] = {0, 0, 0, 0, 0};
   double *c2, *c1, *c0;
 
@@ -186,6 +188,7 @@ void setup(rpf_grid* h) {
   h->up_rows = h->up(P.lev_up.rows);
   h->upd_ptr = h->up(P.upd_ptr);
   h->upd_tgt = h->up(P.upd_tgt);
+  h->rf_ustart = h->up(P.rf_ustart);
   h->jx_sp = h->up(P.jx_src_ptr);
   h->jx_s = h->up(P.jx_src);
   h->ju_ptr = h->up(P.ju_ptr);
@@ -294,6 +297,15 @@ void setup(rpf_grid* h) {
       const int nl = std::max(P.pk_flev_off[q + 1] - P.pk_flev_off[q], P.pk_blev_off[q + 1] - P.pk_blev_off[q]);
       h->lds_packg = std::max(h->lds_packg, packg_lds_bytes(nr, seg, nl));
     }
+    // LDS-resident refactorization: values of the pack's CSR rows + pivots
+    {
+      size_t mx = 0;
+      for (int q = 0; q < h->npacks; ++q) {
+        const int r0 = P.pack_ptr[q], nr = P.pack_ptr[q + 1] - r0;
+        mx = std::max(mx, (size_t)(P.lu_ptr[r0 + nr] - P.lu_ptr[r0] + nr) * sizeof(double));
+      }
+      h->lds_rf = mx <= h->lds_limit ? mx : 0;
+    }
     h->tw_pack = 0;
     for (int k = 0; k < 5; ++k)
       if (h->lds_pack[k] <= h->lds_limit) {
@@ -303,7 +315,7 @@ void setup(rpf_grid* h) {
     if (h->tw_pack == 0) throw std::runtime_error("a pack of subtrees does not fit in LDS");
     // the dense top solve also holds two static tiles (about 50 KB)
     const size_t top_static = 52 * 1024;
-    h->tw_top = 16;
+    h->tw_top = 4;   // 4 columns per workgroup: about one workgroup per CU at 1024 columns
     while (h->tw_top > 1 && (size_t)P.ntop * h->tw_top * 8 + top_static > h->lds_limit) h->tw_top /= 2;
     if ((size_t)P.ntop * 8 + top_static > h->lds_limit)
       throw std::runtime_error("top part of the elimination tree too large for LDS");
@@ -322,6 +334,7 @@ void setup(rpf_grid* h) {
   allow((const void*)k_pack_solve_s<TW, false, true>);      \
   allow((const void*)k_pack_solve_s<TW, false, false>);
     if (h->lds_packg > h->lds_limit) throw std::runtime_error("a pack of subtrees does not fit in LDS");
+    if (h->lds_rf > 0) allow((const void*)k_rf_pack_lds);
     allow((const void*)k_pack_solve_g<true, true>);
     allow((const void*)k_pack_solve_g<true, false>);
     allow((const void*)k_pack_solve_g<false, true>);
@@ -429,7 +442,12 @@ void refactor(rpf_grid* h, hipStream_t s, const int32_t* skip = nullptr) {
   const int wv = h->rf_waves;
   const size_t shm = (size_t)wv * maxrow * sizeof(double);
   size_t pi = h->prof_on ? h->prof_begin(s) : 0;
-  if (h->npacks > 0) {
+  if (h->npacks > 0 && h->lds_rf > 0) {
+    k_rf_pack_lds<<<h->npacks, 1024, h->lds_rf, s>>>(h->pack_ptr, h->pk_flev, h->pk_flev_off, h->pk_frows,
+                                                     h->lu_ptr, h->lu_col, h->lu_diag, h->rf_ustart, h->upd_ptr,
+                                                     h->upd_tgt, h->luv, h->rdiag, 1e-14, h->piv_status, skip);
+    LAUNCHCHK();
+  } else if (h->npacks > 0) {
     k_rf_pack<<<h->npacks, 64 * wv, shm, s>>>(h->pk_flev, h->pk_flev_off, h->pk_frows, h->lu_ptr, h->lu_col,
                                               h->lu_diag, h->upd_ptr, h->upd_tgt, h->luv, h->rdiag, maxrow,
                                               1e-14, h->piv_status, skip);
