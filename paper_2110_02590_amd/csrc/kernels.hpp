@@ -19,6 +19,47 @@ using rpf::RECW;
 using rpf::WREC;
 constexpr int CB = 64;  // dense block width
 
+// Staging through LDS issues all of a thread's loads before its first
+// store: a loop that stores each loaded value would wait for memory once
+// per iteration.  Addresses are clamped into the source block, so every
+// load is in bounds.
+
+// CB x CB tile: element (r, c) = src[r * ld + c] for r < nr, c < nc (nr,
+// nc >= 1); elsewhere diag_pad on the diagonal and 0 off it.  TRANS stores
+// dst[c][r].  NT = threads of the block.
+template <int NT, bool TRANS = false>
+__device__ inline void stage_tile(double (*dst)[CB + 1], const double* __restrict__ src, size_t ld, int nr, int nc,
+                                  double diag_pad) {
+  constexpr int PER = CB * CB / NT;
+  double v[PER];
+#pragma unroll
+  for (int m = 0; m < PER; ++m) {
+    const int e = threadIdx.x + m * NT, r = e >> 6, c = e & 63;
+    const double g = src[(size_t)min(r, nr - 1) * ld + min(c, nc - 1)];
+    v[m] = (r < nr && c < nc) ? g : (r == c ? diag_pad : 0.0);
+  }
+#pragma unroll
+  for (int m = 0; m < PER; ++m) {
+    const int e = threadIdx.x + m * NT, r = e >> 6, c = e & 63;
+    if (TRANS) dst[c][r] = v[m];
+    else dst[r][c] = v[m];
+  }
+}
+
+// dst[e] = src[e] for e < n, eight loads in flight per thread.
+template <class T>
+__device__ inline void stage_1d(T* dst, const T* __restrict__ src, int n) {
+  const int nt = blockDim.x;
+  for (int e0 = threadIdx.x; e0 < n; e0 += 8 * nt) {
+    T v[8];
+#pragma unroll
+    for (int m = 0; m < 8; ++m) v[m] = src[min(e0 + m * nt, n - 1)];
+#pragma unroll
+    for (int m = 0; m < 8; ++m)
+      if (e0 + m * nt < n) dst[e0 + m * nt] = v[m];
+  }
+}
+
 // ------------------------------------------------------------------ helpers
 __global__ void k_permute_gather(int n, const int32_t* __restrict__ idx, const double* __restrict__ src,
                                  double* __restrict__ dst,
@@ -273,8 +314,9 @@ __global__ void k_rf_pack(const int32_t* __restrict__ flev, const int32_t* __res
 // 64 elimination steps of a row (pivot column, U-row start, update range)
 // is loaded at once, lane s holding step s, and broadcast by readlane; the
 // update targets of step s + 2 are loaded during step s.  Reciprocal
-// pivots of finished rows go to LDS and to rdg.  LDS: values of the pack's
-// CSR rows [seg] | 1 / u_ii [nr].
+// pivots of finished rows go to LDS and to rdg.  upd_tgt must hold 64
+// readable entries past its end.  LDS: values of the pack's CSR rows [seg]
+// | 1 / u_ii [nr].
 __device__ inline int64_t readlane64(int64_t v, int s) {
   const int lo = __builtin_amdgcn_readlane((int)(uint32_t)(v & 0xffffffff), s);
   const int hi = __builtin_amdgcn_readlane((int)(v >> 32), s);
@@ -301,13 +343,16 @@ __global__ void __launch_bounds__(1024) k_rf_pack_lds(const int32_t* __restrict_
   const int gp0 = ptr[r0], seg = ptr[r0 + nr] - gp0;
   double* srd = sv + seg;
   const int t = threadIdx.x;
-  for (int e = t; e < seg; e += blockDim.x) sv[e] = a[gp0 + e];
+  stage_1d(sv, a + gp0, seg);
   __syncthreads();
   const int wave = t >> 6, lane = t & 63, nwave = blockDim.x >> 6;
   for (int lv = flev_off[q]; lv < flev_off[q + 1]; ++lv) {
     for (int rr = flev[lv] + wave; rr < flev[lv + 1]; rr += nwave) {
-      const int i = frows[rr];
-      const int p0 = ptr[i], pdg = diag[i], p1 = ptr[i + 1];
+      // row bounds are the same in every lane: keep them scalar
+      const int i = __builtin_amdgcn_readfirstlane(frows[rr]);
+      const int p0 = __builtin_amdgcn_readfirstlane(ptr[i]);
+      const int pdg = __builtin_amdgcn_readfirstlane(diag[i]);
+      const int p1 = __builtin_amdgcn_readfirstlane(ptr[i + 1]);
       double amax = 0.0;
       for (int e = p0 + lane; e < p1; e += 64) amax = fmax(amax, fabs(sv[e - gp0]));
       for (int w0 = p0; w0 < pdg; w0 += 64) {
@@ -321,36 +366,37 @@ __global__ void __launch_bounds__(1024) k_rf_pack_lds(const int32_t* __restrict_
           m_u0 = upd_ptr[p];
           m_nu = (int)(upd_ptr[p + 1] - m_u0);
         }
-        int tg_a = 0, tg_b = 0;
-        {
-          const int64_t u = readlane64(m_u0, 0);
-          if (lane < __builtin_amdgcn_readlane(m_nu, 0)) tg_a = upd_tgt[u + lane];
-        }
-        if (nw > 1) {
-          const int64_t u = readlane64(m_u0, 1);
-          if (lane < __builtin_amdgcn_readlane(m_nu, 1)) tg_b = upd_tgt[u + lane];
-        }
-        for (int s = 0; s < nw; ++s) {
-          const int k = __builtin_amdgcn_readlane(m_k, s);
-          const int us = __builtin_amdgcn_readlane(m_us, s) - gp0;
-          const int nu = __builtin_amdgcn_readlane(m_nu, s);
-          const int tg = tg_a - gp0;
-          tg_a = tg_b;
-          if (s + 2 < nw) {
-            const int64_t u2 = readlane64(m_u0, s + 2);
-            tg_b = lane < __builtin_amdgcn_readlane(m_nu, s + 2) ? upd_tgt[u2 + lane] : 0;
-          }
-          const int pl = w0 + s - gp0;
+        // targets of step s live in tgA (s even) or tgB (s odd); the load
+        // for step s + 2 is issued during step s into the same register
+        // unconditional loads (upd_tgt is padded past its end), so the
+        // compiler can count them and wait only for the older one
+        auto fetch_tg = [&](int st) -> int {
+          const int64_t u = readlane64(m_u0, st);
+          return upd_tgt[u + (lane < __builtin_amdgcn_readlane(m_nu, st) ? lane : 0)];
+        };
+        auto step = [&](int st, int tgabs) {
+          const int k = __builtin_amdgcn_readlane(m_k, st);
+          const int us = __builtin_amdgcn_readlane(m_us, st) - gp0;
+          const int nu = __builtin_amdgcn_readlane(m_nu, st);
+          const int pl = w0 + st - gp0;
           const double av = lane < nu ? sv[us + lane] : 0.0;
           const double l = sv[pl] * srd[k - r0];
-          if (lane < nu) sv[tg] -= l * av;
+          if (lane < nu) sv[tgabs - gp0] -= l * av;
           if (nu > 64) {
-            const int64_t u0 = readlane64(m_u0, s);
+            const int64_t u0 = readlane64(m_u0, st);
             for (int tt = lane + 64; tt < nu; tt += 64) sv[upd_tgt[u0 + tt] - gp0] -= l * sv[us + tt];
           }
           if (lane == 0) sv[pl] = l;
           __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
           __builtin_amdgcn_wave_barrier();
+        };
+        int tgA = fetch_tg(0);
+        int tgB = fetch_tg(min(1, nw - 1));
+        for (int st = 0; st < nw; st += 2) {
+          step(st, tgA);
+          tgA = fetch_tg(min(st + 2, nw - 1));
+          if (st + 1 < nw) step(st + 1, tgB);
+          tgB = fetch_tg(min(st + 3, nw - 1));
         }
       }
       for (int off = 32; off > 0; off >>= 1) amax = fmax(amax, __shfl_xor(amax, off, 64));
@@ -511,11 +557,17 @@ __global__ void __launch_bounds__(64) k_top_diag_inv(int s, const double* __rest
   const int b0 = kb * CB, nb = min(CB, s - b0);
   const int c = threadIdx.x;
   const bool unit = part == 0 ? lower_unit != 0 : upper_unit != 0;
-  for (int e = c; e < CB * CB; e += 64) {
-    const int r = e >> 6, j = e & 63;
-    const bool in = r < nb && j < nb && (part == 0 ? j < r : j > r);
-    T[r][j] = in ? M[(size_t)(b0 + r) * s + b0 + j] : 0.0;
-    Z[r][j] = 0.0;
+  {
+    // lane c loads column c of the block (all loads first, clamped)
+    double v[CB];
+#pragma unroll
+    for (int r = 0; r < CB; ++r) v[r] = M[(size_t)(b0 + min(r, nb - 1)) * s + b0 + min(c, nb - 1)];
+#pragma unroll
+    for (int r = 0; r < CB; ++r) {
+      const bool in = r < nb && c < nb && (part == 0 ? c < r : c > r);
+      T[r][c] = in ? v[r] : 0.0;
+      Z[r][c] = 0.0;
+    }
   }
   rd[c] = (unit || c >= nb) ? 1.0 : 1.0 / M[(size_t)(b0 + c) * s + b0 + c];
   __syncthreads();
@@ -546,7 +598,7 @@ __global__ void __launch_bounds__(64) k_top_diag_inv(int s, const double* __rest
 __device__ inline void top_diag_apply(const double* __restrict__ D, int s, int b0, int nb, double* xs, int tw,
                                       double (*dt)[CB + 1]) {
   const int t = threadIdx.x;
-  for (int e = t; e < CB * CB; e += blockDim.x) dt[e >> 6][e & 63] = D[e];
+  stage_tile<256>(dt, D, CB, CB, CB, 0.0);
   __syncthreads();
   const int npair = nb * tw;
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
@@ -650,9 +702,26 @@ __global__ void __launch_bounds__(256) k_pack_solve_s(const int32_t* __restrict_
   short* srow = (short*)(slev + nlev + 1);
   short* scol = srow + nr;
   const int t = threadIdx.x;
-  for (int e = t; e < ne; e += blockDim.x) {
-    sv[e] = val[epos[e0 + e]];
-    scol[e] = ecol[e0 + e];
+  for (int eb = t; eb < ne; eb += 4 * blockDim.x) {
+    int ps[4];
+    int16_t cs[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const int e = min(eb + m * (int)blockDim.x, ne - 1);
+      ps[m] = epos[e0 + e];
+      cs[m] = ecol[e0 + e];
+    }
+    double vs[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) vs[m] = val[ps[m]];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const int e = eb + m * (int)blockDim.x;
+      if (e < ne) {
+        sv[e] = vs[m];
+        scol[e] = cs[m];
+      }
+    }
   }
   for (int r = t; r <= nr; r += blockDim.x) srp[r] = rp[r0 + r] - e0;
   for (int r = t; r < nr; r += blockDim.x) {
@@ -780,7 +849,7 @@ __global__ void __launch_bounds__(1024) k_pack_solve_g(const int32_t* __restrict
   off = (off + 1) & ~(size_t)1;
   double* srd = (double*)(smi + off);
   const int t = threadIdx.x;
-  for (int e = t; e < seg; e += blockDim.x) scol[e] = col[gp0 + e];
+  stage_1d(scol, col + gp0, seg);
   for (int r = t; r <= nr; r += blockDim.x) sptr[r] = ptr[r0 + r] - gp0;
   for (int r = t; r < nr; r += blockDim.x) {
     const int dg = diag[r0 + r];
@@ -800,34 +869,187 @@ __global__ void __launch_bounds__(1024) k_pack_solve_g(const int32_t* __restrict
     const int segl = lane & (G - 1);
     for (int u = wave; u < units; u += nwave) {
       const int k = u >> lg, qch = u & (G - 1);
-      const int rl = srow[a + k];
+      // the unit's row is the same in every lane: keep its bounds scalar
+      const int rl = __builtin_amdgcn_readfirstlane(srow[a + k]);
       const int i = r0 + rl;
       const int c = c0 + (qch << (6 - lg)) + (lane >> lg);
       const bool cok = c < ncols;
-      const int e0 = FWD ? sptr[rl] : sdiag[rl] + 1;
-      const int e1 = FWD ? sdiag[rl] : sptr[rl + 1];
+      const int cl = cok ? c : ncols - 1;   // in-bounds column for loads
+      const int e0 = __builtin_amdgcn_readfirstlane(FWD ? sptr[rl] : sdiag[rl] + 1);
+      const int e1 = __builtin_amdgcn_readfirstlane(FWD ? sdiag[rl] : sptr[rl + 1]);
+      const size_t xi = (size_t)i * ld + cl;
+      const double xown = X[xi];
+      // entries in groups of 8 G: eight independent loads per lane in flight,
+      // out-of-range slots read entry e0 with weight zero
       double q0 = 0.0, q1 = 0.0, q2 = 0.0, q3 = 0.0;
-      if (cok) {
-        int e = e0 + segl;
-        for (; e + 3 * G < e1; e += 4 * G) {
-          const int j0 = scol[e], j1 = scol[e + G], j2 = scol[e + 2 * G], j3 = scol[e + 3 * G];
-          q0 += val[gp0 + e] * X[(size_t)j0 * ld + c];
-          q1 += val[gp0 + e + G] * X[(size_t)j1 * ld + c];
-          q2 += val[gp0 + e + 2 * G] * X[(size_t)j2 * ld + c];
-          q3 += val[gp0 + e + 3 * G] * X[(size_t)j3 * ld + c];
+      for (int eb = e0; eb < e1; eb += 8 * G) {
+        double v[8], xv[8];
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {
+          const int e = eb + m * G + segl;
+          const bool in = e < e1;
+          const int ec = in ? e : e0;
+          v[m] = in ? val[gp0 + ec] : 0.0;
+          xv[m] = X[(size_t)scol[ec] * ld + cl];
         }
-        for (; e < e1; e += G) q0 += val[gp0 + e] * X[(size_t)scol[e] * ld + c];
+        q0 += v[0] * xv[0] + v[4] * xv[4];
+        q1 += v[1] * xv[1] + v[5] * xv[5];
+        q2 += v[2] * xv[2] + v[6] * xv[6];
+        q3 += v[3] * xv[3] + v[7] * xv[7];
       }
       double part = (q0 + q1) + (q2 + q3);
       for (int o = G >> 1; o > 0; o >>= 1) part += __shfl_xor(part, o, 64);
       if (cok && segl == 0) {
-        const size_t xi = (size_t)i * ld + c;
-        double v = (FWD ? scale * X[xi] : X[xi]) - part;
-        if (!UNIT) v *= srd[rl];
-        X[xi] = v;
+        double xnew = (FWD ? scale * xown : xown) - part;
+        if (!UNIT) xnew *= srd[rl];
+        X[xi] = xnew;
       }
     }
     __syncthreads();
+  }
+}
+
+// Batched pack solves with the pack's right-hand-side tile in LDS: one
+// workgroup of 1024 threads per (pack, TW-column tile).  Staged in LDS: the
+// tile X[r0 .. r1) x [c0, c0 + TW) (forward: times scale; backward: minus
+// the products with the final top rows), and the pack program of the
+// direction: local columns (int16), row pointers, rows in level order,
+// level offsets.  Factor values come from pval, a copy in program order
+// (one load per entry); 1 / u_ii from rdg (non-unit factors).  Per level a
+// wavefront covers R rows x TW columns (lanes: column fastest, then G lanes
+// sharing one row's entries, then R row slots; R G TW = 64); R shrinks on
+// narrow levels so that more lanes share a row.  Eight entries per lane are
+// in flight at a time.
+// LDS: xs[nr TW] (double) | srp[nr + 1] | slev[nlev + 1] (int) | srow[nr] |
+// scol[ne] (int16).
+__host__ __device__ inline size_t packt_lds_bytes(int nr, int ne, int nlev, int tw) {
+  return (size_t)nr * tw * 8 + (size_t)(nr + 1) * 4 + (size_t)(nlev + 1) * 4 + (size_t)nr * 2 + (size_t)ne * 2 + 16;
+}
+
+template <int TW, bool FWD, bool UNIT>
+__global__ void __launch_bounds__(1024) k_pack_solve_t(const int32_t* __restrict__ pack_ptr,
+                                                       const int32_t* __restrict__ lev,
+                                                       const int32_t* __restrict__ lev_off,
+                                                       const int32_t* __restrict__ lrows,
+                                                       const int32_t* __restrict__ rp,
+                                                       const int16_t* __restrict__ ecol,
+                                                       const double* __restrict__ pval,
+                                                       const double* __restrict__ rdg,
+                                                       const int32_t* __restrict__ up_split,
+                                                       const int32_t* __restrict__ ptr,
+                                                       const int32_t* __restrict__ col,
+                                                       const double* __restrict__ val, double* __restrict__ X,
+                                                       int ld, int ncols, double scale,
+                                                       const int32_t* __restrict__ skip) {
+  if (skip && *skip) return;
+  constexpr int S = 64 / TW;   // lanes per column in a wavefront
+  constexpr int LGS = S == 8 ? 3 : S == 4 ? 2 : S == 2 ? 1 : 0;
+  extern __shared__ double smem[];
+  const int q = blockIdx.x;
+  const int c0 = blockIdx.y * TW;
+  const int r0 = pack_ptr[q], nr = pack_ptr[q + 1] - r0;
+  const int e0 = rp[r0], ne = rp[r0 + nr] - e0;
+  const int l0 = lev_off[q], nlev = lev_off[q + 1] - l0;
+  const int base_row = lev[l0];
+  double* xs = smem;
+  int* srp = (int*)(xs + (size_t)nr * TW);
+  int* slev = srp + nr + 1;
+  int16_t* srow = (int16_t*)(slev + nlev + 1);
+  int16_t* scol = srow + nr;
+  const int t = threadIdx.x, nt = blockDim.x;
+  stage_1d(scol, ecol + e0, ne);
+  for (int r = t; r <= nr; r += nt) srp[r] = rp[r0 + r] - e0;
+  for (int r = t; r < nr; r += nt) srow[r] = (int16_t)(lrows[base_row + r] - r0);
+  for (int k = t; k <= nlev; k += nt) slev[k] = lev[l0 + k] - base_row;
+  // right-hand-side tile, eight loads in flight per thread
+  const int ntile = nr * TW;
+  for (int eb = t; eb < ntile; eb += 8 * nt) {
+    double v[8];
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+      const int e = min(eb + m * nt, ntile - 1);
+      const int r = e / TW, c = e - r * TW;
+      v[m] = X[(size_t)(r0 + r) * ld + min(c0 + c, ncols - 1)];
+    }
+#pragma unroll
+    for (int m = 0; m < 8; ++m)
+      if (eb + m * nt < ntile) xs[eb + m * nt] = FWD ? scale * v[m] : v[m];
+  }
+  if (!FWD) {
+    // products with the final top rows (same thread as the element's load)
+    for (int e = t; e < ntile; e += nt) {
+      const int r = e / TW, c = e - r * TW;
+      const int cc = min(c0 + c, ncols - 1);
+      const int i = r0 + r;
+      const int p0 = up_split[i], p1 = ptr[i + 1];
+      double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+      for (int pb = p0; pb < p1; pb += 4) {
+        int jj[4];
+        double vv[4];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+          const int pc = min(pb + m, p1 - 1);
+          jj[m] = col[pc];
+          const double raw = val[pc];
+          vv[m] = pb + m < p1 ? raw : 0.0;
+        }
+        a0 += vv[0] * X[(size_t)jj[0] * ld + cc];
+        a1 += vv[1] * X[(size_t)jj[1] * ld + cc];
+        a2 += vv[2] * X[(size_t)jj[2] * ld + cc];
+        a3 += vv[3] * X[(size_t)jj[3] * ld + cc];
+      }
+      xs[e] -= (a0 + a1) + (a2 + a3);
+    }
+  }
+  __syncthreads();
+  const int wave = t >> 6, lane = t & 63, nwave = nt >> 6;
+  const int cI = lane & (TW - 1);
+  const int sub = lane / TW;   // 0 .. S - 1
+  for (int lv = 0; lv < nlev; ++lv) {
+    const int a = slev[lv], nrow = slev[lv + 1] - a;
+    // R = 2^lgR rows per wavefront, G = S / R lanes per (row, column)
+    int lgR = LGS;
+    while (lgR > 0 && nrow <= (nwave << (lgR - 1))) --lgR;
+    const int lgG = LGS - lgR;
+    const int G = 1 << lgG;
+    const int rowslot = sub >> lgG, seg = sub & (G - 1);
+    for (int base = 0; base < nrow; base += nwave << lgR) {
+      const int k = base + (wave << lgR) + rowslot;
+      const bool act = k < nrow;
+      const int rl = act ? srow[a + k] : 0;
+      double q0 = 0.0, q1 = 0.0, q2 = 0.0, q3 = 0.0;
+      if (act) {
+        const int es = srp[rl], ee = srp[rl + 1];
+        for (int eb = es + seg; eb < ee; eb += 8 * G) {
+          double vv[8], xv[8];
+#pragma unroll
+          for (int m = 0; m < 8; ++m) {
+            const int e = eb + m * G;
+            const bool in = e < ee;
+            const int ec = in ? e : es;
+            const double raw = pval[e0 + ec];
+            vv[m] = in ? raw : 0.0;
+            xv[m] = xs[scol[ec] * TW + cI];
+          }
+          q0 += vv[0] * xv[0] + vv[4] * xv[4];
+          q1 += vv[1] * xv[1] + vv[5] * xv[5];
+          q2 += vv[2] * xv[2] + vv[6] * xv[6];
+          q3 += vv[3] * xv[3] + vv[7] * xv[7];
+        }
+      }
+      double part = (q0 + q1) + (q2 + q3);
+      for (int o = G >> 1; o > 0; o >>= 1) part += __shfl_xor(part, o * TW, 64);
+      if (act && seg == 0) {
+        double v = xs[rl * TW + cI] - part;
+        if (!UNIT) v *= rdg[r0 + rl];
+        xs[rl * TW + cI] = v;
+      }
+    }
+    __syncthreads();
+  }
+  for (int e = t; e < ntile; e += nt) {
+    const int r = e / TW, c = e - r * TW;
+    if (c0 + c < ncols) X[(size_t)(r0 + r) * ld + c0 + c] = xs[e];
   }
 }
 
@@ -842,14 +1064,27 @@ __global__ void k_spmm(int nrows, const int32_t* __restrict__ ptr, const int32_t
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   const int i = blockIdx.y * blockDim.y + threadIdx.y;
   if (i >= nrows || c >= ncols) return;
-  double acc = 0.0;
-  for (int p = ptr[i]; p < ptr[i + 1]; ++p) {
-    const int j = colidx[p];
-    double v = val[valpos ? valpos[p] : p];
-    if (xscale) v *= xscale[j];
-    acc += v * X[(size_t)j * ldx + c];
+  // four entries per step, loads unconditional (clamped), four partial sums
+  const int p0 = ptr[i], p1 = ptr[i + 1];
+  double a[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int pb = p0; pb < p1; pb += 4) {
+    int jj[4];
+    double vv[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const int pc = min(pb + m, p1 - 1);
+      jj[m] = colidx[pc];
+      const double raw = val[valpos ? valpos[pc] : pc];
+      vv[m] = pb + m < p1 ? raw : 0.0;
+    }
+    if (xscale) {
+#pragma unroll
+      for (int m = 0; m < 4; ++m) vv[m] *= xscale[jj[m]];
+    }
+#pragma unroll
+    for (int m = 0; m < 4; ++m) a[m] += vv[m] * X[(size_t)jj[m] * ldx + c];
   }
-  acc *= alpha;
+  double acc = ((a[0] + a[1]) + (a[2] + a[3])) * alpha;
   if (Yadd) acc += Yadd[(size_t)i * ldya + c];
   Y[(size_t)i * ldy + c] = acc;
 }
@@ -1251,10 +1486,7 @@ __global__ void __launch_bounds__(256) k_blk_diag(int n, int b0, double* __restr
   const int t = threadIdx.x;
   // coalesced load through LDS; outside the nb x nb corner an identity, so
   // the padded pivots are 1 and leave the corner's factor unchanged
-  for (int e = t; e < CB * CB; e += 256) {
-    const int r = e >> 6, c = e & 63;
-    tile[r][c] = (r < nb && c < nb) ? A[(size_t)(b0 + r) * n + b0 + c] : (r == c ? 1.0 : 0.0);
-  }
+  stage_tile<256>(tile, A + (size_t)b0 * n + b0, n, nb, nb, 1.0);
   __syncthreads();
   // thread (tr, tc) holds rows 4 tr .. 4 tr + 3, columns 4 tc .. 4 tc + 3
   const int tr = t >> 4, tc = t & 15;
@@ -1357,10 +1589,7 @@ __global__ void k_blk_panel(int n, int b0, double* __restrict__ A, const int32_t
   if (info[0] != 0) return;
   const int nb = min(CB, n - b0);
   const int rest = n - b0 - nb;
-  for (int e = threadIdx.x; e < CB * CB; e += blockDim.x) {
-    const int r = e / CB, c = e % CB;
-    T[r][c] = (r < nb && c < nb) ? A[(size_t)(b0 + r) * n + b0 + c] : (r == c ? 1.0 : 0.0);
-  }
+  stage_tile<256>(T, A + (size_t)b0 * n + b0, n, nb, nb, 1.0);
   __syncthreads();
   for (int j = threadIdx.x; j < CB; j += blockDim.x) rd[j] = 1.0 / T[j][j];
   __syncthreads();
@@ -1399,14 +1628,11 @@ __global__ void k_blk_update(int n, int b0, double* __restrict__ A, const int32_
   const int ti = blockIdx.y, tj = blockIdx.x;
   if (CHOL && tj > ti) return;
   const int i0 = base + ti * CB, j0 = base + tj * CB;
-  for (int e = threadIdx.x; e < CB * CB; e += blockDim.x) {
-    const int r = e / CB, k = e % CB;
-    Ls[r][k] = (i0 + r < n && k < nb) ? A[(size_t)(i0 + r) * n + b0 + k] : 0.0;
-    if (CHOL)
-      Us[k][r] = (j0 + r < n && k < nb) ? A[(size_t)(j0 + r) * n + b0 + k] : 0.0;
-    else
-      Us[r][k] = (r < nb && j0 + k < n) ? A[(size_t)(b0 + r) * n + j0 + k] : 0.0;
-  }
+  stage_tile<256>(Ls, A + (size_t)i0 * n + b0, n, n - i0, nb, 0.0);
+  if (CHOL)
+    stage_tile<256, true>(Us, A + (size_t)j0 * n + b0, n, n - j0, nb, 0.0);
+  else
+    stage_tile<256>(Us, A + (size_t)b0 * n + j0, n, nb, n - j0, 0.0);
   __syncthreads();
   const int tr = (threadIdx.x >> 4) * 4, tc = (threadIdx.x & 15) * 4;
   double acc[4][4] = {};
@@ -1486,10 +1712,7 @@ __global__ void __launch_bounds__(256) k_chol_fwd(int n, const double* __restric
   const int b0 = w * CB, nb = min(CB, n - b0);
   const int t = threadIdx.x;
   // diagonal block and reciprocal pivots first (no dependency)
-  for (int e = t; e < CB * CB; e += 256) {
-    const int r = e >> 6, c = e & 63;
-    tri[r][c] = (r < nb && c < nb) ? L[(size_t)(b0 + r) * n + b0 + c] : (r == c ? 1.0 : 0.0);
-  }
+  stage_tile<256>(tri, L + (size_t)b0 * n + b0, n, nb, nb, 1.0);
   __syncthreads();
   if (t < CB) rd[t] = 1.0 / tri[t][t];
   // products with the solved blocks: thread (row r, slice sl of 16 columns)
@@ -1541,10 +1764,7 @@ __global__ void __launch_bounds__(256) k_chol_bwd(int n, const double* __restric
   const int w = nblk - 1 - blockIdx.x;
   const int b0 = w * CB, nb = min(CB, n - b0);
   const int t = threadIdx.x;
-  for (int e = t; e < CB * CB; e += 256) {
-    const int r = e >> 6, c = e & 63;
-    tri[r][c] = (r < nb && c < nb) ? L[(size_t)(b0 + r) * n + b0 + c] : (r == c ? 1.0 : 0.0);
-  }
+  stage_tile<256>(tri, L + (size_t)b0 * n + b0, n, nb, nb, 1.0);
   __syncthreads();
   if (t < CB) rd[t] = 1.0 / tri[t][t];
   // products with the solved blocks: lane i = column b0 + i of L (row of

@@ -82,6 +82,10 @@ struct rpf_grid {
   int tw_pack = 8, tw_top = 8;
   size_t lds_packg = 0;   // LDS of the global-memory batched pack solves
   size_t lds_rf = 0;      // LDS of the LDS-resident pack refactorization (0: not used)
+  int tw_packt = 0;       // column tile of the LDS-tile batched pack solves (0: not used)
+  size_t lds_packt = 0;
+  // factor values in pack-program order: forward / backward, J_x / J_x^T
+  double *pkfv = nullptr, *pkbv = nullptr, *pkfvT = nullptr, *pkbvT = nullptr;
   size_t lds_limit = 65536, lds_pack[5] = {0, 0, 0, 0, 0};
   double *c2, *c1, *c0;
 
@@ -187,7 +191,12 @@ void setup(rpf_grid* h) {
   h->up_ptr = h->up(P.lev_up.ptr);
   h->up_rows = h->up(P.lev_up.rows);
   h->upd_ptr = h->up(P.upd_ptr);
-  h->upd_tgt = h->up(P.upd_tgt);
+  {
+    // padded by 64 entries: the refactorization loads targets unconditionally
+    std::vector<int32_t> tg(P.upd_tgt);
+    tg.resize(tg.size() + 64, 0);
+    h->upd_tgt = h->up(tg);
+  }
   h->rf_ustart = h->up(P.rf_ustart);
   h->jx_sp = h->up(P.jx_src_ptr);
   h->jx_s = h->up(P.jx_src);
@@ -267,6 +276,10 @@ void setup(rpf_grid* h) {
   h->pkb_rp = h->up(P.pkb_rp);
   h->pkb_pos = h->up(P.pkb_pos);
   h->pkb_col = h->up(P.pkb_col);
+  h->pkfv = h->alloc<double>(std::max<size_t>(P.pkf_pos.size(), 1));
+  h->pkfvT = h->alloc<double>(std::max<size_t>(P.pkf_pos.size(), 1));
+  h->pkbv = h->alloc<double>(std::max<size_t>(P.pkb_pos.size(), 1));
+  h->pkbvT = h->alloc<double>(std::max<size_t>(P.pkb_pos.size(), 1));
   h->dense_top = h->alloc<double>((size_t)P.ntop * P.ntop);
   h->dense_topT = h->alloc<double>((size_t)P.ntop * P.ntop);
   h->top_dinv = h->alloc<double>((size_t)cdiv(P.ntop, CB) * 2 * CB * CB);
@@ -296,6 +309,22 @@ void setup(rpf_grid* h) {
       const int seg = P.lu_ptr[r0 + nr] - P.lu_ptr[r0];
       const int nl = std::max(P.pk_flev_off[q + 1] - P.pk_flev_off[q], P.pk_blev_off[q + 1] - P.pk_blev_off[q]);
       h->lds_packg = std::max(h->lds_packg, packg_lds_bytes(nr, seg, nl));
+    }
+    // LDS-tile batched pack solves: 16-column tiles when the largest pack
+    // fits, else 8
+    for (int tw : {16, 8}) {
+      size_t mx = 0;
+      for (int q = 0; q < h->npacks; ++q) {
+        const int r0 = P.pack_ptr[q], nr = P.pack_ptr[q + 1] - r0;
+        const int nef = P.pkf_rp[r0 + nr] - P.pkf_rp[r0], neb = P.pkb_rp[r0 + nr] - P.pkb_rp[r0];
+        const int nlf = P.pk_flev_off[q + 1] - P.pk_flev_off[q], nlb = P.pk_blev_off[q + 1] - P.pk_blev_off[q];
+        mx = std::max(mx, packt_lds_bytes(nr, std::max(nef, neb), std::max(nlf, nlb), tw));
+      }
+      if (mx <= h->lds_limit) {
+        h->tw_packt = tw;
+        h->lds_packt = mx;
+        break;
+      }
     }
     // LDS-resident refactorization: values of the pack's CSR rows + pivots
     {
@@ -335,6 +364,14 @@ void setup(rpf_grid* h) {
   allow((const void*)k_pack_solve_s<TW, false, false>);
     if (h->lds_packg > h->lds_limit) throw std::runtime_error("a pack of subtrees does not fit in LDS");
     if (h->lds_rf > 0) allow((const void*)k_rf_pack_lds);
+#define RPF_ALLOW_PACKT(TW)                                 \
+  allow((const void*)k_pack_solve_t<TW, true, true>);       \
+  allow((const void*)k_pack_solve_t<TW, true, false>);      \
+  allow((const void*)k_pack_solve_t<TW, false, true>);      \
+  allow((const void*)k_pack_solve_t<TW, false, false>);
+    if (h->tw_packt == 16) { RPF_ALLOW_PACKT(16) }
+    if (h->tw_packt == 8) { RPF_ALLOW_PACKT(8) }
+#undef RPF_ALLOW_PACKT
     allow((const void*)k_pack_solve_g<true, true>);
     allow((const void*)k_pack_solve_g<true, false>);
     allow((const void*)k_pack_solve_g<false, true>);
@@ -514,9 +551,36 @@ void pack_solve(rpf_grid* h, bool fwd, bool unit, const double* val, double* X, 
 
 // Many right-hand sides: one workgroup of 1024 threads per (pack, 64 columns),
 // solved in place in X.
-void pack_solve_g(rpf_grid* h, bool fwd, bool unit, const double* val, double* X, int ld, int ncols, double scale,
-                  int cls, hipStream_t s, const int32_t* skip) {
+template <int TW>
+void pack_solve_t(rpf_grid* h, bool fwd, bool unit, bool transposed, const double* val, double* X, int ld,
+                  int ncols, double scale, hipStream_t s, const int32_t* skip) {
+  dim3 grd(h->npacks, cdiv(ncols, TW));
+  const double* pv = fwd ? (transposed ? h->pkfvT : h->pkfv) : (transposed ? h->pkbvT : h->pkbv);
+  auto launch = [&](auto kern, const int32_t* lev, const int32_t* lev_off, const int32_t* rows, const int32_t* rp,
+                    const int16_t* ecol) {
+    kern<<<grd, 1024, h->lds_packt, s>>>(h->pack_ptr, lev, lev_off, rows, rp, ecol, pv, h->rdiag, h->up_split,
+                                         h->lu_ptr, h->lu_col, val, X, ld, ncols, scale, skip);
+  };
+  if (fwd) {
+    if (unit) launch(k_pack_solve_t<TW, true, true>, h->pk_flev, h->pk_flev_off, h->pk_frows, h->pkf_rp, h->pkf_col);
+    else launch(k_pack_solve_t<TW, true, false>, h->pk_flev, h->pk_flev_off, h->pk_frows, h->pkf_rp, h->pkf_col);
+  } else {
+    if (unit) launch(k_pack_solve_t<TW, false, true>, h->pk_blev, h->pk_blev_off, h->pk_brows, h->pkb_rp, h->pkb_col);
+    else launch(k_pack_solve_t<TW, false, false>, h->pk_blev, h->pk_blev_off, h->pk_brows, h->pkb_rp, h->pkb_col);
+  }
+  LAUNCHCHK();
+}
+
+void pack_solve_g(rpf_grid* h, bool fwd, bool unit, bool transposed, const double* val, double* X, int ld,
+                  int ncols, double scale, int cls, hipStream_t s, const int32_t* skip) {
   if (h->npacks == 0) return;
+  if (h->tw_packt > 0) {
+    size_t pi = h->prof_on ? h->prof_begin(s) : 0;
+    if (h->tw_packt == 16) pack_solve_t<16>(h, fwd, unit, transposed, val, X, ld, ncols, scale, s, skip);
+    else pack_solve_t<8>(h, fwd, unit, transposed, val, X, ld, ncols, scale, s, skip);
+    if (h->prof_on) h->prof_end(cls, pi, s);
+    return;
+  }
   dim3 grd(h->npacks, cdiv(ncols, 64));
   size_t pi = h->prof_on ? h->prof_begin(s) : 0;
   auto launch = [&](auto kern, const int32_t* lev, const int32_t* lev_off, const int32_t* rows) {
@@ -534,9 +598,9 @@ void pack_solve_g(rpf_grid* h, bool fwd, bool unit, const double* val, double* X
   if (h->prof_on) h->prof_end(cls, pi, s);
 }
 
-void pack_solve_any(rpf_grid* h, int tw, bool fwd, bool unit, const double* val, double* X, int ld, int ncols,
-                    double scale, int cls, hipStream_t s, const int32_t* skip) {
-  if (ncols > 1) return pack_solve_g(h, fwd, unit, val, X, ld, ncols, scale, cls, s, skip);
+void pack_solve_any(rpf_grid* h, int tw, bool fwd, bool unit, bool transposed, const double* val, double* X,
+                    int ld, int ncols, double scale, int cls, hipStream_t s, const int32_t* skip) {
+  if (ncols > 1) return pack_solve_g(h, fwd, unit, transposed, val, X, ld, ncols, scale, cls, s, skip);
   switch (tw) {
     case 16: return pack_solve<16>(h, fwd, unit, val, X, ld, ncols, scale, cls, s, skip);
     case 8: return pack_solve<8>(h, fwd, unit, val, X, ld, ncols, scale, cls, s, skip);
@@ -559,7 +623,7 @@ void solve_pair(rpf_grid* h, bool transposed, double* X, int ld, int ncols, doub
   const int cls = ncols > 1 ? 0 : 1;
   const int twp = ncols == 1 ? 1 : h->tw_pack;
   const int twt = ncols == 1 ? 1 : h->tw_top;
-  pack_solve_any(h, twp, true, fwd_unit, val, X, ld, ncols, scale, cls, s, skip);
+  pack_solve_any(h, twp, true, fwd_unit, transposed, val, X, ld, ncols, scale, cls, s, skip);
   if (P.ntop > 0) {
     size_t pi = h->prof_on ? h->prof_begin(s) : 0;
     int bx = 64;
@@ -576,7 +640,7 @@ void solve_pair(rpf_grid* h, bool transposed, double* X, int ld, int ncols, doub
     LAUNCHCHK();
     if (h->prof_on) h->prof_end(cls == 0 ? 5 : cls, pi, s);
   }
-  pack_solve_any(h, twp, false, !fwd_unit, val, X, ld, ncols, 1.0, cls, s, skip);
+  pack_solve_any(h, twp, false, !fwd_unit, transposed, val, X, ld, ncols, 1.0, cls, s, skip);
 }
 
 void spmm(rpf_grid* h, int nrows, const int32_t* ptr, const int32_t* col, const double* val,
@@ -895,6 +959,22 @@ void gradient_core(rpf_grid* h, const double* u, const double* pd, const double*
   k_fill_int<<<1, 4, 0, s>>>(4, h->piv_status, 0);
   LAUNCHCHK();
   refactor(h, s);
+  // factor values in pack-program order for the batched solves
+  if (h->tw_packt > 0) {
+    const int nf = (int)P.pkf_pos.size(), nb_ = (int)P.pkb_pos.size();
+    if (nf > 0) {
+      k_gather_pos<<<cdiv(nf, 256), 256, 0, s>>>(nf, h->pkf_pos, h->luv, h->pkfv, nullptr);
+      LAUNCHCHK();
+      k_gather_pos<<<cdiv(nf, 256), 256, 0, s>>>(nf, h->pkf_pos, h->lutv, h->pkfvT, nullptr);
+      LAUNCHCHK();
+    }
+    if (nb_ > 0) {
+      k_gather_pos<<<cdiv(nb_, 256), 256, 0, s>>>(nb_, h->pkb_pos, h->luv, h->pkbv, nullptr);
+      LAUNCHCHK();
+      k_gather_pos<<<cdiv(nb_, 256), 256, 0, s>>>(nb_, h->pkb_pos, h->lutv, h->pkbvT, nullptr);
+      LAUNCHCHK();
+    }
+  }
   k_copy_vec<<<cdiv(P.nx, 256), 256, 0, s>>>(P.nx, h->varg, h->lam, nullptr);
   LAUNCHCHK();
   solve_pair(h, true, h->lam, 1, 1, -1.0, s);
