@@ -46,6 +46,15 @@ __device__ inline void stage_tile(double (*dst)[CB + 1], const double* __restric
   }
 }
 
+// Workgroup barrier for kernels whose threads communicate only through LDS:
+// waits for the thread's LDS operations, not for its global loads, so
+// prefetched global data can stay in flight across the barrier.
+__device__ inline void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // dst[e] = src[e] for e < n, eight loads in flight per thread.
 template <class T>
 __device__ inline void stage_1d(T* dst, const T* __restrict__ src, int n) {
@@ -410,7 +419,7 @@ __global__ void __launch_bounds__(1024) k_rf_pack_lds(const int32_t* __restrict_
       __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
       __builtin_amdgcn_wave_barrier();
     }
-    __syncthreads();
+    lds_barrier();
   }
   for (int e = t; e < seg; e += blockDim.x) a[gp0 + e] = sv[e];
 }
@@ -488,7 +497,7 @@ __device__ inline void top_block_update(const double* __restrict__ M, int s, int
       const int e = t + 256 * m;
       mt[e >> 5][e & 31] = nxt[m];
     }
-    __syncthreads();
+    lds_barrier();
     if (jt + 32 < j1) load(jt + 32);
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
@@ -505,13 +514,13 @@ __device__ inline void top_block_update(const double* __restrict__ M, int s, int
         acc[k] += (a0 + a1) + (a2 + a3);
       }
     }
-    __syncthreads();
+    lds_barrier();
   }
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     if (t + k * 256 < npair) xs[(b0 + rk[k]) * tw + ck[k]] -= acc[k];
   }
-  __syncthreads();
+  lds_barrier();
 }
 
 // Right-hand side of the top rows: X[i, c] <- scale X[i, c] - sum_p f(p)
@@ -538,6 +547,36 @@ __global__ void k_top_rhs(int t0, int n, const int32_t* __restrict__ lo_split, c
   }
   for (; p < p1; ++p) q0 += fval[p] * X[(size_t)col[p] * ld + c];
   X[(size_t)i * ld + c] = scale * X[(size_t)i * ld + c] - ((q0 + q1) + (q2 + q3));
+}
+
+// Products of the pack rows with the solved top rows, before the backward
+// pack solves: X[i, c] -= sum_p f(p) X[col(p), c] over the upper entries
+// of pack row i in top columns ([up_split[i], ptr[i+1])).  Reads only top
+// rows, so in place.  One thread per (row, column), four partial sums.
+__global__ void k_pack_topmul(int t0, const int32_t* __restrict__ up_split, const int32_t* __restrict__ ptr,
+                              const int32_t* __restrict__ col, const double* __restrict__ fval,
+                              double* __restrict__ X, int ld, int ncols, const int32_t* __restrict__ skip) {
+  if (skip && *skip) return;
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = blockIdx.y * blockDim.y + threadIdx.y;
+  if (i >= t0 || c >= ncols) return;
+  const int p0 = up_split[i], p1 = ptr[i + 1];
+  if (p0 == p1) return;
+  double a[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int pb = p0; pb < p1; pb += 4) {
+    int jj[4];
+    double vv[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const int pc = min(pb + m, p1 - 1);
+      jj[m] = col[pc];
+      const double raw = fval[pc];
+      vv[m] = pb + m < p1 ? raw : 0.0;
+    }
+#pragma unroll
+    for (int m = 0; m < 4; ++m) a[m] += vv[m] * X[(size_t)jj[m] * ld + c];
+  }
+  X[(size_t)i * ld + c] -= (a[0] + a[1]) + (a[2] + a[3]);
 }
 
 // Inverses of the CB x CB diagonal blocks of a dense factor M (s x s,
@@ -599,7 +638,7 @@ __device__ inline void top_diag_apply(const double* __restrict__ D, int s, int b
                                       double (*dt)[CB + 1]) {
   const int t = threadIdx.x;
   stage_tile<256>(dt, D, CB, CB, CB, 0.0);
-  __syncthreads();
+  lds_barrier();
   const int npair = nb * tw;
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
@@ -618,7 +657,7 @@ __device__ inline void top_diag_apply(const double* __restrict__ D, int s, int b
       acc[k] = (a0 + a1) + (a2 + a3);
     }
   }
-  __syncthreads();
+  lds_barrier();
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     const int e = t + k * 256;
@@ -627,7 +666,7 @@ __device__ inline void top_diag_apply(const double* __restrict__ D, int s, int b
       xs[(b0 + r) * tw + c] = acc[k];
     }
   }
-  __syncthreads();
+  lds_barrier();
 }
 
 // Dense forward and backward solves of the top rows (after k_top_rhs) with
@@ -911,8 +950,9 @@ __global__ void __launch_bounds__(1024) k_pack_solve_g(const int32_t* __restrict
 
 // Batched pack solves with the pack's right-hand-side tile in LDS: one
 // workgroup of 1024 threads per (pack, TW-column tile).  Staged in LDS: the
-// tile X[r0 .. r1) x [c0, c0 + TW) (forward: times scale; backward: minus
-// the products with the final top rows), and the pack program of the
+// tile X[r0 .. r1) x [c0, c0 + TW) (forward: times scale; backward: the
+// products with the top rows are already subtracted by k_pack_topmul), and
+// the pack program of the
 // direction: local columns (int16), row pointers, rows in level order,
 // level offsets.  Factor values come from pval, a copy in program order
 // (one load per entry); 1 / u_ii from rdg (non-unit factors).  Per level a
@@ -920,13 +960,15 @@ __global__ void __launch_bounds__(1024) k_pack_solve_g(const int32_t* __restrict
 // sharing one row's entries, then R row slots; R G TW = 64); R shrinks on
 // narrow levels so that more lanes share a row.  Eight entries per lane are
 // in flight at a time.
-// LDS: xs[nr TW] (double) | srp[nr + 1] | slev[nlev + 1] (int) | srow[nr] |
-// scol[ne] (int16).
-__host__ __device__ inline size_t packt_lds_bytes(int nr, int ne, int nlev, int tw) {
-  return (size_t)nr * tw * 8 + (size_t)(nr + 1) * 4 + (size_t)(nlev + 1) * 4 + (size_t)nr * 2 + (size_t)ne * 2 + 16;
+// With SV the values are staged too and every level touches only LDS.
+// LDS: [sval[ne] (double, SV)] | xs[nr TW] (double) | srp[nr + 1] |
+// slev[nlev + 1] (int) | srow[nr] | scol[ne] (int16).
+__host__ __device__ inline size_t packt_lds_bytes(int nr, int ne, int nlev, int tw, bool sv) {
+  return (sv ? (size_t)ne * 8 : 0) + (size_t)nr * tw * 8 + (size_t)(nr + 1) * 4 + (size_t)(nlev + 1) * 4 +
+         (size_t)nr * 2 + (size_t)ne * 2 + 16;
 }
 
-template <int TW, bool FWD, bool UNIT>
+template <int TW, bool FWD, bool UNIT, bool SV>
 __global__ void __launch_bounds__(1024) k_pack_solve_t(const int32_t* __restrict__ pack_ptr,
                                                        const int32_t* __restrict__ lev,
                                                        const int32_t* __restrict__ lev_off,
@@ -939,25 +981,33 @@ __global__ void __launch_bounds__(1024) k_pack_solve_t(const int32_t* __restrict
                                                        const int32_t* __restrict__ ptr,
                                                        const int32_t* __restrict__ col,
                                                        const double* __restrict__ val, double* __restrict__ X,
-                                                       int ld, int ncols, double scale,
+                                                       int ld, int ncols, double scale, int npacks, int ntiles,
                                                        const int32_t* __restrict__ skip) {
   if (skip && *skip) return;
   constexpr int S = 64 / TW;   // lanes per column in a wavefront
   constexpr int LGS = S == 8 ? 3 : S == 4 ? 2 : S == 2 ? 1 : 0;
   extern __shared__ double smem[];
-  const int q = blockIdx.x;
-  const int c0 = blockIdx.y * TW;
+  // XCD-aware mapping: workgroup b runs on XCD b % 8; pack q belongs to XCD
+  // q % 8, whose workgroups take its packs' column tiles in order, so the
+  // tiles of one pack share that XCD's L2 (factor values, columns)
+  const int xcd = blockIdx.x & 7, jx = blockIdx.x >> 3;
+  const int qq = jx / ntiles;
+  const int q = xcd + 8 * qq;
+  if (q >= npacks) return;
+  const int c0 = (jx - qq * ntiles) * TW;
   const int r0 = pack_ptr[q], nr = pack_ptr[q + 1] - r0;
   const int e0 = rp[r0], ne = rp[r0 + nr] - e0;
   const int l0 = lev_off[q], nlev = lev_off[q + 1] - l0;
   const int base_row = lev[l0];
-  double* xs = smem;
+  double* sval = smem;
+  double* xs = smem + (SV ? ne : 0);
   int* srp = (int*)(xs + (size_t)nr * TW);
   int* slev = srp + nr + 1;
   int16_t* srow = (int16_t*)(slev + nlev + 1);
   int16_t* scol = srow + nr;
   const int t = threadIdx.x, nt = blockDim.x;
   stage_1d(scol, ecol + e0, ne);
+  if (SV) stage_1d(sval, pval + e0, ne);
   for (int r = t; r <= nr; r += nt) srp[r] = rp[r0 + r] - e0;
   for (int r = t; r < nr; r += nt) srow[r] = (int16_t)(lrows[base_row + r] - r0);
   for (int k = t; k <= nlev; k += nt) slev[k] = lev[l0 + k] - base_row;
@@ -974,32 +1024,6 @@ __global__ void __launch_bounds__(1024) k_pack_solve_t(const int32_t* __restrict
 #pragma unroll
     for (int m = 0; m < 8; ++m)
       if (eb + m * nt < ntile) xs[eb + m * nt] = FWD ? scale * v[m] : v[m];
-  }
-  if (!FWD) {
-    // products with the final top rows (same thread as the element's load)
-    for (int e = t; e < ntile; e += nt) {
-      const int r = e / TW, c = e - r * TW;
-      const int cc = min(c0 + c, ncols - 1);
-      const int i = r0 + r;
-      const int p0 = up_split[i], p1 = ptr[i + 1];
-      double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-      for (int pb = p0; pb < p1; pb += 4) {
-        int jj[4];
-        double vv[4];
-#pragma unroll
-        for (int m = 0; m < 4; ++m) {
-          const int pc = min(pb + m, p1 - 1);
-          jj[m] = col[pc];
-          const double raw = val[pc];
-          vv[m] = pb + m < p1 ? raw : 0.0;
-        }
-        a0 += vv[0] * X[(size_t)jj[0] * ld + cc];
-        a1 += vv[1] * X[(size_t)jj[1] * ld + cc];
-        a2 += vv[2] * X[(size_t)jj[2] * ld + cc];
-        a3 += vv[3] * X[(size_t)jj[3] * ld + cc];
-      }
-      xs[e] -= (a0 + a1) + (a2 + a3);
-    }
   }
   __syncthreads();
   const int wave = t >> 6, lane = t & 63, nwave = nt >> 6;
@@ -1027,7 +1051,7 @@ __global__ void __launch_bounds__(1024) k_pack_solve_t(const int32_t* __restrict
             const int e = eb + m * G;
             const bool in = e < ee;
             const int ec = in ? e : es;
-            const double raw = pval[e0 + ec];
+            const double raw = SV ? sval[ec] : pval[e0 + ec];
             vv[m] = in ? raw : 0.0;
             xv[m] = xs[scol[ec] * TW + cI];
           }
@@ -1045,7 +1069,7 @@ __global__ void __launch_bounds__(1024) k_pack_solve_t(const int32_t* __restrict
         xs[rl * TW + cI] = v;
       }
     }
-    __syncthreads();
+    lds_barrier();
   }
   for (int e = t; e < ntile; e += nt) {
     const int r = e / TW, c = e - r * TW;
@@ -1634,14 +1658,18 @@ __global__ void k_blk_update(int n, int b0, double* __restrict__ A, const int32_
   else
     stage_tile<256>(Us, A + (size_t)b0 * n + j0, n, nb, n - j0, 0.0);
   __syncthreads();
-  const int tr = (threadIdx.x >> 4) * 4, tc = (threadIdx.x & 15) * 4;
+  // thread: rows tr .. tr + 3, columns tc + 16 q (consecutive lanes read
+  // consecutive Us entries: no bank conflicts); the staged tiles are zero
+  // past nb, so the k loop has a fixed trip count
+  const int tr = (threadIdx.x >> 4) * 4, tc = threadIdx.x & 15;
   double acc[4][4] = {};
-  for (int k = 0; k < nb; ++k) {
+#pragma unroll 8
+  for (int k = 0; k < CB; ++k) {
     double l[4], u[4];
 #pragma unroll
     for (int p = 0; p < 4; ++p) l[p] = Ls[tr + p][k];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) u[q] = Us[k][tc + q];
+    for (int q = 0; q < 4; ++q) u[q] = Us[k][tc + 16 * q];
 #pragma unroll
     for (int p = 0; p < 4; ++p)
 #pragma unroll
@@ -1651,7 +1679,7 @@ __global__ void k_blk_update(int n, int b0, double* __restrict__ A, const int32_
   for (int p = 0; p < 4; ++p)
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
-      const int i = i0 + tr + p, j = j0 + tc + q;
+      const int i = i0 + tr + p, j = j0 + tc + 16 * q;
       if (i < n && j < n && (!CHOL || j <= i)) A[(size_t)i * n + j] -= acc[p][q];
     }
 }
@@ -1701,20 +1729,20 @@ __device__ inline void blk_publish(int32_t* flag) {
   if (threadIdx.x == 0) __hip_atomic_store(flag, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__global__ void __launch_bounds__(256) k_chol_fwd(int n, const double* __restrict__ L, const double* __restrict__ rhs,
+// dinv: inverses of the factor's diagonal blocks, (kb * 2) * CB * CB
+// row-major, zero outside each block's corner.
+__global__ void __launch_bounds__(256) k_chol_fwd(int n, const double* __restrict__ L,
+                                                  const double* __restrict__ dinv, const double* __restrict__ rhs,
                                                   double* __restrict__ y, int32_t* __restrict__ flags,
                                                   int32_t* __restrict__ info) {
   if (info[0] > 0) return;
   __shared__ double part[CB][5];
   __shared__ double tri[CB][CB + 1];
-  __shared__ double rd[CB];
+  __shared__ double rv[CB];
   const int w = blockIdx.x;
   const int b0 = w * CB, nb = min(CB, n - b0);
   const int t = threadIdx.x;
-  // diagonal block and reciprocal pivots first (no dependency)
-  stage_tile<256>(tri, L + (size_t)b0 * n + b0, n, nb, nb, 1.0);
-  __syncthreads();
-  if (t < CB) rd[t] = 1.0 / tri[t][t];
+  stage_tile<256>(tri, dinv + (size_t)(w * 2) * CB * CB, CB, CB, CB, 0.0);
   // products with the solved blocks: thread (row r, slice sl of 16 columns)
   const int r = t >> 2, sl = t & 3;
   double a0 = 0.0, a1 = 0.0;
@@ -1734,39 +1762,35 @@ __global__ void __launch_bounds__(256) k_chol_fwd(int n, const double* __restric
   }
   part[r][sl] = a0 + a1;
   __syncthreads();
-  if (t < 64) {
-    double lr[CB];
+  if (t < CB) rv[t] = t < nb ? -rhs[b0 + t] - ((part[t][0] + part[t][1]) + (part[t][2] + part[t][3])) : 0.0;
+  __syncthreads();
+  // y_block = L_kk^{-1} rv: 16 terms per thread, slices reduced by shuffles
+  double s0 = 0.0, s1 = 0.0;
 #pragma unroll
-    for (int j = 0; j < CB; ++j) lr[j] = tri[t][j];
-    double v = 0.0;
-    if (t < nb) v = -rhs[b0 + t] - ((part[t][0] + part[t][1]) + (part[t][2] + part[t][3]));
-#pragma unroll
-    for (int k = 0; k < CB; ++k) {
-      if (k < nb) {
-        const double yk = __shfl(v, k, 64) * rd[k];
-        if (t == k) v = yk;
-        if (t > k) v -= lr[k] * yk;
-      }
-    }
-    if (t < nb) y[b0 + t] = v;
+  for (int j = 0; j < 16; j += 2) {
+    s0 += tri[r][sl * 16 + j] * rv[sl * 16 + j];
+    s1 += tri[r][sl * 16 + j + 1] * rv[sl * 16 + j + 1];
   }
+  double sacc = s0 + s1;
+  sacc += __shfl_xor(sacc, 1, 64);
+  sacc += __shfl_xor(sacc, 2, 64);
+  if (sl == 0 && r < nb) y[b0 + r] = sacc;
   blk_publish(flags + w);
 }
 
-__global__ void __launch_bounds__(256) k_chol_bwd(int n, const double* __restrict__ L, const double* __restrict__ y,
+__global__ void __launch_bounds__(256) k_chol_bwd(int n, const double* __restrict__ L,
+                                                  const double* __restrict__ dinv, const double* __restrict__ y,
                                                   double* __restrict__ x, int32_t* __restrict__ flags,
                                                   int32_t* __restrict__ info) {
   if (info[0] > 0) return;
   __shared__ double part[4][CB];
   __shared__ double tri[CB][CB + 1];
-  __shared__ double rd[CB];
+  __shared__ double rv[CB];
   const int nblk = (n + CB - 1) / CB;
   const int w = nblk - 1 - blockIdx.x;
   const int b0 = w * CB, nb = min(CB, n - b0);
   const int t = threadIdx.x;
-  stage_tile<256>(tri, L + (size_t)b0 * n + b0, n, nb, nb, 1.0);
-  __syncthreads();
-  if (t < CB) rd[t] = 1.0 / tri[t][t];
+  stage_tile<256>(tri, dinv + (size_t)(w * 2) * CB * CB, CB, CB, CB, 0.0);
   // products with the solved blocks: lane i = column b0 + i of L (row of
   // L^T), wave sl takes rows k CB + 16 sl .. + 15 of each later block
   const int i = t & 63, sl = t >> 6;
@@ -1788,23 +1812,20 @@ __global__ void __launch_bounds__(256) k_chol_bwd(int n, const double* __restric
   }
   part[sl][i] = a0 + a1;
   __syncthreads();
-  if (t < 64) {
-    // lane t holds column t of the triangle: L[b0 + k][b0 + t]
-    double lc[CB];
+  if (t < CB) rv[t] = t < nb ? y[b0 + t] - ((part[0][t] + part[1][t]) + (part[2][t] + part[3][t])) : 0.0;
+  __syncthreads();
+  // x_block = L_kk^{-T} rv: thread (row r, slice sl)
+  const int r = t >> 2, s4 = t & 3;
+  double s0 = 0.0, s1 = 0.0;
 #pragma unroll
-    for (int k = 0; k < CB; ++k) lc[k] = tri[k][t];
-    double v = 0.0;
-    if (t < nb) v = y[b0 + t] - ((part[0][t] + part[1][t]) + (part[2][t] + part[3][t]));
-#pragma unroll
-    for (int k = CB - 1; k >= 0; --k) {
-      if (k < nb) {
-        const double xk = __shfl(v, k, 64) * rd[k];
-        if (t == k) v = xk;
-        if (t < k) v -= lc[k] * xk;
-      }
-    }
-    if (t < nb) x[b0 + t] = v;
+  for (int j = 0; j < 16; j += 2) {
+    s0 += tri[s4 * 16 + j][r] * rv[s4 * 16 + j];
+    s1 += tri[s4 * 16 + j + 1][r] * rv[s4 * 16 + j + 1];
   }
+  double sacc = s0 + s1;
+  sacc += __shfl_xor(sacc, 1, 64);
+  sacc += __shfl_xor(sacc, 2, 64);
+  if (s4 == 0 && r < nb) x[b0 + r] = sacc;
   blk_publish(flags + w);
 }
 

@@ -83,6 +83,7 @@ struct rpf_grid {
   size_t lds_packg = 0;   // LDS of the global-memory batched pack solves
   size_t lds_rf = 0;      // LDS of the LDS-resident pack refactorization (0: not used)
   int tw_packt = 0;       // column tile of the LDS-tile batched pack solves (0: not used)
+  bool sv_packt = false;  // factor values staged in LDS too
   size_t lds_packt = 0;
   // factor values in pack-program order: forward / backward, J_x / J_x^T
   double *pkfv = nullptr, *pkbv = nullptr, *pkfvT = nullptr, *pkbvT = nullptr;
@@ -95,6 +96,7 @@ struct rpf_grid {
   double *cvec, *wvec, *terms, *varg, *lam;
   double *D, *Y, *T, *chol_work;
   int32_t* chol_flags;   // block flags of the dense triangular solves [2 cdiv(n_u, CB)]
+  double* chol_dinv;     // inverses of the Cholesky factor's diagonal blocks
   // tracking step workspace
   double *Hbuf, *Kbuf, *gradbuf, *dstep, *u_try, *xi_save, *scur, *pdt, *qdt, *tres;
   int32_t* tflags;
@@ -276,10 +278,11 @@ void setup(rpf_grid* h) {
   h->pkb_rp = h->up(P.pkb_rp);
   h->pkb_pos = h->up(P.pkb_pos);
   h->pkb_col = h->up(P.pkb_col);
-  h->pkfv = h->alloc<double>(std::max<size_t>(P.pkf_pos.size(), 1));
-  h->pkfvT = h->alloc<double>(std::max<size_t>(P.pkf_pos.size(), 1));
-  h->pkbv = h->alloc<double>(std::max<size_t>(P.pkb_pos.size(), 1));
-  h->pkbvT = h->alloc<double>(std::max<size_t>(P.pkb_pos.size(), 1));
+  // padded: the batched pack solves prefetch up to one entry past a pack
+  h->pkfv = h->alloc<double>(P.pkf_pos.size() + 64);
+  h->pkfvT = h->alloc<double>(P.pkf_pos.size() + 64);
+  h->pkbv = h->alloc<double>(P.pkb_pos.size() + 64);
+  h->pkbvT = h->alloc<double>(P.pkb_pos.size() + 64);
   h->dense_top = h->alloc<double>((size_t)P.ntop * P.ntop);
   h->dense_topT = h->alloc<double>((size_t)P.ntop * P.ntop);
   h->top_dinv = h->alloc<double>((size_t)cdiv(P.ntop, CB) * 2 * CB * CB);
@@ -310,20 +313,32 @@ void setup(rpf_grid* h) {
       const int nl = std::max(P.pk_flev_off[q + 1] - P.pk_flev_off[q], P.pk_blev_off[q + 1] - P.pk_blev_off[q]);
       h->lds_packg = std::max(h->lds_packg, packg_lds_bytes(nr, seg, nl));
     }
-    // LDS-tile batched pack solves: 16-column tiles when the largest pack
-    // fits, else 8
-    for (int tw : {16, 8}) {
-      size_t mx = 0;
-      for (int q = 0; q < h->npacks; ++q) {
-        const int r0 = P.pack_ptr[q], nr = P.pack_ptr[q + 1] - r0;
-        const int nef = P.pkf_rp[r0 + nr] - P.pkf_rp[r0], neb = P.pkb_rp[r0 + nr] - P.pkb_rp[r0];
-        const int nlf = P.pk_flev_off[q + 1] - P.pk_flev_off[q], nlb = P.pk_blev_off[q + 1] - P.pk_blev_off[q];
-        mx = std::max(mx, packt_lds_bytes(nr, std::max(nef, neb), std::max(nlf, nlb), tw));
+    // LDS-tile batched pack solves: the first variant whose largest pack
+    // fits, in the order (8 columns, values staged), (16 columns), (8
+    // columns); RPF_PACK_TW = 8 or 16 and RPF_PACK_SV = 0 or 1 pick one
+    {
+      struct V { int tw; bool sv; };
+      std::vector<V> order = {{16, false}, {8, true}, {8, false}};
+      if (const char* e = std::getenv("RPF_PACK_TW")) {
+        const int tw = std::atoi(e);
+        bool sv = tw == 8;
+        if (const char* f = std::getenv("RPF_PACK_SV")) sv = std::atoi(f) != 0;
+        if (tw == 8 || tw == 16) order.insert(order.begin(), V{tw, sv && tw == 8});
       }
-      if (mx <= h->lds_limit) {
-        h->tw_packt = tw;
-        h->lds_packt = mx;
-        break;
+      for (const V& v : order) {
+        size_t mx = 0;
+        for (int q = 0; q < h->npacks; ++q) {
+          const int r0 = P.pack_ptr[q], nr = P.pack_ptr[q + 1] - r0;
+          const int nef = P.pkf_rp[r0 + nr] - P.pkf_rp[r0], neb = P.pkb_rp[r0 + nr] - P.pkb_rp[r0];
+          const int nlf = P.pk_flev_off[q + 1] - P.pk_flev_off[q], nlb = P.pk_blev_off[q + 1] - P.pk_blev_off[q];
+          mx = std::max(mx, packt_lds_bytes(nr, std::max(nef, neb), std::max(nlf, nlb), v.tw, v.sv));
+        }
+        if (mx <= h->lds_limit) {
+          h->tw_packt = v.tw;
+          h->sv_packt = v.sv;
+          h->lds_packt = mx;
+          break;
+        }
       }
     }
     // LDS-resident refactorization: values of the pack's CSR rows + pivots
@@ -364,13 +379,14 @@ void setup(rpf_grid* h) {
   allow((const void*)k_pack_solve_s<TW, false, false>);
     if (h->lds_packg > h->lds_limit) throw std::runtime_error("a pack of subtrees does not fit in LDS");
     if (h->lds_rf > 0) allow((const void*)k_rf_pack_lds);
-#define RPF_ALLOW_PACKT(TW)                                 \
-  allow((const void*)k_pack_solve_t<TW, true, true>);       \
-  allow((const void*)k_pack_solve_t<TW, true, false>);      \
-  allow((const void*)k_pack_solve_t<TW, false, true>);      \
-  allow((const void*)k_pack_solve_t<TW, false, false>);
-    if (h->tw_packt == 16) { RPF_ALLOW_PACKT(16) }
-    if (h->tw_packt == 8) { RPF_ALLOW_PACKT(8) }
+#define RPF_ALLOW_PACKT(TW, SV)                                 \
+  allow((const void*)k_pack_solve_t<TW, true, true, SV>);       \
+  allow((const void*)k_pack_solve_t<TW, true, false, SV>);      \
+  allow((const void*)k_pack_solve_t<TW, false, true, SV>);      \
+  allow((const void*)k_pack_solve_t<TW, false, false, SV>);
+    if (h->tw_packt == 16) { RPF_ALLOW_PACKT(16, false) }
+    if (h->tw_packt == 8 && !h->sv_packt) { RPF_ALLOW_PACKT(8, false) }
+    if (h->tw_packt == 8 && h->sv_packt) { RPF_ALLOW_PACKT(8, true) }
 #undef RPF_ALLOW_PACKT
     allow((const void*)k_pack_solve_g<true, true>);
     allow((const void*)k_pack_solve_g<true, false>);
@@ -413,6 +429,7 @@ void setup(rpf_grid* h) {
   h->T = h->alloc<double>((size_t)P.nr1 * h->max_batch);
   h->chol_work = h->alloc<double>(P.nu);
   h->chol_flags = h->alloc<int32_t>(2 * (size_t)cdiv(P.nu, CB));
+  h->chol_dinv = h->alloc<double>((size_t)cdiv(P.nu, CB) * 2 * CB * CB);
   h->Hbuf = h->alloc<double>((size_t)P.nu * P.nu);
   h->Kbuf = h->alloc<double>((size_t)P.nu * P.nu);
   h->gradbuf = h->alloc<double>(P.nu);
@@ -551,22 +568,23 @@ void pack_solve(rpf_grid* h, bool fwd, bool unit, const double* val, double* X, 
 
 // Many right-hand sides: one workgroup of 1024 threads per (pack, 64 columns),
 // solved in place in X.
-template <int TW>
+template <int TW, bool SV>
 void pack_solve_t(rpf_grid* h, bool fwd, bool unit, bool transposed, const double* val, double* X, int ld,
                   int ncols, double scale, hipStream_t s, const int32_t* skip) {
-  dim3 grd(h->npacks, cdiv(ncols, TW));
+  const int ntiles = cdiv(ncols, TW);
+  const dim3 grd(8 * cdiv(h->npacks, 8) * ntiles);   // see the XCD mapping in k_pack_solve_t
   const double* pv = fwd ? (transposed ? h->pkfvT : h->pkfv) : (transposed ? h->pkbvT : h->pkbv);
   auto launch = [&](auto kern, const int32_t* lev, const int32_t* lev_off, const int32_t* rows, const int32_t* rp,
                     const int16_t* ecol) {
     kern<<<grd, 1024, h->lds_packt, s>>>(h->pack_ptr, lev, lev_off, rows, rp, ecol, pv, h->rdiag, h->up_split,
-                                         h->lu_ptr, h->lu_col, val, X, ld, ncols, scale, skip);
+                                         h->lu_ptr, h->lu_col, val, X, ld, ncols, scale, h->npacks, ntiles, skip);
   };
   if (fwd) {
-    if (unit) launch(k_pack_solve_t<TW, true, true>, h->pk_flev, h->pk_flev_off, h->pk_frows, h->pkf_rp, h->pkf_col);
-    else launch(k_pack_solve_t<TW, true, false>, h->pk_flev, h->pk_flev_off, h->pk_frows, h->pkf_rp, h->pkf_col);
+    if (unit) launch(k_pack_solve_t<TW, true, true, SV>, h->pk_flev, h->pk_flev_off, h->pk_frows, h->pkf_rp, h->pkf_col);
+    else launch(k_pack_solve_t<TW, true, false, SV>, h->pk_flev, h->pk_flev_off, h->pk_frows, h->pkf_rp, h->pkf_col);
   } else {
-    if (unit) launch(k_pack_solve_t<TW, false, true>, h->pk_blev, h->pk_blev_off, h->pk_brows, h->pkb_rp, h->pkb_col);
-    else launch(k_pack_solve_t<TW, false, false>, h->pk_blev, h->pk_blev_off, h->pk_brows, h->pkb_rp, h->pkb_col);
+    if (unit) launch(k_pack_solve_t<TW, false, true, SV>, h->pk_blev, h->pk_blev_off, h->pk_brows, h->pkb_rp, h->pkb_col);
+    else launch(k_pack_solve_t<TW, false, false, SV>, h->pk_blev, h->pk_blev_off, h->pk_brows, h->pkb_rp, h->pkb_col);
   }
   LAUNCHCHK();
 }
@@ -576,8 +594,9 @@ void pack_solve_g(rpf_grid* h, bool fwd, bool unit, bool transposed, const doubl
   if (h->npacks == 0) return;
   if (h->tw_packt > 0) {
     size_t pi = h->prof_on ? h->prof_begin(s) : 0;
-    if (h->tw_packt == 16) pack_solve_t<16>(h, fwd, unit, transposed, val, X, ld, ncols, scale, s, skip);
-    else pack_solve_t<8>(h, fwd, unit, transposed, val, X, ld, ncols, scale, s, skip);
+    if (h->tw_packt == 16) pack_solve_t<16, false>(h, fwd, unit, transposed, val, X, ld, ncols, scale, s, skip);
+    else if (h->sv_packt) pack_solve_t<8, true>(h, fwd, unit, transposed, val, X, ld, ncols, scale, s, skip);
+    else pack_solve_t<8, false>(h, fwd, unit, transposed, val, X, ld, ncols, scale, s, skip);
     if (h->prof_on) h->prof_end(cls, pi, s);
     return;
   }
@@ -638,6 +657,13 @@ void solve_pair(rpf_grid* h, bool transposed, double* X, int ld, int ncols, doub
     const double* dinv = transposed ? h->top_dinvT : h->top_dinv;
     k_top_dense<<<cdiv(ncols, twt), 256, shm, s>>>(P.t0, P.nx, M, dinv, X, ld, ncols, twt, skip);
     LAUNCHCHK();
+    if (ncols > 1 && h->tw_packt > 0 && h->npacks > 0) {
+      // the LDS-tile pack solves expect the top products already subtracted
+      k_pack_topmul<<<dim3(cdiv(ncols, 64), cdiv(P.t0, 4)), dim3(64, 4), 0, s>>>(P.t0, h->up_split, h->lu_ptr,
+                                                                                  h->lu_col, val, X, ld, ncols,
+                                                                                  skip);
+      LAUNCHCHK();
+    }
     if (h->prof_on) h->prof_end(cls == 0 ? 5 : cls, pi, s);
   }
   pack_solve_any(h, twp, false, !fwd_unit, transposed, val, X, ld, ncols, 1.0, cls, s, skip);
@@ -661,9 +687,12 @@ void chol_solve(rpf_grid* h, int n, const double* L, const double* rhs, double* 
   const int nblk = cdiv(n, CB);
   k_fill_int<<<cdiv(2 * nblk, 256), 256, 0, s>>>(2 * nblk, h->chol_flags, 0);
   LAUNCHCHK();
-  k_chol_fwd<<<nblk, 256, 0, s>>>(n, L, rhs, h->chol_work, h->chol_flags, info);
+  // inverses of the diagonal blocks (skipped when the factorization failed)
+  k_top_diag_inv<<<dim3(nblk, 1), 64, 0, s>>>(n, L, h->chol_dinv, 0, 0, info);
   LAUNCHCHK();
-  k_chol_bwd<<<nblk, 256, 0, s>>>(n, L, h->chol_work, step, h->chol_flags + nblk, info);
+  k_chol_fwd<<<nblk, 256, 0, s>>>(n, L, h->chol_dinv, rhs, h->chol_work, h->chol_flags, info);
+  LAUNCHCHK();
+  k_chol_bwd<<<nblk, 256, 0, s>>>(n, L, h->chol_dinv, h->chol_work, step, h->chol_flags + nblk, info);
   LAUNCHCHK();
 }
 
