@@ -27,6 +27,29 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
 
+# HBM traffic per launch from two rocprofv3 --pmc passes over this bench at
+# batch 1024 (FETCH_SIZE scaled by 2.0 and WRITE_SIZE by 1.0: what the two
+# counters read for a 1 GiB streaming kernel; KiB per dispatch averaged over
+# the four forward/backward x J_x/J_x^T variants).  Valid only for the kernel
+# source it was measured on (sha1 of the kernel's text in kernels.hpp);
+# reported as null once that text changes.  Figures and commands:
+# profiles/pack_solve_t_syn9241_traffic.txt.
+TRAFFIC = {
+    "pack_solve": {"kernel": "k_pack_solve_t", "bytes_per_launch": 261720730,
+                   "source_sha1": "3e04cb8c14f31226f3183b88fb76ae283976c671"},
+}
+
+
+def _kernel_sha1(name):
+    """sha1 of a kernel's text (from its __global__ line to the closing
+    brace) in the library's kernel header."""
+    import hashlib
+    src = open(os.path.join(ROOT, "paper_2110_02590_amd", "csrc", "kernels.hpp")).read()
+    i = src.index(" " + name + "(")
+    st = src.rfind("\n__global__", 0, i)
+    j = src.index("\n}\n", i) + 3
+    return hashlib.sha1(src[st + 1:j].encode()).hexdigest()
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -175,13 +198,17 @@ def main():
         out["batched_over_b1"] = round(out["hvp_only_hvps_per_s"] / out["b1_eager_hvps_per_s"], 1)
 
     if a.copy_probe:
+        # a plain streaming kernel of known size for scaling the HBM byte
+        # counters: 3 launches of dst = src + 0 over 1 GiB (1 GiB read and
+        # 1 GiB written per launch)
         src = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
         dst = torch.empty_like(src)
         src.fill_(1.0)
         for _ in range(3):
-            dst.copy_(src)
+            torch.add(src, 0.0, out=dst)
         torch.cuda.synchronize()
-        out["copy_probe_bytes"] = 2 * src.numel() * 8
+        out["copy_probe_bytes_read_per_launch"] = src.numel() * 8
+        out["copy_probe_bytes_written_per_launch"] = src.numel() * 8
 
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(g, ep, a.cpu_sample_cols)
@@ -191,19 +218,22 @@ def main():
 
 def roofline(g, pr, prof, B, steps):
     """Roofline figures of the batched kernels from the library's HIP-event
-    timings (events on the launch stream around each launch).
+    timings (events recorded on the launch stream around each launch).
 
-    Algorithmic bytes per launch (each factor entry read once, 8 B value +
-    4 B column index; row pointers 4 B; diagonal 8 B for the non-unit
-    factor; every right-hand-side row read and written once, 16 B):
-      pack solve (k_pack_solve_s), rows [0, t0) of one factor, ncols columns:
-        forward  12 nnz(L strict, pack rows) + 4 (t0 + 1) + 16 t0 ncols
-        backward 12 nnz(U strict, pack rows) + 4 (t0 + 1) + 8 t0 + 16 t0 ncols
-        (with J_x^T the unit and non-unit factors swap; the average of the
-        two launches is the same);
-      top solve (k_top_dense), rows [t0, n_x) of both factors:
-        12 nnz(L, top rows, pack columns) + 8 n_top^2 (dense top block
-        L\\U) + 8 ncols #(distinct pack columns read) + 16 n_top ncols.
+    Algorithmic bytes (each factor entry read once as 8 B value + 4 B index,
+    row pointers 4 B, reciprocal pivots 8 B, every right-hand-side element
+    read and written once, 16 B), per launch with ncols columns:
+      pack solve (k_pack_solve_t), pack rows [0, t0), pack-local entries:
+        forward  12 nnz(L_pack) + 4 (t0 + 1) + 16 t0 ncols
+        backward 12 nnz(U_pack, pack columns) + 4 (t0 + 1) + 8 t0 + 16 t0 ncols
+        (nnz(U_pack, pack columns) = nnz(L_pack) by symmetry of the pattern;
+        with J_x^T the unit and non-unit factors swap);
+      top solve (k_top_rhs + k_top_dense + k_pack_topmul), one per solve pair:
+        12 nnz(L, top rows, pack columns) + 8 ncols #(pack columns read)
+        + 8 n_top^2 + 16 n_top ncols
+        + 12 nnz(U, pack rows, top columns) + 16 ncols #(pack rows with top entries);
+      refactorization (per call): LU values read and written (16 B each),
+        update targets 4 B each, update pointers 8 B per entry.
     The dense Cholesky group is priced in FLOPs: n_u^3/3 + 2 n_u^2."""
     import numpy as np
     from paper_2110_02590_amd import binding
@@ -214,46 +244,54 @@ def roofline(g, pr, prof, B, steps):
     rows = np.repeat(np.arange(nx), np.diff(ptr))
     pack = rows < t0
     nnz_lp = int(np.sum(pack & (col < rows)))
-    nnz_up = int(np.sum(pack & (col > rows)))
     topl = (rows >= t0) & (col < t0)
     nnz_tl = int(np.sum(topl))
     ncol_tl = int(np.unique(col[topl]).size)
+    packtop = pack & (col >= t0)
+    nnz_pt = int(np.sum(packtop))
+    nrow_pt = int(np.unique(rows[packtop]).size)
     nu = pr.nu
     cols = [min(B, nu - j0) for j0 in range(0, nu, B)]   # one reduced Hessian
     # per batch: two solve pairs (J_x and J_x^T), each one forward and one
-    # backward pack launch and one top launch
-    pack_bytes = sum(2 * (12 * (nnz_lp + nnz_up) + 8 * (t0 + 1) + 8 * t0 + 32 * t0 * c) for c in cols)
-    top_bytes = sum(2 * (12 * nnz_tl + 8 * ntop * ntop + 8 * c * ncol_tl + 16 * ntop * c) for c in cols)
+    # backward pack launch and one top solve
+    pack_bytes = sum(2 * (12 * 2 * nnz_lp + 8 * (t0 + 1) + 8 * t0 + 32 * t0 * c) for c in cols)
+    top_bytes = sum(2 * (12 * nnz_tl + 8 * c * ncol_tl + 8 * ntop * ntop + 16 * ntop * c
+                         + 12 * nnz_pt + 16 * c * nrow_pt) for c in cols)
     pack_launches, top_launches = 4 * len(cols), 2 * len(cols)
+    rf_bytes = 16 * info["nnz_lu"] + 4 * info["refactor_updates"] + 8 * info["nnz_lu"]
     chol_flops = nu ** 3 / 3.0 + 2.0 * nu * nu
     ent = {}
 
-    def add(name, kernel, cls, alg_total, launches_per_step, bound, peak, unit, per_unit):
+    def add(name, kernel, cls, alg_per_launch, bound, peak, unit, per_unit, launches_per_step=None):
         ms, n = prof[cls]
         if n == 0:
             return
         avg_us = ms * 1e3 / n
-        per_launch = alg_total / launches_per_step
-        achieved = per_launch / (avg_us * 1e-6) / (1e9 if unit == "GB/s" else 1e12)
+        achieved = alg_per_launch / (avg_us * 1e-6) / (1e9 if unit == "GB/s" else 1e12)
         ent[name] = {"bound": bound, "achieved": round(achieved, 2), "peak": peak, "unit": unit,
                      "frac": round(achieved / peak, 5), "traffic": None, "kernel": kernel,
                      "avg_launch_us": round(avg_us, 2), "launches_per_step": n // steps,
                      "ms_per_step": round(ms / steps, 3),
-                     "algorithmic_per_launch": round(per_launch, 1), "per_unit": per_unit}
+                     "algorithmic_per_launch": round(alg_per_launch, 1), "per_unit": per_unit}
 
-    add("pack_solve", "k_pack_solve_s (batched triangular solves in the subtree packs)", "pack_batch",
-        pack_bytes, pack_launches, "hbm", HBM_PEAK_GBS, "GB/s",
-        f"bytes; nnz(L_pack)={nnz_lp}, nnz(U_pack)={nnz_up}, t0={t0}, B={B}")
-    add("top_solve", "k_top_dense (batched triangular solves of the top rows)", "top_batch",
-        top_bytes, top_launches, "hbm", HBM_PEAK_GBS, "GB/s",
-        f"bytes; nnz(L_top,pack cols)={nnz_tl}, n_top={ntop}, distinct pack cols={ncol_tl}, B={B}")
-    add("cholesky", "dense Cholesky group (k_symmetrize, k_blk_*<true>, k_chol_solve)", "dense",
-        chol_flops, 1, "mfma", FP64_PEAK_TFLOPS, "TFLOP/s", f"flops n_u^3/3 + 2 n_u^2, n_u={nu}")
+    add("pack_solve", "k_pack_solve_t (batched triangular solves in the subtree packs)", "pack_batch",
+        pack_bytes / pack_launches, "hbm", HBM_PEAK_GBS, "GB/s",
+        f"bytes; nnz(L_pack)={nnz_lp}, t0={t0}, B={B}")
+    add("top_solve", "k_top_rhs + k_top_dense + k_pack_topmul (top rows of the batched solves)", "top_batch",
+        top_bytes / top_launches, "hbm", HBM_PEAK_GBS, "GB/s",
+        f"bytes; nnz(L_top,pack cols)={nnz_tl}, n_top={ntop}, nnz(U_pack,top cols)={nnz_pt}, B={B}")
+    add("refactor", "LU refactorization (k_rf_pack_lds, k_rf_top_ext, dense top LU)", "refactor",
+        rf_bytes, "hbm", HBM_PEAK_GBS, "GB/s",
+        f"bytes; nnz(L+U)={info['nnz_lu']}, updates={info['refactor_updates']}")
+    add("cholesky", "dense Cholesky group (k_symmetrize, k_blk_*<true>, k_chol_fwd/bwd)", "dense",
+        chol_flops, "mfma", FP64_PEAK_TFLOPS, "TFLOP/s", f"flops n_u^3/3 + 2 n_u^2, n_u={nu}")
+    for name, tr in TRAFFIC.items():
+        if name in ent and _kernel_sha1(tr["kernel"]) == tr["source_sha1"]:
+            ent[name]["traffic"] = tr["bytes_per_launch"]
     if not ent:
         return None, {}
     dom = max(ent, key=lambda k: ent[k]["ms_per_step"])
     return ent[dom], {k: v for k, v in ent.items() if k != dom}
-
 
 
 def tracking_bench(a):

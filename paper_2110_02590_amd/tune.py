@@ -1,6 +1,8 @@
 """Batch-width tuner for the Hessian-vector products: times the full
 reduced Hessian for candidate widths on the device and caches the best per
-(grid fingerprint, device name) in a JSON file next to the package."""
+(grid fingerprint, device name) in a JSON file next to the package.  A
+committed table of earlier tuning results (tune_table.json, same keys) is
+consulted after the local cache and before any sweep."""
 from __future__ import annotations
 
 import json
@@ -8,18 +10,23 @@ import os
 import time
 
 _CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tune_cache.json")
+_TABLE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tune_table.json")
 CANDIDATES = (128, 256, 512, 1024)
 
 
 def _key(g):
+    """(grid fingerprint, GPU architecture) -- the architecture rather than
+    the marketing name, which tools that wrap the runtime may report
+    differently."""
     import gridgen
     import torch
-    return f"{gridgen.fingerprint(g)[:16]}|{torch.cuda.get_device_name(0)}"
+    arch = str(getattr(torch.cuda.get_device_properties(0), "gcnArchName", "")).split(":")[0]
+    return f"{gridgen.fingerprint(g)[:16]}|{arch or torch.cuda.get_device_name(0)}"
 
 
-def _load():
+def _load(path=_CACHE):
     try:
-        with open(_CACHE) as f:
+        with open(path) as f:
             return json.load(f)
     except (OSError, ValueError):
         return {}
@@ -33,6 +40,9 @@ def best_batch(g, ep, candidates=CANDIDATES, reps=2, use_cache=True) -> int:
     cache = _load()
     if use_cache and key in cache:
         return int(cache[key]["batch"])
+    table = _load(_TABLE)
+    if use_cache and key in table:
+        return int(table[key]["batch"])
     nu = 1 + 2 * int((g["bus_type"] == 1).sum())
     cands = sorted({min(c, nu) for c in candidates})
     pr = Problem(g, max_batch=max(cands))
