@@ -28,7 +28,7 @@ constexpr int CB = 64;  // dense block width
 // nc >= 1); elsewhere diag_pad on the diagonal and 0 off it.  TRANS stores
 // dst[c][r].  NT = threads of the block.
 template <int NT, bool TRANS = false>
-__device__ inline void stage_tile(double (*dst)[CB + 1], const double* __restrict__ src, size_t ld, int nr, int nc,
+__device__ __forceinline__ void stage_tile(double (*dst)[CB + 1], const double* __restrict__ src, size_t ld, int nr, int nc,
                                   double diag_pad) {
   constexpr int PER = CB * CB / NT;
   double v[PER];
@@ -49,7 +49,7 @@ __device__ inline void stage_tile(double (*dst)[CB + 1], const double* __restric
 // Workgroup barrier for kernels whose threads communicate only through LDS:
 // waits for the thread's LDS operations, not for its global loads, so
 // prefetched global data can stay in flight across the barrier.
-__device__ inline void lds_barrier() {
+__device__ __forceinline__ void lds_barrier() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
   __builtin_amdgcn_s_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
@@ -57,7 +57,7 @@ __device__ inline void lds_barrier() {
 
 // dst[e] = src[e] for e < n, eight loads in flight per thread.
 template <class T>
-__device__ inline void stage_1d(T* dst, const T* __restrict__ src, int n) {
+__device__ __forceinline__ void stage_1d(T* dst, const T* __restrict__ src, int n) {
   const int nt = blockDim.x;
   for (int e0 = threadIdx.x; e0 < n; e0 += 8 * nt) {
     T v[8];
@@ -241,7 +241,7 @@ __global__ void k_reduce_final(int n, const double* __restrict__ in, double* __r
 // ahead; only the row's own entries in LDS form the dependency chain.  The
 // finished row stores 1 / u_ii in rdg[i].  With check, a pivot
 // |u_ii| <= pivtol max_j |a_ij| records row + 1 in status[0].
-__device__ inline void rf_row(int i, int pend, bool check, const int32_t* __restrict__ ptr,
+__device__ __forceinline__ void rf_row(int i, int pend, bool check, const int32_t* __restrict__ ptr,
                               const int32_t* __restrict__ col, const int32_t* __restrict__ diag,
                               const int64_t* __restrict__ upd_ptr, const int32_t* __restrict__ upd_tgt,
                               double* __restrict__ a, double* __restrict__ rdg, double* __restrict__ w,
@@ -326,7 +326,7 @@ __global__ void k_rf_pack(const int32_t* __restrict__ flev, const int32_t* __res
 // pivots of finished rows go to LDS and to rdg.  upd_tgt must hold 64
 // readable entries past its end.  LDS: values of the pack's CSR rows [seg]
 // | 1 / u_ii [nr].
-__device__ inline int64_t readlane64(int64_t v, int s) {
+__device__ __forceinline__ int64_t readlane64(int64_t v, int s) {
   const int lo = __builtin_amdgcn_readlane((int)(uint32_t)(v & 0xffffffff), s);
   const int hi = __builtin_amdgcn_readlane((int)(v >> 32), s);
   return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
@@ -469,7 +469,7 @@ __global__ void k_dense_xfer(int n, const int32_t* __restrict__ pos, const int64
 // current one is used; each thread accumulates up to four (row, column)
 // pairs over a fully unrolled 32-wide tile.  xs rows are clamped to s - 1
 // where the tile is zero, so every LDS index stays inside xs.
-__device__ inline void top_block_update(const double* __restrict__ M, int s, int b0, int nb, int j0, int j1,
+__device__ __forceinline__ void top_block_update(const double* __restrict__ M, int s, int b0, int nb, int j0, int j1,
                                         double* xs, int tw, double (*mt)[33]) {
   const int t = threadIdx.x;
   const int npair = nb * tw;
@@ -634,7 +634,7 @@ __global__ void __launch_bounds__(64) k_top_diag_inv(int s, const double* __rest
 // (D: a CB x CB inverse diagonal block, zero outside its nb x nb corner,
 // staged through LDS; the unrolled sum clamps xs rows to s - 1 where D is
 // zero).
-__device__ inline void top_diag_apply(const double* __restrict__ D, int s, int b0, int nb, double* xs, int tw,
+__device__ __forceinline__ void top_diag_apply(const double* __restrict__ D, int s, int b0, int nb, double* xs, int tw,
                                       double (*dt)[CB + 1]) {
   const int t = threadIdx.x;
   stage_tile<256>(dt, D, CB, CB, CB, 0.0);
@@ -710,7 +710,7 @@ __global__ void __launch_bounds__(256) k_top_dense(int t0, int n, const double* 
 // and diagonal are copied to LDS first, so the level loop reads only LDS.
 // LDS layout: xs[nr*TW] | val[ne] | dg[nr] | rp[nr+1] (int) | lev[nlev+1]
 // (int) | rows[nr] (short) | col[ne] (short).
-__host__ __device__ inline size_t pack_lds_bytes(int nr, int ne, int nlev, int tw) {
+__host__ __device__ __forceinline__ size_t pack_lds_bytes(int nr, int ne, int nlev, int tw) {
   size_t b = (size_t)nr * tw * 8 + (size_t)ne * 8 + (size_t)nr * 8 + (size_t)(nr + 1) * 4 +
              (size_t)(nlev + 1) * 4 + (size_t)nr * 2 + (size_t)ne * 2;
   return (b + 15) & ~(size_t)15;
@@ -854,7 +854,7 @@ __global__ void __launch_bounds__(256) k_pack_solve_s(const int32_t* __restrict_
 // x_i = b_i - sum; UNIT = false multiplies by 1 / val[diag[i]].
 // LDS: scol[seg] | sptr[nr + 1] | sdiag[nr] | srow[nr] | slev[nlev + 1] |
 // srd[nr] (double), seg = nnz of the pack's CSR rows.
-__host__ __device__ inline size_t packg_lds_bytes(int nr, int seg, int nlev) {
+__host__ __device__ __forceinline__ size_t packg_lds_bytes(int nr, int seg, int nlev) {
   size_t b = (size_t)seg * 4 + (size_t)(nr + 1) * 4 + (size_t)nr * 8 + (size_t)(nlev + 1) * 4;
   b = (b + 7) & ~(size_t)7;
   return b + (size_t)nr * 8;
@@ -963,7 +963,7 @@ __global__ void __launch_bounds__(1024) k_pack_solve_g(const int32_t* __restrict
 // With SV the values are staged too and every level touches only LDS.
 // LDS: [sval[ne] (double, SV)] | xs[nr TW] (double) | srp[nr + 1] |
 // slev[nlev + 1] (int) | srow[nr] | scol[ne] (int16).
-__host__ __device__ inline size_t packt_lds_bytes(int nr, int ne, int nlev, int tw, bool sv) {
+__host__ __device__ __forceinline__ size_t packt_lds_bytes(int nr, int ne, int nlev, int tw, bool sv) {
   return (sv ? (size_t)ne * 8 : 0) + (size_t)nr * tw * 8 + (size_t)(nr + 1) * 4 + (size_t)(nlev + 1) * 4 +
          (size_t)nr * 2 + (size_t)ne * 2 + 16;
 }
@@ -1498,14 +1498,12 @@ __global__ void k_symmetrize(int n, double* __restrict__ K, const double* __rest
 // (and per column for LU), trailing update in 64 x 64 tiles.  A failing
 // pivot records base + (column + 1) in info[0]; later kernels return early.
 
+// Diagonal block factorization with the 256 threads of the calling
+// workgroup; tile (CB x CB + 1), colb and rowb (2 x CB each) are LDS
+// provided by the caller.  Returns false when a pivot fails (info set).
 template <bool CHOL>
-__global__ void __launch_bounds__(256) k_blk_diag(int n, int b0, double* __restrict__ A, int32_t* __restrict__ info,
-                                                  int base, const int32_t* __restrict__ skip) {
-  if (skip && *skip) return;
-  __shared__ double tile[CB][CB + 1];
-  __shared__ double colb[2][CB];
-  __shared__ double rowb[2][CB];
-  if (info[0] != 0) return;
+__device__ __forceinline__ bool diag_factor(int n, int b0, double* __restrict__ A, int32_t* __restrict__ info, int base,
+                                   double (*tile)[CB + 1], double (*colb)[CB], double (*rowb)[CB]) {
   const int nb = min(CB, n - b0);
   const int t = threadIdx.x;
   // coalesced load through LDS; outside the nb x nb corner an identity, so
@@ -1542,7 +1540,7 @@ __global__ void __launch_bounds__(256) k_blk_diag(int n, int b0, double* __restr
       const bool ok = CHOL ? (d > 0.0 && isfinite(d)) : (fabs(d) > 0.0 && isfinite(d));
       if (!ok) {  // same d in every thread: uniform exit
         if (t == 0) info[0] = base + b0 + j + 1;
-        return;
+        return false;
       }
       // rp = 1 / sqrt(d) (Cholesky) or 1 / d (LU): hardware estimate and
       // one Newton step (relative error ~1e-16; far shorter chain than the
@@ -1599,6 +1597,18 @@ __global__ void __launch_bounds__(256) k_blk_diag(int n, int b0, double* __restr
     const int r = e >> 6, c = e & 63;
     if (r < nb && c < nb && (!CHOL || c <= r)) A[(size_t)(b0 + r) * n + b0 + c] = tile[r][c];
   }
+  return true;
+}
+
+template <bool CHOL>
+__global__ void __launch_bounds__(256) k_blk_diag(int n, int b0, double* __restrict__ A, int32_t* __restrict__ info,
+                                                  int base, const int32_t* __restrict__ skip) {
+  if (skip && *skip) return;
+  __shared__ double tile[CB][CB + 1];
+  __shared__ double colb[2][CB];
+  __shared__ double rowb[2][CB];
+  if (info[0] != 0) return;
+  diag_factor<CHOL>(n, b0, A, info, base, tile, colb, rowb);
 }
 
 // Panels: wave task t < rows below: row r solves x U11 = a (LU) or
@@ -1640,12 +1650,17 @@ __global__ void k_blk_panel(int n, int b0, double* __restrict__ A, const int32_t
 }
 
 // Trailing update A22 -= L21 U12 (LU) or L21 L21^T (Cholesky, lower tiles).
+// With fuse, workgroup (0, 0) -- dispatched first -- updates the next
+// diagonal block and then factorizes it (diag_factor, reusing this
+// kernel's LDS) while the other workgroups finish the trailing update.
 template <bool CHOL>
-__global__ void k_blk_update(int n, int b0, double* __restrict__ A, const int32_t* __restrict__ info,
-    const int32_t* __restrict__ skip) {
+__global__ void __launch_bounds__(256) k_blk_update(int n, int b0, double* __restrict__ A,
+                                                    int32_t* __restrict__ info, int fuse, int dbase,
+                                                    const int32_t* __restrict__ skip) {
   if (skip && *skip) return;
-  __shared__ double Ls[CB][CB + 1];
-  __shared__ double Us[CB][CB + 1];
+  __shared__ double sm[2][CB][CB + 1];
+  double (*Ls)[CB + 1] = sm[0];
+  double (*Us)[CB + 1] = sm[1];
   if (info[0] != 0) return;
   const int nb = min(CB, n - b0);
   const int base = b0 + nb;
@@ -1682,6 +1697,12 @@ __global__ void k_blk_update(int n, int b0, double* __restrict__ A, const int32_
       const int i = i0 + tr + p, j = j0 + tc + 16 * q;
       if (i < n && j < n && (!CHOL || j <= i)) A[(size_t)i * n + j] -= acc[p][q];
     }
+  if (fuse && ti == 0 && tj == 0) {
+    __syncthreads();   // the updated block is in A; the LDS tiles are free
+    double (*colb)[CB] = reinterpret_cast<double (*)[CB]>(&sm[1][0][0]);
+    double (*rowb)[CB] = reinterpret_cast<double (*)[CB]>(&sm[1][0][0] + 2 * CB);
+    diag_factor<CHOL>(n, base, A, info, dbase, sm[0], colb, rowb);
+  }
 }
 
 __global__ void k_transpose(int n, const double* __restrict__ A, double* __restrict__ B,
@@ -1711,7 +1732,7 @@ __global__ void k_transpose(int n, const double* __restrict__ A, double* __restr
 // flags: int32 [nblk] per direction (its own array for each launch), zero
 // before the launch.
 
-__device__ inline void blk_wait(const int32_t* flag, int32_t* info) {
+__device__ __forceinline__ void blk_wait(const int32_t* flag, int32_t* info) {
   unsigned it = 0;
   while (__hip_atomic_load(flag, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == 0) {
     // after one expiry anywhere, no further waiting
@@ -1723,7 +1744,7 @@ __device__ inline void blk_wait(const int32_t* flag, int32_t* info) {
   }
 }
 
-__device__ inline void blk_publish(int32_t* flag) {
+__device__ __forceinline__ void blk_publish(int32_t* flag) {
   __threadfence();
   __syncthreads();
   if (threadIdx.x == 0) __hip_atomic_store(flag, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);

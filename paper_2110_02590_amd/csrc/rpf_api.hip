@@ -471,17 +471,19 @@ void x_in(rpf_grid* h, const double* x, hipStream_t s, const int32_t* skip = nul
 // Blocked dense LU (no pivoting) or Cholesky of a row-major n x n matrix.
 template <bool CHOL>
 void dense_factor(int n, double* A, int32_t* info, int base, hipStream_t s, const int32_t* skip = nullptr) {
+  // the first diagonal block on its own; every later one is factorized by
+  // the trailing update of the previous block (fused, see k_blk_update)
+  k_blk_diag<CHOL><<<1, 256, 0, s>>>(n, 0, A, info, base, skip);
+  LAUNCHCHK();
   for (int b0 = 0; b0 < n; b0 += CB) {
     const int nb = std::min(CB, n - b0);
-    k_blk_diag<CHOL><<<1, 256, 0, s>>>(n, b0, A, info, base, skip);
-    LAUNCHCHK();
     const int rest = n - b0 - nb;
     if (rest > 0) {
       const int tasks = CHOL ? rest : 2 * rest;
       k_blk_panel<CHOL><<<cdiv(tasks, 4), 256, 0, s>>>(n, b0, A, info, skip);
       LAUNCHCHK();
       const int nt = cdiv(rest, CB);
-      k_blk_update<CHOL><<<dim3(nt, nt), 256, 0, s>>>(n, b0, A, info, skip);
+      k_blk_update<CHOL><<<dim3(nt, nt), 256, 0, s>>>(n, b0, A, info, 1, base, skip);
       LAUNCHCHK();
     }
   }
