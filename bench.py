@@ -142,7 +142,7 @@ def main():
         step(k, x)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    prof = grid.profile_read(reset=True)
+    prof = grid.profile_read(reset=True, busy=True)
     grid.profile(False)
     ok = all(int(i) == 0 for i in infos)
     ms_step = (t1 - t0) * 1e3 / steps
@@ -169,6 +169,7 @@ def main():
         "roofline": rl,
         "roofline_other_kernels": rl_all,
         "breakdown_ms_per_step": {k: round(v[0] / steps, 4) for k, v in prof.items()},
+        "breakdown_busy_ms_per_step": {k: round(v[2] / steps, 4) for k, v in prof.items()},
         "cholesky_ok": ok,
         "cholesky_shift": delta,
     }
@@ -263,15 +264,21 @@ def roofline(g, pr, prof, B, steps):
     ent = {}
 
     def add(name, kernel, cls, alg_per_launch, bound, peak, unit, per_unit, launches_per_step=None):
-        ms, n = prof[cls]
+        ms, n, busy = prof[cls]
         if n == 0:
             return
+        scale = 1e9 if unit == "GB/s" else 1e12
         avg_us = ms * 1e3 / n
-        achieved = alg_per_launch / (avg_us * 1e-6) / (1e9 if unit == "GB/s" else 1e12)
+        achieved = alg_per_launch / (avg_us * 1e-6) / scale
+        # launches of one class may overlap on the library's concurrent
+        # streams; the busy figure counts overlapped time once
+        ach_busy = alg_per_launch * n / (busy * 1e-3) / scale if busy > 0 else 0.0
         ent[name] = {"bound": bound, "achieved": round(achieved, 2), "peak": peak, "unit": unit,
                      "frac": round(achieved / peak, 5), "traffic": None, "kernel": kernel,
                      "avg_launch_us": round(avg_us, 2), "launches_per_step": n // steps,
                      "ms_per_step": round(ms / steps, 3),
+                     "busy_ms_per_step": round(busy / steps, 3),
+                     "achieved_busy": round(ach_busy, 2), "frac_busy": round(ach_busy / peak, 5),
                      "algorithmic_per_launch": round(alg_per_launch, 1), "per_unit": per_unit}
 
     add("pack_solve", "k_pack_solve_t (batched triangular solves in the subtree packs)", "pack_batch",

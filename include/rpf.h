@@ -156,7 +156,11 @@ int rpf_reduced_hessian_batch(rpf_grid* grid, const double* V, int32_t nbatch, i
 
 /* The dense reduced Hessian H [n_u x n_u] (device, row-major, out) at the
  * cached point: products with the identity in batches of `batch` columns
- * (0 = the library's choice, at most max_batch). */
+ * (0 = the library's choice, at most max_batch).  For max_batch >= 512 the
+ * batches run concurrently on up to three streams owned by the handle, each
+ * with its own workspace, forked from `stream` and joined back to it by
+ * events (the call stays capturable in a graph); RPF_HVP_STREAMS = 1 runs
+ * them one after the other on `stream`. */
 int rpf_reduced_hessian(rpf_grid* grid, double* H, int32_t batch, rpf_stream_t stream);
 
 /* Dense step (Section IV-B.2): K = (H + H^T)/2 + diag(d) + delta I is
@@ -205,6 +209,11 @@ int rpf_track_step(rpf_grid* grid, double* u, double* x, double* y, const double
 #define RPF_PROF_CLASSES 6
 int rpf_profile_enable(rpf_grid* grid, int32_t enable);
 int rpf_profile_read(rpf_grid* grid, double* ms, int64_t* launches, int32_t reset);
+/* As rpf_profile_read, and busy_ms [RPF_PROF_CLASSES] (host, out, may be
+ * NULL): per class the length of the union of its launch intervals (launches
+ * that overlap on concurrent streams are counted once), from the same events
+ * timed against the first recorded one. */
+int rpf_profile_read_busy(rpf_grid* grid, double* ms, int64_t* launches, double* busy_ms, int32_t reset);
 
 /* Host-only presolve introspection (no device needed), for checking the
  * index maps and the symbolic factorization:

@@ -63,6 +63,7 @@ def lib():
             "rpf_profile_enable": [vp, i32],
             "rpf_track_step": [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, dbl, vp, dbl, i32, i32, dbl, vp, vp],
             "rpf_profile_read": [vp, vp, vp, i32],
+            "rpf_profile_read_busy": [vp, vp, vp, vp, i32],
             "rpf_presolve_pattern": [vp, vp, vp, vp],
         }
         for name, args in sig.items():
@@ -192,11 +193,18 @@ class Grid:
     def profile(self, enable: bool = True):
         _check(lib().rpf_profile_enable(self._h, 1 if enable else 0))
 
-    def profile_read(self, reset: bool = True) -> dict:
+    def profile_read(self, reset: bool = True, busy: bool = False) -> dict:
+        """{class: (summed ms, launches)}, or with busy (summed ms, launches,
+        ms of the union of the launch intervals)."""
         ms = np.zeros(len(self.PROF_CLASSES), dtype=np.float64)
         n = np.zeros(len(self.PROF_CLASSES), dtype=np.int64)
-        _check(lib().rpf_profile_read(self._h, ms.ctypes.data, n.ctypes.data, 1 if reset else 0))
-        return {k: (float(ms[i]), int(n[i])) for i, k in enumerate(self.PROF_CLASSES)}
+        if not busy:
+            _check(lib().rpf_profile_read(self._h, ms.ctypes.data, n.ctypes.data, 1 if reset else 0))
+            return {k: (float(ms[i]), int(n[i])) for i, k in enumerate(self.PROF_CLASSES)}
+        bz = np.zeros(len(self.PROF_CLASSES), dtype=np.float64)
+        _check(lib().rpf_profile_read_busy(self._h, ms.ctypes.data, n.ctypes.data, bz.ctypes.data,
+                                           1 if reset else 0))
+        return {k: (float(ms[i]), int(n[i]), float(bz[i])) for i, k in enumerate(self.PROF_CLASSES)}
 
     def _empty(self, n, dtype=None):
         torch = _torch()

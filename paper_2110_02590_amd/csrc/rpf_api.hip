@@ -95,6 +95,13 @@ struct rpf_grid {
   double *luv, *lutv, *juv, *Gv, *Kv, *wrec, *kappa, *a, *b, *Pbus, *Qbus;
   double *cvec, *wvec, *terms, *varg, *lam;
   double *D, *Y, *T, *chol_work;
+  // the batches of rpf_reduced_hessian run on nhs internal streams, each
+  // with its own D, Y, T workspace (slot 0 is D, Y, T above)
+  static constexpr int HS = 3;
+  int nhs = 1;
+  hipStream_t hs[HS] = {};
+  hipEvent_t ev_fork = nullptr, ev_join[HS] = {};
+  double *Dk[HS] = {}, *Yk[HS] = {}, *Tk[HS] = {};
   int32_t* chol_flags;   // block flags of the dense triangular solves [2 cdiv(n_u, CB)]
   double* chol_dinv;     // inverses of the Cholesky factor's diagonal blocks
   // tracking step workspace
@@ -148,6 +155,11 @@ struct rpf_grid {
     return (T*)p;
   }
   ~rpf_grid() {
+    for (int k = 0; k < HS; ++k) {
+      if (hs[k]) (void)hipStreamDestroy(hs[k]);
+      if (ev_join[k]) (void)hipEventDestroy(ev_join[k]);
+    }
+    if (ev_fork) (void)hipEventDestroy(ev_fork);
     for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
     for (void* p : allocs) (void)hipFree(p);
     if (host_resid) (void)hipHostFree(host_resid);
@@ -427,6 +439,24 @@ void setup(rpf_grid* h) {
   h->D = h->alloc<double>((size_t)P.nvar * h->max_batch);
   h->Y = h->alloc<double>((size_t)P.nvar * h->max_batch);
   h->T = h->alloc<double>((size_t)P.nr1 * h->max_batch);
+  h->Dk[0] = h->D;
+  h->Yk[0] = h->Y;
+  h->Tk[0] = h->T;
+  // concurrent batches for large batch widths (RPF_HVP_STREAMS = 1 .. 3)
+  h->nhs = h->max_batch >= 512 ? rpf_grid::HS : 1;
+  if (const char* e = std::getenv("RPF_HVP_STREAMS")) h->nhs = std::max(1, std::min(rpf_grid::HS, std::atoi(e)));
+  if (h->nhs > 1) {
+    HIPCHK(hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming));
+    for (int k = 0; k < h->nhs; ++k) {
+      HIPCHK(hipStreamCreateWithFlags(&h->hs[k], hipStreamNonBlocking));
+      HIPCHK(hipEventCreateWithFlags(&h->ev_join[k], hipEventDisableTiming));
+      if (k > 0) {
+        h->Dk[k] = h->alloc<double>((size_t)P.nvar * h->max_batch);
+        h->Yk[k] = h->alloc<double>((size_t)P.nvar * h->max_batch);
+        h->Tk[k] = h->alloc<double>((size_t)P.nr1 * h->max_batch);
+      }
+    }
+  }
   h->chol_work = h->alloc<double>(P.nu);
   h->chol_flags = h->alloc<int32_t>(2 * (size_t)cdiv(P.nu, CB));
   h->chol_dinv = h->alloc<double>((size_t)cdiv(P.nu, CB) * 2 * CB * CB);
@@ -732,11 +762,16 @@ void bus_injections(rpf_grid* h, hipStream_t s) {
 
 // One batch of reduced Hessian-vector products at the cached point.
 // V (ldv) or, when V is null, identity columns j0.. of the n_u identity.
-void hvp_batch(rpf_grid* h, const double* V, int ldv, int j0, int B, double* HV, int ldhv, hipStream_t s) {
+// Proposition 2 on one batch of directions, in workspace slot ws (D, Y, T).
+void hvp_batch(rpf_grid* h, const double* V, int ldv, int j0, int B, double* HV, int ldhv, hipStream_t s,
+               int ws = 0) {
   const Presolve& P = h->P;
   const int ld = B;
-  double* Dx = h->D;
-  double* Du = h->D + (size_t)P.nx * ld;
+  double* const D = h->Dk[ws];
+  double* const Y = h->Yk[ws];
+  double* const T = h->Tk[ws];
+  double* Dx = D;
+  double* Du = D + (size_t)P.nx * ld;
   dim3 blk(64, 4);
   if (V) {
     k_copy_block<<<dim3(cdiv(B, 64), cdiv(P.nu, 4)), blk, 0, s>>>(P.nu, B, V, ldv, Du, ld);
@@ -749,13 +784,13 @@ void hvp_batch(rpf_grid* h, const double* V, int ldv, int j0, int B, double* HV,
   // Z = U^{-1} L^{-1} R
   solve_pair(h, false, Dx, ld, B, 1.0, s);
   // Y = K [Z; V] + G^T diag(kappa) G [Z; V]
-  spmm(h, P.nvar, h->K_ptr, h->K_col, h->Kv, nullptr, nullptr, h->D, ld, B, 1.0, nullptr, 0, h->Y, ld, s);
-  spmm(h, P.nr1, h->G_ptr, h->G_col, h->Gv, nullptr, nullptr, h->D, ld, B, 1.0, nullptr, 0, h->T, ld, s);
-  spmm(h, P.nvar, h->Gt_ptr, h->Gt_col, h->Gv, h->Gt_pos, h->kappa, h->T, ld, B, 1.0, h->Y, ld, h->Y, ld, s);
+  spmm(h, P.nvar, h->K_ptr, h->K_col, h->Kv, nullptr, nullptr, D, ld, B, 1.0, nullptr, 0, Y, ld, s);
+  spmm(h, P.nr1, h->G_ptr, h->G_col, h->Gv, nullptr, nullptr, D, ld, B, 1.0, nullptr, 0, T, ld, s);
+  spmm(h, P.nvar, h->Gt_ptr, h->Gt_col, h->Gv, h->Gt_pos, h->kappa, T, ld, B, 1.0, Y, ld, Y, ld, s);
   // Psi = -J_x^{-T} Y_x  (U^T then L^T)
-  solve_pair(h, true, h->Y, ld, B, -1.0, s);
+  solve_pair(h, true, Y, ld, B, -1.0, s);
   // HV = Y_u + J_u^T Psi
-  spmm(h, P.nu, h->jut_ptr, h->jut_col, h->juv, h->jut_pos, nullptr, h->Y, ld, B, 1.0, h->Y + (size_t)P.nx * ld,
+  spmm(h, P.nu, h->jut_ptr, h->jut_col, h->juv, h->jut_pos, nullptr, Y, ld, B, 1.0, Y + (size_t)P.nx * ld,
        ld, HV, ldhv, s);
 }
 
@@ -808,19 +843,49 @@ int rpf_profile_enable(rpf_grid* h, int32_t enable) {
   return RPF_OK;
 }
 
-int rpf_profile_read(rpf_grid* h, double* ms, int64_t* launches, int32_t reset) {
+int rpf_profile_read_busy(rpf_grid* h, double* ms, int64_t* launches, double* busy_ms, int32_t reset) {
   if (!h || !ms || !launches) return set_err(RPF_EINVAL, "NULL argument");
   return guard([&]() -> int {
+    std::vector<std::vector<std::pair<double, double>>> iv(RPF_PROF_CLASSES);
     for (int c = 0; c < RPF_PROF_CLASSES; ++c) {
       ms[c] = 0.0;
       launches[c] = 0;
+      if (busy_ms) busy_ms[c] = 0.0;
     }
+    const hipEvent_t ref = h->ev_marks.empty() ? nullptr : h->ev_pool[h->ev_marks.front().second];
     for (auto& mk : h->ev_marks) {
       HIPCHK(hipEventSynchronize(h->ev_pool[mk.second + 1]));
       float t = 0.f;
       HIPCHK(hipEventElapsedTime(&t, h->ev_pool[mk.second], h->ev_pool[mk.second + 1]));
       ms[mk.first] += t;
       launches[mk.first] += 1;
+      if (busy_ms) {
+        // interval of this launch relative to the first recorded event
+        float a = 0.f, b = 0.f;
+        HIPCHK(hipEventElapsedTime(&a, ref, h->ev_pool[mk.second]));
+        HIPCHK(hipEventElapsedTime(&b, ref, h->ev_pool[mk.second + 1]));
+        iv[mk.first].push_back({(double)a, (double)b});
+      }
+    }
+    if (busy_ms) {
+      for (int c = 0; c < RPF_PROF_CLASSES; ++c) {
+        auto& v = iv[c];
+        std::sort(v.begin(), v.end());
+        double total = 0.0, lo = 0.0, hi = 0.0;
+        bool open = false;
+        for (auto& x : v) {
+          if (!open || x.first > hi) {
+            if (open) total += hi - lo;
+            lo = x.first;
+            hi = x.second;
+            open = true;
+          } else {
+            hi = std::max(hi, x.second);
+          }
+        }
+        if (open) total += hi - lo;
+        busy_ms[c] = total;
+      }
     }
     if (reset) {
       h->ev_marks.clear();
@@ -828,6 +893,10 @@ int rpf_profile_read(rpf_grid* h, double* ms, int64_t* launches, int32_t reset) 
     }
     return RPF_OK;
   });
+}
+
+int rpf_profile_read(rpf_grid* h, double* ms, int64_t* launches, int32_t reset) {
+  return rpf_profile_read_busy(h, ms, launches, nullptr, reset);
 }
 
 int rpf_presolve_info(const rpf_grid_desc* desc, int64_t* o) {
@@ -1104,9 +1173,24 @@ int rpf_reduced_hessian(rpf_grid* h, double* H, int32_t batch, rpf_stream_t stre
   return guard([&]() -> int {
     const int nu = h->P.nu;
     int B = batch == 0 ? std::min(h->max_batch, nu) : std::min<int>(batch, std::min(h->max_batch, nu));
-    for (int j0 = 0; j0 < nu; j0 += B) {
-      int nbb = std::min(B, nu - j0);
-      hvp_batch(h, nullptr, 0, j0, nbb, H + j0, nu, (hipStream_t)stream);
+    hipStream_t s = (hipStream_t)stream;
+    const int nbt = cdiv(nu, B);
+    const int nst = std::min(h->nhs, nbt);
+    if (nst <= 1) {
+      for (int j0 = 0; j0 < nu; j0 += B) hvp_batch(h, nullptr, 0, j0, std::min(B, nu - j0), H + j0, nu, s);
+    } else {
+      // fork: batch b on internal stream b % nst with its own workspace;
+      // join back on the caller's stream (capturable: events only)
+      HIPCHK(hipEventRecord(h->ev_fork, s));
+      for (int k = 0; k < nst; ++k) HIPCHK(hipStreamWaitEvent(h->hs[k], h->ev_fork, 0));
+      for (int b = 0; b < nbt; ++b) {
+        const int j0 = b * B;
+        hvp_batch(h, nullptr, 0, j0, std::min(B, nu - j0), H + j0, nu, h->hs[b % nst], b % nst);
+      }
+      for (int k = 0; k < nst; ++k) {
+        HIPCHK(hipEventRecord(h->ev_join[k], h->hs[k]));
+        HIPCHK(hipStreamWaitEvent(s, h->ev_join[k], 0));
+      }
     }
     return RPF_OK;
   });
