@@ -1518,10 +1518,15 @@ __device__ __forceinline__ bool diag_factor(int n, int b0, double* __restrict__ 
 #pragma unroll
     for (int q = 0; q < 4; ++q) a[p][q] = tile[4 * tr + p][4 * tc + q];
   // right-looking elimination, one barrier per pivot: the owners of column
-  // j (and, for LU, row j) publish it in a double-buffered LDS vector and
-  // write the finished column (row) of the factor into the LDS tile; every
-  // thread updates its 16 entries.  Pivots are unrolled by four so that
-  // every register index is static.
+  // j (and, for LU, row j) publish it in a double-buffered LDS vector; every
+  // thread updates its 16 entries.  Finished factor entries stay in the
+  // registers that held them (the update leaves them alone: their l or u
+  // factor is zero), so the tile in LDS is not touched again and the result
+  // is written from registers.  Pivots are unrolled by four so that every
+  // register index is static.  A failed pivot does not branch: the first
+  // failing index is kept and reported after the loop (the factor is then
+  // not written).
+  int bad = CB;
   for (int jt = 0; 4 * jt < nb; ++jt) {
 #pragma unroll
     for (int jq = 0; jq < 4; ++jq) {
@@ -1535,13 +1540,15 @@ __device__ __forceinline__ bool diag_factor(int n, int b0, double* __restrict__ 
 #pragma unroll
         for (int q = 0; q < 4; ++q) rowb[buf][4 * tc + q] = a[jq][q];
       }
-      __syncthreads();
+      lds_barrier();
       const double d = colb[buf][j];
+      double cr[4], cc[4];
+#pragma unroll
+      for (int p = 0; p < 4; ++p) cr[p] = colb[buf][4 * tr + p];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) cc[q] = CHOL ? colb[buf][4 * tc + q] : rowb[buf][4 * tc + q];
       const bool ok = CHOL ? (d > 0.0 && isfinite(d)) : (fabs(d) > 0.0 && isfinite(d));
-      if (!ok) {  // same d in every thread: uniform exit
-        if (t == 0) info[0] = base + b0 + j + 1;
-        return false;
-      }
+      bad = min(bad, ok ? CB : j);
       // rp = 1 / sqrt(d) (Cholesky) or 1 / d (LU): hardware estimate and
       // one Newton step (relative error ~1e-16; far shorter chain than the
       // correctly rounded library sequences)
@@ -1554,12 +1561,6 @@ __device__ __forceinline__ bool diag_factor(int n, int b0, double* __restrict__ 
         const double y0 = __builtin_amdgcn_rcp(d);
         rp = fma(y0, fma(-d, y0, 1.0), y0);
       }
-      const double piv = CHOL ? d * rp : d;
-      double cr[4], cc[4];
-#pragma unroll
-      for (int p = 0; p < 4; ++p) cr[p] = colb[buf][4 * tr + p];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) cc[q] = CHOL ? colb[buf][4 * tc + q] : rowb[buf][4 * tc + q];
       double l[4], u[4];
 #pragma unroll
       for (int p = 0; p < 4; ++p) {
@@ -1575,28 +1576,29 @@ __device__ __forceinline__ bool diag_factor(int n, int b0, double* __restrict__ 
       for (int p = 0; p < 4; ++p)
 #pragma unroll
         for (int q = 0; q < 4; ++q) a[p][q] -= l[p] * u[q];
+      // column j of the factor: multipliers below the pivot (and, for the
+      // Cholesky factor, sqrt(d) on the diagonal) replace the eliminated
+      // entries in the registers of the column's owners
       if (tc == jt) {
 #pragma unroll
         for (int p = 0; p < 4; ++p) {
           const int r = 4 * tr + p;
-          if (r > j) tile[r][j] = l[p];
-          else if (r == j) tile[r][j] = piv;
-        }
-      }
-      if (!CHOL && tr == jt) {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int c = 4 * tc + q;
-          if (c > j) tile[j][c] = u[q];
+          a[p][jq] = r > j ? l[p] : (CHOL && r == j ? d * rp : a[p][jq]);
         }
       }
     }
   }
-  __syncthreads();
-  for (int e = t; e < CB * CB; e += 256) {
-    const int r = e >> 6, c = e & 63;
-    if (r < nb && c < nb && (!CHOL || c <= r)) A[(size_t)(b0 + r) * n + b0 + c] = tile[r][c];
+  if (bad < nb) {  // uniform: every thread saw the same pivots
+    if (t == 0) info[0] = base + b0 + bad + 1;
+    return false;
   }
+#pragma unroll
+  for (int p = 0; p < 4; ++p)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int r = 4 * tr + p, c = 4 * tc + q;
+      if (r < nb && c < nb && (!CHOL || c <= r)) A[(size_t)(b0 + r) * n + b0 + c] = a[p][q];
+    }
   return true;
 }
 

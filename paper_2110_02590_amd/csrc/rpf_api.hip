@@ -899,10 +899,19 @@ int rpf_profile_read(rpf_grid* h, double* ms, int64_t* launches, int32_t reset) 
   return rpf_profile_read_busy(h, ms, launches, nullptr, reset);
 }
 
+
+// packs of independent subtrees: at most RPF_SUBTREE_MAX rows (default 1024,
+// sized for 160 KB of LDS per workgroup)
+static int subtree_max() {
+  int smax = 1024;
+  if (const char* e = std::getenv("RPF_SUBTREE_MAX")) smax = std::max(1, std::min(32767, std::atoi(e)));
+  return smax;
+}
+
 int rpf_presolve_info(const rpf_grid_desc* desc, int64_t* o) {
   if (!o) return set_err(RPF_EINVAL, "out is NULL");
   return guard([&]() -> int {
-    Presolve P = build_presolve(grid_from_desc(desc));
+    Presolve P = build_presolve(grid_from_desc(desc), subtree_max());
     PresolveStats st = stats(P);
     int64_t v[16] = {P.nx, P.nu, P.m, st.nnz_jx, st.nnz_lu, st.nlev_lo, st.nlev_up, st.max_lu_row,
                      st.refactor_updates, st.nnz_ju, st.nnz_k, st.nnz_g, st.npacks, st.ntop,
@@ -914,7 +923,7 @@ int rpf_presolve_info(const rpf_grid_desc* desc, int64_t* o) {
 
 int rpf_presolve_pattern(const rpf_grid_desc* desc, int32_t* perm, int32_t* lu_ptr, int32_t* lu_col) {
   return guard([&]() -> int {
-    Presolve P = build_presolve(grid_from_desc(desc));
+    Presolve P = build_presolve(grid_from_desc(desc), subtree_max());
     if (perm) std::copy(P.x_int2paper.begin(), P.x_int2paper.end(), perm);
     if (lu_ptr) std::copy(P.lu_ptr.begin(), P.lu_ptr.end(), lu_ptr);
     if (lu_col) std::copy(P.lu_col.begin(), P.lu_col.end(), lu_col);
@@ -932,11 +941,7 @@ int rpf_grid_create(const rpf_grid_desc* desc, int32_t max_batch, rpf_grid** out
     try {
       h->G = std::move(G0);
       const GridData& G = h->G;
-      // packs of independent subtrees: at most RPF_SUBTREE_MAX rows (default
-      // 1024, sized for 160 KB of LDS per workgroup)
-      int smax = 1024;
-      if (const char* e = std::getenv("RPF_SUBTREE_MAX")) smax = std::max(1, std::min(32767, std::atoi(e)));
-      h->P = build_presolve(G, smax);
+      h->P = build_presolve(G, subtree_max());
       h->max_batch = max_batch;
       if ((int64_t)h->P.nvar * max_batch >= (int64_t)1 << 31)
         throw std::runtime_error("n_var * max_batch must stay below 2^31");
