@@ -1499,96 +1499,156 @@ __global__ void k_symmetrize(int n, double* __restrict__ K, const double* __rest
 // pivot records base + (column + 1) in info[0]; later kernels return early.
 
 // Diagonal block factorization with the 256 threads of the calling
-// workgroup; tile (CB x CB + 1), colb and rowb (2 x CB each) are LDS
-// provided by the caller.  Returns false when a pivot fails (info set).
+// workgroup; work is LDS provided by the caller (DIAG_WORK doubles).
+// Returns false when a pivot fails (info set).
+//
+// Thread (tr, tc) holds the 4 x 4 register tile of rows 4 tr .. 4 tr + 3,
+// columns 4 tc .. 4 tc + 3.  Per diagonal tile jt: its owner factorizes it
+// alone (four pivots in registers) and publishes it; the tiles below it
+// (and, for LU, right of it) solve against it in registers and publish the
+// result; every tile of the trailing part takes the rank-4 update.  Two
+// barriers per four pivots; finished factor entries stay in the registers
+// that computed them and are written from there.  A failed pivot does not
+// branch: the first failing index is kept (LDS minimum) and reported after
+// the loop, and the factor is then not written.
+constexpr int DIAG_WORK = 16 * 16 * 2 + 20 + 2;
+
 template <bool CHOL>
 __device__ __forceinline__ bool diag_factor(int n, int b0, double* __restrict__ A, int32_t* __restrict__ info, int base,
-                                   double (*tile)[CB + 1], double (*colb)[CB], double (*rowb)[CB]) {
+                                            double* __restrict__ work) {
   const int nb = min(CB, n - b0);
   const int t = threadIdx.x;
-  // coalesced load through LDS; outside the nb x nb corner an identity, so
-  // the padded pivots are 1 and leave the corner's factor unchanged
-  stage_tile<256>(tile, A + (size_t)b0 * n + b0, n, nb, nb, 1.0);
-  __syncthreads();
-  // thread (tr, tc) holds rows 4 tr .. 4 tr + 3, columns 4 tc .. 4 tc + 3
+  double (*colp)[16] = reinterpret_cast<double (*)[16]>(work);        // panel tile below the diagonal
+  double (*rowp)[16] = reinterpret_cast<double (*)[16]>(work + 256);  // LU: panel tile right of it
+  double* dt = work + 512;                                             // diagonal tile, reciprocal pivots
+  int* sbad = reinterpret_cast<int*>(work + 532);
   const int tr = t >> 4, tc = t & 15;
+  // direct loads (clamped addresses, all issued before use); outside the
+  // nb x nb corner an identity, so the padded pivots are 1 and leave the
+  // corner's factor unchanged
   double a[4][4];
+  {
+    double g[4][4];
 #pragma unroll
-  for (int p = 0; p < 4; ++p)
+    for (int p = 0; p < 4; ++p)
 #pragma unroll
-    for (int q = 0; q < 4; ++q) a[p][q] = tile[4 * tr + p][4 * tc + q];
-  // right-looking elimination, one barrier per pivot: the owners of column
-  // j (and, for LU, row j) publish it in a double-buffered LDS vector; every
-  // thread updates its 16 entries.  Finished factor entries stay in the
-  // registers that held them (the update leaves them alone: their l or u
-  // factor is zero), so the tile in LDS is not touched again and the result
-  // is written from registers.  Pivots are unrolled by four so that every
-  // register index is static.  A failed pivot does not branch: the first
-  // failing index is kept and reported after the loop (the factor is then
-  // not written).
-  int bad = CB;
-  for (int jt = 0; 4 * jt < nb; ++jt) {
+      for (int q = 0; q < 4; ++q)
+        g[p][q] = A[(size_t)(b0 + min(4 * tr + p, nb - 1)) * n + b0 + min(4 * tc + q, nb - 1)];
 #pragma unroll
-    for (int jq = 0; jq < 4; ++jq) {
-      const int j = 4 * jt + jq;
-      const int buf = jq & 1;
-      if (tc == jt) {
-#pragma unroll
-        for (int p = 0; p < 4; ++p) colb[buf][4 * tr + p] = a[p][jq];
-      }
-      if (!CHOL && tr == jt) {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) rowb[buf][4 * tc + q] = a[jq][q];
-      }
-      lds_barrier();
-      const double d = colb[buf][j];
-      double cr[4], cc[4];
-#pragma unroll
-      for (int p = 0; p < 4; ++p) cr[p] = colb[buf][4 * tr + p];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) cc[q] = CHOL ? colb[buf][4 * tc + q] : rowb[buf][4 * tc + q];
-      const bool ok = CHOL ? (d > 0.0 && isfinite(d)) : (fabs(d) > 0.0 && isfinite(d));
-      bad = min(bad, ok ? CB : j);
-      // rp = 1 / sqrt(d) (Cholesky) or 1 / d (LU): hardware estimate and
-      // one Newton step (relative error ~1e-16; far shorter chain than the
-      // correctly rounded library sequences)
-      double rp;
-      if (CHOL) {
-        const double y0 = __builtin_amdgcn_rsq(d);
-        const double h = 0.5 * y0, g = d * y0;
-        rp = fma(y0, fma(-h, g, 0.5), y0);
-      } else {
-        const double y0 = __builtin_amdgcn_rcp(d);
-        rp = fma(y0, fma(-d, y0, 1.0), y0);
-      }
-      double l[4], u[4];
-#pragma unroll
-      for (int p = 0; p < 4; ++p) {
-        const bool below = tr > jt || (tr == jt && p > jq);
-        l[p] = below ? cr[p] * rp : 0.0;
-      }
+    for (int p = 0; p < 4; ++p)
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const bool right = tc > jt || (tc == jt && q > jq);
-        u[q] = right ? (CHOL ? cc[q] * rp : cc[q]) : 0.0;
+        const int r = 4 * tr + p, c = 4 * tc + q;
+        a[p][q] = (r < nb && c < nb) ? g[p][q] : (r == c ? 1.0 : 0.0);
+      }
+  }
+  if (t == 0) *sbad = CB;
+  const int njt = (nb + 3) >> 2;
+  for (int jt = 0; jt < njt; ++jt) {
+    if (tr == jt && tc == jt) {
+      int bad = CB;
+      double rd[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const double d = a[k][k];
+        const bool ok = CHOL ? (d > 0.0 && isfinite(d)) : (fabs(d) > 0.0 && isfinite(d));
+        bad = min(bad, ok ? CB : 4 * jt + k);
+        // 1 / sqrt(d) (Cholesky) or 1 / d (LU): hardware estimate and one
+        // Newton step (relative error ~1e-16)
+        double rp;
+        if (CHOL) {
+          const double y0 = __builtin_amdgcn_rsq(d);
+          const double h = 0.5 * y0, g = d * y0;
+          rp = fma(y0, fma(-h, g, 0.5), y0);
+          a[k][k] = d * rp;
+        } else {
+          const double y0 = __builtin_amdgcn_rcp(d);
+          rp = fma(y0, fma(-d, y0, 1.0), y0);
+        }
+        rd[k] = rp;
+#pragma unroll
+        for (int p = k + 1; p < 4; ++p) a[p][k] *= rp;
+#pragma unroll
+        for (int p = k + 1; p < 4; ++p)
+#pragma unroll
+          for (int q = k + 1; q < 4; ++q)
+            if (!CHOL || q <= p) a[p][q] -= a[p][k] * (CHOL ? a[q][k] : a[k][q]);
       }
 #pragma unroll
       for (int p = 0; p < 4; ++p)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) a[p][q] -= l[p] * u[q];
-      // column j of the factor: multipliers below the pivot (and, for the
-      // Cholesky factor, sqrt(d) on the diagonal) replace the eliminated
-      // entries in the registers of the column's owners
-      if (tc == jt) {
+        for (int q = 0; q < 4; ++q) dt[4 * p + q] = a[p][q];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) dt[16 + k] = rd[k];
+      if (bad < CB) atomicMin(sbad, bad);
+    }
+    lds_barrier();
+    if (tc == jt && tr > jt) {
+      // X L^T = A (Cholesky: L the factored diagonal tile) or X U = A (LU)
+      double D[4][4], rd[4];
+#pragma unroll
+      for (int p = 0; p < 4; ++p)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) D[p][q] = dt[4 * p + q];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) rd[k] = dt[16 + k];
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
 #pragma unroll
         for (int p = 0; p < 4; ++p) {
-          const int r = 4 * tr + p;
-          a[p][jq] = r > j ? l[p] : (CHOL && r == j ? d * rp : a[p][jq]);
+          double x = a[p][k];
+#pragma unroll
+          for (int m = 0; m < k; ++m) x -= a[p][m] * (CHOL ? D[k][m] : D[m][k]);
+          a[p][k] = x * rd[k];
         }
-      }
+#pragma unroll
+      for (int p = 0; p < 4; ++p)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) colp[tr][4 * p + q] = a[p][q];
+    }
+    if (!CHOL && tr == jt && tc > jt) {
+      // L Y = A, L the unit lower part of the factored diagonal tile
+      double D[4][4];
+#pragma unroll
+      for (int p = 0; p < 4; ++p)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) D[p][q] = dt[4 * p + q];
+#pragma unroll
+      for (int k = 1; k < 4; ++k)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          double y = a[k][q];
+#pragma unroll
+          for (int m = 0; m < k; ++m) y -= D[k][m] * a[m][q];
+          a[k][q] = y;
+        }
+#pragma unroll
+      for (int p = 0; p < 4; ++p)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) rowp[tc][4 * p + q] = a[p][q];
+    }
+    lds_barrier();
+    if (tr > jt && tc > jt && (!CHOL || tc <= tr)) {
+      double Lt[4][4], Ut[4][4];
+#pragma unroll
+      for (int p = 0; p < 4; ++p)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) Lt[p][k] = colp[tr][4 * p + k];
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) Ut[k][q] = CHOL ? colp[tc][4 * q + k] : rowp[tc][4 * k + q];
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+#pragma unroll
+        for (int p = 0; p < 4; ++p)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) a[p][q] -= Lt[p][k] * Ut[k][q];
     }
   }
-  if (bad < nb) {  // uniform: every thread saw the same pivots
+  lds_barrier();
+  const int bad = *sbad;
+  if (bad < nb) {  // uniform: read after the barrier by every thread
     if (t == 0) info[0] = base + b0 + bad + 1;
     return false;
   }
@@ -1606,11 +1666,9 @@ template <bool CHOL>
 __global__ void __launch_bounds__(256) k_blk_diag(int n, int b0, double* __restrict__ A, int32_t* __restrict__ info,
                                                   int base, const int32_t* __restrict__ skip) {
   if (skip && *skip) return;
-  __shared__ double tile[CB][CB + 1];
-  __shared__ double colb[2][CB];
-  __shared__ double rowb[2][CB];
+  __shared__ double work[DIAG_WORK];
   if (info[0] != 0) return;
-  diag_factor<CHOL>(n, b0, A, info, base, tile, colb, rowb);
+  diag_factor<CHOL>(n, b0, A, info, base, work);
 }
 
 // Panels: wave task t < rows below: row r solves x U11 = a (LU) or
@@ -1701,9 +1759,8 @@ __global__ void __launch_bounds__(256) k_blk_update(int n, int b0, double* __res
     }
   if (fuse && ti == 0 && tj == 0) {
     __syncthreads();   // the updated block is in A; the LDS tiles are free
-    double (*colb)[CB] = reinterpret_cast<double (*)[CB]>(&sm[1][0][0]);
-    double (*rowb)[CB] = reinterpret_cast<double (*)[CB]>(&sm[1][0][0] + 2 * CB);
-    diag_factor<CHOL>(n, base, A, info, dbase, sm[0], colb, rowb);
+    static_assert(DIAG_WORK <= CB * (CB + 1), "diagonal work area must fit one tile");
+    diag_factor<CHOL>(n, base, A, info, dbase, &sm[0][0][0]);
   }
 }
 
