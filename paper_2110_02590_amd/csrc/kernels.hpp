@@ -332,6 +332,13 @@ __device__ __forceinline__ int64_t readlane64(int64_t v, int s) {
   return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
 }
 
+// lane s's double (s uniform)
+__device__ __forceinline__ double readlane_f64(double v, int s) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), s);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), s);
+  return __hiloint2double(hi, lo);
+}
+
 __global__ void __launch_bounds__(1024) k_rf_pack_lds(const int32_t* __restrict__ pack_ptr,
                                                       const int32_t* __restrict__ flev,
                                                       const int32_t* __restrict__ flev_off,
@@ -1689,21 +1696,25 @@ __global__ void k_blk_panel(int n, int b0, double* __restrict__ A, const int32_t
   __syncthreads();
   const int lane = threadIdx.x & 63;
   const int task = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  // substitution along the lanes: the solved entry j is broadcast with
+  // readlane (a scalar register), so each step is a short dependent chain
+  // of vector ALU operations; the factor entries come from LDS off the chain
   if (task < rest) {
     double* a = A + (size_t)(b0 + nb + task) * n + b0;
     double v = lane < nb ? a[lane] : 0.0;
     for (int j = 0; j < nb; ++j) {
-      const double xj = __shfl(v, j, 64) * rd[j];
-      if (lane == j) v = xj;
-      if (lane > j) v -= xj * (CHOL ? T[lane][j] : T[j][lane]);
+      const double f = CHOL ? T[lane][j] : T[j][lane];
+      const double xj = readlane_f64(v, j) * rd[j];
+      v = lane == j ? xj : (lane > j ? fma(-xj, f, v) : v);
     }
     if (lane < nb) a[lane] = v;
   } else if (!CHOL && task < 2 * rest) {
     const int c = b0 + nb + (task - rest);
     double v = lane < nb ? A[(size_t)(b0 + lane) * n + c] : 0.0;
     for (int j = 0; j < nb; ++j) {
-      const double yj = __shfl(v, j, 64);
-      if (lane > j) v -= T[lane][j] * yj;
+      const double f = T[lane][j];
+      const double yj = readlane_f64(v, j);
+      v = lane > j ? fma(-f, yj, v) : v;
     }
     if (lane < nb) A[(size_t)(b0 + lane) * n + c] = v;
   }
