@@ -339,6 +339,29 @@ __device__ __forceinline__ double readlane_f64(double v, int s) {
   return __hiloint2double(hi, lo);
 }
 
+// v of the lane that the DPP control CTRL selects (every lane active)
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+  return __hiloint2double(hi, lo);
+}
+
+// Sum over aligned groups of G consecutive lanes (G a power of two, at most
+// 64, uniform); every lane of a group receives the group's sum.  Within
+// rows of 16 lanes by DPP (quad permutations, then the half-row and row
+// mirrors, each pairing a lane with one holding the other half's partial
+// sum), across rows by lane shuffles.  Every lane must be active.
+__device__ __forceinline__ double group_sum(double v, int G) {
+  if (G >= 2) v += dpp_f64<0xB1>(v);    // quad_perm [1, 0, 3, 2]
+  if (G >= 4) v += dpp_f64<0x4E>(v);    // quad_perm [2, 3, 0, 1]
+  if (G >= 8) v += dpp_f64<0x141>(v);   // row_half_mirror
+  if (G >= 16) v += dpp_f64<0x140>(v);  // row_mirror
+  if (G >= 32) v += __shfl_xor(v, 16, 64);
+  if (G >= 64) v += __shfl_xor(v, 32, 64);
+  return v;
+}
+
 __global__ void __launch_bounds__(1024) k_rf_pack_lds(const int32_t* __restrict__ pack_ptr,
                                                       const int32_t* __restrict__ flev,
                                                       const int32_t* __restrict__ flev_off,
@@ -361,6 +384,21 @@ __global__ void __launch_bounds__(1024) k_rf_pack_lds(const int32_t* __restrict_
   const int t = threadIdx.x;
   stage_1d(sv, a + gp0, seg);
   __syncthreads();
+  // max |a_ij| of each row before elimination, for the pivot test, kept in
+  // the row's reciprocal-pivot slot until the row is finished (no step
+  // reads a slot before its row is done)
+  for (int r = t; r < nr; r += blockDim.x) {
+    const int p0 = ptr[r0 + r] - gp0, p1 = ptr[r0 + r + 1] - gp0;
+    double m0 = 0.0, m1 = 0.0;
+    int e = p0;
+    for (; e + 1 < p1; e += 2) {
+      m0 = fmax(m0, fabs(sv[e]));
+      m1 = fmax(m1, fabs(sv[e + 1]));
+    }
+    if (e < p1) m0 = fmax(m0, fabs(sv[e]));
+    srd[r] = fmax(m0, m1);
+  }
+  __syncthreads();
   const int wave = t >> 6, lane = t & 63, nwave = blockDim.x >> 6;
   for (int lv = flev_off[q]; lv < flev_off[q + 1]; ++lv) {
     for (int rr = flev[lv] + wave; rr < flev[lv + 1]; rr += nwave) {
@@ -369,8 +407,6 @@ __global__ void __launch_bounds__(1024) k_rf_pack_lds(const int32_t* __restrict_
       const int p0 = __builtin_amdgcn_readfirstlane(ptr[i]);
       const int pdg = __builtin_amdgcn_readfirstlane(diag[i]);
       const int p1 = __builtin_amdgcn_readfirstlane(ptr[i + 1]);
-      double amax = 0.0;
-      for (int e = p0 + lane; e < p1; e += 64) amax = fmax(amax, fabs(sv[e - gp0]));
       for (int w0 = p0; w0 < pdg; w0 += 64) {
         const int nw = min(64, pdg - w0);
         int m_k = 0, m_us = 0, m_nu = 0;
@@ -415,8 +451,8 @@ __global__ void __launch_bounds__(1024) k_rf_pack_lds(const int32_t* __restrict_
           tgB = fetch_tg(min(st + 3, nw - 1));
         }
       }
-      for (int off = 32; off > 0; off >>= 1) amax = fmax(amax, __shfl_xor(amax, off, 64));
       if (lane == 0) {
+        const double amax = srd[i - r0];
         const double piv = sv[pdg - gp0];
         const double rp = 1.0 / piv;
         srd[i - r0] = rp;
@@ -833,7 +869,7 @@ __global__ void __launch_bounds__(256) k_pack_solve_s(const int32_t* __restrict_
         for (; e < e1; e += G) q0 += sv[e] * xs[scol[e] * TW + cc];
       }
       double part = (q0 + q1) + (q2 + q3);
-      for (int o = G >> 1; o > 0; o >>= 1) part += __shfl_xor(part, o, 64);
+      part = group_sum(part, G);
       if (act && seg == 0) {
         double acc = xs[r * TW + cc] - part;
         if (!UNIT) acc /= dg[r];
@@ -944,7 +980,7 @@ __global__ void __launch_bounds__(1024) k_pack_solve_g(const int32_t* __restrict
         q3 += v[3] * xv[3] + v[7] * xv[7];
       }
       double part = (q0 + q1) + (q2 + q3);
-      for (int o = G >> 1; o > 0; o >>= 1) part += __shfl_xor(part, o, 64);
+      part = group_sum(part, G);
       if (cok && segl == 0) {
         double xnew = (FWD ? scale * xown : xown) - part;
         if (!UNIT) xnew *= srd[rl];
@@ -1863,8 +1899,7 @@ __global__ void __launch_bounds__(256) k_chol_fwd(int n, const double* __restric
     s1 += tri[r][sl * 16 + j + 1] * rv[sl * 16 + j + 1];
   }
   double sacc = s0 + s1;
-  sacc += __shfl_xor(sacc, 1, 64);
-  sacc += __shfl_xor(sacc, 2, 64);
+  sacc = group_sum(sacc, 4);
   if (sl == 0 && r < nb) y[b0 + r] = sacc;
   blk_publish(flags + w);
 }
@@ -1914,8 +1949,7 @@ __global__ void __launch_bounds__(256) k_chol_bwd(int n, const double* __restric
     s1 += tri[s4 * 16 + j + 1][r] * rv[s4 * 16 + j + 1];
   }
   double sacc = s0 + s1;
-  sacc += __shfl_xor(sacc, 1, 64);
-  sacc += __shfl_xor(sacc, 2, 64);
+  sacc = group_sum(sacc, 4);
   if (s4 == 0 && r < nb) x[b0 + r] = sacc;
   blk_publish(flags + w);
 }
