@@ -28,14 +28,14 @@ HBM_PEAK_GBS = 8000.0
 FP64_PEAK_TFLOPS = 78.6
 
 # HBM traffic per launch from two rocprofv3 --pmc passes over this bench at
-# batch 1024 (FETCH_SIZE scaled by 2.0 and WRITE_SIZE by 1.0: what the two
+# batch 512 (FETCH_SIZE scaled by 2.0 and WRITE_SIZE by 1.0: what the two
 # counters read for a 1 GiB streaming kernel; KiB per dispatch averaged over
 # the four forward/backward x J_x/J_x^T variants).  Valid only for the kernel
-# source it was measured on (sha1 of the kernel's text in kernels.hpp);
-# reported as null once that text changes.  Figures and commands:
-# profiles/pack_solve_t_syn9241_traffic.txt.
+# source it was measured on (sha1 of the kernel's text in kernels.hpp) and
+# for the batch width it was measured at; reported as null otherwise.
+# Figures and commands: profiles/pack_solve_t_syn9241_traffic.txt.
 TRAFFIC = {
-    "pack_solve": {"kernel": "k_pack_solve_t", "bytes_per_launch": 261714358,
+    "pack_solve": {"kernel": "k_pack_solve_t", "batch": 512, "bytes_per_launch": 130531302,
                    "source_sha1": "3e04cb8c14f31226f3183b88fb76ae283976c671"},
 }
 
@@ -293,7 +293,7 @@ def roofline(g, pr, prof, B, steps):
     add("cholesky", "dense Cholesky group (k_symmetrize, k_blk_*<true>, k_chol_fwd/bwd)", "dense",
         chol_flops, "mfma", FP64_PEAK_TFLOPS, "TFLOP/s", f"flops n_u^3/3 + 2 n_u^2, n_u={nu}")
     for name, tr in TRAFFIC.items():
-        if name in ent and _kernel_sha1(tr["kernel"]) == tr["source_sha1"]:
+        if name in ent and _kernel_sha1(tr["kernel"]) == tr["source_sha1"] and tr["batch"] == B:
             ent[name]["traffic"] = tr["bytes_per_launch"]
     if not ent:
         return None, {}

@@ -426,14 +426,20 @@ __global__ void __launch_bounds__(1024) k_rf_pack_lds(const int32_t* __restrict_
           const int64_t u = readlane64(m_u0, st);
           return upd_tgt[u + (lane < __builtin_amdgcn_readlane(m_nu, st) ? lane : 0)];
         };
+        // the U entry and the target's current value are read with clamped
+        // addresses (no branch around the reads; a wavefront's LDS
+        // operations complete in order, so they see every earlier step's
+        // stores); only the store is predicated
         auto step = [&](int st, int tgabs) {
           const int k = __builtin_amdgcn_readlane(m_k, st);
           const int us = __builtin_amdgcn_readlane(m_us, st) - gp0;
           const int nu = __builtin_amdgcn_readlane(m_nu, st);
           const int pl = w0 + st - gp0;
-          const double av = lane < nu ? sv[us + lane] : 0.0;
+          const bool on = lane < nu;
+          const double av = sv[us + (on ? lane : 0)];
+          const double cur = sv[on ? tgabs - gp0 : pl];
           const double l = sv[pl] * srd[k - r0];
-          if (lane < nu) sv[tgabs - gp0] -= l * av;
+          if (on) sv[tgabs - gp0] = cur - l * av;
           if (nu > 64) {
             const int64_t u0 = readlane64(m_u0, st);
             for (int tt = lane + 64; tt < nu; tt += 64) sv[upd_tgt[u0 + tt] - gp0] -= l * sv[us + tt];

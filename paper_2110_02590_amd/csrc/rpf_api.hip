@@ -97,7 +97,7 @@ struct rpf_grid {
   double *D, *Y, *T, *chol_work;
   // the batches of rpf_reduced_hessian run on nhs internal streams, each
   // with its own D, Y, T workspace (slot 0 is D, Y, T above)
-  static constexpr int HS = 3;
+  static constexpr int HS = 8;
   int nhs = 1;
   hipStream_t hs[HS] = {};
   hipEvent_t ev_fork = nullptr, ev_join[HS] = {};
@@ -442,8 +442,9 @@ void setup(rpf_grid* h) {
   h->Dk[0] = h->D;
   h->Yk[0] = h->Y;
   h->Tk[0] = h->T;
-  // concurrent batches for large batch widths (RPF_HVP_STREAMS = 1 .. 3)
-  h->nhs = h->max_batch >= 512 ? rpf_grid::HS : 1;
+  // concurrent batches for large batch widths: three streams
+  // (RPF_HVP_STREAMS = 1 .. 8 overrides)
+  h->nhs = h->max_batch >= 512 ? 3 : 1;
   if (const char* e = std::getenv("RPF_HVP_STREAMS")) h->nhs = std::max(1, std::min(rpf_grid::HS, std::atoi(e)));
   if (h->nhs > 1) {
     HIPCHK(hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming));

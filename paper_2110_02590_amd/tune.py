@@ -45,14 +45,16 @@ def best_batch(g, ep, candidates=CANDIDATES, reps=2, use_cache=True) -> int:
         return int(table[key]["batch"])
     nu = 1 + 2 * int((g["bus_type"] == 1).sum())
     cands = sorted({min(c, nu) for c in candidates})
-    pr = Problem(g, max_batch=max(cands))
-    x = pr.flat_x()
-    pr.grid.pf_solve(pr.u0, pr.pd, pr.qd, x)
-    s, y, rho, sigma = pr.point(ep)
-    pr.grid.reduced_gradient(x, pr.u0, pr.pd, pr.qd, s, y, rho, sigma)
-    H = torch.empty((pr.nu, pr.nu), dtype=torch.float64, device="cuda")
     times = {}
     for B in cands:
+        # one handle per candidate, created as a caller with this batch width
+        # creates it (the handle's stream count depends on its max_batch)
+        pr = Problem(g, max_batch=B)
+        x = pr.flat_x()
+        pr.grid.pf_solve(pr.u0, pr.pd, pr.qd, x)
+        s, y, rho, sigma = pr.point(ep)
+        pr.grid.reduced_gradient(x, pr.u0, pr.pd, pr.qd, s, y, rho, sigma)
+        H = torch.empty((pr.nu, pr.nu), dtype=torch.float64, device="cuda")
         pr.grid.reduced_hessian(batch=B, H=H)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -60,8 +62,9 @@ def best_batch(g, ep, candidates=CANDIDATES, reps=2, use_cache=True) -> int:
             pr.grid.reduced_hessian(batch=B, H=H)
         torch.cuda.synchronize()
         times[B] = (time.perf_counter() - t0) / reps
+        pr.grid.close()
+        del pr, H
     best = min(times, key=times.get)
-    pr.grid.close()
     cache[key] = {"batch": best, "ms": {str(k): round(v * 1e3, 3) for k, v in times.items()}}
     try:
         with open(_CACHE, "w") as f:
