@@ -157,10 +157,11 @@ int rpf_reduced_hessian_batch(rpf_grid* grid, const double* V, int32_t nbatch, i
 /* The dense reduced Hessian H [n_u x n_u] (device, row-major, out) at the
  * cached point: products with the identity in batches of `batch` columns
  * (0 = the library's choice, at most max_batch).  For max_batch >= 512 the
- * batches run concurrently on up to three streams owned by the handle, each
- * with its own workspace, forked from `stream` and joined back to it by
- * events (the call stays capturable in a graph); RPF_HVP_STREAMS = 1 runs
- * them one after the other on `stream`. */
+ * batches run concurrently on three streams owned by the handle, each with
+ * its own workspace, forked from `stream` and joined back to it by events
+ * (the call stays capturable in a graph).  RPF_HVP_STREAMS (1 .. 8, read
+ * when the handle is created) sets the number of streams; 1 runs the
+ * batches one after the other on `stream`. */
 int rpf_reduced_hessian(rpf_grid* grid, double* H, int32_t batch, rpf_stream_t stream);
 
 /* Dense step (Section IV-B.2): K = (H + H^T)/2 + diag(d) + delta I is
