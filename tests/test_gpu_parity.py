@@ -29,7 +29,7 @@ class Case:
         self.M = oracle.Model(self.g)
         self.u = self.M.u_from_setpoints(self.g["vg0"], self.g["pg0"])
         self.P = oracle.Point.from_dict(self.ep)
-        self._o = {}
+        self._o = _ORACLE.setdefault(name, {})   # oracle results shared by a grid's handles
 
     def oracle(self, what):
         if what not in self._o:
@@ -55,6 +55,7 @@ class Case:
 
 
 _cases = {}
+_ORACLE = {}
 
 
 def case(name, max_batch=256):
@@ -142,12 +143,15 @@ def test_random_directions_linear():
     assert _rel(HV.cpu().numpy(), c.oracle("H") @ V.cpu().numpy()) < 1e-9
 
 
-def test_largest_workload_sampled_columns():
+@pytest.mark.parametrize("max_batch", [512, 1024])
+def test_largest_workload_sampled_columns(max_batch):
     """9241-bus grid: full reduced Hessian on the GPU, sampled columns
-    against the oracle's adjoint-adjoint products, symmetry at full size."""
-    c = case("syn9241", max_batch=1024)
+    against the oracle's adjoint-adjoint products, symmetry at full size.
+    512 is the benchmark's launch configuration (six batches, the last one
+    329 columns, on three streams)."""
+    c = case("syn9241", max_batch=max_batch)
     c.gpu_point()
-    H = c.pr.grid.reduced_hessian(batch=1024)
+    H = c.pr.grid.reduced_hessian(batch=max_batch)
     torch.cuda.synchronize()
     Hg = H.cpu().numpy()
     cols = np.array([0, 1, 2, 777, 1444, 1445, 2000, 2888])
@@ -176,6 +180,54 @@ def test_factor_solve_matches_lapack():
     Lg = np.tril(K.cpu().numpy())
     assert _rel(Lg, Lo) < 1e-11
     assert _rel(step.cpu().numpy(), so) < 1e-9
+
+
+def test_factor_solve_full_size():
+    """The Cholesky step at the 9241-bus grid's n_u = 2889 (45 blocks of 64,
+    ragged last block), shifted as the benchmark shifts it, against the
+    oracle's column Cholesky and triangular solves."""
+    c = case("syn9241", max_batch=512)
+    x, st, res, grad, lam = c.gpu_point()
+    H = c.pr.grid.reduced_hessian(batch=512)
+    Hn = H.cpu().numpy()
+    delta = 10.0 * max(oracle.delta_ladder(Hn), 1e-8 * max(1.0, float(np.abs(np.diag(Hn)).max())))
+    K = H.clone()
+    step, info = c.pr.grid.factor_solve(K, grad, delta=delta)
+    torch.cuda.synchronize()
+    Lo, io, so = oracle.factor_solve(Hn, None, delta, grad.cpu().numpy())
+    assert int(info) == 0 and io == 0
+    assert _rel(np.tril(K.cpu().numpy()), Lo) < 1e-11
+    assert _rel(step.cpu().numpy(), so) < 1e-9
+
+
+def test_concurrent_batches_match_one_stream():
+    """Batches on the handle's three streams give the same reduced Hessian,
+    bit for bit, as one stream (each batch has its own workspace; no
+    floating-point atomics)."""
+    import os
+    from paper_2110_02590_amd import Problem
+    g = gridgen.grid("syn2000")
+    ep = gridgen.eval_point(g)
+    out = []
+    for streams in ("1", None):
+        old = os.environ.pop("RPF_HVP_STREAMS", None)
+        if streams:
+            os.environ["RPF_HVP_STREAMS"] = streams
+        try:
+            pr = Problem(g, max_batch=512)
+        finally:
+            os.environ.pop("RPF_HVP_STREAMS", None)
+            if old is not None:
+                os.environ["RPF_HVP_STREAMS"] = old
+        x = pr.flat_x()
+        pr.grid.pf_solve(pr.u0, pr.pd, pr.qd, x)
+        s, y, rho, sigma = pr.point(ep)
+        pr.grid.reduced_gradient(x, pr.u0, pr.pd, pr.qd, s, y, rho, sigma)
+        H = pr.grid.reduced_hessian(batch=96)   # several batches, ragged last
+        torch.cuda.synchronize()
+        out.append(H.cpu().numpy())
+        pr.grid.close()
+    assert np.array_equal(out[0], out[1])
 
 
 def test_factor_reports_first_bad_pivot():
