@@ -347,18 +347,33 @@ __device__ __forceinline__ double dpp_f64(double v) {
   return __hiloint2double(hi, lo);
 }
 
+// v(lane) + v(lane xor 16) and v(lane) + v(lane xor 32), in registers: the
+// permlane swaps exchange alternate 16-lane rows (32-lane halves) of their
+// two operands; with v in both, the two results hold v of the lane and of
+// its partner, in one order or the other (the sum is the same either way)
+__device__ __forceinline__ double sum_xor16(double v) {
+  const auto lo = __builtin_amdgcn_permlane16_swap((unsigned)__double2loint(v), (unsigned)__double2loint(v), false, false);
+  const auto hi = __builtin_amdgcn_permlane16_swap((unsigned)__double2hiint(v), (unsigned)__double2hiint(v), false, false);
+  return __hiloint2double((int)hi[0], (int)lo[0]) + __hiloint2double((int)hi[1], (int)lo[1]);
+}
+__device__ __forceinline__ double sum_xor32(double v) {
+  const auto lo = __builtin_amdgcn_permlane32_swap((unsigned)__double2loint(v), (unsigned)__double2loint(v), false, false);
+  const auto hi = __builtin_amdgcn_permlane32_swap((unsigned)__double2hiint(v), (unsigned)__double2hiint(v), false, false);
+  return __hiloint2double((int)hi[0], (int)lo[0]) + __hiloint2double((int)hi[1], (int)lo[1]);
+}
+
 // Sum over aligned groups of G consecutive lanes (G a power of two, at most
 // 64, uniform); every lane of a group receives the group's sum.  Within
 // rows of 16 lanes by DPP (quad permutations, then the half-row and row
 // mirrors, each pairing a lane with one holding the other half's partial
-// sum), across rows by lane shuffles.  Every lane must be active.
+// sum), across rows by permlane swaps.  Every lane must be active.
 __device__ __forceinline__ double group_sum(double v, int G) {
   if (G >= 2) v += dpp_f64<0xB1>(v);    // quad_perm [1, 0, 3, 2]
   if (G >= 4) v += dpp_f64<0x4E>(v);    // quad_perm [2, 3, 0, 1]
   if (G >= 8) v += dpp_f64<0x141>(v);   // row_half_mirror
   if (G >= 16) v += dpp_f64<0x140>(v);  // row_mirror
-  if (G >= 32) v += __shfl_xor(v, 16, 64);
-  if (G >= 64) v += __shfl_xor(v, 32, 64);
+  if (G >= 32) v = sum_xor16(v);
+  if (G >= 64) v = sum_xor32(v);
   return v;
 }
 
@@ -1111,7 +1126,12 @@ __global__ void __launch_bounds__(1024) k_pack_solve_t(const int32_t* __restrict
         }
       }
       double part = (q0 + q1) + (q2 + q3);
-      for (int o = G >> 1; o > 0; o >>= 1) part += __shfl_xor(part, o * TW, 64);
+      if (TW == 16) {   // lanes c, c + 16, c + 32, c + 48 share column c
+        if (G >= 4) part = sum_xor32(part);
+        if (G >= 2) part = sum_xor16(part);
+      } else {
+        for (int o = G >> 1; o > 0; o >>= 1) part += __shfl_xor(part, o * TW, 64);
+      }
       if (act && seg == 0) {
         double v = xs[rl * TW + cI] - part;
         if (!UNIT) v *= rdg[r0 + rl];
