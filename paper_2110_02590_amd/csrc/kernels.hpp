@@ -1104,7 +1104,12 @@ __global__ void __launch_bounds__(1024) k_pack_solve_t(const int32_t* __restrict
     for (int base = 0; base < nrow; base += nwave << lgR) {
       const int k = base + (wave << lgR) + rowslot;
       const bool act = k < nrow;
-      const int rl = act ? srow[a + k] : 0;
+      const int rl = srow[a + min(k, nrow - 1)];
+      // the row's own right-hand side (no other row writes it) and pivot
+      // reciprocal, loaded before the entry loop, off the chain that ends
+      // in the row's store
+      const double xo = xs[rl * TW + cI];
+      const double rdv = UNIT ? 1.0 : rdg[r0 + rl];
       double q0 = 0.0, q1 = 0.0, q2 = 0.0, q3 = 0.0;
       if (act) {
         const int es = srp[rl], ee = srp[rl + 1];
@@ -1133,8 +1138,8 @@ __global__ void __launch_bounds__(1024) k_pack_solve_t(const int32_t* __restrict
         for (int o = G >> 1; o > 0; o >>= 1) part += __shfl_xor(part, o * TW, 64);
       }
       if (act && seg == 0) {
-        double v = xs[rl * TW + cI] - part;
-        if (!UNIT) v *= rdg[r0 + rl];
+        double v = xo - part;
+        if (!UNIT) v *= rdv;
         xs[rl * TW + cI] = v;
       }
     }
