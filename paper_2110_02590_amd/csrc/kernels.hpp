@@ -1017,15 +1017,15 @@ __global__ void __launch_bounds__(1024) k_pack_solve_g(const int32_t* __restrict
 // tile X[r0 .. r1) x [c0, c0 + TW) (forward: times scale; backward: the
 // products with the top rows are already subtracted by k_pack_topmul), and
 // the pack program of the
-// direction: local columns (int16), row pointers, rows in level order,
-// level offsets.  Factor values come from pval, a copy in program order
+// direction: local columns (int16), rows in level order with each row's
+// first entry and length in one word, level offsets.  Factor values come from pval, a copy in program order
 // (one load per entry); 1 / u_ii from rdg (non-unit factors).  Per level a
 // wavefront covers R rows x TW columns (lanes: column fastest, then G lanes
 // sharing one row's entries, then R row slots; R G TW = 64); R shrinks on
 // narrow levels so that more lanes share a row.  Eight entries per lane are
 // in flight at a time.
 // With SV the values are staged too and every level touches only LDS.
-// LDS: [sval[ne] (double, SV)] | xs[nr TW] (double) | srp[nr + 1] |
+// LDS: [sval[ne] (double, SV)] | xs[nr TW] (double) | smeta[nr + 1] |
 // slev[nlev + 1] (int) | srow[nr] | scol[ne] (int16).
 __host__ __device__ __forceinline__ size_t packt_lds_bytes(int nr, int ne, int nlev, int tw, bool sv) {
   return (sv ? (size_t)ne * 8 : 0) + (size_t)nr * tw * 8 + (size_t)(nr + 1) * 4 + (size_t)(nlev + 1) * 4 +
@@ -1065,15 +1065,22 @@ __global__ void __launch_bounds__(1024) k_pack_solve_t(const int32_t* __restrict
   const int base_row = lev[l0];
   double* sval = smem;
   double* xs = smem + (SV ? ne : 0);
-  int* srp = (int*)(xs + (size_t)nr * TW);
-  int* slev = srp + nr + 1;
+  int* smeta = (int*)(xs + (size_t)nr * TW);
+  int* slev = smeta + nr + 1;
   int16_t* srow = (int16_t*)(slev + nlev + 1);
   int16_t* scol = srow + nr;
   const int t = threadIdx.x, nt = blockDim.x;
   stage_1d(scol, ecol + e0, ne);
   if (SV) stage_1d(sval, pval + e0, ne);
-  for (int r = t; r <= nr; r += nt) srp[r] = rp[r0 + r] - e0;
-  for (int r = t; r < nr; r += nt) srow[r] = (int16_t)(lrows[base_row + r] - r0);
+  // per level position: the row, and its first entry | length << 20 (entries
+  // of a pack below 2^20, row lengths below 2^11: checked on the host), so
+  // that both come from one LDS round trip
+  for (int p = t; p < nr; p += nt) {
+    const int row = lrows[base_row + p] - r0;
+    const int es = rp[r0 + row], ee = rp[r0 + row + 1];
+    srow[p] = (int16_t)row;
+    smeta[p] = (es - e0) | ((ee - es) << 20);
+  }
   for (int k = t; k <= nlev; k += nt) slev[k] = lev[l0 + k] - base_row;
   // right-hand-side tile, eight loads in flight per thread
   const int ntile = nr * TW;
@@ -1104,7 +1111,9 @@ __global__ void __launch_bounds__(1024) k_pack_solve_t(const int32_t* __restrict
     for (int base = 0; base < nrow; base += nwave << lgR) {
       const int k = base + (wave << lgR) + rowslot;
       const bool act = k < nrow;
-      const int rl = srow[a + min(k, nrow - 1)];
+      const int kk = a + min(k, nrow - 1);
+      const int rl = srow[kk];
+      const int meta = smeta[kk];
       // the row's own right-hand side (no other row writes it) and pivot
       // reciprocal, loaded before the entry loop, off the chain that ends
       // in the row's store
@@ -1112,7 +1121,7 @@ __global__ void __launch_bounds__(1024) k_pack_solve_t(const int32_t* __restrict
       const double rdv = UNIT ? 1.0 : rdg[r0 + rl];
       double q0 = 0.0, q1 = 0.0, q2 = 0.0, q3 = 0.0;
       if (act) {
-        const int es = srp[rl], ee = srp[rl + 1];
+        const int es = meta & 0xFFFFF, ee = es + (meta >> 20);
         for (int eb = es + seg; eb < ee; eb += 8 * G) {
           double vv[8], xv[8];
 #pragma unroll

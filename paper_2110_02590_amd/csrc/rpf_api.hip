@@ -337,7 +337,19 @@ void setup(rpf_grid* h) {
         if (const char* f = std::getenv("RPF_PACK_SV")) sv = std::atoi(f) != 0;
         if (tw == 8 || tw == 16) order.insert(order.begin(), V{tw, sv && tw == 8});
       }
+      // the kernel packs a row's first entry and length into one word:
+      // entries of a pack below 2^20, row lengths below 2^11
+      bool fits_word = true;
+      for (int q = 0; q < h->npacks; ++q) {
+        const int r0 = P.pack_ptr[q], nr = P.pack_ptr[q + 1] - r0;
+        for (const auto* rpv : {&P.pkf_rp, &P.pkb_rp}) {
+          if ((*rpv)[r0 + nr] - (*rpv)[r0] >= (1 << 20)) fits_word = false;
+          for (int r = r0; r < r0 + nr; ++r)
+            if ((*rpv)[r + 1] - (*rpv)[r] >= (1 << 11)) fits_word = false;
+        }
+      }
       for (const V& v : order) {
+        if (!fits_word) break;
         size_t mx = 0;
         for (int q = 0; q < h->npacks; ++q) {
           const int r0 = P.pack_ptr[q], nr = P.pack_ptr[q + 1] - r0;
