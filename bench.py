@@ -35,8 +35,8 @@ FP64_PEAK_TFLOPS = 78.6
 # for the batch width it was measured at; reported as null otherwise.
 # Figures and commands: profiles/pack_solve_t_syn9241_traffic.txt.
 TRAFFIC = {
-    "pack_solve": {"kernel": "k_pack_solve_t", "batch": 512, "bytes_per_launch": 130531302,
-                   "source_sha1": "3e04cb8c14f31226f3183b88fb76ae283976c671"},
+    "pack_solve": {"kernel": "k_pack_solve_t", "batch": 512, "bytes_per_launch": 130538394,
+                   "source_sha1": "2679c824e7a7f61f3be60656ef34ca4878385926"},
 }
 
 
