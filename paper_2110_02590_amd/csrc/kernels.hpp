@@ -643,55 +643,74 @@ __global__ void k_pack_topmul(int t0, const int32_t* __restrict__ up_split, cons
   X[(size_t)i * ld + c] -= (a[0] + a[1]) + (a[2] + a[3]);
 }
 
+// Rows of the inverse of one triangular CB x CB block, in solve order
+// (LOWER: top down, terms j < i; upper: bottom up, terms j > i).  Thread
+// (column c, segment seg) holds z[4 m + seg][c] in zr[m] and sums the terms
+// j = 4 m + seg; the four segments of a column are adjacent lanes and
+// combine their partial sums by DPP.  T is the strict triangle (zero
+// elsewhere), so terms outside it, and entries of zr not yet solved (zero),
+// add nothing; loops start or stop at the first term a row can need.
+template <bool LOWER>
+__device__ __forceinline__ void tri_inv_rows(const double (*T)[CB + 1], const double* rd, int c, int seg, int nb,
+                                             double* zr) {
+#pragma unroll
+  for (int k = 0; k < CB; ++k) {
+    const int i = LOWER ? k : CB - 1 - k;
+    double a0 = (i == c && seg == 0) ? 1.0 : 0.0, a1 = 0.0;
+    constexpr int M = CB / 4;
+#pragma unroll
+    for (int m = LOWER ? 0 : i / 4; m < (LOWER ? (i + 3) / 4 : M); ++m) {
+      if (m & 1) a1 -= T[i][4 * m + seg] * zr[m];
+      else a0 -= T[i][4 * m + seg] * zr[m];
+    }
+    double v = group_sum(a0 + a1, 4) * rd[i];
+    v = (i < nb && c < nb) ? v : 0.0;
+    zr[i >> 2] = seg == (i & 3) ? v : zr[i >> 2];
+  }
+}
+
 // Inverses of the CB x CB diagonal blocks of a dense factor M (s x s,
 // row-major, lower part L, upper part U): blockIdx.y = 0 inverts the lower
 // triangle of block blockIdx.x (unit diagonal if lower_unit), 1 the upper
 // triangle (unit if upper_unit).  Output dinv[(kb * 2 + part) * CB * CB],
-// row-major CB x CB, zero outside the block's nb x nb corner.  One
-// wavefront; lane c computes column c of the inverse by substitution.
-__global__ void __launch_bounds__(64) k_top_diag_inv(int s, const double* __restrict__ M, double* __restrict__ dinv,
-                                                     int lower_unit, int upper_unit,
-                                                     const int32_t* __restrict__ skip) {
+// row-major CB x CB, zero outside the block's nb x nb corner.  256 threads:
+// four lanes per column of the inverse (tri_inv_rows).
+__global__ void __launch_bounds__(256) k_top_diag_inv(int s, const double* __restrict__ M, double* __restrict__ dinv,
+                                                      int lower_unit, int upper_unit,
+                                                      const int32_t* __restrict__ skip) {
   if (skip && *skip) return;
   __shared__ double T[CB][CB + 1];   // strict triangle of the part, zero elsewhere
-  __shared__ double Z[CB][CB + 1];   // the inverse, built row by row (zero = not yet)
   __shared__ double rd[CB];          // 1 / diagonal (1 for a unit diagonal)
   const int kb = blockIdx.x, part = blockIdx.y;
   const int b0 = kb * CB, nb = min(CB, s - b0);
-  const int c = threadIdx.x;
+  const int t = threadIdx.x;
   const bool unit = part == 0 ? lower_unit != 0 : upper_unit != 0;
   {
-    // lane c loads column c of the block (all loads first, clamped)
-    double v[CB];
+    // all loads first (clamped into the block), then the stores
+    double v[CB * CB / 256];
 #pragma unroll
-    for (int r = 0; r < CB; ++r) v[r] = M[(size_t)(b0 + min(r, nb - 1)) * s + b0 + min(c, nb - 1)];
+    for (int m = 0; m < CB * CB / 256; ++m) {
+      const int e = t + 256 * m, r = e >> 6, cc = e & 63;
+      v[m] = M[(size_t)(b0 + min(r, nb - 1)) * s + b0 + min(cc, nb - 1)];
+    }
 #pragma unroll
-    for (int r = 0; r < CB; ++r) {
-      const bool in = r < nb && c < nb && (part == 0 ? c < r : c > r);
-      T[r][c] = in ? v[r] : 0.0;
-      Z[r][c] = 0.0;
+    for (int m = 0; m < CB * CB / 256; ++m) {
+      const int e = t + 256 * m, r = e >> 6, cc = e & 63;
+      const bool in = r < nb && cc < nb && (part == 0 ? cc < r : cc > r);
+      T[r][cc] = in ? v[m] : 0.0;
     }
   }
-  rd[c] = (unit || c >= nb) ? 1.0 : 1.0 / M[(size_t)(b0 + c) * s + b0 + c];
+  if (t < CB) rd[t] = (unit || t >= nb) ? 1.0 : 1.0 / M[(size_t)(b0 + t) * s + b0 + t];
   __syncthreads();
-  // lane c: column c of the inverse; row i needs rows solved before it
-  for (int k = 0; k < CB; ++k) {
-    const int i = part == 0 ? k : CB - 1 - k;
-    double a0 = (i == c) ? 1.0 : 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  const int c = t >> 2, seg = t & 3;
+  double zr[CB / 4];
 #pragma unroll
-    for (int j = 0; j < CB; j += 4) {
-      a0 -= T[i][j] * Z[j][c];
-      a1 -= T[i][j + 1] * Z[j + 1][c];
-      a2 -= T[i][j + 2] * Z[j + 2][c];
-      a3 -= T[i][j + 3] * Z[j + 3][c];
-    }
-    const double v = ((a0 + a1) + (a2 + a3)) * rd[i];
-    Z[i][c] = (i < nb && c < nb) ? v : 0.0;
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-  }
+  for (int m = 0; m < CB / 4; ++m) zr[m] = 0.0;
+  if (part == 0) tri_inv_rows<true>(T, rd, c, seg, nb, zr);
+  else tri_inv_rows<false>(T, rd, c, seg, nb, zr);
   double* out = dinv + (size_t)(kb * 2 + part) * CB * CB;
-  for (int e = c; e < CB * CB; e += 64) out[e] = Z[e >> 6][e & 63];
+#pragma unroll
+  for (int m = 0; m < CB / 4; ++m) out[(4 * m + seg) * CB + c] = zr[m];
 }
 
 // xs[b0 + r][c] <- sum_j D[r][j] xs[b0 + j][c] for the nb rows of one block

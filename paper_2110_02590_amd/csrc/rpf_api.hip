@@ -571,9 +571,9 @@ void refactor(rpf_grid* h, hipStream_t s, const int32_t* skip = nullptr) {
     LAUNCHCHK();
     // inverse diagonal blocks: J_x uses L (unit) and U; J_x^T uses U^T and L^T (unit)
     const dim3 gi(cdiv(P.ntop, CB), 2);
-    k_top_diag_inv<<<gi, 64, 0, s>>>(P.ntop, h->dense_top, h->top_dinv, 1, 0, skip);
+    k_top_diag_inv<<<gi, 256, 0, s>>>(P.ntop, h->dense_top, h->top_dinv, 1, 0, skip);
     LAUNCHCHK();
-    k_top_diag_inv<<<gi, 64, 0, s>>>(P.ntop, h->dense_topT, h->top_dinvT, 0, 1, skip);
+    k_top_diag_inv<<<gi, 256, 0, s>>>(P.ntop, h->dense_topT, h->top_dinvT, 0, 1, skip);
     LAUNCHCHK();
   }
   if (h->prof_on) h->prof_end(2, pi, s);
@@ -733,7 +733,7 @@ void chol_solve(rpf_grid* h, int n, const double* L, const double* rhs, double* 
   k_fill_int<<<cdiv(2 * nblk, 256), 256, 0, s>>>(2 * nblk, h->chol_flags, 0);
   LAUNCHCHK();
   // inverses of the diagonal blocks (skipped when the factorization failed)
-  k_top_diag_inv<<<dim3(nblk, 1), 64, 0, s>>>(n, L, h->chol_dinv, 0, 0, info);
+  k_top_diag_inv<<<dim3(nblk, 1), 256, 0, s>>>(n, L, h->chol_dinv, 0, 0, info);
   LAUNCHCHK();
   k_chol_fwd<<<nblk, 256, 0, s>>>(n, L, h->chol_dinv, rhs, h->chol_work, h->chol_flags, info);
   LAUNCHCHK();
