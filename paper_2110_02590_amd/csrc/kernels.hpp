@@ -231,14 +231,29 @@ __global__ void k_reduce_final(int n, const double* __restrict__ in, double* __r
   }
 }
 
+// lane s's 64-bit value (s uniform)
+__device__ __forceinline__ int64_t readlane64(int64_t v, int s) {
+  const int lo = __builtin_amdgcn_readlane((int)(uint32_t)(v & 0xffffffff), s);
+  const int hi = __builtin_amdgcn_readlane((int)(v >> 32), s);
+  return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+
+// lane s's double (s uniform)
+__device__ __forceinline__ double readlane_f64(double v, int s) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), s);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), s);
+  return __hiloint2double(hi, lo);
+}
+
 // ----------------------------------------------------- LU refactorization
 // Row-by-row (up-looking) elimination on the static pattern, one wavefront
 // per row with the row staged in LDS: for each L entry (i, k), k ascending,
 // l_ik = a_ik / u_kk and a_ij -= l_ik u_kj for the U entries of row k
 // (target positions precomputed).  Only L entries in [ptr[i], pend) are
 // eliminated.  Rows k are final when row i starts, so their data (pivot
-// reciprocal rdg[k] = 1 / u_kk, U values, targets) are loaded one step
-// ahead; only the row's own entries in LDS form the dependency chain.  The
+// reciprocal rdg[k] = 1 / u_kk, U values, targets) are loaded ahead: the
+// metadata of 64 steps at once, the values and targets two steps ahead;
+// only the row's own entries in LDS form the dependency chain.  The
 // finished row stores 1 / u_ii in rdg[i].  With check, a pivot
 // |u_ii| <= pivtol max_j |a_ij| records row + 1 in status[0].
 __device__ __forceinline__ void rf_row(int i, int pend, bool check, const int32_t* __restrict__ ptr,
@@ -256,33 +271,51 @@ __device__ __forceinline__ void rf_row(int i, int pend, bool check, const int32_
   }
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   __builtin_amdgcn_wave_barrier();
-  // step data of entry p: U row of k = col[p] starts at diag[k] + 1
-  int n_dk = 0, n_nu = 0, n_tg = 0;
-  int64_t n_u0 = 0;
-  double n_rk = 0.0, n_av = 0.0;
-  auto fetch = [&](int pp) {
-    const int k = col[pp];
-    n_dk = diag[k];
-    n_rk = rdg[k];
-    n_u0 = upd_ptr[pp];
-    n_nu = (int)(upd_ptr[pp + 1] - n_u0);
-    if (lane < n_nu) {
-      n_tg = upd_tgt[n_u0 + lane];
-      n_av = a[n_dk + 1 + lane];
+  // Steps in windows of 64: lane j loads step w0 + j's metadata (column k,
+  // U row start diag[k] + 1, 1 / u_kk, update range) in one batch; a step
+  // reads it by readlane.  Its U values and update targets are loaded two
+  // steps ahead, unconditionally from clamped addresses (upd_tgt is padded
+  // past its end), since they do not depend on the row being eliminated.
+  for (int w0 = p0; w0 < pend; w0 += 64) {
+    const int nw = min(64, pend - w0);
+    const int pm = w0 + min(lane, nw - 1);
+    const int km = col[pm];
+    const int m_dk = diag[km];
+    const double m_rk = rdg[km];
+    const int64_t m_u0 = upd_ptr[pm];
+    const int m_nu = (int)(upd_ptr[pm + 1] - m_u0);
+    auto fetch = [&](int st, int& tg, double& av) {
+      const int64_t u0 = readlane64(m_u0, st);
+      const int nu = __builtin_amdgcn_readlane(m_nu, st);
+      const int dk = __builtin_amdgcn_readlane(m_dk, st);
+      const int q = min(lane, max(nu - 1, 0));
+      tg = upd_tgt[u0 + q];
+      av = a[dk + (nu > 0 ? 1 + q : 0)];
+    };
+    auto step = [&](int st, int tg, double av) {
+      const int p = w0 + st;
+      const int nu = __builtin_amdgcn_readlane(m_nu, st);
+      const double l = w[p - p0] * readlane_f64(m_rk, st);
+      if (lane < nu) w[tg - p0] -= l * av;
+      if (nu > 64) {
+        const int64_t u0 = readlane64(m_u0, st);
+        const int dk = __builtin_amdgcn_readlane(m_dk, st);
+        for (int t = lane + 64; t < nu; t += 64) w[upd_tgt[u0 + t] - p0] -= l * a[dk + 1 + t];
+      }
+      if (lane == 0) w[p - p0] = l;
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+    };
+    int tgA, tgB;
+    double avA, avB;
+    fetch(0, tgA, avA);
+    fetch(min(1, nw - 1), tgB, avB);
+    for (int st = 0; st < nw; st += 2) {
+      step(st, tgA, avA);
+      fetch(min(st + 2, nw - 1), tgA, avA);
+      if (st + 1 < nw) step(st + 1, tgB, avB);
+      fetch(min(st + 3, nw - 1), tgB, avB);
     }
-  };
-  if (p0 < pend) fetch(p0);
-  for (int p = p0; p < pend; ++p) {
-    const int dk = n_dk, nu = n_nu, tg = n_tg;
-    const int64_t u0 = n_u0;
-    const double rk = n_rk, av = n_av;
-    if (p + 1 < pend) fetch(p + 1);
-    const double l = w[p - p0] * rk;
-    if (lane < nu) w[tg - p0] -= l * av;
-    for (int t = lane + 64; t < nu; t += 64) w[upd_tgt[u0 + t] - p0] -= l * a[dk + 1 + t];
-    if (lane == 0) w[p - p0] = l;
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    __builtin_amdgcn_wave_barrier();
   }
   for (int off = 32; off > 0; off >>= 1) amax = fmax(amax, __shfl_xor(amax, off, 64));
   for (int q = lane; q < p1 - p0; q += 64) a[p0 + q] = w[q];
@@ -317,27 +350,6 @@ __global__ void k_rf_pack(const int32_t* __restrict__ flev, const int32_t* __res
   }
 }
 
-// Packs with their LU values resident in LDS: one workgroup (16
-// wavefronts) per pack, forward levels separated by barriers, one
-// wavefront per row, eliminating in place in LDS.  The metadata of up to
-// 64 elimination steps of a row (pivot column, U-row start, update range)
-// is loaded at once, lane s holding step s, and broadcast by readlane; the
-// update targets of step s + 2 are loaded during step s.  Reciprocal
-// pivots of finished rows go to LDS and to rdg.  upd_tgt must hold 64
-// readable entries past its end.  LDS: values of the pack's CSR rows [seg]
-// | 1 / u_ii [nr].
-__device__ __forceinline__ int64_t readlane64(int64_t v, int s) {
-  const int lo = __builtin_amdgcn_readlane((int)(uint32_t)(v & 0xffffffff), s);
-  const int hi = __builtin_amdgcn_readlane((int)(v >> 32), s);
-  return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
-}
-
-// lane s's double (s uniform)
-__device__ __forceinline__ double readlane_f64(double v, int s) {
-  const int lo = __builtin_amdgcn_readlane(__double2loint(v), s);
-  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), s);
-  return __hiloint2double(hi, lo);
-}
 
 // v of the lane that the DPP control CTRL selects (every lane active)
 template <int CTRL>
@@ -377,6 +389,15 @@ __device__ __forceinline__ double group_sum(double v, int G) {
   return v;
 }
 
+// Packs with their LU values resident in LDS: one workgroup (16
+// wavefronts) per pack, forward levels separated by barriers, one
+// wavefront per row, eliminating in place in LDS.  The metadata of up to
+// 64 elimination steps of a row (pivot column, U-row start, update range)
+// is loaded at once, lane s holding step s, and broadcast by readlane; the
+// update targets of step s + 2 are loaded during step s.  Reciprocal
+// pivots of finished rows go to LDS and to rdg.  upd_tgt must hold 64
+// readable entries past its end.  LDS: values of the pack's CSR rows [seg]
+// | 1 / u_ii [nr].
 __global__ void __launch_bounds__(1024) k_rf_pack_lds(const int32_t* __restrict__ pack_ptr,
                                                       const int32_t* __restrict__ flev,
                                                       const int32_t* __restrict__ flev_off,
