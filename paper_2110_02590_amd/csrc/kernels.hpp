@@ -18,6 +18,7 @@ namespace dev {
 using rpf::RECW;
 using rpf::WREC;
 constexpr int CB = 64;  // dense block width
+typedef double dbl4 __attribute__((ext_vector_type(4)));
 
 // Staging through LDS issues all of a thread's loads before its first
 // store: a loop that stores each loaded value would wait for memory once
@@ -694,10 +695,12 @@ __device__ __forceinline__ void tri_inv_rows(const double (*T)[CB + 1], const do
 // row-major, lower part L, upper part U): blockIdx.y = 0 inverts the lower
 // triangle of block blockIdx.x (unit diagonal if lower_unit), 1 the upper
 // triangle (unit if upper_unit).  Output dinv[(kb * 2 + part) * CB * CB],
-// row-major CB x CB, zero outside the block's nb x nb corner.  256 threads:
-// four lanes per column of the inverse (tri_inv_rows).
+// row-major CB x CB, zero outside the block's nb x nb corner.  With dinvT,
+// also the inverse blocks of M^T (lower part U^T, upper part L^T), as the
+// transposes.  256 threads: four lanes per column of the inverse
+// (tri_inv_rows).
 __global__ void __launch_bounds__(256) k_top_diag_inv(int s, const double* __restrict__ M, double* __restrict__ dinv,
-                                                      int lower_unit, int upper_unit,
+                                                      int lower_unit, int upper_unit, double* __restrict__ dinvT,
                                                       const int32_t* __restrict__ skip) {
   if (skip && *skip) return;
   __shared__ double T[CB][CB + 1];   // strict triangle of the part, zero elsewhere
@@ -732,6 +735,13 @@ __global__ void __launch_bounds__(256) k_top_diag_inv(int s, const double* __res
   double* out = dinv + (size_t)(kb * 2 + part) * CB * CB;
 #pragma unroll
   for (int m = 0; m < CB / 4; ++m) out[(4 * m + seg) * CB + c] = zr[m];
+  if (dinvT) {
+    // the transposed factor's inverse blocks: its lower triangle is this
+    // upper one transposed and vice versa, and (T^-1)^T = (T^T)^-1
+    double* ot = dinvT + (size_t)(kb * 2 + 1 - part) * CB * CB;
+#pragma unroll
+    for (int m = 0; m < CB / 4; ++m) ot[c * CB + 4 * m + seg] = zr[m];
+  }
 }
 
 // xs[b0 + r][c] <- sum_j D[r][j] xs[b0 + j][c] for the nb rows of one block
@@ -1203,22 +1213,34 @@ __global__ void __launch_bounds__(1024) k_pack_solve_t(const int32_t* __restrict
 // ------------------------------------------------------------------ SpMM
 // Y[i, c] = (Yadd ? Yadd[i, c] : 0) + alpha * sum_p v(p) * s(col) * X[col, c]
 // with v(p) = val[valpos ? valpos[p] : p], s = xscale ? xscale[col] : 1.
-__global__ void k_spmm(int nrows, const int32_t* __restrict__ ptr, const int32_t* __restrict__ colidx,
-                       const double* __restrict__ val, const int32_t* __restrict__ valpos,
-                       const double* __restrict__ xscale, const double* __restrict__ X, int ldx,
-                       int ncols, double alpha, const double* __restrict__ Yadd, int ldya,
-                       double* __restrict__ Y, int ldy) {
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  const int i = blockIdx.y * blockDim.y + threadIdx.y;
-  if (i >= nrows || c >= ncols) return;
-  // four entries per step, loads unconditional (clamped), four partial sums
+// One wavefront per row: the row's entries are the same in every lane, so
+// they are read once as scalars; lane l takes columns c0 + l + 64 m,
+// m < CPT.  Eight entries per pass with all their X loads in flight
+// (addresses clamped, padding entries weighted 0); entry p adds into
+// partial sum (p - p0) mod 4, the four combined as (s0 + s1) + (s2 + s3).
+// 256 threads: four rows per workgroup.
+template <int CPT>
+__global__ void __launch_bounds__(256) k_spmm(int nrows, const int32_t* __restrict__ ptr,
+                                              const int32_t* __restrict__ colidx, const double* __restrict__ val,
+                                              const int32_t* __restrict__ valpos, const double* __restrict__ xscale,
+                                              const double* __restrict__ X, int ldx, int ncols, double alpha,
+                                              const double* __restrict__ Yadd, int ldya, double* __restrict__ Y,
+                                              int ldy) {
+  const int i = __builtin_amdgcn_readfirstlane(blockIdx.y * 4 + (int)(threadIdx.x >> 6));
+  if (i >= nrows) return;
+  const int lane = threadIdx.x & 63;
+  const int c0 = blockIdx.x * 64 * CPT + lane;
   const int p0 = ptr[i], p1 = ptr[i + 1];
-  double a[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int pb = p0; pb < p1; pb += 4) {
-    int jj[4];
-    double vv[4];
+  double a[CPT][4];
 #pragma unroll
-    for (int m = 0; m < 4; ++m) {
+  for (int k = 0; k < CPT; ++k)
+#pragma unroll
+    for (int m = 0; m < 4; ++m) a[k][m] = 0.0;
+  for (int pb = p0; pb < p1; pb += 8) {
+    int jj[8];
+    double vv[8];
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
       const int pc = min(pb + m, p1 - 1);
       jj[m] = colidx[pc];
       const double raw = val[valpos ? valpos[pc] : pc];
@@ -1226,17 +1248,29 @@ __global__ void k_spmm(int nrows, const int32_t* __restrict__ ptr, const int32_t
     }
     if (xscale) {
 #pragma unroll
-      for (int m = 0; m < 4; ++m) vv[m] *= xscale[jj[m]];
+      for (int m = 0; m < 8; ++m) vv[m] *= xscale[jj[m]];
     }
+    double xv[8][CPT];
 #pragma unroll
-    for (int m = 0; m < 4; ++m) a[m] += vv[m] * X[(size_t)jj[m] * ldx + c];
+    for (int m = 0; m < 8; ++m)
+#pragma unroll
+      for (int k = 0; k < CPT; ++k) xv[m][k] = X[(size_t)jj[m] * ldx + min(c0 + 64 * k, ncols - 1)];
+#pragma unroll
+    for (int m = 0; m < 8; ++m)
+#pragma unroll
+      for (int k = 0; k < CPT; ++k) a[k][m & 3] += vv[m] * xv[m][k];
   }
-  double acc = ((a[0] + a[1]) + (a[2] + a[3])) * alpha;
-  if (Yadd) acc += Yadd[(size_t)i * ldya + c];
-  Y[(size_t)i * ldy + c] = acc;
+#pragma unroll
+  for (int k = 0; k < CPT; ++k) {
+    const int c = c0 + 64 * k;
+    if (c < ncols) {
+      double acc = ((a[k][0] + a[k][1]) + (a[k][2] + a[k][3])) * alpha;
+      if (Yadd) acc += Yadd[(size_t)i * ldya + c];
+      Y[(size_t)i * ldy + c] = acc;
+    }
+  }
 }
 
-// copy an [n x ncols] block between leading dimensions
 __global__ void k_copy_block(int n, int ncols, const double* __restrict__ src, int lds_,
                              double* __restrict__ dst, int ldd) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1618,7 +1652,8 @@ __global__ void k_symmetrize(int n, double* __restrict__ K, const double* __rest
 // Right-looking blocked LU without pivoting (CHOL = false) or Cholesky
 // (CHOL = true, lower triangle) of a row-major n x n matrix, per block of
 // CB columns: diagonal block by one wavefront, panels one wavefront per row
-// (and per column for LU), trailing update in 64 x 64 tiles.  A failing
+// (and per column for LU), trailing update in 64 x 64 tiles on the FP64
+// matrix cores.  A failing
 // pivot records base + (column + 1) in info[0]; later kernels return early.
 
 // Diagonal block factorization with the 256 threads of the calling
@@ -1860,30 +1895,41 @@ __global__ void __launch_bounds__(256) k_blk_update(int n, int b0, double* __res
   else
     stage_tile<256>(Us, A + (size_t)b0 * n + j0, n, nb, n - j0, 0.0);
   __syncthreads();
-  // thread: rows tr .. tr + 3, columns tc + 16 q (consecutive lanes read
-  // consecutive Us entries: no bank conflicts); the staged tiles are zero
-  // past nb, so the k loop has a fixed trip count
-  const int tr = (threadIdx.x >> 4) * 4, tc = threadIdx.x & 15;
-  double acc[4][4] = {};
-#pragma unroll 8
-  for (int k = 0; k < CB; ++k) {
-    double l[4], u[4];
+  // FP64 matrix cores (v_mfma_f64_16x16x4f64): wave w takes the 32 x 32
+  // quadrant (w >> 1, w & 1) of the tile as 2 x 2 blocks of 16 x 16, over
+  // 16 steps of 4 in k.  Operand lanes: A(i, k) from lane i + 16 k, B(k, j)
+  // from lane j + 16 k; result register r of lane j + 16 q holds row
+  // q + 4 r of column j.  The staged tiles are zero past nb, so k runs to
+  // CB.
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int qr = (w >> 1) * 32, qc = (w & 1) * 32;
+  const int li = lane & 15, lk = lane >> 4;
+  // a Cholesky diagonal tile has nothing to update above its diagonal
+  if (!(CHOL && ti == tj && qc > qr)) {
+    dbl4 acc[2][2];
 #pragma unroll
-    for (int p = 0; p < 4; ++p) l[p] = Ls[tr + p][k];
+    for (int p = 0; p < 2; ++p)
 #pragma unroll
-    for (int q = 0; q < 4; ++q) u[q] = Us[k][tc + 16 * q];
+      for (int q = 0; q < 2; ++q) acc[p][q] = dbl4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int p = 0; p < 4; ++p)
-#pragma unroll
-      for (int q = 0; q < 4; ++q) acc[p][q] += l[p] * u[q];
-  }
-#pragma unroll
-  for (int p = 0; p < 4; ++p)
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int i = i0 + tr + p, j = j0 + tc + 16 * q;
-      if (i < n && j < n && (!CHOL || j <= i)) A[(size_t)i * n + j] -= acc[p][q];
+    for (int k0 = 0; k0 < CB; k0 += 4) {
+      const double a0 = Ls[qr + li][k0 + lk], a1 = Ls[qr + 16 + li][k0 + lk];
+      const double b0v = Us[k0 + lk][qc + li], b1v = Us[k0 + lk][qc + 16 + li];
+      acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0v, acc[0][0], 0, 0, 0);
+      acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1v, acc[0][1], 0, 0, 0);
+      acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0v, acc[1][0], 0, 0, 0);
+      acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1v, acc[1][1], 0, 0, 0);
     }
+#pragma unroll
+    for (int p = 0; p < 2; ++p)
+#pragma unroll
+      for (int q = 0; q < 2; ++q)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = i0 + qr + 16 * p + lk + 4 * r, j = j0 + qc + 16 * q + li;
+          if (i < n && j < n && (!CHOL || j <= i)) A[(size_t)i * n + j] -= acc[p][q][r];
+        }
+  }
   if (fuse && ti == 0 && tj == 0) {
     __syncthreads();   // the updated block is in A; the LDS tiles are free
     static_assert(DIAG_WORK <= CB * (CB + 1), "diagonal work area must fit one tile");

@@ -571,9 +571,7 @@ void refactor(rpf_grid* h, hipStream_t s, const int32_t* skip = nullptr) {
     LAUNCHCHK();
     // inverse diagonal blocks: J_x uses L (unit) and U; J_x^T uses U^T and L^T (unit)
     const dim3 gi(cdiv(P.ntop, CB), 2);
-    k_top_diag_inv<<<gi, 256, 0, s>>>(P.ntop, h->dense_top, h->top_dinv, 1, 0, skip);
-    LAUNCHCHK();
-    k_top_diag_inv<<<gi, 256, 0, s>>>(P.ntop, h->dense_topT, h->top_dinvT, 0, 1, skip);
+    k_top_diag_inv<<<gi, 256, 0, s>>>(P.ntop, h->dense_top, h->top_dinv, 1, 0, h->top_dinvT, skip);
     LAUNCHCHK();
   }
   if (h->prof_on) h->prof_end(2, pi, s);
@@ -717,10 +715,14 @@ void solve_pair(rpf_grid* h, bool transposed, double* X, int ld, int ncols, doub
 void spmm(rpf_grid* h, int nrows, const int32_t* ptr, const int32_t* col, const double* val,
           const int32_t* valpos, const double* xscale, const double* X, int ldx, int ncols, double alpha,
           const double* Yadd, int ldya, double* Y, int ldy, hipStream_t s) {
-  dim3 blk(64, 4);
-  dim3 grd(cdiv(ncols, 64), cdiv(nrows, 4));
   size_t pi = h->prof_on ? h->prof_begin(s) : 0;
-  k_spmm<<<grd, blk, 0, s>>>(nrows, ptr, col, val, valpos, xscale, X, ldx, ncols, alpha, Yadd, ldya, Y, ldy);
+  // two columns per lane once a row has more than one wavefront's worth
+  if (ncols > 64)
+    k_spmm<2><<<dim3(cdiv(ncols, 128), cdiv(nrows, 4)), 256, 0, s>>>(nrows, ptr, col, val, valpos, xscale, X, ldx,
+                                                                     ncols, alpha, Yadd, ldya, Y, ldy);
+  else
+    k_spmm<1><<<dim3(cdiv(ncols, 64), cdiv(nrows, 4)), 256, 0, s>>>(nrows, ptr, col, val, valpos, xscale, X, ldx,
+                                                                    ncols, alpha, Yadd, ldya, Y, ldy);
   LAUNCHCHK();
   if (h->prof_on) h->prof_end(3, pi, s);
 }
@@ -733,7 +735,7 @@ void chol_solve(rpf_grid* h, int n, const double* L, const double* rhs, double* 
   k_fill_int<<<cdiv(2 * nblk, 256), 256, 0, s>>>(2 * nblk, h->chol_flags, 0);
   LAUNCHCHK();
   // inverses of the diagonal blocks (skipped when the factorization failed)
-  k_top_diag_inv<<<dim3(nblk, 1), 256, 0, s>>>(n, L, h->chol_dinv, 0, 0, info);
+  k_top_diag_inv<<<dim3(nblk, 1), 256, 0, s>>>(n, L, h->chol_dinv, 0, 0, nullptr, info);
   LAUNCHCHK();
   k_chol_fwd<<<nblk, 256, 0, s>>>(n, L, h->chol_dinv, rhs, h->chol_work, h->chol_flags, info);
   LAUNCHCHK();
