@@ -229,7 +229,8 @@ def roofline(g, pr, prof, B, steps):
         backward 12 nnz(U_pack, pack columns) + 4 (t0 + 1) + 8 t0 + 16 t0 ncols
         (nnz(U_pack, pack columns) = nnz(L_pack) by symmetry of the pattern;
         with J_x^T the unit and non-unit factors swap);
-      top solve (k_top_rhs + k_top_dense + k_pack_topmul), one per solve pair:
+      top solve (k_top_rhs_w + k_top_inv_apply + k_pack_topmul_w), one per solve
+      pair (the dense top inverse read once):
         12 nnz(L, top rows, pack columns) + 8 ncols #(pack columns read)
         + 8 n_top^2 + 16 n_top ncols
         + 12 nnz(U, pack rows, top columns) + 16 ncols #(pack rows with top entries);
@@ -284,7 +285,8 @@ def roofline(g, pr, prof, B, steps):
     add("pack_solve", "k_pack_solve_t (batched triangular solves in the subtree packs)", "pack_batch",
         pack_bytes / pack_launches, "hbm", HBM_PEAK_GBS, "GB/s",
         f"bytes; nnz(L_pack)={nnz_lp}, t0={t0}, B={B}")
-    add("top_solve", "k_top_rhs + k_top_dense + k_pack_topmul (top rows of the batched solves)", "top_batch",
+    add("top_solve", "k_top_rhs_w + k_top_inv_apply + k_pack_topmul_w (top rows of the batched solves)",
+        "top_batch",
         top_bytes / top_launches, "hbm", HBM_PEAK_GBS, "GB/s",
         f"bytes; nnz(L_top,pack cols)={nnz_tl}, n_top={ntop}, nnz(U_pack,top cols)={nnz_pt}, B={B}")
     add("refactor", "LU refactorization (k_rf_pack_lds, k_rf_top_ext, dense top LU)", "refactor",

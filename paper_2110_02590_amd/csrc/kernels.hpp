@@ -639,30 +639,89 @@ __global__ void k_top_rhs(int t0, int n, const int32_t* __restrict__ lo_split, c
 // pack solves: X[i, c] -= sum_p f(p) X[col(p), c] over the upper entries
 // of pack row i in top columns ([up_split[i], ptr[i+1])).  Reads only top
 // rows, so in place.  One thread per (row, column), four partial sums.
-__global__ void k_pack_topmul(int t0, const int32_t* __restrict__ up_split, const int32_t* __restrict__ ptr,
-                              const int32_t* __restrict__ col, const double* __restrict__ fval,
-                              double* __restrict__ X, int ld, int ncols, const int32_t* __restrict__ skip) {
-  if (skip && *skip) return;
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  const int i = blockIdx.y * blockDim.y + threadIdx.y;
-  if (i >= t0 || c >= ncols) return;
-  const int p0 = up_split[i], p1 = ptr[i + 1];
-  if (p0 == p1) return;
-  double a[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int pb = p0; pb < p1; pb += 4) {
-    int jj[4];
-    double vv[4];
+
+// sum_p fval[p] X[col[p]][c] over p in [p0, p1) for columns c0 + 64 m
+// (m < CPT) of one lane, the row's entries read as scalars (p0, p1
+// wave-uniform), eight per pass with their X loads in flight.  Partial sums
+// by (p - p0) mod 4; with TAIL0 the entries past the last full group of
+// four go to the first sum instead.  Combined as (s0 + s1) + (s2 + s3).
+template <int CPT, bool TAIL0>
+__device__ __forceinline__ void row_gather(int p0, int p1, const int32_t* __restrict__ col,
+                                           const double* __restrict__ fval, const double* __restrict__ X, int ld,
+                                           int c0, int ncols, double (&r)[CPT]) {
+  double a[CPT][4];
 #pragma unroll
-    for (int m = 0; m < 4; ++m) {
+  for (int k = 0; k < CPT; ++k)
+#pragma unroll
+    for (int m = 0; m < 4; ++m) a[k][m] = 0.0;
+  const int pfull = p0 + ((p1 - p0) & ~3);
+  for (int pb = p0; pb < p1; pb += 8) {
+    int jj[8];
+    double vv[8];
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
       const int pc = min(pb + m, p1 - 1);
       jj[m] = col[pc];
       const double raw = fval[pc];
       vv[m] = pb + m < p1 ? raw : 0.0;
     }
+    double xv[8][CPT];
 #pragma unroll
-    for (int m = 0; m < 4; ++m) a[m] += vv[m] * X[(size_t)jj[m] * ld + c];
+    for (int m = 0; m < 8; ++m)
+#pragma unroll
+      for (int k = 0; k < CPT; ++k) xv[m][k] = X[(size_t)jj[m] * ld + min(c0 + 64 * k, ncols - 1)];
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+      const int q = (TAIL0 && pb + m >= pfull) ? 0 : (m & 3);
+#pragma unroll
+      for (int k = 0; k < CPT; ++k) a[k][q] += vv[m] * xv[m][k];
+    }
   }
-  X[(size_t)i * ld + c] -= (a[0] + a[1]) + (a[2] + a[3]);
+#pragma unroll
+  for (int k = 0; k < CPT; ++k) r[k] = (a[k][0] + a[k][1]) + (a[k][2] + a[k][3]);
+}
+
+// Batched forms (a wavefront per row, lane l taking columns c0 + l + 64 m):
+// top rows X[i] = scale X[i] - (pack part of row i) X, and pack rows (only
+// those with entries in top columns, listed in rows) X[i] -= (top part of
+// row i) X.  The top rows sum in the same order as k_top_rhs, which
+// serves single columns.
+template <int CPT>
+__global__ void __launch_bounds__(256) k_top_rhs_w(int t0, int n, const int32_t* __restrict__ lo_split,
+                                                   const int32_t* __restrict__ ptr, const int32_t* __restrict__ col,
+                                                   const double* __restrict__ fval, double* __restrict__ X, int ld,
+                                                   int ncols, double scale, const int32_t* __restrict__ skip) {
+  if (skip && *skip) return;
+  const int i = t0 + __builtin_amdgcn_readfirstlane(blockIdx.y * 4 + (int)(threadIdx.x >> 6));
+  if (i >= n) return;
+  const int c0 = blockIdx.x * 64 * CPT + (threadIdx.x & 63);
+  double r[CPT];
+  row_gather<CPT, true>(ptr[i], lo_split[i], col, fval, X, ld, c0, ncols, r);
+#pragma unroll
+  for (int k = 0; k < CPT; ++k) {
+    const int c = c0 + 64 * k;
+    if (c < ncols) X[(size_t)i * ld + c] = scale * X[(size_t)i * ld + c] - r[k];
+  }
+}
+
+template <int CPT>
+__global__ void __launch_bounds__(256) k_pack_topmul_w(int nrows, const int32_t* __restrict__ rows,
+                                                       const int32_t* __restrict__ up_split,
+                                                       const int32_t* __restrict__ ptr, const int32_t* __restrict__ col,
+                                                       const double* __restrict__ fval, double* __restrict__ X,
+                                                       int ld, int ncols, const int32_t* __restrict__ skip) {
+  if (skip && *skip) return;
+  const int idx = __builtin_amdgcn_readfirstlane(blockIdx.y * 4 + (int)(threadIdx.x >> 6));
+  if (idx >= nrows) return;
+  const int i = rows[idx];
+  const int c0 = blockIdx.x * 64 * CPT + (threadIdx.x & 63);
+  double r[CPT];
+  row_gather<CPT, false>(up_split[i], ptr[i + 1], col, fval, X, ld, c0, ncols, r);
+#pragma unroll
+  for (int k = 0; k < CPT; ++k) {
+    const int c = c0 + 64 * k;
+    if (c < ncols) X[(size_t)i * ld + c] -= r[k];
+  }
 }
 
 // Rows of the inverse of one triangular CB x CB block, in solve order
@@ -828,6 +887,60 @@ __host__ __device__ __forceinline__ size_t pack_lds_bytes(int nr, int ne, int nl
   size_t b = (size_t)nr * tw * 8 + (size_t)ne * 8 + (size_t)nr * 8 + (size_t)(nr + 1) * 4 +
              (size_t)(nlev + 1) * 4 + (size_t)nr * 2 + (size_t)ne * 2;
   return (b + 15) & ~(size_t)15;
+}
+
+// X_top <- S^-1 X_top (or S^-T X_top) with the dense inverse of the top
+// block S computed once per point: out[r][c] = sum_k A[k * s + r]
+// X[t0 + k][c], A k-major (S^-T for the J_x solves, S^-1 for J_x^T).  One
+// workgroup per TW columns, staged in LDS; a thread per row, summing over
+// k in order into two partial sums (even and odd k), so every element is
+// the same whatever the batch width or split.  Sixteen rows of A in flight
+// per pass.  blockDim a multiple of 64; rows past it loop.
+template <int TW>
+__global__ void __launch_bounds__(1024) k_top_inv_apply(int t0, int s, const double* __restrict__ A,
+                                                         double* __restrict__ X, int ld, int ncols,
+                                                         const int32_t* __restrict__ skip) {
+  if (skip && *skip) return;
+  extern __shared__ double xs[];  // [s][TW]
+  const int c0 = blockIdx.x * TW;
+  for (int e = threadIdx.x; e < s * TW; e += blockDim.x) {
+    const int k = e / TW, c = e - k * TW;
+    xs[e] = c0 + c < ncols ? X[(size_t)(t0 + k) * ld + c0 + c] : 0.0;
+  }
+  __syncthreads();
+  for (int rb = 0; rb < s; rb += blockDim.x) {
+    const int r = rb + threadIdx.x;
+    const int rr = min(r, s - 1);
+    double a0[TW], a1[TW];
+#pragma unroll
+    for (int c = 0; c < TW; ++c) a0[c] = a1[c] = 0.0;
+    int k = 0;
+    for (; k + 16 <= s; k += 16) {
+      double av[16];
+#pragma unroll
+      for (int m = 0; m < 16; ++m) av[m] = A[(size_t)(k + m) * s + rr];
+#pragma unroll
+      for (int m = 0; m < 16; m += 2)
+#pragma unroll
+        for (int c = 0; c < TW; ++c) {
+          a0[c] += av[m] * xs[(k + m) * TW + c];
+          a1[c] += av[m + 1] * xs[(k + m + 1) * TW + c];
+        }
+    }
+    for (; k < s; ++k) {
+      const double av = A[(size_t)k * s + rr];
+#pragma unroll
+      for (int c = 0; c < TW; ++c) {
+        if (k & 1) a1[c] += av * xs[k * TW + c];
+        else a0[c] += av * xs[k * TW + c];
+      }
+    }
+    if (r < s) {
+#pragma unroll
+      for (int c = 0; c < TW; ++c)
+        if (c0 + c < ncols) X[(size_t)(t0 + r) * ld + c0 + c] = a0[c] + a1[c];
+    }
+  }
 }
 
 template <int TW, bool FWD, bool UNIT>
@@ -1065,7 +1178,7 @@ __global__ void __launch_bounds__(1024) k_pack_solve_g(const int32_t* __restrict
 // Batched pack solves with the pack's right-hand-side tile in LDS: one
 // workgroup of 1024 threads per (pack, TW-column tile).  Staged in LDS: the
 // tile X[r0 .. r1) x [c0, c0 + TW) (forward: times scale; backward: the
-// products with the top rows are already subtracted by k_pack_topmul), and
+// products with the top rows are already subtracted by k_pack_topmul_w), and
 // the pack program of the
 // direction: local columns (int16), rows in level order with each row's
 // first entry and length in one word, level offsets.  Factor values come from pval, a copy in program order
@@ -1211,26 +1324,26 @@ __global__ void __launch_bounds__(1024) k_pack_solve_t(const int32_t* __restrict
 }
 
 // ------------------------------------------------------------------ SpMM
-// Y[i, c] = (Yadd ? Yadd[i, c] : 0) + alpha * sum_p v(p) * s(col) * X[col, c]
+// One CSR term sum_p v(p) * s(col) * X[col, c] of a sparse-dense product,
 // with v(p) = val[valpos ? valpos[p] : p], s = xscale ? xscale[col] : 1.
-// One wavefront per row: the row's entries are the same in every lane, so
-// they are read once as scalars; lane l takes columns c0 + l + 64 m,
-// m < CPT.  Eight entries per pass with all their X loads in flight
-// (addresses clamped, padding entries weighted 0); entry p adds into
-// partial sum (p - p0) mod 4, the four combined as (s0 + s1) + (s2 + s3).
-// 256 threads: four rows per workgroup.
+struct SpTerm {
+  const int32_t* ptr;
+  const int32_t* col;
+  const double* val;
+  const int32_t* valpos;
+  const double* xscale;
+  const double* X;
+  int ldx;
+};
+
+// Row i of a term for columns c0 + 64 m (m < CPT) of one lane: the row's
+// entries are the same in every lane of the wavefront (i uniform), so they
+// are read as scalars.  Eight entries per pass with all their X loads in
+// flight (addresses clamped, padding entries weighted 0); entry p adds into
+// partial sum (p - p0) mod 4, combined as (s0 + s1) + (s2 + s3).
 template <int CPT>
-__global__ void __launch_bounds__(256) k_spmm(int nrows, const int32_t* __restrict__ ptr,
-                                              const int32_t* __restrict__ colidx, const double* __restrict__ val,
-                                              const int32_t* __restrict__ valpos, const double* __restrict__ xscale,
-                                              const double* __restrict__ X, int ldx, int ncols, double alpha,
-                                              const double* __restrict__ Yadd, int ldya, double* __restrict__ Y,
-                                              int ldy) {
-  const int i = __builtin_amdgcn_readfirstlane(blockIdx.y * 4 + (int)(threadIdx.x >> 6));
-  if (i >= nrows) return;
-  const int lane = threadIdx.x & 63;
-  const int c0 = blockIdx.x * 64 * CPT + lane;
-  const int p0 = ptr[i], p1 = ptr[i + 1];
+__device__ __forceinline__ void spmm_row(const SpTerm& A, int i, int c0, int ncols, double (&r)[CPT]) {
+  const int p0 = A.ptr[i], p1 = A.ptr[i + 1];
   double a[CPT][4];
 #pragma unroll
   for (int k = 0; k < CPT; ++k)
@@ -1242,30 +1355,50 @@ __global__ void __launch_bounds__(256) k_spmm(int nrows, const int32_t* __restri
 #pragma unroll
     for (int m = 0; m < 8; ++m) {
       const int pc = min(pb + m, p1 - 1);
-      jj[m] = colidx[pc];
-      const double raw = val[valpos ? valpos[pc] : pc];
+      jj[m] = A.col[pc];
+      const double raw = A.val[A.valpos ? A.valpos[pc] : pc];
       vv[m] = pb + m < p1 ? raw : 0.0;
     }
-    if (xscale) {
+    if (A.xscale) {
 #pragma unroll
-      for (int m = 0; m < 8; ++m) vv[m] *= xscale[jj[m]];
+      for (int m = 0; m < 8; ++m) vv[m] *= A.xscale[jj[m]];
     }
     double xv[8][CPT];
 #pragma unroll
     for (int m = 0; m < 8; ++m)
 #pragma unroll
-      for (int k = 0; k < CPT; ++k) xv[m][k] = X[(size_t)jj[m] * ldx + min(c0 + 64 * k, ncols - 1)];
+      for (int k = 0; k < CPT; ++k) xv[m][k] = A.X[(size_t)jj[m] * A.ldx + min(c0 + 64 * k, ncols - 1)];
 #pragma unroll
     for (int m = 0; m < 8; ++m)
 #pragma unroll
       for (int k = 0; k < CPT; ++k) a[k][m & 3] += vv[m] * xv[m][k];
   }
 #pragma unroll
+  for (int k = 0; k < CPT; ++k) r[k] = (a[k][0] + a[k][1]) + (a[k][2] + a[k][3]);
+}
+
+// Y[i, c] = alpha * (A1 row i)(c) (+ Yadd[i, c]); with TWO, then
+// Y[i, c] = alpha2 * (A2 row i)(c) + that.  One wavefront per row, lane l
+// taking columns c0 + l + 64 m (m < CPT); 256 threads, four rows per
+// workgroup.
+template <int CPT, bool TWO>
+__global__ void __launch_bounds__(256) k_spmm(int nrows, SpTerm A1, SpTerm A2, int ncols, double alpha, double alpha2,
+                                              const double* __restrict__ Yadd, int ldya, double* __restrict__ Y,
+                                              int ldy) {
+  const int i = __builtin_amdgcn_readfirstlane(blockIdx.y * 4 + (int)(threadIdx.x >> 6));
+  if (i >= nrows) return;
+  const int lane = threadIdx.x & 63;
+  const int c0 = blockIdx.x * 64 * CPT + lane;
+  double r[CPT], r2[CPT];
+  spmm_row<CPT>(A1, i, c0, ncols, r);
+  if (TWO) spmm_row<CPT>(A2, i, c0, ncols, r2);
+#pragma unroll
   for (int k = 0; k < CPT; ++k) {
     const int c = c0 + 64 * k;
     if (c < ncols) {
-      double acc = ((a[k][0] + a[k][1]) + (a[k][2] + a[k][3])) * alpha;
+      double acc = r[k] * alpha;
       if (Yadd) acc += Yadd[(size_t)i * ldya + c];
+      if (TWO) acc = r2[k] * alpha2 + acc;
       Y[(size_t)i * ldy + c] = acc;
     }
   }
@@ -1633,17 +1766,40 @@ __global__ void k_zero_if(int n, const int32_t* __restrict__ info, double* __res
 }
 
 // ------------------------------------------------------------ dense step
-// K = (H + H^T)/2 + diag + delta I, written to both triangles.
+// K = (H + H^T)/2 + diag + delta I, written to both triangles.  One
+// workgroup (32 x 8 threads) per pair of 32 x 32 tiles (block row bi >=
+// block column bj) and its mirror: both staged through LDS, so every global
+// access runs along rows.
 __global__ void k_symmetrize(int n, double* __restrict__ K, const double* __restrict__ d, double delta) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  const int i = blockIdx.y * blockDim.y + threadIdx.y;
-  if (i >= n || j > i) return;
-  if (i == j) {
-    K[(size_t)i * n + i] += (d ? d[i] : 0.0) + delta;
-  } else {
-    const double v = 0.5 * (K[(size_t)i * n + j] + K[(size_t)j * n + i]);
-    K[(size_t)i * n + j] = v;
-    K[(size_t)j * n + i] = v;
+  const int bj = blockIdx.x, bi = blockIdx.y;
+  if (bj > bi) return;
+  __shared__ double lo[32][33], up[32][33];
+  const int tx = threadIdx.x, ty = threadIdx.y;
+  const int i0 = bi * 32, j0 = bj * 32;
+  // lo[r][c] = K[i0 + r][j0 + c], up[r][c] = K[j0 + r][i0 + c]
+  double vl[4], vu[4];
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    const int r = ty + 8 * m;
+    vl[m] = (i0 + r < n && j0 + tx < n) ? K[(size_t)(i0 + r) * n + j0 + tx] : 0.0;
+    vu[m] = (j0 + r < n && i0 + tx < n) ? K[(size_t)(j0 + r) * n + i0 + tx] : 0.0;
+  }
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    lo[ty + 8 * m][tx] = vl[m];
+    up[ty + 8 * m][tx] = vu[m];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    const int r = ty + 8 * m;
+    // element (i0 + r, j0 + tx) pairs with (j0 + tx, i0 + r) = up[tx][r]
+    const int i = i0 + r, j = j0 + tx;
+    if (i < n && j < n) K[(size_t)i * n + j] = i == j ? lo[r][tx] + ((d ? d[i] : 0.0) + delta)
+                                                     : 0.5 * (lo[r][tx] + up[tx][r]);
+    // mirror tile: element (j0 + r, i0 + tx) pairs with lo[tx][r]
+    const int i2 = j0 + r, j2 = i0 + tx;
+    if (bi != bj && i2 < n && j2 < n) K[(size_t)i2 * n + j2] = 0.5 * (up[r][tx] + lo[tx][r]);
   }
 }
 
@@ -1997,19 +2153,33 @@ __global__ void __launch_bounds__(256) k_chol_fwd(int n, const double* __restric
   const int t = threadIdx.x;
   stage_tile<256>(tri, dinv + (size_t)(w * 2) * CB * CB, CB, CB, CB, 0.0);
   // products with the solved blocks: thread (row r, slice sl of 16 columns)
+  // The factor entries do not depend on the flags: those of block k + 1
+  // are loaded before the wait for block k's flag.
   const int r = t >> 2, sl = t & 3;
+  const double* Lrow = L + (size_t)(b0 + min(r, nb - 1)) * n + sl * 16;
   double a0 = 0.0, a1 = 0.0;
+  double lv[16];
+  if (w > 0) {
+#pragma unroll
+    for (int q = 0; q < 16; ++q) lv[q] = Lrow[q];
+  }
   for (int k = 0; k < w; ++k) {
+    double lc[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) lc[q] = lv[q];
+    if (k + 1 < w) {
+#pragma unroll
+      for (int q = 0; q < 16; ++q) lv[q] = Lrow[(k + 1) * CB + q];
+    }
     if (t == 0) blk_wait(flags + k, info);
     __syncthreads();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     if (r < nb) {
-      const double* Lr = L + (size_t)(b0 + r) * n + k * CB + sl * 16;
       const double* yk = y + k * CB + sl * 16;
 #pragma unroll
       for (int q = 0; q < 16; q += 2) {
-        a0 += Lr[q] * yk[q];
-        a1 += Lr[q + 1] * yk[q + 1];
+        a0 += lc[q] * yk[q];
+        a1 += lc[q + 1] * yk[q + 1];
       }
     }
   }
@@ -2045,21 +2215,32 @@ __global__ void __launch_bounds__(256) k_chol_bwd(int n, const double* __restric
   stage_tile<256>(tri, dinv + (size_t)(w * 2) * CB * CB, CB, CB, CB, 0.0);
   // products with the solved blocks: lane i = column b0 + i of L (row of
   // L^T), wave sl takes rows k CB + 16 sl .. + 15 of each later block
+  // (the factor entries of block k - 1 are loaded before the wait for
+  // block k's flag; rows past n are clamped and not summed)
   const int i = t & 63, sl = t >> 6;
+  const double* Lcol = L + b0 + min(i, nb - 1);
   double a0 = 0.0, a1 = 0.0;
+  double lv[16];
+  auto load_l = [&](int k) {
+#pragma unroll
+    for (int q = 0; q < 16; ++q) lv[q] = Lcol[(size_t)min(k * CB + sl * 16 + q, n - 1) * n];
+  };
+  if (nblk - 1 > w) load_l(nblk - 1);
   for (int k = nblk - 1; k > w; --k) {
+    double lc[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) lc[q] = lv[q];
+    if (k - 1 > w) load_l(k - 1);
     if (t == 0) blk_wait(flags + k, info);
     __syncthreads();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     const int kr0 = k * CB + sl * 16;
-    const int kr1 = min(kr0 + 16, n);
     if (i < nb) {
-      int j = kr0;
-      for (; j + 1 < kr1; j += 2) {
-        a0 += L[(size_t)j * n + b0 + i] * x[j];
-        a1 += L[(size_t)(j + 1) * n + b0 + i] * x[j + 1];
+#pragma unroll
+      for (int q = 0; q < 16; q += 2) {
+        if (kr0 + q < n) a0 += lc[q] * x[kr0 + q];
+        if (kr0 + q + 1 < n) a1 += lc[q + 1] * x[kr0 + q + 1];
       }
-      if (j < kr1) a0 += L[(size_t)j * n + b0 + i] * x[j];
     }
   }
   part[sl][i] = a0 + a1;

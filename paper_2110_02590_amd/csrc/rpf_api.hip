@@ -72,10 +72,16 @@ struct rpf_grid {
   int32_t *K_ptr, *K_col, *K_sp, *K_s, *K_diag, *vg_sp, *vg_s;
   int32_t *pq, *pv, *gen_pidx, *pv_gen, *var_kind, *var_aux;
   int32_t *pack_ptr, *lo_split, *up_split, *pk_flev, *pk_flev_off, *pk_frows, *pk_blev, *pk_blev_off, *pk_brows;
+  int32_t* topmul_rows = nullptr;   // pack rows with U entries in top columns
+  int n_topmul_rows = 0;
   int32_t *top_flev, *top_frows, *top_blev, *top_brows, *top_pos;
   int64_t* top_dense;
   double *dense_top, *dense_topT;
   double *top_dinv, *top_dinvT;   // inverse diagonal blocks of the dense top factor
+  // dense inverse S^-1 of the top block and its transpose, computed once per
+  // point (after the adjoint solve) for the Hessian-vector products
+  double *top_inv, *top_invT;
+  bool top_inv_ok = false;
   int npacks = 0, max_pack = 0, tw = 16;
   int32_t *pkf_rp, *pkf_pos, *pkb_rp, *pkb_pos;
   int16_t *pkf_col, *pkb_col;
@@ -272,6 +278,13 @@ void setup(rpf_grid* h) {
   h->pack_ptr = h->up(P.pack_ptr);
   h->lo_split = h->up(P.lo_split);
   h->up_split = h->up(P.up_split);
+  {
+    std::vector<int32_t> rows;
+    for (int i = 0; i < P.t0; ++i)
+      if (P.up_split[i] < P.lu_ptr[i + 1]) rows.push_back(i);
+    h->n_topmul_rows = (int)rows.size();
+    h->topmul_rows = h->up(rows);
+  }
   h->pk_flev = h->up(P.pk_flev);
   h->pk_flev_off = h->up(P.pk_flev_off);
   h->pk_frows = h->up(P.pk_frows);
@@ -299,6 +312,8 @@ void setup(rpf_grid* h) {
   h->dense_topT = h->alloc<double>((size_t)P.ntop * P.ntop);
   h->top_dinv = h->alloc<double>((size_t)cdiv(P.ntop, CB) * 2 * CB * CB);
   h->top_dinvT = h->alloc<double>((size_t)cdiv(P.ntop, CB) * 2 * CB * CB);
+  h->top_inv = h->alloc<double>((size_t)P.ntop * P.ntop);
+  h->top_invT = h->alloc<double>((size_t)P.ntop * P.ntop);
   h->npacks = (int)P.pack_ptr.size() - 1;
   for (int q = 0; q < h->npacks; ++q) h->max_pack = std::max(h->max_pack, P.pack_ptr[q + 1] - P.pack_ptr[q]);
   {
@@ -534,6 +549,7 @@ void dense_factor(int n, double* A, int32_t* info, int base, hipStream_t s, cons
 
 void refactor(rpf_grid* h, hipStream_t s, const int32_t* skip = nullptr) {
   const Presolve& P = h->P;
+  h->top_inv_ok = false;
   const size_t nnz = P.lu_col.size();
   k_gather_sum<<<cdiv(nnz, 256), 256, 0, s>>>((int)nnz, h->jx_sp, h->jx_s, h->rec, nullptr, h->luv, skip);
   LAUNCHCHK();
@@ -688,43 +704,83 @@ void solve_pair(rpf_grid* h, bool transposed, double* X, int ld, int ncols, doub
   pack_solve_any(h, twp, true, fwd_unit, transposed, val, X, ld, ncols, scale, cls, s, skip);
   if (P.ntop > 0) {
     size_t pi = h->prof_on ? h->prof_begin(s) : 0;
-    int bx = 64;
-    while (bx > 1 && bx / 2 >= ncols) bx /= 2;
-    const dim3 rb(bx, 256 / bx);
-    k_top_rhs<<<dim3(cdiv(ncols, bx), cdiv(P.ntop, (int)rb.y)), rb, 0, s>>>(P.t0, P.nx, h->lo_split, h->lu_ptr,
+    if (ncols > 64) {
+      k_top_rhs_w<2><<<dim3(cdiv(ncols, 128), cdiv(P.ntop, 4)), 256, 0, s>>>(P.t0, P.nx, h->lo_split, h->lu_ptr,
                                                                             h->lu_col, val, X, ld, ncols, scale,
                                                                             skip);
+    } else if (ncols > 1) {
+      k_top_rhs_w<1><<<dim3(cdiv(ncols, 64), cdiv(P.ntop, 4)), 256, 0, s>>>(P.t0, P.nx, h->lo_split, h->lu_ptr,
+                                                                           h->lu_col, val, X, ld, ncols, scale,
+                                                                           skip);
+    } else {
+      const dim3 rb(1, 256);
+      k_top_rhs<<<dim3(1, cdiv(P.ntop, 256)), rb, 0, s>>>(P.t0, P.nx, h->lo_split, h->lu_ptr, h->lu_col, val, X,
+                                                           ld, ncols, scale, skip);
+    }
     LAUNCHCHK();
-    const size_t shm = (size_t)P.ntop * twt * sizeof(double);
-    const double* M = transposed ? h->dense_topT : h->dense_top;
-    const double* dinv = transposed ? h->top_dinvT : h->top_dinv;
-    k_top_dense<<<cdiv(ncols, twt), 256, shm, s>>>(P.t0, P.nx, M, dinv, X, ld, ncols, twt, skip);
-    LAUNCHCHK();
+    if (h->top_inv_ok) {
+      // one dense product with the inverse (k-major: S^-T gives S^-1 X)
+      const double* A = transposed ? h->top_inv : h->top_invT;
+      const int nt = std::min(1024, 64 * cdiv(P.ntop, 64));
+      if (ncols > 1)
+        // two columns per workgroup: more workgroups to hide the L2 latency
+        // of the inverse's rows (measured: 2 faster than 4 or 8)
+        k_top_inv_apply<2><<<cdiv(ncols, 2), nt, (size_t)P.ntop * 2 * sizeof(double), s>>>(P.t0, P.ntop, A, X, ld,
+                                                                                           ncols, skip);
+      else
+        k_top_inv_apply<1><<<ncols, nt, (size_t)P.ntop * sizeof(double), s>>>(P.t0, P.ntop, A, X, ld, ncols, skip);
+      LAUNCHCHK();
+    } else {
+      const size_t shm = (size_t)P.ntop * twt * sizeof(double);
+      const double* M = transposed ? h->dense_topT : h->dense_top;
+      const double* dinv = transposed ? h->top_dinvT : h->top_dinv;
+      k_top_dense<<<cdiv(ncols, twt), 256, shm, s>>>(P.t0, P.nx, M, dinv, X, ld, ncols, twt, skip);
+      LAUNCHCHK();
+    }
     if (ncols > 1 && h->tw_packt > 0 && h->npacks > 0) {
       // the LDS-tile pack solves expect the top products already subtracted
-      k_pack_topmul<<<dim3(cdiv(ncols, 64), cdiv(P.t0, 4)), dim3(64, 4), 0, s>>>(P.t0, h->up_split, h->lu_ptr,
-                                                                                  h->lu_col, val, X, ld, ncols,
-                                                                                  skip);
-      LAUNCHCHK();
+      if (h->n_topmul_rows > 0) {
+        const int nr = h->n_topmul_rows;
+        if (ncols > 64)
+          k_pack_topmul_w<2><<<dim3(cdiv(ncols, 128), cdiv(nr, 4)), 256, 0, s>>>(nr, h->topmul_rows, h->up_split,
+                                                                                h->lu_ptr, h->lu_col, val, X, ld,
+                                                                                ncols, skip);
+        else
+          k_pack_topmul_w<1><<<dim3(cdiv(ncols, 64), cdiv(nr, 4)), 256, 0, s>>>(nr, h->topmul_rows, h->up_split,
+                                                                               h->lu_ptr, h->lu_col, val, X, ld,
+                                                                               ncols, skip);
+        LAUNCHCHK();
+      }
     }
     if (h->prof_on) h->prof_end(cls == 0 ? 5 : cls, pi, s);
   }
   pack_solve_any(h, twp, false, !fwd_unit, transposed, val, X, ld, ncols, 1.0, cls, s, skip);
 }
 
+// Y = alpha A1 X1 (+ Yadd); with A2, then Y = A2 X2 + that (one pass).
+void spmm_terms(rpf_grid* h, int nrows, const SpTerm& A1, const SpTerm* A2, int ncols, double alpha,
+                const double* Yadd, int ldya, double* Y, int ldy, hipStream_t s) {
+  size_t pi = h->prof_on ? h->prof_begin(s) : 0;
+  const SpTerm B2 = A2 ? *A2 : A1;
+  // two columns per lane once a row has more than one wavefront's worth
+  const dim3 g2(cdiv(ncols, 128), cdiv(nrows, 4)), g1(cdiv(ncols, 64), cdiv(nrows, 4));
+  if (ncols > 64 && A2)
+    k_spmm<2, true><<<g2, 256, 0, s>>>(nrows, A1, B2, ncols, alpha, 1.0, Yadd, ldya, Y, ldy);
+  else if (ncols > 64)
+    k_spmm<2, false><<<g2, 256, 0, s>>>(nrows, A1, B2, ncols, alpha, 1.0, Yadd, ldya, Y, ldy);
+  else if (A2)
+    k_spmm<1, true><<<g1, 256, 0, s>>>(nrows, A1, B2, ncols, alpha, 1.0, Yadd, ldya, Y, ldy);
+  else
+    k_spmm<1, false><<<g1, 256, 0, s>>>(nrows, A1, B2, ncols, alpha, 1.0, Yadd, ldya, Y, ldy);
+  LAUNCHCHK();
+  if (h->prof_on) h->prof_end(3, pi, s);
+}
+
 void spmm(rpf_grid* h, int nrows, const int32_t* ptr, const int32_t* col, const double* val,
           const int32_t* valpos, const double* xscale, const double* X, int ldx, int ncols, double alpha,
           const double* Yadd, int ldya, double* Y, int ldy, hipStream_t s) {
-  size_t pi = h->prof_on ? h->prof_begin(s) : 0;
-  // two columns per lane once a row has more than one wavefront's worth
-  if (ncols > 64)
-    k_spmm<2><<<dim3(cdiv(ncols, 128), cdiv(nrows, 4)), 256, 0, s>>>(nrows, ptr, col, val, valpos, xscale, X, ldx,
-                                                                     ncols, alpha, Yadd, ldya, Y, ldy);
-  else
-    k_spmm<1><<<dim3(cdiv(ncols, 64), cdiv(nrows, 4)), 256, 0, s>>>(nrows, ptr, col, val, valpos, xscale, X, ldx,
-                                                                    ncols, alpha, Yadd, ldya, Y, ldy);
-  LAUNCHCHK();
-  if (h->prof_on) h->prof_end(3, pi, s);
+  const SpTerm A{ptr, col, val, valpos, xscale, X, ldx};
+  spmm_terms(h, nrows, A, nullptr, ncols, alpha, Yadd, ldya, Y, ldy, s);
 }
 
 // step = -(L L^T)^{-1} rhs with the dense Cholesky factor L (row-major n x n,
@@ -799,9 +855,13 @@ void hvp_batch(rpf_grid* h, const double* V, int ldv, int j0, int B, double* HV,
   // Z = U^{-1} L^{-1} R
   solve_pair(h, false, Dx, ld, B, 1.0, s);
   // Y = K [Z; V] + G^T diag(kappa) G [Z; V]
-  spmm(h, P.nvar, h->K_ptr, h->K_col, h->Kv, nullptr, nullptr, D, ld, B, 1.0, nullptr, 0, Y, ld, s);
+  // (T = G [Z; V] first; then both terms of Y in one pass over its rows)
   spmm(h, P.nr1, h->G_ptr, h->G_col, h->Gv, nullptr, nullptr, D, ld, B, 1.0, nullptr, 0, T, ld, s);
-  spmm(h, P.nvar, h->Gt_ptr, h->Gt_col, h->Gv, h->Gt_pos, h->kappa, T, ld, B, 1.0, Y, ld, Y, ld, s);
+  {
+    const SpTerm Kt{h->K_ptr, h->K_col, h->Kv, nullptr, nullptr, D, ld};
+    const SpTerm Gk{h->Gt_ptr, h->Gt_col, h->Gv, h->Gt_pos, h->kappa, T, ld};
+    spmm_terms(h, P.nvar, Kt, &Gk, B, 1.0, nullptr, 0, Y, ld, s);
+  }
   // Psi = -J_x^{-T} Y_x  (U^T then L^T)
   solve_pair(h, true, Y, ld, B, -1.0, s);
   // HV = Y_u + J_u^T Psi
@@ -1126,6 +1186,20 @@ void gradient_core(rpf_grid* h, const double* u, const double* pd, const double*
   k_gather_sum<<<cdiv(P.G_col.size(), 256), 256, 0, s>>>((int)P.G_col.size(), h->G_sp, h->G_s, h->rec, nullptr,
                                                           h->Gv, nullptr);
   LAUNCHCHK();
+  // dense inverse of the top block for the batched solves: the top solve
+  // applied to the identity, then its transpose
+  if (P.ntop > 0 && (size_t)P.ntop * 2 * sizeof(double) <= 64 * 1024) {
+    const int nt = P.ntop;
+    k_identity_block<<<dim3(cdiv(nt, 64), cdiv(nt, 4)), dim3(64, 4), 0, s>>>(nt, nt, 0, h->top_inv, nt);
+    LAUNCHCHK();
+    const int twt = h->tw_top;
+    k_top_dense<<<cdiv(nt, twt), 256, (size_t)nt * twt * sizeof(double), s>>>(0, nt, h->dense_top, h->top_dinv,
+                                                                             h->top_inv, nt, nt, twt, nullptr);
+    LAUNCHCHK();
+    k_transpose<<<dim3(cdiv(nt, 32), cdiv(nt, 32)), dim3(32, 8), 0, s>>>(nt, h->top_inv, h->top_invT, nullptr);
+    LAUNCHCHK();
+    h->top_inv_ok = true;
+  }
   h->rho = rho;
   h->have_point = true;
 }
@@ -1225,7 +1299,7 @@ int rpf_factor_solve(rpf_grid* h, int32_t n, double* K, const double* diag, doub
     k_fill_int<<<1, 1, 0, s>>>(1, info, 0);
     LAUNCHCHK();
     size_t pi = h->prof_on ? h->prof_begin(s) : 0;
-    k_symmetrize<<<dim3(cdiv(n, 32), cdiv(n, 8)), dim3(32, 8), 0, s>>>(n, K, diag, delta);
+    k_symmetrize<<<dim3(cdiv(n, 32), cdiv(n, 32)), dim3(32, 8), 0, s>>>(n, K, diag, delta);
     LAUNCHCHK();
     dense_factor<true>(n, K, info, 0, s);
     chol_solve(h, n, K, rhs, step, info, s);
@@ -1278,7 +1352,7 @@ int rpf_track_step(rpf_grid* h, double* u, double* x, double* y, const double* p
     // 4. step = -(H + delta I)^{-1} grad (zero when the factorization fails)
     k_copy_vec<<<cdiv((long)nu * nu, 256), 256, 0, s>>>(nu * nu, h->Hbuf, h->Kbuf, nullptr);
     LAUNCHCHK();
-    k_symmetrize<<<dim3(cdiv(nu, 32), cdiv(nu, 8)), dim3(32, 8), 0, s>>>(nu, h->Kbuf, nullptr, delta);
+    k_symmetrize<<<dim3(cdiv(nu, 32), cdiv(nu, 32)), dim3(32, 8), 0, s>>>(nu, h->Kbuf, nullptr, delta);
     LAUNCHCHK();
     dense_factor<true>(nu, h->Kbuf, info, 0, s);
     chol_solve(h, nu, h->Kbuf, h->gradbuf, h->dstep, info, s);
