@@ -390,6 +390,10 @@ __device__ __forceinline__ double group_sum(double v, int G) {
   return v;
 }
 
+// Elimination steps between the load of a step's update targets and the
+// step itself in the LDS-resident refactorization.
+constexpr int RF_AHEAD = 2;
+
 // Packs with their LU values resident in LDS: one workgroup (16
 // wavefronts) per pack, forward levels separated by barriers, one
 // wavefront per row, eliminating in place in LDS.  The metadata of up to
@@ -455,10 +459,10 @@ __global__ void __launch_bounds__(1024) k_rf_pack_lds(const int32_t* __restrict_
           m_u0 = upd_ptr[p];
           m_nu = (int)(upd_ptr[p + 1] - m_u0);
         }
-        // targets of step s live in tgA (s even) or tgB (s odd); the load
-        // for step s + 2 is issued during step s into the same register
+        // targets of step s live in tg[s mod RF_AHEAD]; the load for step
+        // s + RF_AHEAD is issued during step s into the same register:
         // unconditional loads (upd_tgt is padded past its end), so the
-        // compiler can count them and wait only for the older one
+        // compiler can count them and wait only for the oldest one
         auto fetch_tg = [&](int st) -> int {
           const int64_t u = readlane64(m_u0, st);
           return upd_tgt[u + (lane < __builtin_amdgcn_readlane(m_nu, st) ? lane : 0)];
@@ -485,13 +489,15 @@ __global__ void __launch_bounds__(1024) k_rf_pack_lds(const int32_t* __restrict_
           __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
           __builtin_amdgcn_wave_barrier();
         };
-        int tgA = fetch_tg(0);
-        int tgB = fetch_tg(min(1, nw - 1));
-        for (int st = 0; st < nw; st += 2) {
-          step(st, tgA);
-          tgA = fetch_tg(min(st + 2, nw - 1));
-          if (st + 1 < nw) step(st + 1, tgB);
-          tgB = fetch_tg(min(st + 3, nw - 1));
+        int tg[RF_AHEAD];
+#pragma unroll
+        for (int d = 0; d < RF_AHEAD; ++d) tg[d] = fetch_tg(min(d, nw - 1));
+        for (int st = 0; st < nw; st += RF_AHEAD) {
+#pragma unroll
+          for (int d = 0; d < RF_AHEAD; ++d) {
+            if (st + d < nw) step(st + d, tg[d]);
+            tg[d] = fetch_tg(min(st + d + RF_AHEAD, nw - 1));
+          }
         }
       }
       if (lane == 0) {
@@ -840,6 +846,92 @@ __device__ __forceinline__ void top_diag_apply(const double* __restrict__ D, int
     }
   }
   lds_barrier();
+}
+
+// Single right-hand side of the power flow and adjoint solves, top rows:
+// X[i] = scale X[i] - sum_{p in [ptr[i], lo_split[i])} fval[p] X[col[p]],
+// a wavefront per row with its lanes splitting the entries (DPP sum).
+__global__ void __launch_bounds__(256) k_top_rhs1(int t0, int n, const int32_t* __restrict__ lo_split,
+                                                  const int32_t* __restrict__ ptr, const int32_t* __restrict__ col,
+                                                  const double* __restrict__ fval, double* __restrict__ X, int ld,
+                                                  double scale, const int32_t* __restrict__ skip) {
+  if (skip && *skip) return;
+  const int i = t0 + __builtin_amdgcn_readfirstlane(blockIdx.x * 4 + (int)(threadIdx.x >> 6));
+  if (i >= n) return;
+  const int lane = threadIdx.x & 63;
+  const int p0 = ptr[i], p1 = lo_split[i];
+  double a0 = 0.0, a1 = 0.0;
+  for (int p = p0 + lane; p < p1; p += 128) {
+    a0 += fval[p] * X[(size_t)col[p] * ld];
+    if (p + 64 < p1) a1 += fval[p + 64] * X[(size_t)col[p + 64] * ld];
+  }
+  const double sum = group_sum(a0 + a1, 64);
+  if (lane == 0) X[(size_t)i * ld] = scale * X[(size_t)i * ld] - sum;
+}
+
+// Single right-hand side: the dense top solves x <- U^-1 L^-1 x (with M,
+// dinv of J_x^T: x <- L^-T U^-T x) for the s = n - t0 top rows, in one
+// workgroup of 1024 threads with x in LDS.  Per block of CB rows (forward,
+// then backward): wavefront w takes rows w + 16 m (m < 4); its lanes split
+// each row's products with the solved part and combine them by DPP; then
+// the block's inverse diagonal block is applied the same way (lane j
+// multiplies entry j).  The inverse's rows are loaded with the factor rows,
+// before the block's first barrier.
+__global__ void __launch_bounds__(1024) k_top_solve1(int t0, int n, const double* __restrict__ M,
+                                                     const double* __restrict__ dinv, double* __restrict__ X, int ld,
+                                                     const int32_t* __restrict__ skip) {
+  if (skip && *skip) return;
+  extern __shared__ double xs[];  // [s]
+  __shared__ double rv[CB];
+  const int s = n - t0;
+  const int t = threadIdx.x, w = t >> 6, lane = t & 63;
+  for (int e = t; e < s; e += blockDim.x) xs[e] = X[(size_t)(t0 + e) * ld];
+  __syncthreads();
+  const int nblk = (s + CB - 1) / CB;
+  for (int part = 0; part < 2; ++part) {
+    for (int q = 0; q < nblk; ++q) {
+      const int kb = part == 0 ? q : nblk - 1 - q;
+      const int b0 = kb * CB, nb = min(CB, s - b0);
+      // solved columns: forward [0, b0), backward [b0 + nb, s)
+      const int j0 = part == 0 ? 0 : b0 + nb, j1 = part == 0 ? b0 : s;
+      const double* D = dinv + (size_t)(kb * 2 + part) * CB * CB;
+      double dv[4], acc[4];
+#pragma unroll
+      for (int m = 0; m < 4; ++m) dv[m] = D[(w + 16 * m) * CB + lane];
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        const int r = w + 16 * m;
+        double a = 0.0;
+        if (r < nb) {
+          const double* Mr = M + (size_t)(b0 + r) * s;
+          for (int j = j0 + lane; j < j1; j += 64) a += Mr[j] * xs[j];
+        }
+        acc[m] = a;
+      }
+#pragma unroll
+      for (int m = 0; m < 4; ++m) acc[m] = group_sum(acc[m], 64);
+      if (lane == 0) {
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+          const int r = w + 16 * m;
+          rv[r] = r < nb ? xs[min(b0 + r, s - 1)] - acc[m] : 0.0;
+        }
+      }
+      __syncthreads();
+      const double rl = rv[lane];
+#pragma unroll
+      for (int m = 0; m < 4; ++m) acc[m] = group_sum(dv[m] * rl, 64);
+      if (lane == 0) {
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+          const int r = w + 16 * m;
+          if (r < nb) xs[b0 + r] = acc[m];
+        }
+      }
+      __syncthreads();
+    }
+  }
+  for (int e = t; e < s; e += blockDim.x) X[(size_t)(t0 + e) * ld] = xs[e];
 }
 
 // Dense forward and backward solves of the top rows (after k_top_rhs) with

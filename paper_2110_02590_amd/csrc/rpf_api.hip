@@ -704,7 +704,14 @@ void solve_pair(rpf_grid* h, bool transposed, double* X, int ld, int ncols, doub
   pack_solve_any(h, twp, true, fwd_unit, transposed, val, X, ld, ncols, scale, cls, s, skip);
   if (P.ntop > 0) {
     size_t pi = h->prof_on ? h->prof_begin(s) : 0;
-    if (ncols > 64) {
+    // single right-hand sides of the power flow and adjoint: lanes split a
+    // row's entries; the Hessian products (any width) sum each column in the
+    // same fixed order
+    const bool single = ncols == 1 && !h->top_inv_ok && (size_t)P.ntop * sizeof(double) <= 64 * 1024;
+    if (single) {
+      k_top_rhs1<<<cdiv(P.ntop, 4), 256, 0, s>>>(P.t0, P.nx, h->lo_split, h->lu_ptr, h->lu_col, val, X, ld, scale,
+                                                 skip);
+    } else if (ncols > 64) {
       k_top_rhs_w<2><<<dim3(cdiv(ncols, 128), cdiv(P.ntop, 4)), 256, 0, s>>>(P.t0, P.nx, h->lo_split, h->lu_ptr,
                                                                             h->lu_col, val, X, ld, ncols, scale,
                                                                             skip);
@@ -731,10 +738,14 @@ void solve_pair(rpf_grid* h, bool transposed, double* X, int ld, int ncols, doub
         k_top_inv_apply<1><<<ncols, nt, (size_t)P.ntop * sizeof(double), s>>>(P.t0, P.ntop, A, X, ld, ncols, skip);
       LAUNCHCHK();
     } else {
-      const size_t shm = (size_t)P.ntop * twt * sizeof(double);
       const double* M = transposed ? h->dense_topT : h->dense_top;
       const double* dinv = transposed ? h->top_dinvT : h->top_dinv;
-      k_top_dense<<<cdiv(ncols, twt), 256, shm, s>>>(P.t0, P.nx, M, dinv, X, ld, ncols, twt, skip);
+      if (single) {
+        k_top_solve1<<<1, 1024, (size_t)P.ntop * sizeof(double), s>>>(P.t0, P.nx, M, dinv, X, ld, skip);
+      } else {
+        const size_t shm = (size_t)P.ntop * twt * sizeof(double);
+        k_top_dense<<<cdiv(ncols, twt), 256, shm, s>>>(P.t0, P.nx, M, dinv, X, ld, ncols, twt, skip);
+      }
       LAUNCHCHK();
     }
     if (ncols > 1 && h->tw_packt > 0 && h->npacks > 0) {
