@@ -392,7 +392,7 @@ __device__ __forceinline__ double group_sum(double v, int G) {
 
 // Elimination steps between the load of a step's update targets and the
 // step itself in the LDS-resident refactorization.
-constexpr int RF_AHEAD = 2;
+constexpr int RF_AHEAD = 4;
 
 // Packs with their LU values resident in LDS: one workgroup (16
 // wavefronts) per pack, forward levels separated by barriers, one
@@ -2202,15 +2202,15 @@ __global__ void k_transpose(int n, const double* __restrict__ A, double* __restr
 }
 
 // Triangular solves with the dense Cholesky factor, L y = -rhs and
-// L^T step = y, spread over one workgroup per block of CB rows.  A block
-// publishes its solved entries by a flag (release at agent scope after its
-// stores); the workgroups that need them wait for the flag (acquire).  A
-// workgroup only waits for blocks of workgroups dispatched before it
-// (forward: lower block indices; backward: block = nblk - 1 - blockIdx.x),
-// so every awaited workgroup is already running.  Each wait is bounded: on
-// expiry info[0] is set to -1 and the solve continues, so every wave exits.
-// flags: int32 [nblk] per direction (its own array for each launch), zero
-// before the launch.
+// L^T step = y, spread over one workgroup per two blocks of CB rows.  A
+// workgroup publishes its solved entries by a flag (release at agent scope
+// after its stores); the workgroups that need them wait for the flag
+// (acquire).  A workgroup only waits for workgroups dispatched before it
+// (forward: lower indices; backward: v = nwg - 1 - blockIdx.x), so every
+// awaited workgroup is already running.  Each wait is bounded: on expiry
+// info[0] is set to -1 and the solve continues, so every wave exits.
+// flags: int32 [nwg] per direction (its own array for each launch), zero
+// before the launch; nwg = ceil(n / (2 CB)).
 
 __device__ __forceinline__ void blk_wait(const int32_t* flag, int32_t* info) {
   unsigned it = 0;
@@ -2232,44 +2232,67 @@ __device__ __forceinline__ void blk_publish(int32_t* flag) {
 
 // dinv: inverses of the factor's diagonal blocks, (kb * 2) * CB * CB
 // row-major, zero outside each block's corner.
-__global__ void __launch_bounds__(256) k_chol_fwd(int n, const double* __restrict__ L,
+// Each workgroup (512 threads) solves two blocks of CB rows, 2 CB v ..
+// 2 CB v + 2 CB: the products with the other workgroups' solved rows come
+// first, one flag per workgroup; its second block then takes the first's
+// solution through LDS, without another flag.  Factor entries and the
+// inverse blocks' rows are loaded before they are needed (those of the next
+// awaited workgroup during the wait for the current one).
+__global__ void __launch_bounds__(512) k_chol_fwd(int n, const double* __restrict__ L,
                                                   const double* __restrict__ dinv, const double* __restrict__ rhs,
                                                   double* __restrict__ y, int32_t* __restrict__ flags,
                                                   int32_t* __restrict__ info) {
   if (info[0] > 0) return;
-  __shared__ double part[CB][5];
-  __shared__ double tri[CB][CB + 1];
+  __shared__ double part[2 * CB][5];
   __shared__ double rv[CB];
-  const int w = blockIdx.x;
-  const int b0 = w * CB, nb = min(CB, n - b0);
+  __shared__ double ys[CB];
+  const int v = blockIdx.x;
+  const int R0 = 2 * CB * v, nr = min(2 * CB, n - R0);
+  const int nA = min(CB, nr), nB = nr - nA;
   const int t = threadIdx.x;
-  stage_tile<256>(tri, dinv + (size_t)(w * 2) * CB * CB, CB, CB, CB, 0.0);
-  // products with the solved blocks: thread (row r, slice sl of 16 columns)
-  // The factor entries do not depend on the flags: those of block k + 1
-  // are loaded before the wait for block k's flag.
+  // products with earlier workgroups: thread (row r, slice sl of 32 columns
+  // of each earlier 2 CB-column block)
   const int r = t >> 2, sl = t & 3;
-  const double* Lrow = L + (size_t)(b0 + min(r, nb - 1)) * n + sl * 16;
-  double a0 = 0.0, a1 = 0.0;
-  double lv[16];
-  if (w > 0) {
+  const double* Lrow = L + (size_t)(R0 + min(r, nr - 1)) * n + sl * 32;
+  // inverse blocks and the block-B-by-block-A factor entries: thread (row i,
+  // segment seg of 8 columns)
+  const int i = t >> 3, seg = t & 7;
+  double dA[8], dB[8], lBA[8];
+  {
+    const double* DA = dinv + (size_t)(2 * v * 2) * CB * CB + i * CB + seg * 8;
 #pragma unroll
-    for (int q = 0; q < 16; ++q) lv[q] = Lrow[q];
+    for (int q = 0; q < 8; ++q) dA[q] = DA[q];
+    if (nB > 0) {
+      const double* DB = dinv + (size_t)((2 * v + 1) * 2) * CB * CB + i * CB + seg * 8;
+      const double* LB = L + (size_t)(R0 + CB + min(i, nB - 1)) * n + R0 + seg * 8;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        dB[q] = DB[q];
+        lBA[q] = LB[q];
+      }
+    }
   }
-  for (int k = 0; k < w; ++k) {
-    double lc[16];
+  double a0 = 0.0, a1 = 0.0;
+  double lv[32];
+  if (v > 0) {
 #pragma unroll
-    for (int q = 0; q < 16; ++q) lc[q] = lv[q];
-    if (k + 1 < w) {
+    for (int q = 0; q < 32; ++q) lv[q] = Lrow[q];
+  }
+  for (int k = 0; k < v; ++k) {
+    double lc[32];
 #pragma unroll
-      for (int q = 0; q < 16; ++q) lv[q] = Lrow[(k + 1) * CB + q];
+    for (int q = 0; q < 32; ++q) lc[q] = lv[q];
+    if (k + 1 < v) {
+#pragma unroll
+      for (int q = 0; q < 32; ++q) lv[q] = Lrow[(k + 1) * 2 * CB + q];
     }
     if (t == 0) blk_wait(flags + k, info);
     __syncthreads();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    if (r < nb) {
-      const double* yk = y + k * CB + sl * 16;
+    if (r < nr) {
+      const double* yk = y + k * 2 * CB + sl * 32;
 #pragma unroll
-      for (int q = 0; q < 16; q += 2) {
+      for (int q = 0; q < 32; q += 2) {
         a0 += lc[q] * yk[q];
         a1 += lc[q + 1] * yk[q + 1];
       }
@@ -2277,80 +2300,142 @@ __global__ void __launch_bounds__(256) k_chol_fwd(int n, const double* __restric
   }
   part[r][sl] = a0 + a1;
   __syncthreads();
-  if (t < CB) rv[t] = t < nb ? -rhs[b0 + t] - ((part[t][0] + part[t][1]) + (part[t][2] + part[t][3])) : 0.0;
+  if (t < CB) rv[t] = t < nA ? -rhs[R0 + t] - ((part[t][0] + part[t][1]) + (part[t][2] + part[t][3])) : 0.0;
   __syncthreads();
-  // y_block = L_kk^{-1} rv: 16 terms per thread, slices reduced by shuffles
-  double s0 = 0.0, s1 = 0.0;
+  // block A: y_A = L_AA^{-1} rv
+  {
+    double sacc = 0.0;
 #pragma unroll
-  for (int j = 0; j < 16; j += 2) {
-    s0 += tri[r][sl * 16 + j] * rv[sl * 16 + j];
-    s1 += tri[r][sl * 16 + j + 1] * rv[sl * 16 + j + 1];
+    for (int q = 0; q < 8; ++q) sacc += dA[q] * rv[seg * 8 + q];
+    sacc = group_sum(sacc, 8);
+    if (seg == 0) {
+      ys[i] = sacc;
+      if (i < nA) y[R0 + i] = sacc;
+    }
   }
-  double sacc = s0 + s1;
-  sacc = group_sum(sacc, 4);
-  if (sl == 0 && r < nb) y[b0 + r] = sacc;
-  blk_publish(flags + w);
+  __syncthreads();
+  if (nB > 0) {
+    // block B: rv = -rhs_B - (earlier workgroups) - L_BA y_A
+    double sacc = 0.0;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) sacc += lBA[q] * ys[seg * 8 + q];
+    sacc = group_sum(sacc, 8);
+    if (seg == 0) {
+      const int rb = CB + i;
+      rv[i] = i < nB ? -rhs[R0 + rb] - ((part[rb][0] + part[rb][1]) + (part[rb][2] + part[rb][3])) - sacc : 0.0;
+    }
+    __syncthreads();
+    double sb = 0.0;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) sb += dB[q] * rv[seg * 8 + q];
+    sb = group_sum(sb, 8);
+    if (seg == 0 && i < nB) y[R0 + CB + i] = sb;
+  }
+  blk_publish(flags + v);
 }
 
-__global__ void __launch_bounds__(256) k_chol_bwd(int n, const double* __restrict__ L,
+// L^T x = y with the same two-block workgroups, in reverse order (workgroup
+// v = nwg - 1 - blockIdx.x, so every awaited workgroup was dispatched
+// earlier): block B (the second) first, then block A with x_B through LDS.
+__global__ void __launch_bounds__(512) k_chol_bwd(int n, const double* __restrict__ L,
                                                   const double* __restrict__ dinv, const double* __restrict__ y,
                                                   double* __restrict__ x, int32_t* __restrict__ flags,
                                                   int32_t* __restrict__ info) {
   if (info[0] > 0) return;
-  __shared__ double part[4][CB];
-  __shared__ double tri[CB][CB + 1];
+  __shared__ double part[4][2 * CB];
   __shared__ double rv[CB];
-  const int nblk = (n + CB - 1) / CB;
-  const int w = nblk - 1 - blockIdx.x;
-  const int b0 = w * CB, nb = min(CB, n - b0);
+  __shared__ double xs[CB];
+  const int nwg = (n + 2 * CB - 1) / (2 * CB);
+  const int v = nwg - 1 - blockIdx.x;
+  const int R0 = 2 * CB * v, nr = min(2 * CB, n - R0);
+  const int nA = min(CB, nr), nB = nr - nA;
   const int t = threadIdx.x;
-  stage_tile<256>(tri, dinv + (size_t)(w * 2) * CB * CB, CB, CB, CB, 0.0);
-  // products with the solved blocks: lane i = column b0 + i of L (row of
-  // L^T), wave sl takes rows k CB + 16 sl .. + 15 of each later block
-  // (the factor entries of block k - 1 are loaded before the wait for
-  // block k's flag; rows past n are clamped and not summed)
-  const int i = t & 63, sl = t >> 6;
-  const double* Lcol = L + b0 + min(i, nb - 1);
+  // products with later workgroups' rows: thread (column c of this
+  // workgroup, slice sl of 32 rows of each later 2 CB-row block)
+  const int c = t & (2 * CB - 1), sl = t >> 7;
+  const double* Lcol = L + R0 + min(c, nr - 1);
+  // thread (column i of a block, segment seg of 8 rows)
+  const int i = t >> 3, seg = t & 7;
+  double dA[8], dB[8], lBA[8];
+  {
+    // (L_AA^{-1})^T: entry (row seg * 8 + q, column i) of the inverse
+    const double* DA = dinv + (size_t)(2 * v * 2) * CB * CB + (seg * 8) * CB + i;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) dA[q] = DA[q * CB];
+    if (nB > 0) {
+      const double* DB = dinv + (size_t)((2 * v + 1) * 2) * CB * CB + (seg * 8) * CB + i;
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        dB[q] = DB[q * CB];
+        // L[R0 + CB + seg * 8 + q][R0 + i] (rows past the block clamped,
+        // weighted by x_B entries that are zero)
+        lBA[q] = L[(size_t)(R0 + CB + min(seg * 8 + q, nB - 1)) * n + R0 + i];
+      }
+    }
+  }
   double a0 = 0.0, a1 = 0.0;
-  double lv[16];
+  double lv[32];
   auto load_l = [&](int k) {
 #pragma unroll
-    for (int q = 0; q < 16; ++q) lv[q] = Lcol[(size_t)min(k * CB + sl * 16 + q, n - 1) * n];
+    for (int q = 0; q < 32; ++q) lv[q] = Lcol[(size_t)min(k * 2 * CB + sl * 32 + q, n - 1) * n];
   };
-  if (nblk - 1 > w) load_l(nblk - 1);
-  for (int k = nblk - 1; k > w; --k) {
-    double lc[16];
+  if (nwg - 1 > v) load_l(nwg - 1);
+  for (int k = nwg - 1; k > v; --k) {
+    double lc[32];
 #pragma unroll
-    for (int q = 0; q < 16; ++q) lc[q] = lv[q];
-    if (k - 1 > w) load_l(k - 1);
+    for (int q = 0; q < 32; ++q) lc[q] = lv[q];
+    if (k - 1 > v) load_l(k - 1);
     if (t == 0) blk_wait(flags + k, info);
     __syncthreads();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-    const int kr0 = k * CB + sl * 16;
-    if (i < nb) {
+    const int kr0 = k * 2 * CB + sl * 32;
+    if (c < nr) {
 #pragma unroll
-      for (int q = 0; q < 16; q += 2) {
+      for (int q = 0; q < 32; q += 2) {
         if (kr0 + q < n) a0 += lc[q] * x[kr0 + q];
         if (kr0 + q + 1 < n) a1 += lc[q + 1] * x[kr0 + q + 1];
       }
     }
   }
-  part[sl][i] = a0 + a1;
+  part[sl][c] = a0 + a1;
   __syncthreads();
-  if (t < CB) rv[t] = t < nb ? y[b0 + t] - ((part[0][t] + part[1][t]) + (part[2][t] + part[3][t])) : 0.0;
-  __syncthreads();
-  // x_block = L_kk^{-T} rv: thread (row r, slice sl)
-  const int r = t >> 2, s4 = t & 3;
-  double s0 = 0.0, s1 = 0.0;
+  if (nB > 0) {
+    if (t < CB) {
+      const int cb = CB + t;
+      rv[t] = t < nB ? y[R0 + cb] - ((part[0][cb] + part[1][cb]) + (part[2][cb] + part[3][cb])) : 0.0;
+    }
+    __syncthreads();
+    // x_B = L_BB^{-T} rv
+    double sb = 0.0;
 #pragma unroll
-  for (int j = 0; j < 16; j += 2) {
-    s0 += tri[s4 * 16 + j][r] * rv[s4 * 16 + j];
-    s1 += tri[s4 * 16 + j + 1][r] * rv[s4 * 16 + j + 1];
+    for (int q = 0; q < 8; ++q) sb += dB[q] * rv[seg * 8 + q];
+    sb = group_sum(sb, 8);
+    if (seg == 0) {
+      xs[i] = i < nB ? sb : 0.0;
+      if (i < nB) x[R0 + CB + i] = sb;
+    }
+    __syncthreads();
   }
-  double sacc = s0 + s1;
-  sacc = group_sum(sacc, 4);
-  if (s4 == 0 && r < nb) x[b0 + r] = sacc;
-  blk_publish(flags + w);
+  // block A: rv = y_A - (later workgroups) - L_BA^T x_B
+  {
+    double sacc = 0.0;
+    if (nB > 0) {
+#pragma unroll
+      for (int q = 0; q < 8; ++q) sacc += lBA[q] * xs[seg * 8 + q];
+    }
+    sacc = group_sum(sacc, 8);
+    if (seg == 0)
+      rv[i] = i < nA ? y[R0 + i] - ((part[0][i] + part[1][i]) + (part[2][i] + part[3][i])) - sacc : 0.0;
+  }
+  __syncthreads();
+  {
+    double sa = 0.0;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) sa += dA[q] * rv[seg * 8 + q];
+    sa = group_sum(sa, 8);
+    if (seg == 0 && i < nA) x[R0 + i] = sa;
+  }
+  blk_publish(flags + v);
 }
 
 }  // namespace dev

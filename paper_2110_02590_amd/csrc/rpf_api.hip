@@ -795,7 +795,8 @@ void spmm(rpf_grid* h, int nrows, const int32_t* ptr, const int32_t* col, const 
 }
 
 // step = -(L L^T)^{-1} rhs with the dense Cholesky factor L (row-major n x n,
-// lower triangle): one workgroup per block of CB rows in each direction.
+// lower triangle): one workgroup per two blocks of CB rows in each
+// direction.
 void chol_solve(rpf_grid* h, int n, const double* L, const double* rhs, double* step, int32_t* info,
                 hipStream_t s) {
   const int nblk = cdiv(n, CB);
@@ -804,9 +805,10 @@ void chol_solve(rpf_grid* h, int n, const double* L, const double* rhs, double* 
   // inverses of the diagonal blocks (skipped when the factorization failed)
   k_top_diag_inv<<<dim3(nblk, 1), 256, 0, s>>>(n, L, h->chol_dinv, 0, 0, nullptr, info);
   LAUNCHCHK();
-  k_chol_fwd<<<nblk, 256, 0, s>>>(n, L, h->chol_dinv, rhs, h->chol_work, h->chol_flags, info);
+  const int nwg = cdiv(n, 2 * CB);   // two blocks per workgroup
+  k_chol_fwd<<<nwg, 512, 0, s>>>(n, L, h->chol_dinv, rhs, h->chol_work, h->chol_flags, info);
   LAUNCHCHK();
-  k_chol_bwd<<<nblk, 256, 0, s>>>(n, L, h->chol_dinv, h->chol_work, step, h->chol_flags + nblk, info);
+  k_chol_bwd<<<nwg, 512, 0, s>>>(n, L, h->chol_dinv, h->chol_work, step, h->chol_flags + nblk, info);
   LAUNCHCHK();
 }
 
