@@ -1060,54 +1060,88 @@ __global__ void __launch_bounds__(256) k_pack_solve_s(const int32_t* __restrict_
   short* srow = (short*)(slev + nlev + 1);
   short* scol = srow + nr;
   const int t = threadIdx.x;
-  for (int eb = t; eb < ne; eb += 4 * blockDim.x) {
-    int ps[4];
-    int16_t cs[4];
+  const int bd = blockDim.x;
+  // staging: each pass issues all of a thread's loads (16 entries, or 4
+  // rows) before its stores, with addresses clamped into range
+  for (int eb = t; eb < ne; eb += 16 * bd) {
+    int ps[16];
+    int16_t cs[16];
 #pragma unroll
-    for (int m = 0; m < 4; ++m) {
-      const int e = min(eb + m * (int)blockDim.x, ne - 1);
+    for (int m = 0; m < 16; ++m) {
+      const int e = min(eb + m * bd, ne - 1);
       ps[m] = epos[e0 + e];
       cs[m] = ecol[e0 + e];
     }
-    double vs[4];
+    double vs[16];
 #pragma unroll
-    for (int m = 0; m < 4; ++m) vs[m] = val[ps[m]];
+    for (int m = 0; m < 16; ++m) vs[m] = val[ps[m]];
 #pragma unroll
-    for (int m = 0; m < 4; ++m) {
-      const int e = eb + m * (int)blockDim.x;
+    for (int m = 0; m < 16; ++m) {
+      const int e = eb + m * bd;
       if (e < ne) {
         sv[e] = vs[m];
         scol[e] = cs[m];
       }
     }
   }
-  for (int r = t; r <= nr; r += blockDim.x) srp[r] = rp[r0 + r] - e0;
-  for (int r = t; r < nr; r += blockDim.x) {
-    if (!UNIT) dg[r] = val[diag[r0 + r]];
-    srow[r] = (short)(lrows[base_row + r] - r0);
+  for (int rb = t; rb <= nr; rb += 4 * bd) {
+    int v[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) v[m] = rp[r0 + min(rb + m * bd, nr)];
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+      if (rb + m * bd <= nr) srp[rb + m * bd] = v[m] - e0;
   }
-  for (int k = t; k <= nlev; k += blockDim.x) slev[k] = lev[l0 + k] - base_row;
-  for (int e = t; e < nr * TW; e += blockDim.x) {
-    const int r = e / TW, c = e - r * TW;
-    const int i = r0 + r;
-    double acc = 0.0;
-    if (c0 + c < ncols) {
-      if (FWD) {
-        acc = scale * X[(size_t)i * ld + c0 + c];
-      } else {
-        // solved top rows: independent products, two partial sums
-        double a0 = 0.0, a1 = 0.0;
-        const int p1 = ptr[i + 1];
-        int p = up_split[i];
-        for (; p + 1 < p1; p += 2) {
-          a0 += val[p] * X[(size_t)col[p] * ld + c0 + c];
-          a1 += val[p + 1] * X[(size_t)col[p + 1] * ld + c0 + c];
-        }
-        if (p < p1) a0 += val[p] * X[(size_t)col[p] * ld + c0 + c];
-        acc = X[(size_t)i * ld + c0 + c] - (a0 + a1);
+  for (int rb = t; rb < nr; rb += 4 * bd) {
+    int di[4], lr[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const int r = min(rb + m * bd, nr - 1);
+      di[m] = UNIT ? 0 : diag[r0 + r];
+      lr[m] = lrows[base_row + r];
+    }
+    double dv[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) dv[m] = UNIT ? 1.0 : val[di[m]];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const int r = rb + m * bd;
+      if (r < nr) {
+        if (!UNIT) dg[r] = dv[m];
+        srow[r] = (short)(lr[m] - r0);
       }
     }
-    xs[e] = acc;
+  }
+  for (int k = t; k <= nlev; k += bd) slev[k] = lev[l0 + k] - base_row;
+  for (int eb = t; eb < nr * TW; eb += 4 * bd) {
+    double xv[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const int ec = min(eb + m * bd, nr * TW - 1);
+      const int r = ec / TW, c = ec - r * TW;
+      const int i = r0 + r;
+      double acc = 0.0;
+      if (c0 + c < ncols) {
+        if (FWD) {
+          acc = scale * X[(size_t)i * ld + c0 + c];
+        } else {
+          // solved top rows: independent products, two partial sums
+          double a0 = 0.0, a1 = 0.0;
+          const int p1 = ptr[i + 1];
+          int p = up_split[i];
+          for (; p + 1 < p1; p += 2) {
+            a0 += val[p] * X[(size_t)col[p] * ld + c0 + c];
+            a1 += val[p + 1] * X[(size_t)col[p + 1] * ld + c0 + c];
+          }
+          if (p < p1) a0 += val[p] * X[(size_t)col[p] * ld + c0 + c];
+          acc = X[(size_t)i * ld + c0 + c] - (a0 + a1);
+        }
+      }
+      xv[m] = acc;
+    }
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+      if (eb + m * bd < nr * TW) xs[eb + m * bd] = xv[m];
   }
   __syncthreads();
   // Level loop.  A level of nrow rows has nrow * TW (row, column) pairs; when
