@@ -200,10 +200,11 @@ int rpf_track_step(rpf_grid* grid, double* u, double* x, double* y, const double
 
 /* Kernel timing with HIP events recorded on the launch stream, per kernel
  * class: 0 batched triangular solves inside the independent subtree packs
- * (k_pack_solve_s, more than one right-hand side), 1 single right-hand-side
- * triangular solves (all parts), 2 LU refactorization, 3 sparse products of
- * the Hessian batches, 4 dense Cholesky kernels, 5 batched triangular solves
- * of the top (separator) rows (k_top_dense, more than one right-hand side).
+ * (more than one right-hand side), 1 single right-hand-side triangular
+ * solves (all parts), 2 LU refactorization, 3 sparse products of the
+ * Hessian batches, 4 dense Cholesky kernels, 5 batched triangular solves of
+ * the top (separator) rows (their pack contributions, the product with the
+ * top block's inverse, and the pack rows' products with the solved top).
  * rpf_profile_read waits for the recorded events, returns the summed
  * milliseconds and launch counts per class (host arrays [RPF_PROF_CLASSES])
  * and clears them when reset != 0. */
