@@ -38,3 +38,17 @@ def test_eval_point_inside_bounds():
 def test_directions_unit_columns():
     V = gridgen.directions(17, 5, 3)
     np.testing.assert_allclose(np.linalg.norm(V, axis=0), 1.0, rtol=1e-14)
+
+
+def test_fingerprints_match_stored():
+    """The generator's draws are pinned by the stored sha256 of every array
+    (tests/golden/grid_fingerprints.json, written by make_fingerprints.py)."""
+    import json
+    import os
+    here = os.path.join(os.path.dirname(__file__), "golden", "grid_fingerprints.json")
+    want = json.load(open(here))
+    for name in ["tiny10", "syn300", "syn2000", "syn9241"]:
+        assert gridgen.fingerprint(gridgen.grid(name)) == want[name], name
+    for seed in (100, 163):
+        g = gridgen.make_grid(gridgen.tracking_workload(seed))
+        assert gridgen.fingerprint(g) == want[f"tracking{seed}"], seed

@@ -379,3 +379,105 @@ def test_tracking_step_is_a_descent_direction():
     un, xn, yn, info = oracle.tracking_step(M, u, x, P.y, g["pd"], g["qd"], fac, P, lo, hi, delta=1e3)
     assert info["info"] == 0
     assert float(info["grad"] @ info["step"]) < 0
+
+
+# ------------------------------------------------------- inertia-control ladder
+def _rotated(eigs, seed=3):
+    """Q diag(eigs) Q^T with a random orthogonal Q: the eigenvalues, hence the
+    first positive definite rung of the shift ladder, are known exactly."""
+    rng = np.random.default_rng(seed)
+    Q, _ = np.linalg.qr(rng.standard_normal((len(eigs), len(eigs))))
+    return (Q * np.asarray(eigs, float)) @ Q.T
+
+
+def test_delta_ladder_positive_definite_needs_no_shift():
+    assert oracle.delta_ladder(np.diag([3.0, 1e-9, 2.0])) == 0.0
+    assert oracle.delta_ladder(_rotated([5.0, 0.5, 1e-3, 2.0])) == 0.0
+
+
+def test_delta_ladder_rung_from_the_eigenvalues():
+    """delta = 0, then base = 1e-8 max(1, max|diag K|), times 10 per failure:
+    the first rung above -lambda_min is returned.
+    diag(5, -2e-6, 1): base 5e-8, rungs 5e-8, 5e-7, 5e-6 -> 5e-6."""
+    d = oracle.delta_ladder(np.diag([5.0, -2e-6, 1.0]))
+    assert d == pytest.approx(5e-6, rel=1e-12)
+    # max|diag| below one: base = 1e-8; lambda_min = -3e-5 -> rung 1e-4
+    d = oracle.delta_ladder(np.diag([0.5, -3e-5, 0.25]))
+    assert d == pytest.approx(1e-4, rel=1e-12)
+    # rotated: eigenvalues (40, 7, -0.02, 1) -> max|diag K| unknown a priori,
+    # so recompute the base from the diagonal and count rungs by hand
+    K = _rotated([40.0, 7.0, -0.02, 1.0])
+    base = 1e-8 * max(1.0, float(np.max(np.abs(np.diag(K)))))
+    k = int(np.ceil(np.log10(0.02 / base) - 1e-12))
+    if base * 10.0 ** k <= 0.02:
+        k += 1
+    assert oracle.delta_ladder(K) == pytest.approx(base * 10.0 ** k, rel=1e-12)
+
+
+def test_delta_ladder_uses_the_symmetric_part():
+    """Only (H + H^T)/2 matters: a large skew part changes nothing."""
+    S = np.diag([2.0, -1e-3, 1.0])
+    A = np.array([[0.0, 50.0, -3.0], [-50.0, 0.0, 7.0], [3.0, -7.0, 0.0]])
+    assert oracle.delta_ladder(S + A) == oracle.delta_ladder(S)
+
+
+# ------------------------------------------- tracking: halving and failed step
+def test_tracking_step_halving_takes_the_first_converging_trial():
+    """With two Newton steps allowed per power flow, the full Newton step's
+    power flow fails and the step is halved (Section IV-C with the step-halving
+    safeguard): the accepted k is the first whose power flow converges within
+    pf_iters from the previous state, and u, x are that trial's."""
+    g, M, u, x, ep, lo, hi = _tracking_setup()
+    P = oracle.Point.from_dict(ep)
+    fac = np.ones(g["nb"])
+    pd, qd = g["pd"], g["qd"]
+    un, xn, yn, info = oracle.tracking_step(M, u, x, P.y, pd, qd, fac, P, lo, hi, delta=40.0, pf_iters=2)
+    k = info["accepted"]
+    assert k >= 1
+    ulo, uhi = M.u_bounds()
+    x0 = oracle.solve_pf(M, u, pd, qd, x0=x, max_iter=2, raise_on_fail=False).x
+    for j in range(k):
+        ut = np.clip(u + info["step"] / 2.0 ** j, ulo, uhi)
+        r = oracle.solve_pf(M, ut, pd, qd, x0=x0, max_iter=2, raise_on_fail=False)
+        assert not r.converged
+    np.testing.assert_array_equal(un, np.clip(u + info["step"] / 2.0 ** k, ulo, uhi))
+    assert np.linalg.norm(M.residual(xn, un, pd, qd)) < 1e-10
+    # more Newton steps let the full step through
+    un3, _, _, info3 = oracle.tracking_step(M, u, x, P.y, pd, qd, fac, P, lo, hi, delta=40.0, pf_iters=3)
+    assert info3["accepted"] == 0
+    np.testing.assert_array_equal(un3, np.clip(u + info3["step"], ulo, uhi))
+
+
+def test_tracking_step_no_trial_converges_keeps_u_and_x():
+    """One Newton step per power flow: no trial converges, so u and the state
+    stay at the first power flow's, and y is still updated at them."""
+    g, M, u, x, ep, lo, hi = _tracking_setup()
+    P = oracle.Point.from_dict(ep)
+    fac = np.ones(g["nb"])
+    un, xn, yn, info = oracle.tracking_step(M, u, x, P.y, g["pd"], g["qd"], fac, P, lo, hi, delta=10.0,
+                                            pf_iters=1)
+    assert info["accepted"] == -1
+    np.testing.assert_array_equal(un, u)
+    c = M.constraints(xn, un, g["pd"], g["qd"])
+    z = np.clip(c + P.y / (P.rho * P.sigma_c), lo, hi)
+    np.testing.assert_allclose(yn, P.y + P.rho * P.sigma_c * (c - z), rtol=0, atol=1e-12)
+
+
+def test_tracking_step_failed_cholesky_gives_zero_step():
+    """A shift too small for the indefinite reduced Hessian makes the Cholesky
+    fail (info > 0): the step is zero, the unchanged control is accepted at
+    k = 0, and only the multipliers move."""
+    g, M, u, x, ep, lo, hi = _tracking_setup()
+    P = oracle.Point.from_dict(ep)
+    fac = np.ones(g["nb"])
+    # the reduced Hessian at this point is indefinite: its smallest eigenvalue
+    # is below -1e-3, so the shift 1e-3 cannot make it positive definite
+    s = oracle.slack_minimiser(M.constraints(x, u, g["pd"], g["qd"]), P, lo, hi)
+    Pt = dataclasses.replace(P, s=s)
+    H = oracle.reduced_hessian(M, x, u, g["pd"], g["qd"], Pt)
+    assert np.linalg.eigvalsh(0.5 * (H + H.T)).min() < -1e-3
+    un, xn, yn, info = oracle.tracking_step(M, u, x, P.y, g["pd"], g["qd"], fac, P, lo, hi, delta=1e-3)
+    assert info["info"] > 0 and info["accepted"] == 0
+    assert not np.any(info["step"])
+    ulo, uhi = M.u_bounds()
+    np.testing.assert_array_equal(un, np.clip(u, ulo, uhi))
