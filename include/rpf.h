@@ -41,16 +41,23 @@
  *  - Pointers marked "device" are device memory on the current HIP device;
  *    "host" pointers are read during the call only.  The caller owns all
  *    buffers it passes; the handle owns its internal workspace.
- *  - Compute calls enqueue work on `stream` and return without waiting,
- *    except rpf_pf_solve, which reads the residual norm on the host after
- *    each Newton step (it synchronises the stream once per step).
+ *  - Compute calls enqueue work on `stream` and return without waiting;
+ *    none of them synchronises the host or allocates, so a sequence of them
+ *    can be captured into a HIP graph (rpf_profile_* timing is for eager
+ *    calls only).
  *  - Dense matrices are row-major.  A batch of vectors is an [n x nbatch]
  *    row-major block with leading dimension ld >= nbatch (element (i, k) at
  *    i * ld + k).
  *  - Return value: 0 on success, a negative RPF_E* code otherwise, with a
  *    message from rpf_last_error().  Numerical outcomes (power flow not
- *    converged, zero pivot, Cholesky failure) are reported in device status
- *    words, never as return codes.
+ *    converged, tiny pivot of J_x, Cholesky failure) are reported in device
+ *    status words, never as return codes.
+ *  - Tiny pivot word (static pivoting, Section V-A.1): the refactorization
+ *    of J_x keeps the pivots the host ordering fixed.  A sparse pivot with
+ *    |u_ii| <= 1e-14 max_j |a_ij| (row i before elimination), or a zero or
+ *    non-finite pivot of the dense top block, is reported as the 1-based
+ *    index in x of a failing pivot (0 = all pivots passed); the solves with
+ *    such a factor are not meaningful.
  *  - A handle is not thread-safe; use one handle per host thread / stream.
  */
 #ifndef RPF_H
@@ -114,14 +121,18 @@ int rpf_dims(const rpf_grid* grid, int32_t* nx, int32_t* nu, int32_t* m);
 int rpf_structure(const rpf_grid* grid, int64_t* out10);
 
 /* Newton-Raphson power flow at fixed control u and loads (Section III-A):
- * x_{k+1} = x_k - (grad_x g_k)^{-1} g_k, stopped when ||g||_2 < tol or after
- * max_iter steps.
+ * x_{k+1} = x_k - (grad_x g_k)^{-1} g_k, stopped when ||g||_2 < tol, when
+ * the residual is not finite, or after max_iter steps.
  *   u [n_u], pd [nb], qd [nb]: device, read only.
  *   x [n_x]: device, in: starting point, out: last iterate.
- *   status [2]: device int32, out: {Newton steps taken, converged (0/1)}.
+ *   max_iter: 0 .. 100.
+ *   status [3]: device int32, out: {Newton steps taken, converged (0/1),
+ *   tiny pivot word of the factorizations of this call}.
  *   resid [1]: device, out: ||g(x, u)||_2 at the returned x.
- * Leaves J_x of the last step factorized in the handle.  Synchronises the
- * stream once per Newton step to test convergence. */
+ * The loop runs on the device: max_iter predicated Newton steps are
+ * enqueued, and once the test is met every later kernel of the loop returns
+ * at once, so the call never waits for the device.  Leaves J_x of the last
+ * step factorized in the handle. */
 int rpf_pf_solve(rpf_grid* grid, const double* u, const double* pd, const double* qd, double* x,
                  double tol, int32_t max_iter, int32_t* status, double* resid, rpf_stream_t stream);
 
@@ -138,11 +149,15 @@ int rpf_al_objective(rpf_grid* grid, const double* x, const double* u, const dou
  * at x, then grad = d_u phi + lambda^T grad_u g.
  *   inputs as rpf_al_objective (device).
  *   grad [n_u], lambda [n_x] (x order): device, out.  lambda may be NULL.
+ *   info [1]: device int32, out, may be NULL: tiny pivot word of J_x's
+ *   factorization at x (nonzero: grad, lambda and the cached point are not
+ *   meaningful).
  * Caches the point (factorized J_x, J_u, the Lagrangian Hessian of
  * l = phi + lambda^T g, rank-one constraint terms) for the Hessian calls. */
 int rpf_reduced_gradient(rpf_grid* grid, const double* x, const double* u, const double* pd,
                          const double* qd, const double* s, const double* y, double rho,
-                         const double* sigma, double* grad, double* lambda, rpf_stream_t stream);
+                         const double* sigma, double* grad, double* lambda, int32_t* info,
+                         rpf_stream_t stream);
 
 /* Reduced Hessian-vector products at the cached point (Proposition 2):
  * for each column w of V: J_x z = -J_u w; J_x^T psi = -(K_xu w + K_xx z);
@@ -158,10 +173,11 @@ int rpf_reduced_hessian_batch(rpf_grid* grid, const double* V, int32_t nbatch, i
  * cached point: products with the identity in batches of `batch` columns
  * (0 = the library's choice, at most max_batch).  For max_batch >= 512 the
  * batches run concurrently on three streams owned by the handle, each with
- * its own workspace, forked from `stream` and joined back to it by events
- * (the call stays capturable in a graph).  RPF_HVP_STREAMS (1 .. 8, read
- * when the handle is created) sets the number of streams; 1 runs the
- * batches one after the other on `stream`. */
+ * its own workspace, forked from `stream` and joined back to it by events.
+ * RPF_HVP_STREAMS (1 .. 8, read when the handle is created) sets the number
+ * of streams; 1 runs the batches one after the other on `stream`.  While
+ * `stream` is being captured into a graph the batches run one after the
+ * other on `stream` (same results, bit for bit). */
 int rpf_reduced_hessian(rpf_grid* grid, double* H, int32_t batch, rpf_stream_t stream);
 
 /* Dense step (Section IV-B.2): K = (H + H^T)/2 + diag(d) + delta I is
@@ -190,9 +206,10 @@ int rpf_factor_solve(rpf_grid* grid, int32_t n, double* Kmat, const double* diag
  *   s = clip(c(u) + y / (rho sigma_c), s_lo, s_hi), y <- y + rho D_c (c - s).
  * u [n_u], x [n_x], y [m]: device, in/out.  pd0, qd0, load_factor [nb],
  * s_lo, s_hi [m], u_lo, u_hi [n_u], sigma [1 + m]: device, read.
- * status [4]: device int32 out {first power flow converged, accepted
+ * status [5]: device int32 out {first power flow converged, accepted
  * halving k (-1: none), Cholesky info, Newton steps of the first power
- * flow}.  Uses the handle's workspace (one step at a time per handle). */
+ * flow, tiny pivot word of the factorization behind the gradient and
+ * Hessian}.  Uses the handle's workspace (one step at a time per handle). */
 int rpf_track_step(rpf_grid* grid, double* u, double* x, double* y, const double* pd0, const double* qd0,
                    const double* load_factor, const double* s_lo, const double* s_hi, const double* u_lo,
                    const double* u_hi, double rho, const double* sigma, double delta, int32_t pf_iters,

@@ -55,7 +55,7 @@ def lib():
             "rpf_structure": [vp, i64p],
             "rpf_pf_solve": [vp, vp, vp, vp, vp, dbl, i32, vp, vp, vp],
             "rpf_al_objective": [vp, vp, vp, vp, vp, vp, vp, dbl, vp, vp, vp, vp],
-            "rpf_reduced_gradient": [vp, vp, vp, vp, vp, vp, vp, dbl, vp, vp, vp, vp],
+            "rpf_reduced_gradient": [vp, vp, vp, vp, vp, vp, vp, dbl, vp, vp, vp, vp, vp],
             "rpf_reduced_hessian_batch": [vp, vp, i32, i32, vp, i32, vp],
             "rpf_reduced_hessian": [vp, vp, i32, vp],
             "rpf_factor_solve": [vp, i32, vp, vp, dbl, vp, vp, vp, vp],
@@ -211,15 +211,16 @@ class Grid:
         return torch.empty(n, dtype=dtype or torch.float64, device="cuda")
 
     # --------------------------------------------------------------- calls
-    def pf_solve(self, u, pd, qd, x, tol=1e-10, max_iter=20):
+    def pf_solve(self, u, pd, qd, x, tol=1e-10, max_iter=20, status=None, resid=None):
         """Newton power flow; x is updated in place.  Returns (status, resid)
-        device tensors: status = (steps, converged)."""
+        device tensors: status = (steps, converged, tiny pivot: 1-based x
+        index or 0)."""
         torch = _torch()
-        status = self._empty(2, torch.int32)
-        resid = self._empty(1)
+        status = self._empty(3, torch.int32) if status is None else status
+        resid = self._empty(1) if resid is None else resid
         _check(lib().rpf_pf_solve(self._h, _dev(u, self.nu, "u"), _dev(pd, self.nb, "pd"),
                                   _dev(qd, self.nb, "qd"), _dev(x, self.nx, "x"), float(tol),
-                                  int(max_iter), _dev(status, 2, "status", torch.int32),
+                                  int(max_iter), _dev(status, 3, "status", torch.int32),
                                   _dev(resid, 1, "resid"), _stream()))
         return status, resid
 
@@ -233,14 +234,19 @@ class Grid:
                                       _dev(c, self.m, "c"), _stream()))
         return phi, c
 
-    def reduced_gradient(self, x, u, pd, qd, s, y, rho, sigma, grad=None, lam=None):
+    def reduced_gradient(self, x, u, pd, qd, s, y, rho, sigma, grad=None, lam=None, info=None):
+        """Proposition 1.  Returns (grad, lambda); `info` (int32 device
+        tensor [1]), when given, receives the tiny-pivot word of J_x's
+        factorization at x (1-based x index, 0 = none)."""
+        torch = _torch()
         grad = self._empty(self.nu) if grad is None else grad
         lam = self._empty(self.nx) if lam is None else lam
+        iptr = _dev(info, 1, "info", torch.int32) if info is not None else None
         _check(lib().rpf_reduced_gradient(self._h, _dev(x, self.nx, "x"), _dev(u, self.nu, "u"),
                                           _dev(pd, self.nb, "pd"), _dev(qd, self.nb, "qd"),
                                           _dev(s, self.m, "s"), _dev(y, self.m, "y"), float(rho),
                                           _dev(sigma, 1 + self.m, "sigma"), _dev(grad, self.nu, "grad"),
-                                          _dev(lam, self.nx, "lambda"), _stream()))
+                                          _dev(lam, self.nx, "lambda"), iptr, _stream()))
         return grad, lam
 
     def hessian_batch(self, V, HV=None):
@@ -263,16 +269,17 @@ class Grid:
                    pf_iters=6, max_halvings=4, tol=1e-10, status=None):
         """One device-resident tracking update; u, x, y updated in place.
         Returns the status tensor (first PF converged, accepted halving,
-        Cholesky info, Newton steps)."""
+        Cholesky info, Newton steps, tiny pivot of the factorization behind
+        the gradient and Hessian)."""
         torch = _torch()
-        status = self._empty(4, torch.int32) if status is None else status
+        status = self._empty(5, torch.int32) if status is None else status
         _check(lib().rpf_track_step(self._h, _dev(u, self.nu, "u"), _dev(x, self.nx, "x"), _dev(y, self.m, "y"),
                                     _dev(pd0, self.nb, "pd0"), _dev(qd0, self.nb, "qd0"),
                                     _dev(factor, self.nb, "factor"), _dev(s_lo, self.m, "s_lo"),
                                     _dev(s_hi, self.m, "s_hi"), _dev(u_lo, self.nu, "u_lo"),
                                     _dev(u_hi, self.nu, "u_hi"), float(rho), _dev(sigma, 1 + self.m, "sigma"),
                                     float(delta), int(pf_iters), int(max_halvings), float(tol),
-                                    _dev(status, 4, "status", torch.int32), _stream()))
+                                    _dev(status, 5, "status", torch.int32), _stream()))
         return status
 
     def factor_solve(self, K, rhs, diag=None, delta=0.0):

@@ -228,7 +228,8 @@ __global__ void k_reduce_final(int n, const double* __restrict__ in, double* __r
   if (threadIdx.x == 0) {
     double r = take_sqrt ? sqrt(red[0]) : red[0];
     out[0] = r;
-    if (done) done[0] = (r < tol) ? 1 : 0;
+    // done: 1 converged, 2 non-finite residual (diverged), 0 otherwise
+    if (done) done[0] = (r < tol) ? 1 : (isfinite(r) ? 0 : 2);
   }
 }
 
@@ -1786,13 +1787,30 @@ __global__ void k_axpy(int n, double a, const double* __restrict__ x, double* __
   if (i < n) y[i] += a * x[i];
 }
 
-__global__ void k_set_status(int32_t* __restrict__ st, int32_t it, int32_t conv,
-                             const double* __restrict__ rsrc, double* __restrict__ rdst) {
+// pivot words of the refactorizations (piv[0]: sparse rows, piv[1]: dense
+// top block; internal row + 1) as a 1-based index in the paper's x order,
+// 0 when every pivot passed
+__device__ __forceinline__ int32_t pivot_report(const int32_t* __restrict__ piv, const int32_t* __restrict__ x_i2p) {
+  const int32_t r = piv[0] != 0 ? piv[0] : piv[1];
+  return r > 0 ? x_i2p[r - 1] + 1 : 0;
+}
+
+// power-flow status {Newton steps, converged, tiny pivot} and residual
+__global__ void k_pf_status(int32_t* __restrict__ st, const int32_t* __restrict__ count,
+                            const int32_t* __restrict__ done, const int32_t* __restrict__ piv,
+                            const int32_t* __restrict__ x_i2p, const double* __restrict__ rsrc,
+                            double* __restrict__ rdst) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
-    st[0] = it;
-    st[1] = conv;
-    if (rdst) rdst[0] = rsrc[0];
+    st[0] = count[0];
+    st[1] = done[0] == 1 ? 1 : 0;
+    st[2] = pivot_report(piv, x_i2p);
+    rdst[0] = rsrc[0];
   }
+}
+
+__global__ void k_piv_report(const int32_t* __restrict__ piv, const int32_t* __restrict__ x_i2p,
+                             int32_t* __restrict__ out) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) out[0] = pivot_report(piv, x_i2p);
 }
 
 __global__ void k_fill_int(int n, int32_t* __restrict__ p, int32_t v) {
@@ -1875,13 +1893,15 @@ __global__ void k_accept(int n, const double* __restrict__ resid, double tol, in
 }
 
 // status of a tracking step: first power flow converged, accepted trial
-// (-1: none), Cholesky info, Newton steps of the first power flow
+// (-1: none), Cholesky info, Newton steps of the first power flow, tiny
+// pivot of the factorization behind the gradient and Hessian
 __global__ void k_track_status(const int32_t* __restrict__ f, int32_t* __restrict__ st) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
-    st[0] = f[5];
+    st[0] = f[5] == 1 ? 1 : 0;
     st[1] = f[3];
     st[2] = f[4];
     st[3] = f[6];
+    st[4] = f[7];
   }
 }
 

@@ -115,7 +115,6 @@ struct rpf_grid {
   int32_t* tflags;
   int32_t *flag, *piv_status;
   double* rdiag;   // 1 / u_ii of the refactorized rows [n_x]
-  double* host_resid;  // pinned
 
   int rf_waves = 16;
 
@@ -168,7 +167,6 @@ struct rpf_grid {
     if (ev_fork) (void)hipEventDestroy(ev_fork);
     for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
     for (void* p : allocs) (void)hipFree(p);
-    if (host_resid) (void)hipHostFree(host_resid);
   }
 };
 
@@ -502,7 +500,6 @@ void setup(rpf_grid* h) {
   h->flag = h->alloc<int32_t>(4);
   h->piv_status = h->alloc<int32_t>(4);
   h->rdiag = h->alloc<double>(P.nx);
-  HIPCHK(hipHostMalloc((void**)&h->host_resid, sizeof(double) * 4, hipHostMallocDefault));
 
   int maxrow = std::max(P.max_lu_row, 1);
   int waves = 16;
@@ -579,7 +576,9 @@ void refactor(rpf_grid* h, hipStream_t s, const int32_t* skip = nullptr) {
     const int ne = (int)P.top_pos.size();
     k_dense_xfer<<<cdiv(ne, 256), 256, 0, s>>>(ne, h->top_pos, h->top_dense, h->luv, h->dense_top, 1, skip);
     LAUNCHCHK();
-    dense_factor<false>(P.ntop, h->dense_top, h->piv_status, P.t0, s, skip);
+    // the dense top LU keeps its own word: a tiny pivot in the packs must not
+    // stop it (its kernels return early once their info word is set)
+    dense_factor<false>(P.ntop, h->dense_top, h->piv_status + 1, P.t0, s, skip);
     k_transpose<<<dim3(cdiv(P.ntop, 32), cdiv(P.ntop, 32)), dim3(32, 8), 0, s>>>(P.ntop, h->dense_top,
                                                                                  h->dense_topT, skip);
     LAUNCHCHK();
@@ -882,6 +881,38 @@ void hvp_batch(rpf_grid* h, const double* V, int ldv, int j0, int B, double* HV,
        ld, HV, ldhv, s);
 }
 
+// Newton power flow on h->xi with `iters` predicated steps and no host
+// synchronisation: done[0] is raised to 1 when ||g||_2 < tol (to 2 when the
+// residual is not finite) and every later kernel of the loop returns at
+// once; count[0] counts the steps taken and resid[0] holds the last
+// residual norm.  A nonzero done[0] on entry skips the whole solve.
+void pf_device(rpf_grid* h, const double* u, const double* pd, const double* qd, int iters, double tol,
+               int32_t* done, int32_t* count, double* resid, hipStream_t s) {
+  const Presolve& P = h->P;
+  const int nblk = cdiv(P.nx, 256);
+  // pivot words start clear for every power flow (the dense top LU skips
+  // its work while its word is set)
+  k_fill_int<<<1, 4, 0, s>>>(4, h->piv_status, 0);
+  LAUNCHCHK();
+  for (int k = 0; k <= iters; ++k) {
+    state_and_records(h, u, s, done);
+    k_residual<<<nblk, 256, 0, s>>>(P.nx, h->g_sp, h->g_s, h->rec, h->row_bus, h->row_isq, h->row_pvar, pd, qd, u,
+                                    h->g, h->partial, done);
+    LAUNCHCHK();
+    k_reduce_final<<<1, 1024, 0, s>>>(nblk, h->partial, resid, 1, tol, done, done);
+    LAUNCHCHK();
+    if (k == iters) break;
+    refactor(h, s, done);
+    k_copy_vec<<<nblk, 256, 0, s>>>(P.nx, h->g, h->d, done);
+    LAUNCHCHK();
+    solve_pair(h, false, h->d, 1, 1, 1.0, s, done);
+    k_axpy<<<nblk, 256, 0, s>>>(P.nx, -1.0, h->d, h->xi, done);
+    LAUNCHCHK();
+    k_count<<<1, 1, 0, s>>>(done, count);
+    LAUNCHCHK();
+  }
+}
+
 template <class F>
 int guard(F&& f) {
   try {
@@ -1064,40 +1095,19 @@ int rpf_structure(const rpf_grid* h, int64_t* o) {
 int rpf_pf_solve(rpf_grid* h, const double* u, const double* pd, const double* qd, double* x, double tol,
                  int32_t max_iter, int32_t* status, double* resid, rpf_stream_t stream) {
   if (!h || !u || !pd || !qd || !x || !status || !resid) return set_err(RPF_EINVAL, "NULL argument");
-  if (max_iter < 0) return set_err(RPF_EINVAL, "max_iter must be >= 0");
+  if (max_iter < 0 || max_iter > 100) return set_err(RPF_EINVAL, "max_iter must be in [0, 100]");
   return guard([&]() -> int {
     hipStream_t s = (hipStream_t)stream;
     const Presolve& P = h->P;
     h->have_point = false;
     x_in(h, x, s);
-    int it = 0, conv = 0;
-    const int nblk = cdiv(P.nx, 256);
-    k_fill_int<<<1, 4, 0, s>>>(4, h->piv_status, 0);
-    for (;;) {
-      state_and_records(h, u, s);
-      k_residual<<<nblk, 256, 0, s>>>(P.nx, h->g_sp, h->g_s, h->rec, h->row_bus, h->row_isq, h->row_pvar, pd,
-                                      qd, u, h->g, h->partial, nullptr);
-      LAUNCHCHK();
-      k_reduce_final<<<1, 1024, 0, s>>>(nblk, h->partial, h->resid_d, 1, tol, nullptr, nullptr);
-      LAUNCHCHK();
-      HIPCHK(hipMemcpyAsync(h->host_resid, h->resid_d, sizeof(double), hipMemcpyDeviceToHost, s));
-      HIPCHK(hipStreamSynchronize(s));
-      const double r = h->host_resid[0];
-      if (r < tol) {
-        conv = 1;
-        break;
-      }
-      if (!std::isfinite(r) || it >= max_iter) break;
-      refactor(h, s);
-      HIPCHK(hipMemcpyAsync(h->d, h->g, sizeof(double) * P.nx, hipMemcpyDeviceToDevice, s));
-      solve_pair(h, false, h->d, 1, 1, 1.0, s);
-      k_axpy<<<nblk, 256, 0, s>>>(P.nx, -1.0, h->d, h->xi, nullptr);
-      LAUNCHCHK();
-      ++it;
-    }
-    k_set_status<<<1, 1, 0, s>>>(status, it, conv, h->resid_d, resid);
+    // flag[0]: predication word of the Newton loop, flag[1]: steps taken
+    k_fill_int<<<1, 4, 0, s>>>(4, h->flag, 0);
     LAUNCHCHK();
-    k_permute_scatter<<<nblk, 256, 0, s>>>(P.nx, h->x_i2p, h->xi, x, nullptr);
+    pf_device(h, u, pd, qd, max_iter, tol, h->flag, h->flag + 1, h->resid_d, s);
+    k_pf_status<<<1, 1, 0, s>>>(status, h->flag + 1, h->flag, h->piv_status, h->x_i2p, h->resid_d, resid);
+    LAUNCHCHK();
+    k_permute_scatter<<<cdiv(P.nx, 256), 256, 0, s>>>(P.nx, h->x_i2p, h->xi, x, nullptr);
     LAUNCHCHK();
     return RPF_OK;
   });
@@ -1217,46 +1227,22 @@ void gradient_core(rpf_grid* h, const double* u, const double* pd, const double*
   h->have_point = true;
 }
 
-// Newton power flow on h->xi with `iters` predicated steps and no host
-// synchronisation: done[0] is raised when ||g||_2 < tol and every later
-// kernel of the loop returns at once; count[0] counts the steps taken and
-// resid[0] holds the last residual norm.  A nonzero done[0] on entry skips
-// the whole solve.
-void pf_device(rpf_grid* h, const double* u, const double* pd, const double* qd, int iters, double tol,
-               int32_t* done, int32_t* count, double* resid, hipStream_t s) {
-  const Presolve& P = h->P;
-  const int nblk = cdiv(P.nx, 256);
-  for (int k = 0; k <= iters; ++k) {
-    state_and_records(h, u, s, done);
-    k_residual<<<nblk, 256, 0, s>>>(P.nx, h->g_sp, h->g_s, h->rec, h->row_bus, h->row_isq, h->row_pvar, pd, qd, u,
-                                    h->g, h->partial, done);
-    LAUNCHCHK();
-    k_reduce_final<<<1, 1024, 0, s>>>(nblk, h->partial, resid, 1, tol, done, done);
-    LAUNCHCHK();
-    if (k == iters) break;
-    refactor(h, s, done);
-    k_copy_vec<<<nblk, 256, 0, s>>>(P.nx, h->g, h->d, done);
-    LAUNCHCHK();
-    solve_pair(h, false, h->d, 1, 1, 1.0, s, done);
-    k_axpy<<<nblk, 256, 0, s>>>(P.nx, -1.0, h->d, h->xi, done);
-    LAUNCHCHK();
-    k_count<<<1, 1, 0, s>>>(done, count);
-    LAUNCHCHK();
-  }
-}
-
 }  // namespace
 
 extern "C" {
 
 int rpf_reduced_gradient(rpf_grid* h, const double* x, const double* u, const double* pd, const double* qd,
                          const double* sv, const double* y, double rho, const double* sigma, double* grad,
-                         double* lambda, rpf_stream_t stream) {
+                         double* lambda, int32_t* info, rpf_stream_t stream) {
   if (!h || !x || !u || !pd || !qd || !sv || !y || !sigma || !grad) return set_err(RPF_EINVAL, "NULL argument");
   return guard([&]() -> int {
     hipStream_t s = (hipStream_t)stream;
     x_in(h, x, s);
     gradient_core(h, u, pd, qd, sv, y, rho, sigma, grad, lambda, s);
+    if (info) {
+      k_piv_report<<<1, 1, 0, s>>>(h->piv_status, h->x_i2p, info);
+      LAUNCHCHK();
+    }
     return RPF_OK;
   });
 }
@@ -1282,7 +1268,11 @@ int rpf_reduced_hessian(rpf_grid* h, double* H, int32_t batch, rpf_stream_t stre
     int B = batch == 0 ? std::min(h->max_batch, nu) : std::min<int>(batch, std::min(h->max_batch, nu));
     hipStream_t s = (hipStream_t)stream;
     const int nbt = cdiv(nu, B);
-    const int nst = std::min(h->nhs, nbt);
+    // one stream while `stream` is being captured into a graph: the fork
+    // onto the handle's streams is not used under capture
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    HIPCHK(hipStreamIsCapturing(s, &cap));
+    const int nst = cap == hipStreamCaptureStatusNone ? std::min(h->nhs, nbt) : 1;
     if (nst <= 1) {
       for (int j0 = 0; j0 < nu; j0 += B) hvp_batch(h, nullptr, 0, j0, std::min(B, nu - j0), H + j0, nu, s);
     } else {
@@ -1360,6 +1350,8 @@ int rpf_track_step(rpf_grid* h, double* u, double* x, double* y, const double* p
     LAUNCHCHK();
     // 3. reduced gradient and Hessian at (u, s, y)
     gradient_core(h, u, h->pdt, h->qdt, h->scur, y, rho, sigma, h->gradbuf, nullptr, s);
+    k_piv_report<<<1, 1, 0, s>>>(h->piv_status, h->x_i2p, h->tflags + 7);
+    LAUNCHCHK();
     const int B = std::min(h->max_batch, nu);
     for (int j0 = 0; j0 < nu; j0 += B) hvp_batch(h, nullptr, 0, j0, std::min(B, nu - j0), h->Hbuf + j0, nu, s);
     // 4. step = -(H + delta I)^{-1} grad (zero when the factorization fails)

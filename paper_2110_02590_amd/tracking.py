@@ -49,7 +49,7 @@ class _Inst:
         lo, hi = pr.u_bounds()
         self.u_lo = torch.tensor(lo, device=dev)
         self.u_hi = torch.tensor(hi, device=dev)
-        self.status = torch.zeros(4, dtype=torch.int32, device=dev)
+        self.status = torch.zeros(5, dtype=torch.int32, device=dev)
         self.delta = self._shift(item)
 
     def _shift(self, item) -> float:

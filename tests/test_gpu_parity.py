@@ -76,12 +76,12 @@ def test_power_flow(name):
     st, res = pr.grid.pf_solve(pr.u0, pr.pd, pr.qd, x)
     torch.cuda.synchronize()
     o = c.oracle("pf")
-    assert int(st[1]) == 1 and float(res) < 1e-10
+    assert int(st[1]) == 1 and float(res) < 1e-10 and int(st[2]) == 0
     assert abs(int(st[0]) - o.iters) <= 1
     assert _rel(x.cpu().numpy(), o.x) < 1e-12
 
 
-@pytest.mark.parametrize("name", SMALL)
+@pytest.mark.parametrize("name", SMALL + ["syn9241"])
 def test_al_objective(name):
     c = case(name)
     pr = c.pr
@@ -144,24 +144,61 @@ def test_random_directions_linear():
 
 
 @pytest.mark.parametrize("max_batch", [512, 1024])
-def test_largest_workload_sampled_columns(max_batch):
-    """9241-bus grid: full reduced Hessian on the GPU, sampled columns
-    against the oracle's adjoint-adjoint products, symmetry at full size.
-    512 is the benchmark's launch configuration (six batches, the last one
-    329 columns, on three streams)."""
+def test_largest_workload_full_hessian(max_batch):
+    """9241-bus grid: all 2889 columns of the reduced Hessian against the
+    oracle's Schur form Z^T (grad^2 l) Z within 1e-9 relative Frobenius error
+    (Proposition 2).  512 is the benchmark's launch configuration (six
+    batches, the last one 329 columns, on three streams); 1024 gives three
+    batches, the last one 841 columns.  Every column is also compared on
+    its own, so that no batch can hide behind the whole matrix's norm."""
     c = case("syn9241", max_batch=max_batch)
     c.gpu_point()
     H = c.pr.grid.reduced_hessian(batch=max_batch)
     torch.cuda.synchronize()
     Hg = H.cpu().numpy()
-    cols = np.array([0, 1, 2, 777, 1444, 1445, 2000, 2888])
-    W = np.zeros((c.M.nu, cols.size))
-    W[cols, np.arange(cols.size)] = 1.0
-    x = c.oracle("pf").x
-    lam = c.oracle("grad")[1]
-    Ho = oracle.hvp_adjoint_adjoint(c.M, x, c.u, c.g["pd"], c.g["qd"], c.P, lam, W)
-    assert _rel(Hg[:, cols], Ho) < 1e-9
+    Ho = c.oracle("H")
+    assert _rel(Hg, Ho) < 1e-9
+    colerr = np.linalg.norm(Hg - Ho, axis=0) / np.maximum(np.linalg.norm(Ho, axis=0), 1e-300)
+    assert colerr.max() < 1e-8, (int(colerr.argmax()), float(colerr.max()))
+    for j0 in range(0, c.M.nu, max_batch):
+        blk = slice(j0, min(j0 + max_batch, c.M.nu))
+        assert _rel(Hg[:, blk], Ho[:, blk]) < 1e-9, j0
     assert np.linalg.norm(Hg - Hg.T) <= 1e-11 * np.linalg.norm(Hg)
+
+
+def test_singular_jacobian_is_reported():
+    """A state with v = 0 at a PQ bus makes the theta column of that bus in
+    J_x exactly zero (every term of dS/dtheta_i carries v_i), so the static
+    pivot of theta_i is zero.  The power flow must stop unconverged and
+    report that pivot; the reduced gradient reports it in its info word
+    (Section V-A.1: refactorization with the presolve's pivots)."""
+    c = case("syn300", max_batch=64)
+    pr = c.pr
+    M = c.M
+    k = 5
+    x0 = c.oracle("pf").x.copy()
+    x0[M.npv + M.npq + k] = 0.0
+    ith = M.npv + k                       # x index of theta at that bus
+    Jx, _ = M.jacobians(x0, c.u)
+    assert abs(Jx.tocsc()[:, ith]).sum() == 0.0
+    x = torch.tensor(x0, device="cuda")
+    st, res = pr.grid.pf_solve(pr.u0, pr.pd, pr.qd, x, max_iter=10)
+    torch.cuda.synchronize()
+    st = st.cpu().numpy()
+    assert st[1] == 0 and st[2] == ith + 1, st
+    assert not np.isfinite(float(res)) or float(res) >= 1e-10
+    s, y, rho, sigma = pr.point(c.ep)
+    info = torch.full((1,), -7, dtype=torch.int32, device="cuda")
+    pr.grid.reduced_gradient(torch.tensor(x0, device="cuda"), pr.u0, pr.pd, pr.qd, s, y, rho, sigma, info=info)
+    torch.cuda.synchronize()
+    assert int(info) == ith + 1
+    # a regular point right after: the words start clear again
+    x = pr.flat_x()
+    st, res = pr.grid.pf_solve(pr.u0, pr.pd, pr.qd, x)
+    pr.grid.reduced_gradient(x, pr.u0, pr.pd, pr.qd, s, y, rho, sigma, info=info)
+    torch.cuda.synchronize()
+    assert int(st[1]) == 1 and int(st[2]) == 0 and int(info) == 0
+    assert _rel(x.cpu().numpy(), c.oracle("pf").x) < 1e-12
 
 
 def test_factor_solve_matches_lapack():

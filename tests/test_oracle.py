@@ -481,3 +481,24 @@ def test_tracking_step_failed_cholesky_gives_zero_step():
     assert not np.any(info["step"])
     ulo, uhi = M.u_bounds()
     np.testing.assert_array_equal(un, np.clip(u, ulo, uhi))
+
+
+def test_zero_voltage_makes_the_jacobian_singular():
+    """Every entry of the theta_i column of J_x carries v_i (dS_k/dtheta_i =
+    j v_k v_i conj(Y_ki) e^{j(theta_k - theta_i)} and dS_i/dtheta_i likewise),
+    so v_i = 0 at a PQ bus zeroes that column: J_x is singular and Newton's
+    step is undefined; the oracle reports a failed power flow."""
+    import warnings
+    g = gridgen.grid("syn300")
+    M, u, x, P = _setup(g)
+    k = 5
+    x0 = x.copy()
+    x0[M.npv + M.npq + k] = 0.0
+    Jx, _ = M.jacobians(x0, u)
+    col = Jx.tocsc()[:, M.npv + k]
+    assert col.nnz == 0 or abs(col).sum() == 0.0
+    assert np.linalg.matrix_rank(Jx.toarray()) == M.nx - 1
+    with warnings.catch_warnings():
+        warnings.simplefilter("ignore")
+        r = oracle.solve_pf(M, u, g["pd"], g["qd"], x0=x0, raise_on_fail=False)
+    assert not r.converged
