@@ -193,6 +193,21 @@ int rpf_reduced_hessian(rpf_grid* grid, double* H, int32_t batch, rpf_stream_t s
 int rpf_factor_solve(rpf_grid* grid, int32_t n, double* Kmat, const double* diag, double delta,
                      const double* rhs, double* step, int32_t* info, rpf_stream_t stream);
 
+/* rpf_factor_solve without a handle and without any allocation, for
+ * callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc).  Same arguments,
+ * kernels and results as rpf_factor_solve (bit for bit), for
+ * 1 <= n <= RPF_NOALLOC_MAX_N; larger n returns RPF_ESIZE.  Its scratch
+ * (about 4.2 MB: inverses of the factor's diagonal blocks, the forward
+ * solve vector, block flags) is a static device array, one per GPU, held
+ * until the process ends; the flags are cleared by a kernel at every call.
+ * Every call on one GPU shares that array: calls that overlap on one GPU
+ * (concurrent streams or host threads) race and must be serialised by the
+ * caller. */
+#define RPF_NOALLOC_MAX_N 4096
+int rpf_factor_solve_noalloc(int32_t n, double* Kmat, const double* diag, double delta, const double* rhs,
+                             double* step, int32_t* info, rpf_stream_t stream);
+
 /* One real-time tracking update at new loads (Section IV-C, steps 1-3),
  * entirely on the device with no host synchronisation (capturable in a HIP
  * graph).  The bounded QP of step 2 is replaced by one shifted Newton step:

@@ -59,6 +59,7 @@ def lib():
             "rpf_reduced_hessian_batch": [vp, vp, i32, i32, vp, i32, vp],
             "rpf_reduced_hessian": [vp, vp, i32, vp],
             "rpf_factor_solve": [vp, i32, vp, vp, dbl, vp, vp, vp, vp],
+            "rpf_factor_solve_noalloc": [i32, vp, vp, dbl, vp, vp, vp, vp],
             "rpf_presolve_info": [vp, i64p],
             "rpf_profile_enable": [vp, i32],
             "rpf_track_step": [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, dbl, vp, dbl, i32, i32, dbl, vp, vp],
@@ -79,6 +80,22 @@ def lib():
 def _check(rc: int):
     if rc != RPF_OK:
         raise RpfError(rc, lib().rpf_last_error().decode())
+
+
+NOALLOC_MAX_N = 4096   # RPF_NOALLOC_MAX_N
+
+
+def factor_solve_noalloc(K, rhs, step, info, diag=None, delta=0.0):
+    """rpf_factor_solve_noalloc: the dense step without a handle and without
+    allocation.  K [n, n] (in: H, out: L in the lower triangle), rhs [n],
+    step [n] (out), info int32 [1] (out), diag [n] or None: caller-owned
+    device tensors."""
+    torch = _torch()
+    n = int(K.shape[0])
+    dptr = _dev(diag, n, "diag") if diag is not None else None
+    _check(lib().rpf_factor_solve_noalloc(n, _dev(K, n * n, "K"), dptr, float(delta), _dev(rhs, n, "rhs"),
+                                          _dev(step, n, "step"), _dev(info, 1, "info", torch.int32),
+                                          _stream()))
 
 
 class _HostDesc:

@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <stdexcept>
 #include <string>
 #include <vector>
@@ -796,19 +797,38 @@ void spmm(rpf_grid* h, int nrows, const int32_t* ptr, const int32_t* col, const 
 // step = -(L L^T)^{-1} rhs with the dense Cholesky factor L (row-major n x n,
 // lower triangle): one workgroup per two blocks of CB rows in each
 // direction.
-void chol_solve(rpf_grid* h, int n, const double* L, const double* rhs, double* step, int32_t* info,
-                hipStream_t s) {
+// Scratch: flags [2 cdiv(n, CB)] (cleared here by a kernel), dinv
+// [cdiv(n, CB) 2 CB CB], work [n].
+void chol_solve_ws(int n, const double* L, const double* rhs, double* step, int32_t* info, int32_t* flags,
+                   double* dinv, double* work, hipStream_t s) {
   const int nblk = cdiv(n, CB);
-  k_fill_int<<<cdiv(2 * nblk, 256), 256, 0, s>>>(2 * nblk, h->chol_flags, 0);
+  k_fill_int<<<cdiv(2 * nblk, 256), 256, 0, s>>>(2 * nblk, flags, 0);
   LAUNCHCHK();
   // inverses of the diagonal blocks (skipped when the factorization failed)
-  k_top_diag_inv<<<dim3(nblk, 1), 256, 0, s>>>(n, L, h->chol_dinv, 0, 0, nullptr, info);
+  k_top_diag_inv<<<dim3(nblk, 1), 256, 0, s>>>(n, L, dinv, 0, 0, nullptr, info);
   LAUNCHCHK();
   const int nwg = cdiv(n, 2 * CB);   // two blocks per workgroup
-  k_chol_fwd<<<nwg, 512, 0, s>>>(n, L, h->chol_dinv, rhs, h->chol_work, h->chol_flags, info);
+  k_chol_fwd<<<nwg, 512, 0, s>>>(n, L, dinv, rhs, work, flags, info);
   LAUNCHCHK();
-  k_chol_bwd<<<nwg, 512, 0, s>>>(n, L, h->chol_dinv, h->chol_work, step, h->chol_flags + nblk, info);
+  k_chol_bwd<<<nwg, 512, 0, s>>>(n, L, dinv, work, step, flags + nblk, info);
   LAUNCHCHK();
+}
+
+void chol_solve(rpf_grid* h, int n, const double* L, const double* rhs, double* step, int32_t* info,
+                hipStream_t s) {
+  chol_solve_ws(n, L, rhs, step, info, h->chol_flags, h->chol_dinv, h->chol_work, s);
+}
+
+// The dense step K = (K + K^T)/2 + diag + delta I = L L^T, step = -K^{-1} rhs,
+// on `s` with the given triangular-solve scratch.
+void factor_solve_ws(int n, double* K, const double* diag, double delta, const double* rhs, double* step,
+                     int32_t* info, int32_t* flags, double* dinv, double* work, hipStream_t s) {
+  k_fill_int<<<1, 1, 0, s>>>(1, info, 0);
+  LAUNCHCHK();
+  k_symmetrize<<<dim3(cdiv(n, 32), cdiv(n, 32)), dim3(32, 8), 0, s>>>(n, K, diag, delta);
+  LAUNCHCHK();
+  dense_factor<true>(n, K, info, 0, s);
+  chol_solve_ws(n, K, rhs, step, info, flags, dinv, work, s);
 }
 
 ALArgs al_args(rpf_grid* h, const double* u, const double* pd, const double* qd, const double* s,
@@ -1299,13 +1319,8 @@ int rpf_factor_solve(rpf_grid* h, int32_t n, double* K, const double* diag, doub
   if (n < 1 || n > h->P.nu) return set_err(RPF_EINVAL, "n must be in [1, n_u]");
   return guard([&]() -> int {
     hipStream_t s = (hipStream_t)stream;
-    k_fill_int<<<1, 1, 0, s>>>(1, info, 0);
-    LAUNCHCHK();
     size_t pi = h->prof_on ? h->prof_begin(s) : 0;
-    k_symmetrize<<<dim3(cdiv(n, 32), cdiv(n, 32)), dim3(32, 8), 0, s>>>(n, K, diag, delta);
-    LAUNCHCHK();
-    dense_factor<true>(n, K, info, 0, s);
-    chol_solve(h, n, K, rhs, step, info, s);
+    factor_solve_ws(n, K, diag, delta, rhs, step, info, h->chol_flags, h->chol_dinv, h->chol_work, s);
     if (h->prof_on) h->prof_end(4, pi, s);
     return RPF_OK;
   });
@@ -1399,3 +1414,58 @@ int rpf_track_step(rpf_grid* h, double* u, double* x, double* y, const double* p
 }
 
 }  // extern "C"
+
+// ------------------------------------------------- no-allocation dense step
+// Scratch of rpf_factor_solve_noalloc in a static device array (one copy per
+// GPU, held until the process ends): the inverses of the diagonal blocks
+// [cdiv(n, CB) 2 CB CB], the forward-solve vector [n] and the block flags
+// [2 cdiv(n, CB)] int32, for n <= RPF_NOALLOC_MAX_N.
+namespace {
+constexpr int kNoallocBlocks = RPF_NOALLOC_MAX_N / CB;
+constexpr size_t kNoallocDinv = (size_t)kNoallocBlocks * 2 * CB * CB;
+constexpr size_t kNoallocWork = RPF_NOALLOC_MAX_N;
+constexpr size_t kNoallocFlags = 2 * kNoallocBlocks;   // int32 words
+constexpr size_t kNoallocDoubles = kNoallocDinv + kNoallocWork + (kNoallocFlags + 1) / 2;
+static_assert(RPF_NOALLOC_MAX_N % CB == 0, "maximum order must be a multiple of the block width");
+}  // namespace
+
+static __device__ __align__(256) double scratch[kNoallocDoubles];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+// device address of `scratch` on the current device, looked up once per
+// device (the array's host-side name is not a device address)
+double* noalloc_scratch() {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) throw std::runtime_error("device index out of range");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) throw HipError("hipGetSymbolAddress returned a null address for the scratch array");
+    g_scratch_ptr[dev] = (double*)p;
+  }
+  return g_scratch_ptr[dev];
+}
+}  // namespace
+
+extern "C" int rpf_factor_solve_noalloc(int32_t n, double* K, const double* diag, double delta, const double* rhs,
+                                        double* step, int32_t* info, rpf_stream_t stream) {
+  if (!K || !rhs || !step || !info) return set_err(RPF_EINVAL, "NULL argument");
+  if (n < 1) return set_err(RPF_EINVAL, "n must be >= 1");
+  if (n > RPF_NOALLOC_MAX_N)
+    return set_err(RPF_ESIZE, "n = " + std::to_string(n) + " above the scratch limit RPF_NOALLOC_MAX_N = " +
+                                  std::to_string(RPF_NOALLOC_MAX_N));
+  return guard([&]() -> int {
+    double* base = noalloc_scratch();
+    double* dinv = base;
+    double* work = base + kNoallocDinv;
+    int32_t* flags = reinterpret_cast<int32_t*>(work + kNoallocWork);
+    factor_solve_ws(n, K, diag, delta, rhs, step, info, flags, dinv, work, (hipStream_t)stream);
+    return RPF_OK;
+  });
+}
