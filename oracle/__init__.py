@@ -5,13 +5,14 @@ baseline import this package.  It shares no code with the GPU library and
 imports nothing from it; its only input module is ``gridgen``.
 
 It computes the plain definitions of the method (power-flow solution,
-augmented-Lagrangian value, reduced gradient, reduced Hessian, Cholesky
-step) with SciPy/NumPy: bus-wise complex admittance formulas, SuperLU, the
+augmented-Lagrangian value, reduced gradient, reduced Jacobian of the
+constraints, reduced Hessian, Cholesky step) with SciPy/NumPy: bus-wise complex admittance formulas, SuperLU, the
 dense Schur-complement form of the reduced Hessian, a textbook Cholesky.
 Pins for each function are in the ``-m "not gpu"`` tests.
 """
 from .model import Model, term_hessian, PQ, PV, REF
 from .reduced import (PFResult, Point, PowerFlowError, al_objective, cholesky_lower,
                       delta_ladder, factor_solve, full_gradient, hvp_adjoint_adjoint,
-                      lagrangian_hessian_full, reduced_gradient, reduced_hessian,
+                      lagrangian_hessian_full, reduced_gradient, reduced_hessian, reduced_jacobian,
                       slack_minimiser, solve_pf, tracking_step)
+from .rtqp import box_qp_ipm, kkt_error, qp_data, rt_step_qp, tracking_step_qp

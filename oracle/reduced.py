@@ -8,6 +8,8 @@ baseline of the benchmark, never by the product path.
   eq. (projection:newtonraphson), stopping rule of Section V-A.1.
 * AL value with scalings: Section IV-A.1 (L_rho) and IV-A.2 (sigma_f, D_c).
 * Reduced gradient by the adjoint: Proposition 1, eq. (reduced_gradient).
+* Reduced Jacobian of the constraints by the direct (forward) sensitivities:
+  Section III-C.
 * Reduced Hessian: the dense Schur-complement form Z^T (grad^2 l) Z with
   Z = [-J_x^{-1} J_u; I], which equals Proposition 2's adjoint-adjoint
   products column by column (eq. hessvecprod, eq. socadjoint).
@@ -202,6 +204,16 @@ def reduced_hessian(M: Model, x, u, pd, qd, P: Point, lam=None, return_parts=Fal
     if return_parts:
         return H, dict(S=S, Hxx=Hxx, Hxu=Hxu, Hux=Hux, Huu=Huu, Jx=Jx, Ju=Ju)
     return H
+
+
+def reduced_jacobian(M: Model, x, u):
+    """Reduced Jacobian of the constraints, grad_u c(x(u), u) = (d_x c) S +
+    d_u c with the sensitivity S = dx/du = -J_x^{-1} J_u (Section III-C,
+    reduced Jacobian), dense [m, n_u]."""
+    Jc = M.constraint_jac_full(x, u).tocsc()
+    Jx, Ju = M.jacobians(x, u)
+    S = -spla.splu(Jx.tocsc()).solve(Ju.toarray())
+    return Jc[:, M.ix] @ S + Jc[:, M.iu].toarray()
 
 
 def hvp_adjoint_adjoint(M: Model, x, u, pd, qd, P: Point, lam, W):

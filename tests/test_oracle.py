@@ -502,3 +502,123 @@ def test_zero_voltage_makes_the_jacobian_singular():
         warnings.simplefilter("ignore")
         r = oracle.solve_pf(M, u, g["pd"], g["qd"], x0=x0, raise_on_fail=False)
     assert not r.converged
+
+
+# ------------------------------------------------------------ reduced Jacobian
+def test_reduced_jacobian_vs_central_differences():
+    """grad_u c(x(u), u) against central differences of c along every control,
+    with the power flow re-solved at u +- h e_i (h = 1e-6 max(1, |u_i|))."""
+    g = gridgen.grid("tiny10")
+    M, u, x, P = _setup(g, tol=1e-13)
+    J = oracle.reduced_jacobian(M, x, u)
+    assert J.shape == (M.m, M.nu)
+    for i in range(M.nu):
+        h = 1e-6 * max(1.0, abs(u[i]))
+        e = np.zeros(M.nu)
+        e[i] = h
+        cp = M.constraints(oracle.solve_pf(M, u + e, g["pd"], g["qd"], x0=x, tol=1e-14).x, u + e, g["pd"], g["qd"])
+        cm = M.constraints(oracle.solve_pf(M, u - e, g["pd"], g["qd"], x0=x, tol=1e-14).x, u - e, g["pd"], g["qd"])
+        fd = (cp - cm) / (2 * h)
+        assert np.linalg.norm(J[:, i] - fd) <= 1e-6 * max(1.0, np.linalg.norm(fd)), i
+
+
+@pytest.mark.parametrize("name", ["tiny10", "syn300"])
+def test_reduced_jacobian_transpose_is_the_adjoint_gradient(name):
+    """With sigma_f = 0 and rho = 0, phi = y^T D_c (c - s), so its reduced
+    gradient by the adjoint (Proposition 1: one transposed solve) must equal
+    J^T D_c y from the direct sensitivities (n_u forward solves)."""
+    g = gridgen.grid(name)
+    M, u, x, P = _setup(g)
+    P0 = dataclasses.replace(P, sigma_f=0.0, rho=0.0)
+    grad, _ = oracle.reduced_gradient(M, x, u, g["pd"], g["qd"], P0)
+    J = oracle.reduced_jacobian(M, x, u)
+    want = J.T @ (P.sigma_c * P.y)
+    assert np.linalg.norm(grad - want) <= 1e-11 * np.linalg.norm(want)
+
+
+def test_reduced_jacobian_state_rows_are_sensitivity_rows():
+    """v at a PQ bus is a state, so its row of the reduced Jacobian is that
+    state's row of dx/du = -J_x^{-1} J_u (here from spsolve, not SuperLU's
+    factor object)."""
+    g = gridgen.grid("syn300")
+    M, u, x, P = _setup(g)
+    J = oracle.reduced_jacobian(M, x, u)
+    Jx, Ju = M.jacobians(x, u)
+    S = -spla.spsolve(Jx.tocsc(), Ju.toarray())
+    o = 2 * M.nl
+    np.testing.assert_allclose(J[o:o + M.npq], S[M.npv + M.npq:], rtol=0, atol=1e-12)
+
+
+# ------------------------------------------------ real-time QP (interior point)
+def _rt_qp_case(name, seed=7):
+    g = gridgen.grid(name)
+    M, u, x, P = _setup(g, seed=seed)
+    lo, hi = gridgen.constraint_bounds(g)
+    s = np.clip(M.constraints(x, u, g["pd"], g["qd"]), lo, hi)
+    Pt = dataclasses.replace(P, s=s)
+    H = oracle.reduced_hessian(M, x, u, g["pd"], g["qd"], Pt)
+    J = oracle.reduced_jacobian(M, x, u)
+    Huu = 0.5 * (H + H.T) - P.rho * (J.T * P.sigma_c ** 2) @ J
+    delta = 1.5 * max(0.0, -float(np.linalg.eigvalsh(Huu).min())) + 1e-2
+    return g, M, u, x, P, s, lo, hi, delta
+
+
+@pytest.mark.parametrize("name", ["tiny10", "syn300"])
+def test_rt_qp_matches_an_active_set_solver(name):
+    """The interior-point solution of the bounded QP of eq. (qp_rto) equals
+    the solution of the same strictly convex QP by scipy's bounded-variable
+    least squares (an active-set method): with Hw = R^T R,
+    g^T d + 1/2 d^T Hw d = 1/2 |R d + R^{-T} g|^2 + const."""
+    from scipy.optimize import lsq_linear
+    import scipy.linalg as sla
+    g, M, u, x, P, s, lo, hi, delta = _rt_qp_case(name)
+    ulo, uhi = M.u_bounds()
+    du, ds, info = oracle.rt_step_qp(M, u, s, x, P.y, g["pd"], g["qd"], P, ulo, uhi, lo, hi, delta, tol=1e-14,
+                                     iters=60)
+    Hw, gw, l, h = info["Hw"], info["g"], info["lo"], info["hi"]
+    R = np.linalg.cholesky(0.5 * (Hw + Hw.T)).T
+    ref = lsq_linear(R, -sla.solve_triangular(R.T, gw, lower=True), bounds=(l, h), method="bvls",
+                     tol=1e-15, max_iter=100000).x
+    d = np.concatenate([du, ds])
+    active = np.sum((ref <= l + 1e-12) | (ref >= h - 1e-12))
+    assert active > 0                         # bounds matter in this QP
+    assert np.linalg.norm(d - ref) <= 1e-9 * np.linalg.norm(ref)
+    assert info["iters"] <= 30
+
+
+def test_box_qp_closed_forms():
+    """Diagonal Hessian: the minimiser is the clipped Newton point
+    clip(-g_i / H_ii, lo_i, hi_i) coordinate by coordinate; a box that no
+    bound touches gives the unconstrained Newton step -Hw^{-1} g."""
+    rng = np.random.default_rng(5)
+    n = 40
+    hd = rng.uniform(0.5, 5.0, n)
+    gv = rng.standard_normal(n) * 3.0
+    lo = -rng.uniform(0.1, 1.0, n)
+    hi = rng.uniform(0.1, 1.0, n)
+    d, zl, zu, it = oracle.box_qp_ipm(np.diag(hd), gv, lo, hi, tol=1e-14, iters=80)
+    want = np.clip(-gv / hd, lo, hi)
+    assert np.max(np.abs(d - want)) <= 1e-10
+    A = rng.standard_normal((n, n))
+    Hw = A @ A.T / n + np.eye(n)
+    x0 = np.linalg.solve(Hw, -gv)
+    d, zl, zu, it = oracle.box_qp_ipm(Hw, gv, x0 - 10.0, x0 + 10.0, tol=1e-14, iters=80)
+    assert np.linalg.norm(d - x0) <= 1e-10 * np.linalg.norm(x0)
+
+
+def test_rt_qp_kkt_certificate_and_slack_coupling():
+    """At the interior-point solution the bound multipliers are non-negative,
+    complementary to the active bounds, and the s block of the stationarity
+    condition gives d_s in closed form from d_u (Proposition 3: the slack
+    direction depends linearly on the control direction)."""
+    g, M, u, x, P, s, lo, hi, delta = _rt_qp_case("syn300")
+    ulo, uhi = M.u_bounds()
+    du, ds, info = oracle.rt_step_qp(M, u, s, x, P.y, g["pd"], g["qd"], P, ulo, uhi, lo, hi, delta, tol=1e-13,
+                                     iters=60)
+    assert info["kkt"] < 1e-13 * 10
+    # inside the s box: rho D^2 (ds - J du) + g_s = 0 for the free slacks
+    c = M.constraints(x, u, g["pd"], g["qd"])
+    gs = -P.sigma_c * (P.y + P.rho * P.sigma_c * (c - s))
+    free = (ds > (lo - s) + 1e-7) & (ds < (hi - s) - 1e-7)
+    want = info["J"][free] @ du - gs[free] / (P.rho * P.sigma_c[free] ** 2)
+    np.testing.assert_allclose(ds[free], want, rtol=0, atol=1e-8 * max(1.0, np.abs(want).max()))
