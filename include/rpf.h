@@ -180,6 +180,15 @@ int rpf_reduced_hessian_batch(rpf_grid* grid, const double* V, int32_t nbatch, i
  * other on `stream` (same results, bit for bit). */
 int rpf_reduced_hessian(rpf_grid* grid, double* H, int32_t batch, rpf_stream_t stream);
 
+/* The dense reduced Hessian H [n_u x n_u] and/or the reduced Jacobian of the
+ * constraints J = grad_u c(x(u), u) = (d_x c) Z + d_u c [m x n_u] (Section
+ * III-C, reduced Jacobian; Z = -J_x^{-1} J_u) at the cached point, both
+ * row-major on the device (out), either may be NULL (not both).  J comes
+ * from the same batches of directions V = I as H, with no extra sparse
+ * solves; with H NULL only the first solve of each batch runs.  Batching,
+ * streams and capture behaviour as rpf_reduced_hessian. */
+int rpf_reduced_derivatives(rpf_grid* grid, double* H, double* J, int32_t batch, rpf_stream_t stream);
+
 /* Dense step (Section IV-B.2): K = (H + H^T)/2 + diag(d) + delta I is
  * factorized as L L^T (Cholesky), then step = -K^{-1} rhs.
  *   n: order; Kmat [n x n]: device, in: H, out: L in the lower triangle

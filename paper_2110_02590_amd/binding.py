@@ -58,6 +58,7 @@ def lib():
             "rpf_reduced_gradient": [vp, vp, vp, vp, vp, vp, vp, dbl, vp, vp, vp, vp, vp],
             "rpf_reduced_hessian_batch": [vp, vp, i32, i32, vp, i32, vp],
             "rpf_reduced_hessian": [vp, vp, i32, vp],
+            "rpf_reduced_derivatives": [vp, vp, vp, i32, vp],
             "rpf_factor_solve": [vp, i32, vp, vp, dbl, vp, vp, vp, vp],
             "rpf_factor_solve_noalloc": [i32, vp, vp, dbl, vp, vp, vp, vp],
             "rpf_presolve_info": [vp, i64p],
@@ -281,6 +282,18 @@ class Grid:
         H = self._empty(self.nu * self.nu).view(self.nu, self.nu) if H is None else H
         _check(lib().rpf_reduced_hessian(self._h, _dev(H, self.nu * self.nu, "H"), int(batch), _stream()))
         return H
+
+    def reduced_derivatives(self, batch=0, H=None, J=None, want_H=True, want_J=True):
+        """Dense reduced Hessian [n_u, n_u] and reduced constraint Jacobian
+        [m, n_u] at the cached point (either may be skipped)."""
+        if want_H and H is None:
+            H = self._empty(self.nu * self.nu).view(self.nu, self.nu)
+        if want_J and J is None:
+            J = self._empty(self.m * self.nu).view(self.m, self.nu)
+        hp = _dev(H, self.nu * self.nu, "H") if want_H else None
+        jp = _dev(J, self.m * self.nu, "J") if want_J else None
+        _check(lib().rpf_reduced_derivatives(self._h, hp, jp, int(batch), _stream()))
+        return (H if want_H else None), (J if want_J else None)
 
     def track_step(self, u, x, y, pd0, qd0, factor, s_lo, s_hi, u_lo, u_hi, rho, sigma, delta,
                    pf_iters=6, max_halvings=4, tol=1e-10, status=None):

@@ -1787,6 +1787,44 @@ __global__ void k_axpy(int n, double a, const double* __restrict__ x, double* __
   if (i < n) y[i] += a * x[i];
 }
 
+// Reduced Jacobian of the constraints for a batch of directions (Section
+// III-C): J[k][j0 + col] = grad c_k . D[:, col], with D = [Z; V] over all
+// variables (internal order), i.e. (d_x c) Z + d_u c.  Rows: h at the from
+// and to ends through the branch records (d|S|^2 = 2 (P dP + Q dQ) over
+// theta_f, theta_t, v_f, v_t), v at the PQ buses (a state row of D), and
+// p_ref, q_ref, q_pv from T = G D (the rank-one rows, rows of T in that
+// order).  Threads (64, 4): the batch's columns along the lanes.
+__global__ void k_cjac_batch(int nl, int npq, int m, int B, const int32_t* __restrict__ br_f,
+                             const int32_t* __restrict__ br_t, const int32_t* __restrict__ th_var,
+                             const int32_t* __restrict__ v_var, const int32_t* __restrict__ pq,
+                             const double* __restrict__ rec, const double* __restrict__ D, int ldd,
+                             const double* __restrict__ T, int ldt, double* __restrict__ J, int ldj, int j0) {
+  const int col = blockIdx.x * 64 + threadIdx.x;
+  const int k = blockIdx.y * 4 + threadIdx.y;
+  if (k >= m || col >= B) return;
+  double v;
+  if (k < 2 * nl) {
+    const int e = k >= nl ? 1 : 0;
+    const int l = k - e * nl;
+    const double* o = rec + (size_t)l * RECW;
+    const double P = o[2 * e], Q = o[2 * e + 1];
+    const double* dP = o + 4 + 8 * e;
+    const double* dQ = dP + 4;
+    const int f = br_f[l], t = br_t[l];
+    const int var[4] = {th_var[f], th_var[t], v_var[f], v_var[t]};
+    double acc = 0.0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      if (var[q] >= 0) acc += (P * dP[q] + Q * dQ[q]) * D[(size_t)var[q] * ldd + col];
+    v = 2.0 * acc;
+  } else if (k < 2 * nl + npq) {
+    v = D[(size_t)v_var[pq[k - 2 * nl]] * ldd + col];
+  } else {
+    v = T[(size_t)(k - 2 * nl - npq) * ldt + col];
+  }
+  J[(size_t)k * ldj + j0 + col] = v;
+}
+
 // pivot words of the refactorizations (piv[0]: sparse rows, piv[1]: dense
 // top block; internal row + 1) as a 1-based index in the paper's x order,
 // 0 when every pivot passed

@@ -866,8 +866,11 @@ void bus_injections(rpf_grid* h, hipStream_t s) {
 // One batch of reduced Hessian-vector products at the cached point.
 // V (ldv) or, when V is null, identity columns j0.. of the n_u identity.
 // Proposition 2 on one batch of directions, in workspace slot ws (D, Y, T).
+// With J (ldj), also the batch's columns j0 .. j0 + B of the reduced
+// Jacobian of the constraints from the same Z (no extra solves); with HV
+// null, only that (the adjoint half is skipped).
 void hvp_batch(rpf_grid* h, const double* V, int ldv, int j0, int B, double* HV, int ldhv, hipStream_t s,
-               int ws = 0) {
+               int ws = 0, double* J = nullptr, int ldj = 0) {
   const Presolve& P = h->P;
   const int ld = B;
   double* const D = h->Dk[ws];
@@ -889,6 +892,13 @@ void hvp_batch(rpf_grid* h, const double* V, int ldv, int j0, int B, double* HV,
   // Y = K [Z; V] + G^T diag(kappa) G [Z; V]
   // (T = G [Z; V] first; then both terms of Y in one pass over its rows)
   spmm(h, P.nr1, h->G_ptr, h->G_col, h->Gv, nullptr, nullptr, D, ld, B, 1.0, nullptr, 0, T, ld, s);
+  if (J) {
+    k_cjac_batch<<<dim3(cdiv(B, 64), cdiv(P.m, 4)), dim3(64, 4), 0, s>>>(P.nl, P.npq, P.m, B, h->br_f, h->br_t,
+                                                                       h->th_var, h->v_var, h->pq, h->rec, D, ld,
+                                                                       T, ld, J, ldj, j0);
+    LAUNCHCHK();
+  }
+  if (!HV) return;
   {
     const SpTerm Kt{h->K_ptr, h->K_col, h->Kv, nullptr, nullptr, D, ld};
     const SpTerm Gk{h->Gt_ptr, h->Gt_col, h->Gv, h->Gt_pos, h->kappa, T, ld};
@@ -1279,8 +1289,8 @@ int rpf_reduced_hessian_batch(rpf_grid* h, const double* V, int32_t nbatch, int3
   });
 }
 
-int rpf_reduced_hessian(rpf_grid* h, double* H, int32_t batch, rpf_stream_t stream) {
-  if (!h || !H) return set_err(RPF_EINVAL, "NULL argument");
+int rpf_reduced_derivatives(rpf_grid* h, double* H, double* J, int32_t batch, rpf_stream_t stream) {
+  if (!h || (!H && !J)) return set_err(RPF_EINVAL, "NULL argument: H and J are both NULL (or no grid)");
   if (!h->have_point) return set_err(RPF_ESTATE, "no cached point: call rpf_reduced_gradient first");
   if (batch < 0) return set_err(RPF_EINVAL, "batch must be >= 0");
   return guard([&]() -> int {
@@ -1294,15 +1304,17 @@ int rpf_reduced_hessian(rpf_grid* h, double* H, int32_t batch, rpf_stream_t stre
     HIPCHK(hipStreamIsCapturing(s, &cap));
     const int nst = cap == hipStreamCaptureStatusNone ? std::min(h->nhs, nbt) : 1;
     if (nst <= 1) {
-      for (int j0 = 0; j0 < nu; j0 += B) hvp_batch(h, nullptr, 0, j0, std::min(B, nu - j0), H + j0, nu, s);
+      for (int j0 = 0; j0 < nu; j0 += B)
+        hvp_batch(h, nullptr, 0, j0, std::min(B, nu - j0), H ? H + j0 : nullptr, nu, s, 0, J, nu);
     } else {
       // fork: batch b on internal stream b % nst with its own workspace;
-      // join back on the caller's stream (capturable: events only)
+      // join back on the caller's stream
       HIPCHK(hipEventRecord(h->ev_fork, s));
       for (int k = 0; k < nst; ++k) HIPCHK(hipStreamWaitEvent(h->hs[k], h->ev_fork, 0));
       for (int b = 0; b < nbt; ++b) {
         const int j0 = b * B;
-        hvp_batch(h, nullptr, 0, j0, std::min(B, nu - j0), H + j0, nu, h->hs[b % nst], b % nst);
+        hvp_batch(h, nullptr, 0, j0, std::min(B, nu - j0), H ? H + j0 : nullptr, nu, h->hs[b % nst], b % nst, J,
+                  nu);
       }
       for (int k = 0; k < nst; ++k) {
         HIPCHK(hipEventRecord(h->ev_join[k], h->hs[k]));
@@ -1311,6 +1323,11 @@ int rpf_reduced_hessian(rpf_grid* h, double* H, int32_t batch, rpf_stream_t stre
     }
     return RPF_OK;
   });
+}
+
+int rpf_reduced_hessian(rpf_grid* h, double* H, int32_t batch, rpf_stream_t stream) {
+  if (!h || !H) return set_err(RPF_EINVAL, "NULL argument");
+  return rpf_reduced_derivatives(h, H, nullptr, batch, stream);
 }
 
 int rpf_factor_solve(rpf_grid* h, int32_t n, double* K, const double* diag, double delta, const double* rhs,

@@ -166,6 +166,41 @@ def test_largest_workload_full_hessian(max_batch):
     assert np.linalg.norm(Hg - Hg.T) <= 1e-11 * np.linalg.norm(Hg)
 
 
+@pytest.mark.parametrize("name,batch", [("tiny10", 0), ("syn300", 64), ("syn2000", 256)])
+def test_reduced_jacobian(name, batch):
+    """grad_u c = (d_x c) Z + d_u c from the V = I batches (Section III-C)
+    against the oracle's direct sensitivities, and the Hessian of the same
+    call equal to rpf_reduced_hessian's bit for bit."""
+    c = case(name)
+    c.gpu_point()
+    H, J = c.pr.grid.reduced_derivatives(batch=batch)
+    H2 = c.pr.grid.reduced_hessian(batch=batch)
+    _, J2 = c.pr.grid.reduced_derivatives(batch=batch, want_H=False)
+    torch.cuda.synchronize()
+    Jo = oracle.reduced_jacobian(c.M, c.oracle("pf").x, c.u)
+    assert _rel(J.cpu().numpy(), Jo) < 1e-9
+    assert torch.equal(H, H2) and torch.equal(J, J2)
+
+
+def test_reduced_jacobian_largest_workload():
+    """The 41340 x 2889 reduced Jacobian of the 9241-bus grid in the
+    benchmark's launch configuration (batches of 512 on three streams),
+    together with the Hessian, against the oracle; per constraint block
+    (line flows, voltages, slack and PV reactive rows) as well."""
+    c = case("syn9241", max_batch=512)
+    c.gpu_point()
+    H, J = c.pr.grid.reduced_derivatives(batch=512)
+    torch.cuda.synchronize()
+    Jg = J.cpu().numpy()
+    del J
+    Jo = oracle.reduced_jacobian(c.M, c.oracle("pf").x, c.u)
+    assert _rel(Jg, Jo) < 1e-9
+    nl, npq = c.M.nl, c.M.npq
+    for a, b in [(0, 2 * nl), (2 * nl, 2 * nl + npq), (2 * nl + npq, c.M.m)]:
+        assert _rel(Jg[a:b], Jo[a:b]) < 1e-9, (a, b)
+    assert _rel(H.cpu().numpy(), c.oracle("H")) < 1e-9
+
+
 def test_singular_jacobian_is_reported():
     """A state with v = 0 at a PQ bus makes the theta column of that bus in
     J_x exactly zero (every term of dS/dtheta_i carries v_i), so the static
