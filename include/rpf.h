@@ -22,6 +22,10 @@
  *   rpf_factor_solve           Cholesky of the symmetrised, shifted reduced
  *                              Hessian and the resulting step (Section IV-B.2,
  *                              Proposition 3 and the inertia-control remark)
+ *   rpf_qp_step                exact real-time step: the bounded QP of eq.
+ *                              qp_rto by an interior-point method whose Newton
+ *                              systems go through the Schur complement of
+ *                              Proposition 3 (Section IV-B.2, IV-C)
  *
  * Variables and orderings (Section II-B, eq. statecontrol):
  *   u = (v_ref, v_pv, p_pv)            n_u = 1 + 2 n_pv
@@ -238,6 +242,47 @@ int rpf_track_step(rpf_grid* grid, double* u, double* x, double* y, const double
                    const double* load_factor, const double* s_lo, const double* s_hi, const double* u_lo,
                    const double* u_hi, double rho, const double* sigma, double delta, int32_t pf_iters,
                    int32_t max_halvings, double tol, int32_t* status, rpf_stream_t stream);
+
+/* Exact real-time step (Section IV-C, step 2): the bounded QP of eq.
+ * (qp_rto) in w = (u, s) at the point (x, u, s, y),
+ *   min_d g^T d + 1/2 d^T Hw d  subject to  w_lo - w <= d <= w_hi - w,
+ *   g  = (grad_u phi, -D_c (y + rho D_c (c - s))),
+ *   Hw = [[H + delta I, -rho J^T D_c^2], [-rho D_c^2 J, rho D_c^2]]
+ * (eq. gradient_auglag, eq. hessian_auglag with the scaling of Section
+ * IV-A.2; H the symmetrised reduced Hessian of phi at fixed s, J = grad_u c
+ * the reduced Jacobian).  The call first does what rpf_reduced_gradient
+ * does at (x, u, s, y), then forms H and J from the same identity batches
+ * (rpf_reduced_derivatives), then runs max_iter predicated iterations of a
+ * primal-dual interior-point method with Mehrotra's predictor-corrector
+ * (Section IV-B.1/2, eq. ipm_kkt_reduced): start d = clip(0, lo + k, hi - k)
+ * with k = 1e-2 (hi - lo), duals 1 / slack, steps stopped 0.995 of the way
+ * to the boundary; it stops once the scaled KKT error max(max|Hw d + g - z_l
+ * + z_u| / (1 + max|g|), max complementarity product) is below tol.  Each
+ * Newton system is solved through the Schur complement of Proposition 3
+ * (eq. schur_matrix): S = H_gn + Sigma_u + delta I, where H_gn is the
+ * reduced Hessian with each constraint's curvature weight rho sigma_k^2
+ * replaced by rho sigma_k^2 Sigma_s,k / (Sigma_s,k + rho sigma_k^2), formed
+ * by the batched Hessian-vector products, then its Cholesky factor.
+ *   x [n_x], u [n_u], pd/qd [nb], s/y [m], sigma [1 + m]: device, read.
+ *   u_lo, u_hi [n_u], s_lo, s_hi [m]: device, read (lo < hi).
+ *   batch: width of the Hessian batches (0 = the handle's).
+ *   H [n_u x n_u] (may be NULL: handle buffer), J [m x n_u]: device, out.
+ *   grad [n_u] (may be NULL): device, out: the reduced gradient.
+ *   dw [n_u + m]: device, out: the step (du, ds).
+ *   zw [2 (n_u + m)] (may be NULL): device, out: bound duals (z_l, z_u).
+ *   kkt [1] (may be NULL): device, out: the last KKT error.
+ *   status [5]: device int32, out: {iterations, converged (0/1), Cholesky
+ *   info of S (1-based column, -1 solve wait expired, 0), raw stop word
+ *   (0 running out of iterations, 1 converged, 2 non-finite, 16 + column
+ *   Cholesky failure, -1), tiny pivot word of J_x at x}.
+ * Leaves the point cached as rpf_reduced_gradient does (its own
+ * second-order data restored).  Uses the handle's workspace and three
+ * internal streams as rpf_reduced_hessian. */
+int rpf_qp_step(rpf_grid* grid, const double* x, const double* u, const double* pd, const double* qd,
+                const double* s, const double* y, double rho, const double* sigma, double delta,
+                const double* u_lo, const double* u_hi, const double* s_lo, const double* s_hi,
+                int32_t max_iter, double tol, int32_t batch, double* H, double* J, double* grad, double* dw,
+                double* zw, double* kkt, int32_t* status, rpf_stream_t stream);
 
 /* Kernel timing with HIP events recorded on the launch stream, per kernel
  * class: 0 batched triangular solves inside the independent subtree packs

@@ -1511,7 +1511,8 @@ __device__ __forceinline__ void spmm_row(const SpTerm& A, int i, int c0, int nco
 template <int CPT, bool TWO>
 __global__ void __launch_bounds__(256) k_spmm(int nrows, SpTerm A1, SpTerm A2, int ncols, double alpha, double alpha2,
                                               const double* __restrict__ Yadd, int ldya, double* __restrict__ Y,
-                                              int ldy) {
+                                              int ldy, const int32_t* __restrict__ skip) {
+  if (skip && *skip) return;
   const int i = __builtin_amdgcn_readfirstlane(blockIdx.y * 4 + (int)(threadIdx.x >> 6));
   if (i >= nrows) return;
   const int lane = threadIdx.x & 63;
@@ -1532,14 +1533,17 @@ __global__ void __launch_bounds__(256) k_spmm(int nrows, SpTerm A1, SpTerm A2, i
 }
 
 __global__ void k_copy_block(int n, int ncols, const double* __restrict__ src, int lds_,
-                             double* __restrict__ dst, int ldd) {
+                             double* __restrict__ dst, int ldd, const int32_t* __restrict__ skip = nullptr) {
+  if (skip && *skip) return;
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   const int i = blockIdx.y * blockDim.y + threadIdx.y;
   if (i < n && c < ncols) dst[(size_t)i * ldd + c] = src[(size_t)i * lds_ + c];
 }
 
 // identity columns j0 .. j0 + ncols - 1 of an n x n identity, as [n x ncols]
-__global__ void k_identity_block(int n, int ncols, int j0, double* __restrict__ dst, int ldd) {
+__global__ void k_identity_block(int n, int ncols, int j0, double* __restrict__ dst, int ldd,
+                                 const int32_t* __restrict__ skip = nullptr) {
+  if (skip && *skip) return;
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   const int i = blockIdx.y * blockDim.y + threadIdx.y;
   if (i < n && c < ncols) dst[(size_t)i * ldd + c] = (i == j0 + c) ? 1.0 : 0.0;
@@ -1608,11 +1612,16 @@ __global__ void k_constraints(ALArgs A, double* __restrict__ c, double* __restri
 
 // Weights of the bus injections in l = phi + lambda^T g: a_i on P_i and
 // b_i on Q_i (lambda may be null); threads past nb fill the rank-one
-// coefficients kappa of (p_ref, q_ref, q_pv).
+// coefficients kappa of (p_ref, q_ref, q_pv): the constraint's curvature
+// weight rho sigma_k^2, or gn[k] when gn is given (the Schur-complement
+// weights of the bounded QP), plus the slack's cost curvature for p_ref.
 __global__ void k_bus_weights(ALArgs A, const double* __restrict__ w, const double* __restrict__ lam,
                               const int32_t* __restrict__ rowP, const int32_t* __restrict__ rowQ,
                               const int32_t* __restrict__ bus_pvpos, double* __restrict__ a,
-                              double* __restrict__ b, double* __restrict__ kappa) {
+                              double* __restrict__ b, double* __restrict__ kappa,
+                              const double* __restrict__ gn = nullptr,
+                              const int32_t* __restrict__ skip = nullptr) {
+  if (skip && *skip) return;
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int kp = 2 * A.nl + A.npq;
   const double sigma_f = A.sigf[0];
@@ -1635,7 +1644,7 @@ __global__ void k_bus_weights(ALArgs A, const double* __restrict__ w, const doub
   } else if (i < A.nb + 2 + A.npv) {
     const int r = i - A.nb;
     const double sc = A.sigma_c[kp + r];
-    double kap = A.rho * sc * sc;
+    double kap = gn ? gn[kp + r] : A.rho * sc * sc;
     if (r == 0) kap += sigma_f * 2.0 * A.c2[A.gen_ref] * A.base * A.base;
     kappa[r] = kap;
   }
@@ -1646,14 +1655,17 @@ __global__ void k_bus_weights(ALArgs A, const double* __restrict__ w, const doub
 // local 4x4 Hessian W in (theta_f, theta_t, v_f, v_t):
 //   alpha_e = a + 2 w_h P_e, beta_e = b + 2 w_h Q_e,
 //   W = sum_e d2(alpha_e P_e + beta_e Q_e) + 2 w_h (dP dP^T + dQ dQ^T)
-//       + kappa_h dh dh^T,  dh = 2 P dP + 2 Q dQ,  kappa_h = rho sigma_h^2.
+//       + kappa_h dh dh^T,  dh = 2 P dP + 2 Q dQ,  kappa_h = rho sigma_h^2
+// (gn[k] instead when gn is given).
 __global__ void k_branch_second(int nl, const int32_t* __restrict__ bf, const int32_t* __restrict__ bt,
                                 const double* __restrict__ br, const double* __restrict__ bx,
                                 const double* __restrict__ bb, const double* __restrict__ th,
                                 const double* __restrict__ vm, const double* __restrict__ rec,
                                 const double* __restrict__ a, const double* __restrict__ b,
                                 const double* __restrict__ w, const double* __restrict__ sigma_c,
-                                double rho, double* __restrict__ wrec) {
+                                double rho, double* __restrict__ wrec, const double* __restrict__ gn = nullptr,
+                                const int32_t* __restrict__ skip = nullptr) {
+  if (skip && *skip) return;
   int l = blockIdx.x * blockDim.x + threadIdx.x;
   if (l >= nl) return;
   const int f = bf[l], t = bt[l];
@@ -1705,7 +1717,7 @@ __global__ void k_branch_second(int nl, const int32_t* __restrict__ bf, const in
     W[1][3] += -vf * Tp;
     W[2][3] += T;
     W[2 + e][2 + e] += 2.0 * K;
-    const double kap = rho * sh * sh;
+    const double kap = gn ? gn[kc] : rho * sh * sh;
     double dh[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
@@ -1764,16 +1776,19 @@ __global__ void k_var_grad(VarArgs V, const int32_t* __restrict__ ptr, const int
   out[c] = acc;
 }
 
-// Diagonal terms of K not carried by branches: rho sigma_v^2 on v_pq and
-// the PV cost curvature sigma_f 2 c2 B^2 on p_pv.
+// Diagonal terms of K not carried by branches: rho sigma_v^2 (gn[k] when
+// gn is given) on v_pq and the PV cost curvature sigma_f 2 c2 B^2 on p_pv.
 __global__ void k_k_diag(VarArgs V, const int32_t* __restrict__ kdiag, const double* __restrict__ sigma_c,
-                         double rho, double* __restrict__ kval) {
+                         double rho, double* __restrict__ kval, const double* __restrict__ gn = nullptr,
+                         const int32_t* __restrict__ skip = nullptr) {
+  if (skip && *skip) return;
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= V.nvar) return;
   const int kd = V.kind[c];
   if (kd == 1) {
-    const double sv = sigma_c[2 * V.nl + V.aux[c]];
-    kval[kdiag[c]] += rho * sv * sv;
+    const int k = 2 * V.nl + V.aux[c];
+    const double sv = sigma_c[k];
+    kval[kdiag[c]] += gn ? gn[k] : rho * sv * sv;
   } else if (kd == 3) {
     const int gi = V.pv_gen[V.aux[c]];
     kval[kdiag[c]] += V.sigf[0] * 2.0 * V.c2[gi] * V.base * V.base;
@@ -1954,7 +1969,9 @@ __global__ void k_zero_if(int n, const int32_t* __restrict__ info, double* __res
 // workgroup (32 x 8 threads) per pair of 32 x 32 tiles (block row bi >=
 // block column bj) and its mirror: both staged through LDS, so every global
 // access runs along rows.
-__global__ void k_symmetrize(int n, double* __restrict__ K, const double* __restrict__ d, double delta) {
+__global__ void k_symmetrize(int n, double* __restrict__ K, const double* __restrict__ d, double delta,
+                             const int32_t* __restrict__ skip = nullptr) {
+  if (skip && *skip) return;
   const int bj = blockIdx.x, bi = blockIdx.y;
   if (bj > bi) return;
   __shared__ double lo[32][33], up[32][33];

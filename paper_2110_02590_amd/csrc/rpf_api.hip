@@ -15,6 +15,7 @@
 
 #include "../../include/rpf.h"
 #include "kernels.hpp"
+#include "qp.hpp"
 #include "presolve.hpp"
 
 using namespace rpf;
@@ -96,6 +97,15 @@ struct rpf_grid {
   double *pkfv = nullptr, *pkbv = nullptr, *pkfvT = nullptr, *pkbvT = nullptr;
   size_t lds_limit = 65536, lds_pack[5] = {0, 0, 0, 0, 0};
   double *c2, *c1, *c0;
+  // predication word for the Hessian-product batches (set while the bounded
+  // QP assembles its Schur complements; null otherwise)
+  const int32_t* skipw = nullptr;
+  // bounded-QP workspace: [n] vectors (n = n_u + m), [m], [n_u], scalars,
+  // partial sums of the transposed products
+  double *qg, *qd_, *qtl, *qtu, *qzl, *qzu, *qsig, *qbase, *qdda, *qdzla, *qdzua, *qrhs, *qdd, *qdzl, *qdzu;
+  double *qcs, *qgn, *qts, *qJv, *qrneg, *qxu, *qHd, *qJt, *qscal, *qpart;
+  int32_t* qflags = nullptr;
+  int qparts = 64;
 
   // ------------------------------------------------------------ workspace
   double *xi, *th, *vm, *rec, *g, *partial, *resid_d, *d;
@@ -501,6 +511,20 @@ void setup(rpf_grid* h) {
   h->flag = h->alloc<int32_t>(4);
   h->piv_status = h->alloc<int32_t>(4);
   h->rdiag = h->alloc<double>(P.nx);
+  {
+    const size_t n = (size_t)P.nu + P.m;
+    double** vn[] = {&h->qg, &h->qd_, &h->qtl, &h->qtu, &h->qzl, &h->qzu, &h->qsig, &h->qbase, &h->qdda,
+                     &h->qdzla, &h->qdzua, &h->qrhs, &h->qdd, &h->qdzl, &h->qdzu};
+    for (double** v : vn) *v = h->alloc<double>(n);
+    double** vm[] = {&h->qcs, &h->qgn, &h->qts, &h->qJv};
+    for (double** v : vm) *v = h->alloc<double>(P.m);
+    double** vu[] = {&h->qrneg, &h->qxu, &h->qHd, &h->qJt};
+    for (double** v : vu) *v = h->alloc<double>(P.nu);
+    h->qscal = h->alloc<double>(QS_NSCAL);
+    h->qparts = std::max(1, std::min(64, cdiv(P.m, 256)));
+    h->qpart = h->alloc<double>((size_t)h->qparts * P.nu);
+    h->qflags = h->alloc<int32_t>(4);
+  }
 
   int maxrow = std::max(P.max_lu_row, 1);
   int waves = 16;
@@ -776,13 +800,17 @@ void spmm_terms(rpf_grid* h, int nrows, const SpTerm& A1, const SpTerm* A2, int 
   // two columns per lane once a row has more than one wavefront's worth
   const dim3 g2(cdiv(ncols, 128), cdiv(nrows, 4)), g1(cdiv(ncols, 64), cdiv(nrows, 4));
   if (ncols > 64 && A2)
-    k_spmm<2, true><<<g2, 256, 0, s>>>(nrows, A1, B2, ncols, alpha, 1.0, Yadd, ldya, Y, ldy);
+    k_spmm<2, true><<<g2, 256, 0, s>>>(nrows, A1, B2, ncols, alpha, 1.0, Yadd, ldya, Y, ldy,
+                                                 h->skipw);
   else if (ncols > 64)
-    k_spmm<2, false><<<g2, 256, 0, s>>>(nrows, A1, B2, ncols, alpha, 1.0, Yadd, ldya, Y, ldy);
+    k_spmm<2, false><<<g2, 256, 0, s>>>(nrows, A1, B2, ncols, alpha, 1.0, Yadd, ldya, Y, ldy,
+                                                 h->skipw);
   else if (A2)
-    k_spmm<1, true><<<g1, 256, 0, s>>>(nrows, A1, B2, ncols, alpha, 1.0, Yadd, ldya, Y, ldy);
+    k_spmm<1, true><<<g1, 256, 0, s>>>(nrows, A1, B2, ncols, alpha, 1.0, Yadd, ldya, Y, ldy,
+                                                 h->skipw);
   else
-    k_spmm<1, false><<<g1, 256, 0, s>>>(nrows, A1, B2, ncols, alpha, 1.0, Yadd, ldya, Y, ldy);
+    k_spmm<1, false><<<g1, 256, 0, s>>>(nrows, A1, B2, ncols, alpha, 1.0, Yadd, ldya, Y, ldy,
+                                                 h->skipw);
   LAUNCHCHK();
   if (h->prof_on) h->prof_end(3, pi, s);
 }
@@ -880,15 +908,15 @@ void hvp_batch(rpf_grid* h, const double* V, int ldv, int j0, int B, double* HV,
   double* Du = D + (size_t)P.nx * ld;
   dim3 blk(64, 4);
   if (V) {
-    k_copy_block<<<dim3(cdiv(B, 64), cdiv(P.nu, 4)), blk, 0, s>>>(P.nu, B, V, ldv, Du, ld);
+    k_copy_block<<<dim3(cdiv(B, 64), cdiv(P.nu, 4)), blk, 0, s>>>(P.nu, B, V, ldv, Du, ld, h->skipw);
   } else {
-    k_identity_block<<<dim3(cdiv(B, 64), cdiv(P.nu, 4)), blk, 0, s>>>(P.nu, B, j0, Du, ld);
+    k_identity_block<<<dim3(cdiv(B, 64), cdiv(P.nu, 4)), blk, 0, s>>>(P.nu, B, j0, Du, ld, h->skipw);
   }
   LAUNCHCHK();
   // R = -J_u V
   spmm(h, P.nx, h->ju_ptr, h->ju_col, h->juv, nullptr, nullptr, Du, ld, B, -1.0, nullptr, 0, Dx, ld, s);
   // Z = U^{-1} L^{-1} R
-  solve_pair(h, false, Dx, ld, B, 1.0, s);
+  solve_pair(h, false, Dx, ld, B, 1.0, s, h->skipw);
   // Y = K [Z; V] + G^T diag(kappa) G [Z; V]
   // (T = G [Z; V] first; then both terms of Y in one pass over its rows)
   spmm(h, P.nr1, h->G_ptr, h->G_col, h->Gv, nullptr, nullptr, D, ld, B, 1.0, nullptr, 0, T, ld, s);
@@ -905,7 +933,7 @@ void hvp_batch(rpf_grid* h, const double* V, int ldv, int j0, int B, double* HV,
     spmm_terms(h, P.nvar, Kt, &Gk, B, 1.0, nullptr, 0, Y, ld, s);
   }
   // Psi = -J_x^{-T} Y_x  (U^T then L^T)
-  solve_pair(h, true, Y, ld, B, -1.0, s);
+  solve_pair(h, true, Y, ld, B, -1.0, s, h->skipw);
   // HV = Y_u + J_u^T Psi
   spmm(h, P.nu, h->jut_ptr, h->jut_col, h->juv, h->jut_pos, nullptr, Y, ld, B, 1.0, Y + (size_t)P.nx * ld,
        ld, HV, ldhv, s);
@@ -1257,6 +1285,145 @@ void gradient_core(rpf_grid* h, const double* u, const double* pd, const double*
   h->have_point = true;
 }
 
+
+// H and/or J (row-major, n_u columns) from batches of identity directions at
+// the cached point; batch 0 = the handle's width.  Batches run on the
+// handle's streams (forked from s, joined back) unless s is being captured.
+void derivative_batches(rpf_grid* h, double* H, double* J, int batch, hipStream_t s) {
+  const int nu = h->P.nu;
+  const int B = batch == 0 ? std::min(h->max_batch, nu) : std::min<int>(batch, std::min(h->max_batch, nu));
+  const int nbt = cdiv(nu, B);
+  // one stream while `s` is being captured into a graph: the fork onto the
+  // handle's streams is not used under capture
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  HIPCHK(hipStreamIsCapturing(s, &cap));
+  const int nst = cap == hipStreamCaptureStatusNone ? std::min(h->nhs, nbt) : 1;
+  if (nst <= 1) {
+    for (int j0 = 0; j0 < nu; j0 += B)
+      hvp_batch(h, nullptr, 0, j0, std::min(B, nu - j0), H ? H + j0 : nullptr, nu, s, 0, J, nu);
+  } else {
+    // fork: batch b on internal stream b % nst with its own workspace;
+    // join back on the caller's stream
+    HIPCHK(hipEventRecord(h->ev_fork, s));
+    for (int k = 0; k < nst; ++k) HIPCHK(hipStreamWaitEvent(h->hs[k], h->ev_fork, 0));
+    for (int b = 0; b < nbt; ++b) {
+      const int j0 = b * B;
+      hvp_batch(h, nullptr, 0, j0, std::min(B, nu - j0), H ? H + j0 : nullptr, nu, h->hs[b % nst], b % nst, J, nu);
+    }
+    for (int k = 0; k < nst; ++k) {
+      HIPCHK(hipEventRecord(h->ev_join[k], h->hs[k]));
+      HIPCHK(hipStreamWaitEvent(s, h->ev_join[k], 0));
+    }
+  }
+}
+
+// Second-order data of the cached point (bus weights with lambda, branch
+// 4x4 blocks, K and its diagonal terms, rank-one coefficients) rebuilt with
+// the constraints' curvature weights gn [m] in place of rho sigma_k^2 (gn
+// null: the point's own weights).
+void second_order(rpf_grid* h, const ALArgs& A, const VarArgs& V, const double* gn, const double* sigma, double rho,
+                  hipStream_t s, const int32_t* skip) {
+  const Presolve& P = h->P;
+  const int nbw = cdiv(P.nb + 2 + P.npv, 256);
+  k_bus_weights<<<nbw, 256, 0, s>>>(A, h->wvec, h->lam, h->rowP, h->rowQ, h->bus_pvpos, h->a, h->b, h->kappa, gn,
+                                    skip);
+  LAUNCHCHK();
+  k_branch_second<<<cdiv(P.nl, 256), 256, 0, s>>>(P.nl, h->br_f, h->br_t, h->br_r, h->br_x, h->br_b, h->th, h->vm,
+                                                   h->rec, h->a, h->b, h->wvec, sigma + 1, rho, h->wrec, gn, skip);
+  LAUNCHCHK();
+  k_gather_sum<<<cdiv(P.K_col.size(), 256), 256, 0, s>>>((int)P.K_col.size(), h->K_sp, h->K_s, h->wrec, nullptr,
+                                                          h->Kv, skip);
+  LAUNCHCHK();
+  k_k_diag<<<cdiv(P.nvar, 256), 256, 0, s>>>(V, h->K_diag, sigma + 1, rho, h->Kv, gn, skip);
+  LAUNCHCHK();
+}
+
+// out = alpha A^T x + beta b (b may be null) for a row-major rows x cols A:
+// partial sums over qparts row chunks, then their sum in chunk order.
+void gemv_t(rpf_grid* h, const double* A, int rows, int cols, const double* x, double alpha, const double* b,
+            double beta, double* out, hipStream_t s, const int32_t* skip) {
+  const int R = h->qparts;
+  const int chunk = cdiv(rows, R);
+  k_gemv_cols_part<<<dim3(cdiv(cols, 256), R), 256, 0, s>>>(rows, cols, chunk, A, cols, x, h->qpart, skip);
+  LAUNCHCHK();
+  k_gemv_cols_sum<<<cdiv(cols, 256), 256, 0, s>>>(cols, R, h->qpart, alpha, b, beta, out, skip);
+  LAUNCHCHK();
+}
+
+QPVec qp_vec(rpf_grid* h, double rho, double delta, double tol, const double* sigma) {
+  QPVec Q;
+  Q.nu = h->P.nu; Q.m = h->P.m; Q.rho = rho; Q.delta = delta; Q.tol = tol;
+  Q.sigma_c = sigma + 1;
+  Q.g = h->qg; Q.d = h->qd_; Q.tl = h->qtl; Q.tu = h->qtu; Q.zl = h->qzl; Q.zu = h->qzu; Q.sig = h->qsig;
+  Q.cs = h->qcs; Q.gn = h->qgn; Q.base = h->qbase; Q.dda = h->qdda; Q.dzla = h->qdzla; Q.dzua = h->qdzua;
+  Q.rhs = h->qrhs; Q.dd = h->qdd; Q.dzl = h->qdzl; Q.dzu = h->qdzu; Q.ts = h->qts; Q.rneg = h->qrneg;
+  Q.xu = h->qxu; Q.Hd = h->qHd; Q.Jv = h->qJv; Q.Jt = h->qJt; Q.qs = h->qscal;
+  Q.done = h->qflags; Q.iters = h->qflags + 1;
+  return Q;
+}
+
+// Schur solve of (Hw + Sigma) x = b (Proposition 3) with S factorized in
+// Sf: xu = S^{-1} (b_u + rho J^T ts), Jv = J xu (ts = sigma^2 b_s / C is
+// already in Q.ts); the s part is formed by the next vector step.
+void qp_schur_solve(rpf_grid* h, const QPVec& Q, const double* J, const double* Sf, const double* b, hipStream_t s) {
+  const int nu = Q.nu, m = Q.m;
+  gemv_t(h, J, m, nu, Q.ts, -Q.rho, b, -1.0, Q.rneg, s, Q.done);
+  // chol_solve gives -S^{-1} rneg; its kernels return at once while done != 0
+  chol_solve(h, nu, Sf, Q.rneg, Q.xu, Q.done, s);
+  k_gemv_rows<<<cdiv(m, 4), 256, 0, s>>>(m, nu, J, nu, Q.xu, Q.Jv, Q.done);
+  LAUNCHCHK();
+}
+
+// Hw d pieces for the KKT test: Hd = H d_u, Jv = J d_u, Jt = J^T ts.
+void qp_kkt_products(rpf_grid* h, const QPVec& Q, const double* H, const double* J, hipStream_t s) {
+  const int nu = Q.nu, m = Q.m;
+  k_gemv_rows<<<cdiv(nu, 4), 256, 0, s>>>(nu, nu, H, nu, Q.d, Q.Hd, Q.done);
+  LAUNCHCHK();
+  k_gemv_rows<<<cdiv(m, 4), 256, 0, s>>>(m, nu, J, nu, Q.d, Q.Jv, Q.done);
+  LAUNCHCHK();
+  gemv_t(h, J, m, nu, Q.ts, 1.0, nullptr, 0.0, Q.Jt, s, Q.done);
+}
+
+// The bounded QP at the cached point (rpf_qp_step after its derivatives):
+// max_iter predicated predictor-corrector iterations, then a last KKT test.
+void qp_ipm(rpf_grid* h, const ALArgs& A, const VarArgs& V, const double* H, const double* J, double* Sbuf,
+            const double* u, const double* sv, const double* u_lo, const double* u_hi, const double* s_lo,
+            const double* s_hi, double rho, const double* sigma, double delta, int max_iter, double tol, int batch,
+            hipStream_t s) {
+  const int nu = h->P.nu;
+  const QPVec Q = qp_vec(h, rho, delta, tol, sigma);
+  k_qp_init<<<1, QP_NT, 0, s>>>(Q, u, sv, u_lo, u_hi, s_lo, s_hi, h->gradbuf, h->wvec);
+  LAUNCHCHK();
+  for (int it = 0; it <= max_iter; ++it) {
+    qp_kkt_products(h, Q, H, J, s);
+    k_qp_kkt<<<1, QP_NT, 0, s>>>(Q, it == max_iter ? 1 : 0);
+    LAUNCHCHK();
+    if (it == max_iter) break;
+    // S = H_gn + Sigma_u + delta I: the reduced Hessian with the Schur
+    // curvature weights, by the batched products (predicated), then Cholesky
+    h->skipw = Q.done;
+    try {
+      second_order(h, A, V, Q.gn, sigma, rho, s, Q.done);
+      derivative_batches(h, Sbuf, nullptr, batch, s);
+    } catch (...) {
+      h->skipw = nullptr;
+      throw;
+    }
+    h->skipw = nullptr;
+    k_symmetrize<<<dim3(cdiv(nu, 32), cdiv(nu, 32)), dim3(32, 8), 0, s>>>(nu, Sbuf, Q.sig, delta, Q.done);
+    LAUNCHCHK();
+    dense_factor<true>(nu, Sbuf, Q.done, QP_CHOL_BASE, s);
+    // predictor, then corrector with the same factor
+    qp_schur_solve(h, Q, J, Sbuf, Q.base, s);
+    k_qp_pred<<<1, QP_NT, 0, s>>>(Q);
+    LAUNCHCHK();
+    qp_schur_solve(h, Q, J, Sbuf, Q.rhs, s);
+    k_qp_corr<<<1, QP_NT, 0, s>>>(Q);
+    LAUNCHCHK();
+  }
+  // the point's own second-order data back for later Hessian products
+  second_order(h, A, V, nullptr, sigma, rho, s, nullptr);
+}
 }  // namespace
 
 extern "C" {
@@ -1294,33 +1461,7 @@ int rpf_reduced_derivatives(rpf_grid* h, double* H, double* J, int32_t batch, rp
   if (!h->have_point) return set_err(RPF_ESTATE, "no cached point: call rpf_reduced_gradient first");
   if (batch < 0) return set_err(RPF_EINVAL, "batch must be >= 0");
   return guard([&]() -> int {
-    const int nu = h->P.nu;
-    int B = batch == 0 ? std::min(h->max_batch, nu) : std::min<int>(batch, std::min(h->max_batch, nu));
-    hipStream_t s = (hipStream_t)stream;
-    const int nbt = cdiv(nu, B);
-    // one stream while `stream` is being captured into a graph: the fork
-    // onto the handle's streams is not used under capture
-    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
-    HIPCHK(hipStreamIsCapturing(s, &cap));
-    const int nst = cap == hipStreamCaptureStatusNone ? std::min(h->nhs, nbt) : 1;
-    if (nst <= 1) {
-      for (int j0 = 0; j0 < nu; j0 += B)
-        hvp_batch(h, nullptr, 0, j0, std::min(B, nu - j0), H ? H + j0 : nullptr, nu, s, 0, J, nu);
-    } else {
-      // fork: batch b on internal stream b % nst with its own workspace;
-      // join back on the caller's stream
-      HIPCHK(hipEventRecord(h->ev_fork, s));
-      for (int k = 0; k < nst; ++k) HIPCHK(hipStreamWaitEvent(h->hs[k], h->ev_fork, 0));
-      for (int b = 0; b < nbt; ++b) {
-        const int j0 = b * B;
-        hvp_batch(h, nullptr, 0, j0, std::min(B, nu - j0), H ? H + j0 : nullptr, nu, h->hs[b % nst], b % nst, J,
-                  nu);
-      }
-      for (int k = 0; k < nst; ++k) {
-        HIPCHK(hipEventRecord(h->ev_join[k], h->hs[k]));
-        HIPCHK(hipStreamWaitEvent(s, h->ev_join[k], 0));
-      }
-    }
+    derivative_batches(h, H, J, batch, (hipStream_t)stream);
     return RPF_OK;
   });
 }
@@ -1339,6 +1480,56 @@ int rpf_factor_solve(rpf_grid* h, int32_t n, double* K, const double* diag, doub
     size_t pi = h->prof_on ? h->prof_begin(s) : 0;
     factor_solve_ws(n, K, diag, delta, rhs, step, info, h->chol_flags, h->chol_dinv, h->chol_work, s);
     if (h->prof_on) h->prof_end(4, pi, s);
+    return RPF_OK;
+  });
+}
+
+int rpf_qp_step(rpf_grid* h, const double* x, const double* u, const double* pd, const double* qd, const double* sv,
+                const double* y, double rho, const double* sigma, double delta, const double* u_lo,
+                const double* u_hi, const double* s_lo, const double* s_hi, int32_t max_iter, double tol,
+                int32_t batch, double* H, double* J, double* grad, double* dw, double* zw, double* kkt,
+                int32_t* status, rpf_stream_t stream) {
+  if (!h || !x || !u || !pd || !qd || !sv || !y || !sigma || !u_lo || !u_hi || !s_lo || !s_hi || !J || !dw ||
+      !status)
+    return set_err(RPF_EINVAL, "NULL argument");
+  if (max_iter < 0 || max_iter > 500) return set_err(RPF_EINVAL, "max_iter must be in [0, 500]");
+  if (batch < 0) return set_err(RPF_EINVAL, "batch must be >= 0");
+  if (!(rho > 0.0)) return set_err(RPF_EINVAL, "rho must be positive");
+  return guard([&]() -> int {
+    hipStream_t s = (hipStream_t)stream;
+    const Presolve& P = h->P;
+    const int nu = P.nu, n = P.nu + P.m;
+    double* Hm = H ? H : h->Hbuf;
+    // 1. point: power-flow state x, reduced gradient, cached second-order data
+    x_in(h, x, s);
+    gradient_core(h, u, pd, qd, sv, y, rho, sigma, h->gradbuf, nullptr, s);
+    k_piv_report<<<1, 1, 0, s>>>(h->piv_status, h->x_i2p, h->qflags + 2);
+    LAUNCHCHK();
+    // 2. reduced Hessian and Jacobian from the same identity batches,
+    // H symmetrised
+    derivative_batches(h, Hm, J, batch, s);
+    k_symmetrize<<<dim3(cdiv(nu, 32), cdiv(nu, 32)), dim3(32, 8), 0, s>>>(nu, Hm, nullptr, 0.0);
+    LAUNCHCHK();
+    // 3. the QP
+    const ALArgs A = al_args(h, u, pd, qd, sv, y, rho, sigma);
+    const VarArgs V = var_args(h, u, sigma);
+    qp_ipm(h, A, V, Hm, J, h->Kbuf, u, sv, u_lo, u_hi, s_lo, s_hi, rho, sigma, delta, max_iter, tol, batch, s);
+    k_copy_vec<<<cdiv(n, 256), 256, 0, s>>>(n, h->qd_, dw, nullptr);
+    LAUNCHCHK();
+    if (zw) {
+      k_copy_vec<<<cdiv(n, 256), 256, 0, s>>>(n, h->qzl, zw, nullptr);
+      LAUNCHCHK();
+      k_copy_vec<<<cdiv(n, 256), 256, 0, s>>>(n, h->qzu, zw + n, nullptr);
+      LAUNCHCHK();
+    }
+    if (grad) {
+      k_copy_vec<<<cdiv(nu, 256), 256, 0, s>>>(nu, h->gradbuf, grad, nullptr);
+      LAUNCHCHK();
+    }
+    k_qp_status<<<1, 1, 0, s>>>(h->qflags, h->qflags + 1, h->qscal, status, kkt);
+    LAUNCHCHK();
+    k_copy_int<<<1, 1, 0, s>>>(h->qflags + 2, status + 4);
+    LAUNCHCHK();
     return RPF_OK;
   });
 }
