@@ -32,6 +32,15 @@ from .reduced import Point, reduced_gradient, reduced_hessian, reduced_jacobian,
 KAPPA = 1e-2
 MU0 = 1.0
 TAU = 0.995
+#: inertia control (Section IV-B.2: the regularisation keeps the Newton
+#: matrix positive definite): first regularisation REG_BASE * max(1, max
+#: |diag H_uu block|), raised REG_UP times per failed factorisation; an
+#: iteration starts from the last successful value / REG_DOWN (0 if it was
+#: 0); beyond REG_MAX the method gives up
+REG_BASE = 1e-4
+REG_UP = 8.0
+REG_DOWN = 4.0
+REG_MAX = 1e30
 
 
 def qp_data(H_red, J, grad_u, c, P: Point, delta):
@@ -45,14 +54,21 @@ def qp_data(H_red, J, grad_u, c, P: Point, delta):
     return g, Hw
 
 
-def box_qp_ipm(Hw, g, lo, hi, iters=50, tol=1e-10):
+def box_qp_ipm(Hw, g, lo, hi, iters=50, tol=1e-10, nreg=None):
     """min g^T d + 1/2 d^T Hw d subject to lo <= d <= hi (lo < hi), by a
     primal-dual interior-point method with Mehrotra's predictor-corrector.
 
     Slacks t_l = d - lo, t_u = hi - d and duals z_l, z_u stay positive; with
     Sigma = z_l / t_l + z_u / t_u every iteration solves (eq. ipm_kkt_reduced)
-      (Hw + Sigma) dd = -(Hw d + g) + r_l / t_l - r_u / t_u
-    twice with one factorization:
+      (Hw + Sigma + w P) dd = -(Hw d + g) + r_l / t_l - r_u / t_u
+    twice with one factorization, where P is the identity on the first nreg
+    variables (the controls) and zero elsewhere, and w the inertia-control
+    regularisation: with nreg given, each iteration factorizes by Cholesky,
+    first with w = 0 if the last successful w was 0, else max(w0, w_last /
+    REG_DOWN), then w0, then REG_UP w after each failure (w0 = REG_BASE
+    max(1, max |diag Hw[:nreg, :nreg]|)); every factorization attempt uses
+    one of the `iters` slots.  Without nreg (the default) w = 0 and any
+    nonsingular Hw + Sigma is solved by LU:
       predictor: r_l = r_u = 0, dz_l = -z_l - z_l/t_l dd, dz_u = -z_u + z_u/t_u dd;
         the largest steps to the boundary give the complementarity mu_a they
         would reach, and the centring target is mu = (mu_a / mu_c)^3 mu_c,
@@ -60,8 +76,10 @@ def box_qp_ipm(Hw, g, lo, hi, iters=50, tol=1e-10):
       corrector: r_l = mu - dd_a dz_la, r_u = mu + dd_a dz_ua,
         dz_l = r_l / t_l - z_l - z_l/t_l dd, dz_u = r_u / t_u - z_u + z_u/t_u dd.
     Primal and dual steps stop TAU of the way to the boundary.  Stops when
-    kkt_error < tol or after `iters` iterations.  Returns
-    (d, z_l, z_u, iterations)."""
+    kkt_error < tol or after `iters` slots.  Returns (d, z_l, z_u,
+    iterations) -- with nreg, (d, z_l, z_u, iterations, info) where info
+    holds the last w, the factorization attempts and `failed` (the
+    regularisation passed REG_MAX)."""
     Hw = np.asarray(Hw, float)
     g = np.asarray(g, float)
     lo = np.asarray(lo, float)
@@ -72,12 +90,32 @@ def box_qp_ipm(Hw, g, lo, hi, iters=50, tol=1e-10):
     tl, tu = d - lo, hi - d
     zl, zu = MU0 / tl, MU0 / tu
     it = 0
-    while it < iters:
-        if _kkt(Hw, g, d, zl, zu, tl, tu) < tol:
-            break
-        Sig = zl / tl + zu / tu
+    slots = 0
+    w0 = REG_BASE * max(1.0, float(np.max(np.abs(np.diag(Hw)[:nreg])))) if nreg else 0.0
+    wlast, w, failed = 0.0, None, False
+    while slots < iters:
+        if w is None:
+            # a new iteration: convergence test, barrier terms, first w
+            if _kkt(Hw, g, d, zl, zu, tl, tu) < tol:
+                break
+            Sig = zl / tl + zu / tu
+            base = -(Hw @ d + g)
+            w = 0.0 if wlast == 0.0 else max(w0, wlast / REG_DOWN)
+        slots += 1
         A = Hw + np.diag(Sig)
-        base = -(Hw @ d + g)
+        if nreg:
+            A[:nreg, :nreg] += w * np.eye(nreg)
+            try:
+                np.linalg.cholesky(A)
+            except np.linalg.LinAlgError:
+                w = w0 if w == 0.0 else REG_UP * w
+                if w > REG_MAX:
+                    failed = True
+                    break
+                continue
+            wlast, w = w, None
+        else:
+            w = None
         # predictor
         dda = np.linalg.solve(A, base)
         dzla = -zl - (zl / tl) * dda
@@ -101,6 +139,8 @@ def box_qp_ipm(Hw, g, lo, hi, iters=50, tol=1e-10):
         zl = zl + ad * dzl
         zu = zu + ad * dzu
         it += 1
+    if nreg:
+        return d, zl, zu, it, dict(w=wlast, slots=slots, failed=failed)
     return d, zl, zu, it
 
 
@@ -126,7 +166,8 @@ def kkt_error(Hw, g, lo, hi, d, zl, zu):
 
 def rt_step_qp(M: Model, u, s, x, y, pd, qd, P: Point, u_lo, u_hi, s_lo, s_hi, delta, iters=50, tol=1e-10):
     """The QP of eq. (qp_rto) at w_t = (u, s) for loads (pd, qd) with the
-    state x solving the power flow there: returns (du, ds, info dict)."""
+    state x solving the power flow there, by box_qp_ipm with inertia control
+    on the control block: returns (du, ds, info dict)."""
     Pt = dataclasses.replace(P, s=s, y=y)
     c = M.constraints(x, u, pd, qd)
     grad, lam = reduced_gradient(M, x, u, pd, qd, Pt)
@@ -135,9 +176,9 @@ def rt_step_qp(M: Model, u, s, x, y, pd, qd, P: Point, u_lo, u_hi, s_lo, s_hi, d
     g, Hw = qp_data(0.5 * (H + H.T), J, grad, c, Pt, delta)
     lo = np.concatenate([u_lo - u, s_lo - s])
     hi = np.concatenate([u_hi - u, s_hi - s])
-    d, zl, zu, it = box_qp_ipm(Hw, g, lo, hi, iters=iters, tol=tol)
+    d, zl, zu, it, reg = box_qp_ipm(Hw, g, lo, hi, iters=iters, tol=tol, nreg=M.nu)
     return d[:M.nu], d[M.nu:], dict(iters=it, kkt=kkt_error(Hw, g, lo, hi, d, zl, zu), grad=grad, H=H, J=J,
-                                    g=g, Hw=Hw, lo=lo, hi=hi)
+                                    g=g, Hw=Hw, lo=lo, hi=hi, zl=zl, zu=zu, reg=reg)
 
 
 def tracking_step_qp(M: Model, u, s, x, y, pd0, qd0, factor, P: Point, s_lo, s_hi, delta, pf_iters=6,

@@ -606,6 +606,46 @@ def test_box_qp_closed_forms():
     assert np.linalg.norm(d - x0) <= 1e-10 * np.linalg.norm(x0)
 
 
+def test_box_qp_inertia_control_convex_case_unchanged():
+    """On a strictly convex QP the inertia control never regularises: the
+    first factorization of every iteration succeeds with w = 0 and the
+    iterates are those of the unregularised method."""
+    rng = np.random.default_rng(11)
+    n = 30
+    A = rng.standard_normal((n, n))
+    Hw = A @ A.T / n + 0.1 * np.eye(n)
+    gv = rng.standard_normal(n)
+    lo, hi = -rng.uniform(0.05, 0.5, n), rng.uniform(0.05, 0.5, n)
+    d0, zl0, zu0, it0 = oracle.box_qp_ipm(Hw, gv, lo, hi, tol=1e-13, iters=80)
+    d1, zl1, zu1, it1, info = oracle.box_qp_ipm(Hw, gv, lo, hi, tol=1e-13, iters=80, nreg=n)
+    assert it1 == it0 and info["slots"] == it1 and info["w"] == 0.0 and not info["failed"]
+    assert np.max(np.abs(d1 - d0)) <= 1e-13
+
+
+def test_box_qp_inertia_control_reaches_a_local_minimiser():
+    """Separable indefinite QP (diagonal Hw, ten negative entries): the
+    regularised iteration ends at a local minimiser, checked coordinate by
+    coordinate -- a positive-curvature coordinate at its clipped Newton point
+    clip(-g_i / h_i, lo_i, hi_i), a negative-curvature one at a bound where
+    the derivative g_i + h_i d_i points outward (strict local minimum of a
+    concave parabola on an interval).  The first factorization fails, so the
+    regularisation was used."""
+    rng = np.random.default_rng(12)
+    n = 30
+    hd = rng.uniform(0.5, 5.0, n)
+    hd[:10] = -rng.uniform(0.5, 5.0, 10)
+    gv = rng.standard_normal(n)
+    lo, hi = -rng.uniform(0.1, 1.0, n), rng.uniform(0.1, 1.0, n)
+    d, zl, zu, it, info = oracle.box_qp_ipm(np.diag(hd), gv, lo, hi, tol=1e-12, iters=300, nreg=n)
+    assert not info["failed"] and info["slots"] > it
+    assert oracle.kkt_error(np.diag(hd), gv, lo, hi, d, zl, zu) < 1e-12
+    np.testing.assert_allclose(d[10:], np.clip(-gv[10:] / hd[10:], lo[10:], hi[10:]), rtol=0, atol=1e-9)
+    for i in range(10):
+        slope = gv[i] + hd[i] * d[i]
+        at_lo, at_hi = abs(d[i] - lo[i]) < 1e-9, abs(d[i] - hi[i]) < 1e-9
+        assert (at_lo and slope > 0) or (at_hi and slope < 0), (i, d[i], lo[i], hi[i], slope)
+
+
 def test_rt_qp_kkt_certificate_and_slack_coupling():
     """At the interior-point solution the bound multipliers are non-negative,
     complementary to the active bounds, and the s block of the stationarity
