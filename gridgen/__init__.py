@@ -373,6 +373,15 @@ def tracking_factors(seed: int, steps: int, nb: int, sd: float = 0.02) -> np.nda
     return 1.0 + sd * rng.standard_normal((steps, nb))
 
 
+def load_drop_factors(nb: int, steps: int = 60, t_drop: int = 2, drop: float = 0.2) -> np.ndarray:
+    """Load factors of the load-drop scenario: every load at its base value
+    before step t_drop and at (1 - drop) times it from t_drop on (all loads
+    drop together, as in the paper's real-time experiment)."""
+    f = np.ones((steps, nb))
+    f[t_drop:] = 1.0 - drop
+    return f
+
+
 def fingerprint(g: dict) -> str:
     h = hashlib.sha256()
     for k in sorted(g):

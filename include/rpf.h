@@ -254,7 +254,7 @@ int rpf_track_step(rpf_grid* grid, double* u, double* x, double* y, const double
  * does at (x, u, s, y), then forms H and J from the same identity batches
  * (rpf_reduced_derivatives), then runs max_iter predicated iterations of a
  * primal-dual interior-point method with Mehrotra's predictor-corrector
- * (Section IV-B.1/2, eq. ipm_kkt_reduced): start d = clip(0, lo + k, hi - k)
+ * (Section IV-B.1/2, eq. ipm_kkt_reduced) in max_iter slots: start d = clip(0, lo + k, hi - k)
  * with k = 1e-2 (hi - lo), duals 1 / slack, steps stopped 0.995 of the way
  * to the boundary; it stops once the scaled KKT error max(max|Hw d + g - z_l
  * + z_u| / (1 + max|g|), max complementarity product) is below tol.  Each
@@ -263,6 +263,10 @@ int rpf_track_step(rpf_grid* grid, double* u, double* x, double* y, const double
  * reduced Hessian with each constraint's curvature weight rho sigma_k^2
  * replaced by rho sigma_k^2 Sigma_s,k / (Sigma_s,k + rho sigma_k^2), formed
  * by the batched Hessian-vector products, then its Cholesky factor.
+ * Inertia control (Section IV-B.2): the Cholesky runs on S + w I, w = 0
+ * first (or max(w0, w_last / 4) after a regularised iteration), raised to
+ * w0 = 1e-4 max(1, max|diag H|) and then 8 times per failed attempt, each
+ * attempt one of the max_iter slots; past w = 1e30 the call gives up.
  *   x [n_x], u [n_u], pd/qd [nb], s/y [m], sigma [1 + m]: device, read.
  *   u_lo, u_hi [n_u], s_lo, s_hi [m]: device, read (lo < hi).
  *   batch: width of the Hessian batches (0 = the handle's).
@@ -271,10 +275,12 @@ int rpf_track_step(rpf_grid* grid, double* u, double* x, double* y, const double
  *   dw [n_u + m]: device, out: the step (du, ds).
  *   zw [2 (n_u + m)] (may be NULL): device, out: bound duals (z_l, z_u).
  *   kkt [1] (may be NULL): device, out: the last KKT error.
- *   status [5]: device int32, out: {iterations, converged (0/1), Cholesky
- *   info of S (1-based column, -1 solve wait expired, 0), raw stop word
- *   (0 running out of iterations, 1 converged, 2 non-finite, 16 + column
- *   Cholesky failure, -1), tiny pivot word of J_x at x}.
+ *   wreg [1] (may be NULL): device, out: the last regularisation w.
+ *   status [6]: device int32, out: {iterations, converged (0/1), Cholesky
+ *   info of S once the regularisation gave up (1-based column, -1 solve
+ *   wait expired, 0), raw stop word (0 out of slots, 1 converged, 2
+ *   non-finite, 16 + column, -1), tiny pivot word of J_x at x,
+ *   factorization attempts}.
  * Leaves the point cached as rpf_reduced_gradient does (its own
  * second-order data restored).  Uses the handle's workspace and three
  * internal streams as rpf_reduced_hessian. */
@@ -282,7 +288,35 @@ int rpf_qp_step(rpf_grid* grid, const double* x, const double* u, const double* 
                 const double* s, const double* y, double rho, const double* sigma, double delta,
                 const double* u_lo, const double* u_hi, const double* s_lo, const double* s_hi,
                 int32_t max_iter, double tol, int32_t batch, double* H, double* J, double* grad, double* dw,
-                double* zw, double* kkt, int32_t* status, rpf_stream_t stream);
+                double* zw, double* kkt, double* wreg, int32_t* status, rpf_stream_t stream);
+
+/* One real-time tracking update with the exact step (Section IV-C, steps
+ * 1-3), entirely on the device (no host synchronisation):
+ *   loads pd = pd0 * load_factor, qd = qd0 * load_factor (per bus);
+ *   p_pv <- p_pv * dispatch_scale (1.0: unchanged), the generators' share
+ *   of a uniform load change taken before the power flow (as primary
+ *   frequency response would), for load steps a single slack bus cannot
+ *   absorb;
+ *   power flow at u from x (pf_iters predicated Newton steps, tol);
+ *   the bounded QP of eq. (qp_rto) at w = (u, s) with the multipliers y, as
+ *   rpf_qp_step (qp_iters iterations at most, stopping tolerance qp_tol);
+ *   w <- w + dw / 2^k for the first k <= max_halvings whose power flow
+ *   converges (w unchanged if none);
+ *   y <- y + rho D_c (c(u) - s).
+ * u [n_u], s [m], x [n_x], y [m]: device, in/out.  pd0, qd0, load_factor
+ * [nb], s_lo, s_hi [m], u_lo, u_hi [n_u], sigma [1 + m]: device, read.
+ * dispatch_scale: host, > 0.  J [m x n_u]: device workspace (out: the reduced Jacobian at the step's
+ * point).  batch: width of the Hessian batches (0 = the handle's).
+ * status [8]: device int32, out: {first power flow converged, accepted
+ * halving k (-1: none), QP iterations, QP converged, Cholesky info of the
+ * Schur complement, Newton steps of the first power flow, tiny pivot word
+ * of the factorization behind the QP data, QP stop word (as rpf_qp_step)}.
+ * Uses the handle's workspace (one step at a time per handle). */
+int rpf_track_step_qp(rpf_grid* grid, double* u, double* s, double* x, double* y, const double* pd0,
+                      const double* qd0, const double* load_factor, const double* s_lo, const double* s_hi,
+                      const double* u_lo, const double* u_hi, double rho, const double* sigma, double delta,
+                      int32_t pf_iters, int32_t max_halvings, double tol, int32_t qp_iters, double qp_tol,
+                      int32_t batch, double dispatch_scale, double* J, int32_t* status, rpf_stream_t stream);
 
 /* Kernel timing with HIP events recorded on the launch stream, per kernel
  * class: 0 batched triangular solves inside the independent subtree packs

@@ -64,8 +64,10 @@ def lib():
             "rpf_presolve_info": [vp, i64p],
             "rpf_profile_enable": [vp, i32],
             "rpf_track_step": [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, dbl, vp, dbl, i32, i32, dbl, vp, vp],
+            "rpf_track_step_qp": [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, dbl, vp, dbl, i32, i32, dbl,
+                                  i32, dbl, i32, dbl, vp, vp, vp],
             "rpf_qp_step": [vp, vp, vp, vp, vp, vp, vp, dbl, vp, dbl, vp, vp, vp, vp, i32, dbl, i32, vp, vp, vp,
-                            vp, vp, vp, vp, vp],
+                            vp, vp, vp, vp, vp, vp],
             "rpf_profile_read": [vp, vp, vp, i32],
             "rpf_profile_read_busy": [vp, vp, vp, vp, i32],
             "rpf_presolve_pattern": [vp, vp, vp, vp],
@@ -328,13 +330,14 @@ class Grid:
         return step, info
 
     def qp_step(self, x, u, pd, qd, s, y, rho, sigma, delta, u_lo, u_hi, s_lo, s_hi, max_iter=50, tol=1e-10,
-                batch=0, H=None, J=None, grad=None, dw=None, zw=None, kkt=None, status=None):
+                batch=0, H=None, J=None, grad=None, dw=None, zw=None, kkt=None, wreg=None, status=None):
         """Exact real-time step: the bounded QP of eq. (qp_rto) in w = (u, s)
         at the point (x, u, s, y) by the device interior-point method.
         Returns a dict of device tensors: dw [n_u + m] (du, ds), zw [2 (n_u +
-        m)] (z_l, z_u), kkt [1], status int32 [5] (iterations, converged,
-        Cholesky info of the Schur complement, done word, tiny pivot word),
-        H [n_u, n_u] (symmetrised reduced Hessian), J [m, n_u], grad [n_u]."""
+        m)] (z_l, z_u), kkt [1], wreg [1] (last regularisation), status int32
+        [6] (iterations, converged, Cholesky info of the Schur complement,
+        done word, tiny pivot word, factorization attempts), H [n_u, n_u]
+        (symmetrised reduced Hessian), J [m, n_u], grad [n_u]."""
         torch = _torch()
         nu, m = self.nu, self.m
         n = nu + m
@@ -344,13 +347,34 @@ class Grid:
         dw = self._empty(n) if dw is None else dw
         zw = self._empty(2 * n) if zw is None else zw
         kkt = self._empty(1) if kkt is None else kkt
-        status = self._empty(5, torch.int32) if status is None else status
+        wreg = self._empty(1) if wreg is None else wreg
+        status = self._empty(6, torch.int32) if status is None else status
         _check(lib().rpf_qp_step(self._h, _dev(x, self.nx, "x"), _dev(u, nu, "u"), _dev(pd, self.nb, "pd"),
                                  _dev(qd, self.nb, "qd"), _dev(s, m, "s"), _dev(y, m, "y"), float(rho),
                                  _dev(sigma, 1 + m, "sigma"), float(delta), _dev(u_lo, nu, "u_lo"),
                                  _dev(u_hi, nu, "u_hi"), _dev(s_lo, m, "s_lo"), _dev(s_hi, m, "s_hi"),
                                  int(max_iter), float(tol), int(batch), _dev(H, nu * nu, "H"),
                                  _dev(J, m * nu, "J"), _dev(grad, nu, "grad"), _dev(dw, n, "dw"),
-                                 _dev(zw, 2 * n, "zw"), _dev(kkt, 1, "kkt"),
-                                 _dev(status, 5, "status", torch.int32), _stream()))
-        return dict(dw=dw, zw=zw, kkt=kkt, status=status, H=H, J=J, grad=grad)
+                                 _dev(zw, 2 * n, "zw"), _dev(kkt, 1, "kkt"), _dev(wreg, 1, "wreg"),
+                                 _dev(status, 6, "status", torch.int32), _stream()))
+        return dict(dw=dw, zw=zw, kkt=kkt, wreg=wreg, status=status, H=H, J=J, grad=grad)
+
+    def track_step_qp(self, u, s, x, y, pd0, qd0, factor, s_lo, s_hi, u_lo, u_hi, rho, sigma, delta,
+                      pf_iters=6, max_halvings=4, tol=1e-10, qp_iters=50, qp_tol=1e-10, batch=0, J=None,
+                      status=None, dispatch_scale=1.0):
+        """One device-resident tracking update with the exact QP step; u, s,
+        x, y updated in place (p_pv scaled by dispatch_scale first).
+        Returns (status int32 [8], J)."""
+        torch = _torch()
+        J = self._empty(self.m * self.nu).view(self.m, self.nu) if J is None else J
+        status = self._empty(8, torch.int32) if status is None else status
+        _check(lib().rpf_track_step_qp(self._h, _dev(u, self.nu, "u"), _dev(s, self.m, "s"), _dev(x, self.nx, "x"),
+                                       _dev(y, self.m, "y"), _dev(pd0, self.nb, "pd0"), _dev(qd0, self.nb, "qd0"),
+                                       _dev(factor, self.nb, "factor"), _dev(s_lo, self.m, "s_lo"),
+                                       _dev(s_hi, self.m, "s_hi"), _dev(u_lo, self.nu, "u_lo"),
+                                       _dev(u_hi, self.nu, "u_hi"), float(rho), _dev(sigma, 1 + self.m, "sigma"),
+                                       float(delta), int(pf_iters), int(max_halvings), float(tol), int(qp_iters),
+                                       float(qp_tol), int(batch), float(dispatch_scale),
+                                       _dev(J, self.m * self.nu, "J"),
+                                       _dev(status, 8, "status", torch.int32), _stream()))
+        return status, J

@@ -1928,6 +1928,71 @@ __global__ void k_try_u(int n, const double* __restrict__ u, const double* __res
   if (i < n) ut[i] = fmin(fmax(u[i] + f * d[i], lo[i]), hi[i]);
 }
 
+// v *= a
+__global__ void k_scale_vec(int n, double a, double* __restrict__ v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) v[i] *= a;
+}
+
+// trial point of the exact step: ut = u + f du, st = s + f ds (the QP's box
+// keeps both inside their bounds; no clipping)
+__global__ void k_try_w(int nu, int m, const double* __restrict__ u, const double* __restrict__ sv,
+                        const double* __restrict__ dw, double f, double* __restrict__ ut, double* __restrict__ st,
+                        const int32_t* __restrict__ skip) {
+  if (skip && *skip) return;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nu) ut[i] = u[i] + f * dw[i];
+  else if (i < nu + m) st[i - nu] = sv[i - nu] + f * dw[i];
+}
+
+// accept the trial point (u, s) when its power flow converged
+__global__ void k_accept_w(int nu, int m, const double* __restrict__ resid, double tol,
+                           int32_t* __restrict__ accepted, const double* __restrict__ ut,
+                           const double* __restrict__ st, double* __restrict__ u, double* __restrict__ sv,
+                           int32_t attempt, int32_t* __restrict__ which) {
+  __shared__ int ok;
+  if (threadIdx.x == 0) ok = (accepted[0] == 0 && resid[0] < tol) ? 1 : 0;
+  __syncthreads();
+  if (!ok) return;
+  for (int i = threadIdx.x; i < nu + m; i += blockDim.x) {
+    if (i < nu) u[i] = ut[i];
+    else sv[i - nu] = st[i - nu];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    accepted[0] = 1;
+    which[0] = attempt;
+  }
+}
+
+// multiplier update of the exact step (Section IV-C, step 3):
+// y += rho sigma_c (c - s)
+__global__ void k_y_update_s(int m, const double* __restrict__ c, const double* __restrict__ sigma_c, double rho,
+                             const double* __restrict__ sv, double* __restrict__ y) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < m) y[k] = y[k] + rho * sigma_c[k] * (c[k] - sv[k]);
+}
+
+// status of the exact tracking step from the step's flags (f) and the QP's
+// words (q = done, iterations): {first power flow converged, accepted
+// halving (-1 none), QP iterations, QP converged, Cholesky info of the
+// Schur complement, Newton steps of the first power flow, tiny pivot word
+// of the factorization behind the QP data, QP stop word}
+__global__ void k_track_qp_status(const int32_t* __restrict__ f, const int32_t* __restrict__ q,
+                                  int32_t* __restrict__ st) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    const int dn = q[0];
+    st[0] = f[5] == 1 ? 1 : 0;
+    st[1] = f[3];
+    st[2] = q[1];
+    st[3] = dn == 1 ? 1 : 0;
+    st[4] = dn >= 16 ? dn - 16 : (dn < 0 ? -1 : 0);
+    st[5] = f[6];
+    st[6] = f[7];
+    st[7] = dn;
+  }
+}
+
 // accept the trial control when its power flow converged: accepted = 1,
 // u = ut, status = attempt index
 __global__ void k_accept(int n, const double* __restrict__ resid, double tol, int32_t* __restrict__ accepted,

@@ -18,13 +18,22 @@
 // rho sigma_k^2 replaced by rho sigma_k^2 Sigma_s,k / C_k (it is formed by
 // the batched Hessian-vector products, not from J).
 //
+// Inertia control (Section IV-B.2: the regularisation keeps the Newton
+// matrix, hence S, positive definite): the Cholesky runs on S + w I, first
+// with w = 0 if the last successful w was 0, else max(w0, w_last /
+// QP_REG_DOWN); a failed factorization raises w (w0, then QP_REG_UP times)
+// and the next slot retries with the same S; w0 = QP_REG_BASE max(1, max
+// |diag H|).  Every factorization attempt takes one of the host's slots.
+//
 // The iteration is predicated on the device: `done` is 0 while it runs,
 // 1 once the KKT error is below tol, 2 when it is not finite, 16 + column
-// when the Cholesky of S fails (the Schur factor's info word is `done`
-// itself with base 16) and -1 when a triangular-solve workgroup gave up
-// waiting; every kernel of a later step returns at once.  The vector steps
-// run in one 1024-thread workgroup with fixed-order reductions, so the
-// results do not depend on the launch.
+// when w passes QP_REG_MAX (column of the last failed Cholesky) and -1 when
+// a triangular-solve workgroup gave up waiting; every kernel of a later
+// step returns at once.  Within a slot, skF (done or retrying) skips the
+// fresh part (KKT test, assembly of S) and sk2 (done or the factorization
+// failed) the solves and steps.  The vector steps run in one 1024-thread
+// workgroup with fixed-order reductions, so the results do not depend on
+// the launch.
 #pragma once
 #include "kernels.hpp"
 
@@ -38,10 +47,16 @@ constexpr double QP_KAPPA = 1e-2;
 constexpr double QP_MU0 = 1.0;
 constexpr double QP_TAU = 0.995;
 constexpr int QP_CHOL_BASE = 16;
+constexpr double QP_REG_BASE = 1e-4;
+constexpr double QP_REG_UP = 8.0;
+constexpr double QP_REG_DOWN = 4.0;
+constexpr double QP_REG_MAX = 1e30;
 constexpr int QP_NT = 1024;   // threads of the vector-step kernels
 
 // device scalars of the iteration
-enum { QS_MAXG = 0, QS_AP, QS_AD, QS_MUC, QS_MUA, QS_MU, QS_ERR, QS_NSCAL = 8 };
+enum { QS_MAXG = 0, QS_AP, QS_AD, QS_MUC, QS_MUA, QS_MU, QS_ERR, QS_W0, QS_W, QS_WLAST, QS_NSCAL = 12 };
+// device words of the iteration (int32)
+enum { QF_DONE = 0, QF_ITERS, QF_PIV, QF_RETRY, QF_SKF, QF_SK2, QF_CINFO, QF_FACT, QF_N = 8 };
 
 struct QPVec {
   int nu, m;
@@ -65,6 +80,11 @@ struct QPVec {
   double* qs;              // scalars
   int32_t* done;
   int32_t* iters;
+  int32_t* retry;          // the last factorization failed: this slot retries
+  int32_t* skF;            // done or retrying
+  int32_t* sk2;            // done or the factorization of this slot failed
+  int32_t* cinfo;          // info word of this slot's Cholesky (-2: not run)
+  int32_t* fact;           // factorization attempts
 };
 
 // OP 0: sum, 1: max, 2: min over the workgroup, in a fixed order (wave
@@ -155,15 +175,17 @@ __global__ void k_gemv_cols_sum(int cols, int nparts, const double* __restrict__
 // Starting point: bounds of the step lo = w_lo - w, hi = w_hi - w; d the
 // origin clipped into [lo + kappa, hi - kappa], kappa = QP_KAPPA (hi - lo);
 // slacks and duals; the QP gradient g = (grad, -wc) (wc = D_c (y + rho D_c
-// (c - s))) and max |g|; ts = sigma^2 d_s for the first KKT product.
+// (c - s))) and max |g|; ts = sigma^2 d_s for the first KKT product; the
+// first regularisation w0 from max |diag H| (H row-major n_u x n_u).
 __global__ void __launch_bounds__(QP_NT) k_qp_init(QPVec Q, const double* __restrict__ u,
                                                    const double* __restrict__ sv, const double* __restrict__ ulo,
                                                    const double* __restrict__ uhi, const double* __restrict__ slo,
                                                    const double* __restrict__ shi, const double* __restrict__ grad,
-                                                   const double* __restrict__ wc) {
+                                                   const double* __restrict__ wc, const double* __restrict__ H) {
   __shared__ double sh[QP_NT / 64];
   const int n = Q.nu + Q.m;
-  double gmax = 0.0;
+  double gmax = 0.0, hmax = 0.0;
+  for (int i = threadIdx.x; i < Q.nu; i += blockDim.x) hmax = fmax(hmax, fabs(H[(size_t)i * Q.nu + i]));
   for (int i = threadIdx.x; i < n; i += blockDim.x) {
     const bool isu = i < Q.nu;
     const int k = i - Q.nu;
@@ -186,10 +208,70 @@ __global__ void __launch_bounds__(QP_NT) k_qp_init(QPVec Q, const double* __rest
     }
   }
   gmax = wg_reduce<1>(gmax, sh);
+  hmax = wg_reduce<1>(hmax, sh);
   if (threadIdx.x == 0) {
     Q.qs[QS_MAXG] = gmax;
+    Q.qs[QS_W0] = QP_REG_BASE * fmax(1.0, hmax);
+    Q.qs[QS_W] = 0.0;
+    Q.qs[QS_WLAST] = 0.0;
     Q.done[0] = 0;
     Q.iters[0] = 0;
+    Q.retry[0] = 0;
+    Q.skF[0] = 0;
+    Q.sk2[0] = 0;
+    Q.cinfo[0] = -2;
+    Q.fact[0] = 0;
+  }
+}
+
+// start of a slot: skF = done or retrying
+__global__ void k_qp_slot(QPVec Q) {
+  if (threadIdx.x == 0) Q.skF[0] = (Q.done[0] != 0 || Q.retry[0] != 0) ? 1 : 0;
+}
+
+// regularisation of this slot: the Cholesky's info word (-2 = skip when the
+// iteration is over), the attempt count
+__global__ void k_qp_reg_set(QPVec Q) {
+  if (threadIdx.x != 0) return;
+  if (Q.done[0] != 0) {
+    Q.cinfo[0] = -2;
+    return;
+  }
+  Q.cinfo[0] = 0;
+  Q.fact[0] += 1;
+}
+
+// Sf = S + w I (row-major n x n), unless the iteration is over
+__global__ void k_qp_reg_copy(int n, const double* __restrict__ S, double* __restrict__ Sf, QPVec Q) {
+  if (*Q.done) return;
+  const double w = Q.qs[QS_W];
+  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= (size_t)n * n) return;
+  const size_t i = e / n, j = e - i * n;
+  Sf[e] = i == j ? S[e] + w : S[e];
+}
+
+// after this slot's Cholesky: success keeps w as w_last and lets the solves
+// run; failure raises w (w0 if it was 0, else QP_REG_UP w) for a retry in
+// the next slot, or ends the iteration past QP_REG_MAX
+__global__ void k_qp_reg_check(QPVec Q) {
+  if (threadIdx.x != 0) return;
+  if (Q.done[0] != 0) {
+    Q.sk2[0] = 1;
+    return;
+  }
+  const int ci = Q.cinfo[0];
+  if (ci != 0) {
+    const double w = Q.qs[QS_W];
+    const double wn = w == 0.0 ? Q.qs[QS_W0] : QP_REG_UP * w;
+    Q.retry[0] = 1;
+    Q.sk2[0] = 1;
+    if (wn > QP_REG_MAX) Q.done[0] = QP_CHOL_BASE + (ci > 0 ? ci : 0);
+    else Q.qs[QS_W] = wn;
+  } else {
+    Q.retry[0] = 0;
+    Q.sk2[0] = 0;
+    Q.qs[QS_WLAST] = Q.qs[QS_W];
   }
 }
 
@@ -202,7 +284,7 @@ __global__ void __launch_bounds__(QP_NT) k_qp_init(QPVec Q, const double* __rest
 // final != 0, then Sigma, C, the curvature weights gn and the predictor's
 // Schur right-hand side ts = sigma^2 base_s / C.
 __global__ void __launch_bounds__(QP_NT) k_qp_kkt(QPVec Q, int final_check) {
-  if (*Q.done) return;
+  if (*Q.skF) return;
   __shared__ double sh[QP_NT / 64];
   const int n = Q.nu + Q.m;
   double amax = 0.0, cmax = 0.0, bad = 0.0;
@@ -233,6 +315,12 @@ __global__ void __launch_bounds__(QP_NT) k_qp_kkt(QPVec Q, int final_check) {
     Q.qs[QS_ERR] = bad > 0.0 ? NAN : err;
     if (bad > 0.0) Q.done[0] = 2;
     else if (err < Q.tol) Q.done[0] = 1;
+    if (stop) Q.skF[0] = 1;
+    if (!stop && !final_check) {
+      // first regularisation of the iteration
+      const double wl = Q.qs[QS_WLAST];
+      Q.qs[QS_W] = wl == 0.0 ? 0.0 : fmax(Q.qs[QS_W0], wl / QP_REG_DOWN);
+    }
   }
   if (stop || final_check) return;
   for (int i = threadIdx.x; i < n; i += blockDim.x) {
@@ -257,7 +345,9 @@ __global__ void __launch_bounds__(QP_NT) k_qp_kkt(QPVec Q, int final_check) {
 // right-hand side rhs = base + r_l / t_l - r_u / t_u with r_l = mu - dda
 // dz_la, r_u = mu + dda dz_ua (ts = sigma^2 rhs_s / C for its Schur solve).
 __global__ void __launch_bounds__(QP_NT) k_qp_pred(QPVec Q) {
-  if (*Q.done) return;
+  const int k2 = *Q.sk2;
+  if (k2 < 0 && threadIdx.x == 0 && Q.done[0] == 0) Q.done[0] = -1;   // a solve gave up waiting
+  if (k2) return;
   __shared__ double sh[QP_NT / 64];
   const int n = Q.nu + Q.m;
   double ap = INFINITY, ad = INFINITY, cs = 0.0;
@@ -316,7 +406,9 @@ __global__ void __launch_bounds__(QP_NT) k_qp_pred(QPVec Q) {
 // + z_u / t_u dd, steps QP_TAU of the way to the boundary, then the update
 // of d, t_l, t_u, z_l, z_u and ts = sigma^2 d_s for the next KKT product.
 __global__ void __launch_bounds__(QP_NT) k_qp_corr(QPVec Q) {
-  if (*Q.done) return;
+  const int k2 = *Q.sk2;
+  if (k2 < 0 && threadIdx.x == 0 && Q.done[0] == 0) Q.done[0] = -1;
+  if (k2) return;
   __shared__ double sh[QP_NT / 64];
   const int n = Q.nu + Q.m;
   const double mu = Q.qs[QS_MU];
@@ -365,16 +457,22 @@ __global__ void __launch_bounds__(QP_NT) k_qp_corr(QPVec Q) {
   }
 }
 
-// status = {iterations, converged, Cholesky info of S (1-based column, -1
-// solve wait expired, 0), done word}; kkt = last KKT error.
-__global__ void k_qp_status(const int32_t* __restrict__ done, const int32_t* __restrict__ iters,
-                            const double* __restrict__ qs, int32_t* __restrict__ status, double* __restrict__ kkt) {
-  const int dn = done[0];
-  status[0] = iters[0];
+// status = {iterations, converged, Cholesky info of S (1-based column of
+// the last failed Cholesky once the regularisation gave up, -1 solve wait
+// expired, 0), done word, (tiny pivot word, copied by the caller),
+// factorization attempts}; kkt = last KKT error, wreg = last successful
+// regularisation.
+__global__ void k_qp_status(const int32_t* __restrict__ f, const double* __restrict__ qs,
+                            int32_t* __restrict__ status, double* __restrict__ kkt, double* __restrict__ wreg) {
+  const int dn = f[QF_DONE];
+  status[0] = f[QF_ITERS];
   status[1] = dn == 1 ? 1 : 0;
   status[2] = dn >= QP_CHOL_BASE ? dn - QP_CHOL_BASE : (dn < 0 ? -1 : 0);
   status[3] = dn;
+  status[4] = f[QF_PIV];
+  status[5] = f[QF_FACT];
   if (kkt) kkt[0] = qs[QS_ERR];
+  if (wreg) wreg[0] = qs[QS_WLAST];
 }
 
 }  // namespace dev

@@ -104,6 +104,8 @@ struct rpf_grid {
   // partial sums of the transposed products
   double *qg, *qd_, *qtl, *qtu, *qzl, *qzu, *qsig, *qbase, *qdda, *qdzla, *qdzua, *qrhs, *qdd, *qdzl, *qdzu;
   double *qcs, *qgn, *qts, *qJv, *qrneg, *qxu, *qHd, *qJt, *qscal, *qpart;
+  double* s_try = nullptr;
+  double* qS = nullptr;   // the Schur complement before regularisation [n_u x n_u]
   int32_t* qflags = nullptr;
   int qparts = 64;
 
@@ -504,6 +506,7 @@ void setup(rpf_grid* h) {
   h->u_try = h->alloc<double>(P.nu);
   h->xi_save = h->alloc<double>(P.nx);
   h->scur = h->alloc<double>(P.m);
+  h->s_try = h->alloc<double>(P.m);
   h->pdt = h->alloc<double>(P.nb);
   h->qdt = h->alloc<double>(P.nb);
   h->tres = h->alloc<double>(4);
@@ -523,7 +526,8 @@ void setup(rpf_grid* h) {
     h->qscal = h->alloc<double>(QS_NSCAL);
     h->qparts = std::max(1, std::min(64, cdiv(P.m, 256)));
     h->qpart = h->alloc<double>((size_t)h->qparts * P.nu);
-    h->qflags = h->alloc<int32_t>(4);
+    h->qflags = h->alloc<int32_t>(QF_N);
+    h->qS = h->alloc<double>((size_t)P.nu * P.nu);
   }
 
   int maxrow = std::max(P.max_lu_row, 1);
@@ -1358,72 +1362,88 @@ QPVec qp_vec(rpf_grid* h, double rho, double delta, double tol, const double* si
   Q.cs = h->qcs; Q.gn = h->qgn; Q.base = h->qbase; Q.dda = h->qdda; Q.dzla = h->qdzla; Q.dzua = h->qdzua;
   Q.rhs = h->qrhs; Q.dd = h->qdd; Q.dzl = h->qdzl; Q.dzu = h->qdzu; Q.ts = h->qts; Q.rneg = h->qrneg;
   Q.xu = h->qxu; Q.Hd = h->qHd; Q.Jv = h->qJv; Q.Jt = h->qJt; Q.qs = h->qscal;
-  Q.done = h->qflags; Q.iters = h->qflags + 1;
+  Q.done = h->qflags + QF_DONE; Q.iters = h->qflags + QF_ITERS; Q.retry = h->qflags + QF_RETRY;
+  Q.skF = h->qflags + QF_SKF; Q.sk2 = h->qflags + QF_SK2; Q.cinfo = h->qflags + QF_CINFO;
+  Q.fact = h->qflags + QF_FACT;
   return Q;
 }
 
-// Schur solve of (Hw + Sigma) x = b (Proposition 3) with S factorized in
-// Sf: xu = S^{-1} (b_u + rho J^T ts), Jv = J xu (ts = sigma^2 b_s / C is
-// already in Q.ts); the s part is formed by the next vector step.
+// Schur solve of (Hw + Sigma + w P_u) x = b (Proposition 3) with S + w I
+// factorized in Sf: xu = (S + w I)^{-1} (b_u + rho J^T ts), Jv = J xu
+// (ts = sigma^2 b_s / C is already in Q.ts); the s part is formed by the
+// next vector step.  Skipped while sk2 is set.
 void qp_schur_solve(rpf_grid* h, const QPVec& Q, const double* J, const double* Sf, const double* b, hipStream_t s) {
   const int nu = Q.nu, m = Q.m;
-  gemv_t(h, J, m, nu, Q.ts, -Q.rho, b, -1.0, Q.rneg, s, Q.done);
-  // chol_solve gives -S^{-1} rneg; its kernels return at once while done != 0
-  chol_solve(h, nu, Sf, Q.rneg, Q.xu, Q.done, s);
-  k_gemv_rows<<<cdiv(m, 4), 256, 0, s>>>(m, nu, J, nu, Q.xu, Q.Jv, Q.done);
+  gemv_t(h, J, m, nu, Q.ts, -Q.rho, b, -1.0, Q.rneg, s, Q.sk2);
+  // chol_solve gives -S^{-1} rneg; its kernels return at once while sk2 != 0
+  // (and a solve that gives up waiting writes -1 there)
+  chol_solve(h, nu, Sf, Q.rneg, Q.xu, Q.sk2, s);
+  k_gemv_rows<<<cdiv(m, 4), 256, 0, s>>>(m, nu, J, nu, Q.xu, Q.Jv, Q.sk2);
   LAUNCHCHK();
 }
 
 // Hw d pieces for the KKT test: Hd = H d_u, Jv = J d_u, Jt = J^T ts.
 void qp_kkt_products(rpf_grid* h, const QPVec& Q, const double* H, const double* J, hipStream_t s) {
   const int nu = Q.nu, m = Q.m;
-  k_gemv_rows<<<cdiv(nu, 4), 256, 0, s>>>(nu, nu, H, nu, Q.d, Q.Hd, Q.done);
+  k_gemv_rows<<<cdiv(nu, 4), 256, 0, s>>>(nu, nu, H, nu, Q.d, Q.Hd, Q.skF);
   LAUNCHCHK();
-  k_gemv_rows<<<cdiv(m, 4), 256, 0, s>>>(m, nu, J, nu, Q.d, Q.Jv, Q.done);
+  k_gemv_rows<<<cdiv(m, 4), 256, 0, s>>>(m, nu, J, nu, Q.d, Q.Jv, Q.skF);
   LAUNCHCHK();
-  gemv_t(h, J, m, nu, Q.ts, 1.0, nullptr, 0.0, Q.Jt, s, Q.done);
+  gemv_t(h, J, m, nu, Q.ts, 1.0, nullptr, 0.0, Q.Jt, s, Q.skF);
 }
 
 // The bounded QP at the cached point (rpf_qp_step after its derivatives):
-// max_iter predicated predictor-corrector iterations, then a last KKT test.
-void qp_ipm(rpf_grid* h, const ALArgs& A, const VarArgs& V, const double* H, const double* J, double* Sbuf,
+// max_iter predicated slots (an iteration, or a retried factorization with
+// a larger regularisation), then a last KKT test.
+void qp_ipm(rpf_grid* h, const ALArgs& A, const VarArgs& V, const double* H, const double* J, double* Sf,
             const double* u, const double* sv, const double* u_lo, const double* u_hi, const double* s_lo,
             const double* s_hi, double rho, const double* sigma, double delta, int max_iter, double tol, int batch,
             hipStream_t s) {
   const int nu = h->P.nu;
   const QPVec Q = qp_vec(h, rho, delta, tol, sigma);
-  k_qp_init<<<1, QP_NT, 0, s>>>(Q, u, sv, u_lo, u_hi, s_lo, s_hi, h->gradbuf, h->wvec);
+  double* S = h->qS;
+  k_qp_init<<<1, QP_NT, 0, s>>>(Q, u, sv, u_lo, u_hi, s_lo, s_hi, h->gradbuf, h->wvec, H);
   LAUNCHCHK();
   for (int it = 0; it <= max_iter; ++it) {
+    k_qp_slot<<<1, 64, 0, s>>>(Q);
+    LAUNCHCHK();
     qp_kkt_products(h, Q, H, J, s);
     k_qp_kkt<<<1, QP_NT, 0, s>>>(Q, it == max_iter ? 1 : 0);
     LAUNCHCHK();
     if (it == max_iter) break;
     // S = H_gn + Sigma_u + delta I: the reduced Hessian with the Schur
-    // curvature weights, by the batched products (predicated), then Cholesky
-    h->skipw = Q.done;
+    // curvature weights, by the batched products (skipped on a retry)
+    h->skipw = Q.skF;
     try {
-      second_order(h, A, V, Q.gn, sigma, rho, s, Q.done);
-      derivative_batches(h, Sbuf, nullptr, batch, s);
+      second_order(h, A, V, Q.gn, sigma, rho, s, Q.skF);
+      derivative_batches(h, S, nullptr, batch, s);
     } catch (...) {
       h->skipw = nullptr;
       throw;
     }
     h->skipw = nullptr;
-    k_symmetrize<<<dim3(cdiv(nu, 32), cdiv(nu, 32)), dim3(32, 8), 0, s>>>(nu, Sbuf, Q.sig, delta, Q.done);
+    k_symmetrize<<<dim3(cdiv(nu, 32), cdiv(nu, 32)), dim3(32, 8), 0, s>>>(nu, S, Q.sig, delta, Q.skF);
     LAUNCHCHK();
-    dense_factor<true>(nu, Sbuf, Q.done, QP_CHOL_BASE, s);
+    // inertia control: Cholesky of S + w I
+    k_qp_reg_set<<<1, 64, 0, s>>>(Q);
+    LAUNCHCHK();
+    k_qp_reg_copy<<<cdiv((long)nu * nu, 256), 256, 0, s>>>(nu, S, Sf, Q);
+    LAUNCHCHK();
+    dense_factor<true>(nu, Sf, Q.cinfo, 0, s);
+    k_qp_reg_check<<<1, 64, 0, s>>>(Q);
+    LAUNCHCHK();
     // predictor, then corrector with the same factor
-    qp_schur_solve(h, Q, J, Sbuf, Q.base, s);
+    qp_schur_solve(h, Q, J, Sf, Q.base, s);
     k_qp_pred<<<1, QP_NT, 0, s>>>(Q);
     LAUNCHCHK();
-    qp_schur_solve(h, Q, J, Sbuf, Q.rhs, s);
+    qp_schur_solve(h, Q, J, Sf, Q.rhs, s);
     k_qp_corr<<<1, QP_NT, 0, s>>>(Q);
     LAUNCHCHK();
   }
   // the point's own second-order data back for later Hessian products
   second_order(h, A, V, nullptr, sigma, rho, s, nullptr);
 }
+
 }  // namespace
 
 extern "C" {
@@ -1488,7 +1508,7 @@ int rpf_qp_step(rpf_grid* h, const double* x, const double* u, const double* pd,
                 const double* y, double rho, const double* sigma, double delta, const double* u_lo,
                 const double* u_hi, const double* s_lo, const double* s_hi, int32_t max_iter, double tol,
                 int32_t batch, double* H, double* J, double* grad, double* dw, double* zw, double* kkt,
-                int32_t* status, rpf_stream_t stream) {
+                double* wreg, int32_t* status, rpf_stream_t stream) {
   if (!h || !x || !u || !pd || !qd || !sv || !y || !sigma || !u_lo || !u_hi || !s_lo || !s_hi || !J || !dw ||
       !status)
     return set_err(RPF_EINVAL, "NULL argument");
@@ -1503,7 +1523,7 @@ int rpf_qp_step(rpf_grid* h, const double* x, const double* u, const double* pd,
     // 1. point: power-flow state x, reduced gradient, cached second-order data
     x_in(h, x, s);
     gradient_core(h, u, pd, qd, sv, y, rho, sigma, h->gradbuf, nullptr, s);
-    k_piv_report<<<1, 1, 0, s>>>(h->piv_status, h->x_i2p, h->qflags + 2);
+    k_piv_report<<<1, 1, 0, s>>>(h->piv_status, h->x_i2p, h->qflags + QF_PIV);
     LAUNCHCHK();
     // 2. reduced Hessian and Jacobian from the same identity batches,
     // H symmetrised
@@ -1526,9 +1546,7 @@ int rpf_qp_step(rpf_grid* h, const double* x, const double* u, const double* pd,
       k_copy_vec<<<cdiv(nu, 256), 256, 0, s>>>(nu, h->gradbuf, grad, nullptr);
       LAUNCHCHK();
     }
-    k_qp_status<<<1, 1, 0, s>>>(h->qflags, h->qflags + 1, h->qscal, status, kkt);
-    LAUNCHCHK();
-    k_copy_int<<<1, 1, 0, s>>>(h->qflags + 2, status + 4);
+    k_qp_status<<<1, 1, 0, s>>>(h->qflags, h->qscal, status, kkt, wreg);
     LAUNCHCHK();
     return RPF_OK;
   });
@@ -1616,6 +1634,95 @@ int rpf_track_step(rpf_grid* h, double* u, double* x, double* y, const double* p
     k_permute_scatter<<<cdiv(nx, 256), 256, 0, s>>>(nx, h->x_i2p, h->xi, x, nullptr);
     LAUNCHCHK();
     k_track_status<<<1, 1, 0, s>>>(h->tflags, status);
+    LAUNCHCHK();
+    return RPF_OK;
+  });
+}
+
+
+int rpf_track_step_qp(rpf_grid* h, double* u, double* sv, double* x, double* y, const double* pd0,
+                      const double* qd0, const double* load_factor, const double* s_lo, const double* s_hi,
+                      const double* u_lo, const double* u_hi, double rho, const double* sigma, double delta,
+                      int32_t pf_iters, int32_t max_halvings, double tol, int32_t qp_iters, double qp_tol,
+                      int32_t batch, double dispatch_scale, double* J, int32_t* status, rpf_stream_t stream) {
+  if (!h || !u || !sv || !x || !y || !pd0 || !qd0 || !load_factor || !s_lo || !s_hi || !u_lo || !u_hi || !sigma ||
+      !J || !status)
+    return set_err(RPF_EINVAL, "NULL argument");
+  if (pf_iters < 1 || max_halvings < 0 || max_halvings > 30 || qp_iters < 0 || qp_iters > 500)
+    return set_err(RPF_EINVAL, "bad iteration counts");
+  if (batch < 0) return set_err(RPF_EINVAL, "batch must be >= 0");
+  if (!(rho > 0.0)) return set_err(RPF_EINVAL, "rho must be positive");
+  if (!(dispatch_scale > 0.0)) return set_err(RPF_EINVAL, "dispatch_scale must be positive");
+  return guard([&]() -> int {
+    hipStream_t s = (hipStream_t)stream;
+    const Presolve& P = h->P;
+    const int nu = P.nu, nx = P.nx, m = P.m;
+    int32_t* done = h->tflags;        // predication flag of the current power flow
+    int32_t* count = h->tflags + 1;
+    int32_t* accepted = h->tflags + 2;
+    int32_t* which = h->tflags + 3;
+    k_fill_int<<<1, 8, 0, s>>>(8, h->tflags, 0);
+    LAUNCHCHK();
+    k_fill_int<<<1, 1, 0, s>>>(1, which, -1);
+    LAUNCHCHK();
+    k_track_loads<<<cdiv(P.nb, 256), 256, 0, s>>>(P.nb, pd0, qd0, load_factor, h->pdt, h->qdt);
+    LAUNCHCHK();
+    if (dispatch_scale != 1.0 && P.npv > 0) {
+      // p_pv, the last n_pv controls, follow a uniform load change
+      k_scale_vec<<<cdiv(P.npv, 256), 256, 0, s>>>(P.npv, dispatch_scale, u + 1 + P.npv);
+      LAUNCHCHK();
+    }
+    // 1. power flow at the current control and the new loads (warm start)
+    x_in(h, x, s);
+    pf_device(h, u, h->pdt, h->qdt, pf_iters, tol, done, count, h->tres, s);
+    k_copy_int<<<1, 1, 0, s>>>(done, h->tflags + 5);
+    LAUNCHCHK();
+    k_copy_int<<<1, 1, 0, s>>>(count, h->tflags + 6);
+    LAUNCHCHK();
+    // 2. the bounded QP at (u, s, y): gradient, H and J, interior point
+    gradient_core(h, u, h->pdt, h->qdt, sv, y, rho, sigma, h->gradbuf, nullptr, s);
+    k_piv_report<<<1, 1, 0, s>>>(h->piv_status, h->x_i2p, h->tflags + 7);
+    LAUNCHCHK();
+    derivative_batches(h, h->Hbuf, J, batch, s);
+    k_symmetrize<<<dim3(cdiv(nu, 32), cdiv(nu, 32)), dim3(32, 8), 0, s>>>(nu, h->Hbuf, nullptr, 0.0);
+    LAUNCHCHK();
+    {
+      const ALArgs A = al_args(h, u, h->pdt, h->qdt, sv, y, rho, sigma);
+      const VarArgs V = var_args(h, u, sigma);
+      qp_ipm(h, A, V, h->Hbuf, J, h->Kbuf, u, sv, u_lo, u_hi, s_lo, s_hi, rho, sigma, delta, qp_iters, qp_tol,
+             batch, s);
+    }
+    // 3. w + dw / 2^k for the first k whose power flow converges
+    k_copy_vec<<<cdiv(nx, 256), 256, 0, s>>>(nx, h->xi, h->xi_save, nullptr);
+    LAUNCHCHK();
+    double f = 1.0;
+    for (int k = 0; k <= max_halvings; ++k, f *= 0.5) {
+      k_try_w<<<cdiv(nu + m, 256), 256, 0, s>>>(nu, m, u, sv, h->qd_, f, h->u_try, h->s_try, accepted);
+      LAUNCHCHK();
+      k_copy_vec<<<cdiv(nx, 256), 256, 0, s>>>(nx, h->xi_save, h->xi, accepted);
+      LAUNCHCHK();
+      k_copy_int<<<1, 1, 0, s>>>(accepted, done);
+      LAUNCHCHK();
+      pf_device(h, h->u_try, h->pdt, h->qdt, pf_iters, tol, done, count, h->tres + 1, s);
+      k_accept_w<<<1, 256, 0, s>>>(nu, m, h->tres + 1, tol, accepted, h->u_try, h->s_try, u, sv, k, which);
+      LAUNCHCHK();
+    }
+    // no trial accepted: keep (u, s) and the power flow at u
+    k_fill_int<<<1, 1, 0, s>>>(1, done, 0);
+    LAUNCHCHK();
+    k_copy_vec<<<cdiv(nx, 256), 256, 0, s>>>(nx, h->xi_save, h->xi, accepted);
+    LAUNCHCHK();
+    // 4. multiplier update at the new point: y += rho D_c (c(u) - s)
+    state_and_records(h, u, s);
+    bus_injections(h, s);
+    const ALArgs A2 = al_args(h, u, h->pdt, h->qdt, sv, y, rho, sigma);
+    k_constraints<<<cdiv(m + P.ng, 256), 256, 0, s>>>(A2, h->cvec, nullptr, nullptr);
+    LAUNCHCHK();
+    k_y_update_s<<<cdiv(m, 256), 256, 0, s>>>(m, h->cvec, sigma + 1, rho, sv, y);
+    LAUNCHCHK();
+    k_permute_scatter<<<cdiv(nx, 256), 256, 0, s>>>(nx, h->x_i2p, h->xi, x, nullptr);
+    LAUNCHCHK();
+    k_track_qp_status<<<1, 1, 0, s>>>(h->tflags, h->qflags, status);
     LAUNCHCHK();
     return RPF_OK;
   });

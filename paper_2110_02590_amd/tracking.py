@@ -31,7 +31,8 @@ class TrackingItem:
 
 
 class _Inst:
-    def __init__(self, item: TrackingItem, max_batch: int):
+    def __init__(self, item: TrackingItem, max_batch: int, mode: str = "newton"):
+        self.mode = mode
         self.pr = pr = Problem(item.grid, max_batch=max_batch)
         dev = "cuda"
         self.u = pr.u0.clone()
@@ -49,8 +50,37 @@ class _Inst:
         lo, hi = pr.u_bounds()
         self.u_lo = torch.tensor(lo, device=dev)
         self.u_hi = torch.tensor(hi, device=dev)
-        self.status = torch.zeros(5, dtype=torch.int32, device=dev)
-        self.delta = self._shift(item)
+        if mode == "qp":
+            # slack at the base point: the constraints clipped into their box
+            pr_s = torch.zeros(pr.m, dtype=torch.float64, device=dev)
+            _, c = pr.grid.al_objective(self.x, self.u, pr.pd, pr.qd, pr_s, self.y, self.rho, self.sigma)
+            self.s = torch.minimum(torch.maximum(c, self.s_lo), self.s_hi).contiguous()
+            self.J = torch.empty((pr.m, pr.nu), dtype=torch.float64, device=dev)
+            self.status = torch.zeros(8, dtype=torch.int32, device=dev)
+            self.delta = self._qp_shift()
+        else:
+            self.s = None
+            self.status = torch.zeros(5, dtype=torch.int32, device=dev)
+            self.delta = self._shift(item)
+
+    def _qp_shift(self) -> float:
+        """Shift of the exact step's QP: at the base point, 1.5 times the most
+        negative eigenvalue of H_uu = H - rho J^T D_c^2 J (the curvature the
+        penalty does not supply) plus 1e-2 makes the QP strictly convex; ten
+        times that keeps it convex while the loads move (the inertia control
+        of the interior-point method covers the rest)."""
+        pr = self.pr
+        g = pr.grid
+        lo, hi = pr.u_bounds()
+        ulo = torch.tensor(lo, device="cuda")
+        uhi = torch.tensor(hi, device="cuda")
+        out = g.qp_step(self.x, self.u, pr.pd, pr.qd, self.s, self.y, self.rho, self.sigma, 0.0, ulo, uhi,
+                        self.s_lo, self.s_hi, max_iter=0, J=self.J)
+        H, J = out["H"], out["J"]
+        sc2 = self.sigma[1:] ** 2
+        Huu = H - self.rho * (J.T.contiguous() @ (sc2[:, None] * J))
+        lam = float(torch.linalg.eigvalsh(0.5 * (Huu + Huu.T)).min())
+        return 10.0 * (1.5 * max(0.0, -lam) + 1e-2)
 
     def _shift(self, item) -> float:
         """Inertia-control shift at the base point: the smallest value of the
@@ -72,10 +102,23 @@ class _Inst:
 
 
 class TrackingBatch:
+    """mode "newton": the shifted Newton step (rpf_track_step); mode "qp":
+    the exact step, the bounded QP by the interior-point method
+    (rpf_track_step_qp, qp_iters and qp_tol)."""
+
     def __init__(self, items: List[TrackingItem], max_batch: int = 256, pf_iters: int = 6,
-                 max_halvings: int = 4, tol: float = 1e-10, nstreams: int = 8):
+                 max_halvings: int = 4, tol: float = 1e-10, nstreams: int = 8, mode: str = "newton",
+                 qp_iters: int = 50, qp_tol: float = 1e-10, redispatch: bool = False):
+        if mode not in ("newton", "qp"):
+            raise ValueError("mode must be 'newton' or 'qp'")
         self.items = items
-        self.inst = [_Inst(it, max_batch) for it in items]
+        self.mode = mode
+        self.qp_iters, self.qp_tol = qp_iters, qp_tol
+        # exact step only: at a change of the total load the PV dispatch is
+        # scaled by the ratio of total loads before the update
+        self.redispatch = redispatch and mode == "qp"
+        self.t = 0
+        self.inst = [_Inst(it, max_batch, mode) for it in items]
         self.pf_iters, self.max_halvings, self.tol = pf_iters, max_halvings, tol
         sizes = [int(it.grid["nb"]) for it in items]
         self.offs = np.concatenate([[0], np.cumsum(sizes)])
@@ -91,10 +134,29 @@ class TrackingBatch:
         it = self.inst[k]
         pr = it.pr
         fac = self.cur[int(self.offs[k]):int(self.offs[k + 1])]
+        if self.mode == "qp":
+            pr.grid.track_step_qp(it.u, it.s, it.x, it.y, pr.pd, pr.qd, fac, it.s_lo, it.s_hi, it.u_lo, it.u_hi,
+                                  it.rho, it.sigma, it.delta, self.pf_iters, self.max_halvings, self.tol,
+                                  self.qp_iters, self.qp_tol, J=it.J, status=it.status,
+                                  dispatch_scale=self.dispatch_scale(k, self.t))
+            return
         pr.grid.track_step(it.u, it.x, it.y, pr.pd, pr.qd, fac, it.s_lo, it.s_hi, it.u_lo, it.u_hi, it.rho,
                            it.sigma, it.delta, self.pf_iters, self.max_halvings, self.tol, status=it.status)
 
+    def dispatch_scale(self, k: int, t: int) -> float:
+        """Ratio of instance k's total load at step t to that at step t - 1
+        when redispatching (1.0 otherwise): host figures of the scenario's
+        load factors."""
+        if not self.redispatch or t == 0:
+            return 1.0
+        it = self.items[k]
+        pd0 = np.asarray(it.grid["pd"], float)
+        a = float(pd0 @ it.factors[t])
+        b = float(pd0 @ it.factors[t - 1])
+        return 1.0 if a == b else a / b
+
     def set_step(self, t: int):
+        self.t = t
         self.cur.copy_(self.fac_all[t])
 
     def step_eager(self, t: int):
@@ -132,11 +194,14 @@ class TrackingBatch:
         self.graph.replay()
 
     def state(self):
-        return [(i.u.clone(), i.x.clone(), i.y.clone(), i.status.clone()) for i in self.inst]
+        return [(i.u.clone(), i.x.clone(), i.y.clone(), i.status.clone(),
+                 None if i.s is None else i.s.clone()) for i in self.inst]
 
     def load_state(self, st):
-        for i, (u, x, y, s) in zip(self.inst, st):
+        for i, (u, x, y, stt, sv) in zip(self.inst, st):
             i.u.copy_(u)
             i.x.copy_(x)
             i.y.copy_(y)
-            i.status.copy_(s)
+            i.status.copy_(stt)
+            if sv is not None:
+                i.s.copy_(sv)

@@ -67,7 +67,8 @@ def test_fixed_iterations_match_oracle(name, iters):
     assert info["iters"] == iters
     r = _gpu(pr, x, u, s, P, lo, hi, delta, iters, 0.0, batch=64)
     st = r["status"]
-    assert st[0] == iters and st[2] == 0 and st[3] == 0 and st[4] == 0, st
+    assert st[0] == iters and st[2] == 0 and st[3] == 0 and st[4] == 0 and st[5] == iters, st
+    assert info["reg"]["slots"] == iters and info["reg"]["w"] == 0.0
     d = np.concatenate([du, ds])
     assert np.linalg.norm(r["dw"] - d) <= 1e-9 * np.linalg.norm(d), np.linalg.norm(r["dw"] - d) / np.linalg.norm(d)
     # the QP data the GPU built: reduced gradient and symmetrised H, J
@@ -156,12 +157,24 @@ def test_largest_workload_kkt_certificate():
     assert np.linalg.norm(r["grad"] - go) <= 1e-10 * np.linalg.norm(go)
 
 
-def test_schur_cholesky_failure_is_reported():
-    """A shift that makes S indefinite: the Cholesky of the Schur complement
-    fails in the first iteration, the status names the column, and the
-    iteration stops (every later kernel returns at once)."""
-    print("[case] qp failure syn300", flush=True)
+@pytest.mark.parametrize("slots", [3, 12])
+def test_inertia_control_matches_oracle(slots):
+    """delta = 0 leaves the QP indefinite (H_uu has negative eigenvalues at
+    this point), so the first Cholesky of S fails and the regularisation
+    w I engages (Section IV-B.2).  Both sides take the same decisions: the
+    same iterations and factorization attempts in `slots` slots, and the
+    same iterate."""
+    print(f"[case] qp inertia control syn300 slots={slots}", flush=True)
     g, ep, M, u, x, P, s, lo, hi, pr = _case("syn300")
-    r = _gpu(pr, x, u, s, P, lo, hi, -1e8, 20, 1e-12, batch=64)
+    assert _delta(M, u, x, g, P, s) > 1.0        # H_uu is indefinite here
+    ulo, uhi = M.u_bounds()
+    du, ds, info = oracle.rt_step_qp(M, u, s, x, P.y, g["pd"], g["qd"], P, ulo, uhi, lo, hi, 0.0, iters=slots,
+                                     tol=0.0)
+    r = _gpu(pr, x, u, s, P, lo, hi, 0.0, slots, 0.0, batch=64)
     st = r["status"]
-    assert st[0] == 0 and st[1] == 0 and st[2] >= 1 and st[3] == 16 + st[2], st
+    print("status", st.tolist(), "oracle", info["iters"], info["reg"], "gpu w", float(r["wreg"][0]), flush=True)
+    assert st[5] == slots and st[0] == info["iters"] and st[0] < slots, (st, info["iters"])
+    assert st[2] == 0 and st[3] == 0
+    d = np.concatenate([du, ds])
+    assert np.linalg.norm(r["dw"] - d) <= 1e-9 * np.linalg.norm(d)
+    assert abs(float(r["wreg"][0]) - info["reg"]["w"]) <= 1e-12 * max(1.0, info["reg"]["w"])
