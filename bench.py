@@ -68,6 +68,9 @@ def parse():
                     help="batched real-time tracking: 64 grids, one tracking update per step")
     ap.add_argument("--instances", type=int, default=64)
     ap.add_argument("--track-steps", type=int, default=50)
+    ap.add_argument("--tracking-mode", default="newton", choices=["newton", "qp"])
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the exact-step, load-drop and 64-grid tracking legs of the default run")
     return ap.parse_args()
 
 
@@ -210,6 +213,11 @@ def main():
         torch.cuda.synchronize()
         out["b1_eager_hvps_per_s"] = round(nd / (time.perf_counter() - t0), 1)
         out["batched_over_b1"] = round(out["hvp_only_hvps_per_s"] / out["b1_eager_hvps_per_s"], 1)
+
+    if not a.no_extras:
+        out["rt_qp"] = rt_qp_leg(g, ep, pr)
+        out["load_drop_tracking"] = load_drop_leg()
+        out["tracking_64"] = tracking_leg(a.instances, a.track_steps, 10)
 
     if a.copy_probe:
         # a plain streaming kernel of known size for scaling the HBM byte
@@ -372,35 +380,35 @@ def roofline(g, pr, prof, B, steps):
     return ent[dom], {k: v for k, v in ent.items() if k != dom}
 
 
-def tracking_bench(a):
+def tracking_leg(instances, steps, eager_steps, mode="newton", qp_iters=40):
     """64 synthetic grids (n_b ~ U[300, 2000], seeds 100..163), each tracking
-    per-step load perturbations with one device-resident reduced-Hessian
-    Newton AL update; eager per-instance launches vs. one HIP graph per step
-    (instances forked over streams)."""
+    per-step load perturbations with one device-resident update per step
+    (mode "newton": shifted Newton step; "qp": exact step by the bounded
+    QP): one HIP graph per step (instances forked over 8 streams, captured
+    once, replayed every step) timed over `steps` steps, and eager
+    per-instance launches over `eager_steps` steps."""
     import numpy as np
     import torch
 
     import gridgen
     from paper_2110_02590_amd.tracking import TrackingBatch, TrackingItem
 
-    torch.cuda.set_device(0)
-    steps = a.track_steps
     items = []
-    for sd in gridgen.TRACKING_SEEDS[:a.instances]:
+    for sd in gridgen.TRACKING_SEEDS[:instances]:
         g = gridgen.make_grid(gridgen.tracking_workload(sd))
         ep = gridgen.eval_point(g, seed=sd + 1000)
         lo, hi = gridgen.constraint_bounds(g)
-        items.append(TrackingItem(g, ep, lo, hi, gridgen.tracking_factors(sd, steps, g["nb"])))
+        items.append(TrackingItem(g, ep, lo, hi, gridgen.tracking_factors(sd, max(steps, eager_steps), g["nb"])))
     t0 = time.perf_counter()
-    tb = TrackingBatch(items, max_batch=256, nstreams=8)
+    tb = TrackingBatch(items, max_batch=256, nstreams=8, mode=mode, qp_iters=qp_iters)
     setup_s = time.perf_counter() - t0
     n = len(items)
 
-    def run(fn):
+    def run(fn, nsteps):
         lat = []
         torch.cuda.synchronize()
         T0 = time.perf_counter()
-        for t in range(steps):
+        for t in range(nsteps):
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             e0.record()
             fn(t)
@@ -414,33 +422,146 @@ def tracking_bench(a):
     tb.step_eager(0)                      # warm-up
     torch.cuda.synchronize()
     tb.load_state(s0)
-    te, le = run(tb.step_eager)
-    st_e = [i.status.cpu().numpy().copy() for i in tb.inst]
+    te, le = run(tb.step_eager, eager_steps)
     tb.load_state(s0)
     tb.capture()
     tb.load_state(s0)
-    tg, lg = run(tb.step_graph)
-    st_g = [i.status.cpu().numpy().copy() for i in tb.inst]
-    acc = np.array([s[1] for s in st_g])
+    tg, lg = run(tb.step_graph, steps)
+    st_g = np.array([i.status.cpu().numpy().copy() for i in tb.inst])
     out = {
-        "metric": "batched real-time tracking: instances/s and step latency (64 grids, FP64)",
-        "value": round(n * steps / tg, 1), "unit": "instances/s", "n_gpus": 1, "steps": steps,
-        "higher_is_better": True, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": f"{n} grids, n_b in [{min(int(i.grid['nb']) for i in items)}, "
-                               f"{max(int(i.grid['nb']) for i in items)}], one tracking update per grid "
-                               f"and step (power flow, gradient, full reduced Hessian, Cholesky step, "
-                               f"halving on power-flow failure, multiplier update)",
-                   "streams": tb.nstreams},
+        "workload": f"{n} grids, n_b in [{min(int(i.grid['nb']) for i in items)}, "
+                    f"{max(int(i.grid['nb']) for i in items)}], one tracking update per grid and step "
+                    + ("(power flow, gradient, full reduced Hessian, Cholesky step, halving on power-flow "
+                       "failure, multiplier update)" if mode == "newton" else
+                       "(power flow, reduced Hessian and Jacobian, bounded QP by the interior-point method, "
+                       "halving on power-flow failure, multiplier update)"),
+        "mode": mode, "steps": steps, "streams": tb.nstreams,
         "graph": {"instances_per_s": round(n * steps / tg, 1), "p50_ms": round(float(np.percentile(lg, 50)), 3),
                   "p99_ms": round(float(np.percentile(lg, 99)), 3)},
-        "eager_per_instance": {"instances_per_s": round(n * steps / te, 1),
+        "eager_per_instance": {"steps": eager_steps, "instances_per_s": round(n * eager_steps / te, 1),
                                "p50_ms": round(float(np.percentile(le, 50)), 3),
                                "p99_ms": round(float(np.percentile(le, 99)), 3)},
-        "graph_over_eager": round(te / tg, 2),
-        "last_step_accepted_full_step": int((acc == 0).sum()), "last_step_no_step": int((acc < 0).sum()),
+        "graph_over_eager": round((te / eager_steps) / (tg / steps), 2),
+        "last_step_accepted_full_step": int((st_g[:, 1] == 0).sum()),
+        "last_step_no_step": int((st_g[:, 1] < 0).sum()),
         "setup_s": round(setup_s, 1),
     }
+    if mode == "qp":
+        out["last_step_qp_converged"] = int(st_g[:, 3].sum())
+    return out
+
+
+def tracking_bench(a):
+    import torch
+    torch.cuda.set_device(0)
+    r = tracking_leg(a.instances, a.track_steps, a.track_steps, mode=a.tracking_mode)
+    out = {
+        "metric": "batched real-time tracking: instances/s and step latency (64 grids, FP64)",
+        "value": r["graph"]["instances_per_s"], "unit": "instances/s", "n_gpus": 1, "steps": a.track_steps,
+        "higher_is_better": True, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": r.pop("workload"), "streams": r.pop("streams")},
+    }
+    out.update(r)
     print(json.dumps(out), flush=True)
+
+
+def rt_qp_leg(g, ep, pr, reps=3, iters=60, tol=1e-10):
+    """The exact real-time step (the bounded QP of eq. qp_rto) at the
+    workload's evaluation point, timed like the paper's real-time table: the
+    QP data alone (power flow state given; reduced gradient, Hessian and
+    Jacobian from the identity batches) and the whole step with its
+    interior-point iterations.  The shift is the one that makes the QP
+    strictly convex at this point (1.5 |most negative eigenvalue of
+    H - rho J^T D^2 J| + 1e-2)."""
+    import numpy as np
+    import torch
+
+    import gridgen
+    nu, m = pr.nu, pr.m
+    s, y, rho, sigma = pr.point(ep)
+    x = pr.flat_x()
+    pr.grid.pf_solve(pr.u0, pr.pd, pr.qd, x)
+    sz = torch.zeros(m, dtype=torch.float64, device="cuda")
+    _, c = pr.grid.al_objective(x, pr.u0, pr.pd, pr.qd, sz, y, rho, sigma)
+    lo, hi = gridgen.constraint_bounds(g)
+    slo = torch.tensor(lo, device="cuda")
+    shi = torch.tensor(hi, device="cuda")
+    s = torch.minimum(torch.maximum(c, slo), shi).contiguous()
+    ul, uh = pr.u_bounds()
+    ulo = torch.tensor(ul, device="cuda")
+    uhi = torch.tensor(uh, device="cuda")
+    H = torch.empty((nu, nu), dtype=torch.float64, device="cuda")
+    J = torch.empty((m, nu), dtype=torch.float64, device="cuda")
+    q = pr.grid.qp_step(x, pr.u0, pr.pd, pr.qd, s, y, rho, sigma, 0.0, ulo, uhi, slo, shi, max_iter=0, H=H, J=J)
+    Huu = H - rho * (J.T.contiguous() @ ((sigma[1:] ** 2)[:, None] * J))
+    delta = 1.5 * max(0.0, -float(torch.linalg.eigvalsh(0.5 * (Huu + Huu.T)).min())) + 1e-2
+    del Huu
+
+    def timed(max_iter):
+        ts = []
+        for _ in range(reps + 1):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = pr.grid.qp_step(x, pr.u0, pr.pd, pr.qd, s, y, rho, sigma, delta, ulo, uhi, slo, shi,
+                                max_iter=max_iter, tol=tol, H=H, J=J)
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        return float(np.median(ts[1:])) * 1e3, r
+
+    t_data, _ = timed(0)
+    t_all, r = timed(iters)
+    st = r["status"].cpu().numpy()
+    return {"what": "exact real-time step at the evaluation point: QP data (reduced gradient, Hessian, "
+                    "Jacobian) + bounded QP by the interior-point method with Schur-complement solves",
+            "n": nu + m, "delta": delta, "iterations": int(st[0]), "factorizations": int(st[5]),
+            "converged": bool(st[1]), "kkt": float(r["kkt"][0]),
+            "qp_data_ms": round(t_data, 3), "qp_iterations_ms": round(t_all - t_data, 3),
+            "total_ms": round(t_all, 3),
+            "ms_per_iteration": round((t_all - t_data) / max(1, int(st[5])), 3)}
+
+
+def load_drop_leg(name="syn2000", steps=60, t_drop=2, drop=0.2, qp_iters=60):
+    """Tracking with the exact step through a sudden load drop (the paper's
+    real-time experiment): all loads at their base values, then (1 - drop)
+    times them from step t_drop on, the PV dispatch scaled with the total
+    load at the drop; eager, one grid."""
+    import numpy as np
+    import torch
+
+    import gridgen
+    from paper_2110_02590_amd.tracking import TrackingBatch, TrackingItem
+
+    g = gridgen.grid(name)
+    ep = gridgen.eval_point(g)
+    lo, hi = gridgen.constraint_bounds(g)
+    it = TrackingItem(g, ep, lo, hi, gridgen.load_drop_factors(g["nb"], steps=steps, t_drop=t_drop, drop=drop))
+    tb = TrackingBatch([it], max_batch=256, nstreams=1, mode="qp", qp_iters=qp_iters, redispatch=True)
+    inst = tb.inst[0]
+    lat, stat = [], []
+    for t in range(steps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        tb.step_eager(t)
+        e1.record()
+        e1.synchronize()
+        lat.append(e0.elapsed_time(e1))
+        stat.append(inst.status.cpu().numpy().copy())
+    stat = np.array(stat)
+    # constraint violation at the final point (host check of the device state)
+    pr = inst.pr
+    fac = torch.tensor(it.factors[-1], device="cuda")
+    _, c = pr.grid.al_objective(inst.x, inst.u, pr.pd * fac, pr.qd * fac, inst.s, inst.y, inst.rho, inst.sigma)
+    c = c.cpu().numpy()
+    viol = float(np.max(np.maximum(0.0, np.maximum(c - hi, lo - c))))
+    lat = np.array(lat)
+    return {"workload": f"{name}: {g['nb']} buses, {steps} steps, loads x{1 - drop:.2f} from step {t_drop}",
+            "p50_ms": round(float(np.percentile(lat, 50)), 3), "p99_ms": round(float(np.percentile(lat, 99)), 3),
+            "drop_step_ms": round(float(lat[t_drop]), 3),
+            "steps_power_flow_converged": int(stat[:, 0].sum()),
+            "steps_full_step_accepted": int((stat[:, 1] == 0).sum()),
+            "steps_qp_converged": int(stat[:, 3].sum()),
+            "qp_iterations_p50": float(np.percentile(stat[:, 2], 50)),
+            "final_max_violation": viol}
 
 
 def _cpu_model():
