@@ -339,14 +339,17 @@ int rpf_profile_read_busy(rpf_grid* grid, double* ms, int64_t* launches, double*
 
 /* Host-only presolve introspection (no device needed), for checking the
  * index maps and the symbolic factorization:
- *   rpf_presolve_info: out16 = {n_x, n_u, m, nnz(J_x), nnz(L+U), forward
+ *   rpf_presolve_info: out20 = {n_x, n_u, m, nnz(J_x), nnz(L+U), forward
  *   levels, backward levels, longest LU row, refactorization updates,
  *   nnz(J_u), nnz(K), nnz(rank-one rows), packs of independent subtrees,
- *   rows of the top part, most levels in one pack, levels of the top part}.
+ *   rows of the top part, most levels in one pack, levels of the top part,
+ *   most forward / backward levels of a pack in the batched solves (dense
+ *   tails taken out), rows in dense tails, tail limit (RPF_TAIL_MAX,
+ *   0 .. 128, read at each call; default 128)}.
  *   rpf_presolve_pattern: perm [n_x] (internal state index -> paper x
  *   index), lu_ptr [n_x + 1], lu_col [nnz(L+U)] (internal order, sorted
  *   columns, diagonal included); any pointer may be NULL. */
-int rpf_presolve_info(const rpf_grid_desc* desc, int64_t* out16);
+int rpf_presolve_info(const rpf_grid_desc* desc, int64_t* out20);
 int rpf_presolve_pattern(const rpf_grid_desc* desc, int32_t* perm, int32_t* lu_ptr, int32_t* lu_col);
 
 /* Message for the last nonzero return on this thread. */

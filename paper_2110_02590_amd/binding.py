@@ -131,11 +131,11 @@ class _HostDesc:
 def presolve_info(g: dict) -> dict:
     """Host-only presolve figures (no GPU needed)."""
     d = _HostDesc(g)
-    out = np.zeros(16, dtype=np.int64)
+    out = np.zeros(20, dtype=np.int64)
     _check(lib().rpf_presolve_info(d.ref(), out.ctypes.data))
     keys = ["nx", "nu", "m", "nnz_jx", "nnz_lu", "nlev_lo", "nlev_up", "max_lu_row",
             "refactor_updates", "nnz_ju", "nnz_k", "nnz_g", "npacks", "ntop", "max_pack_levels",
-            "top_levels"]
+            "top_levels", "max_tail_fwd_levels", "max_tail_bwd_levels", "tail_rows", "tail_max"]
     return dict(zip(keys, out.tolist()))
 
 

@@ -18,6 +18,7 @@ namespace dev {
 using rpf::RECW;
 using rpf::WREC;
 constexpr int CB = 64;  // dense block width
+using rpf::TAIL_MAX;   // leading dimension of the dense pack tails
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 
 // Staging through LDS issues all of a thread's loads before its first
@@ -1319,7 +1320,55 @@ __global__ void __launch_bounds__(1024) k_pack_solve_g(const int32_t* __restrict
 // slev[nlev + 1] (int) | srow[nr] | scol[ne] (int16).
 __host__ __device__ __forceinline__ size_t packt_lds_bytes(int nr, int ne, int nlev, int tw, bool sv) {
   return (sv ? (size_t)ne * 8 : 0) + (size_t)nr * tw * 8 + (size_t)(nr + 1) * 4 + (size_t)(nlev + 1) * 4 +
-         (size_t)nr * 2 + (size_t)ne * 2 + 16;
+         (size_t)nr * 2 + (size_t)ne * 2 + 2 * TAIL_MAX + 16;
+}
+
+// Dense tail of a pack (the rows T near the subtree roots, rows sT[0 .. nT)
+// of the tile, ascending): x_T <- M x_T with M the dense inverse of the
+// factor's T x T block (row-major, leading dimension TAIL_MAX; lower
+// triangular for the forward solves, upper for the backward ones).  Thread
+// t computes column t % TW of rows t / TW + k (1024 / TW), k < passes, all
+// reads before the barrier, then the stores.
+template <int TW>
+__device__ __forceinline__ void tail_apply(double* xs, const int16_t* sT, int nT, const double* __restrict__ M,
+                                           bool lower) {
+  constexpr int RPP = 1024 / TW;
+  constexpr int NP = (TAIL_MAX + RPP - 1) / RPP;
+  const int t = threadIdx.x;
+  const int c = t & (TW - 1), i0 = t / TW;
+  double acc[NP];
+#pragma unroll
+  for (int pp = 0; pp < NP; ++pp) {
+    const int i = i0 + pp * RPP;
+    double a0 = 0.0, a1 = 0.0;
+    if (i < nT) {
+      const double* mrow = M + (size_t)i * TAIL_MAX;
+      const int k0 = lower ? 0 : i, k1 = lower ? i + 1 : nT;
+      int k = k0;
+      for (; k + 8 <= k1; k += 8) {
+        double mv[8], xv[8];
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {
+          mv[m] = mrow[k + m];
+          xv[m] = xs[sT[k + m] * TW + c];
+        }
+#pragma unroll
+        for (int m = 0; m < 8; m += 2) {
+          a0 += mv[m] * xv[m];
+          a1 += mv[m + 1] * xv[m + 1];
+        }
+      }
+      for (; k < k1; ++k) a0 += mrow[k] * xs[sT[k] * TW + c];
+    }
+    acc[pp] = a0 + a1;
+  }
+  lds_barrier();
+#pragma unroll
+  for (int pp = 0; pp < NP; ++pp) {
+    const int i = i0 + pp * RPP;
+    if (i < nT) xs[sT[i] * TW + c] = acc[pp];
+  }
+  lds_barrier();
 }
 
 template <int TW, bool FWD, bool UNIT, bool SV>
@@ -1336,6 +1385,9 @@ __global__ void __launch_bounds__(1024) k_pack_solve_t(const int32_t* __restrict
                                                        const int32_t* __restrict__ col,
                                                        const double* __restrict__ val, double* __restrict__ X,
                                                        int ld, int ncols, double scale, int npacks, int ntiles,
+                                                       const int32_t* __restrict__ toff,
+                                                       const int16_t* __restrict__ trows,
+                                                       const double* __restrict__ tinv,
                                                        const int32_t* __restrict__ skip) {
   if (skip && *skip) return;
   constexpr int S = 64 / TW;   // lanes per column in a wavefront
@@ -1353,19 +1405,24 @@ __global__ void __launch_bounds__(1024) k_pack_solve_t(const int32_t* __restrict
   const int e0 = rp[r0], ne = rp[r0 + nr] - e0;
   const int l0 = lev_off[q], nlev = lev_off[q + 1] - l0;
   const int base_row = lev[l0];
+  const int nprog = lev[l0 + nlev] - base_row;   // rows of the program (the tail rows are not
+                                                 // in the backward one)
+  const int tq = toff ? toff[q] : 0, nT = toff ? toff[q + 1] - tq : 0;
   double* sval = smem;
   double* xs = smem + (SV ? ne : 0);
   int* smeta = (int*)(xs + (size_t)nr * TW);
   int* slev = smeta + nr + 1;
   int16_t* srow = (int16_t*)(slev + nlev + 1);
   int16_t* scol = srow + nr;
+  int16_t* sT = scol + ne;
   const int t = threadIdx.x, nt = blockDim.x;
   stage_1d(scol, ecol + e0, ne);
   if (SV) stage_1d(sval, pval + e0, ne);
+  for (int k = t; k < nT; k += nt) sT[k] = trows[tq + k];
   // per level position: the row, and its first entry | length << 20 (entries
   // of a pack below 2^20, row lengths below 2^11: checked on the host), so
   // that both come from one LDS round trip
-  for (int p = t; p < nr; p += nt) {
+  for (int p = t; p < nprog; p += nt) {
     const int row = lrows[base_row + p] - r0;
     const int es = rp[r0 + row], ee = rp[r0 + row + 1];
     srow[p] = (int16_t)row;
@@ -1387,11 +1444,17 @@ __global__ void __launch_bounds__(1024) k_pack_solve_t(const int32_t* __restrict
       if (eb + m * nt < ntile) xs[eb + m * nt] = FWD ? scale * v[m] : v[m];
   }
   __syncthreads();
+  const double* Mq = tinv + (size_t)q * TAIL_MAX * TAIL_MAX;
+  // backward: the tail rows first, by the dense inverse of U_TT (or L_TT^T)
+  if (!FWD && nT > 0) tail_apply<TW>(xs, sT, nT, Mq, false);
   const int wave = t >> 6, lane = t & 63, nwave = nt >> 6;
   const int cI = lane & (TW - 1);
   const int sub = lane / TW;   // 0 .. S - 1
   for (int lv = 0; lv < nlev; ++lv) {
     const int a = slev[lv], nrow = slev[lv + 1] - a;
+    // forward: the last level holds the tail rows, gathering only their
+    // entries outside the tail (no pivot: the dense inverse has it)
+    const bool gather = FWD && nT > 0 && lv == nlev - 1;
     // R = 2^lgR rows per wavefront, G = S / R lanes per (row, column)
     int lgR = LGS;
     while (lgR > 0 && nrow <= (nwave << (lgR - 1))) --lgR;
@@ -1438,15 +1501,96 @@ __global__ void __launch_bounds__(1024) k_pack_solve_t(const int32_t* __restrict
       }
       if (act && seg == 0) {
         double v = xo - part;
-        if (!UNIT) v *= rdv;
+        if (!UNIT && !gather) v *= rdv;
         xs[rl * TW + cI] = v;
       }
     }
     lds_barrier();
   }
+  // forward: the tail rows by the dense inverse of L_TT (or U_TT^T)
+  if (FWD && nT > 0) tail_apply<TW>(xs, sT, nT, Mq, true);
   for (int e = t; e < ntile; e += nt) {
     const int r = e / TW, c = e - r * TW;
     if (c0 + c < ncols) X[(size_t)(r0 + r) * ld + c0 + c] = xs[e];
+  }
+}
+
+// Dense T x T blocks of the pack tails from the LU values: A[q][0] = L_TT
+// (unit diagonal), A[q][1] = U_TT, row-major with leading dimension
+// TAIL_MAX, zero elsewhere (k_fill_dbl first).  One thread per entry.
+__global__ void k_tail_gather(int ne, const int32_t* __restrict__ eoff, int npacks, const int32_t* __restrict__ pos,
+                              const int32_t* __restrict__ dense, const int32_t* __restrict__ toff,
+                              const double* __restrict__ luv, double* __restrict__ A,
+                              const int32_t* __restrict__ skip) {
+  if (skip && *skip) return;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < ne) {
+    int lo = 0, hi = npacks;   // pack of entry e: eoff[q] <= e < eoff[q + 1]
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (eoff[mid] <= e) lo = mid;
+      else hi = mid;
+    }
+    const int q = lo;
+    const int d = dense[e];
+    const int a = d / TAIL_MAX, b = d - a * TAIL_MAX;
+    double* Aq = A + (size_t)q * 2 * TAIL_MAX * TAIL_MAX;
+    if (b < a) Aq[d] = luv[pos[e]];
+    else Aq[TAIL_MAX * TAIL_MAX + d] = luv[pos[e]];
+    if (a == b) Aq[d] = 1.0;
+  }
+}
+
+// Inverses of the tail blocks, one workgroup per (pack, part): part 0
+// inverts L_TT (unit lower) row by row, X_i = e_i - sum_{k<i} L_ik X_k;
+// part 1 inverts U_TT from the last row, X_i = (e_i - sum_{k>i} U_ik X_k)
+// / U_ii.  X lives in LDS (nT x TAIL_MAX); thread (column j, group g)
+// sums the k = g (mod 1024 / TAIL_MAX) terms, the groups are added in a
+// fixed order.  Out: Minv[0] = L_TT^-1, [1] = U_TT^-1, [2] = (L_TT^-1)^T,
+// [3] = (U_TT^-1)^T, each [npacks][TAIL_MAX x TAIL_MAX] (rows and columns
+// past nT left as they are: never read).
+__global__ void __launch_bounds__(1024) k_tail_inv(const int32_t* __restrict__ toff, const double* __restrict__ A,
+                                                   double* __restrict__ Minv, int npacks,
+                                                   const int32_t* __restrict__ skip) {
+  if (skip && *skip) return;
+  extern __shared__ double X[];
+  __shared__ double red[1024];
+  constexpr int KG = 1024 / TAIL_MAX;
+  const int q = blockIdx.x, part = blockIdx.y;
+  const int nT = toff[q + 1] - toff[q];
+  if (nT == 0) return;
+  const double* Aq = A + ((size_t)q * 2 + part) * TAIL_MAX * TAIL_MAX;
+  const int t = threadIdx.x, j = t % TAIL_MAX, g = t / TAIL_MAX;
+  for (int step = 0; step < nT; ++step) {
+    const int i = part == 0 ? step : nT - 1 - step;
+    double s0 = 0.0;
+    if (j < nT) {
+      if (part == 0) {
+        for (int k = g; k < i; k += KG) s0 += Aq[(size_t)i * TAIL_MAX + k] * X[k * TAIL_MAX + j];
+      } else {
+        for (int k = i + 1 + g; k < nT; k += KG) s0 += Aq[(size_t)i * TAIL_MAX + k] * X[k * TAIL_MAX + j];
+      }
+    }
+    red[t] = s0;
+    __syncthreads();
+    if (g == 0 && j < nT) {
+      double tot = red[j];
+      for (int gg = 1; gg < KG; ++gg) tot += red[gg * TAIL_MAX + j];
+      const double v = (i == j ? 1.0 : 0.0) - tot;
+      X[i * TAIL_MAX + j] = part == 0 ? v : v / Aq[(size_t)i * TAIL_MAX + i];
+    }
+    __syncthreads();
+  }
+  const size_t blk = (size_t)TAIL_MAX * TAIL_MAX, n4 = (size_t)npacks * blk;
+  double* Mo = Minv + (size_t)part * n4 + (size_t)q * blk;
+  double* Mt = Minv + (size_t)(2 + part) * n4 + (size_t)q * blk;
+  for (int e = t; e < nT * TAIL_MAX; e += blockDim.x) {
+    const int r = e / TAIL_MAX, c = e - r * TAIL_MAX;
+    if (c < nT) {
+      const double v = X[e];
+      Mo[(size_t)r * TAIL_MAX + c] = v;
+      Mt[(size_t)c * TAIL_MAX + r] = v;
+    }
   }
 }
 

@@ -108,9 +108,11 @@ void to_lists(int nslots, std::vector<std::pair<int, int>>& pairs, std::vector<i
 
 }  // namespace
 
-Presolve build_presolve(const GridData& g, int subtree_max) {
+Presolve build_presolve(const GridData& g, int subtree_max, int tail_max) {
   Presolve P;
   P.subtree_max = subtree_max;
+  if (tail_max < 0 || tail_max > TAIL_MAX) fail("tail_max must be in [0, 128]");
+  P.tail_max = tail_max;
   const int nb = g.nb, nl = g.nl, ng = g.ng;
   if (nb < 2 || nl < 1 || ng < 1) fail("grid needs nb >= 2, nl >= 1, ng >= 1");
   if ((int)g.bus_type.size() != nb || (int)g.br_from.size() != nl || (int)g.br_to.size() != nl ||
@@ -440,6 +442,103 @@ Presolve build_presolve(const GridData& g, int subtree_max) {
         P.pkb_rp[i + 1] = (int32_t)P.pkb_pos.size();
       }
     }
+    // dense tails and the batched programs (see Presolve::ptl_*)
+    {
+      const int TD = P.tail_max;
+      P.ptl_off.assign(npk + 1, 0);
+      P.ptl_eoff.assign(npk + 1, 0);
+      P.ptl_rows.clear(); P.ptl_pos.clear(); P.ptl_dense.clear();
+      P.ptf_lev.assign(1, 0); P.ptb_lev.assign(1, 0);
+      P.ptf_lev_off.assign(npk + 1, 0); P.ptb_lev_off.assign(npk + 1, 0);
+      P.ptf_rows.clear(); P.ptb_rows.clear();
+      P.ptf_rp.assign(t0 + 1, 0); P.ptb_rp.assign(t0 + 1, 0);
+      P.ptf_pos.clear(); P.ptf_col.clear(); P.ptb_pos.clear(); P.ptb_col.clear();
+      std::vector<int> hgt(nx, 0), tix(nx, -1), blv(nx, 0);
+      for (int q = 0; q < npk; ++q) {
+        const int r0 = P.pack_ptr[q], r1 = P.pack_ptr[q + 1];
+        int hmax = 0;
+        for (int i = r0; i < r1; ++i) {
+          int v = 0;
+          for (int k : lrow[i]) v = std::max(v, hgt[k] + 1);
+          hgt[i] = v;
+          hmax = std::max(hmax, v);
+        }
+        // cut hc: the fewest levels left with at most TD rows at heights >= hc
+        std::vector<int> cnt(hmax + 1, 0);
+        for (int i = r0; i < r1; ++i) cnt[hgt[i]]++;
+        int hc = hmax + 1, acc = 0;
+        while (hc > 0 && acc + cnt[hc - 1] <= TD) acc += cnt[--hc];
+        int nT = 0;
+        for (int i = r0; i < r1; ++i) {
+          tix[i] = hgt[i] >= hc ? nT++ : -1;
+          if (tix[i] >= 0) P.ptl_rows.push_back((int16_t)(i - r0));
+        }
+        P.ptl_off[q + 1] = (int)P.ptl_rows.size();
+        // an ancestor-closed T: the parent of a T row is in T (heights grow
+        // towards the root), so no other row depends on a T row going up
+        for (int i = r0; i < r1; ++i)
+          if (tix[i] < 0)
+            for (int k : lrow[i])
+              if (tix[k] >= 0) fail("internal: tail rows are not ancestor-closed");
+        for (int i = r0; i < r1; ++i) {
+          if (tix[i] < 0) continue;
+          for (int p = P.lu_ptr[i]; p < P.lu_ptr[i + 1]; ++p) {
+            const int c = P.lu_col[p];
+            if (c >= r0 && c < r1 && tix[c] >= 0) {
+              P.ptl_pos.push_back(p);
+              P.ptl_dense.push_back(tix[i] * TAIL_MAX + tix[c]);
+            }
+          }
+        }
+        P.ptl_eoff[q + 1] = (int)P.ptl_pos.size();
+        // forward: other rows by height, then the T rows as one level
+        std::vector<std::vector<int>> byl(hc + (nT > 0 ? 1 : 0));
+        for (int i = r0; i < r1; ++i) byl[tix[i] >= 0 ? hc : hgt[i]].push_back(i);
+        for (auto& b : byl) {
+          if (b.empty()) continue;
+          P.ptf_rows.insert(P.ptf_rows.end(), b.begin(), b.end());
+          P.ptf_lev.push_back((int)P.ptf_rows.size());
+        }
+        P.ptf_lev_off[q + 1] = (int)P.ptf_lev.size() - 1;
+        // backward: the other rows, levels over their dependencies among
+        // themselves (the T rows are done first)
+        int nbl = 0;
+        for (int i = r1 - 1; i >= r0; --i) {
+          if (tix[i] >= 0) continue;
+          int v = 0;
+          for (int j : urow[i])
+            if (j < r1 && tix[j] < 0) v = std::max(v, blv[j] + 1);
+          blv[i] = v;
+          nbl = std::max(nbl, v + 1);
+        }
+        std::vector<std::vector<int>> byb(nbl);
+        for (int i = r0; i < r1; ++i)
+          if (tix[i] < 0) byb[blv[i]].push_back(i);
+        for (auto& b : byb) {
+          P.ptb_rows.insert(P.ptb_rows.end(), b.begin(), b.end());
+          P.ptb_lev.push_back((int)P.ptb_rows.size());
+        }
+        P.ptb_lev_off[q + 1] = (int)P.ptb_lev.size() - 1;
+        // staged entries: forward, a T row keeps only its columns outside T;
+        // backward, T rows have none
+        for (int i = r0; i < r1; ++i) {
+          for (int p = P.lu_ptr[i]; p < P.lu_diag[i]; ++p) {
+            const int c = P.lu_col[p];
+            if (tix[i] >= 0 && tix[c] >= 0) continue;
+            P.ptf_pos.push_back(p);
+            P.ptf_col.push_back((int16_t)(c - r0));
+          }
+          P.ptf_rp[i + 1] = (int32_t)P.ptf_pos.size();
+          if (tix[i] < 0) {
+            for (int p = P.lu_diag[i] + 1; p < P.up_split[i]; ++p) {
+              P.ptb_pos.push_back(p);
+              P.ptb_col.push_back((int16_t)(P.lu_col[p] - r0));
+            }
+          }
+          P.ptb_rp[i + 1] = (int32_t)P.ptb_pos.size();
+        }
+      }
+    }
     // top part: forward levels over top-internal lower entries, backward over upper
     std::vector<int> tl(nx, 0);
     int ntf = 0, ntb = 0;
@@ -709,6 +808,14 @@ PresolveStats stats(const Presolve& p) {
   for (int64_t q = 0; q < s.npacks; ++q)
     mx = std::max<int64_t>(mx, p.pk_flev_off[q + 1] - p.pk_flev_off[q]);
   s.max_pack_levels = mx;
+  int64_t mf = 0, mb = 0;
+  for (size_t q = 0; q + 1 < p.ptf_lev_off.size(); ++q) {
+    mf = std::max<int64_t>(mf, p.ptf_lev_off[q + 1] - p.ptf_lev_off[q]);
+    mb = std::max<int64_t>(mb, p.ptb_lev_off[q + 1] - p.ptb_lev_off[q]);
+  }
+  s.max_tail_fwd_levels = mf;
+  s.max_tail_bwd_levels = mb;
+  s.tail_rows = (int64_t)p.ptl_rows.size();
   s.top_levels = (int64_t)p.top_flev.size() - 1;
   return s;
 }

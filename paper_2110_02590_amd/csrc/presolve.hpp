@@ -36,6 +36,8 @@ constexpr int RECW = 20;
 // Branch second-order record: 4x4 symmetric W (row-major, 16 doubles) and
 // the local gradient (4 doubles).
 constexpr int WREC = 20;
+// leading dimension of the dense tail blocks (and the largest tail)
+constexpr int TAIL_MAX = 128;
 
 struct Levels {
   std::vector<int32_t> ptr;   // [nlev + 1]
@@ -84,6 +86,23 @@ struct Presolve {
   // columns), likewise pkb_*
   std::vector<int32_t> pkf_rp, pkf_pos, pkb_rp, pkb_pos;
   std::vector<int16_t> pkf_col, pkb_col;
+  // dense tails of the packs for the batched solves.  In pack q the rows
+  // whose forward level (height in the elimination tree) is at least the
+  // pack's cut form an ancestor-closed set T_q of at most tail_max rows
+  // (the chains near the subtree roots): ptl_rows[ptl_off[q] ..
+  // ptl_off[q+1]) (pack-local, ascending).  The entries of the LU pattern
+  // inside T_q x T_q are ptl_pos (LU positions) with dense offsets ptl_dense
+  // (a * TAIL_MAX + b, a = row, b = column index within T_q), pack q's from
+  // ptl_eoff[q].  The batched programs (levels, rows, staged entries, as
+  // pk_*): forward = the other rows by level, then one level of the T rows
+  // with only their entries outside T_q; backward = the other rows by level
+  // (the T rows are solved before them with the dense inverse).
+  int tail_max = 128;
+  std::vector<int32_t> ptl_off, ptl_eoff, ptl_pos, ptl_dense;
+  std::vector<int16_t> ptl_rows;
+  std::vector<int32_t> ptf_lev, ptf_lev_off, ptf_rows, ptb_lev, ptb_lev_off, ptb_rows;
+  std::vector<int32_t> ptf_rp, ptf_pos, ptb_rp, ptb_pos;
+  std::vector<int16_t> ptf_col, ptb_col;
   // top-part levels (global row ids)
   std::vector<int32_t> top_flev, top_frows, top_blev, top_brows;
   // dense top block: LU positions and their dense (row-major) offsets
@@ -130,11 +149,12 @@ struct Presolve {
 
 // Throws std::runtime_error with a message on invalid input.
 // subtree_max bounds the rows of one pack of independent subtrees.
-Presolve build_presolve(const GridData& g, int subtree_max = 1024);
+Presolve build_presolve(const GridData& g, int subtree_max = 1024, int tail_max = 128);
 
 struct PresolveStats {
   int64_t nnz_jx, nnz_lu, nlev_lo, nlev_up, max_lu_row, refactor_updates, nnz_ju, nnz_k, nnz_g;
   int64_t npacks, ntop, max_pack_levels, top_levels;
+  int64_t max_tail_fwd_levels, max_tail_bwd_levels, tail_rows;   // batched programs with dense tails
 };
 PresolveStats stats(const Presolve& p);
 

@@ -93,8 +93,16 @@ struct rpf_grid {
   int tw_packt = 0;       // column tile of the LDS-tile batched pack solves (0: not used)
   bool sv_packt = false;  // factor values staged in LDS too
   size_t lds_packt = 0;
-  // factor values in pack-program order: forward / backward, J_x / J_x^T
+  // factor values in the batched programs' order: forward / backward, J_x / J_x^T
   double *pkfv = nullptr, *pkbv = nullptr, *pkfvT = nullptr, *pkbvT = nullptr;
+  // batched programs with dense pack tails (Presolve::ptf_* / ptb_* / ptl_*),
+  // the tail blocks and their inverses [4][npacks][TAIL_MAX^2] (L_TT^-1,
+  // U_TT^-1 and their transposes)
+  int32_t *ptf_lev, *ptf_lev_off, *ptf_rows, *ptf_rp, *ptf_pos, *ptb_lev, *ptb_lev_off, *ptb_rows, *ptb_rp,
+      *ptb_pos;
+  int16_t *ptf_col, *ptb_col, *ptl_rows;
+  int32_t *ptl_off, *ptl_eoff, *ptl_pos, *ptl_dense;
+  double *tailA = nullptr, *tailM = nullptr;
   size_t lds_limit = 65536, lds_pack[5] = {0, 0, 0, 0, 0};
   double *c2, *c1, *c0;
   // predication word for the Hessian-product batches (set while the bounded
@@ -314,11 +322,33 @@ void setup(rpf_grid* h) {
   h->pkb_rp = h->up(P.pkb_rp);
   h->pkb_pos = h->up(P.pkb_pos);
   h->pkb_col = h->up(P.pkb_col);
+  h->ptf_lev = h->up(P.ptf_lev);
+  h->ptf_lev_off = h->up(P.ptf_lev_off);
+  h->ptf_rows = h->up(P.ptf_rows);
+  h->ptf_rp = h->up(P.ptf_rp);
+  h->ptf_pos = h->up(P.ptf_pos);
+  h->ptf_col = h->up(P.ptf_col);
+  h->ptb_lev = h->up(P.ptb_lev);
+  h->ptb_lev_off = h->up(P.ptb_lev_off);
+  h->ptb_rows = h->up(P.ptb_rows);
+  h->ptb_rp = h->up(P.ptb_rp);
+  h->ptb_pos = h->up(P.ptb_pos);
+  h->ptb_col = h->up(P.ptb_col);
+  h->ptl_off = h->up(P.ptl_off);
+  h->ptl_rows = h->up(P.ptl_rows);
+  h->ptl_eoff = h->up(P.ptl_eoff);
+  h->ptl_pos = h->up(P.ptl_pos);
+  h->ptl_dense = h->up(P.ptl_dense);
+  {
+    const size_t npk = P.pack_ptr.size() - 1, blk = (size_t)TAIL_MAX * TAIL_MAX;
+    h->tailA = h->alloc<double>(std::max<size_t>(1, npk * 2 * blk));
+    h->tailM = h->alloc<double>(std::max<size_t>(1, npk * 4 * blk));
+  }
   // padded: the batched pack solves prefetch up to one entry past a pack
-  h->pkfv = h->alloc<double>(P.pkf_pos.size() + 64);
-  h->pkfvT = h->alloc<double>(P.pkf_pos.size() + 64);
-  h->pkbv = h->alloc<double>(P.pkb_pos.size() + 64);
-  h->pkbvT = h->alloc<double>(P.pkb_pos.size() + 64);
+  h->pkfv = h->alloc<double>(P.ptf_pos.size() + 64);
+  h->pkfvT = h->alloc<double>(P.ptf_pos.size() + 64);
+  h->pkbv = h->alloc<double>(P.ptb_pos.size() + 64);
+  h->pkbvT = h->alloc<double>(P.ptb_pos.size() + 64);
   h->dense_top = h->alloc<double>((size_t)P.ntop * P.ntop);
   h->dense_topT = h->alloc<double>((size_t)P.ntop * P.ntop);
   h->top_dinv = h->alloc<double>((size_t)cdiv(P.ntop, CB) * 2 * CB * CB);
@@ -368,7 +398,7 @@ void setup(rpf_grid* h) {
       bool fits_word = true;
       for (int q = 0; q < h->npacks; ++q) {
         const int r0 = P.pack_ptr[q], nr = P.pack_ptr[q + 1] - r0;
-        for (const auto* rpv : {&P.pkf_rp, &P.pkb_rp}) {
+        for (const auto* rpv : {&P.ptf_rp, &P.ptb_rp}) {
           if ((*rpv)[r0 + nr] - (*rpv)[r0] >= (1 << 20)) fits_word = false;
           for (int r = r0; r < r0 + nr; ++r)
             if ((*rpv)[r + 1] - (*rpv)[r] >= (1 << 11)) fits_word = false;
@@ -379,8 +409,8 @@ void setup(rpf_grid* h) {
         size_t mx = 0;
         for (int q = 0; q < h->npacks; ++q) {
           const int r0 = P.pack_ptr[q], nr = P.pack_ptr[q + 1] - r0;
-          const int nef = P.pkf_rp[r0 + nr] - P.pkf_rp[r0], neb = P.pkb_rp[r0 + nr] - P.pkb_rp[r0];
-          const int nlf = P.pk_flev_off[q + 1] - P.pk_flev_off[q], nlb = P.pk_blev_off[q + 1] - P.pk_blev_off[q];
+          const int nef = P.ptf_rp[r0 + nr] - P.ptf_rp[r0], neb = P.ptb_rp[r0 + nr] - P.ptb_rp[r0];
+          const int nlf = P.ptf_lev_off[q + 1] - P.ptf_lev_off[q], nlb = P.ptb_lev_off[q + 1] - P.ptb_lev_off[q];
           mx = std::max(mx, packt_lds_bytes(nr, std::max(nef, neb), std::max(nlf, nlb), v.tw, v.sv));
         }
         if (mx <= h->lds_limit) {
@@ -422,6 +452,8 @@ void setup(rpf_grid* h) {
       HIPCHK(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, ldsmax - (int)top_static));
     };
     allow_top((const void*)k_top_dense);
+    HIPCHK(hipFuncSetAttribute((const void*)k_tail_inv, hipFuncAttributeMaxDynamicSharedMemorySize,
+                               (int)((size_t)TAIL_MAX * TAIL_MAX * sizeof(double))));
 #define RPF_ALLOW_PACK(TW)                                  \
   allow((const void*)k_pack_solve_s<TW, true, true>);       \
   allow((const void*)k_pack_solve_s<TW, true, false>);      \
@@ -661,17 +693,23 @@ void pack_solve_t(rpf_grid* h, bool fwd, bool unit, bool transposed, const doubl
   const int ntiles = cdiv(ncols, TW);
   const dim3 grd(8 * cdiv(h->npacks, 8) * ntiles);   // see the XCD mapping in k_pack_solve_t
   const double* pv = fwd ? (transposed ? h->pkfvT : h->pkfv) : (transposed ? h->pkbvT : h->pkbv);
+  // dense tail inverse of this solve: forward L_TT^-1 (J_x) or (U_TT^-1)^T
+  // (J_x^T), backward U_TT^-1 (J_x) or (L_TT^-1)^T (J_x^T)
+  const size_t n4 = (size_t)h->npacks * TAIL_MAX * TAIL_MAX;
+  const int which = fwd ? (transposed ? 3 : 0) : (transposed ? 2 : 1);
+  const double* tinv = h->tailM + which * n4;
   auto launch = [&](auto kern, const int32_t* lev, const int32_t* lev_off, const int32_t* rows, const int32_t* rp,
                     const int16_t* ecol) {
     kern<<<grd, 1024, h->lds_packt, s>>>(h->pack_ptr, lev, lev_off, rows, rp, ecol, pv, h->rdiag, h->up_split,
-                                         h->lu_ptr, h->lu_col, val, X, ld, ncols, scale, h->npacks, ntiles, skip);
+                                         h->lu_ptr, h->lu_col, val, X, ld, ncols, scale, h->npacks, ntiles,
+                                         h->ptl_off, h->ptl_rows, tinv, skip);
   };
   if (fwd) {
-    if (unit) launch(k_pack_solve_t<TW, true, true, SV>, h->pk_flev, h->pk_flev_off, h->pk_frows, h->pkf_rp, h->pkf_col);
-    else launch(k_pack_solve_t<TW, true, false, SV>, h->pk_flev, h->pk_flev_off, h->pk_frows, h->pkf_rp, h->pkf_col);
+    if (unit) launch(k_pack_solve_t<TW, true, true, SV>, h->ptf_lev, h->ptf_lev_off, h->ptf_rows, h->ptf_rp, h->ptf_col);
+    else launch(k_pack_solve_t<TW, true, false, SV>, h->ptf_lev, h->ptf_lev_off, h->ptf_rows, h->ptf_rp, h->ptf_col);
   } else {
-    if (unit) launch(k_pack_solve_t<TW, false, true, SV>, h->pk_blev, h->pk_blev_off, h->pk_brows, h->pkb_rp, h->pkb_col);
-    else launch(k_pack_solve_t<TW, false, false, SV>, h->pk_blev, h->pk_blev_off, h->pk_brows, h->pkb_rp, h->pkb_col);
+    if (unit) launch(k_pack_solve_t<TW, false, true, SV>, h->ptb_lev, h->ptb_lev_off, h->ptb_rows, h->ptb_rp, h->ptb_col);
+    else launch(k_pack_solve_t<TW, false, false, SV>, h->ptb_lev, h->ptb_lev_off, h->ptb_rows, h->ptb_rp, h->ptb_col);
   }
   LAUNCHCHK();
 }
@@ -1089,14 +1127,22 @@ static int subtree_max() {
   return smax;
 }
 
+// rows of the dense tail of each pack in the batched solves (0 = none)
+static int tail_max() {
+  int t = 128;
+  if (const char* e = std::getenv("RPF_TAIL_MAX")) t = std::max(0, std::min(128, std::atoi(e)));
+  return t;
+}
+
 int rpf_presolve_info(const rpf_grid_desc* desc, int64_t* o) {
   if (!o) return set_err(RPF_EINVAL, "out is NULL");
   return guard([&]() -> int {
-    Presolve P = build_presolve(grid_from_desc(desc), subtree_max());
+    Presolve P = build_presolve(grid_from_desc(desc), subtree_max(), tail_max());
     PresolveStats st = stats(P);
-    int64_t v[16] = {P.nx, P.nu, P.m, st.nnz_jx, st.nnz_lu, st.nlev_lo, st.nlev_up, st.max_lu_row,
+    int64_t v[20] = {P.nx, P.nu, P.m, st.nnz_jx, st.nnz_lu, st.nlev_lo, st.nlev_up, st.max_lu_row,
                      st.refactor_updates, st.nnz_ju, st.nnz_k, st.nnz_g, st.npacks, st.ntop,
-                     st.max_pack_levels, st.top_levels};
+                     st.max_pack_levels, st.top_levels, st.max_tail_fwd_levels, st.max_tail_bwd_levels,
+                     st.tail_rows, P.tail_max};
     std::memcpy(o, v, sizeof(v));
     return RPF_OK;
   });
@@ -1104,7 +1150,7 @@ int rpf_presolve_info(const rpf_grid_desc* desc, int64_t* o) {
 
 int rpf_presolve_pattern(const rpf_grid_desc* desc, int32_t* perm, int32_t* lu_ptr, int32_t* lu_col) {
   return guard([&]() -> int {
-    Presolve P = build_presolve(grid_from_desc(desc), subtree_max());
+    Presolve P = build_presolve(grid_from_desc(desc), subtree_max(), tail_max());
     if (perm) std::copy(P.x_int2paper.begin(), P.x_int2paper.end(), perm);
     if (lu_ptr) std::copy(P.lu_ptr.begin(), P.lu_ptr.end(), lu_ptr);
     if (lu_col) std::copy(P.lu_col.begin(), P.lu_col.end(), lu_col);
@@ -1122,7 +1168,7 @@ int rpf_grid_create(const rpf_grid_desc* desc, int32_t max_batch, rpf_grid** out
     try {
       h->G = std::move(G0);
       const GridData& G = h->G;
-      h->P = build_presolve(G, subtree_max());
+      h->P = build_presolve(G, subtree_max(), tail_max());
       h->max_batch = max_batch;
       if ((int64_t)h->P.nvar * max_batch >= (int64_t)1 << 31)
         throw std::runtime_error("n_var * max_batch must stay below 2^31");
@@ -1224,19 +1270,32 @@ void gradient_core(rpf_grid* h, const double* u, const double* pd, const double*
   k_fill_int<<<1, 4, 0, s>>>(4, h->piv_status, 0);
   LAUNCHCHK();
   refactor(h, s);
-  // factor values in pack-program order for the batched solves
+  // factor values in the batched programs' order, and the inverses of the
+  // packs' dense tails
   if (h->tw_packt > 0) {
-    const int nf = (int)P.pkf_pos.size(), nb_ = (int)P.pkb_pos.size();
+    const int nf = (int)P.ptf_pos.size(), nb_ = (int)P.ptb_pos.size();
     if (nf > 0) {
-      k_gather_pos<<<cdiv(nf, 256), 256, 0, s>>>(nf, h->pkf_pos, h->luv, h->pkfv, nullptr);
+      k_gather_pos<<<cdiv(nf, 256), 256, 0, s>>>(nf, h->ptf_pos, h->luv, h->pkfv, nullptr);
       LAUNCHCHK();
-      k_gather_pos<<<cdiv(nf, 256), 256, 0, s>>>(nf, h->pkf_pos, h->lutv, h->pkfvT, nullptr);
+      k_gather_pos<<<cdiv(nf, 256), 256, 0, s>>>(nf, h->ptf_pos, h->lutv, h->pkfvT, nullptr);
       LAUNCHCHK();
     }
     if (nb_ > 0) {
-      k_gather_pos<<<cdiv(nb_, 256), 256, 0, s>>>(nb_, h->pkb_pos, h->luv, h->pkbv, nullptr);
+      k_gather_pos<<<cdiv(nb_, 256), 256, 0, s>>>(nb_, h->ptb_pos, h->luv, h->pkbv, nullptr);
       LAUNCHCHK();
-      k_gather_pos<<<cdiv(nb_, 256), 256, 0, s>>>(nb_, h->pkb_pos, h->lutv, h->pkbvT, nullptr);
+      k_gather_pos<<<cdiv(nb_, 256), 256, 0, s>>>(nb_, h->ptb_pos, h->lutv, h->pkbvT, nullptr);
+      LAUNCHCHK();
+    }
+    const int nte = (int)P.ptl_pos.size();
+    if (nte > 0 && h->npacks > 0) {
+      const int64_t na = (int64_t)h->npacks * 2 * TAIL_MAX * TAIL_MAX;
+      k_fill_dbl<<<cdiv(na, 256), 256, 0, s>>>(na, h->tailA, 0.0, nullptr);
+      LAUNCHCHK();
+      k_tail_gather<<<cdiv(nte, 256), 256, 0, s>>>(nte, h->ptl_eoff, h->npacks, h->ptl_pos, h->ptl_dense, h->ptl_off,
+                                                   h->luv, h->tailA, nullptr);
+      LAUNCHCHK();
+      k_tail_inv<<<dim3(h->npacks, 2), 1024, (size_t)TAIL_MAX * TAIL_MAX * sizeof(double), s>>>(
+          h->ptl_off, h->tailA, h->tailM, h->npacks, nullptr);
       LAUNCHCHK();
     }
   }
