@@ -405,6 +405,16 @@ constexpr int RF_AHEAD = 4;
 // pivots of finished rows go to LDS and to rdg.  upd_tgt must hold 64
 // readable entries past its end.  LDS: values of the pack's CSR rows [seg]
 // | 1 / u_ii [nr].
+//
+// Dense tails (toff non-null; flev/frows/erp/epos the batched forward
+// program): the last level holds the pack's tail rows T, which eliminate
+// only their columns outside T there (erp/epos list each row's L entries to
+// eliminate: all of them for the other rows, the ones outside T for T rows)
+// and keep their pivots open.  Then the T x T block is finished
+// right-looking, one tail pivot k at a time (one barrier per pivot): every L
+// entry (i, k) of a later tail row (tl_pos[tl_ptr[g] .. tl_ptr[g + 1]), g
+// the pivot's tail index) takes l = a_ik / u_kk and updates row i's targets
+// of row k's U entries (tail and top columns), the rows in parallel.
 __global__ void __launch_bounds__(1024) k_rf_pack_lds(const int32_t* __restrict__ pack_ptr,
                                                       const int32_t* __restrict__ flev,
                                                       const int32_t* __restrict__ flev_off,
@@ -417,7 +427,13 @@ __global__ void __launch_bounds__(1024) k_rf_pack_lds(const int32_t* __restrict_
                                                       const int32_t* __restrict__ upd_tgt,
                                                       double* __restrict__ a, double* __restrict__ rdg,
                                                       double pivtol, int32_t* __restrict__ status,
-                                                      const int32_t* __restrict__ skip) {
+                                                      const int32_t* __restrict__ skip,
+                                                      const int32_t* __restrict__ erp = nullptr,
+                                                      const int32_t* __restrict__ epos = nullptr,
+                                                      const int32_t* __restrict__ toff = nullptr,
+                                                      const int16_t* __restrict__ trows = nullptr,
+                                                      const int32_t* __restrict__ tl_ptr = nullptr,
+                                                      const int32_t* __restrict__ tl_pos = nullptr) {
   if (skip && *skip) return;
   extern __shared__ double sv[];
   const int q = blockIdx.x;
@@ -443,19 +459,25 @@ __global__ void __launch_bounds__(1024) k_rf_pack_lds(const int32_t* __restrict_
   }
   __syncthreads();
   const int wave = t >> 6, lane = t & 63, nwave = blockDim.x >> 6;
-  for (int lv = flev_off[q]; lv < flev_off[q + 1]; ++lv) {
+  const int tq = toff ? toff[q] : 0, nT = toff ? toff[q + 1] - tq : 0;
+  const int lv1 = flev_off[q + 1];
+  for (int lv = flev_off[q]; lv < lv1; ++lv) {
+    const bool tail = nT > 0 && lv == lv1 - 1;   // the tail rows: pivots stay open
     for (int rr = flev[lv] + wave; rr < flev[lv + 1]; rr += nwave) {
       // row bounds are the same in every lane: keep them scalar
       const int i = __builtin_amdgcn_readfirstlane(frows[rr]);
-      const int p0 = __builtin_amdgcn_readfirstlane(ptr[i]);
       const int pdg = __builtin_amdgcn_readfirstlane(diag[i]);
-      const int p1 = __builtin_amdgcn_readfirstlane(ptr[i + 1]);
-      for (int w0 = p0; w0 < pdg; w0 += 64) {
-        const int nw = min(64, pdg - w0);
-        int m_k = 0, m_us = 0, m_nu = 0;
+      // the row's L entries to eliminate: [e0, e1) of epos, or the
+      // contiguous positions ptr[i] .. diag[i]
+      const int e0 = __builtin_amdgcn_readfirstlane(erp ? erp[i] : ptr[i]);
+      const int e1 = __builtin_amdgcn_readfirstlane(erp ? erp[i + 1] : pdg);
+      for (int w0 = e0; w0 < e1; w0 += 64) {
+        const int nw = min(64, e1 - w0);
+        int m_k = 0, m_us = 0, m_nu = 0, m_p = 0;
         int64_t m_u0 = 0;
         if (lane < nw) {
-          const int p = w0 + lane;
+          const int p = epos ? epos[w0 + lane] : w0 + lane;
+          m_p = p;
           m_k = col[p];
           m_us = ustart[p];
           m_u0 = upd_ptr[p];
@@ -477,7 +499,7 @@ __global__ void __launch_bounds__(1024) k_rf_pack_lds(const int32_t* __restrict_
           const int k = __builtin_amdgcn_readlane(m_k, st);
           const int us = __builtin_amdgcn_readlane(m_us, st) - gp0;
           const int nu = __builtin_amdgcn_readlane(m_nu, st);
-          const int pl = w0 + st - gp0;
+          const int pl = __builtin_amdgcn_readlane(m_p, st) - gp0;
           const bool on = lane < nu;
           const double av = sv[us + (on ? lane : 0)];
           const double cur = sv[on ? tgabs - gp0 : pl];
@@ -502,7 +524,7 @@ __global__ void __launch_bounds__(1024) k_rf_pack_lds(const int32_t* __restrict_
           }
         }
       }
-      if (lane == 0) {
+      if (lane == 0 && !tail) {
         const double amax = srd[i - r0];
         const double piv = sv[pdg - gp0];
         const double rp = 1.0 / piv;
@@ -512,6 +534,30 @@ __global__ void __launch_bounds__(1024) k_rf_pack_lds(const int32_t* __restrict_
       }
       __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
       __builtin_amdgcn_wave_barrier();
+    }
+    lds_barrier();
+  }
+  // the tail block, right-looking over its pivots
+  for (int b = 0; b < nT; ++b) {
+    const int k = r0 + trows[tq + b];
+    const int dk = __builtin_amdgcn_readfirstlane(diag[k]) - gp0;
+    const double piv = sv[dk];   // final: every earlier pivot has updated row k
+    if (t == 0) {
+      const double rp = 1.0 / piv;
+      rdg[k] = rp;
+      if (!(fabs(piv) > pivtol * srd[k - r0])) atomicCAS(status, 0, k + 1);
+    }
+    const double rp = 1.0 / piv;
+    const int g = tq + b;
+    const int c0 = tl_ptr[g], c1 = tl_ptr[g + 1];
+    for (int c = c0 + wave; c < c1; c += nwave) {
+      const int p = __builtin_amdgcn_readfirstlane(tl_pos[c]);
+      const int us = __builtin_amdgcn_readfirstlane(ustart[p]) - gp0;
+      const int64_t u0 = upd_ptr[p];
+      const int nu = (int)(upd_ptr[p + 1] - u0);
+      const double l = sv[p - gp0] * rp;
+      for (int tt = lane; tt < nu; tt += 64) sv[upd_tgt[u0 + tt] - gp0] -= l * sv[us + tt];
+      if (lane == 0) sv[p - gp0] = l;
     }
     lds_barrier();
   }

@@ -453,6 +453,8 @@ Presolve build_presolve(const GridData& g, int subtree_max, int tail_max) {
       P.ptf_rows.clear(); P.ptb_rows.clear();
       P.ptf_rp.assign(t0 + 1, 0); P.ptb_rp.assign(t0 + 1, 0);
       P.ptf_pos.clear(); P.ptf_col.clear(); P.ptb_pos.clear(); P.ptb_col.clear();
+      P.rft_ptr.assign(1, 0);
+      P.rft_pos.clear();
       std::vector<int> hgt(nx, 0), tix(nx, -1), blv(nx, 0);
       for (int q = 0; q < npk; ++q) {
         const int r0 = P.pack_ptr[q], r1 = P.pack_ptr[q + 1];
@@ -491,6 +493,20 @@ Presolve build_presolve(const GridData& g, int subtree_max, int tail_max) {
           }
         }
         P.ptl_eoff[q + 1] = (int)P.ptl_pos.size();
+        // right-looking lists of the tail block for the refactorization
+        {
+          std::vector<int> trow;
+          for (int i = r0; i < r1; ++i)
+            if (tix[i] >= 0) trow.push_back(i);
+          for (int b = 0; b < nT; ++b) {
+            const int k = trow[b];
+            for (int b2 = b + 1; b2 < nT; ++b2) {
+              const int pos = find_pos(P.lu_ptr, P.lu_col, trow[b2], k);
+              if (pos >= 0) P.rft_pos.push_back(pos);
+            }
+            P.rft_ptr.push_back((int)P.rft_pos.size());
+          }
+        }
         // forward: other rows by height, then the T rows as one level
         std::vector<std::vector<int>> byl(hc + (nT > 0 ? 1 : 0));
         for (int i = r0; i < r1; ++i) byl[tix[i] >= 0 ? hc : hgt[i]].push_back(i);

@@ -103,6 +103,11 @@ struct Presolve {
   std::vector<int32_t> ptf_lev, ptf_lev_off, ptf_rows, ptb_lev, ptb_lev_off, ptb_rows;
   std::vector<int32_t> ptf_rp, ptf_pos, ptb_rp, ptb_pos;
   std::vector<int16_t> ptf_col, ptb_col;
+  // refactorization of the tails, right-looking: for the b-th tail row k of
+  // pack q (global tail index ptl_off[q] + b), the LU positions of the L
+  // entries (i, k) of the tail rows i > k are rft_pos[rft_ptr[g] ..
+  // rft_ptr[g + 1])
+  std::vector<int32_t> rft_ptr, rft_pos;
   // top-part levels (global row ids)
   std::vector<int32_t> top_flev, top_frows, top_blev, top_brows;
   // dense top block: LU positions and their dense (row-major) offsets

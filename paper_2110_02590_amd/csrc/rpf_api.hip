@@ -101,7 +101,7 @@ struct rpf_grid {
   int32_t *ptf_lev, *ptf_lev_off, *ptf_rows, *ptf_rp, *ptf_pos, *ptb_lev, *ptb_lev_off, *ptb_rows, *ptb_rp,
       *ptb_pos;
   int16_t *ptf_col, *ptb_col, *ptl_rows;
-  int32_t *ptl_off, *ptl_eoff, *ptl_pos, *ptl_dense;
+  int32_t *ptl_off, *ptl_eoff, *ptl_pos, *ptl_dense, *rft_ptr, *rft_pos;
   double *tailA = nullptr, *tailM = nullptr;
   size_t lds_limit = 65536, lds_pack[5] = {0, 0, 0, 0, 0};
   double *c2, *c1, *c0;
@@ -339,6 +339,8 @@ void setup(rpf_grid* h) {
   h->ptl_eoff = h->up(P.ptl_eoff);
   h->ptl_pos = h->up(P.ptl_pos);
   h->ptl_dense = h->up(P.ptl_dense);
+  h->rft_ptr = h->up(P.rft_ptr);
+  h->rft_pos = h->up(P.rft_pos);
   {
     const size_t npk = P.pack_ptr.size() - 1, blk = (size_t)TAIL_MAX * TAIL_MAX;
     h->tailA = h->alloc<double>(std::max<size_t>(1, npk * 2 * blk));
@@ -616,9 +618,13 @@ void refactor(rpf_grid* h, hipStream_t s, const int32_t* skip = nullptr) {
   const size_t shm = (size_t)wv * maxrow * sizeof(double);
   size_t pi = h->prof_on ? h->prof_begin(s) : 0;
   if (h->npacks > 0 && h->lds_rf > 0) {
-    k_rf_pack_lds<<<h->npacks, 1024, h->lds_rf, s>>>(h->pack_ptr, h->pk_flev, h->pk_flev_off, h->pk_frows,
+    // the batched forward program's levels: rows outside the dense tails by
+    // level, then the tails (finished right-looking)
+    k_rf_pack_lds<<<h->npacks, 1024, h->lds_rf, s>>>(h->pack_ptr, h->ptf_lev, h->ptf_lev_off, h->ptf_rows,
                                                      h->lu_ptr, h->lu_col, h->lu_diag, h->rf_ustart, h->upd_ptr,
-                                                     h->upd_tgt, h->luv, h->rdiag, 1e-14, h->piv_status, skip);
+                                                     h->upd_tgt, h->luv, h->rdiag, 1e-14, h->piv_status, skip,
+                                                     h->ptf_rp, h->ptf_pos, h->ptl_off, h->ptl_rows, h->rft_ptr,
+                                                     h->rft_pos);
     LAUNCHCHK();
   } else if (h->npacks > 0) {
     k_rf_pack<<<h->npacks, 64 * wv, shm, s>>>(h->pk_flev, h->pk_flev_off, h->pk_frows, h->lu_ptr, h->lu_col,
