@@ -1587,55 +1587,127 @@ __global__ void k_tail_gather(int ne, const int32_t* __restrict__ eoff, int npac
   }
 }
 
-// Inverses of the tail blocks, one workgroup per (pack, part): part 0
-// inverts L_TT (unit lower) row by row, X_i = e_i - sum_{k<i} L_ik X_k;
-// part 1 inverts U_TT from the last row, X_i = (e_i - sum_{k>i} U_ik X_k)
-// / U_ii.  X lives in LDS (nT x TAIL_MAX); thread (column j, group g)
-// sums the k = g (mod 1024 / TAIL_MAX) terms, the groups are added in a
-// fixed order.  Out: Minv[0] = L_TT^-1, [1] = U_TT^-1, [2] = (L_TT^-1)^T,
-// [3] = (U_TT^-1)^T, each [npacks][TAIL_MAX x TAIL_MAX] (rows and columns
-// past nT left as they are: never read).
-__global__ void __launch_bounds__(1024) k_tail_inv(const int32_t* __restrict__ toff, const double* __restrict__ A,
-                                                   double* __restrict__ Minv, int npacks,
-                                                   const int32_t* __restrict__ skip) {
+// Inverses of the tail blocks in 64 x 64 blocks (a tail has at most two):
+// k_tail_diag_inv inverts the diagonal blocks of L_TT (unit) and U_TT, one
+// workgroup per (pack, part, block), as k_top_diag_inv does for the top;
+// k_tail_offdiag then forms the off-diagonal block of each inverse,
+//   (L^-1)_21 = -L22^-1 (L21 L11^-1),  (U^-1)_12 = -U11^-1 (U12 U22^-1).
+// Out: Minv[0] = L_TT^-1, [1] = U_TT^-1, [2] = (L_TT^-1)^T, [3] =
+// (U_TT^-1)^T, each [npacks][TAIL_MAX x TAIL_MAX] (entries past nT are
+// never read).
+__global__ void __launch_bounds__(256) k_tail_diag_inv(const int32_t* __restrict__ toff, const double* __restrict__ A,
+                                                       double* __restrict__ Minv, int npacks,
+                                                       const int32_t* __restrict__ skip) {
   if (skip && *skip) return;
-  extern __shared__ double X[];
-  __shared__ double red[1024];
-  constexpr int KG = 1024 / TAIL_MAX;
-  const int q = blockIdx.x, part = blockIdx.y;
+  __shared__ double T[CB][CB + 1];
+  __shared__ double rd[CB];
+  const int q = blockIdx.x, part = blockIdx.y, kb = blockIdx.z;
   const int nT = toff[q + 1] - toff[q];
-  if (nT == 0) return;
+  const int b0 = kb * CB;
+  if (b0 >= nT) return;
+  const int nb = min(CB, nT - b0);
   const double* Aq = A + ((size_t)q * 2 + part) * TAIL_MAX * TAIL_MAX;
-  const int t = threadIdx.x, j = t % TAIL_MAX, g = t / TAIL_MAX;
-  for (int step = 0; step < nT; ++step) {
-    const int i = part == 0 ? step : nT - 1 - step;
-    double s0 = 0.0;
-    if (j < nT) {
-      if (part == 0) {
-        for (int k = g; k < i; k += KG) s0 += Aq[(size_t)i * TAIL_MAX + k] * X[k * TAIL_MAX + j];
-      } else {
-        for (int k = i + 1 + g; k < nT; k += KG) s0 += Aq[(size_t)i * TAIL_MAX + k] * X[k * TAIL_MAX + j];
-      }
+  const int t = threadIdx.x;
+  {
+    double v[CB * CB / 256];
+#pragma unroll
+    for (int m = 0; m < CB * CB / 256; ++m) {
+      const int e = t + 256 * m, r = e >> 6, cc = e & 63;
+      v[m] = Aq[(size_t)(b0 + min(r, nb - 1)) * TAIL_MAX + b0 + min(cc, nb - 1)];
     }
-    red[t] = s0;
-    __syncthreads();
-    if (g == 0 && j < nT) {
-      double tot = red[j];
-      for (int gg = 1; gg < KG; ++gg) tot += red[gg * TAIL_MAX + j];
-      const double v = (i == j ? 1.0 : 0.0) - tot;
-      X[i * TAIL_MAX + j] = part == 0 ? v : v / Aq[(size_t)i * TAIL_MAX + i];
+#pragma unroll
+    for (int m = 0; m < CB * CB / 256; ++m) {
+      const int e = t + 256 * m, r = e >> 6, cc = e & 63;
+      const bool in = r < nb && cc < nb && (part == 0 ? cc < r : cc > r);
+      T[r][cc] = in ? v[m] : 0.0;
     }
-    __syncthreads();
   }
+  if (t < CB) rd[t] = (part == 0 || t >= nb) ? 1.0 : 1.0 / Aq[(size_t)(b0 + t) * TAIL_MAX + b0 + t];
+  __syncthreads();
+  const int c = t >> 2, seg = t & 3;
+  double zr[CB / 4];
+#pragma unroll
+  for (int m = 0; m < CB / 4; ++m) zr[m] = 0.0;
+  if (part == 0) tri_inv_rows<true>(T, rd, c, seg, nb, zr);
+  else tri_inv_rows<false>(T, rd, c, seg, nb, zr);
   const size_t blk = (size_t)TAIL_MAX * TAIL_MAX, n4 = (size_t)npacks * blk;
   double* Mo = Minv + (size_t)part * n4 + (size_t)q * blk;
   double* Mt = Minv + (size_t)(2 + part) * n4 + (size_t)q * blk;
-  for (int e = t; e < nT * TAIL_MAX; e += blockDim.x) {
-    const int r = e / TAIL_MAX, c = e - r * TAIL_MAX;
-    if (c < nT) {
-      const double v = X[e];
-      Mo[(size_t)r * TAIL_MAX + c] = v;
-      Mt[(size_t)c * TAIL_MAX + r] = v;
+#pragma unroll
+  for (int m = 0; m < CB / 4; ++m) {
+    const int r = b0 + 4 * m + seg, cc = b0 + c;
+    Mo[(size_t)r * TAIL_MAX + cc] = zr[m];
+    Mt[(size_t)cc * TAIL_MAX + r] = zr[m];
+  }
+}
+
+// Off-diagonal blocks of the tail inverses (tails longer than CB rows):
+// part 0, rows CB .. nT of L^-1: X21 = -D2 (L21 D1); part 1, columns CB ..
+// nT of U^-1: Y12 = -E1 (U12 E2), with D1, D2, E1, E2 the diagonal-block
+// inverses from k_tail_diag_inv.  One workgroup (256 threads) per (pack,
+// part): the operands pass through two 64 x 64 LDS blocks (a wavefront
+// reads one row of the left operand, broadcast, and consecutive columns of
+// the right one), each thread forms 16 entries.
+__global__ void __launch_bounds__(256) k_tail_offdiag(const int32_t* __restrict__ toff, const double* __restrict__ A,
+                                                      double* __restrict__ Minv, int npacks,
+                                                      const int32_t* __restrict__ skip) {
+  if (skip && *skip) return;
+  __shared__ double S1[CB][CB], S2[CB][CB];
+  const int q = blockIdx.x, part = blockIdx.y;
+  const int nT = toff[q + 1] - toff[q];
+  if (nT <= CB) return;
+  const int n2 = nT - CB;
+  const size_t blk = (size_t)TAIL_MAX * TAIL_MAX, n4 = (size_t)npacks * blk;
+  const double* Aq = A + ((size_t)q * 2 + part) * blk;
+  double* Mo = Minv + (size_t)part * n4 + (size_t)q * blk;
+  double* Mt = Minv + (size_t)(2 + part) * n4 + (size_t)q * blk;
+  const int t = threadIdx.x;
+  constexpr int PER = CB * CB / 256;
+  // part 0: S1 = L21 (n2 x CB), S2 = D1 (CB x CB); part 1: S1 = U12
+  // (CB x n2), S2 = E2 (n2 x n2)
+  for (int e = t; e < CB * CB; e += 256) {
+    const int r = e >> 6, cc = e & 63;
+    if (part == 0) {
+      S1[r][cc] = r < n2 ? Aq[(size_t)(CB + r) * TAIL_MAX + cc] : 0.0;
+      S2[r][cc] = Mo[(size_t)r * TAIL_MAX + cc];
+    } else {
+      S1[r][cc] = cc < n2 ? Aq[(size_t)r * TAIL_MAX + CB + cc] : 0.0;
+      S2[r][cc] = (r < n2 && cc < n2) ? Mo[(size_t)(CB + r) * TAIL_MAX + CB + cc] : 0.0;
+    }
+  }
+  __syncthreads();
+  double pr[PER];
+#pragma unroll
+  for (int m = 0; m < PER; ++m) {
+    const int e = t + 256 * m, r = e >> 6, cc = e & 63;
+    double acc = 0.0;
+    for (int k = 0; k < CB; ++k) acc += S1[r][k] * S2[k][cc];
+    pr[m] = acc;
+  }
+  __syncthreads();
+  // S1 = the product, S2 = D2 (part 0) or E1 (part 1)
+#pragma unroll
+  for (int m = 0; m < PER; ++m) {
+    const int e = t + 256 * m, r = e >> 6, cc = e & 63;
+    S1[r][cc] = pr[m];
+    if (part == 0) S2[r][cc] = (r < n2 && cc < n2) ? Mo[(size_t)(CB + r) * TAIL_MAX + CB + cc] : 0.0;
+    else S2[r][cc] = Mo[(size_t)r * TAIL_MAX + cc];
+  }
+  __syncthreads();
+  // part 0: X21 = -D2 S1 (n2 x CB); part 1: Y12 = -E1 S1 (CB x n2)
+#pragma unroll
+  for (int m = 0; m < PER; ++m) {
+    const int e = t + 256 * m, r = e >> 6, cc = e & 63;
+    double acc = 0.0;
+    for (int k = 0; k < CB; ++k) acc += S2[r][k] * S1[k][cc];
+    if (part == 0) {
+      if (r < n2) {
+        Mo[(size_t)(CB + r) * TAIL_MAX + cc] = -acc;
+        Mt[(size_t)cc * TAIL_MAX + CB + r] = -acc;
+      }
+    } else if (cc < n2) {
+      Mo[(size_t)r * TAIL_MAX + CB + cc] = -acc;
+      Mt[(size_t)(CB + cc) * TAIL_MAX + r] = -acc;
     }
   }
 }

@@ -454,8 +454,7 @@ void setup(rpf_grid* h) {
       HIPCHK(hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, ldsmax - (int)top_static));
     };
     allow_top((const void*)k_top_dense);
-    HIPCHK(hipFuncSetAttribute((const void*)k_tail_inv, hipFuncAttributeMaxDynamicSharedMemorySize,
-                               (int)((size_t)TAIL_MAX * TAIL_MAX * sizeof(double))));
+
 #define RPF_ALLOW_PACK(TW)                                  \
   allow((const void*)k_pack_solve_s<TW, true, true>);       \
   allow((const void*)k_pack_solve_s<TW, true, false>);      \
@@ -1300,8 +1299,10 @@ void gradient_core(rpf_grid* h, const double* u, const double* pd, const double*
       k_tail_gather<<<cdiv(nte, 256), 256, 0, s>>>(nte, h->ptl_eoff, h->npacks, h->ptl_pos, h->ptl_dense, h->ptl_off,
                                                    h->luv, h->tailA, nullptr);
       LAUNCHCHK();
-      k_tail_inv<<<dim3(h->npacks, 2), 1024, (size_t)TAIL_MAX * TAIL_MAX * sizeof(double), s>>>(
-          h->ptl_off, h->tailA, h->tailM, h->npacks, nullptr);
+      k_tail_diag_inv<<<dim3(h->npacks, 2, TAIL_MAX / CB), 256, 0, s>>>(h->ptl_off, h->tailA, h->tailM, h->npacks,
+                                                                       nullptr);
+      LAUNCHCHK();
+      k_tail_offdiag<<<dim3(h->npacks, 2), 256, 0, s>>>(h->ptl_off, h->tailA, h->tailM, h->npacks, nullptr);
       LAUNCHCHK();
     }
   }
