@@ -662,3 +662,58 @@ def test_rt_qp_kkt_certificate_and_slack_coupling():
     free = (ds > (lo - s) + 1e-7) & (ds < (hi - s) - 1e-7)
     want = info["J"][free] @ du - gs[free] / (P.rho * P.sigma_c[free] ** 2)
     np.testing.assert_allclose(ds[free], want, rtol=0, atol=1e-8 * max(1.0, np.abs(want).max()))
+
+
+# ------------------------------------------- static OPF (augmented Lagrangian)
+def _static_case(name):
+    g = gridgen.grid(name)
+    ep = gridgen.eval_point(g, sigma="ones")
+    M = oracle.Model(g)
+    u = M.u_from_setpoints(g["vg0"], g["pg0"])
+    x = oracle.solve_pf(M, u, g["pd"], g["qd"]).x
+    P = oracle.Point.from_dict(ep)
+    lo, hi = gridgen.constraint_bounds(g)
+    s = np.clip(M.constraints(x, u, g["pd"], g["qd"]), lo, hi)
+    return g, M, u, x, P, lo, hi, s
+
+
+def test_static_opf_matches_a_full_space_nlp_solver():
+    """The augmented-Lagrangian method (Section IV-B.3) on tiny10 stops
+    within the tolerances of Section V-B, at the optimum that a general NLP
+    solver finds for the full-space problem eq. (acopf) -- SciPy's SLSQP over
+    (x, u) with the power flow as equalities and the operational constraints
+    and control bounds as inequalities: objectives within 1e-5 relative (the
+    AL point is feasible only to 1e-5), controls within 1e-3."""
+    from scipy.optimize import minimize
+    g, M, u, x, P, lo, hi, s = _static_case("tiny10")
+    u2, s2, x2, y2, rho, hist = oracle.static_opf(M, u, s, np.zeros(M.m), g["pd"], g["qd"], P, lo, hi)
+    assert hist[-1]["converged"] and hist[-1]["theta"] <= 1e-5 and hist[-1]["pg"] <= 1e-4
+    assert any(h["updated"] for h in hist) and rho > 10.0      # both updates of the method were taken
+    nx = M.nx
+    pd, qd = g["pd"], g["qd"]
+    ulo, uhi = M.u_bounds()
+    split = lambda z: (z[:nx], z[nx:])
+    cons = [dict(type="eq", fun=lambda z: M.residual(*split(z), pd, qd)),
+            dict(type="ineq", fun=lambda z: M.constraints(*split(z), pd, qd) - lo),
+            dict(type="ineq", fun=lambda z: hi - M.constraints(*split(z), pd, qd))]
+    ref = minimize(lambda z: M.cost(M.gen_p(*split(z), pd)) / 1e4, np.concatenate([x, u]), method="SLSQP",
+                   constraints=cons, bounds=[(None, None)] * nx + list(zip(ulo, uhi)),
+                   options=dict(maxiter=500, ftol=1e-12))
+    assert ref.success
+    f_al = M.cost(M.gen_p(x2, u2, pd))
+    assert abs(f_al - 1e4 * ref.fun) <= 1e-5 * abs(f_al)
+    np.testing.assert_allclose(u2, ref.x[nx:], rtol=0, atol=1e-3)
+    # the AL's final point solves the power flow and keeps u in its box
+    assert np.linalg.norm(M.residual(x2, u2, pd, qd)) < 1e-9
+    assert np.all(u2 >= ulo - 1e-12) and np.all(u2 <= uhi + 1e-12)
+
+
+def test_projected_gradient_measure():
+    """Zero exactly at a stationary point of a box-constrained problem:
+    interior points with zero gradient, and bound points whose gradient
+    points outward; positive otherwise."""
+    lo, hi = np.zeros(3), np.ones(3)
+    w = np.array([0.5, 0.0, 1.0])
+    assert oracle.projected_gradient(w, np.array([0.0, 2.0, -3.0]), lo, hi) == 0.0
+    assert oracle.projected_gradient(w, np.array([0.1, 0.0, 0.0]), lo, hi) == pytest.approx(0.1)
+    assert oracle.projected_gradient(w, np.array([0.0, -0.2, 0.0]), lo, hi) == pytest.approx(0.2)
