@@ -26,6 +26,9 @@
  *                              qp_rto by an interior-point method whose Newton
  *                              systems go through the Schur complement of
  *                              Proposition 3 (Section IV-B.2, IV-C)
+ *   rpf_track_step_qp          one real-time tracking update with that step
+ *   rpf_static_opf             static OPF by the augmented-Lagrangian method
+ *                              (Section IV-B.3, tolerances of Section V-B)
  *
  * Variables and orderings (Section II-B, eq. statecontrol):
  *   u = (v_ref, v_pv, p_pv)            n_u = 1 + 2 n_pv
@@ -317,6 +320,39 @@ int rpf_track_step_qp(rpf_grid* grid, double* u, double* s, double* x, double* y
                       const double* u_lo, const double* u_hi, double rho, const double* sigma, double delta,
                       int32_t pf_iters, int32_t max_halvings, double tol, int32_t qp_iters, double qp_tol,
                       int32_t batch, double dispatch_scale, double* J, int32_t* status, rpf_stream_t stream);
+
+/* Static OPF by the augmented-Lagrangian method (Section IV-B.3; the
+ * bound-constrained Lagrangian method of the textbook it cites; stopping
+ * tolerances of Section V-B: ||c(u) - s||_inf <= 1e-5 and projected
+ * gradient <= 1e-4).  Outer iteration at multipliers y and penalty rho:
+ *   the subproblem eq. (auglag_subproblem), min L_rho(w; y) over the box of
+ *   w = (u, s), warm-started from the current w: repeated bounded QPs of the
+ *   form eq. (qp_rto) at the current point (as rpf_qp_step, shift 0, the
+ *   interior point's inertia control keeping its systems positive definite,
+ *   qp_iters slots, qp_tol), each followed by a backtracking line search on
+ *   L_rho (Armijo 1e-4, at most 10 halvings, a power flow from the current
+ *   state at every trial point), until ||w - clip(w - grad L_rho, lo, hi)||
+ *   _inf <= omega (at most max_inner QPs);
+ *   theta = ||c(u) - s||_inf <= eta: stop if theta <= 1e-5 and the measure
+ *   <= 1e-4, else y <- y + rho D_c (c - s), eta <- eta / rho^0.9, omega <-
+ *   omega / rho; otherwise rho <- 10 rho, eta <- rho^-0.1, omega <- 1 / rho
+ *   (omega = 1 / rho0, eta = rho0^-0.1 at the start).
+ * x [n_x] (start: any point from which the power flow at u converges; out:
+ * the power-flow state at the final u), u [n_u], s [m], y [m]: device,
+ * in/out.  pd, qd [nb], sigma [1 + m], u_lo, u_hi [n_u], s_lo, s_hi [m]:
+ * device, read.  J [m x n_u]: device workspace.  hist [max_outer x 8]:
+ * HOST, out, per outer iteration {rho, QPs of the subproblem, theta,
+ * projected-gradient measure, cost f, multipliers updated (0/1),
+ * converged (0/1), L_rho}; nhist (host): outer iterations done; rho_out
+ * (host, may be NULL): the final penalty.
+ * Unlike the compute calls above, this driver synchronises the host after
+ * every QP and every trial point to take its decisions (it is not
+ * capturable); RPF_EINVAL if the power flow at the starting u fails. */
+int rpf_static_opf(rpf_grid* grid, double* x, double* u, double* s, double* y, const double* pd, const double* qd,
+                   double rho0, const double* sigma, const double* u_lo, const double* u_hi, const double* s_lo,
+                   const double* s_hi, int32_t max_outer, int32_t max_inner, int32_t qp_iters, double qp_tol,
+                   int32_t pf_iters, double tol, double* J, double* hist, int32_t* nhist, double* rho_out,
+                   rpf_stream_t stream);
 
 /* Kernel timing with HIP events recorded on the launch stream, per kernel
  * class: 0 batched triangular solves inside the independent subtree packs

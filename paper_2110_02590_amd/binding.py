@@ -66,6 +66,8 @@ def lib():
             "rpf_track_step": [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, dbl, vp, dbl, i32, i32, dbl, vp, vp],
             "rpf_track_step_qp": [vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, dbl, vp, dbl, i32, i32, dbl,
                                   i32, dbl, i32, dbl, vp, vp, vp],
+            "rpf_static_opf": [vp, vp, vp, vp, vp, vp, vp, dbl, vp, vp, vp, vp, vp, i32, i32, i32, dbl, i32, dbl,
+                               vp, vp, vp, vp, vp],
             "rpf_qp_step": [vp, vp, vp, vp, vp, vp, vp, dbl, vp, dbl, vp, vp, vp, vp, i32, dbl, i32, vp, vp, vp,
                             vp, vp, vp, vp, vp, vp],
             "rpf_profile_read": [vp, vp, vp, i32],
@@ -378,3 +380,22 @@ class Grid:
                                        _dev(J, self.m * self.nu, "J"),
                                        _dev(status, 8, "status", torch.int32), _stream()))
         return status, J
+
+    def static_opf(self, x, u, s, y, pd, qd, rho, sigma, u_lo, u_hi, s_lo, s_hi, max_outer=30, max_inner=20,
+                   qp_iters=60, qp_tol=1e-10, pf_iters=20, tol=1e-10, J=None):
+        """Static OPF by the augmented-Lagrangian method; x, u, s, y updated
+        in place.  Returns (history rows [n, 8] as a NumPy array: rho, QPs,
+        theta, projected gradient, cost, multipliers updated, converged,
+        L_rho; final rho)."""
+        J = self._empty(self.m * self.nu).view(self.m, self.nu) if J is None else J
+        hist = np.zeros((max_outer, 8), dtype=np.float64)
+        nh = ctypes.c_int32(0)
+        rho_out = ctypes.c_double(0.0)
+        _check(lib().rpf_static_opf(self._h, _dev(x, self.nx, "x"), _dev(u, self.nu, "u"), _dev(s, self.m, "s"),
+                                    _dev(y, self.m, "y"), _dev(pd, self.nb, "pd"), _dev(qd, self.nb, "qd"),
+                                    float(rho), _dev(sigma, 1 + self.m, "sigma"), _dev(u_lo, self.nu, "u_lo"),
+                                    _dev(u_hi, self.nu, "u_hi"), _dev(s_lo, self.m, "s_lo"),
+                                    _dev(s_hi, self.m, "s_hi"), int(max_outer), int(max_inner), int(qp_iters),
+                                    float(qp_tol), int(pf_iters), float(tol), _dev(J, self.m * self.nu, "J"),
+                                    hist.ctypes.data, ctypes.byref(nh), ctypes.byref(rho_out), _stream()))
+        return hist[:nh.value].copy(), rho_out.value

@@ -475,5 +475,42 @@ __global__ void k_qp_status(const int32_t* __restrict__ f, const double* __restr
   if (wreg) wreg[0] = qs[QS_WLAST];
 }
 
+// Scalars of the static OPF driver (one workgroup): out[0] = the
+// projected-gradient measure ||w - clip(w - g, lo, hi)||_inf of w = (u, s)
+// with the QP gradient g, out[1] = g . d with the QP step d.
+__global__ void __launch_bounds__(QP_NT) k_static_pg(int nu, int m, const double* __restrict__ u,
+                                                     const double* __restrict__ sv, const double* __restrict__ ulo,
+                                                     const double* __restrict__ uhi, const double* __restrict__ slo,
+                                                     const double* __restrict__ shi, const double* __restrict__ g,
+                                                     const double* __restrict__ d, double* __restrict__ out) {
+  __shared__ double sh[QP_NT / 64];
+  const int n = nu + m;
+  double pg = 0.0, sl = 0.0;
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    const bool isu = i < nu;
+    const double w = isu ? u[i] : sv[i - nu];
+    const double lo = isu ? ulo[i] : slo[i - nu];
+    const double hi = isu ? uhi[i] : shi[i - nu];
+    pg = fmax(pg, fabs(w - fmin(fmax(w - g[i], lo), hi)));
+    sl += g[i] * d[i];
+  }
+  pg = wg_reduce<1>(pg, sh);
+  sl = wg_reduce<0>(sl, sh);
+  if (threadIdx.x == 0) {
+    out[0] = pg;
+    out[1] = sl;
+  }
+}
+
+// out[0] = ||c - s||_inf over the m constraints (one workgroup)
+__global__ void __launch_bounds__(QP_NT) k_static_theta(int m, const double* __restrict__ c,
+                                                        const double* __restrict__ sv, double* __restrict__ out) {
+  __shared__ double sh[QP_NT / 64];
+  double th = 0.0;
+  for (int k = threadIdx.x; k < m; k += blockDim.x) th = fmax(th, fabs(c[k] - sv[k]));
+  th = wg_reduce<1>(th, sh);
+  if (threadIdx.x == 0) out[0] = th;
+}
+
 }  // namespace dev
 }  // namespace rpf

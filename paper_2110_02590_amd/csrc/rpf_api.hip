@@ -1796,6 +1796,164 @@ int rpf_track_step_qp(rpf_grid* h, double* u, double* sv, double* x, double* y, 
 
 }  // extern "C"
 
+// ---------------------------------------------------------------- static OPF
+namespace {
+
+// AL value (and, with cost, the cost f times sigma_f) at the state in h->xi,
+// control u, slack sv; c into h->cvec.  Device scalars out.
+void al_value(rpf_grid* h, const double* u, const double* pd, const double* qd, const double* sv, const double* y,
+              double rho, const double* sigma, double* phi, double* cost, hipStream_t s) {
+  const Presolve& P = h->P;
+  state_and_records(h, u, s);
+  bus_injections(h, s);
+  ALArgs A = al_args(h, u, pd, qd, sv, y, rho, sigma);
+  k_constraints<<<cdiv(P.m + P.ng, 256), 256, 0, s>>>(A, h->cvec, nullptr, h->terms);
+  LAUNCHCHK();
+  k_reduce_final<<<1, 1024, 0, s>>>(P.m + P.ng, h->terms, phi, 0, 0.0, nullptr, nullptr);
+  LAUNCHCHK();
+  if (cost) {
+    k_reduce_final<<<1, 1024, 0, s>>>(P.ng, h->terms + P.m, cost, 0, 0.0, nullptr, nullptr);
+    LAUNCHCHK();
+  }
+}
+
+template <class T>
+T read1(const T* d, hipStream_t s) {
+  T v;
+  HIPCHK(hipMemcpyAsync(&v, d, sizeof(T), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  return v;
+}
+
+}  // namespace
+
+extern "C" {
+
+int rpf_static_opf(rpf_grid* h, double* x, double* u, double* sv, double* y, const double* pd, const double* qd,
+                   double rho0, const double* sigma, const double* u_lo, const double* u_hi, const double* s_lo,
+                   const double* s_hi, int32_t max_outer, int32_t max_inner, int32_t qp_iters, double qp_tol,
+                   int32_t pf_iters, double tol, double* J, double* hist, int32_t* nhist, double* rho_out,
+                   rpf_stream_t stream) {
+  if (!h || !x || !u || !sv || !y || !pd || !qd || !sigma || !u_lo || !u_hi || !s_lo || !s_hi || !J || !hist ||
+      !nhist)
+    return set_err(RPF_EINVAL, "NULL argument");
+  if (!(rho0 > 0.0)) return set_err(RPF_EINVAL, "rho must be positive");
+  if (max_outer < 1 || max_outer > 1000 || max_inner < 0 || max_inner > 1000 || qp_iters < 1 || qp_iters > 500 ||
+      pf_iters < 1 || pf_iters > 100)
+    return set_err(RPF_EINVAL, "bad iteration counts");
+  return guard([&]() -> int {
+    hipStream_t s = (hipStream_t)stream;
+    const Presolve& P = h->P;
+    const int nu = P.nu, nx = P.nx, m = P.m;
+    const double kArmijo = 1e-4, kRhoUp = 10.0, kEtaPrimal = 1e-5, kEtaDual = 1e-4;
+    const int kHalvings = 10;
+    double* sc = h->resid_d;   // device scalars: [0] pg, [1] slope, [2] phi, [3] cost
+    double* sc2 = h->tres;     // [0] theta, [1] trial phi
+    int32_t* done = h->flag;
+    int32_t* count = h->flag + 1;
+    *nhist = 0;
+    // the state at the starting control
+    x_in(h, x, s);
+    k_fill_int<<<1, 4, 0, s>>>(4, h->flag, 0);
+    LAUNCHCHK();
+    pf_device(h, u, pd, qd, pf_iters, tol, done, count, sc2, s);
+    if (read1(done, s) != 1) return set_err(RPF_EINVAL, "power flow at the starting control did not converge");
+    const double sigf = read1(sigma, s);
+    double rho = rho0, omega = 1.0 / rho0, eta = 1.0 / std::pow(rho0, 0.1);
+    for (int k = 0; k < max_outer; ++k) {
+      int inner = 0;
+      double pg = 0.0;
+      for (inner = 0; inner <= max_inner; ++inner) {
+        // the bounded QP of L_rho at (u, s, y): gradient, H, J, interior point
+        gradient_core(h, u, pd, qd, sv, y, rho, sigma, h->gradbuf, nullptr, s);
+        derivative_batches(h, h->Hbuf, J, 0, s);
+        k_symmetrize<<<dim3(cdiv(nu, 32), cdiv(nu, 32)), dim3(32, 8), 0, s>>>(nu, h->Hbuf, nullptr, 0.0);
+        LAUNCHCHK();
+        {
+          const ALArgs A = al_args(h, u, pd, qd, sv, y, rho, sigma);
+          const VarArgs V = var_args(h, u, sigma);
+          qp_ipm(h, A, V, h->Hbuf, J, h->Kbuf, u, sv, u_lo, u_hi, s_lo, s_hi, rho, sigma, 0.0, qp_iters, qp_tol, 0,
+                 s);
+        }
+        k_static_pg<<<1, QP_NT, 0, s>>>(nu, m, u, sv, u_lo, u_hi, s_lo, s_hi, h->qg, h->qd_, sc);
+        LAUNCHCHK();
+        double pv[2];
+        HIPCHK(hipMemcpyAsync(pv, sc, 2 * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        pg = pv[0];
+        const double slope = pv[1];
+        if (pg <= omega || inner == max_inner) break;
+        if (!(slope < 0.0)) break;
+        // backtracking line search on L_rho, a power flow at each trial point
+        al_value(h, u, pd, qd, sv, y, rho, sigma, sc + 2, nullptr, s);
+        const double phi0 = read1(sc + 2, s);
+        k_copy_vec<<<cdiv(nx, 256), 256, 0, s>>>(nx, h->xi, h->xi_save, nullptr);
+        LAUNCHCHK();
+        bool accepted = false;
+        double a = 1.0;
+        for (int hh = 0; hh <= kHalvings; ++hh, a *= 0.5) {
+          k_try_w<<<cdiv(nu + m, 256), 256, 0, s>>>(nu, m, u, sv, h->qd_, a, h->u_try, h->s_try, nullptr);
+          LAUNCHCHK();
+          k_copy_vec<<<cdiv(nx, 256), 256, 0, s>>>(nx, h->xi_save, h->xi, nullptr);
+          LAUNCHCHK();
+          k_fill_int<<<1, 4, 0, s>>>(4, h->flag, 0);
+          LAUNCHCHK();
+          pf_device(h, h->u_try, pd, qd, pf_iters, tol, done, count, sc2, s);
+          if (read1(done, s) != 1) continue;
+          al_value(h, h->u_try, pd, qd, h->s_try, y, rho, sigma, sc2 + 1, nullptr, s);
+          const double phi = read1(sc2 + 1, s);
+          if (phi <= phi0 + kArmijo * a * slope) {
+            k_copy_vec<<<cdiv(nu, 256), 256, 0, s>>>(nu, h->u_try, u, nullptr);
+            LAUNCHCHK();
+            k_copy_vec<<<cdiv(m, 256), 256, 0, s>>>(m, h->s_try, sv, nullptr);
+            LAUNCHCHK();
+            accepted = true;
+            break;
+          }
+        }
+        if (!accepted) {
+          k_copy_vec<<<cdiv(nx, 256), 256, 0, s>>>(nx, h->xi_save, h->xi, nullptr);
+          LAUNCHCHK();
+          break;
+        }
+      }
+      // primal infeasibility, multipliers or penalty
+      al_value(h, u, pd, qd, sv, y, rho, sigma, sc + 2, sc + 3, s);
+      k_static_theta<<<1, QP_NT, 0, s>>>(m, h->cvec, sv, sc2);
+      LAUNCHCHK();
+      const double theta = read1(sc2, s);
+      const double fcost = read1(sc + 3, s) / sigf;
+      double* rec = hist + (size_t)k * 8;
+      rec[0] = rho; rec[1] = inner; rec[2] = theta; rec[3] = pg; rec[4] = fcost; rec[5] = 0.0; rec[6] = 0.0;
+      rec[7] = read1(sc + 2, s);
+      *nhist = k + 1;
+      if (theta <= eta) {
+        if (theta <= kEtaPrimal && pg <= kEtaDual) {
+          rec[6] = 1.0;
+          break;
+        }
+        k_y_update_s<<<cdiv(m, 256), 256, 0, s>>>(m, h->cvec, sigma + 1, rho, sv, y);
+        LAUNCHCHK();
+        eta /= std::pow(rho, 0.9);
+        omega /= rho;
+        rec[5] = 1.0;
+      } else {
+        rho *= kRhoUp;
+        eta = 1.0 / std::pow(rho, 0.1);
+        omega = 1.0 / rho;
+      }
+    }
+    if (rho_out) *rho_out = rho;
+    k_permute_scatter<<<cdiv(nx, 256), 256, 0, s>>>(nx, h->x_i2p, h->xi, x, nullptr);
+    LAUNCHCHK();
+    HIPCHK(hipStreamSynchronize(s));
+    h->have_point = false;
+    return RPF_OK;
+  });
+}
+
+}  // extern "C"
+
 // ------------------------------------------------- no-allocation dense step
 // Scratch of rpf_factor_solve_noalloc in a static device array (one copy per
 // GPU, held until the process ends): the inverses of the diagonal blocks
