@@ -69,6 +69,8 @@ def parse():
     ap.add_argument("--instances", type=int, default=64)
     ap.add_argument("--track-steps", type=int, default=50)
     ap.add_argument("--tracking-mode", default="newton", choices=["newton", "qp"])
+    ap.add_argument("--static-opf", action="store_true", help="static OPF on --workload only")
+    ap.add_argument("--max-outer", type=int, default=40)
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the exact-step, load-drop and 64-grid tracking legs of the default run")
     return ap.parse_args()
@@ -89,6 +91,10 @@ def main():
 
     if a.tracking:
         return tracking_bench(a)
+    if a.static_opf:
+        torch.cuda.set_device(0)
+        print(json.dumps(static_opf_leg(a.workload, a.max_outer)), flush=True)
+        return
 
     torch.cuda.set_device(0)
     g = gridgen.grid(a.workload)
@@ -218,6 +224,7 @@ def main():
         out["rt_qp"] = rt_qp_leg(g, ep, pr)
         out["load_drop_tracking"] = load_drop_leg()
         out["tracking_64"] = tracking_leg(a.instances, a.track_steps, 10)
+        out["static_opf"] = static_opf_leg()
 
     if a.copy_probe:
         # a plain streaming kernel of known size for scaling the HBM byte
@@ -562,6 +569,43 @@ def load_drop_leg(name="syn2000", steps=60, t_drop=2, drop=0.2, qp_iters=60):
             "steps_qp_converged": int(stat[:, 3].sum()),
             "qp_iterations_p50": float(np.percentile(stat[:, 2], 50)),
             "final_max_violation": viol}
+
+
+def static_opf_leg(name="syn300", max_outer=40):
+    """The static OPF by the augmented-Lagrangian method from the base
+    dispatch (multipliers 0, penalty 10, unit constraint scaling): wall
+    time, outer iterations, subproblem QPs, final infeasibility and cost."""
+    import numpy as np
+    import torch
+
+    import gridgen
+    from paper_2110_02590_amd import Problem
+    g = gridgen.grid(name)
+    ep = gridgen.eval_point(g, sigma="ones")
+    pr = Problem(g, max_batch=256)
+    s0, y0, rho, sigma = pr.point(ep)
+    x = pr.flat_x()
+    pr.grid.pf_solve(pr.u0, pr.pd, pr.qd, x)
+    lo, hi = gridgen.constraint_bounds(g)
+    slo = torch.tensor(lo, device="cuda")
+    shi = torch.tensor(hi, device="cuda")
+    _, c = pr.grid.al_objective(x, pr.u0, pr.pd, pr.qd, s0, y0, rho, sigma)
+    s = torch.minimum(torch.maximum(c, slo), shi).contiguous()
+    y = torch.zeros(pr.m, dtype=torch.float64, device="cuda")
+    ul, uh = pr.u_bounds()
+    u = pr.u0.clone()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    hist, rho_f = pr.grid.static_opf(x, u, s, y, pr.pd, pr.qd, 10.0, sigma, torch.tensor(ul, device="cuda"),
+                                     torch.tensor(uh, device="cuda"), slo, shi, max_outer=max_outer)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    last = hist[-1]
+    return {"workload": f"{name}: {g['nb']} buses, static OPF from the base dispatch",
+            "seconds": round(dt, 3), "outer_iterations": int(len(hist)), "qps": int(hist[:, 1].sum()),
+            "converged": bool(last[6]), "final_infeasibility": float(last[2]),
+            "final_projected_gradient": float(last[3]), "cost": float(last[4]), "final_rho": rho_f,
+            "seconds_per_outer": round(dt / len(hist), 4)}
 
 
 def _cpu_model():
