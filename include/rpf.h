@@ -178,13 +178,12 @@ int rpf_reduced_hessian_batch(rpf_grid* grid, const double* V, int32_t nbatch, i
 
 /* The dense reduced Hessian H [n_u x n_u] (device, row-major, out) at the
  * cached point: products with the identity in batches of `batch` columns
- * (0 = the library's choice, at most max_batch).  For max_batch >= 512 the
- * batches run concurrently on three streams owned by the handle, each with
- * its own workspace, forked from `stream` and joined back to it by events.
- * RPF_HVP_STREAMS (1 .. 8, read when the handle is created) sets the number
- * of streams; 1 runs the batches one after the other on `stream`.  While
- * `stream` is being captured into a graph the batches run one after the
- * other on `stream` (same results, bit for bit). */
+ * (0 = the library's choice, at most max_batch).  The batches run one after
+ * the other on `stream`.  With RPF_HVP_STREAMS = 2 .. 8 (read when the handle
+ * is created) they run concurrently on that many streams owned by the
+ * handle, each with its own workspace, forked from `stream` and joined back
+ * to it by events (same results, bit for bit); while `stream` is being
+ * captured into a graph they run on `stream` alone. */
 int rpf_reduced_hessian(rpf_grid* grid, double* H, int32_t batch, rpf_stream_t stream);
 
 /* The dense reduced Hessian H [n_u x n_u] and/or the reduced Jacobian of the
@@ -285,8 +284,8 @@ int rpf_track_step(rpf_grid* grid, double* u, double* x, double* y, const double
  *   non-finite, 16 + column, -1), tiny pivot word of J_x at x,
  *   factorization attempts}.
  * Leaves the point cached as rpf_reduced_gradient does (its own
- * second-order data restored).  Uses the handle's workspace and three
- * internal streams as rpf_reduced_hessian. */
+ * second-order data restored).  Uses the handle's workspace, and its
+ * streams as rpf_reduced_hessian does. */
 int rpf_qp_step(rpf_grid* grid, const double* x, const double* u, const double* pd, const double* qd,
                 const double* s, const double* y, double rho, const double* sigma, double delta,
                 const double* u_lo, const double* u_hi, const double* s_lo, const double* s_hi,

@@ -1645,14 +1645,34 @@ __global__ void __launch_bounds__(256) k_tail_diag_inv(const int32_t* __restrict
 // part 0, rows CB .. nT of L^-1: X21 = -D2 (L21 D1); part 1, columns CB ..
 // nT of U^-1: Y12 = -E1 (U12 E2), with D1, D2, E1, E2 the diagonal-block
 // inverses from k_tail_diag_inv.  One workgroup (256 threads) per (pack,
-// part): the operands pass through two 64 x 64 LDS blocks (a wavefront
-// reads one row of the left operand, broadcast, and consecutive columns of
-// the right one), each thread forms 16 entries.
+// part): the operands pass through two 64 x 64 LDS blocks; thread (tr, tc)
+// forms the 4 x 4 register tile of rows 4 tr.., columns 4 tc.., reading
+// four entries of each operand per step k.
+__device__ __forceinline__ void tile_mm4(const double (*X)[CB + 1], const double (*Y)[CB + 1], int tr, int tc,
+                                         double (&acc)[4][4]) {
+#pragma unroll
+  for (int p = 0; p < 4; ++p)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc[p][q] = 0.0;
+#pragma unroll 4
+  for (int k = 0; k < CB; ++k) {
+    double a[4], b[4];
+#pragma unroll
+    for (int p = 0; p < 4; ++p) a[p] = X[4 * tr + p][k];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) b[q] = Y[k][4 * tc + q];
+#pragma unroll
+    for (int p = 0; p < 4; ++p)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) acc[p][q] += a[p] * b[q];
+  }
+}
+
 __global__ void __launch_bounds__(256) k_tail_offdiag(const int32_t* __restrict__ toff, const double* __restrict__ A,
                                                       double* __restrict__ Minv, int npacks,
                                                       const int32_t* __restrict__ skip) {
   if (skip && *skip) return;
-  __shared__ double S1[CB][CB], S2[CB][CB];
+  __shared__ double S1[CB][CB + 1], S2[CB][CB + 1];
   const int q = blockIdx.x, part = blockIdx.y;
   const int nT = toff[q + 1] - toff[q];
   if (nT <= CB) return;
@@ -1661,8 +1681,7 @@ __global__ void __launch_bounds__(256) k_tail_offdiag(const int32_t* __restrict_
   const double* Aq = A + ((size_t)q * 2 + part) * blk;
   double* Mo = Minv + (size_t)part * n4 + (size_t)q * blk;
   double* Mt = Minv + (size_t)(2 + part) * n4 + (size_t)q * blk;
-  const int t = threadIdx.x;
-  constexpr int PER = CB * CB / 256;
+  const int t = threadIdx.x, tr = t >> 4, tc = t & 15;
   // part 0: S1 = L21 (n2 x CB), S2 = D1 (CB x CB); part 1: S1 = U12
   // (CB x n2), S2 = E2 (n2 x n2)
   for (int e = t; e < CB * CB; e += 256) {
@@ -1676,40 +1695,38 @@ __global__ void __launch_bounds__(256) k_tail_offdiag(const int32_t* __restrict_
     }
   }
   __syncthreads();
-  double pr[PER];
-#pragma unroll
-  for (int m = 0; m < PER; ++m) {
-    const int e = t + 256 * m, r = e >> 6, cc = e & 63;
-    double acc = 0.0;
-    for (int k = 0; k < CB; ++k) acc += S1[r][k] * S2[k][cc];
-    pr[m] = acc;
-  }
+  double acc[4][4];
+  tile_mm4(S1, S2, tr, tc, acc);
   __syncthreads();
   // S1 = the product, S2 = D2 (part 0) or E1 (part 1)
 #pragma unroll
-  for (int m = 0; m < PER; ++m) {
-    const int e = t + 256 * m, r = e >> 6, cc = e & 63;
-    S1[r][cc] = pr[m];
+  for (int p = 0; p < 4; ++p)
+#pragma unroll
+    for (int qq = 0; qq < 4; ++qq) S1[4 * tr + p][4 * tc + qq] = acc[p][qq];
+  for (int e = t; e < CB * CB; e += 256) {
+    const int r = e >> 6, cc = e & 63;
     if (part == 0) S2[r][cc] = (r < n2 && cc < n2) ? Mo[(size_t)(CB + r) * TAIL_MAX + CB + cc] : 0.0;
     else S2[r][cc] = Mo[(size_t)r * TAIL_MAX + cc];
   }
   __syncthreads();
   // part 0: X21 = -D2 S1 (n2 x CB); part 1: Y12 = -E1 S1 (CB x n2)
+  tile_mm4(S2, S1, tr, tc, acc);
 #pragma unroll
-  for (int m = 0; m < PER; ++m) {
-    const int e = t + 256 * m, r = e >> 6, cc = e & 63;
-    double acc = 0.0;
-    for (int k = 0; k < CB; ++k) acc += S2[r][k] * S1[k][cc];
-    if (part == 0) {
-      if (r < n2) {
-        Mo[(size_t)(CB + r) * TAIL_MAX + cc] = -acc;
-        Mt[(size_t)cc * TAIL_MAX + CB + r] = -acc;
+  for (int p = 0; p < 4; ++p)
+#pragma unroll
+    for (int qq = 0; qq < 4; ++qq) {
+      const int r = 4 * tr + p, cc = 4 * tc + qq;
+      const double v = -acc[p][qq];
+      if (part == 0) {
+        if (r < n2) {
+          Mo[(size_t)(CB + r) * TAIL_MAX + cc] = v;
+          Mt[(size_t)cc * TAIL_MAX + CB + r] = v;
+        }
+      } else if (cc < n2) {
+        Mo[(size_t)r * TAIL_MAX + CB + cc] = v;
+        Mt[(size_t)(CB + cc) * TAIL_MAX + r] = v;
       }
-    } else if (cc < n2) {
-      Mo[(size_t)r * TAIL_MAX + CB + cc] = -acc;
-      Mt[(size_t)(CB + cc) * TAIL_MAX + r] = -acc;
     }
-  }
 }
 
 // ------------------------------------------------------------------ SpMM

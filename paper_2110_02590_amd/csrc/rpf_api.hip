@@ -513,9 +513,10 @@ void setup(rpf_grid* h) {
   h->Dk[0] = h->D;
   h->Yk[0] = h->Y;
   h->Tk[0] = h->T;
-  // concurrent batches for large batch widths: three streams
-  // (RPF_HVP_STREAMS = 1 .. 8 overrides)
-  h->nhs = h->max_batch >= 512 ? 3 : 1;
+  // batches one after the other on the caller's stream (with the dense pack
+  // tails, concurrent batches on three streams measured no faster);
+  // RPF_HVP_STREAMS = 2 .. 8 runs them on that many handle-owned streams
+  h->nhs = 1;
   if (const char* e = std::getenv("RPF_HVP_STREAMS")) h->nhs = std::max(1, std::min(rpf_grid::HS, std::atoi(e)));
   if (h->nhs > 1) {
     HIPCHK(hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming));

@@ -17,7 +17,7 @@ def test_full_step_graph_replay_equals_eager():
     print("[case] capture syn9241 max_batch=512", flush=True)
     g = gridgen.grid("syn9241")
     ep = gridgen.eval_point(g)
-    pr = Problem(g, max_batch=512)          # three internal streams when eager
+    pr = Problem(g, max_batch=512)
     grid = pr.grid
     nu, nx, m = pr.nu, pr.nx, pr.m
     s, y, rho, sigma = pr.point(ep)

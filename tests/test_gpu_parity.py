@@ -148,7 +148,7 @@ def test_largest_workload_full_hessian(max_batch):
     """9241-bus grid: all 2889 columns of the reduced Hessian against the
     oracle's Schur form Z^T (grad^2 l) Z within 1e-9 relative Frobenius error
     (Proposition 2).  512 is the benchmark's launch configuration (six
-    batches, the last one 329 columns, on three streams); 1024 gives three
+    batches, the last one 329 columns); 1024 gives three
     batches, the last one 841 columns.  Every column is also compared on
     its own, so that no batch can hide behind the whole matrix's norm."""
     c = case("syn9241", max_batch=max_batch)
@@ -184,7 +184,7 @@ def test_reduced_jacobian(name, batch):
 
 def test_reduced_jacobian_largest_workload():
     """The 41340 x 2889 reduced Jacobian of the 9241-bus grid in the
-    benchmark's launch configuration (batches of 512 on three streams),
+    benchmark's launch configuration (batches of 512),
     together with the Hessian, against the oracle; per constraint block
     (line flows, voltages, slack and PV reactive rows) as well."""
     c = case("syn9241", max_batch=512)
@@ -273,15 +273,15 @@ def test_factor_solve_full_size():
 
 
 def test_concurrent_batches_match_one_stream():
-    """Batches on the handle's three streams give the same reduced Hessian,
-    bit for bit, as one stream (each batch has its own workspace; no
-    floating-point atomics)."""
+    """Batches on three handle-owned streams (RPF_HVP_STREAMS=3) give the
+    same reduced Hessian, bit for bit, as one stream (each batch has its own
+    workspace; no floating-point atomics)."""
     import os
     from paper_2110_02590_amd import Problem
     g = gridgen.grid("syn2000")
     ep = gridgen.eval_point(g)
     out = []
-    for streams in ("1", None):
+    for streams in ("1", "3"):
         old = os.environ.pop("RPF_HVP_STREAMS", None)
         if streams:
             os.environ["RPF_HVP_STREAMS"] = streams

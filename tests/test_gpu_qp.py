@@ -118,10 +118,10 @@ def _kkt_blocks(H, J, grad, P, c, s, delta, d, nu):
 
 
 def test_largest_workload_kkt_certificate():
-    """9241 buses in the benchmark's launch configuration (batches of 512 on
-    three streams): the GPU step satisfies the QP's KKT conditions, built in
-    NumPy from the GPU's own H and J, to the stopping tolerance; the
-    multipliers are positive and the step lies inside its box."""
+    """9241 buses in the benchmark's launch configuration (batches of 512):
+    the GPU step satisfies the QP's KKT conditions, built in NumPy from the
+    GPU's own H and J, to the stopping tolerance; the multipliers are
+    positive and the step lies inside its box."""
     print("[case] qp syn9241", flush=True)
     g, ep, M, u, x, P, s, lo, hi, pr = _case("syn9241", max_batch=512)
     ulo, uhi = M.u_bounds()
