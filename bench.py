@@ -318,6 +318,31 @@ def graph_leg(grid, pr, PD, QD, s, y, rho, sigma, B, delta, steps, warm):
                     "captured inputs before each replay (inside the timed region)"}
 
 
+def _ju_row_counts(g, perm):
+    """Entries of J_u in each row of the library's state order (perm maps a
+    row to its index in x = (theta_pv, theta_pq, v_pq); a row is the P or Q
+    balance of that bus).  The balance of bus i depends on the voltage
+    magnitudes of the REF and PV buses among i and its neighbours, and the P
+    balance of a PV bus on its own p_pv."""
+    import numpy as np
+
+    import gridgen
+    bt, nb = g["bus_type"], g["nb"]
+    pv = np.flatnonzero(bt == gridgen.PV)
+    pq = np.flatnonzero(bt == gridgen.PQ)
+    ctrl = bt != gridgen.PQ
+    nbr = [{i} for i in range(nb)]
+    for f, t in zip(g["br_from"], g["br_to"]):
+        nbr[f].add(int(t))
+        nbr[t].add(int(f))
+    nv = np.array([sum(1 for j in nbr[i] if ctrl[j]) for i in range(nb)])
+    npv, npq = pv.size, pq.size
+    perm = np.asarray(perm)
+    bus = np.where(perm < npv, pv[np.minimum(perm, npv - 1)],
+                   pq[np.clip(np.where(perm < npv + npq, perm - npv, perm - npv - npq), 0, npq - 1)])
+    return nv[bus] + (perm < npv)
+
+
 def roofline(g, pr, prof, B, steps):
     """Roofline figures of the batched kernels from the library's HIP-event
     timings (events recorded on the launch stream around each launch).
@@ -330,11 +355,15 @@ def roofline(g, pr, prof, B, steps):
         backward 12 nnz(U_pack, pack columns) + 4 (t0 + 1) + 8 t0 + 16 t0 ncols
         (nnz(U_pack, pack columns) = nnz(L_pack) by symmetry of the pattern;
         with J_x^T the unit and non-unit factors swap);
-      top solve (k_top_rhs_w + k_top_inv_apply + k_pack_topmul_w), one per solve
-      pair (the dense top inverse read once):
+        the forward launch of J_x forms its right-hand side R = -J_u V
+        itself: its R read is replaced by 12 nnz(J_u, pack rows) + 8 n_u
+        ncols (V read once); every backward launch subtracts the pack rows'
+        top-column products itself: + 12 nnz(U, pack rows, top columns)
+        + 8 n_top ncols (the solved top part read once);
+      top solve (k_top_rhs_w + k_top_inv_apply), one per solve pair (the
+      dense top inverse read once):
         12 nnz(L, top rows, pack columns) + 8 ncols #(pack columns read)
-        + 8 n_top^2 + 16 n_top ncols
-        + 12 nnz(U, pack rows, top columns) + 16 ncols #(pack rows with top entries);
+        + 8 n_top^2 + 16 n_top ncols;
       refactorization (per call): LU values read and written (16 B each),
         update targets 4 B each, update pointers 8 B per entry.
     The dense Cholesky group is priced in FLOPs: n_u^3/3 + 2 n_u^2."""
@@ -354,12 +383,17 @@ def roofline(g, pr, prof, B, steps):
     nnz_pt = int(np.sum(packtop))
     nrow_pt = int(np.unique(rows[packtop]).size)
     nu = pr.nu
+    ju_rows = _ju_row_counts(g, binding.presolve_pattern(g)[0])
+    nnz_ju_pack = int(ju_rows[:t0].sum())
+    if int(ju_rows.sum()) != info["nnz_ju"]:
+        raise RuntimeError("J_u pattern count disagrees with the library's")
     cols = [min(B, nu - j0) for j0 in range(0, nu, B)]   # one reduced Hessian
     # per batch: two solve pairs (J_x and J_x^T), each one forward and one
     # backward pack launch and one top solve
-    pack_bytes = sum(2 * (12 * 2 * nnz_lp + 8 * (t0 + 1) + 8 * t0 + 32 * t0 * c) for c in cols)
-    top_bytes = sum(2 * (12 * nnz_tl + 8 * c * ncol_tl + 8 * ntop * ntop + 16 * ntop * c
-                         + 12 * nnz_pt + 16 * c * nrow_pt) for c in cols)
+    pack_bytes = sum(2 * (12 * 2 * nnz_lp + 8 * (t0 + 1) + 8 * t0 + 32 * t0 * c)
+                     - 8 * t0 * c + 12 * nnz_ju_pack + 8 * nu * c
+                     + 2 * (12 * nnz_pt + 8 * ntop * c) for c in cols)
+    top_bytes = sum(2 * (12 * nnz_tl + 8 * c * ncol_tl + 8 * ntop * ntop + 16 * ntop * c) for c in cols)
     pack_launches, top_launches = 4 * len(cols), 2 * len(cols)
     rf_bytes = 16 * info["nnz_lu"] + 4 * info["refactor_updates"] + 8 * info["nnz_lu"]
     chol_flops = nu ** 3 / 3.0 + 2.0 * nu * nu
@@ -385,11 +419,12 @@ def roofline(g, pr, prof, B, steps):
 
     add("pack_solve", "k_pack_solve_t (batched triangular solves in the subtree packs)", "pack_batch",
         pack_bytes / pack_launches, "hbm", HBM_PEAK_GBS, "GB/s",
-        f"bytes; nnz(L_pack)={nnz_lp}, t0={t0}, B={B}")
-    add("top_solve", "k_top_rhs_w + k_top_inv_apply + k_pack_topmul_w (top rows of the batched solves)",
+        f"bytes; nnz(L_pack)={nnz_lp}, t0={t0}, nnz(J_u,pack rows)={nnz_ju_pack}, "
+        f"nnz(U_pack,top cols)={nnz_pt}, B={B}")
+    add("top_solve", "k_top_rhs_w + k_top_inv_apply (top rows of the batched solves)",
         "top_batch",
         top_bytes / top_launches, "hbm", HBM_PEAK_GBS, "GB/s",
-        f"bytes; nnz(L_top,pack cols)={nnz_tl}, n_top={ntop}, nnz(U_pack,top cols)={nnz_pt}, B={B}")
+        f"bytes; nnz(L_top,pack cols)={nnz_tl}, n_top={ntop}, B={B}")
     add("refactor", "LU refactorization (k_rf_pack_lds, k_rf_top_ext, dense top LU)", "refactor",
         rf_bytes, "hbm", HBM_PEAK_GBS, "GB/s",
         f"bytes; nnz(L+U)={info['nnz_lu']}, updates={info['refactor_updates']}")
@@ -398,9 +433,11 @@ def roofline(g, pr, prof, B, steps):
     # J_u^T Psi (n_u rows): each entry 12 B, each operand row read and each
     # result row written once (8 B per column)
     nvar, nr1 = nx + nu, 2 + (nu - 1) // 2     # rank-one rows: p_ref, q_ref, q at each PV bus
-    spmm_bytes = sum(12 * (2 * info["nnz_ju"] + 2 * info["nnz_g"] + info["nnz_k"])
-                     + 8 * c * ((nu + nx) + (nvar + nr1) + (2 * nvar + nr1) + (nx + 2 * nu)) for c in cols)
-    add("spmm", "k_spmm (J_u V, G D, K D + G^T diag(kappa) T, J_u^T Psi)", "spmm", spmm_bytes / (4 * len(cols)),
+    # (R only on the top rows: the pack rows are formed in the pack solve)
+    spmm_bytes = sum(12 * (2 * info["nnz_ju"] - nnz_ju_pack + 2 * info["nnz_g"] + info["nnz_k"])
+                     + 8 * c * ((nu + ntop) + (nvar + nr1) + (2 * nvar + nr1) + (nx + 2 * nu)) for c in cols)
+    add("spmm", "k_spmm (top rows of J_u V, G D, K D + G^T diag(kappa) T, J_u^T Psi)", "spmm",
+        spmm_bytes / (4 * len(cols)),
         "hbm", HBM_PEAK_GBS, "GB/s",
         f"bytes; nnz(J_u)={info['nnz_ju']}, nnz(K)={info['nnz_k']}, nnz(G)={info['nnz_g']}, B={B}")
     add("cholesky", "dense Cholesky group (k_symmetrize, k_blk_*<true>, k_chol_fwd/bwd)", "dense",

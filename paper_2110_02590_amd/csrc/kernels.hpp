@@ -1417,6 +1417,22 @@ __device__ __forceinline__ void tail_apply(double* xs, const int16_t* sT, int nT
   lds_barrier();
 }
 
+// Optional fusions of the batched pack solves: forward, the right-hand side
+// R = -J_u V staged from V (J_u in CSR over the state rows: jp, jc, jv; V
+// [n_u x ncols] with leading dimension ldv) instead of read from X;
+// backward, the top-column products of the pack rows listed in tmrows
+// [tmoff[q] .. tmoff[q+1]) subtracted after staging (their values from val,
+// the solved top rows from X).
+struct PackFuse {
+  const int32_t* jp = nullptr;
+  const int32_t* jc = nullptr;
+  const double* jv = nullptr;
+  const double* V = nullptr;
+  int ldv = 0;
+  const int32_t* tmoff = nullptr;
+  const int32_t* tmrows = nullptr;
+};
+
 template <int TW, bool FWD, bool UNIT, bool SV>
 __global__ void __launch_bounds__(1024) k_pack_solve_t(const int32_t* __restrict__ pack_ptr,
                                                        const int32_t* __restrict__ lev,
@@ -1434,7 +1450,7 @@ __global__ void __launch_bounds__(1024) k_pack_solve_t(const int32_t* __restrict
                                                        const int32_t* __restrict__ toff,
                                                        const int16_t* __restrict__ trows,
                                                        const double* __restrict__ tinv,
-                                                       const int32_t* __restrict__ skip) {
+                                                       const int32_t* __restrict__ skip, PackFuse fz) {
   if (skip && *skip) return;
   constexpr int S = 64 / TW;   // lanes per column in a wavefront
   constexpr int LGS = S == 8 ? 3 : S == 4 ? 2 : S == 2 ? 1 : 0;
@@ -1475,21 +1491,93 @@ __global__ void __launch_bounds__(1024) k_pack_solve_t(const int32_t* __restrict
     smeta[p] = (es - e0) | ((ee - es) << 20);
   }
   for (int k = t; k <= nlev; k += nt) slev[k] = lev[l0 + k] - base_row;
-  // right-hand-side tile, eight loads in flight per thread
   const int ntile = nr * TW;
-  for (int eb = t; eb < ntile; eb += 8 * nt) {
-    double v[8];
+  if (FWD && fz.jp) {
+    // right-hand side R = -J_u V formed here from the directions V (rows of
+    // J_u over the pack's rows, a few entries each): eight elements per
+    // thread at a time, each round of loads (row bounds, entries, V) issued
+    // for all eight before any is used
+    for (int eb = t; eb < ntile; eb += 8 * nt) {
+      int pa[8], pb[8], cc[8];
+      int kmax = 0;
 #pragma unroll
-    for (int m = 0; m < 8; ++m) {
-      const int e = min(eb + m * nt, ntile - 1);
-      const int r = e / TW, c = e - r * TW;
-      v[m] = X[(size_t)(r0 + r) * ld + min(c0 + c, ncols - 1)];
+      for (int m = 0; m < 8; ++m) {
+        const int e = min(eb + m * nt, ntile - 1);
+        const int r = e / TW;
+        cc[m] = min(c0 + (e - r * TW), ncols - 1);
+        pa[m] = fz.jp[r0 + r];
+        pb[m] = fz.jp[r0 + r + 1];
+      }
+#pragma unroll
+      for (int m = 0; m < 8; ++m) kmax = max(kmax, pb[m] - pa[m]);
+      double acc[8];
+#pragma unroll
+      for (int m = 0; m < 8; ++m) acc[m] = 0.0;
+      for (int k = 0; k < kmax; ++k) {
+        double jv[8];
+        int jc[8];
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {
+          const int pp = min(pa[m] + k, max(pb[m] - 1, pa[m]));
+          jv[m] = pa[m] + k < pb[m] ? fz.jv[pp] : 0.0;
+          jc[m] = pa[m] + k < pb[m] ? fz.jc[pp] : 0;
+        }
+        double vv[8];
+#pragma unroll
+        for (int m = 0; m < 8; ++m) vv[m] = fz.V[(size_t)jc[m] * fz.ldv + cc[m]];
+#pragma unroll
+        for (int m = 0; m < 8; ++m) acc[m] += jv[m] * vv[m];
+      }
+#pragma unroll
+      for (int m = 0; m < 8; ++m)
+        if (eb + m * nt < ntile) xs[eb + m * nt] = -scale * acc[m];
     }
+  } else {
+    // right-hand-side tile, eight loads in flight per thread
+    for (int eb = t; eb < ntile; eb += 8 * nt) {
+      double v[8];
 #pragma unroll
-    for (int m = 0; m < 8; ++m)
-      if (eb + m * nt < ntile) xs[eb + m * nt] = FWD ? scale * v[m] : v[m];
+      for (int m = 0; m < 8; ++m) {
+        const int e = min(eb + m * nt, ntile - 1);
+        const int r = e / TW, c = e - r * TW;
+        v[m] = X[(size_t)(r0 + r) * ld + min(c0 + c, ncols - 1)];
+      }
+#pragma unroll
+      for (int m = 0; m < 8; ++m)
+        if (eb + m * nt < ntile) xs[eb + m * nt] = FWD ? scale * v[m] : v[m];
+    }
   }
   __syncthreads();
+  if (!FWD && fz.tmoff) {
+    // backward: the products of the pack rows that have entries in top
+    // columns with the solved top part, subtracted here (one thread per row
+    // and column; a row's entries eight at a time, all their loads issued
+    // before the first is used, summed in entry order)
+    const int a0 = fz.tmoff[q], na = fz.tmoff[q + 1] - a0;
+    for (int e = t; e < na * TW; e += nt) {
+      const int rr = e / TW, c = e - rr * TW;
+      const int i = fz.tmrows[a0 + rr];
+      const int cc = min(c0 + c, ncols - 1);
+      const int pa = up_split[i], pb = ptr[i + 1];
+      double acc = 0.0;
+      for (int pp = pa; pp < pb; pp += 8) {
+        double vv[8], xv[8];
+        int cl[8];
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {
+          const int pm = min(pp + m, pb - 1);
+          vv[m] = pp + m < pb ? val[pm] : 0.0;
+          cl[m] = col[pm];
+        }
+#pragma unroll
+        for (int m = 0; m < 8; ++m) xv[m] = X[(size_t)cl[m] * ld + cc];
+#pragma unroll
+        for (int m = 0; m < 8; ++m) acc += vv[m] * xv[m];
+      }
+      xs[(i - r0) * TW + c] -= acc;
+    }
+    __syncthreads();
+  }
   const double* Mq = tinv + (size_t)q * TAIL_MAX * TAIL_MAX;
   // backward: the tail rows first, by the dense inverse of U_TT (or L_TT^T)
   if (!FWD && nT > 0) tail_apply<TW>(xs, sT, nT, Mq, false);

@@ -75,6 +75,7 @@ struct rpf_grid {
   int32_t *pq, *pv, *gen_pidx, *pv_gen, *var_kind, *var_aux;
   int32_t *pack_ptr, *lo_split, *up_split, *pk_flev, *pk_flev_off, *pk_frows, *pk_blev, *pk_blev_off, *pk_brows;
   int32_t* topmul_rows = nullptr;   // pack rows with U entries in top columns
+  int32_t* tm_off = nullptr;        // per pack: its range of topmul_rows
   int n_topmul_rows = 0;
   int32_t *top_flev, *top_frows, *top_blev, *top_brows, *top_pos;
   int64_t* top_dense;
@@ -303,6 +304,12 @@ void setup(rpf_grid* h) {
       if (P.up_split[i] < P.lu_ptr[i + 1]) rows.push_back(i);
     h->n_topmul_rows = (int)rows.size();
     h->topmul_rows = h->up(rows);
+    // per pack: its rows' range in that ascending list
+    const int npk = (int)P.pack_ptr.size() - 1;
+    std::vector<int32_t> off(npk + 1, 0);
+    for (int q = 0; q < npk; ++q)
+      off[q + 1] = (int)(std::lower_bound(rows.begin(), rows.end(), P.pack_ptr[q + 1]) - rows.begin());
+    h->tm_off = h->up(off);
   }
   h->pk_flev = h->up(P.pk_flev);
   h->pk_flev_off = h->up(P.pk_flev_off);
@@ -695,7 +702,8 @@ void pack_solve(rpf_grid* h, bool fwd, bool unit, const double* val, double* X, 
 // solved in place in X.
 template <int TW, bool SV>
 void pack_solve_t(rpf_grid* h, bool fwd, bool unit, bool transposed, const double* val, double* X, int ld,
-                  int ncols, double scale, hipStream_t s, const int32_t* skip) {
+                  int ncols, double scale, hipStream_t s, const int32_t* skip, const PackFuse* fzp = nullptr) {
+  const PackFuse fz = fzp ? *fzp : PackFuse{};
   const int ntiles = cdiv(ncols, TW);
   const dim3 grd(8 * cdiv(h->npacks, 8) * ntiles);   // see the XCD mapping in k_pack_solve_t
   const double* pv = fwd ? (transposed ? h->pkfvT : h->pkfv) : (transposed ? h->pkbvT : h->pkbv);
@@ -708,7 +716,7 @@ void pack_solve_t(rpf_grid* h, bool fwd, bool unit, bool transposed, const doubl
                     const int16_t* ecol) {
     kern<<<grd, 1024, h->lds_packt, s>>>(h->pack_ptr, lev, lev_off, rows, rp, ecol, pv, h->rdiag, h->up_split,
                                          h->lu_ptr, h->lu_col, val, X, ld, ncols, scale, h->npacks, ntiles,
-                                         h->ptl_off, h->ptl_rows, tinv, skip);
+                                         h->ptl_off, h->ptl_rows, tinv, skip, fz);
   };
   if (fwd) {
     if (unit) launch(k_pack_solve_t<TW, true, true, SV>, h->ptf_lev, h->ptf_lev_off, h->ptf_rows, h->ptf_rp, h->ptf_col);
@@ -721,13 +729,14 @@ void pack_solve_t(rpf_grid* h, bool fwd, bool unit, bool transposed, const doubl
 }
 
 void pack_solve_g(rpf_grid* h, bool fwd, bool unit, bool transposed, const double* val, double* X, int ld,
-                  int ncols, double scale, int cls, hipStream_t s, const int32_t* skip) {
+                  int ncols, double scale, int cls, hipStream_t s, const int32_t* skip,
+                  const PackFuse* fz = nullptr) {
   if (h->npacks == 0) return;
   if (h->tw_packt > 0) {
     size_t pi = h->prof_on ? h->prof_begin(s) : 0;
-    if (h->tw_packt == 16) pack_solve_t<16, false>(h, fwd, unit, transposed, val, X, ld, ncols, scale, s, skip);
-    else if (h->sv_packt) pack_solve_t<8, true>(h, fwd, unit, transposed, val, X, ld, ncols, scale, s, skip);
-    else pack_solve_t<8, false>(h, fwd, unit, transposed, val, X, ld, ncols, scale, s, skip);
+    if (h->tw_packt == 16) pack_solve_t<16, false>(h, fwd, unit, transposed, val, X, ld, ncols, scale, s, skip, fz);
+    else if (h->sv_packt) pack_solve_t<8, true>(h, fwd, unit, transposed, val, X, ld, ncols, scale, s, skip, fz);
+    else pack_solve_t<8, false>(h, fwd, unit, transposed, val, X, ld, ncols, scale, s, skip, fz);
     if (h->prof_on) h->prof_end(cls, pi, s);
     return;
   }
@@ -749,8 +758,8 @@ void pack_solve_g(rpf_grid* h, bool fwd, bool unit, bool transposed, const doubl
 }
 
 void pack_solve_any(rpf_grid* h, int tw, bool fwd, bool unit, bool transposed, const double* val, double* X,
-                    int ld, int ncols, double scale, int cls, hipStream_t s, const int32_t* skip) {
-  if (ncols > 1) return pack_solve_g(h, fwd, unit, transposed, val, X, ld, ncols, scale, cls, s, skip);
+                    int ld, int ncols, double scale, int cls, hipStream_t s, const int32_t* skip, const PackFuse* fz = nullptr) {
+  if (ncols > 1) return pack_solve_g(h, fwd, unit, transposed, val, X, ld, ncols, scale, cls, s, skip, fz);
   switch (tw) {
     case 16: return pack_solve<16>(h, fwd, unit, val, X, ld, ncols, scale, cls, s, skip);
     case 8: return pack_solve<8>(h, fwd, unit, val, X, ld, ncols, scale, cls, s, skip);
@@ -764,8 +773,12 @@ void pack_solve_any(rpf_grid* h, int tw, bool fwd, bool unit, bool transposed, c
 // (scale X), or of J_x^T (transposed = true): X <- L^{-T} U^{-T} (scale X).
 // Four launches: packs forward, right-hand side of the top rows (pack
 // contributions), dense top part forward + backward, packs backward.
+// rf (forward, J_x only): the first pack solve forms R = -J_u V itself
+// (the caller has formed the top rows of R).  With the LDS-tile pack solves
+// the backward pack solve subtracts the pack rows' top-column products
+// itself.
 void solve_pair(rpf_grid* h, bool transposed, double* X, int ld, int ncols, double scale, hipStream_t s,
-                const int32_t* skip = nullptr) {
+                const int32_t* skip = nullptr, const PackFuse* rf = nullptr) {
   const Presolve& P = h->P;
   const double* val = transposed ? h->lutv : h->luv;
   // forward factor: L (unit) or U^T (non-unit); backward: U (non-unit) or L^T (unit)
@@ -773,7 +786,8 @@ void solve_pair(rpf_grid* h, bool transposed, double* X, int ld, int ncols, doub
   const int cls = ncols > 1 ? 0 : 1;
   const int twp = ncols == 1 ? 1 : h->tw_pack;
   const int twt = ncols == 1 ? 1 : h->tw_top;
-  pack_solve_any(h, twp, true, fwd_unit, transposed, val, X, ld, ncols, scale, cls, s, skip);
+  pack_solve_any(h, twp, true, fwd_unit, transposed, val, X, ld, ncols, scale, cls, s, skip, rf);
+  const bool fuse_top = ncols > 1 && h->tw_packt > 0 && h->npacks > 0;
   if (P.ntop > 0) {
     size_t pi = h->prof_on ? h->prof_begin(s) : 0;
     // single right-hand sides of the power flow and adjoint: lanes split a
@@ -820,7 +834,7 @@ void solve_pair(rpf_grid* h, bool transposed, double* X, int ld, int ncols, doub
       }
       LAUNCHCHK();
     }
-    if (ncols > 1 && h->tw_packt > 0 && h->npacks > 0) {
+    if (ncols > 1 && h->tw_packt > 0 && h->npacks > 0 && !fuse_top) {
       // the LDS-tile pack solves expect the top products already subtracted
       if (h->n_topmul_rows > 0) {
         const int nr = h->n_topmul_rows;
@@ -837,7 +851,13 @@ void solve_pair(rpf_grid* h, bool transposed, double* X, int ld, int ncols, doub
     }
     if (h->prof_on) h->prof_end(cls == 0 ? 5 : cls, pi, s);
   }
-  pack_solve_any(h, twp, false, !fwd_unit, transposed, val, X, ld, ncols, 1.0, cls, s, skip);
+  PackFuse bf;
+  if (fuse_top && P.ntop > 0) {
+    bf.tmoff = h->tm_off;
+    bf.tmrows = h->topmul_rows;
+  }
+  pack_solve_any(h, twp, false, !fwd_unit, transposed, val, X, ld, ncols, 1.0, cls, s, skip,
+                 fuse_top ? &bf : nullptr);
 }
 
 // Y = alpha A1 X1 (+ Yadd); with A2, then Y = A2 X2 + that (one pass).
@@ -961,10 +981,24 @@ void hvp_batch(rpf_grid* h, const double* V, int ldv, int j0, int B, double* HV,
     k_identity_block<<<dim3(cdiv(B, 64), cdiv(P.nu, 4)), blk, 0, s>>>(P.nu, B, j0, Du, ld, h->skipw);
   }
   LAUNCHCHK();
-  // R = -J_u V
-  spmm(h, P.nx, h->ju_ptr, h->ju_col, h->juv, nullptr, nullptr, Du, ld, B, -1.0, nullptr, 0, Dx, ld, s);
-  // Z = U^{-1} L^{-1} R
-  solve_pair(h, false, Dx, ld, B, 1.0, s, h->skipw);
+  // R = -J_u V, then Z = U^{-1} L^{-1} R.  With the LDS-tile pack solves
+  // the first pack solve forms the pack rows of R itself; only the top rows
+  // are formed here
+  if (h->tw_packt > 0 && h->npacks > 0 && B > 1) {
+    if (P.ntop > 0)
+      spmm(h, P.ntop, h->ju_ptr + P.t0, h->ju_col, h->juv, nullptr, nullptr, Du, ld, B, -1.0, nullptr, 0,
+           Dx + (size_t)P.t0 * ld, ld, s);
+    PackFuse rf;
+    rf.jp = h->ju_ptr;
+    rf.jc = h->ju_col;
+    rf.jv = h->juv;
+    rf.V = Du;
+    rf.ldv = ld;
+    solve_pair(h, false, Dx, ld, B, 1.0, s, h->skipw, &rf);
+  } else {
+    spmm(h, P.nx, h->ju_ptr, h->ju_col, h->juv, nullptr, nullptr, Du, ld, B, -1.0, nullptr, 0, Dx, ld, s);
+    solve_pair(h, false, Dx, ld, B, 1.0, s, h->skipw);
+  }
   // Y = K [Z; V] + G^T diag(kappa) G [Z; V]
   // (T = G [Z; V] first; then both terms of Y in one pass over its rows)
   spmm(h, P.nr1, h->G_ptr, h->G_col, h->Gv, nullptr, nullptr, D, ld, B, 1.0, nullptr, 0, T, ld, s);
