@@ -272,6 +272,31 @@ def test_factor_solve_full_size():
     assert _rel(step.cpu().numpy(), so) < 1e-9
 
 
+@pytest.mark.parametrize("n", [1, 63, 64, 65, 128, 129, 200, 191 + 64 * 3, 700, 1500])
+def test_factor_sizes_match_oracle(n):
+    """The blocked dense Cholesky and its triangular solves at orders from
+    one 64-column block to 24 blocks (full and ragged last blocks), on
+    seeded SPD matrices, against the oracle's column Cholesky and
+    triangular solves; the upper triangle is not touched."""
+    c = case("syn9241", max_batch=512)
+    print(f"[case] factor n={n}", flush=True)
+    rng = np.random.default_rng(1000 + n)
+    A = rng.standard_normal((n, n))
+    K = A @ A.T / n + np.eye(n)
+    K = 0.5 * (K + K.T)                  # exactly symmetric
+    Kt = torch.tensor(K, device="cuda")
+    rhs = rng.standard_normal(n)
+    step, info = c.pr.grid.factor_solve(Kt, torch.tensor(rhs, device="cuda"))
+    torch.cuda.synchronize()
+    Lo, io, so = oracle.factor_solve(K, None, 0.0, rhs)
+    assert int(info) == 0 and io == 0
+    assert _rel(np.tril(Kt.cpu().numpy()), Lo) < 1e-12
+    assert _rel(step.cpu().numpy(), so) < 1e-11
+    # the upper triangle is left as it was
+    iu = np.triu_indices(n, 1)
+    assert np.array_equal(Kt.cpu().numpy()[iu], K[iu])
+
+
 def test_concurrent_batches_match_one_stream():
     """Batches on three handle-owned streams (RPF_HVP_STREAMS=3) give the
     same reduced Hessian, bit for bit, as one stream (each batch has its own
