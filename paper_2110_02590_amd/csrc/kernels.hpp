@@ -1417,6 +1417,68 @@ __device__ __forceinline__ void tail_apply(double* xs, const int16_t* sT, int nT
   lds_barrier();
 }
 
+// tail_apply for 16 columns on the FP64 matrix cores: wave w < 8 forms rows
+// 16 w .. 16 w + 15 of M x_T (v_mfma_f64_16x16x4f64: A = rows of M read
+// straight from memory, lane i + 16 k holding M(i, k); B = the tail rows of
+// the tile, lane c + 16 k holding x(k, c); the result's lane c + 16 q holds
+// rows q + 4 r of column c), over the triangle's k range in chunks of 32,
+// the next chunk's operands loaded during the current chunk's products.
+// Entries of M outside the triangle or past nT are not used.
+__device__ __forceinline__ void tail_apply_mfma(double* xs, const int16_t* sT, int nT, const double* __restrict__ M,
+                                                bool lower) {
+  constexpr int TW = 16;
+  const int t = threadIdx.x, w = t >> 6, l = t & 63;
+  const int li = l & 15, lk = l >> 4;
+  const int rb = w;
+  const bool active = rb < 8 && 16 * rb < nT;
+  dbl4 acc = dbl4{0.0, 0.0, 0.0, 0.0};
+  if (active) {
+    const int i = 16 * rb + li;
+    const int ka = lower ? 0 : 16 * rb, kb = lower ? min(16 * rb + 16, nT) : nT;
+    const double* mrow = M + (size_t)i * TAIL_MAX;
+    double av[8], bv[8];
+    auto load = [&](int k0) {
+#pragma unroll
+      for (int m = 0; m < 8; ++m) {
+        const int k = k0 + 4 * m + lk;
+        const int kc = min(k, nT - 1);
+        const bool inA = i < nT && k < kb && (lower ? k <= i : k >= i);
+        const double g = mrow[kc];
+        av[m] = inA ? g : 0.0;
+        bv[m] = k < kb ? xs[sT[kc] * TW + li] : 0.0;
+      }
+    };
+    load(ka);
+    for (int k0 = ka; k0 < kb; k0 += 32) {
+      double a2[8], b2[8];
+#pragma unroll
+      for (int m = 0; m < 8; ++m) {
+        a2[m] = av[m];
+        b2[m] = bv[m];
+      }
+      if (k0 + 32 < kb) load(k0 + 32);
+#pragma unroll
+      for (int m = 0; m < 8; ++m) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a2[m], b2[m], acc, 0, 0, 0);
+    }
+  }
+  lds_barrier();
+  if (active) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = 16 * rb + lk + 4 * r;
+      if (row < nT) xs[sT[row] * TW + li] = acc[r];
+    }
+  }
+  lds_barrier();
+}
+
+template <int TW>
+__device__ __forceinline__ void tail_apply_any(double* xs, const int16_t* sT, int nT, const double* __restrict__ M,
+                                               bool lower) {
+  if constexpr (TW == 16) tail_apply_mfma(xs, sT, nT, M, lower);
+  else tail_apply<TW>(xs, sT, nT, M, lower);
+}
+
 // Optional fusions of the batched pack solves: forward, the right-hand side
 // R = -J_u V staged from V (J_u in CSR over the state rows: jp, jc, jv; V
 // [n_u x ncols] with leading dimension ldv) instead of read from X;
@@ -1580,7 +1642,7 @@ __global__ void __launch_bounds__(1024) k_pack_solve_t(const int32_t* __restrict
   }
   const double* Mq = tinv + (size_t)q * TAIL_MAX * TAIL_MAX;
   // backward: the tail rows first, by the dense inverse of U_TT (or L_TT^T)
-  if (!FWD && nT > 0) tail_apply<TW>(xs, sT, nT, Mq, false);
+  if (!FWD && nT > 0) tail_apply_any<TW>(xs, sT, nT, Mq, false);
   const int wave = t >> 6, lane = t & 63, nwave = nt >> 6;
   const int cI = lane & (TW - 1);
   const int sub = lane / TW;   // 0 .. S - 1
@@ -1642,7 +1704,7 @@ __global__ void __launch_bounds__(1024) k_pack_solve_t(const int32_t* __restrict
     lds_barrier();
   }
   // forward: the tail rows by the dense inverse of L_TT (or U_TT^T)
-  if (FWD && nT > 0) tail_apply<TW>(xs, sT, nT, Mq, true);
+  if (FWD && nT > 0) tail_apply_any<TW>(xs, sT, nT, Mq, true);
   for (int e = t; e < ntile; e += nt) {
     const int r = e / TW, c = e - r * TW;
     if (c0 + c < ncols) X[(size_t)(r0 + r) * ld + c0 + c] = xs[e];
