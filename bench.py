@@ -35,24 +35,39 @@ FP64_PEAK_TFLOPS = 78.6
 # batch 512 (FETCH_SIZE scaled by 2.0 and WRITE_SIZE by 1.0: what the two
 # counters read for a 1 GiB streaming kernel; KiB per dispatch averaged over
 # the four forward/backward x J_x/J_x^T variants).  Valid only for the kernel
-# source it was measured on (sha1 of the kernel's text in kernels.hpp) and
-# for the batch width it was measured at; reported as null otherwise.
+# source it was measured on (sha1 of the kernel's text and of the device
+# functions it calls, in kernels.hpp) and for the batch width it was
+# measured at; reported as null otherwise.
 # Figures and commands: profiles/pack_solve_t_syn9241_traffic.txt.
 TRAFFIC = {
-    "pack_solve": {"kernel": "k_pack_solve_t", "batch": 512, "bytes_per_launch": 130533888,
-                   "source_sha1": "2679c824e7a7f61f3be60656ef34ca4878385926"},
+    "pack_solve": {"kernel": "k_pack_solve_t", "helpers": ["tail_apply", "tail_apply_mfma", "tail_apply_any",
+                                                           "stage_1d", "sum_xor16", "sum_xor32", "lds_barrier"],
+                   "batch": 512, "bytes_per_launch": 120593011,
+                   "source_sha1": "9dc375d36de5548b62e2830f72acd14df4219992"},
 }
 
 
-def _kernel_sha1(name):
-    """sha1 of a kernel's text (from its __global__ line to the closing
-    brace) in the library's kernel header."""
+def _func_text(src, name):
+    """Text of a function definition in the kernel header: from its
+    __global__ / __device__ line (with a template line before it) to the
+    closing brace at column 0."""
+    import re
+    m = re.search(r"\n((?:template <[^\n]*>\n)?__(?:global|device)__[^\n]*[ *&]" + re.escape(name) + r"\()", src)
+    if m is None:
+        raise KeyError(name)
+    j = src.index("\n}\n", m.start(1)) + 3
+    return src[m.start(1):j]
+
+
+def _kernel_sha1(name, helpers=()):
+    """sha1 of a kernel's text and of the listed device functions' texts in
+    the library's kernel header."""
     import hashlib
     src = open(os.path.join(ROOT, "paper_2110_02590_amd", "csrc", "kernels.hpp")).read()
-    i = src.index(" " + name + "(")
-    st = src.rfind("\n__global__", 0, i)
-    j = src.index("\n}\n", i) + 3
-    return hashlib.sha1(src[st + 1:j].encode()).hexdigest()
+    h = hashlib.sha1(_func_text(src, name).encode())
+    for f in helpers:
+        h.update(_func_text(src, f).encode())
+    return h.hexdigest()
 
 
 def parse():
@@ -443,7 +458,7 @@ def roofline(g, pr, prof, B, steps):
     add("cholesky", "dense Cholesky group (k_symmetrize, k_blk_*<true>, k_chol_fwd/bwd)", "dense",
         chol_flops, "mfma", FP64_PEAK_TFLOPS, "TFLOP/s", f"flops n_u^3/3 + 2 n_u^2, n_u={nu}")
     for name, tr in TRAFFIC.items():
-        if name in ent and _kernel_sha1(tr["kernel"]) == tr["source_sha1"] and tr["batch"] == B:
+        if name in ent and _kernel_sha1(tr["kernel"], tr["helpers"]) == tr["source_sha1"] and tr["batch"] == B:
             ent[name]["traffic"] = tr["bytes_per_launch"]
     if not ent:
         return None, {}
