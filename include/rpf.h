@@ -66,6 +66,12 @@
  *    index in x of a failing pivot (0 = all pivots passed); the solves with
  *    such a factor are not meaningful.
  *  - A handle is not thread-safe; use one handle per host thread / stream.
+ *  - Tracing: with the environment variable RPF_TRACE set (not empty, not
+ *    "0") when a handle is created, each compute call on it records two
+ *    events on `stream` and, once they have completed, writes one line
+ *    {"rpf_trace": "<call>", "ms": <device time>, "arg": <size argument>}
+ *    to stderr -- polled at later calls on the handle, waited for when it is
+ *    destroyed.  Calls on a stream that is capturing a graph are not traced.
  */
 #ifndef RPF_H
 #define RPF_H

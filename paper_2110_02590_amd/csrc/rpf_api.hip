@@ -8,6 +8,8 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <deque>
+#include <exception>
 #include <mutex>
 #include <stdexcept>
 #include <string>
@@ -164,6 +166,48 @@ struct rpf_grid {
     ev_marks.push_back({cls, i});
   }
 
+  // per-call device timings, when RPF_TRACE was set (not empty, not "0")
+  // as the handle was created: two events around each traced call, each
+  // call reported as one JSON line on stderr once both have completed
+  // (polled at later calls, waited for when the handle is destroyed)
+  struct TraceRec {
+    const char* name;
+    hipEvent_t a, b;
+    long long arg;
+  };
+  bool trace_on = false;
+  std::deque<TraceRec> trace_q;
+  std::vector<hipEvent_t> trace_free;
+  hipEvent_t trace_event() {
+    if (trace_free.empty()) {
+      hipEvent_t e;
+      HIPCHK(hipEventCreate(&e));
+      return e;
+    }
+    hipEvent_t e = trace_free.back();
+    trace_free.pop_back();
+    return e;
+  }
+  void trace_report(bool wait) {
+    while (!trace_q.empty()) {
+      TraceRec r = trace_q.front();
+      if (wait) {
+        if (hipEventSynchronize(r.b) != hipSuccess) (void)hipGetLastError();
+      } else if (hipEventQuery(r.b) != hipSuccess) {
+        (void)hipGetLastError();   // not ready: not an error of the next call
+        break;
+      }
+      float ms = 0.0f;
+      if (hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess)
+        std::fprintf(stderr, "{\"rpf_trace\": \"%s\", \"ms\": %.4f, \"arg\": %lld}\n", r.name, ms, r.arg);
+      else
+        (void)hipGetLastError();
+      trace_free.push_back(r.a);
+      trace_free.push_back(r.b);
+      trace_q.pop_front();
+    }
+  }
+
   template <class T>
   T* up(const std::vector<T>& v) {
     size_t n = std::max<size_t>(v.size(), 1);
@@ -182,6 +226,8 @@ struct rpf_grid {
     return (T*)p;
   }
   ~rpf_grid() {
+    if (trace_on) trace_report(true);
+    for (hipEvent_t e : trace_free) (void)hipEventDestroy(e);
     for (int k = 0; k < HS; ++k) {
       if (hs[k]) (void)hipStreamDestroy(hs[k]);
       if (ev_join[k]) (void)hipEventDestroy(ev_join[k]);
@@ -190,6 +236,51 @@ struct rpf_grid {
     for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
     for (void* p : allocs) (void)hipFree(p);
   }
+};
+
+// Traced call (see rpf_grid::trace_on); calls on a stream that is capturing
+// a graph are not traced, and a call that fails reports nothing.
+struct Traced {
+  rpf_grid* h;
+  const char* name;
+  hipStream_t s;
+  long long arg;
+  hipEvent_t a = nullptr;
+  Traced(rpf_grid* h_, const char* name_, hipStream_t s_, long long arg_ = 0)
+      : h(h_), name(name_), s(s_), arg(arg_) {
+    if (!h->trace_on) return;
+    h->trace_report(false);
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) {
+      (void)hipGetLastError();
+      return;
+    }
+    a = h->trace_event();
+    HIPCHK(hipEventRecord(a, s));
+  }
+  ~Traced() {
+    if (!a) return;
+    if (std::uncaught_exceptions() > 0) {
+      h->trace_free.push_back(a);
+      return;
+    }
+    hipEvent_t b = nullptr;
+    if (!h->trace_free.empty()) {
+      b = h->trace_free.back();
+      h->trace_free.pop_back();
+    } else if (hipEventCreate(&b) != hipSuccess) {
+      b = nullptr;
+    }
+    if (!b || hipEventRecord(b, s) != hipSuccess) {
+      (void)hipGetLastError();
+      h->trace_free.push_back(a);
+      if (b) h->trace_free.push_back(b);
+      return;
+    }
+    h->trace_q.push_back({name, a, b, arg});
+  }
+  Traced(const Traced&) = delete;
+  Traced& operator=(const Traced&) = delete;
 };
 
 namespace {
@@ -1213,6 +1304,8 @@ int rpf_grid_create(const rpf_grid_desc* desc, int32_t max_batch, rpf_grid** out
       if ((int64_t)h->P.nvar * max_batch >= (int64_t)1 << 31)
         throw std::runtime_error("n_var * max_batch must stay below 2^31");
       setup(h);
+      const char* tr = std::getenv("RPF_TRACE");
+      h->trace_on = tr && *tr && std::strcmp(tr, "0") != 0;
     } catch (...) {
       delete h;
       throw;
@@ -1246,6 +1339,7 @@ int rpf_pf_solve(rpf_grid* h, const double* u, const double* pd, const double* q
   if (max_iter < 0 || max_iter > 100) return set_err(RPF_EINVAL, "max_iter must be in [0, 100]");
   return guard([&]() -> int {
     hipStream_t s = (hipStream_t)stream;
+    Traced trace_scope(h, "rpf_pf_solve", s, (long long)max_iter);
     const Presolve& P = h->P;
     h->have_point = false;
     x_in(h, x, s);
@@ -1267,6 +1361,7 @@ int rpf_al_objective(rpf_grid* h, const double* x, const double* u, const double
   if (!h || !x || !u || !pd || !qd || !sv || !y || !sigma || !phi) return set_err(RPF_EINVAL, "NULL argument");
   return guard([&]() -> int {
     hipStream_t s = (hipStream_t)stream;
+    Traced trace_scope(h, "rpf_al_objective", s);
     const Presolve& P = h->P;
     x_in(h, x, s);
     state_and_records(h, u, s);
@@ -1555,6 +1650,7 @@ int rpf_reduced_gradient(rpf_grid* h, const double* x, const double* u, const do
   if (!h || !x || !u || !pd || !qd || !sv || !y || !sigma || !grad) return set_err(RPF_EINVAL, "NULL argument");
   return guard([&]() -> int {
     hipStream_t s = (hipStream_t)stream;
+    Traced trace_scope(h, "rpf_reduced_gradient", s);
     x_in(h, x, s);
     gradient_core(h, u, pd, qd, sv, y, rho, sigma, grad, lambda, s);
     if (info) {
@@ -1572,6 +1668,7 @@ int rpf_reduced_hessian_batch(rpf_grid* h, const double* V, int32_t nbatch, int3
   if (nbatch < 1 || nbatch > h->max_batch) return set_err(RPF_ESIZE, "nbatch outside [1, max_batch]");
   if (ldv < nbatch || ldhv < nbatch) return set_err(RPF_EINVAL, "leading dimension below nbatch");
   return guard([&]() -> int {
+    Traced trace_scope(h, "rpf_reduced_hessian_batch", (hipStream_t)stream, (long long)nbatch);
     hvp_batch(h, V, ldv, 0, nbatch, HV, ldhv, (hipStream_t)stream);
     return RPF_OK;
   });
@@ -1582,6 +1679,7 @@ int rpf_reduced_derivatives(rpf_grid* h, double* H, double* J, int32_t batch, rp
   if (!h->have_point) return set_err(RPF_ESTATE, "no cached point: call rpf_reduced_gradient first");
   if (batch < 0) return set_err(RPF_EINVAL, "batch must be >= 0");
   return guard([&]() -> int {
+    Traced trace_scope(h, "rpf_reduced_derivatives", (hipStream_t)stream, (long long)batch);
     derivative_batches(h, H, J, batch, (hipStream_t)stream);
     return RPF_OK;
   });
@@ -1598,6 +1696,7 @@ int rpf_factor_solve(rpf_grid* h, int32_t n, double* K, const double* diag, doub
   if (n < 1 || n > h->P.nu) return set_err(RPF_EINVAL, "n must be in [1, n_u]");
   return guard([&]() -> int {
     hipStream_t s = (hipStream_t)stream;
+    Traced trace_scope(h, "rpf_factor_solve", s, (long long)n);
     size_t pi = h->prof_on ? h->prof_begin(s) : 0;
     factor_solve_ws(n, K, diag, delta, rhs, step, info, h->chol_flags, h->chol_dinv, h->chol_work, s);
     if (h->prof_on) h->prof_end(4, pi, s);
@@ -1618,6 +1717,7 @@ int rpf_qp_step(rpf_grid* h, const double* x, const double* u, const double* pd,
   if (!(rho > 0.0)) return set_err(RPF_EINVAL, "rho must be positive");
   return guard([&]() -> int {
     hipStream_t s = (hipStream_t)stream;
+    Traced trace_scope(h, "rpf_qp_step", s, (long long)max_iter);
     const Presolve& P = h->P;
     const int nu = P.nu, n = P.nu + P.m;
     double* Hm = H ? H : h->Hbuf;
@@ -1662,6 +1762,7 @@ int rpf_track_step(rpf_grid* h, double* u, double* x, double* y, const double* p
   if (pf_iters < 1 || max_halvings < 0 || max_halvings > 30) return set_err(RPF_EINVAL, "bad iteration counts");
   return guard([&]() -> int {
     hipStream_t s = (hipStream_t)stream;
+    Traced trace_scope(h, "rpf_track_step", s);
     const Presolve& P = h->P;
     const int nu = P.nu, nx = P.nx, m = P.m;
     int32_t* done = h->tflags;        // predication flag of the current power flow
@@ -1756,6 +1857,7 @@ int rpf_track_step_qp(rpf_grid* h, double* u, double* sv, double* x, double* y, 
   if (!(dispatch_scale > 0.0)) return set_err(RPF_EINVAL, "dispatch_scale must be positive");
   return guard([&]() -> int {
     hipStream_t s = (hipStream_t)stream;
+    Traced trace_scope(h, "rpf_track_step_qp", s);
     const Presolve& P = h->P;
     const int nu = P.nu, nx = P.nx, m = P.m;
     int32_t* done = h->tflags;        // predication flag of the current power flow
@@ -1878,6 +1980,7 @@ int rpf_static_opf(rpf_grid* h, double* x, double* u, double* sv, double* y, con
     return set_err(RPF_EINVAL, "bad iteration counts");
   return guard([&]() -> int {
     hipStream_t s = (hipStream_t)stream;
+    Traced trace_scope(h, "rpf_static_opf", s, (long long)max_outer);
     const Presolve& P = h->P;
     const int nu = P.nu, nx = P.nx, m = P.m;
     const double kArmijo = 1e-4, kRhoUp = 10.0, kEtaPrimal = 1e-5, kEtaDual = 1e-4;

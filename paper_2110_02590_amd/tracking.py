@@ -197,6 +197,50 @@ class TrackingBatch:
         return [(i.u.clone(), i.x.clone(), i.y.clone(), i.status.clone(),
                  None if i.s is None else i.s.clone()) for i in self.inst]
 
+    def save(self, path, t: int):
+        """The tracking state between steps as a .npz: per instance u, x, y,
+        the status words, the slack s (exact step), rho and the step's shift;
+        the index t of the next step; the step mode; and the content hash of
+        each instance's grid (gridgen.fingerprint), which `load` checks.  The
+        load factors are not stored: they come from the instances' items."""
+        import gridgen
+        arrs = {"t": np.array(int(t)), "mode": np.array(self.mode), "n": np.array(len(self.inst)),
+                "fingerprint": np.array([gridgen.fingerprint(it.grid) for it in self.items])}
+        for k, i in enumerate(self.inst):
+            arrs[f"u{k}"] = i.u.cpu().numpy()
+            arrs[f"x{k}"] = i.x.cpu().numpy()
+            arrs[f"y{k}"] = i.y.cpu().numpy()
+            arrs[f"status{k}"] = i.status.cpu().numpy()
+            arrs[f"param{k}"] = np.array([i.rho, i.delta])
+            if i.s is not None:
+                arrs[f"s{k}"] = i.s.cpu().numpy()
+        np.savez(path, **arrs)
+
+    def load(self, path) -> int:
+        """Restore a state written by `save` into the instances' tensors (in
+        place, so a captured graph stays valid) and return the index of the
+        next step.  The file must come from a batch of the same grids (by
+        content hash), mode, AL penalty and shifts."""
+        import gridgen
+        with np.load(path, allow_pickle=False) as z:
+            if str(z["mode"]) != self.mode or int(z["n"]) != len(self.inst):
+                raise ValueError("saved state is for another mode or number of instances")
+            fp = [gridgen.fingerprint(it.grid) for it in self.items]
+            if [str(v) for v in z["fingerprint"]] != fp:
+                raise ValueError("saved state is for other grids")
+            for k, i in enumerate(self.inst):
+                rho, delta = (float(v) for v in z[f"param{k}"])
+                if rho != i.rho or delta != i.delta:
+                    raise ValueError(f"instance {k}: saved with another penalty or shift")
+                for name, dst in (("u", i.u), ("x", i.x), ("y", i.y), ("status", i.status), ("s", i.s)):
+                    if dst is None:
+                        continue
+                    src = z[f"{name}{k}"]
+                    if src.shape != tuple(dst.shape):
+                        raise ValueError(f"instance {k}: {name} has shape {src.shape}, expected {tuple(dst.shape)}")
+                    dst.copy_(torch.from_numpy(src).to(dst.device))
+            return int(z["t"])
+
     def load_state(self, st):
         for i, (u, x, y, stt, sv) in zip(self.inst, st):
             i.u.copy_(u)

@@ -374,3 +374,42 @@ def test_power_flow_divergence_is_reported():
     torch.cuda.synchronize()
     o = oracle.solve_pf(c.M, c.u, c.g["pd"] * 8.0, c.g["qd"] * 8.0, max_iter=8, raise_on_fail=False)
     assert int(st[1]) == 0 and not o.converged
+
+
+def test_trace_lines(capfd):
+    """RPF_TRACE: each compute call on a handle created with it set writes
+    one JSON line with its device time once it has completed (the last ones
+    when the handle is destroyed); a handle created without it writes
+    nothing."""
+    import json
+    import os
+    from paper_2110_02590_amd import Problem
+    g = gridgen.grid("syn300")
+    ep = gridgen.eval_point(g)
+    old = os.environ.get("RPF_TRACE")
+    os.environ["RPF_TRACE"] = "1"
+    try:
+        pr = Problem(g, max_batch=64)
+    finally:
+        if old is None:
+            os.environ.pop("RPF_TRACE")
+        else:
+            os.environ["RPF_TRACE"] = old
+    x = pr.flat_x()
+    pr.grid.pf_solve(pr.u0, pr.pd, pr.qd, x)
+    s, y, rho, sigma = pr.point(ep)
+    pr.grid.reduced_gradient(x, pr.u0, pr.pd, pr.qd, s, y, rho, sigma)
+    pr.grid.reduced_hessian(batch=64)
+    torch.cuda.synchronize()
+    pr.grid.close()
+    err = capfd.readouterr().err
+    recs = [json.loads(l) for l in err.splitlines() if l.startswith('{"rpf_trace"')]
+    names = [r["rpf_trace"] for r in recs]
+    assert names == ["rpf_pf_solve", "rpf_reduced_gradient", "rpf_reduced_derivatives"], names
+    assert all(r["ms"] > 0.0 for r in recs)
+    assert recs[2]["arg"] == 64
+    quiet = Problem(g, max_batch=64)
+    quiet.grid.pf_solve(quiet.u0, quiet.pd, quiet.qd, quiet.flat_x())
+    torch.cuda.synchronize()
+    quiet.grid.close()
+    assert '"rpf_trace"' not in capfd.readouterr().err

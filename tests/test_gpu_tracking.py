@@ -137,3 +137,31 @@ def test_graph_replay_equals_eager():
     for a, b in zip(eager, graph):
         for va, vb in zip(a, b):
             assert (va is None and vb is None) or torch.equal(va, vb)
+
+
+def test_saved_state_resumes_bitwise(tmp_path):
+    """A state saved between steps and loaded back resumes the same
+    trajectory bit for bit; a file from other grids is refused."""
+    from paper_2110_02590_amd.tracking import TrackingBatch
+    print("[case] tracking save/load seeds 108 101", flush=True)
+    items = _items([108, 101], 4)
+    tb = TrackingBatch(items, max_batch=256, nstreams=2)
+    for t in range(2):
+        tb.step_eager(t)
+    path = str(tmp_path / "track.npz")
+    tb.save(path, 2)
+    tb.step_eager(2)
+    tb.step_eager(3)
+    torch.cuda.synchronize()
+    ref = [tuple(v.cpu().numpy() for v in st[:4]) for st in tb.state()]
+    assert tb.load(path) == 2
+    tb.step_eager(2)
+    tb.step_eager(3)
+    torch.cuda.synchronize()
+    got = [tuple(v.cpu().numpy() for v in st[:4]) for st in tb.state()]
+    for a, b in zip(ref, got):
+        for va, vb in zip(a, b):
+            assert np.array_equal(va, vb)
+    other = TrackingBatch(_items([108, 100], 2), max_batch=256, nstreams=2)
+    with pytest.raises(ValueError):
+        other.load(path)
