@@ -400,48 +400,54 @@ constexpr int RF_AHEAD = 4;
 // wavefronts) per pack, forward levels separated by barriers, one
 // wavefront per row, eliminating in place in LDS.  The metadata of up to
 // 64 elimination steps of a row (pivot column, U-row start, update range)
-// is loaded at once, lane s holding step s, and broadcast by readlane; the
-// update targets of step s + 2 are loaded during step s.  Reciprocal
-// pivots of finished rows go to LDS and to rdg.  upd_tgt must hold 64
-// readable entries past its end.  LDS: values of the pack's CSR rows [seg]
-// | 1 / u_ii [nr].
+// is loaded at once, lane s holding step s, and broadcast by readlane --
+// for a wavefront's next row while it works on the current one; the
+// update targets of step s + RF_AHEAD are loaded during step s.
+// Reciprocal pivots of finished rows go to LDS and to rdg.  upd_tgt must
+// hold 64 readable entries past its end, ent and entu0 one entry past
+// theirs.  LDS: values of the pack's CSR rows [seg] | 1 / u_ii [nr] | the
+// program's row records [nprog] (16-byte aligned).
 //
-// Dense tails (toff non-null; flev/frows/erp/epos the batched forward
-// program): the last level holds the pack's tail rows T, which eliminate
-// only their columns outside T there (erp/epos list each row's L entries to
-// eliminate: all of them for the other rows, the ones outside T for T rows)
-// and keep their pivots open.  Then the T x T block is finished
-// right-looking, one tail pivot k at a time (one barrier per pivot): every L
-// entry (i, k) of a later tail row (tl_pos[tl_ptr[g] .. tl_ptr[g + 1]), g
-// the pivot's tail index) takes l = a_ik / u_kk and updates row i's targets
-// of row k's U entries (tail and top columns), the rows in parallel.
+// Dense tails (toff non-null; flev the batched forward program): the last
+// level holds the pack's tail rows T (in the order of trows), which
+// eliminate only their columns outside T there and keep their pivots open.
+// Then the T x T block is finished right-looking, one tail pivot k at a
+// time (one barrier per pivot): every L entry (i, k) of a later tail row
+// (tlrec[tl_ptr[g] .. tl_ptr[g + 1]), g the pivot's tail index) takes l =
+// a_ik / u_kk and updates row i's targets of row k's U entries (tail and
+// top columns), the rows in parallel.
+// Static records (built on the host): rowrec per program position {row,
+// diagonal position, first and end entry of its elimination list}, staged
+// in LDS; ent per list entry {LU position, pivot column, U-row start of the
+// pivot row, update count} with entu0 its first update; tlrec per tail
+// entry {LU position, U-row start, update count, first update}.
 __global__ void __launch_bounds__(1024) k_rf_pack_lds(const int32_t* __restrict__ pack_ptr,
                                                       const int32_t* __restrict__ flev,
                                                       const int32_t* __restrict__ flev_off,
-                                                      const int32_t* __restrict__ frows,
+                                                      const int4* __restrict__ rowrec,
                                                       const int32_t* __restrict__ ptr,
-                                                      const int32_t* __restrict__ col,
-                                                      const int32_t* __restrict__ diag,
-                                                      const int32_t* __restrict__ ustart,
-                                                      const int64_t* __restrict__ upd_ptr,
+                                                      const int4* __restrict__ ent,
+                                                      const int32_t* __restrict__ entu0,
                                                       const int32_t* __restrict__ upd_tgt,
                                                       double* __restrict__ a, double* __restrict__ rdg,
                                                       double pivtol, int32_t* __restrict__ status,
                                                       const int32_t* __restrict__ skip,
-                                                      const int32_t* __restrict__ erp = nullptr,
-                                                      const int32_t* __restrict__ epos = nullptr,
-                                                      const int32_t* __restrict__ toff = nullptr,
-                                                      const int16_t* __restrict__ trows = nullptr,
-                                                      const int32_t* __restrict__ tl_ptr = nullptr,
-                                                      const int32_t* __restrict__ tl_pos = nullptr) {
+                                                      const int32_t* __restrict__ toff,
+                                                      const int16_t* __restrict__ trows,
+                                                      const int32_t* __restrict__ tl_ptr,
+                                                      const int4* __restrict__ tlrec) {
   if (skip && *skip) return;
   extern __shared__ double sv[];
   const int q = blockIdx.x;
   const int r0 = pack_ptr[q], nr = pack_ptr[q + 1] - r0;
   const int gp0 = ptr[r0], seg = ptr[r0 + nr] - gp0;
+  const int lv0 = flev_off[q], lv1 = flev_off[q + 1];
+  const int base = flev[lv0], nprog = flev[lv1] - base;
   double* srd = sv + seg;
+  int4* srec = reinterpret_cast<int4*>((reinterpret_cast<uintptr_t>(srd + nr) + 15) & ~uintptr_t(15));
   const int t = threadIdx.x;
   stage_1d(sv, a + gp0, seg);
+  for (int k = t; k < nprog; k += blockDim.x) srec[k] = rowrec[base + k];
   __syncthreads();
   // max |a_ij| of each row before elimination, for the pivot test, kept in
   // the row's reciprocal-pivot slot until the row is finished (no step
@@ -460,35 +466,51 @@ __global__ void __launch_bounds__(1024) k_rf_pack_lds(const int32_t* __restrict_
   __syncthreads();
   const int wave = t >> 6, lane = t & 63, nwave = blockDim.x >> 6;
   const int tq = toff ? toff[q] : 0, nT = toff ? toff[q + 1] - tq : 0;
-  const int lv1 = flev_off[q + 1];
-  for (int lv = flev_off[q]; lv < lv1; ++lv) {
+  // a row's step metadata (lane s: step s of its first 64) is loaded one
+  // row ahead: during row rr the wavefront's next row's records are in
+  // flight
+  int4 nE = make_int4(0, 0, 0, 0);
+  int nU = 0;
+  auto fetch_row = [&](int rr) {
+    const int4 R = srec[rr - base];
+    const int e0 = R.z, nw = min(64, R.w - R.z);
+    const int e = e0 + (lane < nw ? lane : 0);
+    nE = ent[e];
+    nU = entu0[e];
+  };
+  for (int lv = lv0; lv < lv1; ++lv) {
     const bool tail = nT > 0 && lv == lv1 - 1;   // the tail rows: pivots stay open
-    for (int rr = flev[lv] + wave; rr < flev[lv + 1]; rr += nwave) {
-      // row bounds are the same in every lane: keep them scalar
-      const int i = __builtin_amdgcn_readfirstlane(frows[rr]);
-      const int pdg = __builtin_amdgcn_readfirstlane(diag[i]);
-      // the row's L entries to eliminate: [e0, e1) of epos, or the
-      // contiguous positions ptr[i] .. diag[i]
-      const int e0 = __builtin_amdgcn_readfirstlane(erp ? erp[i] : ptr[i]);
-      const int e1 = __builtin_amdgcn_readfirstlane(erp ? erp[i + 1] : pdg);
+    const int rend = flev[lv + 1];
+    int rr = flev[lv] + wave;
+    if (rr < rend) fetch_row(rr);
+    for (; rr < rend; rr += nwave) {
+      // the row record is the same in every lane: keep it scalar
+      const int4 R = srec[rr - base];
+      const int i = __builtin_amdgcn_readfirstlane(R.x);
+      const int pdg = __builtin_amdgcn_readfirstlane(R.y);
+      const int e0 = __builtin_amdgcn_readfirstlane(R.z);
+      const int e1 = __builtin_amdgcn_readfirstlane(R.w);
+      int4 cE = nE;
+      int cU = nU;
+      if (rr + nwave < rend) fetch_row(rr + nwave);
       for (int w0 = e0; w0 < e1; w0 += 64) {
         const int nw = min(64, e1 - w0);
-        int m_k = 0, m_us = 0, m_nu = 0, m_p = 0;
-        int64_t m_u0 = 0;
-        if (lane < nw) {
-          const int p = epos ? epos[w0 + lane] : w0 + lane;
-          m_p = p;
-          m_k = col[p];
-          m_us = ustart[p];
-          m_u0 = upd_ptr[p];
-          m_nu = (int)(upd_ptr[p + 1] - m_u0);
+        if (w0 != e0) {
+          const int e = w0 + (lane < nw ? lane : 0);
+          cE = ent[e];
+          cU = entu0[e];
         }
+        const int m_p = lane < nw ? cE.x : 0;
+        const int m_k = lane < nw ? cE.y : 0;
+        const int m_us = lane < nw ? cE.z : 0;
+        const int m_nu = lane < nw ? cE.w : 0;
+        const int m_u0 = lane < nw ? cU : 0;
         // targets of step s live in tg[s mod RF_AHEAD]; the load for step
         // s + RF_AHEAD is issued during step s into the same register:
         // unconditional loads (upd_tgt is padded past its end), so the
         // compiler can count them and wait only for the oldest one
         auto fetch_tg = [&](int st) -> int {
-          const int64_t u = readlane64(m_u0, st);
+          const int u = __builtin_amdgcn_readlane(m_u0, st);
           return upd_tgt[u + (lane < __builtin_amdgcn_readlane(m_nu, st) ? lane : 0)];
         };
         // the U entry and the target's current value are read with clamped
@@ -506,7 +528,7 @@ __global__ void __launch_bounds__(1024) k_rf_pack_lds(const int32_t* __restrict_
           const double l = sv[pl] * srd[k - r0];
           if (on) sv[tgabs - gp0] = cur - l * av;
           if (nu > 64) {
-            const int64_t u0 = readlane64(m_u0, st);
+            const int u0 = __builtin_amdgcn_readlane(m_u0, st);
             for (int tt = lane + 64; tt < nu; tt += 64) sv[upd_tgt[u0 + tt] - gp0] -= l * sv[us + tt];
           }
           if (lane == 0) sv[pl] = l;
@@ -537,26 +559,53 @@ __global__ void __launch_bounds__(1024) k_rf_pack_lds(const int32_t* __restrict_
     }
     lds_barrier();
   }
-  // the tail block, right-looking over its pivots
+  // the tail block, right-looking over its pivots: entry c of pivot g's
+  // list (wavefront c mod 16) has its record {LU position, U-row start,
+  // update count, first update} and its update targets loaded during the
+  // previous pivot
+  int4 tR = make_int4(0, 0, 0, 0);
+  int tT = 0;
+  auto fetch_tail = [&](int b) {
+    const int g = tq + b;
+    const int c = tl_ptr[g] + wave;
+    if (c < tl_ptr[g + 1]) {
+      tR = tlrec[c];
+      tT = upd_tgt[tR.w + (lane < tR.z ? lane : 0)];
+    }
+  };
+  const int tbase = flev[lv1 - 1] - base;
+  if (nT > 0) fetch_tail(0);
   for (int b = 0; b < nT; ++b) {
-    const int k = r0 + trows[tq + b];
-    const int dk = __builtin_amdgcn_readfirstlane(diag[k]) - gp0;
-    const double piv = sv[dk];   // final: every earlier pivot has updated row k
+    // the tail rows are the program's last level, in the order of trows
+    const int4 KR = srec[tbase + b];
+    const int k = __builtin_amdgcn_readfirstlane(KR.x);
+    const int pk = __builtin_amdgcn_readfirstlane(KR.y);
+    const int g = tq + b;
+    const int c0 = tl_ptr[g], c1 = tl_ptr[g + 1];
+    const int4 cR = tR;
+    const int cT = tT;
+    if (b + 1 < nT) fetch_tail(b + 1);
+    const double piv = sv[pk - gp0];   // final: every earlier pivot has updated row k
     if (t == 0) {
       const double rp = 1.0 / piv;
       rdg[k] = rp;
       if (!(fabs(piv) > pivtol * srd[k - r0])) atomicCAS(status, 0, k + 1);
     }
     const double rp = 1.0 / piv;
-    const int g = tq + b;
-    const int c0 = tl_ptr[g], c1 = tl_ptr[g + 1];
     for (int c = c0 + wave; c < c1; c += nwave) {
-      const int p = __builtin_amdgcn_readfirstlane(tl_pos[c]);
-      const int us = __builtin_amdgcn_readfirstlane(ustart[p]) - gp0;
-      const int64_t u0 = upd_ptr[p];
-      const int nu = (int)(upd_ptr[p + 1] - u0);
+      int4 R = cR;
+      int tg = cT;
+      if (c != c0 + wave) {
+        R = tlrec[c];
+        tg = upd_tgt[R.w + (lane < R.z ? lane : 0)];
+      }
+      const int p = __builtin_amdgcn_readfirstlane(R.x);
+      const int us = __builtin_amdgcn_readfirstlane(R.y) - gp0;
+      const int nu = __builtin_amdgcn_readfirstlane(R.z);
+      const int u0 = __builtin_amdgcn_readfirstlane(R.w);
       const double l = sv[p - gp0] * rp;
-      for (int tt = lane; tt < nu; tt += 64) sv[upd_tgt[u0 + tt] - gp0] -= l * sv[us + tt];
+      if (lane < nu) sv[tg - gp0] -= l * sv[us + lane];
+      for (int tt = lane + 64; tt < nu; tt += 64) sv[upd_tgt[u0 + tt] - gp0] -= l * sv[us + tt];
       if (lane == 0) sv[p - gp0] = l;
     }
     lds_barrier();

@@ -105,6 +105,8 @@ struct rpf_grid {
       *ptb_pos;
   int16_t *ptf_col, *ptb_col, *ptl_rows;
   int32_t *ptl_off, *ptl_eoff, *ptl_pos, *ptl_dense, *rft_ptr, *rft_pos;
+  int4 *rf_rowrec = nullptr, *rf_ent = nullptr, *rf_tlrec = nullptr;   // k_rf_pack_lds records
+  int32_t* rf_entu0 = nullptr;
   double *tailA = nullptr, *tailM = nullptr;
   size_t lds_limit = 65536, lds_pack[5] = {0, 0, 0, 0, 0};
   double *c2, *c1, *c0;
@@ -440,6 +442,56 @@ void setup(rpf_grid* h) {
   h->rft_ptr = h->up(P.rft_ptr);
   h->rft_pos = h->up(P.rft_pos);
   {
+    // records of the LDS-resident pack refactorization (k_rf_pack_lds):
+    // per program position, per elimination-list entry, per tail entry
+    auto i4 = [](std::vector<int32_t>& v) {
+      std::vector<int4> r(v.size() / 4);
+      std::memcpy(r.data(), v.data(), v.size() * sizeof(int32_t));
+      return r;
+    };
+    auto u32 = [&](int64_t u) {
+      if (u > INT32_MAX) throw std::runtime_error("refactorization updates exceed 2^31");
+      return (int32_t)u;
+    };
+    std::vector<int32_t> rr, en, eu, tl;
+    for (size_t r = 0; r < P.ptf_rows.size(); ++r) {
+      const int i = P.ptf_rows[r];
+      rr.insert(rr.end(), {i, P.lu_diag[i], P.ptf_rp[i], P.ptf_rp[i + 1]});
+    }
+    for (size_t e = 0; e < P.ptf_pos.size(); ++e) {
+      const int q = P.ptf_pos[e];
+      en.insert(en.end(), {q, P.lu_col[q], P.rf_ustart[q], u32(P.upd_ptr[q + 1] - P.upd_ptr[q])});
+      eu.push_back(u32(P.upd_ptr[q]));
+    }
+    for (size_t c = 0; c < P.rft_pos.size(); ++c) {
+      const int q = P.rft_pos[c];
+      tl.insert(tl.end(), {q, P.rf_ustart[q], u32(P.upd_ptr[q + 1] - P.upd_ptr[q]), u32(P.upd_ptr[q])});
+    }
+    // the kernel finds tail pivot b as the b-th row of its pack's last
+    // forward level
+    const int npk = (int)P.pack_ptr.size() - 1;
+    for (int q = 0; q < npk; ++q) {
+      const int nT = P.ptl_off[q + 1] - P.ptl_off[q];
+      if (nT == 0) continue;
+      const int lv = P.ptf_lev_off[q + 1] - 1;
+      if (P.ptf_lev[lv + 1] - P.ptf_lev[lv] != nT)
+        throw std::runtime_error("internal: the tail rows are not the last forward level");
+      for (int b = 0; b < nT; ++b)
+        if (P.ptf_rows[P.ptf_lev[lv] + b] != P.pack_ptr[q] + P.ptl_rows[P.ptl_off[q] + b])
+          throw std::runtime_error("internal: tail rows out of order in the last forward level");
+    }
+    // one record past the end of the entry lists: a row with an empty list
+    // still reads the record at its (final) start
+    en.insert(en.end(), {0, 0, 0, 0});
+    eu.push_back(0);
+    if (rr.empty()) rr.assign(4, 0);
+    if (tl.empty()) tl.assign(4, 0);
+    h->rf_rowrec = h->up(i4(rr));
+    h->rf_ent = h->up(i4(en));
+    h->rf_entu0 = h->up(eu);
+    h->rf_tlrec = h->up(i4(tl));
+  }
+  {
     const size_t npk = P.pack_ptr.size() - 1, blk = (size_t)TAIL_MAX * TAIL_MAX;
     h->tailA = h->alloc<double>(std::max<size_t>(1, npk * 2 * blk));
     h->tailM = h->alloc<double>(std::max<size_t>(1, npk * 4 * blk));
@@ -522,11 +574,14 @@ void setup(rpf_grid* h) {
       }
     }
     // LDS-resident refactorization: values of the pack's CSR rows + pivots
+    // + the program's row records
     {
       size_t mx = 0;
       for (int q = 0; q < h->npacks; ++q) {
         const int r0 = P.pack_ptr[q], nr = P.pack_ptr[q + 1] - r0;
-        mx = std::max(mx, (size_t)(P.lu_ptr[r0 + nr] - P.lu_ptr[r0] + nr) * sizeof(double));
+        const int nprog = P.ptf_lev[P.ptf_lev_off[q + 1]] - P.ptf_lev[P.ptf_lev_off[q]];
+        mx = std::max(mx, (size_t)(P.lu_ptr[r0 + nr] - P.lu_ptr[r0] + nr) * sizeof(double) + 16 +
+                              (size_t)nprog * sizeof(int4));
       }
       h->lds_rf = mx <= h->lds_limit ? mx : 0;
     }
@@ -718,11 +773,10 @@ void refactor(rpf_grid* h, hipStream_t s, const int32_t* skip = nullptr) {
   if (h->npacks > 0 && h->lds_rf > 0) {
     // the batched forward program's levels: rows outside the dense tails by
     // level, then the tails (finished right-looking)
-    k_rf_pack_lds<<<h->npacks, 1024, h->lds_rf, s>>>(h->pack_ptr, h->ptf_lev, h->ptf_lev_off, h->ptf_rows,
-                                                     h->lu_ptr, h->lu_col, h->lu_diag, h->rf_ustart, h->upd_ptr,
-                                                     h->upd_tgt, h->luv, h->rdiag, 1e-14, h->piv_status, skip,
-                                                     h->ptf_rp, h->ptf_pos, h->ptl_off, h->ptl_rows, h->rft_ptr,
-                                                     h->rft_pos);
+    k_rf_pack_lds<<<h->npacks, 1024, h->lds_rf, s>>>(h->pack_ptr, h->ptf_lev, h->ptf_lev_off, h->rf_rowrec,
+                                                     h->lu_ptr, h->rf_ent, h->rf_entu0, h->upd_tgt, h->luv,
+                                                     h->rdiag, 1e-14, h->piv_status, skip, h->ptl_off,
+                                                     h->ptl_rows, h->rft_ptr, h->rf_tlrec);
     LAUNCHCHK();
   } else if (h->npacks > 0) {
     k_rf_pack<<<h->npacks, 64 * wv, shm, s>>>(h->pk_flev, h->pk_flev_off, h->pk_frows, h->lu_ptr, h->lu_col,
