@@ -117,8 +117,12 @@ def main():
     torch.cuda.set_device(0)
     g = gridgen.grid(a.workload)
     ep = gridgen.eval_point(g)
-    B = a.batch if a.batch > 0 else tune.best_batch(g, ep)
-    pr = Problem(g, max_batch=B)
+    if a.batch > 0:
+        B, tile = a.batch, None
+    else:
+        cfg = tune.best_config(g, ep)
+        B, tile = int(cfg["batch"]), (int(cfg["pack_tw"]), bool(cfg["pack_sv"]))
+    pr = Problem(g, max_batch=B, pack_tile=tile)
     grid = pr.grid
     nu, nx = pr.nu, pr.nx
     s, y, rho, sigma = pr.point(ep)
@@ -209,7 +213,9 @@ def main():
         "config": {"workload": f"{a.workload}: {pr.nb} buses, {g['nl']} branches, n_x={nx}, n_u={nu}, "
                                f"m={pr.m}; step = warm power flow at perturbed loads + AL value + "
                                f"reduced gradient + {nu} HVPs + Cholesky step",
-                   "hvp_batch": B, "parallelism": "single GPU",
+                   "hvp_batch": B, "pack_tile": ("library default" if tile is None else
+                                                   f"{tile[0]} columns{', values staged' if tile[1] else ''}"),
+                   "parallelism": "single GPU",
                    "form": "one HIP graph per step, captured once and replayed" if form == "graph"
                    else "eager launches"},
         "eager": {"hvps_per_s": round(value_eager, 1), "ms_per_step": round(ms_eager, 3),

@@ -405,8 +405,9 @@ constexpr int RF_AHEAD = 4;
 // update targets of step s + RF_AHEAD are loaded during step s.
 // Reciprocal pivots of finished rows go to LDS and to rdg.  upd_tgt must
 // hold 64 readable entries past its end, ent and entu0 one entry past
-// theirs.  LDS: values of the pack's CSR rows [seg] | 1 / u_ii [nr] | the
-// program's row records [nprog] (16-byte aligned).
+// theirs.  LDS: values of the pack's CSR rows [seg] | 1 / u_ii [nr] | with
+// RECS_LDS, the program's row records [nprog] (16-byte aligned; otherwise
+// they are read from global memory).
 //
 // Dense tails (toff non-null; flev the batched forward program): the last
 // level holds the pack's tail rows T (in the order of trows), which
@@ -421,6 +422,7 @@ constexpr int RF_AHEAD = 4;
 // in LDS; ent per list entry {LU position, pivot column, U-row start of the
 // pivot row, update count} with entu0 its first update; tlrec per tail
 // entry {LU position, U-row start, update count, first update}.
+template <bool RECS_LDS>
 __global__ void __launch_bounds__(1024) k_rf_pack_lds(const int32_t* __restrict__ pack_ptr,
                                                       const int32_t* __restrict__ flev,
                                                       const int32_t* __restrict__ flev_off,
@@ -444,10 +446,12 @@ __global__ void __launch_bounds__(1024) k_rf_pack_lds(const int32_t* __restrict_
   const int lv0 = flev_off[q], lv1 = flev_off[q + 1];
   const int base = flev[lv0], nprog = flev[lv1] - base;
   double* srd = sv + seg;
-  int4* srec = reinterpret_cast<int4*>((reinterpret_cast<uintptr_t>(srd + nr) + 15) & ~uintptr_t(15));
+  int4* srec_l = reinterpret_cast<int4*>((reinterpret_cast<uintptr_t>(srd + nr) + 15) & ~uintptr_t(15));
+  const int4* srec = RECS_LDS ? srec_l : rowrec + base;
   const int t = threadIdx.x;
   stage_1d(sv, a + gp0, seg);
-  for (int k = t; k < nprog; k += blockDim.x) srec[k] = rowrec[base + k];
+  if (RECS_LDS)
+    for (int k = t; k < nprog; k += blockDim.x) srec_l[k] = rowrec[base + k];
   __syncthreads();
   // max |a_ij| of each row before elimination, for the pivot test, kept in
   // the row's reciprocal-pivot slot until the row is finished (no step

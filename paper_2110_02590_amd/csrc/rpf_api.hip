@@ -93,6 +93,7 @@ struct rpf_grid {
   int tw_pack = 8, tw_top = 8;
   size_t lds_packg = 0;   // LDS of the global-memory batched pack solves
   size_t lds_rf = 0;      // LDS of the LDS-resident pack refactorization (0: not used)
+  bool rf_recs_lds = true;   // its row records staged in LDS as well
   int tw_packt = 0;       // column tile of the LDS-tile batched pack solves (0: not used)
   bool sv_packt = false;  // factor values staged in LDS too
   size_t lds_packt = 0;
@@ -576,14 +577,17 @@ void setup(rpf_grid* h) {
     // LDS-resident refactorization: values of the pack's CSR rows + pivots
     // + the program's row records
     {
-      size_t mx = 0;
+      size_t mx = 0, mxr = 0;
       for (int q = 0; q < h->npacks; ++q) {
         const int r0 = P.pack_ptr[q], nr = P.pack_ptr[q + 1] - r0;
         const int nprog = P.ptf_lev[P.ptf_lev_off[q + 1]] - P.ptf_lev[P.ptf_lev_off[q]];
-        mx = std::max(mx, (size_t)(P.lu_ptr[r0 + nr] - P.lu_ptr[r0] + nr) * sizeof(double) + 16 +
-                              (size_t)nprog * sizeof(int4));
+        const size_t v = (size_t)(P.lu_ptr[r0 + nr] - P.lu_ptr[r0] + nr) * sizeof(double);
+        mx = std::max(mx, v);
+        mxr = std::max(mxr, v + 16 + (size_t)nprog * sizeof(int4));
       }
-      h->lds_rf = mx <= h->lds_limit ? mx : 0;
+      // the row records in LDS too when they fit, else read from memory
+      h->rf_recs_lds = mxr <= h->lds_limit;
+      h->lds_rf = h->rf_recs_lds ? mxr : (mx <= h->lds_limit ? mx : 0);
     }
     h->tw_pack = 0;
     for (int k = 0; k < 5; ++k)
@@ -614,7 +618,7 @@ void setup(rpf_grid* h) {
   allow((const void*)k_pack_solve_s<TW, false, true>);      \
   allow((const void*)k_pack_solve_s<TW, false, false>);
     if (h->lds_packg > h->lds_limit) throw std::runtime_error("a pack of subtrees does not fit in LDS");
-    if (h->lds_rf > 0) allow((const void*)k_rf_pack_lds);
+    if (h->lds_rf > 0) allow(h->rf_recs_lds ? (const void*)k_rf_pack_lds<true> : (const void*)k_rf_pack_lds<false>);
 #define RPF_ALLOW_PACKT(TW, SV)                                 \
   allow((const void*)k_pack_solve_t<TW, true, true, SV>);       \
   allow((const void*)k_pack_solve_t<TW, true, false, SV>);      \
@@ -773,10 +777,16 @@ void refactor(rpf_grid* h, hipStream_t s, const int32_t* skip = nullptr) {
   if (h->npacks > 0 && h->lds_rf > 0) {
     // the batched forward program's levels: rows outside the dense tails by
     // level, then the tails (finished right-looking)
-    k_rf_pack_lds<<<h->npacks, 1024, h->lds_rf, s>>>(h->pack_ptr, h->ptf_lev, h->ptf_lev_off, h->rf_rowrec,
-                                                     h->lu_ptr, h->rf_ent, h->rf_entu0, h->upd_tgt, h->luv,
-                                                     h->rdiag, 1e-14, h->piv_status, skip, h->ptl_off,
-                                                     h->ptl_rows, h->rft_ptr, h->rf_tlrec);
+    if (h->rf_recs_lds)
+      k_rf_pack_lds<true><<<h->npacks, 1024, h->lds_rf, s>>>(h->pack_ptr, h->ptf_lev, h->ptf_lev_off, h->rf_rowrec,
+                                                       h->lu_ptr, h->rf_ent, h->rf_entu0, h->upd_tgt, h->luv,
+                                                       h->rdiag, 1e-14, h->piv_status, skip, h->ptl_off,
+                                                       h->ptl_rows, h->rft_ptr, h->rf_tlrec);
+    else
+      k_rf_pack_lds<false><<<h->npacks, 1024, h->lds_rf, s>>>(h->pack_ptr, h->ptf_lev, h->ptf_lev_off, h->rf_rowrec,
+                                                       h->lu_ptr, h->rf_ent, h->rf_entu0, h->upd_tgt, h->luv,
+                                                       h->rdiag, 1e-14, h->piv_status, skip, h->ptl_off,
+                                                       h->ptl_rows, h->rft_ptr, h->rf_tlrec);
     LAUNCHCHK();
   } else if (h->npacks > 0) {
     k_rf_pack<<<h->npacks, 64 * wv, shm, s>>>(h->pk_flev, h->pk_flev_off, h->pk_frows, h->lu_ptr, h->lu_col,

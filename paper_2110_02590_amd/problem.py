@@ -12,11 +12,32 @@ PQ, PV, REF = 0, 1, 2
 
 
 class Problem:
-    def __init__(self, g: dict, max_batch: int = 256):
+    def __init__(self, g: dict, max_batch: int = 256, pack_tile=None):
+        """pack_tile: (columns, staged) of the batched pack solves' tiles --
+        (16, False), (8, True) or (8, False), as `tune.best_config` picks
+        them; None keeps the library's choice (the first that fits in LDS)."""
+        import os
+
         import torch
         self.torch = torch
         self.g = g
-        self.grid = Grid(g, max_batch=max_batch)
+        env = {}
+        if pack_tile is not None:
+            tw, sv = int(pack_tile[0]), bool(pack_tile[1])
+            if (tw, sv) not in ((16, False), (8, True), (8, False)):
+                raise ValueError("pack_tile must be (16, False), (8, True) or (8, False)")
+            env = {"RPF_PACK_TW": str(tw), "RPF_PACK_SV": "1" if sv else "0"}
+        old = {k: os.environ.get(k) for k in env}
+        os.environ.update(env)
+        try:
+            # the handle reads the tile choice when it is created
+            self.grid = Grid(g, max_batch=max_batch)
+        finally:
+            for k, v in old.items():
+                if v is None:
+                    os.environ.pop(k, None)
+                else:
+                    os.environ[k] = v
         bt = np.asarray(g["bus_type"])
         self.ref = int(np.flatnonzero(bt == REF)[0])
         self.pv = np.flatnonzero(bt == PV)

@@ -413,3 +413,60 @@ def test_trace_lines(capfd):
     torch.cuda.synchronize()
     quiet.grid.close()
     assert '"rpf_trace"' not in capfd.readouterr().err
+
+
+@pytest.mark.parametrize("env", [
+    {"RPF_PACK_TW": "8", "RPF_PACK_SV": "1"},
+    {"RPF_PACK_TW": "8", "RPF_PACK_SV": "0"},
+    {"RPF_TAIL_MAX": "0"},
+    {"RPF_TAIL_MAX": "32"},
+    {"RPF_SUBTREE_MAX": "256"},
+    {"RPF_SUBTREE_MAX": "1536"},
+    {"RPF_SUBTREE_MAX": "2048"},
+], ids=lambda e: ",".join(f"{k}={v}" for k, v in e.items()))
+def test_solve_variants_match_default(env):
+    """The other batched-solve variants -- 8-column tiles with and without
+    staged factor values, packs without dense tails or with small ones,
+    smaller packs, and larger packs (past the LDS-resident refactorization:
+    its global-memory version) -- give the default handle's power flow,
+    gradient and full reduced Hessian (syn2000, 1e-10 relative; the
+    orderings differ, so not bit for bit).  A pack too large for any of the
+    solves is refused at handle creation with an error."""
+    import os
+    from paper_2110_02590_amd import Problem
+    print(f"[case] solve variant {env}", flush=True)
+    g = gridgen.grid("syn2000")
+    ep = gridgen.eval_point(g)
+
+    from paper_2110_02590_amd import RpfError
+
+    def run(extra):
+        old = {k: os.environ.get(k) for k in extra}
+        os.environ.update(extra)
+        try:
+            pr = Problem(g, max_batch=256)
+        except RpfError as e:
+            assert "does not fit in LDS" in str(e)
+            pytest.skip(f"refused at creation: {e}")
+        finally:
+            for k, v in old.items():
+                if v is None:
+                    os.environ.pop(k, None)
+                else:
+                    os.environ[k] = v
+        x = pr.flat_x()
+        st, _ = pr.grid.pf_solve(pr.u0, pr.pd, pr.qd, x)
+        s, y, rho, sigma = pr.point(ep)
+        grad, _ = pr.grid.reduced_gradient(x, pr.u0, pr.pd, pr.qd, s, y, rho, sigma)
+        H = pr.grid.reduced_hessian(batch=256)
+        torch.cuda.synchronize()
+        out = (st.cpu().numpy(), x.cpu().numpy(), grad.cpu().numpy(), H.cpu().numpy())
+        pr.grid.close()
+        return out
+
+    st0, x0, g0, H0 = run({})
+    st1, x1, g1, H1 = run(env)
+    assert st1[1] == 1 and st1[0] == st0[0], (st0, st1)
+    assert _rel(x1, x0) < 1e-12
+    assert _rel(g1, g0) < 1e-10
+    assert _rel(H1, H0) < 1e-10
