@@ -72,6 +72,13 @@
  *    {"rpf_trace": "<call>", "ms": <device time>, "arg": <size argument>}
  *    to stderr -- polled at later calls on the handle, waited for when it is
  *    destroyed.  Calls on a stream that is capturing a graph are not traced.
+ *  - Launch-shape switches, read when a handle is created: RPF_HVP_STREAMS
+ *    (see rpf_reduced_hessian), RPF_PACK_TW = 8 | 16 and RPF_PACK_SV = 0 | 1
+ *    (column tile of the batched pack solves, factor values staged in LDS),
+ *    RPF_PACK_THREADS = 512 (512-thread workgroups for 16-column tiles: two
+ *    per CU when packs are at most 512 rows), RPF_SUBTREE_MAX and
+ *    RPF_TAIL_MAX (presolve: largest pack, largest dense tail).  Results
+ *    agree to rounding across them.
  */
 #ifndef RPF_H
 #define RPF_H

@@ -96,6 +96,7 @@ struct rpf_grid {
   bool rf_recs_lds = true;   // its row records staged in LDS as well
   int tw_packt = 0;       // column tile of the LDS-tile batched pack solves (0: not used)
   bool sv_packt = false;  // factor values staged in LDS too
+  int packt_threads = 1024;   // threads per workgroup of the LDS-tile pack solves
   size_t lds_packt = 0;
   // factor values in the batched programs' order: forward / backward, J_x / J_x^T
   double *pkfv = nullptr, *pkbv = nullptr, *pkfvT = nullptr, *pkbvT = nullptr;
@@ -675,6 +676,10 @@ void setup(rpf_grid* h) {
   // RPF_HVP_STREAMS = 2 .. 8 runs them on that many handle-owned streams
   h->nhs = 1;
   if (const char* e = std::getenv("RPF_HVP_STREAMS")) h->nhs = std::max(1, std::min(rpf_grid::HS, std::atoi(e)));
+  // 512 threads (16-column tiles only): two workgroups per CU when a
+  // pack's tile fits twice in LDS
+  if (const char* e = std::getenv("RPF_PACK_THREADS"))
+    if (std::atoi(e) == 512 && h->tw_packt == 16) h->packt_threads = 512;
   if (h->nhs > 1) {
     HIPCHK(hipEventCreateWithFlags(&h->ev_fork, hipEventDisableTiming));
     for (int k = 0; k < h->nhs; ++k) {
@@ -869,7 +874,7 @@ void pack_solve_t(rpf_grid* h, bool fwd, bool unit, bool transposed, const doubl
   const double* tinv = h->tailM + which * n4;
   auto launch = [&](auto kern, const int32_t* lev, const int32_t* lev_off, const int32_t* rows, const int32_t* rp,
                     const int16_t* ecol) {
-    kern<<<grd, 1024, h->lds_packt, s>>>(h->pack_ptr, lev, lev_off, rows, rp, ecol, pv, h->rdiag, h->up_split,
+    kern<<<grd, h->packt_threads, h->lds_packt, s>>>(h->pack_ptr, lev, lev_off, rows, rp, ecol, pv, h->rdiag, h->up_split,
                                          h->lu_ptr, h->lu_col, val, X, ld, ncols, scale, h->npacks, ntiles,
                                          h->ptl_off, h->ptl_rows, tinv, skip, fz);
   };
