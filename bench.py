@@ -32,7 +32,7 @@ PF_ITERS = 6
 FP64_PEAK_TFLOPS = 78.6
 
 # HBM traffic per launch from two rocprofv3 --pmc passes over this bench at
-# batch 512 (FETCH_SIZE scaled by 2.0 and WRITE_SIZE by 1.0: what the two
+# batch 1024 (FETCH_SIZE scaled by 2.0 and WRITE_SIZE by 1.0: what the two
 # counters read for a 1 GiB streaming kernel; KiB per dispatch averaged over
 # the four forward/backward x J_x/J_x^T variants).  Valid only for the kernel
 # source it was measured on (sha1 of the kernel's text and of the device
@@ -42,7 +42,7 @@ FP64_PEAK_TFLOPS = 78.6
 TRAFFIC = {
     "pack_solve": {"kernel": "k_pack_solve_t", "helpers": ["tail_apply", "tail_apply_mfma", "tail_apply_any",
                                                            "stage_1d", "sum_xor16", "sum_xor32", "lds_barrier"],
-                   "batch": 512, "bytes_per_launch": 120593011,
+                   "batch": 1024, "bytes_per_launch": 241146136,
                    "source_sha1": "9dc375d36de5548b62e2830f72acd14df4219992"},
 }
 
