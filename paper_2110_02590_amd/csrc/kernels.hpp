@@ -2555,10 +2555,11 @@ __global__ void k_symmetrize(int n, double* __restrict__ K, const double* __rest
 // ------------------------------------------- blocked dense factorizations
 // Right-looking blocked LU without pivoting (CHOL = false) or Cholesky
 // (CHOL = true, lower triangle) of a row-major n x n matrix, per block of
-// CB columns: diagonal block by one wavefront, panels one wavefront per row
-// (and per column for LU), trailing update in 64 x 64 tiles on the FP64
-// matrix cores.  A failing
-// pivot records base + (column + 1) in info[0]; later kernels return early.
+// CB columns: diagonal block by one workgroup (diag_factor for LU,
+// chol_diag_rows for Cholesky), panels one wavefront per row (and per
+// column for LU), trailing update in 64 x 64 tiles on the FP64 matrix
+// cores.  A failing pivot records base + (column + 1) in info[0]; later
+// kernels return early.
 
 // Diagonal block factorization with the 256 threads of the calling
 // workgroup; work is LDS provided by the caller (DIAG_WORK doubles).
@@ -2724,13 +2725,186 @@ __device__ __forceinline__ bool diag_factor(int n, int b0, double* __restrict__ 
   return true;
 }
 
+// Cholesky of the CB x CB diagonal block by the four wavefronts of the
+// workgroup (256 threads).  The block arrives in LDS (S: lower triangle,
+// identity past nb) and leaves as L in A's lower triangle at (b0, b0).
+//
+// Wave w holds the rows of the 4-row blocks b = w, w + 4, w + 8, w + 12 of
+// the symmetric block as FP64 matrix-core accumulators (v_mfma_f64_16x16x4f64
+// layout: register r of lane c + 16 g holds row 16 r + 4 w + g, column
+// 16 ch + c of chunk ch).  Step J factorizes block J + 1 with the four rows
+// of L^T of block J (V_J) in LDS:
+// * every other wave subtracts the rank-4 product of V_J from its rows with
+//   four matrix-core products (its coefficients as the A operand, V_J as the
+//   B operand; rows of finished blocks take zero coefficients);
+// * the owner of block J + 1 (wave (J + 1) & 3) holds that block's rows one
+//   column per lane, taken from its accumulators one step earlier; it
+//   applies V_J to them on the vector ALU (coefficients by LDS broadcast),
+//   reads the 4 x 4 diagonal block by readlane, factorizes it as uniform
+//   values and solves the rows into V_{J+1}; its own matrix-core products
+//   with V_J wait for the next step, off the chain of pivots;
+// * the owner of block J + 2 takes that block's rows out of its
+//   accumulators once V_J is applied, for the next step.
+// One barrier per four columns.  A failed pivot does not branch: the first
+// failing index is kept and reported after the loop, and the factor is then
+// not written.  buf: CHOL_BUF doubles; S collects the rows of L^T once the
+// block is read.
+constexpr int CHOL_BUF = 3 * 4 * CB + 4 * 4 * CB;
+
+__device__ __forceinline__ bool chol_diag_rows(int n, int b0, double* __restrict__ A, int32_t* __restrict__ info,
+                                               int base, double (*S)[CB + 1], double* __restrict__ buf,
+                                               int* __restrict__ sbad) {
+  const int nb = min(CB, n - b0);
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int li = lane & 15, lg = lane >> 4;
+  double* ext = buf + 3 * 4 * CB + w * 4 * CB;   // this wave's row extraction
+  dbl4 acc[4];
+#pragma unroll
+  for (int ch = 0; ch < 4; ++ch)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = 16 * r + 4 * w + lg, k = 16 * ch + li;
+      acc[ch][r] = i >= k ? S[i][k] : S[k][i];
+    }
+  if (threadIdx.x == 0) *sbad = CB;
+  int bad = CB;
+  lds_barrier();
+  // block J's rows (this wave's, q = J >> 2) one column per lane, through
+  // LDS (the same wave writes and reads)
+  auto take_rows = [&](const int J, double (&r)[4]) {
+#pragma unroll
+    for (int ch = 0; ch < 4; ++ch) ext[lg * CB + 16 * ch + li] = acc[ch][J >> 2];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) r[t] = ext[t * CB + lane];
+  };
+  // block J's rows, every earlier block applied -> rows of L^T (zero left of
+  // the pivot), to buf (for the other waves) and S (for the output)
+  auto factor_rows = [&](const int J, const double (&r)[4]) {
+    const int j0 = 4 * J;
+    double a[4][4], Ld[4][4], rp[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+      for (int m2 = 0; m2 <= m; ++m2) a[m][m2] = readlane_f64(r[m], j0 + m2);
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      double d = a[m][m];
+#pragma unroll
+      for (int p = 0; p < m; ++p) d = fma(-Ld[m][p], Ld[m][p], d);
+      bad = (bad == CB && !(d > 0.0 && isfinite(d))) ? j0 + m : bad;
+      // 1 / sqrt(d): hardware estimate and one Newton step
+      const double y0 = __builtin_amdgcn_rsq(d);
+      const double h = 0.5 * y0, g = d * y0;
+      rp[m] = fma(y0, fma(-h, g, 0.5), y0);
+      Ld[m][m] = d * rp[m];
+#pragma unroll
+      for (int m2 = m + 1; m2 < 4; ++m2) {
+        double v = a[m2][m];
+#pragma unroll
+        for (int p = 0; p < m; ++p) v = fma(-Ld[m2][p], Ld[m][p], v);
+        Ld[m2][m] = v * rp[m];
+      }
+    }
+    double* out = buf + (J % 3) * 4 * CB;
+    double l[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      double v = r[m];
+#pragma unroll
+      for (int p = 0; p < m; ++p) v = fma(-Ld[m][p], l[p], v);
+      l[m] = lane >= j0 + m ? v * rp[m] : 0.0;
+      out[m * CB + lane] = l[m];
+      S[j0 + m][lane] = l[m];
+    }
+  };
+  double r[4];
+  if (w == 0) {
+    take_rows(0, r);
+    factor_rows(0, r);
+  } else if (w == 1) {
+    take_rows(1, r);
+  }
+  lds_barrier();
+  // operands of V_J: this wave's coefficients (A, rows of finished blocks
+  // zero) and V_J by chunk (B)
+  auto operands = [&](const double* vb, const int J, double& aop, double (&bop)[4]) {
+    const double av = vb[lg * CB + 16 * (li >> 2) + 4 * w + (li & 3)];
+    aop = w + 4 * (li >> 2) > J ? -av : 0.0;
+#pragma unroll
+    for (int ch = 0; ch < 4; ++ch) bop[ch] = vb[lg * CB + 16 * ch + li];
+  };
+  auto apply = [&](const double aop, const double (&bop)[4]) {
+#pragma unroll
+    for (int ch = 0; ch < 4; ++ch) acc[ch] = __builtin_amdgcn_mfma_f64_16x16x4f64(aop, bop[ch], acc[ch], 0, 0, 0);
+  };
+  // V_J sits in buf slot J % 3 until the end of step J + 1: the owner of
+  // step J applies it to its accumulators in step J + 1
+#pragma unroll
+  for (int J = 0; J < CB / 4 - 1; ++J) {
+    const double* vb = buf + (J % 3) * 4 * CB;
+    if (w == ((J + 1) & 3)) {
+      // block J + 1: V_J on the vector ALU, then its pivots
+      const int R0 = 4 * (J + 1);
+      double lv[4], cf[4][4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        lv[k] = vb[k * CB + lane];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) cf[k][t] = vb[k * CB + R0 + t];
+      }
+#pragma unroll
+      for (int t = 0; t < 4; ++t)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) r[t] = fma(-cf[k][t], lv[k], r[t]);
+      factor_rows(J + 1, r);
+    } else if (w + 12 > J) {   // the wave still has rows past block J
+      if (J >= 1 && w == (J & 3)) {
+        double daop, dbop[4];
+        operands(buf + ((J - 1) % 3) * 4 * CB, J - 1, daop, dbop);
+        apply(daop, dbop);
+      }
+      double aop, bop[4];
+      operands(vb, J, aop, bop);
+      apply(aop, bop);
+      if (J + 2 < CB / 4 && w == ((J + 2) & 3)) take_rows(J + 2, r);
+    }
+    lds_barrier();
+  }
+  if (bad < CB && lane == 0) atomicMin(sbad, bad);
+  lds_barrier();
+  const int bd = *sbad;
+  if (bd < nb) {  // uniform: read after the barrier by every thread
+    if (threadIdx.x == 0) info[0] = base + b0 + bd + 1;
+    return false;
+  }
+  // S[j][k] = L[k][j]
+  const int k = threadIdx.x >> 2, seg = threadIdx.x & 3;
+  if (k < nb) {
+    double* dst = A + (size_t)(b0 + k) * n + b0 + 16 * seg;
+#pragma unroll
+    for (int c = 0; c < 16; ++c)
+      if (16 * seg + c <= k) dst[c] = S[16 * seg + c][k];
+  }
+  return true;
+}
+
 template <bool CHOL>
 __global__ void __launch_bounds__(256) k_blk_diag(int n, int b0, double* __restrict__ A, int32_t* __restrict__ info,
                                                   int base, const int32_t* __restrict__ skip) {
   if (skip && *skip) return;
-  __shared__ double work[DIAG_WORK];
   if (info[0] != 0) return;
-  diag_factor<CHOL>(n, b0, A, info, base, work);
+  if constexpr (CHOL) {
+    __shared__ double S[CB][CB + 1];
+    __shared__ double buf[CHOL_BUF];
+    __shared__ int sbad;
+    stage_tile<256>(S, A + (size_t)b0 * n + b0, n, min(CB, n - b0), min(CB, n - b0), 1.0);
+    lds_barrier();
+    chol_diag_rows(n, b0, A, info, base, S, buf, &sbad);
+  } else {
+    __shared__ double work[DIAG_WORK];
+    diag_factor<false>(n, b0, A, info, base, work);
+  }
 }
 
 // Panels: wave task t < rows below: row r solves x U11 = a (LU) or
@@ -2808,6 +2982,10 @@ __global__ void __launch_bounds__(256) k_blk_update(int n, int b0, double* __res
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int qr = (w >> 1) * 32, qc = (w & 1) * 32;
   const int li = lane & 15, lk = lane >> 4;
+  // Cholesky with fuse: tile (0, 0) is the next diagonal block; its updated
+  // values go to LDS for the factorization instead of back to A
+  const bool dtile = CHOL && fuse && ti == 0 && tj == 0;
+  double sv[2][2][4];
   // a Cholesky diagonal tile has nothing to update above its diagonal
   if (!(CHOL && ti == tj && qc > qr)) {
     dbl4 acc[2][2];
@@ -2831,13 +3009,36 @@ __global__ void __launch_bounds__(256) k_blk_update(int n, int b0, double* __res
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int i = i0 + qr + 16 * p + lk + 4 * r, j = j0 + qc + 16 * q + li;
-          if (i < n && j < n && (!CHOL || j <= i)) A[(size_t)i * n + j] -= acc[p][q][r];
+          if (dtile) {
+            const double a = A[(size_t)min(i, n - 1) * n + min(j, n - 1)];
+            sv[p][q][r] = (i < n && j < n) ? a - acc[p][q][r] : (i == j ? 1.0 : 0.0);
+          } else if (i < n && j < n && (!CHOL || j <= i)) {
+            A[(size_t)i * n + j] -= acc[p][q][r];
+          }
         }
   }
-  if (fuse && ti == 0 && tj == 0) {
-    __syncthreads();   // the updated block is in A; the LDS tiles are free
-    static_assert(DIAG_WORK <= CB * (CB + 1), "diagonal work area must fit one tile");
-    diag_factor<CHOL>(n, base, A, info, dbase, &sm[0][0][0]);
+  if constexpr (CHOL) {
+    if (dtile) {
+      __shared__ int sbad;
+      __syncthreads();   // every wave is done with the staged tiles
+      if (qc <= qr) {
+#pragma unroll
+        for (int p = 0; p < 2; ++p)
+#pragma unroll
+          for (int q = 0; q < 2; ++q)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) sm[0][qr + 16 * p + lk + 4 * r][qc + 16 * q + li] = sv[p][q][r];
+      }
+      lds_barrier();
+      static_assert(CHOL_BUF <= CB * (CB + 1), "pivot-row exchange must fit one tile");
+      chol_diag_rows(n, base, A, info, dbase, sm[0], &sm[1][0][0], &sbad);
+    }
+  } else {
+    if (fuse && ti == 0 && tj == 0) {
+      __syncthreads();   // the updated block is in A; the LDS tiles are free
+      static_assert(DIAG_WORK <= CB * (CB + 1), "diagonal work area must fit one tile");
+      diag_factor<false>(n, base, A, info, dbase, &sm[0][0][0]);
+    }
   }
 }
 
