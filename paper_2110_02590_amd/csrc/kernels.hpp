@@ -2361,6 +2361,11 @@ __global__ void k_copy_vec(int n, const double* __restrict__ src, double* __rest
   if (i < n) dst[i] = src[i];
 }
 
+__global__ void k_neg_copy(int n, const double* __restrict__ src, double* __restrict__ dst) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) dst[i] = -src[i];
+}
+
 __global__ void k_count(const int32_t* __restrict__ skip, int32_t* __restrict__ count) {
   if (skip && *skip) return;
   if (threadIdx.x == 0 && blockIdx.x == 0) count[0] += 1;
@@ -2745,20 +2750,30 @@ __device__ __forceinline__ bool diag_factor(int n, int b0, double* __restrict__ 
 //   with V_J wait for the next step, off the chain of pivots;
 // * the owner of block J + 2 takes that block's rows out of its
 //   accumulators once V_J is applied, for the next step.
+// With yin (LDS, the block's entries of a right-hand side v, one per row),
+// the forward solve L y = v runs alongside: every wave keeps v less the
+// solved blocks' terms one row per lane, the owner solves the block's four
+// entries of y as uniform values next to its pivots and passes them with
+// V_J, and y goes to ydst at the end.
 // One barrier per four columns.  A failed pivot does not branch: the first
-// failing index is kept and reported after the loop, and the factor is then
-// not written.  buf: CHOL_BUF doubles; S collects the rows of L^T once the
-// block is read.
-constexpr int CHOL_BUF = 3 * 4 * CB + 4 * 4 * CB;
+// failing index is kept and reported after the loop, and the factor (and y)
+// is then not written.  buf: CHOL_BUF doubles; S collects the rows of L^T
+// once the block is read.
+constexpr int CHOL_BUF = 3 * 4 * CB + 4 * 4 * CB + 3 * 4 + CB;
 
 __device__ __forceinline__ bool chol_diag_rows(int n, int b0, double* __restrict__ A, int32_t* __restrict__ info,
                                                int base, double (*S)[CB + 1], double* __restrict__ buf,
-                                               int* __restrict__ sbad) {
+                                               int* __restrict__ sbad, const double* yin = nullptr,
+                                               double* __restrict__ ydst = nullptr) {
   const int nb = min(CB, n - b0);
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   const int li = lane & 15, lg = lane >> 4;
   double* ext = buf + 3 * 4 * CB + w * 4 * CB;   // this wave's row extraction
+  double* ys = buf + 3 * 4 * CB + 4 * 4 * CB;    // y of V_J's block, slot J % 3
+  double* yout = ys + 3 * 4;                     // y of the whole block
+  const bool wy = yin != nullptr;
+  double bv = wy ? yin[lane] : 0.0;              // v less the solved blocks' terms
   dbl4 acc[4];
 #pragma unroll
   for (int ch = 0; ch < 4; ++ch)
@@ -2782,11 +2797,15 @@ __device__ __forceinline__ bool chol_diag_rows(int n, int b0, double* __restrict
   // the pivot), to buf (for the other waves) and S (for the output)
   auto factor_rows = [&](const int J, const double (&r)[4]) {
     const int j0 = 4 * J;
-    double a[4][4], Ld[4][4], rp[4];
+    double a[4][4], Ld[4][4], rp[4], bj[4];
 #pragma unroll
     for (int m = 0; m < 4; ++m)
 #pragma unroll
       for (int m2 = 0; m2 <= m; ++m2) a[m][m2] = readlane_f64(r[m], j0 + m2);
+    if (wy) {
+#pragma unroll
+      for (int m = 0; m < 4; ++m) bj[m] = readlane_f64(bv, j0 + m);
+    }
 #pragma unroll
     for (int m = 0; m < 4; ++m) {
       double d = a[m][m];
@@ -2817,6 +2836,21 @@ __device__ __forceinline__ bool chol_diag_rows(int n, int b0, double* __restrict
       out[m * CB + lane] = l[m];
       S[j0 + m][lane] = l[m];
     }
+    if (wy) {
+      double yv[4];
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        double v = bj[m];
+#pragma unroll
+        for (int p = 0; p < m; ++p) v = fma(-Ld[m][p], yv[p], v);
+        yv[m] = v * rp[m];
+      }
+      if (lane < 4) {
+        const double ym = lane == 0 ? yv[0] : lane == 1 ? yv[1] : lane == 2 ? yv[2] : yv[3];
+        ys[(J % 3) * 4 + lane] = ym;
+        yout[j0 + lane] = ym;
+      }
+    }
   };
   double r[4];
   if (w == 0) {
@@ -2843,6 +2877,11 @@ __device__ __forceinline__ bool chol_diag_rows(int n, int b0, double* __restrict
 #pragma unroll
   for (int J = 0; J < CB / 4 - 1; ++J) {
     const double* vb = buf + (J % 3) * 4 * CB;
+    // v less block J's terms
+    auto take_y = [&](const double (&lv)[4]) {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) bv = fma(-lv[k], ys[(J % 3) * 4 + k], bv);
+    };
     if (w == ((J + 1) & 3)) {
       // block J + 1: V_J on the vector ALU, then its pivots
       const int R0 = 4 * (J + 1);
@@ -2853,12 +2892,19 @@ __device__ __forceinline__ bool chol_diag_rows(int n, int b0, double* __restrict
 #pragma unroll
         for (int t = 0; t < 4; ++t) cf[k][t] = vb[k * CB + R0 + t];
       }
+      if (wy) take_y(lv);
 #pragma unroll
       for (int t = 0; t < 4; ++t)
 #pragma unroll
         for (int k = 0; k < 4; ++k) r[t] = fma(-cf[k][t], lv[k], r[t]);
       factor_rows(J + 1, r);
     } else if (w + 12 > J) {   // the wave still has rows past block J
+      if (wy) {
+        double lv[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) lv[k] = vb[k * CB + lane];
+        take_y(lv);
+      }
       if (J >= 1 && w == (J & 3)) {
         double daop, dbop[4];
         operands(buf + ((J - 1) % 3) * 4 * CB, J - 1, daop, dbop);
@@ -2886,21 +2932,27 @@ __device__ __forceinline__ bool chol_diag_rows(int n, int b0, double* __restrict
     for (int c = 0; c < 16; ++c)
       if (16 * seg + c <= k) dst[c] = S[16 * seg + c][k];
   }
+  if (wy && threadIdx.x < nb) ydst[threadIdx.x] = yout[threadIdx.x];
   return true;
 }
 
 template <bool CHOL>
 __global__ void __launch_bounds__(256) k_blk_diag(int n, int b0, double* __restrict__ A, int32_t* __restrict__ info,
-                                                  int base, const int32_t* __restrict__ skip) {
+                                                  int base, const int32_t* __restrict__ skip,
+                                                  double* __restrict__ y = nullptr) {
   if (skip && *skip) return;
   if (info[0] != 0) return;
   if constexpr (CHOL) {
     __shared__ double S[CB][CB + 1];
     __shared__ double buf[CHOL_BUF];
     __shared__ int sbad;
-    stage_tile<256>(S, A + (size_t)b0 * n + b0, n, min(CB, n - b0), min(CB, n - b0), 1.0);
+    __shared__ double yl[CB];
+    const int nb = min(CB, n - b0);
+    const double yv = (y && threadIdx.x < CB) ? y[b0 + min((int)threadIdx.x, nb - 1)] : 0.0;
+    stage_tile<256>(S, A + (size_t)b0 * n + b0, n, nb, nb, 1.0);
+    if (y && threadIdx.x < CB) yl[threadIdx.x] = (int)threadIdx.x < nb ? yv : 0.0;
     lds_barrier();
-    chol_diag_rows(n, b0, A, info, base, S, buf, &sbad);
+    chol_diag_rows(n, b0, A, info, base, S, buf, &sbad, y ? yl : nullptr, y ? y + b0 : nullptr);
   } else {
     __shared__ double work[DIAG_WORK];
     diag_factor<false>(n, b0, A, info, base, work);
@@ -2951,14 +3003,20 @@ __global__ void k_blk_panel(int n, int b0, double* __restrict__ A, const int32_t
 
 // Trailing update A22 -= L21 U12 (LU) or L21 L21^T (Cholesky, lower tiles).
 // With fuse, workgroup (0, 0) -- dispatched first -- updates the next
-// diagonal block and then factorizes it (diag_factor, reusing this
-// kernel's LDS) while the other workgroups finish the trailing update.
+// diagonal block and then factorizes it (diag_factor, or chol_diag_rows
+// with the tile handed over in LDS) while the other workgroups finish the
+// trailing update.  y (Cholesky, optional): the fused forward solve; the
+// workgroups of the first tile column subtract L21 y_k (y_k = y[b0 ..],
+// solved by the previous launch) from their rows of y, and workgroup (0, 0)
+// then solves the next block's entries through the new diagonal factor.
 template <bool CHOL>
 __global__ void __launch_bounds__(256) k_blk_update(int n, int b0, double* __restrict__ A,
                                                     int32_t* __restrict__ info, int fuse, int dbase,
-                                                    const int32_t* __restrict__ skip) {
+                                                    const int32_t* __restrict__ skip,
+                                                    double* __restrict__ y = nullptr) {
   if (skip && *skip) return;
   __shared__ double sm[2][CB][CB + 1];
+  __shared__ double yk[CB];
   double (*Ls)[CB + 1] = sm[0];
   double (*Us)[CB + 1] = sm[1];
   if (info[0] != 0) return;
@@ -2967,12 +3025,34 @@ __global__ void __launch_bounds__(256) k_blk_update(int n, int b0, double* __res
   const int ti = blockIdx.y, tj = blockIdx.x;
   if (CHOL && tj > ti) return;
   const int i0 = base + ti * CB, j0 = base + tj * CB;
+  const bool ysolve = CHOL && y && tj == 0;
+  // y loads issued ahead of the tile loads
+  double ykv = 0.0, yrow = 0.0;
+  if (ysolve) {
+    if (threadIdx.x < CB) ykv = y[b0 + min((int)threadIdx.x, nb - 1)];
+    yrow = y[min(i0 + (int)(threadIdx.x >> 2), n - 1)];
+  }
   stage_tile<256>(Ls, A + (size_t)i0 * n + b0, n, n - i0, nb, 0.0);
   if (CHOL)
     stage_tile<256, true>(Us, A + (size_t)j0 * n + b0, n, n - j0, nb, 0.0);
   else
     stage_tile<256>(Us, A + (size_t)b0 * n + j0, n, nb, n - j0, 0.0);
+  if (ysolve && threadIdx.x < CB) yk[threadIdx.x] = (int)threadIdx.x < nb ? ykv : 0.0;
   __syncthreads();
+  // y rows i0 .. i0 + 63 -= L21 y_k: thread (row, quarter of the columns)
+  double ynew = 0.0;
+  if (ysolve) {
+    const int r = threadIdx.x >> 2, c4 = threadIdx.x & 3;
+    double a0 = 0.0, a1 = 0.0;
+#pragma unroll
+    for (int m = 0; m < 16; m += 2) {
+      a0 = fma(Ls[r][16 * c4 + m], yk[16 * c4 + m], a0);
+      a1 = fma(Ls[r][16 * c4 + m + 1], yk[16 * c4 + m + 1], a1);
+    }
+    const double sum = group_sum(a0 + a1, 4);
+    ynew = i0 + r < n ? yrow - sum : 0.0;
+    if (!(fuse && ti == 0) && c4 == 0 && i0 + r < n) y[i0 + r] = ynew;
+  }
   // FP64 matrix cores (v_mfma_f64_16x16x4f64): wave w takes the 32 x 32
   // quadrant (w >> 1, w & 1) of the tile as 2 x 2 blocks of 16 x 16, over
   // 16 steps of 4 in k.  Operand lanes: A(i, k) from lane i + 16 k, B(k, j)
@@ -3029,9 +3109,11 @@ __global__ void __launch_bounds__(256) k_blk_update(int n, int b0, double* __res
 #pragma unroll
             for (int r = 0; r < 4; ++r) sm[0][qr + 16 * p + lk + 4 * r][qc + 16 * q + li] = sv[p][q][r];
       }
+      if (ysolve && (threadIdx.x & 3) == 0) yk[threadIdx.x >> 2] = ynew;   // the next block's y
       lds_barrier();
       static_assert(CHOL_BUF <= CB * (CB + 1), "pivot-row exchange must fit one tile");
-      chol_diag_rows(n, base, A, info, dbase, sm[0], &sm[1][0][0], &sbad);
+      chol_diag_rows(n, base, A, info, dbase, sm[0], &sm[1][0][0], &sbad, ysolve ? yk : nullptr,
+                     ysolve ? y + base : nullptr);
     }
   } else {
     if (fuse && ti == 0 && tj == 0) {

@@ -749,11 +749,14 @@ void x_in(rpf_grid* h, const double* x, hipStream_t s, const int32_t* skip = nul
 }
 
 // Blocked dense LU (no pivoting) or Cholesky of a row-major n x n matrix.
+// y (Cholesky only, optional): the forward solve L y = v fused into the
+// factorization (on entry v, on exit y).
 template <bool CHOL>
-void dense_factor(int n, double* A, int32_t* info, int base, hipStream_t s, const int32_t* skip = nullptr) {
+void dense_factor(int n, double* A, int32_t* info, int base, hipStream_t s, const int32_t* skip = nullptr,
+                  double* y = nullptr) {
   // the first diagonal block on its own; every later one is factorized by
   // the trailing update of the previous block (fused, see k_blk_update)
-  k_blk_diag<CHOL><<<1, 256, 0, s>>>(n, 0, A, info, base, skip);
+  k_blk_diag<CHOL><<<1, 256, 0, s>>>(n, 0, A, info, base, skip, y);
   LAUNCHCHK();
   for (int b0 = 0; b0 < n; b0 += CB) {
     const int nb = std::min(CB, n - b0);
@@ -763,7 +766,7 @@ void dense_factor(int n, double* A, int32_t* info, int base, hipStream_t s, cons
       k_blk_panel<CHOL><<<cdiv(tasks, 4), 256, 0, s>>>(n, b0, A, info, skip);
       LAUNCHCHK();
       const int nt = cdiv(rest, CB);
-      k_blk_update<CHOL><<<dim3(nt, nt), 256, 0, s>>>(n, b0, A, info, 1, base, skip);
+      k_blk_update<CHOL><<<dim3(nt, nt), 256, 0, s>>>(n, b0, A, info, 1, base, skip, y);
       LAUNCHCHK();
     }
   }
@@ -1075,6 +1078,24 @@ void chol_solve(rpf_grid* h, int n, const double* L, const double* rhs, double* 
   chol_solve_ws(n, L, rhs, step, info, h->chol_flags, h->chol_dinv, h->chol_work, s);
 }
 
+// K = L L^T in place and step = -K^{-1} rhs with the forward solve fused
+// into the factorization (y = -L^{-1} rhs in work), then L^T step = y.
+// Scratch as chol_solve_ws.
+void factor_then_solve(int n, double* K, const double* rhs, double* step, int32_t* info, int32_t* flags,
+                       double* dinv, double* work, hipStream_t s) {
+  const int nblk = cdiv(n, CB);
+  k_neg_copy<<<cdiv(n, 256), 256, 0, s>>>(n, rhs, work);
+  LAUNCHCHK();
+  dense_factor<true>(n, K, info, 0, s, nullptr, work);
+  k_fill_int<<<cdiv(nblk, 256), 256, 0, s>>>(nblk, flags + nblk, 0);
+  LAUNCHCHK();
+  // inverses of the diagonal blocks (skipped when the factorization failed)
+  k_top_diag_inv<<<dim3(nblk, 1), 256, 0, s>>>(n, K, dinv, 0, 0, nullptr, info);
+  LAUNCHCHK();
+  k_chol_bwd<<<cdiv(n, 2 * CB), 512, 0, s>>>(n, K, dinv, work, step, flags + nblk, info);
+  LAUNCHCHK();
+}
+
 // The dense step K = (K + K^T)/2 + diag + delta I = L L^T, step = -K^{-1} rhs,
 // on `s` with the given triangular-solve scratch.
 void factor_solve_ws(int n, double* K, const double* diag, double delta, const double* rhs, double* step,
@@ -1083,8 +1104,7 @@ void factor_solve_ws(int n, double* K, const double* diag, double delta, const d
   LAUNCHCHK();
   k_symmetrize<<<dim3(cdiv(n, 32), cdiv(n, 32)), dim3(32, 8), 0, s>>>(n, K, diag, delta);
   LAUNCHCHK();
-  dense_factor<true>(n, K, info, 0, s);
-  chol_solve_ws(n, K, rhs, step, info, flags, dinv, work, s);
+  factor_then_solve(n, K, rhs, step, info, flags, dinv, work, s);
 }
 
 ALArgs al_args(rpf_grid* h, const double* u, const double* pd, const double* qd, const double* s,
@@ -1871,8 +1891,7 @@ int rpf_track_step(rpf_grid* h, double* u, double* x, double* y, const double* p
     LAUNCHCHK();
     k_symmetrize<<<dim3(cdiv(nu, 32), cdiv(nu, 32)), dim3(32, 8), 0, s>>>(nu, h->Kbuf, nullptr, delta);
     LAUNCHCHK();
-    dense_factor<true>(nu, h->Kbuf, info, 0, s);
-    chol_solve(h, nu, h->Kbuf, h->gradbuf, h->dstep, info, s);
+    factor_then_solve(nu, h->Kbuf, h->gradbuf, h->dstep, info, h->chol_flags, h->chol_dinv, h->chol_work, s);
     k_zero_if<<<cdiv(nu, 256), 256, 0, s>>>(nu, info, h->dstep);
     LAUNCHCHK();
     // 5. u + step / 2^k clipped to the bounds, first k whose power flow converges
