@@ -13,7 +13,7 @@ import time
 
 _CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tune_cache.json")
 _TABLE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tune_table.json")
-CANDIDATES = (128, 256, 512, 1024)
+CANDIDATES = (128, 256, 512, 1024, 2048, 4096)   # capped at n_u: one batch of every column
 TILES = ((16, False), (8, True), (8, False))
 
 
@@ -95,14 +95,15 @@ def best_batch(g, ep, candidates=CANDIDATES, reps=2, use_cache=True) -> int:
 
 
 def main(argv=None):
-    """python -m paper_2110_02590_amd.tune WORKLOAD ...: sweep the named
-    synthetic workloads on this device and write their entries into the
-    committed table (tune_table.json)."""
+    """python -m paper_2110_02590_amd.tune WORKLOAD ... [--out PATH]: sweep
+    the named synthetic workloads on this device and write their entries
+    into the committed table (tune_table.json) or PATH."""
     import argparse
 
     import gridgen
     ap = argparse.ArgumentParser()
     ap.add_argument("workloads", nargs="+")
+    ap.add_argument("--out", default=_TABLE, help="table to write (default: the committed table)")
     a = ap.parse_args(argv)
     table = _load(_TABLE)
     for name in a.workloads:
@@ -110,7 +111,7 @@ def main(argv=None):
         e = best_config(g, gridgen.eval_point(g), use_cache=False)
         table[_key(g)] = e
         print(name, _key(g), {k: e[k] for k in ("batch", "pack_tw", "pack_sv")}, flush=True)
-    with open(_TABLE, "w") as f:
+    with open(a.out, "w") as f:
         json.dump(table, f, indent=1)
 
 

@@ -14,10 +14,10 @@ torch = pytest.importorskip("torch")
 
 def test_full_step_graph_replay_equals_eager():
     from paper_2110_02590_amd import Problem
-    print("[case] capture syn9241 max_batch=1024", flush=True)
+    print("[case] capture syn9241 max_batch=2889", flush=True)
     g = gridgen.grid("syn9241")
     ep = gridgen.eval_point(g)
-    pr = Problem(g, max_batch=1024)
+    pr = Problem(g, max_batch=2889)
     grid = pr.grid
     nu, nx, m = pr.nu, pr.nx, pr.m
     s, y, rho, sigma = pr.point(ep)
@@ -42,7 +42,7 @@ def test_full_step_graph_replay_equals_eager():
         o["phi"], _ = grid.al_objective(o["x"], pr.u0, pd, qd, s, y, rho, sigma, c=o["c"])
         grid.reduced_gradient(o["x"], pr.u0, pd, qd, s, y, rho, sigma, grad=o["grad"], lam=o["lam"],
                               info=o["ginfo"])
-        grid.reduced_hessian(batch=1024, H=o["H"])
+        grid.reduced_hessian(batch=2889, H=o["H"])
         torch.add(o["H"], 0.0, out=o["K"])
         o["step"], o["cinfo"] = grid.factor_solve(o["K"], o["grad"], delta=delta)
 
@@ -65,7 +65,7 @@ def test_full_step_graph_replay_equals_eager():
         xt = x0.clone()
         st2, _ = grid.pf_solve(pr.u0, pd2, qd2, xt)
         grid.reduced_gradient(xt, pr.u0, pd2, qd2, s, y, rho, sigma)
-        grid.reduced_hessian(batch=1024)
+        grid.reduced_hessian(batch=2889)
         torch.cuda.synchronize()
         assert int(st2[1]) == 1
         graph.replay()

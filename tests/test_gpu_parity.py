@@ -143,13 +143,13 @@ def test_random_directions_linear():
     assert _rel(HV.cpu().numpy(), c.oracle("H") @ V.cpu().numpy()) < 1e-9
 
 
-@pytest.mark.parametrize("max_batch", [512, 1024])
+@pytest.mark.parametrize("max_batch", [512, 1024, 2889])
 def test_largest_workload_full_hessian(max_batch):
     """9241-bus grid: all 2889 columns of the reduced Hessian against the
     oracle's Schur form Z^T (grad^2 l) Z within 1e-9 relative Frobenius error
-    (Proposition 2).  1024 is the benchmark's launch configuration (three
-    batches, the last one 841 columns); 512 gives six batches, the last one
-    329 columns.  Every column is also compared on
+    (Proposition 2).  2889 is the benchmark's launch configuration (one batch
+    of every column); 1024 gives three batches, the last one 841 columns, and
+    512 six, the last one 329 columns.  Every column is also compared on
     its own, so that no batch can hide behind the whole matrix's norm."""
     c = case("syn9241", max_batch=max_batch)
     c.gpu_point()
@@ -184,12 +184,12 @@ def test_reduced_jacobian(name, batch):
 
 def test_reduced_jacobian_largest_workload():
     """The 41340 x 2889 reduced Jacobian of the 9241-bus grid in the
-    benchmark's launch configuration (batches of 1024),
+    benchmark's launch configuration (one batch of all 2889 columns),
     together with the Hessian, against the oracle; per constraint block
     (line flows, voltages, slack and PV reactive rows) as well."""
-    c = case("syn9241", max_batch=1024)
+    c = case("syn9241", max_batch=2889)
     c.gpu_point()
-    H, J = c.pr.grid.reduced_derivatives(batch=1024)
+    H, J = c.pr.grid.reduced_derivatives(batch=2889)
     torch.cuda.synchronize()
     Jg = J.cpu().numpy()
     del J

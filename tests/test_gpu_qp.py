@@ -118,23 +118,23 @@ def _kkt_blocks(H, J, grad, P, c, s, delta, d, nu):
 
 
 def test_largest_workload_kkt_certificate():
-    """9241 buses in the benchmark's launch configuration (batches of 1024):
+    """9241 buses in the benchmark's launch configuration (one batch of all 2889 columns):
     the GPU step satisfies the QP's KKT conditions, built in NumPy from the
     GPU's own H and J, to the stopping tolerance; the multipliers are
     positive and the step lies inside its box."""
     print("[case] qp syn9241", flush=True)
-    g, ep, M, u, x, P, s, lo, hi, pr = _case("syn9241", max_batch=1024)
+    g, ep, M, u, x, P, s, lo, hi, pr = _case("syn9241", max_batch=2889)
     ulo, uhi = M.u_bounds()
     # the QP data alone (no iteration), then the shift that makes the QP
     # strictly convex: H_uu = H - rho J^T D^2 J + delta I positive definite
-    r0 = _gpu(pr, x, u, s, P, lo, hi, 0.0, 0, 1e-10, batch=1024)
+    r0 = _gpu(pr, x, u, s, P, lo, hi, 0.0, 0, 1e-10, batch=2889)
     Ht = torch.tensor(r0["H"], device="cuda")
     Jt = torch.tensor(r0["J"], device="cuda")
     sc2 = torch.tensor(P.sigma_c ** 2, device="cuda")
     Huu = (Ht - P.rho * (Jt.T.contiguous() @ (sc2[:, None] * Jt))).cpu().numpy()
     delta = 1.5 * max(0.0, -float(np.linalg.eigvalsh(0.5 * (Huu + Huu.T)).min())) + 1e-2
     del Ht, Jt
-    r = _gpu(pr, x, u, s, P, lo, hi, delta, 60, 1e-10, batch=1024)
+    r = _gpu(pr, x, u, s, P, lo, hi, delta, 60, 1e-10, batch=2889)
     st = r["status"]
     print("status", st.tolist(), "kkt", float(r["kkt"][0]), flush=True)
     assert st[1] == 1 and st[2] == 0 and st[4] == 0, st
