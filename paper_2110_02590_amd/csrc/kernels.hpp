@@ -3151,9 +3151,13 @@ __global__ void k_transpose(int n, const double* __restrict__ A, double* __restr
 // flags: int32 [nwg] per direction (its own array for each launch), zero
 // before the launch; nwg = ceil(n / (2 CB)).
 
+// One thread polls with relaxed loads (an acquire load would invalidate the
+// caches at every poll) and takes one acquire fence once the flag is seen;
+// the workgroup barrier that follows the call orders the other threads'
+// reads after it.
 __device__ __forceinline__ void blk_wait(const int32_t* flag, int32_t* info) {
   unsigned it = 0;
-  while (__hip_atomic_load(flag, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == 0) {
+  while (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
     // after one expiry anywhere, no further waiting
     if (++it > (1u << 20) || __hip_atomic_load(info, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < 0) {
       __hip_atomic_store(info, -1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -3161,10 +3165,12 @@ __device__ __forceinline__ void blk_wait(const int32_t* flag, int32_t* info) {
     }
     __builtin_amdgcn_s_sleep(2);
   }
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
 }
 
+// The workgroup barrier orders every thread's stores before thread 0's
+// release store of the flag (one cache write-back per publication).
 __device__ __forceinline__ void blk_publish(int32_t* flag) {
-  __threadfence();
   __syncthreads();
   if (threadIdx.x == 0) __hip_atomic_store(flag, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
 }
@@ -3227,7 +3233,6 @@ __global__ void __launch_bounds__(512) k_chol_fwd(int n, const double* __restric
     }
     if (t == 0) blk_wait(flags + k, info);
     __syncthreads();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     if (r < nr) {
       const double* yk = y + k * 2 * CB + sl * 32;
 #pragma unroll
@@ -3326,7 +3331,6 @@ __global__ void __launch_bounds__(512) k_chol_bwd(int n, const double* __restric
     if (k - 1 > v) load_l(k - 1);
     if (t == 0) blk_wait(flags + k, info);
     __syncthreads();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     const int kr0 = k * 2 * CB + sl * 32;
     if (c < nr) {
 #pragma unroll
