@@ -3026,6 +3026,30 @@ __global__ void __launch_bounds__(256) k_blk_update(int n, int b0, double* __res
   if (CHOL && tj > ti) return;
   const int i0 = base + ti * CB, j0 = base + tj * CB;
   const bool ysolve = CHOL && y && tj == 0;
+  // FP64 matrix cores (v_mfma_f64_16x16x4f64): wave w takes the 32 x 32
+  // quadrant (w >> 1, w & 1) of the tile as 2 x 2 blocks of 16 x 16, over
+  // 16 steps of 4 in k.  Operand lanes: A(i, k) from lane i + 16 k, B(k, j)
+  // from lane j + 16 k; result register r of lane j + 16 q holds row
+  // q + 4 r of column j.  The staged tiles are zero past nb, so k runs to
+  // CB.  The wave's entries of the tile to update are loaded first, with
+  // the staging, so the write-back does not wait for memory.
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int qr = (w >> 1) * 32, qc = (w & 1) * 32;
+  const int li = lane & 15, lk = lane >> 4;
+  // a Cholesky diagonal tile has nothing to update above its diagonal
+  const bool active = !(CHOL && ti == tj && qc > qr);
+  double cv[2][2][4];
+  if (active) {
+#pragma unroll
+    for (int p = 0; p < 2; ++p)
+#pragma unroll
+      for (int q = 0; q < 2; ++q)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int i = i0 + qr + 16 * p + lk + 4 * r, j = j0 + qc + 16 * q + li;
+          cv[p][q][r] = A[(size_t)min(i, n - 1) * n + min(j, n - 1)];
+        }
+  }
   // y loads issued ahead of the tile loads
   double ykv = 0.0, yrow = 0.0;
   if (ysolve) {
@@ -3053,21 +3077,11 @@ __global__ void __launch_bounds__(256) k_blk_update(int n, int b0, double* __res
     ynew = i0 + r < n ? yrow - sum : 0.0;
     if (!(fuse && ti == 0) && c4 == 0 && i0 + r < n) y[i0 + r] = ynew;
   }
-  // FP64 matrix cores (v_mfma_f64_16x16x4f64): wave w takes the 32 x 32
-  // quadrant (w >> 1, w & 1) of the tile as 2 x 2 blocks of 16 x 16, over
-  // 16 steps of 4 in k.  Operand lanes: A(i, k) from lane i + 16 k, B(k, j)
-  // from lane j + 16 k; result register r of lane j + 16 q holds row
-  // q + 4 r of column j.  The staged tiles are zero past nb, so k runs to
-  // CB.
-  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int qr = (w >> 1) * 32, qc = (w & 1) * 32;
-  const int li = lane & 15, lk = lane >> 4;
   // Cholesky with fuse: tile (0, 0) is the next diagonal block; its updated
   // values go to LDS for the factorization instead of back to A
   const bool dtile = CHOL && fuse && ti == 0 && tj == 0;
   double sv[2][2][4];
-  // a Cholesky diagonal tile has nothing to update above its diagonal
-  if (!(CHOL && ti == tj && qc > qr)) {
+  if (active) {
     dbl4 acc[2][2];
 #pragma unroll
     for (int p = 0; p < 2; ++p)
@@ -3090,10 +3104,9 @@ __global__ void __launch_bounds__(256) k_blk_update(int n, int b0, double* __res
         for (int r = 0; r < 4; ++r) {
           const int i = i0 + qr + 16 * p + lk + 4 * r, j = j0 + qc + 16 * q + li;
           if (dtile) {
-            const double a = A[(size_t)min(i, n - 1) * n + min(j, n - 1)];
-            sv[p][q][r] = (i < n && j < n) ? a - acc[p][q][r] : (i == j ? 1.0 : 0.0);
+            sv[p][q][r] = (i < n && j < n) ? cv[p][q][r] - acc[p][q][r] : (i == j ? 1.0 : 0.0);
           } else if (i < n && j < n && (!CHOL || j <= i)) {
-            A[(size_t)i * n + j] -= acc[p][q][r];
+            A[(size_t)i * n + j] = cv[p][q][r] - acc[p][q][r];
           }
         }
   }
