@@ -2971,18 +2971,23 @@ __global__ void k_blk_panel(int n, int b0, double* __restrict__ A, const int32_t
   if (info[0] != 0) return;
   const int nb = min(CB, n - b0);
   const int rest = n - b0 - nb;
+  const int lane = threadIdx.x & 63;
+  const int task = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  // the wave's row (or LU column) is loaded with the diagonal block
+  double v = 0.0;
+  if (task < rest)
+    v = lane < nb ? A[(size_t)(b0 + nb + task) * n + b0 + lane] : 0.0;
+  else if (!CHOL && task < 2 * rest)
+    v = lane < nb ? A[(size_t)(b0 + lane) * n + b0 + nb + (task - rest)] : 0.0;
   stage_tile<256>(T, A + (size_t)b0 * n + b0, n, nb, nb, 1.0);
   __syncthreads();
   for (int j = threadIdx.x; j < CB; j += blockDim.x) rd[j] = 1.0 / T[j][j];
   __syncthreads();
-  const int lane = threadIdx.x & 63;
-  const int task = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   // substitution along the lanes: the solved entry j is broadcast with
   // readlane (a scalar register), so each step is a short dependent chain
   // of vector ALU operations; the factor entries come from LDS off the chain
   if (task < rest) {
     double* a = A + (size_t)(b0 + nb + task) * n + b0;
-    double v = lane < nb ? a[lane] : 0.0;
     for (int j = 0; j < nb; ++j) {
       const double f = CHOL ? T[lane][j] : T[j][lane];
       const double xj = readlane_f64(v, j) * rd[j];
@@ -2991,7 +2996,6 @@ __global__ void k_blk_panel(int n, int b0, double* __restrict__ A, const int32_t
     if (lane < nb) a[lane] = v;
   } else if (!CHOL && task < 2 * rest) {
     const int c = b0 + nb + (task - rest);
-    double v = lane < nb ? A[(size_t)(b0 + lane) * n + c] : 0.0;
     for (int j = 0; j < nb; ++j) {
       const double f = T[lane][j];
       const double yj = readlane_f64(v, j);
