@@ -978,9 +978,15 @@ void solve_pair(rpf_grid* h, bool transposed, double* X, int ld, int ncols, doub
       // one dense product with the inverse (k-major: S^-T gives S^-1 X)
       const double* A = transposed ? h->top_inv : h->top_invT;
       const int nt = std::min(1024, 64 * cdiv(P.ntop, 64));
-      if (ncols > 1)
+      if (ncols >= 2048)
+        // wide batches: four columns per workgroup, half the L2 reads of the
+        // inverse (measured at 2889 columns: 4 faster than 2 or 8)
+        k_top_inv_apply<4><<<cdiv(ncols, 4), nt, (size_t)P.ntop * 4 * sizeof(double), s>>>(P.t0, P.ntop, A, X, ld,
+                                                                                           ncols, skip);
+      else if (ncols > 1)
         // two columns per workgroup: more workgroups to hide the L2 latency
-        // of the inverse's rows (measured: 2 faster than 4 or 8)
+        // of the inverse's rows (measured up to 1024 columns: 2 faster than
+        // 4 or 8)
         k_top_inv_apply<2><<<cdiv(ncols, 2), nt, (size_t)P.ntop * 2 * sizeof(double), s>>>(P.t0, P.ntop, A, X, ld,
                                                                                            ncols, skip);
       else
