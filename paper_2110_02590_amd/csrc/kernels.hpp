@@ -749,9 +749,12 @@ __global__ void k_top_rhs(int t0, int n, const int32_t* __restrict__ lo_split, c
 
 // sum_p fval[p] X[col[p]][c] over p in [p0, p1) for columns c0 + 64 m
 // (m < CPT) of one lane, the row's entries read as scalars (p0, p1
-// wave-uniform), eight per pass with their X loads in flight.  Partial sums
-// by (p - p0) mod 4; with TAIL0 the entries past the last full group of
-// four go to the first sum instead.  Combined as (s0 + s1) + (s2 + s3).
+// wave-uniform), eight per pass with their X loads in flight; the next
+// pass's entries and loads are issued before this pass's products (always,
+// clamped, so every pass issues the same loads), and entries past p1 are
+// masked where they are used.  Partial sums by (p - p0) mod 4; with TAIL0
+// the entries past the last full group of four go to the first sum
+// instead.  Combined as (s0 + s1) + (s2 + s3).
 template <int CPT, bool TAIL0>
 __device__ __forceinline__ void row_gather(int p0, int p1, const int32_t* __restrict__ col,
                                            const double* __restrict__ fval, const double* __restrict__ X, int ld,
@@ -761,27 +764,42 @@ __device__ __forceinline__ void row_gather(int p0, int p1, const int32_t* __rest
   for (int k = 0; k < CPT; ++k)
 #pragma unroll
     for (int m = 0; m < 4; ++m) a[k][m] = 0.0;
+  if (p1 <= p0) {
+#pragma unroll
+    for (int k = 0; k < CPT; ++k) r[k] = 0.0;
+    return;
+  }
   const int pfull = p0 + ((p1 - p0) & ~3);
-  for (int pb = p0; pb < p1; pb += 8) {
+  auto fetch = [&](int pb, double (&vv)[8], double (&xv)[8][CPT]) {
     int jj[8];
-    double vv[8];
 #pragma unroll
     for (int m = 0; m < 8; ++m) {
       const int pc = min(pb + m, p1 - 1);
       jj[m] = col[pc];
-      const double raw = fval[pc];
-      vv[m] = pb + m < p1 ? raw : 0.0;
+      vv[m] = fval[pc];
     }
-    double xv[8][CPT];
 #pragma unroll
     for (int m = 0; m < 8; ++m)
 #pragma unroll
       for (int k = 0; k < CPT; ++k) xv[m][k] = X[(size_t)jj[m] * ld + min(c0 + 64 * k, ncols - 1)];
+  };
+  double vv[8], xv[8][CPT];
+  fetch(p0, vv, xv);
+  for (int pb = p0; pb < p1; pb += 8) {
+    double vn[8], xn[8][CPT];
+    fetch(pb + 8 < p1 ? pb + 8 : pb, vn, xn);
 #pragma unroll
     for (int m = 0; m < 8; ++m) {
       const int q = (TAIL0 && pb + m >= pfull) ? 0 : (m & 3);
+      const double v = pb + m < p1 ? vv[m] : 0.0;
 #pragma unroll
-      for (int k = 0; k < CPT; ++k) a[k][q] += vv[m] * xv[m][k];
+      for (int k = 0; k < CPT; ++k) a[k][q] += v * xv[m][k];
+    }
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+      vv[m] = vn[m];
+#pragma unroll
+      for (int k = 0; k < CPT; ++k) xv[m][k] = xn[m][k];
     }
   }
 #pragma unroll
