@@ -48,6 +48,32 @@ __device__ __forceinline__ void stage_tile(double (*dst)[CB + 1], const double* 
   }
 }
 
+// Two CB x CB tiles as stage_tile (the second stored transposed with
+// TRANS2), every load of both issued before the first store: one memory
+// round trip for the pair.
+template <int NT, bool TRANS2>
+__device__ __forceinline__ void stage_tile_pair(double (*d1)[CB + 1], const double* __restrict__ s1, int nr1, int nc1,
+                                                double (*d2)[CB + 1], const double* __restrict__ s2, int nr2, int nc2,
+                                                size_t ld, double diag_pad) {
+  constexpr int PER = CB * CB / NT;
+  double v1[PER], v2[PER];
+#pragma unroll
+  for (int m = 0; m < PER; ++m) {
+    const int e = threadIdx.x + m * NT, r = e >> 6, c = e & 63;
+    v1[m] = s1[(size_t)min(r, nr1 - 1) * ld + min(c, nc1 - 1)];
+    v2[m] = s2[(size_t)min(r, nr2 - 1) * ld + min(c, nc2 - 1)];
+  }
+#pragma unroll
+  for (int m = 0; m < PER; ++m) {
+    const int e = threadIdx.x + m * NT, r = e >> 6, c = e & 63;
+    const double pad = r == c ? diag_pad : 0.0;
+    d1[r][c] = (r < nr1 && c < nc1) ? v1[m] : pad;
+    const double w2 = (r < nr2 && c < nc2) ? v2[m] : pad;
+    if (TRANS2) d2[c][r] = w2;
+    else d2[r][c] = w2;
+  }
+}
+
 // Workgroup barrier for kernels whose threads communicate only through LDS:
 // waits for the thread's LDS operations, not for its global loads, so
 // prefetched global data can stay in flight across the barrier.
@@ -674,21 +700,23 @@ __device__ __forceinline__ void top_block_update(const double* __restrict__ M, i
     rk[k] = e < npair ? e / tw : 0;
     ck[k] = e < npair ? e - rk[k] * tw : 0;
   }
-  // tile element e = t + 256 m (m < 8): row e >> 5, column e & 31
+  // tile element e = t + 256 m (m < 8): row e >> 5, column e & 31; loaded
+  // with clamped addresses and masked at the LDS store, so the loads of the
+  // next tile stay in flight while the current one is used
   double nxt[8];
   auto load = [&](int jt) {
 #pragma unroll
     for (int m = 0; m < 8; ++m) {
       const int e = t + 256 * m, r = e >> 5, j = e & 31;
-      nxt[m] = (r < nb && jt + j < j1) ? M[(size_t)(b0 + r) * s + jt + j] : 0.0;
+      nxt[m] = M[(size_t)(b0 + min(r, nb - 1)) * s + min(jt + j, s - 1)];
     }
   };
   if (j0 < j1) load(j0);
   for (int jt = j0; jt < j1; jt += 32) {
 #pragma unroll
     for (int m = 0; m < 8; ++m) {
-      const int e = t + 256 * m;
-      mt[e >> 5][e & 31] = nxt[m];
+      const int e = t + 256 * m, r = e >> 5, j = e & 31;
+      mt[r][j] = (r < nb && jt + j < j1) ? nxt[m] : 0.0;
     }
     lds_barrier();
     if (jt + 32 < j1) load(jt + 32);
@@ -3078,11 +3106,12 @@ __global__ void __launch_bounds__(256) k_blk_update(int n, int b0, double* __res
     if (threadIdx.x < CB) ykv = y[b0 + min((int)threadIdx.x, nb - 1)];
     yrow = y[min(i0 + (int)(threadIdx.x >> 2), n - 1)];
   }
-  stage_tile<256>(Ls, A + (size_t)i0 * n + b0, n, n - i0, nb, 0.0);
   if (CHOL)
-    stage_tile<256, true>(Us, A + (size_t)j0 * n + b0, n, n - j0, nb, 0.0);
+    stage_tile_pair<256, true>(Ls, A + (size_t)i0 * n + b0, n - i0, nb, Us, A + (size_t)j0 * n + b0, n - j0, nb, n,
+                               0.0);
   else
-    stage_tile<256>(Us, A + (size_t)b0 * n + j0, n, nb, n - j0, 0.0);
+    stage_tile_pair<256, false>(Ls, A + (size_t)i0 * n + b0, n - i0, nb, Us, A + (size_t)b0 * n + j0, nb, n - j0, n,
+                                0.0);
   if (ysolve && threadIdx.x < CB) yk[threadIdx.x] = (int)threadIdx.x < nb ? ykv : 0.0;
   __syncthreads();
   // y rows i0 .. i0 + 63 -= L21 y_k: thread (row, quarter of the columns)
