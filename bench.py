@@ -42,8 +42,8 @@ FP64_PEAK_TFLOPS = 78.6
 TRAFFIC = {
     "pack_solve": {"kernel": "k_pack_solve_t", "helpers": ["tail_apply", "tail_apply_mfma", "tail_apply_any",
                                                            "stage_1d", "sum_xor16", "sum_xor32", "lds_barrier"],
-                   "batch": 2889, "bytes_per_launch": 729417949,
-                   "source_sha1": "9dc375d36de5548b62e2830f72acd14df4219992"},
+                   "batch": 2889, "bytes_per_launch": 729805842,
+                   "source_sha1": "eaf8998a300b58a3b1574444071592faf783b206"},
 }
 
 

@@ -1639,20 +1639,69 @@ __global__ void __launch_bounds__(1024) k_pack_solve_t(const int32_t* __restrict
   int16_t* scol = srow + nr;
   int16_t* sT = scol + ne;
   const int t = threadIdx.x, nt = blockDim.x;
-  stage_1d(scol, ecol + e0, ne);
-  if (SV) stage_1d(sval, pval + e0, ne);
-  for (int k = t; k < nT; k += nt) sT[k] = trows[tq + k];
-  // per level position: the row, and its first entry | length << 20 (entries
-  // of a pack below 2^20, row lengths below 2^11: checked on the host), so
-  // that both come from one LDS round trip
-  for (int p = t; p < nprog; p += nt) {
+  const int ntile = nr * TW;
+  // metadata.  Per level position: the row, and its first entry | length <<
+  // 20 (entries of a pack below 2^20, row lengths below 2^11: checked on the
+  // host), so that both come from one LDS round trip.  The first pass of
+  // every array (column indices and values eight per thread, tail rows,
+  // program rows, level bounds) is loaded at once, then the row bounds that
+  // depend on the program rows, then everything is stored: two memory round
+  // trips; items past one pass (packs larger than the workgroup) follow.
+  {
+    int16_t cv[8];
+    double pv[8];
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+      const int e = min(t + m * nt, ne - 1);
+      cv[m] = ne > 0 ? ecol[e0 + e] : (int16_t)0;
+      if (SV) pv[m] = ne > 0 ? pval[e0 + e] : 0.0;
+    }
+    const int16_t tv = nT > 0 ? trows[tq + min(t, nT - 1)] : (int16_t)0;
+    const int lr = nprog > 0 ? lrows[base_row + min(t, nprog - 1)] : r0;
+    const int lvv = lev[l0 + min(t, nlev)];
+    const int row = lr - r0;
+    const int es = rp[r0 + row], ee = rp[r0 + row + 1];
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+      const int e = t + m * nt;
+      if (e < ne) {
+        scol[e] = cv[m];
+        if (SV) sval[e] = pv[m];
+      }
+    }
+    if (t < nT) sT[t] = tv;
+    if (t < nprog) {
+      srow[t] = (int16_t)row;
+      smeta[t] = (es - e0) | ((ee - es) << 20);
+    }
+    if (t <= nlev) slev[t] = lvv - base_row;
+  }
+  for (int eb = t + 8 * nt; eb < ne; eb += 8 * nt) {
+    int16_t cv[8];
+    double pv[8];
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+      const int e = min(eb + m * nt, ne - 1);
+      cv[m] = ecol[e0 + e];
+      if (SV) pv[m] = pval[e0 + e];
+    }
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+      const int e = eb + m * nt;
+      if (e < ne) {
+        scol[e] = cv[m];
+        if (SV) sval[e] = pv[m];
+      }
+    }
+  }
+  for (int k = t + nt; k < nT; k += nt) sT[k] = trows[tq + k];
+  for (int p = t + nt; p < nprog; p += nt) {
     const int row = lrows[base_row + p] - r0;
     const int es = rp[r0 + row], ee = rp[r0 + row + 1];
     srow[p] = (int16_t)row;
     smeta[p] = (es - e0) | ((ee - es) << 20);
   }
-  for (int k = t; k <= nlev; k += nt) slev[k] = lev[l0 + k] - base_row;
-  const int ntile = nr * TW;
+  for (int k = t + nt; k <= nlev; k += nt) slev[k] = lev[l0 + k] - base_row;
   if (FWD && fz.jp) {
     // right-hand side R = -J_u V formed here from the directions V (rows of
     // J_u over the pack's rows, a few entries each): eight elements per
