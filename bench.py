@@ -97,8 +97,8 @@ def parse():
 def main():
     a = parse()
     if a.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is "
-                                   "described in DESIGN.md and not implemented", "n_gpus": a.gpus}))
+        print(json.dumps({"error": "one GPU only: the column blocks of the reduced Hessian would shard "
+                                   "over GPUs, but no multi-GPU path is implemented", "n_gpus": a.gpus}))
         sys.exit(2)
     import numpy as np
     import torch
