@@ -1017,66 +1017,66 @@ __global__ void __launch_bounds__(256) k_top_rhs1(int t0, int n, const int32_t* 
 }
 
 // Single right-hand side: the dense top solves x <- U^-1 L^-1 x (with M,
-// dinv of J_x^T: x <- L^-T U^-T x) for the s = n - t0 top rows, in one
-// workgroup of 1024 threads with x in LDS.  Per block of CB rows (forward,
-// then backward): wavefront w takes rows w + 16 m (m < 4); its lanes split
-// each row's products with the solved part and combine them by DPP; then
-// the block's inverse diagonal block is applied the same way (lane j
-// multiplies entry j).  The inverse's rows are loaded with the factor rows,
-// before the block's first barrier.
+// dinv of J_x^T: x <- L^-T U^-T x) for the s = n - t0 top rows (after
+// k_top_rhs1), with the factor M (s x s, row-major) and the inverses of its
+// diagonal blocks, in one workgroup of 1024 threads with x in LDS.  Per block of CB rows (forward, then backward): lane i is row i
+// of the block and wavefront w takes 16 columns of each 256 of the solved
+// part, so every product is a lane's own sum; the sixteen waves' partial
+// sums are added by wave 0 through LDS, and the block's inverse is applied
+// the same way (wave w its four columns), with no cross-lane reductions.
 __global__ void __launch_bounds__(1024) k_top_solve1(int t0, int n, const double* __restrict__ M,
                                                      const double* __restrict__ dinv, double* __restrict__ X, int ld,
                                                      const int32_t* __restrict__ skip) {
   if (skip && *skip) return;
   extern __shared__ double xs[];  // [s]
+  __shared__ double part[16][CB + 1];
   __shared__ double rv[CB];
   const int s = n - t0;
   const int t = threadIdx.x, w = t >> 6, lane = t & 63;
   for (int e = t; e < s; e += blockDim.x) xs[e] = X[(size_t)(t0 + e) * ld];
-  __syncthreads();
   const int nblk = (s + CB - 1) / CB;
-  for (int part = 0; part < 2; ++part) {
-    for (int q = 0; q < nblk; ++q) {
-      const int kb = part == 0 ? q : nblk - 1 - q;
-      const int b0 = kb * CB, nb = min(CB, s - b0);
-      // solved columns: forward [0, b0), backward [b0 + nb, s)
-      const int j0 = part == 0 ? 0 : b0 + nb, j1 = part == 0 ? b0 : s;
-      const double* D = dinv + (size_t)(kb * 2 + part) * CB * CB;
-      double dv[4], acc[4];
+  constexpr int CH = 16;   // columns per wave and pass
+  lds_barrier();
+  for (int q = 0; q < 2 * nblk; ++q) {
+    const int bwd = q >= nblk ? 1 : 0;
+    const int kb = bwd == 0 ? q : 2 * nblk - 1 - q;
+    const int b0 = kb * CB, nb = min(CB, s - b0);
+    // solved columns: forward [0, b0), backward [b0 + nb, s)
+    const int j0 = bwd == 0 ? 0 : b0 + nb, j1 = bwd == 0 ? b0 : s;
+    const double* D = dinv + (size_t)(kb * 2 + bwd) * CB * CB;
+    const double* Mr = M + (size_t)(b0 + min(lane, nb - 1)) * s;
+    double dv[4];
 #pragma unroll
-      for (int m = 0; m < 4; ++m) dv[m] = D[(w + 16 * m) * CB + lane];
+    for (int c = 0; c < 4; ++c) dv[c] = D[lane * CB + 4 * w + c];
+    double a = 0.0;
+    for (int jb = j0 + CH * w; jb < j1; jb += CH * 16) {
+      double mv[CH];
 #pragma unroll
-      for (int m = 0; m < 4; ++m) {
-        const int r = w + 16 * m;
-        double a = 0.0;
-        if (r < nb) {
-          const double* Mr = M + (size_t)(b0 + r) * s;
-          for (int j = j0 + lane; j < j1; j += 64) a += Mr[j] * xs[j];
-        }
-        acc[m] = a;
-      }
+      for (int c = 0; c < CH; ++c) mv[c] = Mr[min(jb + c, s - 1)];
 #pragma unroll
-      for (int m = 0; m < 4; ++m) acc[m] = group_sum(acc[m], 64);
-      if (lane == 0) {
-#pragma unroll
-        for (int m = 0; m < 4; ++m) {
-          const int r = w + 16 * m;
-          rv[r] = r < nb ? xs[min(b0 + r, s - 1)] - acc[m] : 0.0;
-        }
-      }
-      __syncthreads();
-      const double rl = rv[lane];
-#pragma unroll
-      for (int m = 0; m < 4; ++m) acc[m] = group_sum(dv[m] * rl, 64);
-      if (lane == 0) {
-#pragma unroll
-        for (int m = 0; m < 4; ++m) {
-          const int r = w + 16 * m;
-          if (r < nb) xs[b0 + r] = acc[m];
-        }
-      }
-      __syncthreads();
+      for (int c = 0; c < CH; ++c) a += (jb + c < j1 ? mv[c] : 0.0) * xs[min(jb + c, s - 1)];
     }
+    part[w][lane] = a;
+    lds_barrier();
+    if (w == 0) {
+      double sum = 0.0;
+#pragma unroll
+      for (int v = 0; v < 16; ++v) sum += part[v][lane];
+      rv[lane] = lane < nb ? xs[min(b0 + lane, s - 1)] - sum : 0.0;
+    }
+    lds_barrier();
+    double y = 0.0;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) y += dv[c] * rv[4 * w + c];
+    part[w][lane] = y;
+    lds_barrier();
+    if (w == 0) {
+      double sum = 0.0;
+#pragma unroll
+      for (int v = 0; v < 16; ++v) sum += part[v][lane];
+      if (lane < nb) xs[b0 + lane] = sum;
+    }
+    lds_barrier();
   }
   for (int e = t; e < s; e += blockDim.x) X[(size_t)(t0 + e) * ld] = xs[e];
 }
