@@ -1341,6 +1341,222 @@ __global__ void __launch_bounds__(256) k_pack_solve_s(const int32_t* __restrict_
   }
 }
 
+// Single right-hand side pack solves (power flow Newton steps and the
+// adjoint), with the level loop's metadata read one level ahead.  Only a
+// row's solved inputs xs[j] depend on earlier levels; the row's position,
+// entry range, column indices, factor values, own right-hand side and
+// reciprocal pivot are fixed once staged, so they are loaded during the
+// previous level and a level waits for one LDS round trip (the xs[j]
+// loads), its in-register group sum and the barrier.  G = 2^lg lanes share
+// a row (G as large as the level allows, at most 64); each lane's first
+// four entries come with the prefetch, longer rows loop over the rest.
+// Levels of more than 256 / G rows take further passes without prefetch.
+// FWD: entries [ptr[i], diag[i]), x_i = scale b_i - sum; backward: entries
+// (diag[i], up_split[i]), x_i = b_i - sum(top columns) - sum; UNIT = false
+// multiplies by the staged 1 / u_ii.
+// LDS: xs[nr] | val[ne + 1] | 1/dg[nr] | unit[nr] (int2: row | length << 16,
+// first entry) | rp[nr + 1] (int) | lev[nlev + 1] (int) | rows[nr] (short) |
+// col[ne + 1] (short); entry ne is a zero pad that out-of-row lanes read.
+__host__ __device__ __forceinline__ size_t pack1_lds_bytes(int nr, int ne, int nlev) {
+  size_t b = (size_t)nr * 8 + (size_t)(ne + 1) * 8 + (size_t)nr * 8 + (size_t)nr * 8 + (size_t)(nr + 1) * 4 +
+             (size_t)(nlev + 1) * 4 + (size_t)nr * 2 + (size_t)(ne + 1) * 2;
+  return (b + 15) & ~(size_t)15;
+}
+
+template <bool FWD, bool UNIT>
+__global__ void __launch_bounds__(256) k_pack_solve_1(const int32_t* __restrict__ pack_ptr, const int32_t* __restrict__ lev,
+                               const int32_t* __restrict__ lev_off, const int32_t* __restrict__ lrows,
+                               const int32_t* __restrict__ rp, const int32_t* __restrict__ epos,
+                               const int16_t* __restrict__ ecol, const int32_t* __restrict__ diag,
+                               const int32_t* __restrict__ up_split, const int32_t* __restrict__ ptr,
+                               const int32_t* __restrict__ col, const double* __restrict__ val,
+                               double* __restrict__ X, int ld, double scale, const int32_t* __restrict__ skip) {
+  if (skip && *skip) return;
+  extern __shared__ double smem[];
+  const int q = blockIdx.x;
+  const int r0 = pack_ptr[q], nr = pack_ptr[q + 1] - r0;
+  const int e0 = rp[r0], ne = rp[r0 + nr] - e0;
+  const int l0 = lev_off[q], nlev = lev_off[q + 1] - l0;
+  const int base_row = lev[l0];
+  double* xs = smem;
+  double* sv = xs + nr;
+  double* rdg = sv + ne + 1;
+  int2* sun = reinterpret_cast<int2*>(rdg + nr);
+  int* srp = reinterpret_cast<int*>(sun + nr);
+  int* slev = srp + nr + 1;
+  short* srow = reinterpret_cast<short*>(slev + nlev + 1);
+  short* scol = srow + nr;
+  const int t = threadIdx.x;
+  const int bd = blockDim.x;
+  for (int eb = t; eb < ne; eb += 16 * bd) {
+    int ps[16];
+    int16_t cs[16];
+#pragma unroll
+    for (int m = 0; m < 16; ++m) {
+      const int e = min(eb + m * bd, ne - 1);
+      ps[m] = epos[e0 + e];
+      cs[m] = ecol[e0 + e];
+    }
+    double vs[16];
+#pragma unroll
+    for (int m = 0; m < 16; ++m) vs[m] = val[ps[m]];
+#pragma unroll
+    for (int m = 0; m < 16; ++m) {
+      const int e = eb + m * bd;
+      if (e < ne) {
+        sv[e] = vs[m];
+        scol[e] = cs[m];
+      }
+    }
+  }
+  if (t == 0) {
+    sv[ne] = 0.0;
+    scol[ne] = 0;
+  }
+  for (int rb = t; rb <= nr; rb += 4 * bd) {
+    int v[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) v[m] = rp[r0 + min(rb + m * bd, nr)];
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+      if (rb + m * bd <= nr) srp[rb + m * bd] = v[m] - e0;
+  }
+  for (int rb = t; rb < nr; rb += 4 * bd) {
+    int di[4], lr[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const int r = min(rb + m * bd, nr - 1);
+      di[m] = UNIT ? 0 : diag[r0 + r];
+      lr[m] = lrows[base_row + r];
+    }
+    double dv[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) dv[m] = UNIT ? 1.0 : val[di[m]];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const int r = rb + m * bd;
+      if (r < nr) {
+        if (!UNIT) rdg[r] = 1.0 / dv[m];
+        srow[r] = (short)(lr[m] - r0);
+      }
+    }
+  }
+  for (int k = t; k <= nlev; k += bd) slev[k] = lev[l0 + k] - base_row;
+  for (int rb = t; rb < nr; rb += 4 * bd) {
+    double xv[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const int i = r0 + min(rb + m * bd, nr - 1);
+      double acc;
+      if (FWD) {
+        acc = scale * X[(size_t)i * ld];
+      } else {
+        // solved top rows: independent products, two partial sums
+        double a0 = 0.0, a1 = 0.0;
+        const int p1 = ptr[i + 1];
+        int p = up_split[i];
+        for (; p + 1 < p1; p += 2) {
+          a0 += val[p] * X[(size_t)col[p] * ld];
+          a1 += val[p + 1] * X[(size_t)col[p + 1] * ld];
+        }
+        if (p < p1) a0 += val[p] * X[(size_t)col[p] * ld];
+        acc = X[(size_t)i * ld] - (a0 + a1);
+      }
+      xv[m] = acc;
+    }
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+      if (rb + m * bd < nr) xs[rb + m * bd] = xv[m];
+  }
+  __syncthreads();
+  // one record per level position: the row, its entry count and first entry
+  for (int k = t; k < nr; k += bd) {
+    const int r = srow[k];
+    const int b = srp[r];
+    sun[k] = make_int2(r | ((srp[r + 1] - b) << 16), b);
+  }
+  __syncthreads();
+  if (nlev == 0) return;
+  auto level_lg = [&](int nrow) {
+    int lg = 0;
+    while (lg < 6 && (nrow << (lg + 1)) <= bd) ++lg;
+    return lg;
+  };
+  // a lane's unit at a level: its row, first entry, row end, first four
+  // (column, value) pairs, right-hand side and reciprocal pivot
+  struct Unit {
+    int r, e, e1;
+    int j[4];
+    double v[4];
+    double xr, rd;
+  };
+  auto fetch = [&](const int2 rec, int seg, int G, Unit& u) {
+    u.r = rec.x & 0xFFFF;
+    u.e = rec.y + seg;
+    u.e1 = rec.y + (rec.x >> 16);
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const int em = u.e + m * G;
+      const int ec = em < u.e1 ? em : ne;
+      u.j[m] = scol[ec];
+      u.v[m] = sv[ec];
+    }
+    u.xr = xs[u.r];
+    u.rd = UNIT ? 1.0 : rdg[u.r];
+  };
+  // the unit's sum over its lanes and the row's new value
+  auto finish = [&](const Unit& u, const double (&x)[4], int G, int seg, bool act) {
+    double p[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) p[m] = (u.e + m * G < u.e1) ? u.v[m] * x[m] : 0.0;
+    double part = (p[0] + p[1]) + (p[2] + p[3]);
+    if (act)
+      for (int e = u.e + 4 * G; e < u.e1; e += G) part += sv[e] * xs[scol[e]];
+    part = group_sum(part, G);
+    if (act && seg == 0) {
+      double acc = u.xr - part;
+      if (!UNIT) acc *= u.rd;
+      xs[u.r] = acc;
+    }
+  };
+  int s0 = slev[0], s1 = slev[1], s2 = slev[min(2, nlev)];
+  int lg = level_lg(s1 - s0);
+  Unit cur;
+  fetch(sun[max(s0 + min(t >> lg, s1 - s0 - 1), 0)], t & ((1 << lg) - 1), 1 << lg, cur);
+  for (int lv = 0; lv < nlev; ++lv) {
+    const int nrow = s1 - s0, G = 1 << lg, work = nrow << lg;
+    const int seg = t & (G - 1);
+    double x[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) x[m] = xs[cur.j[m]];
+    // the next level's record and the bound of the level after it, loaded
+    // without a branch (after the last level the indices stay in range and
+    // the values go unused), so that no wait for them lands before the sums
+    const int nlg = level_lg(s2 - s1);
+    const int2 rec = sun[max(s1 + min(t >> nlg, s2 - s1 - 1), 0)];
+    const int s3 = slev[min(lv + 3, nlev)];
+    Unit nxt;
+    fetch(rec, t & ((1 << nlg) - 1), 1 << nlg, nxt);
+    finish(cur, x, G, seg, t < work);
+    // levels wider than one pass of the workgroup
+    for (int w = t + bd; w - t < work; w += bd) {
+      Unit u;
+      fetch(sun[s0 + min(w >> lg, nrow - 1)], seg, G, u);
+      double xu[4];
+#pragma unroll
+      for (int m = 0; m < 4; ++m) xu[m] = xs[u.j[m]];
+      finish(u, xu, G, seg, w < work);
+    }
+    __syncthreads();
+    cur = nxt;
+    s0 = s1;
+    s1 = s2;
+    s2 = s3;
+    lg = nlg;
+  }
+  for (int r = t; r < nr; r += bd) X[(size_t)(r0 + r) * ld] = xs[r];
+}
+
 // Batched pack solves in place in global memory, for many right-hand
 // sides.  One workgroup (16 wavefronts) per (pack, 64-column tile); the
 // pack's column indices and row ranges are staged in LDS, factor values

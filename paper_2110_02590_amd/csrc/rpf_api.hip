@@ -110,7 +110,7 @@ struct rpf_grid {
   int4 *rf_rowrec = nullptr, *rf_ent = nullptr, *rf_tlrec = nullptr;   // k_rf_pack_lds records
   int32_t* rf_entu0 = nullptr;
   double *tailA = nullptr, *tailM = nullptr;
-  size_t lds_limit = 65536, lds_pack[5] = {0, 0, 0, 0, 0};
+  size_t lds_limit = 65536, lds_pack[5] = {0, 0, 0, 0, 0}, lds_pack1 = 0;
   double *c2, *c1, *c0;
   // predication word for the Hessian-product batches (set while the bounded
   // QP assembles its Schur complements; null otherwise)
@@ -528,6 +528,13 @@ void setup(rpf_grid* h) {
       }
       h->lds_pack[k] = mx;
     }
+    // single right-hand side pack solves with level records (either direction)
+    for (int q = 0; q < h->npacks; ++q) {
+      const int r0 = P.pack_ptr[q], nr = P.pack_ptr[q + 1] - r0;
+      const int nef = P.pkf_rp[r0 + nr] - P.pkf_rp[r0], neb = P.pkb_rp[r0 + nr] - P.pkb_rp[r0];
+      const int nlf = P.pk_flev_off[q + 1] - P.pk_flev_off[q], nlb = P.pk_blev_off[q + 1] - P.pk_blev_off[q];
+      h->lds_pack1 = std::max(h->lds_pack1, pack1_lds_bytes(nr, std::max(nef, neb), std::max(nlf, nlb)));
+    }
     // global-memory batched pack solves: largest pack, either direction
     for (int q = 0; q < h->npacks; ++q) {
       const int r0 = P.pack_ptr[q], nr = P.pack_ptr[q + 1] - r0;
@@ -639,6 +646,10 @@ void setup(rpf_grid* h) {
     RPF_ALLOW_PACK(2)
     RPF_ALLOW_PACK(1)
 #undef RPF_ALLOW_PACK
+    allow((const void*)k_pack_solve_1<true, true>);
+    allow((const void*)k_pack_solve_1<true, false>);
+    allow((const void*)k_pack_solve_1<false, true>);
+    allow((const void*)k_pack_solve_1<false, false>);
   }
   const size_t nnz = P.lu_col.size();
   h->xi = h->alloc<double>(P.nx);
@@ -845,7 +856,27 @@ void pack_solve(rpf_grid* h, bool fwd, bool unit, const double* val, double* X, 
     kern<<<grd, 256, shm, s>>>(h->pack_ptr, lev, lev_off, rows, rp, pos, ecol, h->lu_diag, h->up_split, h->lu_ptr,
                                h->lu_col, val, X, ld, ncols, scale, skip);
   };
-  if (fwd) {
+  auto launch1 = [&](auto kern, const int32_t* lev, const int32_t* lev_off, const int32_t* rows, const int32_t* rp,
+                     const int32_t* pos, const int16_t* ecol) {
+    kern<<<h->npacks, 256, h->lds_pack1, s>>>(h->pack_ptr, lev, lev_off, rows, rp, pos, ecol, h->lu_diag,
+                                               h->up_split, h->lu_ptr, h->lu_col, val, X, ld, scale, skip);
+  };
+  if (TW == 1 && ncols == 1 && h->lds_pack1 <= h->lds_limit) {
+    if (fwd) {
+      if (unit)
+        launch1(k_pack_solve_1<true, true>, h->pk_flev, h->pk_flev_off, h->pk_frows, h->pkf_rp, h->pkf_pos, h->pkf_col);
+      else
+        launch1(k_pack_solve_1<true, false>, h->pk_flev, h->pk_flev_off, h->pk_frows, h->pkf_rp, h->pkf_pos,
+                h->pkf_col);
+    } else {
+      if (unit)
+        launch1(k_pack_solve_1<false, true>, h->pk_blev, h->pk_blev_off, h->pk_brows, h->pkb_rp, h->pkb_pos,
+                h->pkb_col);
+      else
+        launch1(k_pack_solve_1<false, false>, h->pk_blev, h->pk_blev_off, h->pk_brows, h->pkb_rp, h->pkb_pos,
+                h->pkb_col);
+    }
+  } else if (fwd) {
     if (unit)
       launch(k_pack_solve_s<TW, true, true>, h->pk_flev, h->pk_flev_off, h->pk_frows, h->pkf_rp, h->pkf_pos, h->pkf_col);
     else
