@@ -1342,30 +1342,33 @@ __global__ void __launch_bounds__(256) k_pack_solve_s(const int32_t* __restrict_
 }
 
 // Single right-hand side pack solves (power flow Newton steps and the
-// adjoint), with the level loop's metadata read one level ahead.  Only a
-// row's solved inputs xs[j] depend on earlier levels; the row's position,
-// entry range, column indices, factor values, own right-hand side and
-// reciprocal pivot are fixed once staged, so they are loaded during the
-// previous level and a level waits for one LDS round trip (the xs[j]
-// loads), its in-register group sum and the barrier.  G = 2^lg lanes share
-// a row (G as large as the level allows, at most 64); each lane's first
-// four entries come with the prefetch, longer rows loop over the rest.
-// Levels of more than 256 / G rows take further passes without prefetch.
+// adjoint).  A level costs the instructions of one wavefront more than
+// memory, so the loop is kept short: G = 2^lg lanes share a row, with lg
+// per level from the host (enough lanes for two entries each on the
+// level's longest row, at most 64, at most 256 lanes in all); each lane's
+// two entries, the row's position, right-hand side and reciprocal pivot
+// are loaded during the previous level (only the solved inputs xs[j]
+// depend on earlier levels); entries past a row's end read a zero pad
+// (value 0, column nr, xs[nr] = 0), so the sums need no masks; longer rows
+// loop over the rest, and levels of more than 256 / G rows take further
+// passes without prefetch.  The loop is unrolled by two so the prefetched
+// state alternates between two register sets.
 // FWD: entries [ptr[i], diag[i]), x_i = scale b_i - sum; backward: entries
 // (diag[i], up_split[i]), x_i = b_i - sum(top columns) - sum; UNIT = false
 // multiplies by the staged 1 / u_ii.
-// LDS: xs[nr] | val[ne + 1] | 1/dg[nr] | unit[nr] (int2: row | length << 16,
-// first entry) | rp[nr + 1] (int) | lev[nlev + 1] (int) | rows[nr] (short) |
-// col[ne + 1] (short); entry ne is a zero pad that out-of-row lanes read.
+// LDS: xs[nr + 1] | val[ne + 1] | 1/dg[nr] | unit[nr] (int2: row | length
+// << 16, first entry) | rp[nr + 1] (int) | lev[nlev + 1] (int: first
+// position | lg << 16) | rows[nr] (short) | col[ne + 1] (short).
 __host__ __device__ __forceinline__ size_t pack1_lds_bytes(int nr, int ne, int nlev) {
-  size_t b = (size_t)nr * 8 + (size_t)(ne + 1) * 8 + (size_t)nr * 8 + (size_t)nr * 8 + (size_t)(nr + 1) * 4 +
+  size_t b = (size_t)(nr + 1) * 8 + (size_t)(ne + 1) * 8 + (size_t)nr * 8 + (size_t)nr * 8 + (size_t)(nr + 1) * 4 +
              (size_t)(nlev + 1) * 4 + (size_t)nr * 2 + (size_t)(ne + 1) * 2;
   return (b + 15) & ~(size_t)15;
 }
 
 template <bool FWD, bool UNIT>
 __global__ void __launch_bounds__(256) k_pack_solve_1(const int32_t* __restrict__ pack_ptr, const int32_t* __restrict__ lev,
-                               const int32_t* __restrict__ lev_off, const int32_t* __restrict__ lrows,
+                               const int32_t* __restrict__ lev_off, const int8_t* __restrict__ lev_lg,
+                               const int32_t* __restrict__ lrows,
                                const int32_t* __restrict__ rp, const int32_t* __restrict__ epos,
                                const int16_t* __restrict__ ecol, const int32_t* __restrict__ diag,
                                const int32_t* __restrict__ up_split, const int32_t* __restrict__ ptr,
@@ -1379,7 +1382,7 @@ __global__ void __launch_bounds__(256) k_pack_solve_1(const int32_t* __restrict_
   const int l0 = lev_off[q], nlev = lev_off[q + 1] - l0;
   const int base_row = lev[l0];
   double* xs = smem;
-  double* sv = xs + nr;
+  double* sv = xs + nr + 1;
   double* rdg = sv + ne + 1;
   int2* sun = reinterpret_cast<int2*>(rdg + nr);
   int* srp = reinterpret_cast<int*>(sun + nr);
@@ -1411,7 +1414,8 @@ __global__ void __launch_bounds__(256) k_pack_solve_1(const int32_t* __restrict_
   }
   if (t == 0) {
     sv[ne] = 0.0;
-    scol[ne] = 0;
+    scol[ne] = (short)nr;
+    xs[nr] = 0.0;
   }
   for (int rb = t; rb <= nr; rb += 4 * bd) {
     int v[4];
@@ -1441,7 +1445,10 @@ __global__ void __launch_bounds__(256) k_pack_solve_1(const int32_t* __restrict_
       }
     }
   }
-  for (int k = t; k <= nlev; k += bd) slev[k] = lev[l0 + k] - base_row;
+  for (int k = t; k <= nlev; k += bd) {
+    const int lg = k < nlev ? (int)lev_lg[l0 + k] : 0;
+    slev[k] = (lev[l0 + k] - base_row) | (lg << 16);
+  }
   for (int rb = t; rb < nr; rb += 4 * bd) {
     double xv[4];
 #pragma unroll
@@ -1477,17 +1484,12 @@ __global__ void __launch_bounds__(256) k_pack_solve_1(const int32_t* __restrict_
   }
   __syncthreads();
   if (nlev == 0) return;
-  auto level_lg = [&](int nrow) {
-    int lg = 0;
-    while (lg < 6 && (nrow << (lg + 1)) <= bd) ++lg;
-    return lg;
-  };
-  // a lane's unit at a level: its row, first entry, row end, first four
+  // a lane's unit at a level: its row, first entry, row end, first two
   // (column, value) pairs, right-hand side and reciprocal pivot
   struct Unit {
     int r, e, e1;
-    int j[4];
-    double v[4];
+    int j[2];
+    double v[2];
     double xr, rd;
   };
   auto fetch = [&](const int2 rec, int seg, int G, Unit& u) {
@@ -1495,7 +1497,7 @@ __global__ void __launch_bounds__(256) k_pack_solve_1(const int32_t* __restrict_
     u.e = rec.y + seg;
     u.e1 = rec.y + (rec.x >> 16);
 #pragma unroll
-    for (int m = 0; m < 4; ++m) {
+    for (int m = 0; m < 2; ++m) {
       const int em = u.e + m * G;
       const int ec = em < u.e1 ? em : ne;
       u.j[m] = scol[ec];
@@ -1504,14 +1506,17 @@ __global__ void __launch_bounds__(256) k_pack_solve_1(const int32_t* __restrict_
     u.xr = xs[u.r];
     u.rd = UNIT ? 1.0 : rdg[u.r];
   };
+  // the unit of the level whose words are wa (first position | lg << 16)
+  // and wb (the next level's)
+  auto fetch_level = [&](int wa, int wb, Unit& u) {
+    const int a = wa & 0xFFFF, nrow = (wb & 0xFFFF) - a, lg = wa >> 16;
+    fetch(sun[max(a + min(t >> lg, nrow - 1), 0)], t & ((1 << lg) - 1), 1 << lg, u);
+  };
   // the unit's sum over its lanes and the row's new value
-  auto finish = [&](const Unit& u, const double (&x)[4], int G, int seg, bool act) {
-    double p[4];
-#pragma unroll
-    for (int m = 0; m < 4; ++m) p[m] = (u.e + m * G < u.e1) ? u.v[m] * x[m] : 0.0;
-    double part = (p[0] + p[1]) + (p[2] + p[3]);
+  auto finish = [&](const Unit& u, const double (&x)[2], int G, int seg, bool act) {
+    double part = fma(u.v[1], x[1], u.v[0] * x[0]);
     if (act)
-      for (int e = u.e + 4 * G; e < u.e1; e += G) part += sv[e] * xs[scol[e]];
+      for (int e = u.e + 2 * G; e < u.e1; e += G) part += sv[e] * xs[scol[e]];
     part = group_sum(part, G);
     if (act && seg == 0) {
       double acc = u.xr - part;
@@ -1519,40 +1524,37 @@ __global__ void __launch_bounds__(256) k_pack_solve_1(const int32_t* __restrict_
       xs[u.r] = acc;
     }
   };
-  int s0 = slev[0], s1 = slev[1], s2 = slev[min(2, nlev)];
-  int lg = level_lg(s1 - s0);
-  Unit cur;
-  fetch(sun[max(s0 + min(t >> lg, s1 - s0 - 1), 0)], t & ((1 << lg) - 1), 1 << lg, cur);
-  for (int lv = 0; lv < nlev; ++lv) {
-    const int nrow = s1 - s0, G = 1 << lg, work = nrow << lg;
-    const int seg = t & (G - 1);
-    double x[4];
+  int w0 = slev[0], w1 = slev[1], w2 = slev[min(2, nlev)];
+  Unit ua, ub;
+  fetch_level(w0, w1, ua);
+  auto step = [&](int lv, const Unit& cur, Unit& nxt) {
+    const int a = w0 & 0xFFFF, nrow = (w1 & 0xFFFF) - a, lg = w0 >> 16;
+    const int G = 1 << lg, work = nrow << lg, seg = t & (G - 1);
+    double x[2];
 #pragma unroll
-    for (int m = 0; m < 4; ++m) x[m] = xs[cur.j[m]];
-    // the next level's record and the bound of the level after it, loaded
-    // without a branch (after the last level the indices stay in range and
-    // the values go unused), so that no wait for them lands before the sums
-    const int nlg = level_lg(s2 - s1);
-    const int2 rec = sun[max(s1 + min(t >> nlg, s2 - s1 - 1), 0)];
-    const int s3 = slev[min(lv + 3, nlev)];
-    Unit nxt;
-    fetch(rec, t & ((1 << nlg) - 1), 1 << nlg, nxt);
+    for (int m = 0; m < 2; ++m) x[m] = xs[cur.j[m]];
+    // the next level's unit (after the last level the indices stay in range
+    // and the values go unused) and the word of the level after it
+    const int w3 = slev[min(lv + 3, nlev)];
+    fetch_level(w1, w2, nxt);
     finish(cur, x, G, seg, t < work);
     // levels wider than one pass of the workgroup
     for (int w = t + bd; w - t < work; w += bd) {
       Unit u;
-      fetch(sun[s0 + min(w >> lg, nrow - 1)], seg, G, u);
-      double xu[4];
+      fetch(sun[a + min(w >> lg, nrow - 1)], seg, G, u);
+      double xu[2];
 #pragma unroll
-      for (int m = 0; m < 4; ++m) xu[m] = xs[u.j[m]];
+      for (int m = 0; m < 2; ++m) xu[m] = xs[u.j[m]];
       finish(u, xu, G, seg, w < work);
     }
     __syncthreads();
-    cur = nxt;
-    s0 = s1;
-    s1 = s2;
-    s2 = s3;
-    lg = nlg;
+    w0 = w1;
+    w1 = w2;
+    w2 = w3;
+  };
+  for (int lv = 0; lv < nlev; lv += 2) {
+    step(lv, ua, ub);
+    if (lv + 1 < nlev) step(lv + 1, ub, ua);
   }
   for (int r = t; r < nr; r += bd) X[(size_t)(r0 + r) * ld] = xs[r];
 }

@@ -47,6 +47,25 @@ struct HipError : std::runtime_error {
 
 inline int cdiv(long a, long b) { return (int)((a + b - 1) / b); }
 
+// Lanes per row (log2) of each level of a single right-hand side pack
+// program (levels lev[l] .. lev[l + 1] of rows, entries rp[i] .. rp[i + 1]
+// of row i): enough for two entries per lane on the level's longest row,
+// at most 64 lanes per row and 256 lanes per level.
+std::vector<int8_t> level_lanes(const std::vector<int32_t>& lev, const std::vector<int32_t>& rows,
+                                const std::vector<int32_t>& rp) {
+  const int nl = std::max((int)lev.size() - 1, 0);
+  std::vector<int8_t> lg(nl, 0);
+  for (int l = 0; l < nl; ++l) {
+    const int nrow = lev[l + 1] - lev[l];
+    int len = 0;
+    for (int k = lev[l]; k < lev[l + 1]; ++k) len = std::max(len, rp[rows[k] + 1] - rp[rows[k]]);
+    int g = 0;
+    while (g < 6 && (2 << g) < len && (nrow << (g + 1)) <= 256) ++g;
+    lg[l] = (int8_t)g;
+  }
+  return lg;
+}
+
 }  // namespace
 
 struct rpf_grid {
@@ -89,6 +108,7 @@ struct rpf_grid {
   bool top_inv_ok = false;
   int npacks = 0, max_pack = 0, tw = 16;
   int32_t *pkf_rp, *pkf_pos, *pkb_rp, *pkb_pos;
+  int8_t *pk_flg = nullptr, *pk_blg = nullptr;
   int16_t *pkf_col, *pkb_col;
   int tw_pack = 8, tw_top = 8;
   size_t lds_packg = 0;   // LDS of the global-memory batched pack solves
@@ -411,6 +431,8 @@ void setup(rpf_grid* h) {
   h->pk_frows = h->up(P.pk_frows);
   h->pk_blev = h->up(P.pk_blev);
   h->pk_blev_off = h->up(P.pk_blev_off);
+  h->pk_flg = h->up(level_lanes(P.pk_flev, P.pk_frows, P.pkf_rp));
+  h->pk_blg = h->up(level_lanes(P.pk_blev, P.pk_brows, P.pkb_rp));
   h->pk_brows = h->up(P.pk_brows);
   h->top_flev = h->up(P.top_flev);
   h->top_frows = h->up(P.top_frows);
@@ -856,25 +878,26 @@ void pack_solve(rpf_grid* h, bool fwd, bool unit, const double* val, double* X, 
     kern<<<grd, 256, shm, s>>>(h->pack_ptr, lev, lev_off, rows, rp, pos, ecol, h->lu_diag, h->up_split, h->lu_ptr,
                                h->lu_col, val, X, ld, ncols, scale, skip);
   };
-  auto launch1 = [&](auto kern, const int32_t* lev, const int32_t* lev_off, const int32_t* rows, const int32_t* rp,
-                     const int32_t* pos, const int16_t* ecol) {
-    kern<<<h->npacks, 256, h->lds_pack1, s>>>(h->pack_ptr, lev, lev_off, rows, rp, pos, ecol, h->lu_diag,
+  auto launch1 = [&](auto kern, const int32_t* lev, const int32_t* lev_off, const int8_t* lgs, const int32_t* rows,
+                     const int32_t* rp, const int32_t* pos, const int16_t* ecol) {
+    kern<<<h->npacks, 256, h->lds_pack1, s>>>(h->pack_ptr, lev, lev_off, lgs, rows, rp, pos, ecol, h->lu_diag,
                                                h->up_split, h->lu_ptr, h->lu_col, val, X, ld, scale, skip);
   };
   if (TW == 1 && ncols == 1 && h->lds_pack1 <= h->lds_limit) {
     if (fwd) {
       if (unit)
-        launch1(k_pack_solve_1<true, true>, h->pk_flev, h->pk_flev_off, h->pk_frows, h->pkf_rp, h->pkf_pos, h->pkf_col);
+        launch1(k_pack_solve_1<true, true>, h->pk_flev, h->pk_flev_off, h->pk_flg, h->pk_frows, h->pkf_rp,
+                h->pkf_pos, h->pkf_col);
       else
-        launch1(k_pack_solve_1<true, false>, h->pk_flev, h->pk_flev_off, h->pk_frows, h->pkf_rp, h->pkf_pos,
-                h->pkf_col);
+        launch1(k_pack_solve_1<true, false>, h->pk_flev, h->pk_flev_off, h->pk_flg, h->pk_frows, h->pkf_rp,
+                h->pkf_pos, h->pkf_col);
     } else {
       if (unit)
-        launch1(k_pack_solve_1<false, true>, h->pk_blev, h->pk_blev_off, h->pk_brows, h->pkb_rp, h->pkb_pos,
-                h->pkb_col);
+        launch1(k_pack_solve_1<false, true>, h->pk_blev, h->pk_blev_off, h->pk_blg, h->pk_brows, h->pkb_rp,
+                h->pkb_pos, h->pkb_col);
       else
-        launch1(k_pack_solve_1<false, false>, h->pk_blev, h->pk_blev_off, h->pk_brows, h->pkb_rp, h->pkb_pos,
-                h->pkb_col);
+        launch1(k_pack_solve_1<false, false>, h->pk_blev, h->pk_blev_off, h->pk_blg, h->pk_brows, h->pkb_rp,
+                h->pkb_pos, h->pkb_col);
     }
   } else if (fwd) {
     if (unit)
