@@ -1391,24 +1391,106 @@ __global__ void __launch_bounds__(256) k_pack_solve_1(const int32_t* __restrict_
   short* scol = srow + nr;
   const int t = threadIdx.x;
   const int bd = blockDim.x;
-  for (int eb = t; eb < ne; eb += 16 * bd) {
-    int ps[16];
-    int16_t cs[16];
+  // Staging.  The first pass of the entries and of every per-row and
+  // per-level array is loaded at once, then what depends on it (factor
+  // values, pivots, the first two top-column terms of backward rows and
+  // their solved values), and only then stored to LDS; further passes
+  // (packs of more than 4096 entries or 1024 rows) and longer top-column
+  // products follow.  Indices are clamped into their arrays; a pack
+  // without entries reads entry 0 of the LU values.
+  constexpr int EP = 16, RP = 4;
+  {
+    const bool has_e = ne > 0;
+    int ps[EP];
+    int16_t cs[EP];
 #pragma unroll
-    for (int m = 0; m < 16; ++m) {
-      const int e = min(eb + m * bd, ne - 1);
-      ps[m] = epos[e0 + e];
-      cs[m] = ecol[e0 + e];
+    for (int m = 0; m < EP; ++m) {
+      const int gi = has_e ? e0 + min(t + m * bd, ne - 1) : 0;
+      ps[m] = epos[gi];
+      cs[m] = ecol[gi];
     }
-    double vs[16];
+    int rpv[RP + 1];
 #pragma unroll
-    for (int m = 0; m < 16; ++m) vs[m] = val[ps[m]];
+    for (int m = 0; m <= RP; ++m) rpv[m] = rp[r0 + min(t + m * bd, nr)];
+    int di[RP], lr[RP], ri[RP];
 #pragma unroll
-    for (int m = 0; m < 16; ++m) {
-      const int e = eb + m * bd;
+    for (int m = 0; m < RP; ++m) {
+      ri[m] = r0 + min(t + m * bd, nr - 1);
+      di[m] = UNIT ? 0 : diag[ri[m]];
+      lr[m] = lrows[base_row + min(t + m * bd, nr - 1)];
+    }
+    const int kl = min(t, nlev);
+    const int lvw = lev[l0 + kl];
+    const int lgw = t < nlev ? (int)lev_lg[l0 + t] : 0;
+    double xi[RP];
+    int us[RP], pe[RP];
+#pragma unroll
+    for (int m = 0; m < RP; ++m) {
+      xi[m] = X[(size_t)ri[m] * ld];
+      us[m] = FWD ? 0 : up_split[ri[m]];
+      pe[m] = FWD ? 0 : ptr[ri[m] + 1];
+    }
+    double vs[EP];
+#pragma unroll
+    for (int m = 0; m < EP; ++m) vs[m] = val[has_e ? ps[m] : 0];
+    double dv[RP];
+#pragma unroll
+    for (int m = 0; m < RP; ++m) dv[m] = UNIT ? 1.0 : val[di[m]];
+    // backward: the first two terms of each row's solved top-column product
+    int tc[RP][2];
+    double tv[RP][2];
+    if (!FWD) {
+#pragma unroll
+      for (int m = 0; m < RP; ++m)
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+          const int pp = min(us[m] + k, pe[m] - 1);
+          tc[m][k] = col[pp];
+          tv[m][k] = val[pp];
+        }
+    }
+    double tx[RP][2];
+    if (!FWD) {
+#pragma unroll
+      for (int m = 0; m < RP; ++m)
+#pragma unroll
+        for (int k = 0; k < 2; ++k) tx[m][k] = X[(size_t)tc[m][k] * ld];
+    }
+#pragma unroll
+    for (int m = 0; m < EP; ++m) {
+      const int e = t + m * bd;
       if (e < ne) {
         sv[e] = vs[m];
         scol[e] = cs[m];
+      }
+    }
+#pragma unroll
+    for (int m = 0; m <= RP; ++m)
+      if (t + m * bd <= nr) srp[t + m * bd] = rpv[m] - e0;
+    if (t <= nlev) slev[t] = (lvw - base_row) | (lgw << 16);
+#pragma unroll
+    for (int m = 0; m < RP; ++m) {
+      const int r = t + m * bd;
+      double acc;
+      if (FWD) {
+        acc = scale * xi[m];
+      } else {
+        // independent products, two partial sums
+        const int p1 = pe[m];
+        double a0 = us[m] < p1 ? tv[m][0] * tx[m][0] : 0.0;
+        double a1 = us[m] + 1 < p1 ? tv[m][1] * tx[m][1] : 0.0;
+        int p = us[m] + 2;
+        for (; p + 1 < p1; p += 2) {
+          a0 += val[p] * X[(size_t)col[p] * ld];
+          a1 += val[p + 1] * X[(size_t)col[p + 1] * ld];
+        }
+        if (p < p1) a0 += val[p] * X[(size_t)col[p] * ld];
+        acc = xi[m] - (a0 + a1);
+      }
+      if (r < nr) {
+        if (!UNIT) rdg[r] = 1.0 / dv[m];
+        srow[r] = (short)(lr[m] - r0);
+        xs[r] = acc;
       }
     }
   }
@@ -1417,63 +1499,49 @@ __global__ void __launch_bounds__(256) k_pack_solve_1(const int32_t* __restrict_
     scol[ne] = (short)nr;
     xs[nr] = 0.0;
   }
-  for (int rb = t; rb <= nr; rb += 4 * bd) {
-    int v[4];
+  // further passes
+  for (int eb = t + EP * bd; eb < ne; eb += EP * bd) {
+    int ps[EP];
+    int16_t cs[EP];
 #pragma unroll
-    for (int m = 0; m < 4; ++m) v[m] = rp[r0 + min(rb + m * bd, nr)];
-#pragma unroll
-    for (int m = 0; m < 4; ++m)
-      if (rb + m * bd <= nr) srp[rb + m * bd] = v[m] - e0;
-  }
-  for (int rb = t; rb < nr; rb += 4 * bd) {
-    int di[4], lr[4];
-#pragma unroll
-    for (int m = 0; m < 4; ++m) {
-      const int r = min(rb + m * bd, nr - 1);
-      di[m] = UNIT ? 0 : diag[r0 + r];
-      lr[m] = lrows[base_row + r];
+    for (int m = 0; m < EP; ++m) {
+      const int e = min(eb + m * bd, ne - 1);
+      ps[m] = epos[e0 + e];
+      cs[m] = ecol[e0 + e];
     }
-    double dv[4];
+    double vs[EP];
 #pragma unroll
-    for (int m = 0; m < 4; ++m) dv[m] = UNIT ? 1.0 : val[di[m]];
+    for (int m = 0; m < EP; ++m) vs[m] = val[ps[m]];
 #pragma unroll
-    for (int m = 0; m < 4; ++m) {
-      const int r = rb + m * bd;
-      if (r < nr) {
-        if (!UNIT) rdg[r] = 1.0 / dv[m];
-        srow[r] = (short)(lr[m] - r0);
+    for (int m = 0; m < EP; ++m) {
+      const int e = eb + m * bd;
+      if (e < ne) {
+        sv[e] = vs[m];
+        scol[e] = cs[m];
       }
     }
   }
-  for (int k = t; k <= nlev; k += bd) {
-    const int lg = k < nlev ? (int)lev_lg[l0 + k] : 0;
-    slev[k] = (lev[l0 + k] - base_row) | (lg << 16);
-  }
-  for (int rb = t; rb < nr; rb += 4 * bd) {
-    double xv[4];
-#pragma unroll
-    for (int m = 0; m < 4; ++m) {
-      const int i = r0 + min(rb + m * bd, nr - 1);
-      double acc;
-      if (FWD) {
-        acc = scale * X[(size_t)i * ld];
-      } else {
-        // solved top rows: independent products, two partial sums
-        double a0 = 0.0, a1 = 0.0;
-        const int p1 = ptr[i + 1];
-        int p = up_split[i];
-        for (; p + 1 < p1; p += 2) {
-          a0 += val[p] * X[(size_t)col[p] * ld];
-          a1 += val[p + 1] * X[(size_t)col[p + 1] * ld];
-        }
-        if (p < p1) a0 += val[p] * X[(size_t)col[p] * ld];
-        acc = X[(size_t)i * ld] - (a0 + a1);
+  for (int k = t + (RP + 1) * bd; k <= nr; k += bd) srp[k] = rp[r0 + k] - e0;
+  for (int k = t + bd; k <= nlev; k += bd) slev[k] = (lev[l0 + k] - base_row) | ((k < nlev ? (int)lev_lg[l0 + k] : 0) << 16);
+  for (int r = t + RP * bd; r < nr; r += bd) {
+    const int i = r0 + r;
+    double acc;
+    if (FWD) {
+      acc = scale * X[(size_t)i * ld];
+    } else {
+      double a0 = 0.0, a1 = 0.0;
+      const int p1 = ptr[i + 1];
+      int p = up_split[i];
+      for (; p + 1 < p1; p += 2) {
+        a0 += val[p] * X[(size_t)col[p] * ld];
+        a1 += val[p + 1] * X[(size_t)col[p + 1] * ld];
       }
-      xv[m] = acc;
+      if (p < p1) a0 += val[p] * X[(size_t)col[p] * ld];
+      acc = X[(size_t)i * ld] - (a0 + a1);
     }
-#pragma unroll
-    for (int m = 0; m < 4; ++m)
-      if (rb + m * bd < nr) xs[rb + m * bd] = xv[m];
+    if (!UNIT) rdg[r] = 1.0 / val[diag[i]];
+    srow[r] = (short)(lrows[base_row + r] - r0);
+    xs[r] = acc;
   }
   __syncthreads();
   // one record per level position: the row, its entry count and first entry
