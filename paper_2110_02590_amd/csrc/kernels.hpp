@@ -1395,10 +1395,10 @@ __global__ void __launch_bounds__(256) k_pack_solve_1(const int32_t* __restrict_
   // per-level array is loaded at once, then what depends on it (factor
   // values, pivots, the first two top-column terms of backward rows and
   // their solved values), and only then stored to LDS; further passes
-  // (packs of more than 4096 entries or 1024 rows) and longer top-column
+  // (packs of more than 8192 entries or 1024 rows) and longer top-column
   // products follow.  Indices are clamped into their arrays; a pack
   // without entries reads entry 0 of the LU values.
-  constexpr int EP = 16, RP = 4;
+  constexpr int EP = 32, RP = 4;
   {
     const bool has_e = ne > 0;
     int ps[EP];
