@@ -1601,6 +1601,9 @@ __global__ void __launch_bounds__(256) k_pack_solve_1(const int32_t* __restrict_
     double x[2];
 #pragma unroll
     for (int m = 0; m < 2; ++m) x[m] = xs[cur.j[m]];
+    // keep these loads ahead of the next level's (the scheduler would issue
+    // the longer chain first and put its round trip before the sums)
+    __builtin_amdgcn_sched_barrier(0);
     // the next level's unit (after the last level the indices stay in range
     // and the values go unused) and the word of the level after it
     const int w3 = slev[min(lv + 3, nlev)];
