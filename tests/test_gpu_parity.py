@@ -423,13 +423,18 @@ def test_trace_lines(capfd):
     {"RPF_SUBTREE_MAX": "256"},
     {"RPF_SUBTREE_MAX": "512", "RPF_PACK_THREADS": "512"},
     {"RPF_SUBTREE_MAX": "1536"},
+    {"RPF_SUBTREE_MAX": "1792"},
     {"RPF_SUBTREE_MAX": "2048"},
 ], ids=lambda e: ",".join(f"{k}={v}" for k, v in e.items()))
 def test_solve_variants_match_default(env):
     """The other batched-solve variants -- 8-column tiles with and without
     staged factor values, packs without dense tails or with small ones,
     smaller packs (also with 512-thread workgroups), and larger packs (past the LDS-resident refactorization:
-    its global-memory version) -- give the default handle's power flow,
+    its global-memory version; at 1792 rows the largest pack, 1769 rows with
+    8757 entries and a level of 300 rows, takes the single right-hand side
+    solve's second staging passes and a level of two passes; at 2048 that
+    solve's level records no longer fit in LDS and the solve without them
+    runs) -- give the default handle's power flow,
     gradient and full reduced Hessian (syn2000, 1e-10 relative; the
     orderings differ, so not bit for bit).  A pack too large for any of the
     solves is refused at handle creation with an error."""
