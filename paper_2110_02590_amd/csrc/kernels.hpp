@@ -1350,15 +1350,16 @@ __global__ void __launch_bounds__(256) k_pack_solve_s(const int32_t* __restrict_
 // are loaded during the previous level (only the solved inputs xs[j]
 // depend on earlier levels); entries past a row's end read a zero pad
 // (value 0, column nr, xs[nr] = 0), so the sums need no masks; longer rows
-// loop over the rest, and levels of more than 256 / G rows take further
-// passes without prefetch.  The loop is unrolled by two so the prefetched
+// loop over the rest (only in levels the host marks), and levels of more
+// than 256 / G rows take further passes without prefetch.  The loop is unrolled by two so the prefetched
 // state alternates between two register sets.
 // FWD: entries [ptr[i], diag[i]), x_i = scale b_i - sum; backward: entries
 // (diag[i], up_split[i]), x_i = b_i - sum(top columns) - sum; UNIT = false
 // multiplies by the staged 1 / u_ii.
 // LDS: xs[nr + 1] | val[ne + 1] | 1/dg[nr] | unit[nr] (int2: row | length
 // << 16, first entry) | rp[nr + 1] (int) | lev[nlev + 1] (int: first
-// position | lg << 16) | rows[nr] (short) | col[ne + 1] (short).
+// position | lg << 16 | long rows << 19) | rows[nr] (short) | col[ne + 1]
+// (short).
 __host__ __device__ __forceinline__ size_t pack1_lds_bytes(int nr, int ne, int nlev) {
   size_t b = (size_t)(nr + 1) * 8 + (size_t)(ne + 1) * 8 + (size_t)nr * 8 + (size_t)nr * 8 + (size_t)(nr + 1) * 4 +
              (size_t)(nlev + 1) * 4 + (size_t)nr * 2 + (size_t)(ne + 1) * 2;
@@ -1577,13 +1578,14 @@ __global__ void __launch_bounds__(256) k_pack_solve_1(const int32_t* __restrict_
   // the unit of the level whose words are wa (first position | lg << 16)
   // and wb (the next level's)
   auto fetch_level = [&](int wa, int wb, Unit& u) {
-    const int a = wa & 0xFFFF, nrow = (wb & 0xFFFF) - a, lg = wa >> 16;
+    const int a = wa & 0xFFFF, nrow = (wb & 0xFFFF) - a, lg = (wa >> 16) & 7;
     fetch(sun[max(a + min(t >> lg, nrow - 1), 0)], t & ((1 << lg) - 1), 1 << lg, u);
   };
   // the unit's sum over its lanes and the row's new value
-  auto finish = [&](const Unit& u, const double (&x)[2], int G, int seg, bool act) {
+  auto finish = [&](const Unit& u, const double (&x)[2], int lg, bool longrows, int seg, bool act) {
+    const int G = 1 << lg;
     double part = fma(u.v[1], x[1], u.v[0] * x[0]);
-    if (act)
+    if (longrows && act)
       for (int e = u.e + 2 * G; e < u.e1; e += G) part += sv[e] * xs[scol[e]];
     part = group_sum(part, G);
     if (act && seg == 0) {
@@ -1596,7 +1598,8 @@ __global__ void __launch_bounds__(256) k_pack_solve_1(const int32_t* __restrict_
   Unit ua, ub;
   fetch_level(w0, w1, ua);
   auto step = [&](int lv, const Unit& cur, Unit& nxt) {
-    const int a = w0 & 0xFFFF, nrow = (w1 & 0xFFFF) - a, lg = w0 >> 16;
+    const int a = w0 & 0xFFFF, nrow = (w1 & 0xFFFF) - a, lg = (w0 >> 16) & 7;
+    const bool longrows = (w0 >> 19) & 1;
     const int G = 1 << lg, work = nrow << lg, seg = t & (G - 1);
     double x[2];
 #pragma unroll
@@ -1608,7 +1611,7 @@ __global__ void __launch_bounds__(256) k_pack_solve_1(const int32_t* __restrict_
     // and the values go unused) and the word of the level after it
     const int w3 = slev[min(lv + 3, nlev)];
     fetch_level(w1, w2, nxt);
-    finish(cur, x, G, seg, t < work);
+    finish(cur, x, lg, longrows, seg, t < work);
     // levels wider than one pass of the workgroup
     for (int w = t + bd; w - t < work; w += bd) {
       Unit u;
@@ -1616,7 +1619,7 @@ __global__ void __launch_bounds__(256) k_pack_solve_1(const int32_t* __restrict_
       double xu[2];
 #pragma unroll
       for (int m = 0; m < 2; ++m) xu[m] = xs[u.j[m]];
-      finish(u, xu, G, seg, w < work);
+      finish(u, xu, lg, longrows, seg, w < work);
     }
     __syncthreads();
     w0 = w1;

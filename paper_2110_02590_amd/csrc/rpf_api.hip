@@ -50,7 +50,8 @@ inline int cdiv(long a, long b) { return (int)((a + b - 1) / b); }
 // Lanes per row (log2) of each level of a single right-hand side pack
 // program (levels lev[l] .. lev[l + 1] of rows, entries rp[i] .. rp[i + 1]
 // of row i): enough for two entries per lane on the level's longest row,
-// at most 64 lanes per row and 256 lanes per level.
+// at most 64 lanes per row and 256 lanes per level; + 8 when a row of the
+// level still has more than two entries per lane.
 std::vector<int8_t> level_lanes(const std::vector<int32_t>& lev, const std::vector<int32_t>& rows,
                                 const std::vector<int32_t>& rp) {
   const int nl = std::max((int)lev.size() - 1, 0);
@@ -61,7 +62,7 @@ std::vector<int8_t> level_lanes(const std::vector<int32_t>& lev, const std::vect
     for (int k = lev[l]; k < lev[l + 1]; ++k) len = std::max(len, rp[rows[k] + 1] - rp[rows[k]]);
     int g = 0;
     while (g < 6 && (2 << g) < len && (nrow << (g + 1)) <= 256) ++g;
-    lg[l] = (int8_t)g;
+    lg[l] = (int8_t)(g | ((2 << g) < len ? 8 : 0));
   }
   return lg;
 }
