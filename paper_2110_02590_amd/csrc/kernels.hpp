@@ -1351,8 +1351,9 @@ __global__ void __launch_bounds__(256) k_pack_solve_s(const int32_t* __restrict_
 // depend on earlier levels); entries past a row's end read a zero pad
 // (value 0, column nr, xs[nr] = 0), so the sums need no masks; longer rows
 // loop over the rest (only in levels the host marks), and levels of more
-// than 256 / G rows take further passes without prefetch.  The loop is unrolled by two so the prefetched
-// state alternates between two register sets.
+// than 256 / G rows take further passes without prefetch.  The loop is
+// unrolled by two so the prefetched state alternates between two register
+// sets.
 // FWD: entries [ptr[i], diag[i]), x_i = scale b_i - sum; backward: entries
 // (diag[i], up_split[i]), x_i = b_i - sum(top columns) - sum; UNIT = false
 // multiplies by the staged 1 / u_ii.
