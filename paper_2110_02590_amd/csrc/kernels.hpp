@@ -1120,6 +1120,8 @@ __global__ void __launch_bounds__(256) k_top_dense(int t0, int n, const double* 
 
 // Staged pack solves: the pack's level lists, local columns, factor values
 // and diagonal are copied to LDS first, so the level loop reads only LDS.
+// For one right-hand side k_pack_solve_1 (below) is used when its level
+// records fit in LDS; this kernel serves the packs where they do not.
 // LDS layout: xs[nr*TW] | val[ne] | dg[nr] | rp[nr+1] (int) | lev[nlev+1]
 // (int) | rows[nr] (short) | col[ne] (short).
 __host__ __device__ __forceinline__ size_t pack_lds_bytes(int nr, int ne, int nlev, int tw) {
