@@ -111,7 +111,7 @@ struct rpf_grid {
   int32_t *pkf_rp, *pkf_pos, *pkb_rp, *pkb_pos;
   int8_t *pk_flg = nullptr, *pk_blg = nullptr;
   int16_t *pkf_col, *pkb_col;
-  int tw_pack = 8, tw_top = 8;
+  int tw_top = 8;
   size_t lds_packg = 0;   // LDS of the global-memory batched pack solves
   size_t lds_rf = 0;      // LDS of the LDS-resident pack refactorization (0: not used)
   bool rf_recs_lds = true;   // its row records staged in LDS as well
@@ -131,7 +131,7 @@ struct rpf_grid {
   int4 *rf_rowrec = nullptr, *rf_ent = nullptr, *rf_tlrec = nullptr;   // k_rf_pack_lds records
   int32_t* rf_entu0 = nullptr;
   double *tailA = nullptr, *tailM = nullptr;
-  size_t lds_limit = 65536, lds_pack[5] = {0, 0, 0, 0, 0}, lds_pack1 = 0;
+  size_t lds_limit = 65536, lds_pack_s = 0, lds_pack1 = 0;
   double *c2, *c1, *c0;
   // predication word for the Hessian-product batches (set while the bounded
   // QP assembles its Schur complements; null otherwise)
@@ -539,23 +539,14 @@ void setup(rpf_grid* h) {
     HIPCHK(hipGetDevice(&dev));
     HIPCHK(hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
     h->lds_limit = (size_t)std::max(lim, 32768);
-    // staged pack solves: LDS of the largest pack for each column tile width
-    const int tws[5] = {16, 8, 4, 2, 1};
-    for (int k = 0; k < 5; ++k) {
-      size_t mx = 0;
-      for (int q = 0; q < h->npacks; ++q) {
-        const int r0 = P.pack_ptr[q], nr = P.pack_ptr[q + 1] - r0;
-        const int nef = P.pkf_rp[r0 + nr] - P.pkf_rp[r0], neb = P.pkb_rp[r0 + nr] - P.pkb_rp[r0];
-        const int nlf = P.pk_flev_off[q + 1] - P.pk_flev_off[q], nlb = P.pk_blev_off[q + 1] - P.pk_blev_off[q];
-        mx = std::max(mx, pack_lds_bytes(nr, std::max(nef, neb), std::max(nlf, nlb), tws[k]));
-      }
-      h->lds_pack[k] = mx;
-    }
-    // single right-hand side pack solves with level records (either direction)
+    // single right-hand side pack solves, either direction: LDS of the
+    // largest pack with level records (k_pack_solve_1) and without them
+    // (k_pack_solve_s, for packs where the records do not fit)
     for (int q = 0; q < h->npacks; ++q) {
       const int r0 = P.pack_ptr[q], nr = P.pack_ptr[q + 1] - r0;
       const int nef = P.pkf_rp[r0 + nr] - P.pkf_rp[r0], neb = P.pkb_rp[r0 + nr] - P.pkb_rp[r0];
       const int nlf = P.pk_flev_off[q + 1] - P.pk_flev_off[q], nlb = P.pk_blev_off[q + 1] - P.pk_blev_off[q];
+      h->lds_pack_s = std::max(h->lds_pack_s, pack_lds_bytes(nr, std::max(nef, neb), std::max(nlf, nlb), 1));
       h->lds_pack1 = std::max(h->lds_pack1, pack1_lds_bytes(nr, std::max(nef, neb), std::max(nlf, nlb)));
     }
     // global-memory batched pack solves: largest pack, either direction
@@ -620,13 +611,7 @@ void setup(rpf_grid* h) {
       h->rf_recs_lds = mxr <= h->lds_limit;
       h->lds_rf = h->rf_recs_lds ? mxr : (mx <= h->lds_limit ? mx : 0);
     }
-    h->tw_pack = 0;
-    for (int k = 0; k < 5; ++k)
-      if (h->lds_pack[k] <= h->lds_limit) {
-        h->tw_pack = tws[k];
-        break;
-      }
-    if (h->tw_pack == 0) throw std::runtime_error("a pack of subtrees does not fit in LDS");
+    if (h->lds_pack_s > h->lds_limit) throw std::runtime_error("a pack of subtrees does not fit in LDS");
     // the dense top solve also holds two static tiles (about 50 KB)
     const size_t top_static = 52 * 1024;
     h->tw_top = 4;   // 4 columns per workgroup: about one workgroup per CU at 1024 columns
@@ -643,11 +628,6 @@ void setup(rpf_grid* h) {
     };
     allow_top((const void*)k_top_dense);
 
-#define RPF_ALLOW_PACK(TW)                                  \
-  allow((const void*)k_pack_solve_s<TW, true, true>);       \
-  allow((const void*)k_pack_solve_s<TW, true, false>);      \
-  allow((const void*)k_pack_solve_s<TW, false, true>);      \
-  allow((const void*)k_pack_solve_s<TW, false, false>);
     if (h->lds_packg > h->lds_limit) throw std::runtime_error("a pack of subtrees does not fit in LDS");
     if (h->lds_rf > 0) allow(h->rf_recs_lds ? (const void*)k_rf_pack_lds<true> : (const void*)k_rf_pack_lds<false>);
 #define RPF_ALLOW_PACKT(TW, SV)                                 \
@@ -663,12 +643,10 @@ void setup(rpf_grid* h) {
     allow((const void*)k_pack_solve_g<true, false>);
     allow((const void*)k_pack_solve_g<false, true>);
     allow((const void*)k_pack_solve_g<false, false>);
-    RPF_ALLOW_PACK(16)
-    RPF_ALLOW_PACK(8)
-    RPF_ALLOW_PACK(4)
-    RPF_ALLOW_PACK(2)
-    RPF_ALLOW_PACK(1)
-#undef RPF_ALLOW_PACK
+    allow((const void*)k_pack_solve_s<1, true, true>);
+    allow((const void*)k_pack_solve_s<1, true, false>);
+    allow((const void*)k_pack_solve_s<1, false, true>);
+    allow((const void*)k_pack_solve_s<1, false, false>);
     allow((const void*)k_pack_solve_1<true, true>);
     allow((const void*)k_pack_solve_1<true, false>);
     allow((const void*)k_pack_solve_1<false, true>);
@@ -865,14 +843,15 @@ void refactor(rpf_grid* h, hipStream_t s, const int32_t* skip = nullptr) {
   LAUNCHCHK();
 }
 
-template <int TW>
-void pack_solve(rpf_grid* h, bool fwd, bool unit, const double* val, double* X, int ld, int ncols, double scale,
-                int cls, hipStream_t s, const int32_t* skip) {
+// One right-hand side: the pack solves with level records when they fit in
+// LDS, else the staged solves without them.
+void pack_solve1(rpf_grid* h, bool fwd, bool unit, const double* val, double* X, int ld, double scale, int cls,
+                 hipStream_t s, const int32_t* skip) {
   const Presolve& P = h->P;
   if (h->npacks == 0) return;
-  const int k = TW == 16 ? 0 : TW == 8 ? 1 : TW == 4 ? 2 : TW == 2 ? 3 : 4;
-  const size_t shm = h->lds_pack[k];
-  dim3 grd(h->npacks, cdiv(ncols, TW));
+  const int ncols = 1;
+  const size_t shm = h->lds_pack_s;
+  const dim3 grd(h->npacks, 1);
   size_t pi = h->prof_on ? h->prof_begin(s) : 0;
   auto launch = [&](auto kern, const int32_t* lev, const int32_t* lev_off, const int32_t* rows, const int32_t* rp,
                     const int32_t* pos, const int16_t* ecol) {
@@ -884,7 +863,7 @@ void pack_solve(rpf_grid* h, bool fwd, bool unit, const double* val, double* X, 
     kern<<<h->npacks, 256, h->lds_pack1, s>>>(h->pack_ptr, lev, lev_off, lgs, rows, rp, pos, ecol, h->lu_diag,
                                                h->up_split, h->lu_ptr, h->lu_col, val, X, ld, scale, skip);
   };
-  if (TW == 1 && ncols == 1 && h->lds_pack1 <= h->lds_limit) {
+  if (h->lds_pack1 <= h->lds_limit) {
     if (fwd) {
       if (unit)
         launch1(k_pack_solve_1<true, true>, h->pk_flev, h->pk_flev_off, h->pk_flg, h->pk_frows, h->pkf_rp,
@@ -902,14 +881,14 @@ void pack_solve(rpf_grid* h, bool fwd, bool unit, const double* val, double* X, 
     }
   } else if (fwd) {
     if (unit)
-      launch(k_pack_solve_s<TW, true, true>, h->pk_flev, h->pk_flev_off, h->pk_frows, h->pkf_rp, h->pkf_pos, h->pkf_col);
+      launch(k_pack_solve_s<1, true, true>, h->pk_flev, h->pk_flev_off, h->pk_frows, h->pkf_rp, h->pkf_pos, h->pkf_col);
     else
-      launch(k_pack_solve_s<TW, true, false>, h->pk_flev, h->pk_flev_off, h->pk_frows, h->pkf_rp, h->pkf_pos, h->pkf_col);
+      launch(k_pack_solve_s<1, true, false>, h->pk_flev, h->pk_flev_off, h->pk_frows, h->pkf_rp, h->pkf_pos, h->pkf_col);
   } else {
     if (unit)
-      launch(k_pack_solve_s<TW, false, true>, h->pk_blev, h->pk_blev_off, h->pk_brows, h->pkb_rp, h->pkb_pos, h->pkb_col);
+      launch(k_pack_solve_s<1, false, true>, h->pk_blev, h->pk_blev_off, h->pk_brows, h->pkb_rp, h->pkb_pos, h->pkb_col);
     else
-      launch(k_pack_solve_s<TW, false, false>, h->pk_blev, h->pk_blev_off, h->pk_brows, h->pkb_rp, h->pkb_pos, h->pkb_col);
+      launch(k_pack_solve_s<1, false, false>, h->pk_blev, h->pk_blev_off, h->pk_brows, h->pkb_rp, h->pkb_pos, h->pkb_col);
   }
   LAUNCHCHK();
   if (h->prof_on) h->prof_end(cls, pi, s);
@@ -975,16 +954,10 @@ void pack_solve_g(rpf_grid* h, bool fwd, bool unit, bool transposed, const doubl
   if (h->prof_on) h->prof_end(cls, pi, s);
 }
 
-void pack_solve_any(rpf_grid* h, int tw, bool fwd, bool unit, bool transposed, const double* val, double* X,
+void pack_solve_any(rpf_grid* h, bool fwd, bool unit, bool transposed, const double* val, double* X,
                     int ld, int ncols, double scale, int cls, hipStream_t s, const int32_t* skip, const PackFuse* fz = nullptr) {
   if (ncols > 1) return pack_solve_g(h, fwd, unit, transposed, val, X, ld, ncols, scale, cls, s, skip, fz);
-  switch (tw) {
-    case 16: return pack_solve<16>(h, fwd, unit, val, X, ld, ncols, scale, cls, s, skip);
-    case 8: return pack_solve<8>(h, fwd, unit, val, X, ld, ncols, scale, cls, s, skip);
-    case 4: return pack_solve<4>(h, fwd, unit, val, X, ld, ncols, scale, cls, s, skip);
-    case 2: return pack_solve<2>(h, fwd, unit, val, X, ld, ncols, scale, cls, s, skip);
-    default: return pack_solve<1>(h, fwd, unit, val, X, ld, ncols, scale, cls, s, skip);
-  }
+  pack_solve1(h, fwd, unit, val, X, ld, scale, cls, s, skip);
 }
 
 // Solves with both factors of J_x (transposed = false): X <- U^{-1} L^{-1}
@@ -1002,9 +975,8 @@ void solve_pair(rpf_grid* h, bool transposed, double* X, int ld, int ncols, doub
   // forward factor: L (unit) or U^T (non-unit); backward: U (non-unit) or L^T (unit)
   const bool fwd_unit = !transposed;
   const int cls = ncols > 1 ? 0 : 1;
-  const int twp = ncols == 1 ? 1 : h->tw_pack;
   const int twt = ncols == 1 ? 1 : h->tw_top;
-  pack_solve_any(h, twp, true, fwd_unit, transposed, val, X, ld, ncols, scale, cls, s, skip, rf);
+  pack_solve_any(h, true, fwd_unit, transposed, val, X, ld, ncols, scale, cls, s, skip, rf);
   const bool fuse_top = ncols > 1 && h->tw_packt > 0 && h->npacks > 0;
   if (P.ntop > 0) {
     size_t pi = h->prof_on ? h->prof_begin(s) : 0;
@@ -1080,7 +1052,7 @@ void solve_pair(rpf_grid* h, bool transposed, double* X, int ld, int ncols, doub
     bf.tmoff = h->tm_off;
     bf.tmrows = h->topmul_rows;
   }
-  pack_solve_any(h, twp, false, !fwd_unit, transposed, val, X, ld, ncols, 1.0, cls, s, skip,
+  pack_solve_any(h, false, !fwd_unit, transposed, val, X, ld, ncols, 1.0, cls, s, skip,
                  fuse_top ? &bf : nullptr);
 }
 
